@@ -1,0 +1,200 @@
+/*
+ * ddfem.h -- C ABI of the MI355X domain-decomposed Whitney-edge Newmark solver.
+ *
+ * The library advances the edge-element wave equation
+ *     T e'' + S e = -j'           (Sec. II-B: Whitney 1-forms, PEC walls)
+ * with Newmark-beta (gamma = 1/2), one implicit solve per step:
+ *     A e^{n+1} = (2A - dt^2 S) e^n - A e^{n-1} - dt (J^{n+1/2} - J^{n-1/2}),
+ *     A = T + beta dt^2 S,
+ * and solves each step with the dual-primal tearing of Sec. III-A
+ * (MFETI-DP1 without the face unknowns): per-subdomain SPD blocks ordered
+ * [interior | interface | corner], a signed Boolean interface map, an
+ * unsigned corner map, a coarse corner problem and the interface Schur
+ * system of eq. (f1schur), solved by conjugate gradients.
+ *
+ * Conventions
+ *  - Edges are the unique vertex pairs (v_lo, v_hi), v_lo < v_hi, numbered
+ *    lexicographically ("canonical edges").  An edge is on the conductor
+ *    (PEC) iff it is an edge of a boundary face (a face of exactly one
+ *    tetrahedron); PEC edges carry no unknown.
+ *  - Field and current arrays are row-major [nrhs][n_edges] float64 in
+ *    device memory; PEC entries are ignored on input and written as 0.
+ *  - Host arrays are read during the call only; the library never keeps a
+ *    caller pointer (except the stream).  The library owns everything it
+ *    allocates and frees it in dd_destroy.
+ *  - All device work of a call is enqueued on opt.stream (NULL = default
+ *    stream).  Calls that must read device results on the host (convergence
+ *    decisions, stats) synchronise that stream before returning.
+ *  - Calls on one context are not thread safe.
+ *  - Every int-returning call returns DD_OK (0) or a negative dd_status;
+ *    dd_last_error() then returns a message (thread-local).
+ */
+#ifndef DDFEM_H
+#define DDFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DD_OK = 0,
+  DD_ERR_ARG = -1,            /* bad argument (null pointer, size, beta <= 0, ...) */
+  DD_ERR_MESH = -2,           /* vertex index out of range or degenerate tetrahedron */
+  DD_ERR_PARTITION = -3,      /* subdomain id out of range or empty subdomain */
+  DD_ERR_NOT_SPD = -4,        /* non-positive pivot; message names the subdomain */
+  DD_ERR_NO_CONVERGENCE = -5, /* CG or refinement hit its cap (context stays usable) */
+  DD_ERR_STATE = -6,          /* e.g. dd_step before dd_factor */
+  DD_ERR_HIP = -7,            /* HIP runtime error (context must be destroyed) */
+  DD_ERR_OOM = -8,            /* device or host allocation failed */
+  DD_ERR_NONFINITE = -9       /* non-finite value in an input */
+} dd_status;
+
+typedef enum {
+  DD_FP64 = 0,        /* factors, local solves and CG all in float64 */
+  DD_FP32_REFINE = 1  /* float32 factors and local solves, float64 CG vectors,
+                         float64 global residual and iterative refinement */
+} dd_precision;
+
+typedef struct {
+  int precision;      /* dd_precision */
+  int nrhs;           /* right-hand sides solved together, 1..32 */
+  double cg_tol;      /* relative interface residual ||d - F lambda|| / ||d|| */
+  int cg_max_iter;    /* cap on CG iterations per solve */
+  double refine_tol;  /* relative global residual ||b - A e|| / ||b|| (FP32_REFINE) */
+  int refine_max;     /* cap on refinement sweeps (FP32_REFINE) */
+  int warm_start;     /* start CG from the previous solve's multipliers */
+  int use_graph;      /* replay the CG iteration as a captured HIP graph */
+  int check_every;    /* CG iterations between host convergence checks (>= 1) */
+  void* stream;       /* hipStream_t; NULL = default stream */
+} dd_options;
+
+typedef struct {
+  int cg_iters[32];        /* CG iterations of the last solve, per RHS */
+  int refine_sweeps;       /* refinement sweeps of the last step */
+  int dd_solves;           /* DD solves in the last step (1 + sweeps) */
+  double cg_relres[32];    /* final relative interface residual, per RHS */
+  double global_relres[32];/* final ||b - A e|| / ||b|| (FP32_REFINE), per RHS */
+} dd_stats;
+
+typedef struct {
+  int64_t n_edges, n_interior, n_tets, n_vertices;
+  int32_t n_sub, n_lambda, n_corner, nrhs, precision, tile;
+  int64_t factor_bytes;    /* device bytes of all stored factors */
+  int64_t trailing_bytes;  /* bytes of the interface blocks of the inverse factors
+                              (read twice per CG iteration), unpadded */
+  int64_t coupling_bytes;  /* bytes of the corner-interface coupling blocks, unpadded */
+  int64_t coarse_bytes;    /* bytes of the coarse inverse factor, unpadded */
+  int64_t full_bytes;      /* bytes of the full r-block inverse factors, unpadded */
+} dd_info;
+
+/* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
+ * refine_tol 1e-12, refine_max 10, warm_start 1, use_graph 0, check_every 4. */
+void dd_default_options(dd_options* opt);
+
+/* Build a solver context (host analysis + device upload + element assembly
+ * inputs).  Sec. III: the tetrahedra with partition[t] == s form subdomain
+ * s; an edge shared by two subdomains is an interface edge (one Lagrange
+ * multiplier, +1 in the lower subdomain id, -1 in the higher); an edge shared
+ * by three or more is a corner (a primal unknown of the coarse problem).
+ *   coords    host [n_vertices][3] float64
+ *   tets      host [n_tets][4] int32 (any vertex order)
+ *   partition host [n_tets] int32 in [0, n_sub), every id used
+ *   eps, mu   host [n_tets] float64 relative permittivity / permeability
+ *             (> 0, finite); mu may be NULL (= 1)
+ *   dt, beta  time step and Newmark beta (> 0, finite)
+ * Errors: DD_ERR_ARG, DD_ERR_MESH, DD_ERR_PARTITION, DD_ERR_NONFINITE,
+ * DD_ERR_HIP, DD_ERR_OOM.  On error *out is NULL. */
+int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tets,
+             const int32_t* tets, const int32_t* partition, const double* eps,
+             const double* mu, double dt, double beta, const dd_options* opt);
+
+/* Sizes of a context. */
+int dd_get_info(void* ctx, dd_info* info);
+
+/* Canonical edges: host [n_edges][2] int32 (v_lo, v_hi) and host [n_edges]
+ * uint8 PEC flags.  Either pointer may be NULL. */
+int dd_get_edges(void* ctx, int32_t* edges, uint8_t* is_pec);
+
+/* Replace the per-tetrahedron permittivity (host [n_tets] float64);
+ * dd_factor must be called again before the next solve. */
+int dd_set_eps(void* ctx, const double* eps);
+
+/* Element matrices, per-subdomain assembly [I | Gamma | c], partial Cholesky
+ * of the r = I u Gamma block with the local corner Schur complement
+ * K_s = A_cc - L_cr L_cr^T (Sec. III-A, eq. (cF1)), inversion of the
+ * triangular factors (the stored local inverses of Sec. III-C), assembly and
+ * factorisation of the coarse corner matrix K_cc = sum_s B_c^T K_s B_c
+ * (eq. (F1uc)).  Synchronises the stream.  DD_ERR_NOT_SPD names the first
+ * subdomain with a non-positive pivot. */
+int dd_factor(void* ctx);
+
+/* One Newmark step for all nrhs right-hand sides (device pointers):
+ *   J_half, J_prev_half  [nrhs][n_edges]: J^{n+1/2}, J^{n-1/2}
+ *   E_n, E_nm1           [nrhs][n_edges]: e^n, e^{n-1}
+ *   E_next               [nrhs][n_edges]: e^{n+1} (output; may not alias inputs)
+ * stats: host pointer or NULL.  DD_ERR_NO_CONVERGENCE leaves E_next holding
+ * the last iterate and the context usable. */
+int dd_step(void* ctx, const double* J_half, const double* J_prev_half,
+            const double* E_n, const double* E_nm1, double* E_next, dd_stats* stats);
+
+/* x = A^{-1} b on canonical-edge arrays [nrhs][n_edges] (device), through the
+ * same decomposed solve (with refinement in DD_FP32_REFINE). */
+int dd_solve(void* ctx, const double* b, double* x, dd_stats* stats);
+
+/* One reverse step of the recurrence (A is symmetric, so the factors are
+ * reused).  With ebar_next the total adjoint of e^{n+1}:
+ *   g = A^{-1} ebar_next;  ebar_n += (2A - dt^2 S) g;  ebar_nm1 -= A g;
+ *   eps_bar[k] -= g . T_k (e^{n+1} - 2 e^n + e^{n-1})   (T_k: unit-eps mass)
+ * summed over the right-hand sides.  All pointers are device pointers;
+ * arrays are [nrhs][n_edges] except eps_bar [n_tets] (accumulated).
+ * ebar_nm1 or eps_bar may be NULL (skipped).  E_nm1 NULL means e^{n-1} = 0. */
+int dd_adjoint_step(void* ctx, const double* ebar_next, double* ebar_n, double* ebar_nm1,
+                    double* g_out, const double* E_next, const double* E_n,
+                    const double* E_nm1, double* eps_bar, dd_stats* stats);
+
+/* Discrete Gauss law (Sec. V-B charge conservation), device pointers:
+ *   dd_charge_update:  q += dt * G^T J_half   (q [nrhs][n_vertices], entries
+ *                      of boundary vertices stay 0; G: +1 at the higher-id end)
+ *   dd_gauss_residual: res[r] = max_k |(G^T T e + q)_k| over interior vertices
+ *                      (res: host [nrhs]); synchronises. */
+int dd_charge_update(void* ctx, const double* J_half, double* q);
+int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res);
+
+/* Discrete energy H^{n+1/2} = |e^{n+1}-e^n|_T^2 / dt^2 + |(e^{n+1}+e^n)/2|_S^2
+ * per RHS (host out [nrhs]); synchronises. */
+int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out);
+
+void dd_destroy(void* ctx);
+
+/* Message of the last error on this thread ("" if none). */
+const char* dd_last_error(void);
+
+/* ---- host-only analysis (no device calls; usable without a GPU) -------- */
+typedef struct {
+  int64_t n_edges, n_interior;
+  int32_t n_sub, n_lambda, n_corner, max_multiplicity;
+  int64_t sum_nr3;         /* sum over subdomains of n_r^3 */
+} dd_analysis;
+
+/* Partition analysis of Sec. III (interior / interface / corner classes).
+ * per_sub (host [n_sub][3] int32, may be NULL) receives n_I, n_Gamma, n_c. */
+int dd_analyze(int64_t n_vertices, const double* coords, int64_t n_tets,
+               const int32_t* tets, const int32_t* partition, dd_analysis* out,
+               int32_t* per_sub);
+
+/* Interface map of the same analysis: for each multiplier l (host arrays
+ * [n_lambda]): its canonical edge, the two subdomains (lo < hi) and the
+ * positions of the edge in their local orders (0-based within the
+ * [I | Gamma | c] order, unpadded).  The multiplier enters subdomain lo with
+ * +1 and hi with -1. */
+int dd_analyze_lambda(int64_t n_vertices, const double* coords, int64_t n_tets,
+                      const int32_t* tets, const int32_t* partition,
+                      int32_t* edge, int32_t* sub_lo, int32_t* sub_hi,
+                      int32_t* pos_lo, int32_t* pos_hi);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDFEM_H */

@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in include/ddfem.h (argument marshalling
+only; every step of the solve runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddfem.so")
+
+DD_OK = 0
+DD_ERR = {
+    -1: "DD_ERR_ARG", -2: "DD_ERR_MESH", -3: "DD_ERR_PARTITION", -4: "DD_ERR_NOT_SPD",
+    -5: "DD_ERR_NO_CONVERGENCE", -6: "DD_ERR_STATE", -7: "DD_ERR_HIP", -8: "DD_ERR_OOM",
+    -9: "DD_ERR_NONFINITE",
+}
+DD_FP64, DD_FP32_REFINE = 0, 1
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("nrhs", C.c_int), ("cg_tol", C.c_double),
+                ("cg_max_iter", C.c_int), ("refine_tol", C.c_double), ("refine_max", C.c_int),
+                ("warm_start", C.c_int), ("use_graph", C.c_int), ("check_every", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cg_iters", C.c_int * 32), ("refine_sweeps", C.c_int), ("dd_solves", C.c_int),
+                ("cg_relres", C.c_double * 32), ("global_relres", C.c_double * 32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n_edges", C.c_int64), ("n_interior", C.c_int64), ("n_tets", C.c_int64),
+                ("n_vertices", C.c_int64), ("n_sub", C.c_int32), ("n_lambda", C.c_int32),
+                ("n_corner", C.c_int32), ("nrhs", C.c_int32), ("precision", C.c_int32),
+                ("tile", C.c_int32), ("factor_bytes", C.c_int64), ("trailing_bytes", C.c_int64),
+                ("coupling_bytes", C.c_int64), ("coarse_bytes", C.c_int64), ("full_bytes", C.c_int64)]
+
+
+class Analysis(C.Structure):
+    _fields_ = [("n_edges", C.c_int64), ("n_interior", C.c_int64), ("n_sub", C.c_int32),
+                ("n_lambda", C.c_int32), ("n_corner", C.c_int32), ("max_multiplicity", C.c_int32),
+                ("sum_nr3", C.c_int64)]
+
+
+P = C.c_void_p
+I64 = C.c_int64
+D = C.c_double
+
+SIGNATURES = {
+    "dd_default_options": (None, [C.POINTER(Options)]),
+    "dd_setup": (C.c_int, [C.POINTER(C.c_void_p), I64, P, I64, P, P, P, P, D, D, C.POINTER(Options)]),
+    "dd_get_info": (C.c_int, [P, C.POINTER(Info)]),
+    "dd_get_edges": (C.c_int, [P, P, P]),
+    "dd_set_eps": (C.c_int, [P, P]),
+    "dd_factor": (C.c_int, [P]),
+    "dd_step": (C.c_int, [P, P, P, P, P, P, C.POINTER(Stats)]),
+    "dd_solve": (C.c_int, [P, P, P, C.POINTER(Stats)]),
+    "dd_adjoint_step": (C.c_int, [P, P, P, P, P, P, P, P, P, C.POINTER(Stats)]),
+    "dd_charge_update": (C.c_int, [P, P, P]),
+    "dd_gauss_residual": (C.c_int, [P, P, P, P]),
+    "dd_energy": (C.c_int, [P, P, P, P]),
+    "dd_destroy": (None, [P]),
+    "dd_last_error": (C.c_char_p, []),
+    "dd_analyze": (C.c_int, [I64, P, I64, P, P, C.POINTER(Analysis), P]),
+    "dd_analyze_lambda": (C.c_int, [I64, P, I64, P, P, P, P, P, P, P]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libddfem.so; raise (never fall back) if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2204_13254_amd/build.py "
+                               "(or __graft_entry__.build()) first")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class DDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{DD_ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc != DD_OK:
+        raise DDError(rc, load().dd_last_error().decode())
+    return rc

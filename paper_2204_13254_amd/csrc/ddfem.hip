@@ -1,0 +1,1325 @@
+// Solver context and C ABI (include/ddfem.h).
+//
+// Per-step data flow of the decomposed solve (Sec. III-A, eq. (f1schur);
+// local factors L_rr of [I | Gamma] with the corner rows L_cr and local
+// corner Schur complements K_s; stored inverses Linv = L^-1, Sec. III-C):
+//   pre-solve : w = owner split of b;  t = Linv_rr w_r;
+//               f_c = sum_s B_c^T (w_c - L_cr t);  z0 = K_cc^-1 f_c;
+//               d = sum_s B_s Linv_GG^T (t_G - L_cG^T z0_s)
+//   CG on F lambda = d with
+//               F p = sum_s B_s Linv_GG^T (v + L_cG^T z_s),
+//               v = Linv_GG B_s^T p,  z = K_cc^-1 sum_s B_c^T L_cG v
+//   recovery  : t_l = Linv_GG B_s^T lambda;
+//               x_c = K_cc^-1 (f_c + sum_s B_c^T L_cG t_l);
+//               x_r = Linv_rr^T (t - [0; t_l] - L_cr^T x_c);
+//               e = owner's copy.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ddfem.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace ddfem {
+
+static thread_local std::string g_err;
+
+struct DDError {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw DDError{DD_ERR_HIP, std::string("HIP error ") + hipGetErrorString(e_) + " at " \
+                                    + #x + " (line " + std::to_string(__LINE__) + ")"};   \
+  } while (0)
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+template <class V>
+static V* upload(const std::vector<V>& h, std::vector<void*>& owned, hipStream_t st) {
+  V* d = nullptr;
+  size_t bytes = std::max<size_t>(1, h.size()) * sizeof(V);
+  hipError_t e = hipMalloc((void**)&d, bytes);
+  if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation failed"};
+  HIPCHK(e);
+  owned.push_back(d);
+  if (!h.empty()) {
+    // the host vector may be freed right after: finish the copy here
+    HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(V), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return d;
+}
+
+template <class V>
+static V* dalloc(size_t n, std::vector<void*>& owned) {
+  V* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, std::max<size_t>(1, n) * sizeof(V));
+  if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation failed"};
+  HIPCHK(e);
+  owned.push_back(d);
+  return d;
+}
+
+struct Items {
+  MvItem* d = nullptr;
+  int64_t n = 0;
+};
+
+struct Ctx {
+  Plan P;
+  dd_options opt;
+  hipStream_t st = nullptr;
+  double dt = 0, beta = 0;
+  int nrhs = 1;
+  bool fp32 = false;
+  bool factored = false;
+  std::vector<void*> owned;
+
+  // sizes
+  int nsub = 0;  // subdomains; the coarse block is descriptor index nsub
+  int Kc = 0;    // coarse tile rows
+  int64_t ntiles = 0, rows_total = 0, coarse_row0 = 0;
+  int max_kr = 0;
+  std::vector<SubDev> subs_h;
+
+  // device: mesh and elements
+  double *d_coords = nullptr, *d_mu = nullptr, *d_eps = nullptr, *d_Te = nullptr, *d_Se = nullptr;
+  int32_t* d_tsort = nullptr;
+  SubDev* d_subs = nullptr;
+  void* d_tiles = nullptr;
+  void* d_scratch = nullptr;
+  int64_t* d_scratch_off = nullptr;
+  int* d_err = nullptr;
+  // local assembly pull
+  int64_t n_lent = 0;
+  int64_t *d_lptr = nullptr, *d_ldest = nullptr;
+  int32_t* d_lcon = nullptr;
+  int64_t n_pad = 0;
+  int64_t* d_padpos = nullptr;
+  // coarse assembly pull
+  int64_t n_cent = 0;
+  int64_t *d_cptr = nullptr, *d_csrc = nullptr, *d_cdest = nullptr;
+  // global CSR (T, S)
+  int64_t nnz = 0;
+  int64_t *d_rp = nullptr, *d_gptr = nullptr;
+  int32_t *d_ci = nullptr, *d_gcon = nullptr;
+  double2* d_vals = nullptr;
+  // vector maps
+  int32_t* d_rowsrc = nullptr;           // [rows_total]
+  int64_t n_grow = 0;
+  int64_t* d_grow = nullptr;             // interface-block rows
+  int32_t* d_glam = nullptr;             // lambda code (id<<1 | negative) or -1
+  int64_t *d_lrow0 = nullptr, *d_lrow1 = nullptr;
+  int64_t *d_cgptr = nullptr, *d_cgrows = nullptr;  // coarse gather
+  int64_t n_csc = 0;
+  int64_t *d_cscrows = nullptr, *d_csccrow = nullptr;  // corner scatter
+  uint8_t* d_gamma_row = nullptr;
+  int64_t* d_dsrc = nullptr;
+  int32_t *d_interior = nullptr, *d_dof = nullptr, *d_tdof = nullptr;
+  // Gauss law adjacency (interior edges only)
+  int64_t* d_vptr = nullptr;
+  int32_t* d_vedge = nullptr;
+  uint8_t* d_nodeint = nullptr;
+  double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
+  // work lists
+  Items full_N, full_T, trail_N, trail_T, cr_N, cr_T, cg_N, cg_T, co_N, co_T;
+  // work vectors
+  void* X[9] = {};
+  int64_t nlam = 0;
+  double *d_d = nullptr, *d_lam = nullptr, *d_res = nullptr, *d_p = nullptr, *d_Fp = nullptr;
+  double *d_lam_prev = nullptr, *d_lam_prev_adj = nullptr;
+  bool have_prev = false, have_prev_adj = false;
+  double* d_partial = nullptr;
+  CgState* d_cg = nullptr;
+  int* h_done = nullptr;  // pinned
+  double* h_partial = nullptr;  // pinned [kDotBlocks * kMaxRhs]
+  // global vectors [nint][nrhs]
+  double *g_b = nullptr, *g_e = nullptr, *g_r = nullptr, *g_x = nullptr, *g_t1 = nullptr, *g_t2 = nullptr,
+         *g_t3 = nullptr, *g_t4 = nullptr;
+
+  int64_t factor_bytes = 0, trailing_bytes = 0, coupling_bytes = 0, coarse_bytes = 0, full_bytes = 0;
+
+  ~Ctx() {
+    if (st) (void)hipStreamSynchronize(st);
+    for (void* p : owned) (void)hipFree(p);
+    if (h_done) (void)hipHostFree(h_done);
+    if (h_partial) (void)hipHostFree(h_partial);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+static Items make_items(Ctx& C, std::vector<MvItem> v) {
+  std::stable_sort(v.begin(), v.end(),
+                   [](const MvItem& a, const MvItem& b) { return (a.hi - a.lo) > (b.hi - b.lo); });
+  Items it;
+  it.n = (int64_t)v.size();
+  it.d = upload(v, C.owned, C.st);
+  return it;
+}
+
+static void build_device(Ctx& C, const double* coords) {
+  Plan& P = C.P;
+  hipStream_t st = C.st;
+  const int nsub = P.nsub;
+  C.nsub = nsub;
+  const int64_t nc = P.ncorner();
+  C.Kc = (int)((nc + NB - 1) / NB);
+  // ---- descriptors --------------------------------------------------------
+  C.subs_h.resize(nsub + 1);
+  int64_t toff = 0, roff = 0;
+  C.max_kr = 0;
+  for (int s = 0; s <= nsub; ++s) {
+    SubDev q{};
+    if (s < nsub) {
+      const SubInfo& si = P.subs[s];
+      q.nI = si.nI; q.nG = si.nG; q.nC = si.nC;
+      q.kI = si.kI; q.kG = si.kG; q.kC = si.kC; q.K = si.K;
+      C.max_kr = std::max(C.max_kr, si.kr());
+    } else {
+      q.nI = (int32_t)nc; q.nG = 0; q.nC = 0;
+      q.kI = C.Kc; q.kG = 0; q.kC = 0; q.K = C.Kc;
+      C.coarse_row0 = roff;
+    }
+    q.tile_off = toff;
+    q.row_off = roff;
+    toff += (int64_t)q.K * (q.K + 1) / 2;
+    roff += (int64_t)q.K * NB;
+    C.subs_h[s] = q;
+    if (s < nsub) {
+      P.subs[s].tile_off = q.tile_off;
+      P.subs[s].row_off = q.row_off;
+    }
+  }
+  C.ntiles = toff;
+  C.rows_total = roff;
+  const size_t wsz = C.fp32 ? 4 : 8;
+  C.d_subs = upload(C.subs_h, C.owned, st);
+  {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<int64_t>(1, C.ntiles) * kTile * wsz);
+    if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation of the factor store failed"};
+    HIPCHK(e);
+    C.owned.push_back(p);
+    C.d_tiles = p;
+  }
+  // algorithmic byte counts (unpadded, packed triangles)
+  C.factor_bytes = C.ntiles * kTile * (int64_t)wsz;
+  for (int s = 0; s < nsub; ++s) {
+    const SubInfo& q = P.subs[s];
+    int64_t nr = q.nI + q.nG;
+    C.trailing_bytes += (int64_t)q.nG * (q.nG + 1) / 2 * wsz;
+    C.coupling_bytes += (int64_t)q.nC * q.nG * wsz;
+    C.full_bytes += nr * (nr + 1) / 2 * wsz;
+  }
+  C.coarse_bytes = nc * (nc + 1) / 2 * (int64_t)wsz;
+  // scratch rows for the triangular inversion
+  {
+    std::vector<int64_t> so(nsub + 1);
+    int64_t acc = 0;
+    for (int s = 0; s <= nsub; ++s) {
+      so[s] = acc;
+      acc += C.subs_h[s].kI + C.subs_h[s].kG;
+    }
+    C.d_scratch_off = upload(so, C.owned, st);
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<int64_t>(1, acc) * kTile * wsz));
+    C.owned.push_back(p);
+    C.d_scratch = p;
+  }
+  C.d_err = dalloc<int>(1, C.owned);
+
+  // ---- mesh arrays ------------------------------------------------------------
+  std::vector<double> ch(coords, coords + 3 * P.nv);
+  C.d_coords = upload(ch, C.owned, st);
+  C.d_tsort = upload(P.tsort, C.owned, st);
+  C.d_mu = dalloc<double>(P.nt, C.owned);
+  C.d_eps = dalloc<double>(P.nt, C.owned);
+  C.d_Te = dalloc<double>(P.nt * 36, C.owned);
+  C.d_Se = dalloc<double>(P.nt * 36, C.owned);
+
+  // ---- local assembly pull lists -------------------------------------------------
+  std::vector<std::vector<int64_t>> tets_of(nsub);
+  for (int64_t t = 0; t < P.nt; ++t) tets_of[P.part[t]].push_back(t);
+  std::vector<int32_t> dof2row(P.nint, -1);
+  std::vector<int64_t> lptr{0}, ldest;
+  std::vector<int32_t> lcon;
+  std::vector<int64_t> padpos;
+  std::vector<std::pair<int64_t, int32_t>> pairs;
+  for (int s = 0; s < nsub; ++s) {
+    const SubInfo& q = P.subs[s];
+    const SubDev& qd = C.subs_h[s];
+    const auto& L = P.local[s];
+    for (int32_t p = 0; p < (int32_t)L.size(); ++p) dof2row[L[p]] = P.padded_row(s, p);
+    pairs.clear();
+    for (int64_t t : tets_of[s])
+      for (int a = 0; a < 6; ++a) {
+        int32_t da = P.dof[P.tet_edges[t * 6 + a]];
+        if (da < 0) continue;
+        for (int b = 0; b < 6; ++b) {
+          int32_t db = P.dof[P.tet_edges[t * 6 + b]];
+          if (db < 0) continue;
+          int32_t ra = dof2row[da], rb = dof2row[db];
+          if (ra < rb) continue;
+          int64_t ti = qd.tile_off + (int64_t)(ra / NB) * (ra / NB + 1) / 2 + rb / NB;
+          int64_t pos = ti * kTile + (ra % NB) * NB + (rb % NB);
+          pairs.emplace_back(pos, (int32_t)(t * 36 + a * 6 + b));
+        }
+      }
+    std::sort(pairs.begin(), pairs.end());
+    for (size_t i = 0; i < pairs.size();) {
+      size_t j = i;
+      while (j < pairs.size() && pairs[j].first == pairs[i].first) {
+        lcon.push_back(pairs[j].second);
+        ++j;
+      }
+      ldest.push_back(pairs[i].first);
+      lptr.push_back((int64_t)lcon.size());
+      i = j;
+    }
+    for (int32_t p : L) dof2row[p] = -1;
+    // padding diagonals
+    auto add_pad = [&](int32_t r0, int32_t r1) {
+      for (int32_t r = r0; r < r1; ++r) {
+        int64_t ti = qd.tile_off + (int64_t)(r / NB) * (r / NB + 1) / 2 + r / NB;
+        padpos.push_back(ti * kTile + (r % NB) * NB + (r % NB));
+      }
+    };
+    add_pad(q.nI, q.kI * NB);
+    add_pad(q.kI * NB + q.nG, q.kr() * NB);
+    add_pad(q.kr() * NB + q.nC, q.K * NB);
+  }
+  {
+    const SubDev& qc = C.subs_h[nsub];
+    for (int32_t r = (int32_t)nc; r < C.Kc * NB; ++r) {
+      int64_t ti = qc.tile_off + (int64_t)(r / NB) * (r / NB + 1) / 2 + r / NB;
+      padpos.push_back(ti * kTile + (r % NB) * NB + (r % NB));
+    }
+  }
+  C.n_lent = (int64_t)ldest.size();
+  C.d_lptr = upload(lptr, C.owned, st);
+  C.d_ldest = upload(ldest, C.owned, st);
+  C.d_lcon = upload(lcon, C.owned, st);
+  C.n_pad = (int64_t)padpos.size();
+  C.d_padpos = upload(padpos, C.owned, st);
+  std::vector<int64_t>().swap(lptr);
+  std::vector<int64_t>().swap(ldest);
+  std::vector<int32_t>().swap(lcon);
+
+  // ---- coarse assembly pull lists --------------------------------------------------
+  {
+    std::vector<std::pair<int64_t, int64_t>> cp;
+    const SubDev& qc = C.subs_h[nsub];
+    for (int s = 0; s < nsub; ++s) {
+      const SubInfo& q = P.subs[s];
+      const SubDev& qd = C.subs_h[s];
+      const auto& L = P.local[s];
+      int32_t base = q.nI + q.nG;
+      int32_t r0 = q.kr() * NB;
+      for (int32_t a = 0; a < q.nC; ++a) {
+        int32_t I = P.dof_corner[L[base + a]];
+        for (int32_t b = 0; b < q.nC; ++b) {
+          int32_t J = P.dof_corner[L[base + b]];
+          if (I < J) continue;
+          int32_t ra = r0 + a, rb = r0 + b;
+          if (ra < rb) std::swap(ra, rb);
+          int64_t sti = qd.tile_off + (int64_t)(ra / NB) * (ra / NB + 1) / 2 + rb / NB;
+          int64_t spos = sti * kTile + (ra % NB) * NB + (rb % NB);
+          int64_t dti = qc.tile_off + (int64_t)(I / NB) * (I / NB + 1) / 2 + J / NB;
+          int64_t dpos = dti * kTile + (I % NB) * NB + (J % NB);
+          cp.emplace_back(dpos, spos);
+        }
+      }
+    }
+    std::sort(cp.begin(), cp.end());
+    std::vector<int64_t> cptr{0}, csrc, cdest;
+    for (size_t i = 0; i < cp.size();) {
+      size_t j = i;
+      while (j < cp.size() && cp[j].first == cp[i].first) csrc.push_back(cp[j++].second);
+      cdest.push_back(cp[i].first);
+      cptr.push_back((int64_t)csrc.size());
+      i = j;
+    }
+    C.n_cent = (int64_t)cdest.size();
+    C.d_cptr = upload(cptr, C.owned, st);
+    C.d_csrc = upload(csrc, C.owned, st);
+    C.d_cdest = upload(cdest, C.owned, st);
+  }
+
+  // ---- global CSR pattern of (T, S) and its pull list ------------------------------
+  {
+    std::vector<std::pair<uint64_t, int32_t>> gp;
+    gp.reserve(P.nt * 36);
+    for (int64_t t = 0; t < P.nt; ++t)
+      for (int a = 0; a < 6; ++a) {
+        int32_t da = P.dof[P.tet_edges[t * 6 + a]];
+        if (da < 0) continue;
+        for (int b = 0; b < 6; ++b) {
+          int32_t db = P.dof[P.tet_edges[t * 6 + b]];
+          if (db < 0) continue;
+          gp.emplace_back((uint64_t)da * (uint64_t)P.nint + (uint64_t)db, (int32_t)(t * 36 + a * 6 + b));
+        }
+      }
+    std::sort(gp.begin(), gp.end());
+    std::vector<int64_t> rp(P.nint + 1, 0), gptr{0};
+    std::vector<int32_t> ci, gcon;
+    gcon.reserve(gp.size());
+    for (size_t i = 0; i < gp.size();) {
+      size_t j = i;
+      while (j < gp.size() && gp[j].first == gp[i].first) gcon.push_back(gp[j++].second);
+      uint64_t key = gp[i].first;
+      int64_t row = (int64_t)(key / (uint64_t)P.nint);
+      ci.push_back((int32_t)(key % (uint64_t)P.nint));
+      rp[row + 1]++;
+      gptr.push_back((int64_t)gcon.size());
+      i = j;
+    }
+    for (int64_t r = 0; r < P.nint; ++r) rp[r + 1] += rp[r];
+    C.nnz = (int64_t)ci.size();
+    C.d_rp = upload(rp, C.owned, st);
+    C.d_ci = upload(ci, C.owned, st);
+    C.d_gptr = upload(gptr, C.owned, st);
+    C.d_gcon = upload(gcon, C.owned, st);
+    C.d_vals = dalloc<double2>(C.nnz, C.owned);
+  }
+
+  // ---- vector maps -------------------------------------------------------------------
+  {
+    std::vector<int32_t> rowsrc(C.rows_total, -1);
+    std::vector<uint8_t> gamma_row(C.rows_total, 0);
+    std::vector<int64_t> grow;
+    std::vector<int32_t> glam;
+    std::vector<int64_t> cscrows, csccrow;
+    // lambda id per (subdomain, unpadded position) for interface rows
+    std::vector<std::vector<int32_t>> lam_at(nsub);
+    for (int s = 0; s < nsub; ++s) lam_at[s].assign(P.subs[s].nG, -1);
+    for (int64_t l = 0; l < P.nlambda(); ++l) {
+      int s0 = P.lam_s0[l], s1 = P.lam_s1[l];
+      lam_at[s0][P.lam_p0[l] - P.subs[s0].nI] = (int32_t)(l << 1);
+      lam_at[s1][P.lam_p1[l] - P.subs[s1].nI] = (int32_t)((l << 1) | 1);
+    }
+    for (int s = 0; s < nsub; ++s) {
+      const SubInfo& q = P.subs[s];
+      const SubDev& qd = C.subs_h[s];
+      const auto& L = P.local[s];
+      for (int32_t p = 0; p < (int32_t)L.size(); ++p) {
+        int32_t d = L[p];
+        if (P.owner[d] == s) rowsrc[qd.row_off + P.padded_row(s, p)] = d;
+      }
+      for (int32_t r = q.kI * NB; r < q.kr() * NB; ++r) {
+        gamma_row[qd.row_off + r] = 1;
+        grow.push_back(qd.row_off + r);
+        int32_t g = r - q.kI * NB;
+        glam.push_back(g < q.nG ? lam_at[s][g] : -1);
+      }
+      for (int32_t r = q.kr() * NB; r < q.K * NB; ++r) {
+        int32_t c = r - q.kr() * NB;
+        cscrows.push_back(qd.row_off + r);
+        csccrow.push_back(c < q.nC ? C.coarse_row0 + P.dof_corner[L[q.nI + q.nG + c]] : -1);
+      }
+    }
+    C.d_rowsrc = upload(rowsrc, C.owned, st);
+    C.d_gamma_row = upload(gamma_row, C.owned, st);
+    C.n_grow = (int64_t)grow.size();
+    C.d_grow = upload(grow, C.owned, st);
+    C.d_glam = upload(glam, C.owned, st);
+    C.n_csc = (int64_t)cscrows.size();
+    C.d_cscrows = upload(cscrows, C.owned, st);
+    C.d_csccrow = upload(csccrow, C.owned, st);
+    // multipliers
+    C.nlam = P.nlambda();
+    std::vector<int64_t> r0(C.nlam), r1(C.nlam);
+    for (int64_t l = 0; l < C.nlam; ++l) {
+      r0[l] = C.subs_h[P.lam_s0[l]].row_off + P.padded_row(P.lam_s0[l], P.lam_p0[l]);
+      r1[l] = C.subs_h[P.lam_s1[l]].row_off + P.padded_row(P.lam_s1[l], P.lam_p1[l]);
+    }
+    C.d_lrow0 = upload(r0, C.owned, st);
+    C.d_lrow1 = upload(r1, C.owned, st);
+    // coarse gather: corner c <- its subdomain corner rows, ascending subdomain
+    std::vector<int64_t> cgptr((int64_t)C.Kc * NB + 1, 0), cgrows;
+    std::vector<std::vector<int64_t>> byc(nc);
+    for (int s = 0; s < nsub; ++s) {
+      const SubInfo& q = P.subs[s];
+      const auto& L = P.local[s];
+      for (int32_t c = 0; c < q.nC; ++c)
+        byc[P.dof_corner[L[q.nI + q.nG + c]]].push_back(C.subs_h[s].row_off + q.kr() * NB + c);
+    }
+    for (int64_t c = 0; c < (int64_t)C.Kc * NB; ++c) {
+      if (c < nc)
+        for (int64_t r : byc[c]) cgrows.push_back(r);
+      cgptr[c + 1] = (int64_t)cgrows.size();
+    }
+    C.d_cgptr = upload(cgptr, C.owned, st);
+    C.d_cgrows = upload(cgrows, C.owned, st);
+    // owner's copy of each unknown
+    std::vector<int64_t> dsrc(P.nint);
+    for (int s = 0; s < nsub; ++s) {
+      const auto& L = P.local[s];
+      for (int32_t p = 0; p < (int32_t)L.size(); ++p) {
+        int32_t d = L[p];
+        if (P.owner[d] != s) continue;
+        dsrc[d] = P.dof_corner[d] >= 0 ? C.coarse_row0 + P.dof_corner[d]
+                                       : C.subs_h[s].row_off + P.padded_row(s, p);
+      }
+    }
+    C.d_dsrc = upload(dsrc, C.owned, st);
+    C.d_interior = upload(P.interior, C.owned, st);
+    C.d_dof = upload(P.dof, C.owned, st);
+    std::vector<int32_t> tdof(P.nt * 6);
+    for (int64_t i = 0; i < P.nt * 6; ++i) tdof[i] = P.dof[P.tet_edges[i]];
+    C.d_tdof = upload(tdof, C.owned, st);
+  }
+  // ---- Gauss-law adjacency: interior edges at each vertex ------------------------
+  {
+    std::vector<int64_t> vptr(P.nv + 1, 0);
+    for (int64_t d = 0; d < P.nint; ++d) {
+      int32_t e = P.interior[d];
+      vptr[P.edges[2 * e] + 1]++;
+      vptr[P.edges[2 * e + 1] + 1]++;
+    }
+    for (int64_t v = 0; v < P.nv; ++v) vptr[v + 1] += vptr[v];
+    std::vector<int32_t> vedge(vptr[P.nv]);
+    std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+    for (int64_t d = 0; d < P.nint; ++d) {
+      int32_t e = P.interior[d];
+      vedge[fill[P.edges[2 * e + 1]]++] = e << 1;        // head: +1
+      vedge[fill[P.edges[2 * e]]++] = (e << 1) | 1;      // tail: -1
+    }
+    C.d_vptr = upload(vptr, C.owned, st);
+    C.d_vedge = upload(vedge, C.owned, st);
+    C.d_nodeint = upload(P.node_interior, C.owned, st);
+    C.d_vres = dalloc<double>(P.nv * C.nrhs, C.owned);
+  }
+  // ---- work lists --------------------------------------------------------------------
+  {
+    std::vector<MvItem> fN, fT, tN, tT, rN, rT, gN, gT, oN, oT;
+    for (int s = 0; s < nsub; ++s) {
+      const SubDev& q = C.subs_h[s];
+      int kr = q.kI + q.kG;
+      for (int o = 0; o < kr; ++o) {
+        fN.push_back({s, o, 0, o + 1});
+        fT.push_back({s, o, o, kr});
+        rT.push_back({s, o, kr, q.K});
+      }
+      for (int o = q.kI; o < kr; ++o) {
+        tN.push_back({s, o, q.kI, o + 1});
+        tT.push_back({s, o, o, kr});
+        gT.push_back({s, o, kr, q.K});
+      }
+      for (int o = kr; o < q.K; ++o) {
+        rN.push_back({s, o, 0, kr});
+        gN.push_back({s, o, q.kI, kr});
+      }
+    }
+    for (int o = 0; o < C.Kc; ++o) {
+      oN.push_back({nsub, o, 0, o + 1});
+      oT.push_back({nsub, o, o, C.Kc});
+    }
+    C.full_N = make_items(C, fN);
+    C.full_T = make_items(C, fT);
+    C.trail_N = make_items(C, tN);
+    C.trail_T = make_items(C, tT);
+    C.cr_N = make_items(C, rN);
+    C.cr_T = make_items(C, rT);
+    C.cg_N = make_items(C, gN);
+    C.cg_T = make_items(C, gT);
+    C.co_N = make_items(C, oN);
+    C.co_T = make_items(C, oT);
+  }
+  // ---- work vectors --------------------------------------------------------------------
+  const int nr = C.nrhs;
+  for (int i = 0; i < 9; ++i) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<int64_t>(1, C.rows_total) * nr * wsz);
+    if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation failed"};
+    HIPCHK(e);
+    C.owned.push_back(p);
+    C.X[i] = p;
+    HIPCHK(hipMemsetAsync(p, 0, std::max<int64_t>(1, C.rows_total) * nr * wsz, st));
+  }
+  const int64_t nl = std::max<int64_t>(1, C.nlam) * nr;
+  C.d_d = dalloc<double>(nl, C.owned);
+  C.d_lam = dalloc<double>(nl, C.owned);
+  C.d_res = dalloc<double>(nl, C.owned);
+  C.d_p = dalloc<double>(nl, C.owned);
+  C.d_Fp = dalloc<double>(nl, C.owned);
+  C.d_lam_prev = dalloc<double>(nl, C.owned);
+  C.d_lam_prev_adj = dalloc<double>(nl, C.owned);
+  C.d_partial = dalloc<double>(kDotBlocks * kMaxRhs, C.owned);
+  C.d_cg = dalloc<CgState>(1, C.owned);
+  HIPCHK(hipHostMalloc((void**)&C.h_done, sizeof(int) * 4, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&C.h_partial, sizeof(double) * kDotBlocks * kMaxRhs, hipHostMallocDefault));
+  const int64_t ng = std::max<int64_t>(1, P.nint) * nr;
+  C.g_b = dalloc<double>(ng, C.owned);
+  C.g_e = dalloc<double>(ng, C.owned);
+  C.g_r = dalloc<double>(ng, C.owned);
+  C.g_x = dalloc<double>(ng, C.owned);
+  C.g_t1 = dalloc<double>(ng, C.owned);
+  C.g_t2 = dalloc<double>(ng, C.owned);
+  C.g_t3 = dalloc<double>(ng, C.owned);
+  C.g_t4 = dalloc<double>(ng, C.owned);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// factor
+// ---------------------------------------------------------------------------
+template <class T>
+static void factor_range(Ctx& C, int s0, int cnt) {
+  hipStream_t st = C.st;
+  T* tiles = (T*)C.d_tiles;
+  int max_kr = 0;
+  for (int s = s0; s < s0 + cnt; ++s)
+    max_kr = std::max(max_kr, C.subs_h[s].kI + C.subs_h[s].kG);
+  for (int k = 0; k < max_kr; ++k) {
+    int tmax = 0;
+    for (int s = s0; s < s0 + cnt; ++s) {
+      const SubDev& q = C.subs_h[s];
+      if (k < q.kI + q.kG) tmax = std::max(tmax, q.K - k - 1);
+    }
+    hipLaunchKernelGGL(k_potrf<T>, dim3(cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs, C.d_err);
+    if (tmax > 0) {
+      hipLaunchKernelGGL(k_trsm<T>, dim3(tmax, cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs);
+      int64_t np = (int64_t)tmax * (tmax + 1) / 2;
+      hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)np, cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs);
+    }
+  }
+  for (int i = 1; i < max_kr; ++i) {
+    hipLaunchKernelGGL(k_trtri_row<T>, dim3(i, cnt), dim3(256), 0, st, i, s0, (const T*)tiles, C.d_subs,
+                       C.d_scratch_off, (T*)C.d_scratch);
+    hipLaunchKernelGGL(k_trtri_copy<T>, dim3(i, cnt), dim3(256), 0, st, i, s0, tiles, C.d_subs,
+                       C.d_scratch_off, (const T*)C.d_scratch);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <class T>
+static int factor_impl(Ctx& C) {
+  Plan& P = C.P;
+  hipStream_t st = C.st;
+  T* tiles = (T*)C.d_tiles;
+  HIPCHK(hipMemsetAsync(tiles, 0, std::max<int64_t>(1, C.ntiles) * kTile * sizeof(T), st));
+  int big = INT32_MAX;
+  HIPCHK(hipMemcpyAsync(C.d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_element, dim3(nblk(P.nt)), dim3(256), 0, st, (int64_t)P.nt, C.d_coords, C.d_tsort,
+                     C.d_mu, C.d_Te, C.d_Se);
+  hipLaunchKernelGGL(k_pull_local<T>, dim3(nblk(C.n_lent)), dim3(256), 0, st, C.n_lent, C.d_lptr, C.d_lcon,
+                     C.d_ldest, C.d_Te, C.d_Se, C.d_eps, C.beta * C.dt * C.dt, tiles);
+  if (C.n_pad)
+    hipLaunchKernelGGL(k_pad_diag<T>, dim3(nblk(C.n_pad)), dim3(256), 0, st, C.n_pad, C.d_padpos, tiles);
+  hipLaunchKernelGGL(k_pull_csr, dim3(nblk(C.nnz)), dim3(256), 0, st, C.nnz, C.d_gptr, C.d_gcon, C.d_Te,
+                     C.d_Se, C.d_eps, C.d_vals);
+  HIPCHK(hipGetLastError());
+  factor_range<T>(C, 0, C.nsub);
+  if (C.Kc > 0) {
+    if (C.n_cent)
+      hipLaunchKernelGGL(k_pull_coarse<T>, dim3(nblk(C.n_cent)), dim3(256), 0, st, C.n_cent, C.d_cptr,
+                         C.d_csrc, C.d_cdest, tiles);
+    factor_range<T>(C, C.nsub, 1);
+  }
+  int err = 0;
+  HIPCHK(hipMemcpyAsync(&err, C.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (err != INT32_MAX) {
+    C.factored = false;
+    if (err == C.nsub) throw DDError{DD_ERR_NOT_SPD, "coarse corner matrix is not positive definite"};
+    throw DDError{DD_ERR_NOT_SPD, "non-positive pivot in subdomain " + std::to_string(err)};
+  }
+  C.factored = true;
+  C.have_prev = C.have_prev_adj = false;
+  return DD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+template <class T>
+static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
+               const int* skip = nullptr) {
+  if (it.n == 0) return;
+  if (trans)
+    hipLaunchKernelGGL((k_tile_mv<T, true>), dim3((unsigned)it.n), dim3(256), 0, C.st, it.n, it.d, C.d_subs,
+                       (const T*)C.d_tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, skip);
+  else
+    hipLaunchKernelGGL((k_tile_mv<T, false>), dim3((unsigned)it.n), dim3(256), 0, C.st, it.n, it.d, C.d_subs,
+                       (const T*)C.d_tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, skip);
+}
+
+// coarse: y rows of Xin (coarse block) -> Xout coarse rows = K_cc^-1 y via
+// Linv then Linv^T (tmp holds the intermediate)
+template <class T>
+static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* skip) {
+  mv<T>(C, C.co_N, false, Xin, Xtmp, nullptr, (T)1, skip);
+  mv<T>(C, C.co_T, true, Xtmp, Xout, nullptr, (T)1, skip);
+}
+
+// F p -> Fp (uses X5..X8)
+template <class T>
+static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip) {
+  const int nr = C.nrhs;
+  hipStream_t st = C.st;
+  void **X = C.X;
+  hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                     C.d_glam, p, (T*)X[5], nr, skip);
+  mv<T>(C, C.trail_N, false, X[5], X[6], nullptr, (T)1, skip);
+  if (C.Kc > 0) {
+    mv<T>(C, C.cg_N, false, X[6], X[6], nullptr, (T)1, skip);
+    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
+                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
+                       (const T*)nullptr, nr, skip);
+    coarse_solve<T>(C, X[6], X[7], X[5], skip);
+    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
+                       C.d_csccrow, (const T*)X[5], (T*)X[5], nr, skip);
+    mv<T>(C, C.cg_T, true, X[5], X[7], X[6], (T)1, skip);
+    mv<T>(C, C.trail_T, true, X[7], X[8], nullptr, (T)1, skip);
+  } else {
+    mv<T>(C, C.trail_T, true, X[6], X[8], nullptr, (T)1, skip);
+  }
+  hipLaunchKernelGGL(k_lambda_scatter<T>, dim3(nblk(C.nlam * nr)), dim3(256), 0, st, C.nlam, C.d_lrow0,
+                     C.d_lrow1, (const T*)X[8], Fp, nr, skip);
+}
+
+static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, double* out) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, C.st, n, x, y, C.nrhs, C.d_partial,
+                     (const int*)nullptr);
+  HIPCHK(hipMemcpyAsync(C.h_partial, C.d_partial, sizeof(double) * kDotBlocks * kMaxRhs, hipMemcpyDeviceToHost,
+                        C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+  for (int r = 0; r < C.nrhs; ++r) {
+    double s = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) s += C.h_partial[b * kMaxRhs + r];
+    out[r] = s;
+  }
+}
+
+// x = A^-1 b (one decomposed solve, unknown-major [nint][nrhs] FP64).
+// Returns DD_OK or DD_ERR_NO_CONVERGENCE; fills iters/relres.
+template <class T>
+static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* lam_prev, bool* have_prev,
+                         int* iters, double* relres) {
+  const int nr = C.nrhs;
+  hipStream_t st = C.st;
+  void** X = C.X;
+  const T one = 1, mone = -1;
+  // ---- pre-solve --------------------------------------------------------
+  hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
+                     (T*)X[0], nr);
+  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one);
+  mv<T>(C, C.cr_N, false, X[1], X[1], X[0], mone);  // corner rows: w_c - L_cr t
+  if (C.Kc > 0) {
+    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
+                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[1], (T*)X[1],
+                       (const T*)nullptr, nr, (const int*)nullptr);
+    coarse_solve<T>(C, X[1], X[2], X[3], nullptr);
+    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
+                       C.d_csccrow, (const T*)X[3], (T*)X[3], nr, (const int*)nullptr);
+    mv<T>(C, C.cg_T, true, X[3], X[2], X[1], mone);  // t_G - L_cG^T z0
+    mv<T>(C, C.trail_T, true, X[2], X[4], nullptr, one);
+  } else {
+    mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one);
+  }
+  for (int r = 0; r < nr; ++r) {
+    iters[r] = 0;
+    relres[r] = 0.0;
+  }
+  int status = DD_OK;
+  if (C.nlam > 0) {
+    const int64_t nl = C.nlam * nr;
+    hipLaunchKernelGGL(k_lambda_scatter<T>, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
+                       (const T*)X[4], C.d_d, nr, (const int*)nullptr);
+    // ---- CG on F lambda = d ----------------------------------------------------
+    HIPCHK(hipMemsetAsync(C.d_cg, 0, sizeof(CgState), st));
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
+                       C.d_partial, (const int*)nullptr);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+    HIPCHK(hipMemcpyAsync(C.d_res, C.d_d, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (warm && *have_prev) {
+      HIPCHK(hipMemcpyAsync(C.d_lam, lam_prev, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+      apply_F<T>(C, C.d_lam, C.d_Fp, nullptr);
+      hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_d, C.d_Fp, C.d_res);
+      hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
+                         C.d_partial, (const int*)nullptr);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 3, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+    } else {
+      HIPCHK(hipMemsetAsync(C.d_lam, 0, nl * sizeof(double), st));
+    }
+    HIPCHK(hipMemcpyAsync(C.d_p, C.d_res, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    const int* done = &C.d_cg->done;
+    int it = 0;
+    const int chk = std::max(1, C.opt.check_every);
+    bool converged = false;
+    HIPCHK(hipMemcpyAsync(C.h_done, done, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    converged = *C.h_done != 0;
+    while (!converged && it < C.opt.cg_max_iter) {
+      int todo = std::min(chk, C.opt.cg_max_iter - it);
+      for (int k = 0; k < todo; ++k) {
+        apply_F<T>(C, C.d_p, C.d_Fp, done);
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_p, C.d_Fp, nr,
+                           C.d_partial, done);
+        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+        hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_p, C.d_Fp,
+                           C.d_lam, C.d_res);
+        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
+                           C.d_partial, done);
+        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+        hipLaunchKernelGGL(k_cg_p, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_res, C.d_p);
+      }
+      it += todo;
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(C.h_done, done, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      converged = *C.h_done != 0;
+    }
+    CgState hs;
+    HIPCHK(hipMemcpyAsync(&hs, C.d_cg, sizeof(CgState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int r = 0; r < nr; ++r) {
+      iters[r] = hs.iters[r];
+      relres[r] = hs.rr0[r] > 0 ? std::sqrt(hs.rr[r] / hs.rr0[r]) : 0.0;
+    }
+    if (!converged || hs.breakdown) status = DD_ERR_NO_CONVERGENCE;
+    if (lam_prev) {
+      HIPCHK(hipMemcpyAsync(lam_prev, C.d_lam, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+      *have_prev = true;
+    }
+    // ---- recovery -------------------------------------------------------------------
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                       C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, (const int*)nullptr);
+    mv<T>(C, C.trail_N, false, X[5], X[6], nullptr, one);
+  } else {
+    // no interface: t_l = 0
+    HIPCHK(hipMemsetAsync(X[6], 0, C.rows_total * nr * sizeof(T), st));
+  }
+  if (C.Kc > 0) {
+    mv<T>(C, C.cg_N, false, X[6], X[6], nullptr, one);
+    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
+                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
+                       (const T*)X[1], nr, (const int*)nullptr);
+    coarse_solve<T>(C, X[6], X[7], X[5], nullptr);
+    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
+                       C.d_csccrow, (const T*)X[5], (T*)X[5], nr, (const int*)nullptr);
+  }
+  hipLaunchKernelGGL(k_sub_rows<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_gamma_row,
+                     (const T*)X[1], (const T*)X[6], (T*)X[8], nr);
+  mv<T>(C, C.cr_T, true, X[5], X[7], X[8], mone);
+  mv<T>(C, C.full_T, true, X[7], X[5], nullptr, one);
+  hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
+                     (const T*)X[5], x, nr);
+  HIPCHK(hipGetLastError());
+  return status;
+}
+
+// A^-1 b with iterative refinement in the mixed form.  b, x: [nint][nrhs].
+template <class T>
+static int solve_refined(Ctx& C, const double* b, double* x, bool warm, double* lam_prev, bool* have_prev,
+                         dd_stats* stats) {
+  const int nr = C.nrhs;
+  const int64_t n = C.P.nint * nr;
+  hipStream_t st = C.st;
+  int iters[kMaxRhs];
+  double relres[kMaxRhs];
+  int status = dd_solve_once<T>(C, b, x, warm, lam_prev, have_prev, iters, relres);
+  int sweeps = 0;
+  double gres[kMaxRhs] = {0};
+  if (C.fp32 && C.opt.refine_max > 0) {
+    double bn[kMaxRhs];
+    dot_to_host(C, b, b, C.P.nint, bn);
+    for (;;) {
+      hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 1, (int64_t)C.P.nint, C.d_rp, C.d_ci, C.d_vals,
+                         (const double*)x, (const double*)nullptr, (const double*)nullptr,
+                         (const double*)nullptr, b, C.dt, C.beta * C.dt * C.dt,
+                         (2 * C.beta - 1) * C.dt * C.dt, C.g_r, (double*)nullptr, nr);
+      double rn[kMaxRhs];
+      dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
+      bool ok = true;
+      for (int r = 0; r < nr; ++r) {
+        gres[r] = bn[r] > 0 ? std::sqrt(rn[r] / bn[r]) : 0.0;
+        if (!(gres[r] <= C.opt.refine_tol)) ok = false;
+      }
+      if (ok) break;
+      if (sweeps >= C.opt.refine_max) {
+        status = DD_ERR_NO_CONVERGENCE;
+        break;
+      }
+      int it2[kMaxRhs];
+      double rr2[kMaxRhs];
+      int s2 = dd_solve_once<T>(C, C.g_r, C.g_t4, false, nullptr, nullptr, it2, rr2);
+      if (s2 != DD_OK) status = s2;
+      for (int r = 0; r < nr; ++r) iters[r] += it2[r];
+      hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t4, x);
+      ++sweeps;
+    }
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(dd_stats));
+    for (int r = 0; r < nr; ++r) {
+      stats->cg_iters[r] = iters[r];
+      stats->cg_relres[r] = relres[r];
+      stats->global_relres[r] = gres[r];
+    }
+    stats->refine_sweeps = sweeps;
+    stats->dd_solves = 1 + sweeps;
+  }
+  return status;
+}
+
+template <class T>
+static int step_impl(Ctx& C, const double* J1, const double* J0, const double* En, const double* Enm1,
+                     double* Enext, dd_stats* stats) {
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne;
+  hipStream_t st = C.st;
+  const int64_t n = ni * nr;
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, En, ne, C.g_t1, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, Enm1, ne, C.g_t2, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, J0, ne, C.g_x, nr, 1.0);
+  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 0, ni, C.d_rp, C.d_ci, C.d_vals,
+                     (const double*)C.g_t1, (const double*)C.g_t2, (const double*)C.g_t3, (const double*)C.g_x,
+                     (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_b,
+                     (double*)nullptr, nr);
+  int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start != 0, C.d_lam_prev, &C.have_prev, stats);
+  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
+                     Enext, nr, 0, 1.0);
+  HIPCHK(hipGetLastError());
+  return status;
+}
+
+template <class T>
+static int solve_api_impl(Ctx& C, const double* b, double* x, dd_stats* stats) {
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne;
+  hipStream_t st = C.st;
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni * nr)), dim3(256), 0, st, ni, C.d_interior, b, ne, C.g_t1, nr,
+                     1.0);
+  int status = solve_refined<T>(C, C.g_t1, C.g_e, false, nullptr, nullptr, stats);
+  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e, x,
+                     nr, 0, 1.0);
+  HIPCHK(hipGetLastError());
+  return status;
+}
+
+template <class T>
+static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double* ebar_nm1, double* g_out,
+                        const double* E_next, const double* E_n, const double* E_nm1, double* eps_bar,
+                        dd_stats* stats) {
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne;
+  hipStream_t st = C.st;
+  const int64_t n = ni * nr;
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, ebar_next, ne, C.g_t1, nr,
+                     1.0);
+  int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start != 0, C.d_lam_prev_adj, &C.have_prev_adj,
+                                stats);
+  // B1 g -> g_t2, A g -> g_t3
+  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 2, ni, C.d_rp, C.d_ci, C.d_vals, (const double*)C.g_x,
+                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_t2,
+                     C.g_t3, nr);
+  if (ebar_n)
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t2,
+                       ebar_n, nr, 1, 1.0);
+  if (ebar_nm1)
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t3,
+                       ebar_nm1, nr, 1, -1.0);
+  if (g_out)
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_x,
+                       g_out, nr, 0, 1.0);
+  if (eps_bar) {
+    // acc = e^{n+1} - 2 e^n + e^{n-1} in unknown-major layout
+    hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
+                       1.0);
+    hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
+                       1.0);
+    if (E_nm1)
+      hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_nm1, ne, C.g_t4,
+                         nr, 1.0);
+    hipLaunchKernelGGL(k_second_diff, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t2,
+                       (const double*)C.g_t3, (const double*)(E_nm1 ? C.g_t4 : nullptr), C.g_t2);
+    hipLaunchKernelGGL(k_eps_bar, dim3(nblk(C.P.nt)), dim3(256), 0, st, (int64_t)C.P.nt, C.d_tdof, C.d_Te,
+                       (const double*)C.g_x, (const double*)C.g_t2, nr, eps_bar);
+  }
+  HIPCHK(hipGetLastError());
+  return status;
+}
+
+}  // namespace ddfem
+
+using namespace ddfem;
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+#define API_BEGIN try {
+#define API_END                                 \
+  }                                             \
+  catch (const DDError& e) {                    \
+    g_err = e.msg;                              \
+    return e.code;                              \
+  }                                             \
+  catch (const std::bad_alloc&) {               \
+    g_err = "host allocation failed";           \
+    return DD_ERR_OOM;                          \
+  }                                             \
+  catch (const std::exception& e) {             \
+    g_err = e.what();                           \
+    return DD_ERR_ARG;                          \
+  }
+
+extern "C" {
+
+void dd_default_options(dd_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = DD_FP64;
+  o->nrhs = 1;
+  o->cg_tol = 1e-10;
+  o->cg_max_iter = 500;
+  o->refine_tol = 1e-12;
+  o->refine_max = 10;
+  o->warm_start = 1;
+  o->use_graph = 0;
+  o->check_every = 4;
+  o->stream = nullptr;
+}
+
+const char* dd_last_error(void) { return g_err.c_str(); }
+
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tets, const int32_t* tets,
+             const int32_t* partition, const double* eps, const double* mu, double dt, double beta,
+             const dd_options* opt) {
+  g_err.clear();
+  if (!out) {
+    g_err = "out is NULL";
+    return DD_ERR_ARG;
+  }
+  *out = nullptr;
+  Ctx* C = nullptr;
+  API_BEGIN
+  if (!coords || !tets || !partition || !eps) throw DDError{DD_ERR_ARG, "null input pointer"};
+  if (!std::isfinite(dt) || !std::isfinite(beta)) throw DDError{DD_ERR_NONFINITE, "non-finite dt or beta"};
+  if (!(dt > 0) || !(beta > 0)) throw DDError{DD_ERR_ARG, "dt and beta must be positive"};
+  dd_options o;
+  dd_default_options(&o);
+  if (opt) o = *opt;
+  if (o.nrhs < 1 || o.nrhs > kMaxRhs) throw DDError{DD_ERR_ARG, "nrhs must be in 1..32"};
+  if (o.precision != DD_FP64 && o.precision != DD_FP32_REFINE) throw DDError{DD_ERR_ARG, "unknown precision"};
+  if (!(o.cg_tol > 0) || o.cg_max_iter < 1 || o.check_every < 1 || o.refine_max < 0 || !(o.refine_tol > 0))
+    throw DDError{DD_ERR_ARG, "bad solver option"};
+  for (int64_t t = 0; t < n_tets; ++t) {
+    if (!std::isfinite(eps[t]) || (mu && !std::isfinite(mu[t])))
+      throw DDError{DD_ERR_NONFINITE, "non-finite eps or mu at tetrahedron " + std::to_string(t)};
+    if (!finite_pos(eps[t]) || (mu && !finite_pos(mu[t])))
+      throw DDError{DD_ERR_ARG, "eps and mu must be positive (tetrahedron " + std::to_string(t) + ")"};
+  }
+  C = new Ctx();
+  C->opt = o;
+  C->st = (hipStream_t)o.stream;
+  C->dt = dt;
+  C->beta = beta;
+  C->nrhs = o.nrhs;
+  C->fp32 = o.precision == DD_FP32_REFINE;
+  std::string msg;
+  int rc = build_plan(n_vertices, coords, n_tets, tets, partition, C->P, msg);
+  if (rc != DD_OK) throw DDError{rc, msg};
+  build_device(*C, coords);
+  std::vector<double> mh(n_tets, 1.0);
+  if (mu) mh.assign(mu, mu + n_tets);
+  HIPCHK(hipMemcpyAsync(C->d_mu, mh.data(), n_tets * sizeof(double), hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipMemcpyAsync(C->d_eps, eps, n_tets * sizeof(double), hipMemcpyHostToDevice, C->st));
+  HIPCHK(hipStreamSynchronize(C->st));
+  *out = C;
+  return DD_OK;
+  }
+  catch (const DDError& e) {
+    g_err = e.msg;
+    delete C;
+    return e.code;
+  }
+  catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    delete C;
+    return DD_ERR_OOM;
+  }
+  catch (const std::exception& e) {
+    g_err = e.what();
+    delete C;
+    return DD_ERR_ARG;
+  }
+}
+
+int dd_get_info(void* ctx, dd_info* info) {
+  if (!ctx || !info) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  std::memset(info, 0, sizeof(*info));
+  info->n_edges = C.P.ne;
+  info->n_interior = C.P.nint;
+  info->n_tets = C.P.nt;
+  info->n_vertices = C.P.nv;
+  info->n_sub = C.nsub;
+  info->n_lambda = (int32_t)C.nlam;
+  info->n_corner = (int32_t)C.P.ncorner();
+  info->nrhs = C.nrhs;
+  info->precision = C.fp32 ? DD_FP32_REFINE : DD_FP64;
+  info->tile = NB;
+  info->factor_bytes = C.factor_bytes;
+  info->trailing_bytes = C.trailing_bytes;
+  info->coupling_bytes = C.coupling_bytes;
+  info->coarse_bytes = C.coarse_bytes;
+  info->full_bytes = C.full_bytes;
+  return DD_OK;
+}
+
+int dd_get_edges(void* ctx, int32_t* edges, uint8_t* is_pec) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (edges) std::memcpy(edges, C.P.edges.data(), C.P.edges.size() * sizeof(int32_t));
+  if (is_pec) std::memcpy(is_pec, C.P.pec.data(), C.P.pec.size());
+  return DD_OK;
+}
+
+int dd_set_eps(void* ctx, const double* eps) {
+  if (!ctx || !eps) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  for (int64_t t = 0; t < C.P.nt; ++t) {
+    if (!std::isfinite(eps[t])) throw DDError{DD_ERR_NONFINITE, "non-finite eps"};
+    if (!(eps[t] > 0)) throw DDError{DD_ERR_ARG, "eps must be positive"};
+  }
+  HIPCHK(hipMemcpyAsync(C.d_eps, eps, C.P.nt * sizeof(double), hipMemcpyHostToDevice, C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+  C.factored = false;
+  return DD_OK;
+  API_END
+}
+
+int dd_factor(void* ctx) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  return C.fp32 ? factor_impl<float>(C) : factor_impl<double>(C);
+  API_END
+}
+
+int dd_step(void* ctx, const double* J_half, const double* J_prev_half, const double* E_n, const double* E_nm1,
+            double* E_next, dd_stats* stats) {
+  if (!ctx || !J_half || !J_prev_half || !E_n || !E_nm1 || !E_next) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_step called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  API_BEGIN
+  int rc = C.fp32 ? step_impl<float>(C, J_half, J_prev_half, E_n, E_nm1, E_next, stats)
+                  : step_impl<double>(C, J_half, J_prev_half, E_n, E_nm1, E_next, stats);
+  if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
+  return rc;
+  API_END
+}
+
+int dd_solve(void* ctx, const double* b, double* x, dd_stats* stats) {
+  if (!ctx || !b || !x) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_solve called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  API_BEGIN
+  int rc = C.fp32 ? solve_api_impl<float>(C, b, x, stats) : solve_api_impl<double>(C, b, x, stats);
+  if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
+  return rc;
+  API_END
+}
+
+int dd_adjoint_step(void* ctx, const double* ebar_next, double* ebar_n, double* ebar_nm1, double* g_out,
+                    const double* E_next, const double* E_n, const double* E_nm1, double* eps_bar,
+                    dd_stats* stats) {
+  if (!ctx || !ebar_next || (eps_bar && (!E_next || !E_n))) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_adjoint_step called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  API_BEGIN
+  int rc = C.fp32 ? adjoint_impl<float>(C, ebar_next, ebar_n, ebar_nm1, g_out, E_next, E_n, E_nm1, eps_bar, stats)
+                  : adjoint_impl<double>(C, ebar_next, ebar_n, ebar_nm1, g_out, E_next, E_n, E_nm1, eps_bar,
+                                         stats);
+  if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
+  return rc;
+  API_END
+}
+
+int dd_charge_update(void* ctx, const double* J_half, double* q) {
+  if (!ctx || !J_half || !q) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  int64_t n = C.P.nv * C.nrhs;
+  hipLaunchKernelGGL(k_charge, dim3(nblk(n)), dim3(256), 0, C.st, (int64_t)C.P.nv, C.d_vptr, C.d_vedge,
+                     C.d_nodeint, J_half, (int64_t)C.P.ne, C.dt, q, C.nrhs);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
+  API_END
+}
+
+int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res) {
+  if (!ctx || !E || !q || !res) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne, nv = C.P.nv;
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni * nr)), dim3(256), 0, C.st, ni, C.d_interior, E, ne, C.g_t1, nr,
+                     1.0);
+  hipLaunchKernelGGL(k_csr, dim3(nblk(ni * nr)), dim3(256), 0, C.st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+                     (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t2, C.g_t3, nr);
+  double* d_res = C.d_vres;
+  hipLaunchKernelGGL(k_gauss, dim3(nblk(nv * nr)), dim3(256), 0, C.st, nv, C.d_vptr, C.d_vedge, C.d_nodeint,
+                     C.d_dof, (const double*)C.g_t2, q, nr, d_res);
+  std::vector<double> h(nv * nr);
+  HIPCHK(hipMemcpyAsync(h.data(), d_res, nv * nr * sizeof(double), hipMemcpyDeviceToHost, C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+  for (int r = 0; r < nr; ++r) {
+    double m = 0.0;
+    for (int64_t v = 0; v < nv; ++v) m = std::max(m, std::fabs(h[r * nv + v]));
+    res[r] = m;
+  }
+  return DD_OK;
+  API_END
+}
+
+int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
+  if (!ctx || !E_next || !E_n || !out) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne, n = ni * nr;
+  hipStream_t st = C.st;
+  // g_t1 = (e1 - e0)/dt, g_t2 = (e1 + e0)/2
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t1, nr,
+                     1.0 / C.dt);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
+                     1.0 / C.dt);
+  hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t1, (const double*)C.g_t3,
+                     C.g_t1);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
+                     0.5);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr, 0.5);
+  hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t3, C.g_t2);
+  // T dv -> g_t3 (S dv unused -> g_t4); then S av -> g_x (T av -> g_t4)
+  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+                     (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t3, C.g_t4, nr);
+  double a[kMaxRhs], b[kMaxRhs];
+  dot_to_host(C, C.g_t1, C.g_t3, ni, a);
+  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+                     (const double*)C.g_t2, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t4, C.g_x, nr);
+  dot_to_host(C, C.g_t2, C.g_x, ni, b);
+  for (int r = 0; r < nr; ++r) out[r] = a[r] + b[r];
+  return DD_OK;
+  API_END
+}
+
+void dd_destroy(void* ctx) { delete (Ctx*)ctx; }
+
+int dd_analyze(int64_t n_vertices, const double* coords, int64_t n_tets, const int32_t* tets,
+               const int32_t* partition, dd_analysis* out, int32_t* per_sub) {
+  g_err.clear();
+  if (!out) {
+    g_err = "out is NULL";
+    return DD_ERR_ARG;
+  }
+  API_BEGIN
+  Plan P;
+  std::string msg;
+  int rc = build_plan(n_vertices, coords, n_tets, tets, partition, P, msg);
+  if (rc != DD_OK) throw DDError{rc, msg};
+  std::memset(out, 0, sizeof(*out));
+  out->n_edges = P.ne;
+  out->n_interior = P.nint;
+  out->n_sub = P.nsub;
+  out->n_lambda = (int32_t)P.nlambda();
+  out->n_corner = (int32_t)P.ncorner();
+  out->max_multiplicity = P.max_mult;
+  for (int s = 0; s < P.nsub; ++s) {
+    int64_t nr = P.subs[s].nI + P.subs[s].nG;
+    out->sum_nr3 += nr * nr * nr;
+    if (per_sub) {
+      per_sub[3 * s] = P.subs[s].nI;
+      per_sub[3 * s + 1] = P.subs[s].nG;
+      per_sub[3 * s + 2] = P.subs[s].nC;
+    }
+  }
+  return DD_OK;
+  API_END
+}
+
+int dd_analyze_lambda(int64_t n_vertices, const double* coords, int64_t n_tets, const int32_t* tets,
+                      const int32_t* partition, int32_t* edge, int32_t* sub_lo, int32_t* sub_hi, int32_t* pos_lo,
+                      int32_t* pos_hi) {
+  g_err.clear();
+  API_BEGIN
+  Plan P;
+  std::string msg;
+  int rc = build_plan(n_vertices, coords, n_tets, tets, partition, P, msg);
+  if (rc != DD_OK) throw DDError{rc, msg};
+  for (int64_t l = 0; l < P.nlambda(); ++l) {
+    if (edge) edge[l] = P.interior[P.lam_dof[l]];
+    if (sub_lo) sub_lo[l] = P.lam_s0[l];
+    if (sub_hi) sub_hi[l] = P.lam_s1[l];
+    if (pos_lo) pos_lo[l] = P.lam_p0[l];
+    if (pos_hi) pos_hi[l] = P.lam_p1[l];
+  }
+  return DD_OK;
+  API_END
+}
+
+}  // extern "C"

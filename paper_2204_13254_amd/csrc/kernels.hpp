@@ -1,0 +1,782 @@
+// Device kernels of the domain-decomposed Newmark solve (gfx950, wave64).
+//
+// Storage: every dense per-subdomain matrix (and the coarse corner matrix)
+// is a packed lower triangle of NB x NB tiles, tile (i, j), i >= j, at
+// tile index tile_off + i(i+1)/2 + j, each tile row-major.  Local vectors
+// are [rows][nrhs] row-major with rows = K*NB per subdomain.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ddfem {
+
+constexpr int kNB = 32;
+constexpr int kTile = kNB * kNB;
+constexpr int kMaxRhs = 32;
+
+struct SubDev {
+  int32_t nI, nG, nC;
+  int32_t kI, kG, kC, K;
+  int32_t pad_;
+  int64_t tile_off;
+  int64_t row_off;
+};
+
+__device__ __forceinline__ int64_t tile_index(const SubDev& q, int i, int j) {
+  return q.tile_off + (int64_t)i * (i + 1) / 2 + j;
+}
+
+// --------------------------------------------------------------------------
+// K1: element matrices (Sec. II-B-1, Whitney 1-forms), FP64.
+// Te[(ij),(kl)] = eps V/20 [(1+d_ik) g_j.g_l - (1+d_il) g_j.g_k
+//                          - (1+d_jk) g_i.g_l + (1+d_jl) g_i.g_k]
+// Se[(ij),(kl)] = (4V/mu) (g_i x g_j).(g_k x g_l)
+// with g = grad(barycentric), local edges 01,02,03,12,13,23 of the sorted
+// tetrahedron.  Te is stored with eps = 1 (unit mass) and scaled where used.
+// --------------------------------------------------------------------------
+__global__ void k_element(int64_t nt, const double* __restrict__ coords,
+                          const int32_t* __restrict__ tsort, const double* __restrict__ mu,
+                          double* __restrict__ Te, double* __restrict__ Se) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  double x[4][3];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 3; ++c) x[a][c] = coords[3 * (int64_t)tsort[4 * t + a] + c];
+  double d[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) d[a][c] = x[a + 1][c] - x[0][c];
+  // rows of inverse of D (D has columns d[a]) are grad lam_1..3:
+  // inv(D) = adj(D)/det, with D[c][a] = d[a][c]
+  double D[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) D[r][c] = d[c][r];
+  double det = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) -
+               D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+               D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+  double inv = 1.0 / det;
+  double g[4][3];
+  g[1][0] = (D[1][1] * D[2][2] - D[1][2] * D[2][1]) * inv;
+  g[1][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * inv;
+  g[1][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * inv;
+  g[2][0] = (D[1][2] * D[2][0] - D[1][0] * D[2][2]) * inv;
+  g[2][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * inv;
+  g[2][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * inv;
+  g[3][0] = (D[1][0] * D[2][1] - D[1][1] * D[2][0]) * inv;
+  g[3][1] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) * inv;
+  g[3][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * inv;
+  for (int c = 0; c < 3; ++c) g[0][c] = -(g[1][c] + g[2][c] + g[3][c]);
+  double V = fabs(det) / 6.0;
+  double gg[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) gg[a][b] = g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2];
+  const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  double cr[6][3];
+  for (int e = 0; e < 6; ++e) {
+    const double* u = g[LE[e][0]];
+    const double* v = g[LE[e][1]];
+    cr[e][0] = u[1] * v[2] - u[2] * v[1];
+    cr[e][1] = u[2] * v[0] - u[0] * v[2];
+    cr[e][2] = u[0] * v[1] - u[1] * v[0];
+  }
+  double m = V / 20.0, sc = 4.0 * V / mu[t];
+  for (int A = 0; A < 6; ++A) {
+    int i = LE[A][0], j = LE[A][1];
+    for (int B = 0; B < 6; ++B) {
+      int k = LE[B][0], l = LE[B][1];
+      double te = (1 + (i == k)) * gg[j][l] - (1 + (i == l)) * gg[j][k] - (1 + (j == k)) * gg[i][l] +
+                  (1 + (j == l)) * gg[i][k];
+      Te[36 * t + 6 * A + B] = m * te;
+      Se[36 * t + 6 * A + B] = sc * (cr[A][0] * cr[B][0] + cr[A][1] * cr[B][1] + cr[A][2] * cr[B][2]);
+    }
+  }
+}
+
+// Pull assembly into the per-subdomain tile stores: entry e sums its
+// contributions c in [ptr[e], ptr[e+1]) (contribution = tet*36 + a*6 + b)
+// in a fixed order in FP64, then writes once (deterministic, no atomics).
+// A = eps T_unit + cs * S.
+template <class T>
+__global__ void k_pull_local(int64_t n_entries, const int64_t* __restrict__ ptr,
+                             const int32_t* __restrict__ contrib, const int64_t* __restrict__ dest,
+                             const double* __restrict__ Te, const double* __restrict__ Se,
+                             const double* __restrict__ eps, double cs, T* __restrict__ tiles) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_entries) return;
+  double s = 0.0;
+  for (int64_t c = ptr[e]; c < ptr[e + 1]; ++c) {
+    int32_t k = contrib[c];
+    s += eps[k / 36] * Te[k] + cs * Se[k];
+  }
+  tiles[dest[e]] = (T)s;
+}
+
+// Global CSR values: the mass T (with eps) and curl-curl S (with 1/mu)
+// interleaved per nonzero; A = T + beta dt^2 S and B1 = 2A - dt^2 S are
+// formed inside the products.
+__global__ void k_pull_csr(int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ contrib,
+                           const double* __restrict__ Te, const double* __restrict__ Se,
+                           const double* __restrict__ eps, double2* __restrict__ vals) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  double t = 0.0, s = 0.0;
+  for (int64_t c = ptr[e]; c < ptr[e + 1]; ++c) {
+    int32_t k = contrib[c];
+    t += eps[k / 36] * Te[k];
+    s += Se[k];
+  }
+  vals[e] = make_double2(t, s);
+}
+
+// Unit diagonal on padding rows of every tile store (rows that carry no
+// unknown), so padded blocks factor to the identity.
+template <class T>
+__global__ void k_pad_diag(int64_t n, const int64_t* __restrict__ pos, T* __restrict__ tiles) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) tiles[pos[i]] = (T)1;
+}
+
+// --------------------------------------------------------------------------
+// K2: right-looking tiled partial Cholesky.  For panel k of every subdomain
+// with k < kr: (1) factor the diagonal tile and replace it by the inverse of
+// its Cholesky factor; (2) panel tiles (i, k) <- A_ik Dinv_k^T for i > k
+// (interface and corner rows alike, so corner rows become L_cr);
+// (3) trailing tiles (i, j), k < j <= i, -= L_ik L_jk^T (corner block
+// becomes K_s = A_cc - L_cr L_cr^T).  Arithmetic in the storage type T
+// except the diagonal tile, which is factored and inverted in FP64.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_potrf(int k, int s0, T* __restrict__ tiles,
+                                               const SubDev* __restrict__ subs, int* __restrict__ err) {
+  const SubDev q = subs[s0 + blockIdx.x];
+  if (k >= q.kI + q.kG) return;
+  __shared__ double a[kNB][kNB + 1];
+  __shared__ double li[kNB][kNB + 1];
+  __shared__ int bad;
+  T* tp = tiles + tile_index(q, k, k) * kTile;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < kTile; e += 256) a[e / kNB][e % kNB] = (double)tp[e];
+  __syncthreads();
+  for (int j = 0; j < kNB; ++j) {
+    if (tid == 0) {
+      double d = a[j][j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        d = 1.0;
+      }
+      a[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    if (tid > j && tid < kNB) a[tid][j] /= a[j][j];
+    __syncthreads();
+    for (int e = tid; e < kTile; e += 256) {
+      int r = e / kNB, c = e % kNB;
+      if (c > j && r >= c) a[r][c] -= a[r][j] * a[c][j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular factor, one column per thread
+  if (tid < kNB) {
+    const int c = tid;
+    for (int r = 0; r < c; ++r) li[r][c] = 0.0;
+    li[c][c] = 1.0 / a[c][c];
+    for (int r = c + 1; r < kNB; ++r) {
+      double s = 0.0;
+      for (int m = c; m < r; ++m) s += a[r][m] * li[m][c];
+      li[r][c] = -s / a[r][r];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kTile; e += 256) tp[e] = (T)li[e / kNB][e % kNB];
+  if (tid == 0 && bad) atomicMin(err, s0 + (int)blockIdx.x);
+}
+
+// C (NB x NB) = op over two LDS tiles; each of 256 threads owns 4 entries
+// (row tid/8, columns 4*(tid%8)..+3).
+template <class T>
+__global__ void __launch_bounds__(256) k_trsm(int k, int s0, T* __restrict__ tiles,
+                                              const SubDev* __restrict__ subs) {
+  const SubDev q = subs[s0 + blockIdx.y];
+  const int i = k + 1 + blockIdx.x;
+  if (k >= q.kI + q.kG || i >= q.K) return;
+  __shared__ T A[kNB][kNB + 1];
+  __shared__ T Dv[kNB][kNB + 1];
+  T* ap = tiles + tile_index(q, i, k) * kTile;
+  const T* dp = tiles + tile_index(q, k, k) * kTile;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kTile; e += 256) {
+    A[e / kNB][e % kNB] = ap[e];
+    Dv[e / kNB][e % kNB] = dp[e];
+  }
+  __syncthreads();
+  const int r = tid / 8, c0 = 4 * (tid % 8);
+  T acc[4] = {0, 0, 0, 0};
+  for (int m = 0; m < kNB; ++m) {
+    T av = A[r][m];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += av * Dv[c0 + u][m];  // (A Dinv^T)[r][c] = sum_m A[r][m] Dinv[c][m]
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) ap[r * kNB + c0 + u] = acc[u];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_syrk(int k, int s0, T* __restrict__ tiles,
+                                              const SubDev* __restrict__ subs) {
+  const SubDev q = subs[s0 + blockIdx.y];
+  if (k >= q.kI + q.kG) return;
+  const int64_t p = blockIdx.x;
+  const int Tn = q.K - k - 1;
+  if (p >= (int64_t)Tn * (Tn + 1) / 2) return;
+  int ii = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(ii + 1) * (ii + 2) / 2 <= p) ++ii;
+  while ((int64_t)ii * (ii + 1) / 2 > p) --ii;
+  const int jj = (int)(p - (int64_t)ii * (ii + 1) / 2);
+  const int i = k + 1 + ii, j = k + 1 + jj;
+  __shared__ T A[kNB][kNB + 1];
+  __shared__ T B[kNB][kNB + 1];
+  const T* ap = tiles + tile_index(q, i, k) * kTile;
+  const T* bp = tiles + tile_index(q, j, k) * kTile;
+  T* cp = tiles + tile_index(q, i, j) * kTile;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kTile; e += 256) {
+    A[e / kNB][e % kNB] = ap[e];
+    B[e / kNB][e % kNB] = bp[e];
+  }
+  __syncthreads();
+  const int r = tid / 8, c0 = 4 * (tid % 8);
+  T acc[4] = {0, 0, 0, 0};
+  for (int m = 0; m < kNB; ++m) {
+    T av = A[r][m];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += av * B[c0 + u][m];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) cp[r * kNB + c0 + u] -= acc[u];
+}
+
+// --------------------------------------------------------------------------
+// Inversion of the r-block Cholesky factor, one block row at a time:
+// Linv_ij = -Dinv_i sum_{m=j}^{i-1} L_im Linv_mj  (rows < i already inverted,
+// row i still holds L), written to a scratch row, then copied back.
+// --------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __restrict__ tiles,
+                                                   const SubDev* __restrict__ subs,
+                                                   const int64_t* __restrict__ scratch_off,
+                                                   T* __restrict__ scratch) {
+  const int sidx = s0 + blockIdx.y;
+  const SubDev q = subs[sidx];
+  const int j = blockIdx.x;
+  const int kr = q.kI + q.kG;
+  if (i >= kr || j >= i) return;
+  __shared__ T A[kNB][kNB + 1];
+  __shared__ T B[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int r = tid / 8, c0 = 4 * (tid % 8);
+  T acc[4] = {0, 0, 0, 0};
+  for (int m = j; m < i; ++m) {
+    const T* ap = tiles + tile_index(q, i, m) * kTile;  // L_im
+    const T* bp = tiles + tile_index(q, m, j) * kTile;  // Linv_mj
+    __syncthreads();
+    for (int e = tid; e < kTile; e += 256) {
+      A[e / kNB][e % kNB] = ap[e];
+      B[e / kNB][e % kNB] = bp[e];
+    }
+    __syncthreads();
+    for (int mm = 0; mm < kNB; ++mm) {
+      T av = A[r][mm];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += av * B[mm][c0 + u];
+    }
+  }
+  // multiply by -Dinv_i
+  __syncthreads();
+  const T* dp = tiles + tile_index(q, i, i) * kTile;
+  for (int e = tid; e < kTile; e += 256) A[e / kNB][e % kNB] = dp[e];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) B[r][c0 + u] = acc[u];
+  __syncthreads();
+  T out[4] = {0, 0, 0, 0};
+  for (int mm = 0; mm <= r; ++mm) {
+    T dv = A[r][mm];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) out[u] += dv * B[mm][c0 + u];
+  }
+  T* sp = scratch + (scratch_off[sidx] + j) * kTile;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) sp[r * kNB + c0 + u] = -out[u];
+}
+
+template <class T>
+__global__ void k_trtri_copy(int i, int s0, T* __restrict__ tiles, const SubDev* __restrict__ subs,
+                             const int64_t* __restrict__ scratch_off, const T* __restrict__ scratch) {
+  const int sidx = s0 + blockIdx.y;
+  const SubDev q = subs[sidx];
+  const int j = blockIdx.x;
+  if (i >= q.kI + q.kG || j >= i) return;
+  T* dst = tiles + tile_index(q, i, j) * kTile;
+  const T* src = scratch + (scratch_off[sidx] + j) * kTile;
+  for (int e = threadIdx.x; e < kTile; e += blockDim.x) dst[e] = src[e];
+}
+
+// Coarse corner matrix K_cc = sum_s B_c^T K_s B_c by pull (fixed order).
+template <class T>
+__global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const int64_t* __restrict__ src,
+                              const int64_t* __restrict__ dest, T* __restrict__ tiles) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double s = 0.0;
+  for (int64_t c = ptr[e]; c < ptr[e + 1]; ++c) s += (double)tiles[src[c]];
+  tiles[dest[e]] = (T)s;
+}
+
+// --------------------------------------------------------------------------
+// Batched tile products for the solves (the substitutions, applied through
+// the stored inverse factors).  One work item = (subdomain, output block o);
+// the block's contributing tiles are
+//   NOTRANS: (o, j), j in [jlo, jhi)      out_o  = sum_j tile(o,j)   in_j
+//   TRANS  : (i, o), i in [ilo, ihi)      out_o  = sum_i tile(i,o)^T in_i
+// 256 threads = 8 slots of 32 lanes; a slot takes every 8th tile, stages it
+// in LDS, and lane rho accumulates row (NOTRANS) or column (TRANS) rho of
+// the product for all right-hand sides; slots are summed at the end.
+// out_o = (add ? add_o : 0) + alpha * sum.
+// --------------------------------------------------------------------------
+struct MvItem {
+  int32_t s, o, lo, hi;  // subdomain, output block, tile range [lo, hi)
+};
+
+template <class T, bool TRANS>
+__global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* __restrict__ items,
+                                                 const SubDev* __restrict__ subs,
+                                                 const T* __restrict__ tiles, const T* __restrict__ in,
+                                                 T* __restrict__ out, const T* __restrict__ add, T alpha,
+                                                 int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t it = blockIdx.x;
+  if (it >= n_items) return;
+  const MvItem w = items[it];
+  const SubDev q = subs[w.s];
+  constexpr int SLOTS = 8;
+  __shared__ T lds[SLOTS][kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int slot = tid / kNB, rho = tid % kNB;
+  T acc[kMaxRhs];
+#pragma unroll
+  for (int r = 0; r < kMaxRhs; ++r) acc[r] = 0;
+  const int cnt = w.hi - w.lo;
+  for (int base = 0; base < cnt; base += SLOTS) {
+    const int m = base + slot;
+    const bool active = m < cnt;
+    const int ti = TRANS ? (w.lo + m) : w.o;
+    const int tj = TRANS ? w.o : (w.lo + m);
+    __syncthreads();
+    if (active) {
+      const T* tp = tiles + tile_index(q, ti, tj) * kTile;
+      for (int e = rho; e < kTile; e += kNB) lds[slot][e / kNB][e % kNB] = tp[e];
+    }
+    __syncthreads();
+    if (active) {
+      const int ib = TRANS ? ti : tj;  // input block
+      const T* xp = in + (q.row_off + (int64_t)ib * kNB) * nrhs;
+      for (int kk = 0; kk < kNB; ++kk) {
+        const T a = TRANS ? lds[slot][kk][rho] : lds[slot][rho][kk];
+        const T* xr = xp + kk * nrhs;
+#pragma unroll
+        for (int r = 0; r < kMaxRhs; ++r)
+          if (r < nrhs) acc[r] += a * xr[r];
+      }
+    }
+  }
+  // reduce the slots through LDS (reuse the tile buffers: SLOTS*NB*(NB+1) >= SLOTS*NB*nrhs)
+  __syncthreads();
+  T* red = &lds[0][0][0];
+  for (int r = 0; r < nrhs; ++r) red[(slot * kNB + rho) * nrhs + r] = acc[r];
+  __syncthreads();
+  T* op = out + (q.row_off + (int64_t)w.o * kNB) * nrhs;
+  const T* adp = add ? add + (q.row_off + (int64_t)w.o * kNB) * nrhs : nullptr;
+  for (int e = tid; e < kNB * nrhs; e += 256) {
+    T s = 0;
+    for (int sl = 0; sl < SLOTS; ++sl) s += red[sl * kNB * nrhs + e];
+    op[e] = (adp ? adp[e] : (T)0) + alpha * s;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Maps between the global unknown space, the multipliers and local blocks.
+// --------------------------------------------------------------------------
+// Local block rows <- owner split of a global FP64 vector [nint][nrhs]
+// (src[row] = unknown id if this subdomain owns it, else -1).
+template <class T>
+__global__ void k_split(int64_t rows, const int32_t* __restrict__ src, const double* __restrict__ b,
+                        T* __restrict__ w, int nrhs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * nrhs) return;
+  int64_t row = i / nrhs;
+  int r = (int)(i % nrhs);
+  int32_t d = src[row];
+  w[i] = d >= 0 ? (T)b[(int64_t)d * nrhs + r] : (T)0;
+}
+
+// v[row] = sign(row) * p[lam(row)] on listed rows (interface rows of every
+// subdomain, padding rows included with lam = -1 -> 0): B_s^T p.
+template <class T>
+__global__ void k_lambda_gather(int64_t n, const int64_t* __restrict__ rows, const int32_t* __restrict__ lam,
+                                const double* __restrict__ p, T* __restrict__ v, int nrhs,
+                                const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int64_t k = i / nrhs;
+  int r = (int)(i % nrhs);
+  int32_t l = lam[k];
+  double x = 0.0;
+  if (l >= 0) x = (double)(l & 1 ? -1 : 1) * p[(int64_t)(l >> 1) * nrhs + r];
+  v[rows[k] * nrhs + r] = (T)x;
+}
+
+// F p = sum_s B_s u_s: each multiplier pulls its two copies (+lo, -hi).
+template <class T>
+__global__ void k_lambda_scatter(int64_t nlam, const int64_t* __restrict__ row0, const int64_t* __restrict__ row1,
+                                 const T* __restrict__ u, double* __restrict__ out, int nrhs,
+                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlam * nrhs) return;
+  int64_t l = i / nrhs;
+  int r = (int)(i % nrhs);
+  out[i] = (double)u[row0[l] * nrhs + r] - (double)u[row1[l] * nrhs + r];
+}
+
+// Coarse vector rows <- sum of the subdomain corner rows of each corner
+// (fixed order) [+ add]; padding rows of the coarse block get 0.
+template <class T>
+__global__ void k_coarse_gather(int64_t ncrows, int64_t crow0, const int64_t* __restrict__ ptr,
+                                const int64_t* __restrict__ rows, const T* __restrict__ x, T* __restrict__ y,
+                                const T* __restrict__ add, int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncrows * nrhs) return;
+  int64_t c = i / nrhs;
+  int r = (int)(i % nrhs);
+  double s = 0.0;
+  for (int64_t k = ptr[c]; k < ptr[c + 1]; ++k) s += (double)x[rows[k] * nrhs + r];
+  int64_t o = (crow0 + c) * nrhs + r;
+  if (add) s += (double)add[o];
+  y[o] = (T)s;
+}
+
+// Subdomain corner rows <- coarse solution (B_c z); crow = -1 -> 0.
+template <class T>
+__global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, const int64_t* __restrict__ crow,
+                                 const T* __restrict__ z, T* __restrict__ x, int nrhs,
+                                 const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int64_t k = i / nrhs;
+  int r = (int)(i % nrhs);
+  int64_t c = crow[k];
+  x[rows[k] * nrhs + r] = c >= 0 ? z[c * nrhs + r] : (T)0;
+}
+
+// y = a - b on listed rows (t - [0; t_lambda]); rows with flag 0 copy a.
+template <class T>
+__global__ void k_sub_rows(int64_t rows_total, const uint8_t* __restrict__ gamma_row, const T* __restrict__ a,
+                           const T* __restrict__ b, T* __restrict__ y, int nrhs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows_total * nrhs) return;
+  int64_t row = i / nrhs;
+  y[i] = gamma_row[row] ? a[i] - b[i] : a[i];
+}
+
+// Global FP64 result of unknown d = the owner's copy (dsrc[d] = row).
+template <class T>
+__global__ void k_collect(int64_t nint, const int64_t* __restrict__ dsrc, const T* __restrict__ x,
+                          double* __restrict__ e, int nrhs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nint * nrhs) return;
+  int64_t d = i / nrhs;
+  int r = (int)(i % nrhs);
+  e[i] = (double)x[dsrc[d] * nrhs + r];
+}
+
+// --------------------------------------------------------------------------
+// Layout changes between caller arrays [nrhs][n_edges] and unknown-major
+// [nint][nrhs].
+// --------------------------------------------------------------------------
+__global__ void k_edges_to_int(int64_t nint, const int32_t* __restrict__ interior, const double* __restrict__ src,
+                               int64_t ne, double* __restrict__ dst, int nrhs, double scale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nint * nrhs) return;
+  int64_t d = i / nrhs;
+  int r = (int)(i % nrhs);
+  dst[i] = scale * src[(int64_t)r * ne + interior[d]];
+}
+
+__global__ void k_int_to_edges(int64_t ne, const int32_t* __restrict__ dof, const double* __restrict__ src,
+                               double* __restrict__ dst, int nrhs, int accumulate, double scale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne * nrhs) return;
+  int r = (int)(i / ne);
+  int64_t e = i % ne;
+  int32_t d = dof[e];
+  double v = d >= 0 ? scale * src[(int64_t)d * nrhs + r] : 0.0;
+  if (accumulate) {
+    if (d >= 0) dst[i] += v;
+  } else {
+    dst[i] = v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// K4: Newmark right-hand side and residuals with the global CSR of (T, S);
+// ca = beta dt^2 (A = T + ca S), cb = (2 beta - 1) dt^2 (B1 = 2T + cb S).
+//   mode 0: y = B1 x1 - A x2 - dt (j1 - j2)       (Newmark right-hand side)
+//   mode 1: y = z - A x1                          (refinement residual)
+//   mode 2: y = B1 x1, y2 = A x1                  (adjoint application)
+//   mode 3: y = T x1,  y2 = S x1                  (Gauss law, energy)
+// One thread per (row, rhs); vectors [nint][nrhs].
+// --------------------------------------------------------------------------
+__global__ void k_csr(int mode, int64_t nint, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                      const double2* __restrict__ v, const double* __restrict__ x1, const double* __restrict__ x2,
+                      const double* __restrict__ j1, const double* __restrict__ j2, const double* __restrict__ z,
+                      double dt, double ca, double cb, double* __restrict__ y, double* __restrict__ y2,
+                      int nrhs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nint * nrhs) return;
+  int64_t row = i / nrhs;
+  int r = (int)(i % nrhs);
+  double t1 = 0.0, s1 = 0.0, t2 = 0.0, s2 = 0.0;
+  for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
+    double2 av = v[k];
+    int64_t c = (int64_t)ci[k] * nrhs + r;
+    double a = x1[c];
+    t1 += av.x * a;
+    s1 += av.y * a;
+    if (mode == 0) {
+      double b = x2[c];
+      t2 += av.x * b;
+      s2 += av.y * b;
+    }
+  }
+  if (mode == 0) {
+    y[i] = (2.0 * t1 + cb * s1) - (t2 + ca * s2) - dt * (j1[i] - j2[i]);
+  } else if (mode == 1) {
+    y[i] = z[i] - (t1 + ca * s1);
+  } else if (mode == 2) {
+    y[i] = 2.0 * t1 + cb * s1;
+    y2[i] = t1 + ca * s1;
+  } else {
+    y[i] = t1;
+    y2[i] = s1;
+  }
+}
+
+// --------------------------------------------------------------------------
+// K8: conjugate gradients on the interface system, per right-hand side.
+// Dot products: fixed-order two-stage reductions (deterministic).
+// --------------------------------------------------------------------------
+constexpr int kDotBlocks = 256;
+
+__global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double* __restrict__ x,
+                                                     const double* __restrict__ y, int nrhs,
+                                                     double* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  // block b sums rows b, b + B, ... for every rhs; layout [n][nrhs]
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int lanes_per_rhs = 256 / nrhs;  // nrhs divides 256 (powers of two) or nrhs <= 256
+  const int r = tid % nrhs;
+  const int lane = tid / nrhs;
+  double s = 0.0;
+  if (lane < lanes_per_rhs) {
+    for (int64_t row = (int64_t)blockIdx.x * lanes_per_rhs + lane; row < n;
+         row += (int64_t)gridDim.x * lanes_per_rhs)
+      s += x[row * nrhs + r] * y[row * nrhs + r];
+  }
+  red[tid] = s;
+  __syncthreads();
+  if (tid < nrhs) {
+    double t = 0.0;
+    for (int l = 0; l < lanes_per_rhs; ++l) t += red[l * nrhs + tid];
+    partial[blockIdx.x * kMaxRhs + tid] = t;
+  }
+}
+
+struct CgState {
+  double rr[kMaxRhs];      // current r.r
+  double rr0[kMaxRhs];     // d.d (relative tolerance reference)
+  double alpha[kMaxRhs];
+  double beta[kMaxRhs];
+  int active[kMaxRhs];
+  int iters[kMaxRhs];
+  int done;                // all right-hand sides converged (or broke down)
+  int breakdown;
+};
+
+// stage: 0 = init (rr = rr0 = sum), 1 = alpha (pFp = sum), 2 = beta (rr_new = sum),
+//        3 = warm start (rr = sum, convergence flags only)
+__global__ void k_cg_scalar(int stage, int nrhs, const double* __restrict__ partial, CgState* __restrict__ st,
+                            double tol) {
+  if (stage != 0 && st->done) return;
+  const int r = threadIdx.x;
+  __shared__ int any_active;
+  if (r == 0) any_active = 0;
+  __syncthreads();
+  if (r < nrhs) {
+    double s = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) s += partial[b * kMaxRhs + r];
+    if (stage == 0) {
+      st->rr[r] = s;
+      st->rr0[r] = s;
+      st->iters[r] = 0;
+      st->active[r] = s > 0.0 ? 1 : 0;
+      st->alpha[r] = 0.0;
+      st->beta[r] = 0.0;
+    } else if (stage == 3) {
+      st->rr[r] = s;
+      st->beta[r] = 0.0;
+      if (st->active[r] && s <= tol * tol * st->rr0[r]) st->active[r] = 0;
+    } else if (stage == 1) {
+      if (st->active[r]) {
+        if (!(s > 0.0) || !isfinite(s)) {
+          st->active[r] = 0;
+          st->alpha[r] = 0.0;
+          atomicOr(&st->breakdown, 1);
+        } else {
+          st->alpha[r] = st->rr[r] / s;
+        }
+      } else {
+        st->alpha[r] = 0.0;
+      }
+    } else {
+      if (st->active[r]) {
+        st->iters[r] += 1;
+        st->beta[r] = s / st->rr[r];
+        st->rr[r] = s;
+        if (!(s <= tol * tol * st->rr0[r])) {
+          // keep iterating (also on NaN: caught by the caller's cap)
+        } else {
+          st->active[r] = 0;
+        }
+      } else {
+        st->beta[r] = 0.0;
+      }
+    }
+    if (st->active[r]) atomicOr(&any_active, 1);
+  }
+  __syncthreads();
+  if (r == 0) st->done = any_active ? 0 : 1;
+}
+
+// lambda += alpha p ; r -= alpha Fp   (alpha = 0 for inactive rhs)
+__global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, const double* __restrict__ p,
+                        const double* __restrict__ Fp, double* __restrict__ lam, double* __restrict__ res) {
+  if (st->done) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int r = (int)(i % nrhs);
+  double a = st->alpha[r];
+  lam[i] += a * p[i];
+  res[i] -= a * Fp[i];
+}
+
+// p = r + beta p for active rhs
+__global__ void k_cg_p(int64_t n, int nrhs, const CgState* __restrict__ st, const double* __restrict__ res,
+                       double* __restrict__ p) {
+  if (st->done) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  int r = (int)(i % nrhs);
+  if (st->active[r]) p[i] = res[i] + st->beta[r] * p[i];
+}
+
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+__global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] - b[i];
+}
+
+// --------------------------------------------------------------------------
+// Adjoint: eps_bar[k] -= sum_r g_r . T_k acc_r over the tet's interior
+// edges (T_k = unit-eps element mass), acc = e^{n+1} - 2 e^n + e^{n-1}.
+// --------------------------------------------------------------------------
+__global__ void k_eps_bar(int64_t nt, const int32_t* __restrict__ tdof, const double* __restrict__ Te,
+                          const double* __restrict__ g, const double* __restrict__ acc, int nrhs,
+                          double* __restrict__ eps_bar) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  int32_t d[6];
+  for (int a = 0; a < 6; ++a) d[a] = tdof[6 * t + a];
+  double s = 0.0;
+  for (int r = 0; r < nrhs; ++r)
+    for (int a = 0; a < 6; ++a) {
+      if (d[a] < 0) continue;
+      double ga = g[(int64_t)d[a] * nrhs + r];
+      double u = 0.0;
+      for (int b = 0; b < 6; ++b)
+        if (d[b] >= 0) u += Te[36 * t + 6 * a + b] * acc[(int64_t)d[b] * nrhs + r];
+      s += ga * u;
+    }
+  eps_bar[t] -= s;
+}
+
+__global__ void k_second_diff(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                              const double* __restrict__ c, double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] - 2.0 * b[i] + (c ? c[i] : 0.0);
+}
+
+// --------------------------------------------------------------------------
+// K10: discrete Gauss law and energy.
+// Node charge: q[r][v] += dt * sum_{edges e at v} G[e,v] J[r][e],
+// G = +1 at the head (higher id), -1 at the tail; pull over the edge list of
+// each vertex (vptr/vedge, sign in the low bit).
+// --------------------------------------------------------------------------
+__global__ void k_charge(int64_t nv, const int64_t* __restrict__ vptr, const int32_t* __restrict__ vedge,
+                         const uint8_t* __restrict__ node_int, const double* __restrict__ J, int64_t ne,
+                         double dt, double* __restrict__ q, int nrhs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * nrhs) return;
+  int r = (int)(i / nv);
+  int64_t v = i % nv;
+  if (!node_int[v]) return;
+  double s = 0.0;
+  for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+    int32_t code = vedge[k];
+    int32_t e = code >> 1;
+    s += (code & 1 ? -1.0 : 1.0) * J[(int64_t)r * ne + e];
+  }
+  q[i] += dt * s;
+}
+
+// res[v] = (G^T (T e))_v + q_v with Te = T e given per unknown [nint][nrhs]
+__global__ void k_gauss(int64_t nv, const int64_t* __restrict__ vptr, const int32_t* __restrict__ vedge,
+                        const uint8_t* __restrict__ node_int, const int32_t* __restrict__ dof,
+                        const double* __restrict__ Tx, const double* __restrict__ q, int nrhs,
+                        double* __restrict__ res) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * nrhs) return;
+  int r = (int)(i / nv);
+  int64_t v = i % nv;
+  if (!node_int[v]) {
+    res[i] = 0.0;
+    return;
+  }
+  double s = 0.0;
+  for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+    int32_t code = vedge[k];
+    int32_t d = dof[code >> 1];
+    if (d >= 0) s += (code & 1 ? -1.0 : 1.0) * Tx[(int64_t)d * nrhs + r];
+  }
+  res[i] = s + q[i];
+}
+
+}  // namespace ddfem

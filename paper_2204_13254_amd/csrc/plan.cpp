@@ -1,0 +1,245 @@
+// Host-side partition analysis; see plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "ddfem.h"
+
+namespace ddfem {
+
+namespace {
+const int LE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+template <class T>
+void sort_unique(std::vector<T>& v) {
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+}
+}  // namespace
+
+int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets,
+               const int32_t* partition, Plan& P, std::string& msg) {
+  if (nv <= 0 || nt <= 0 || !coords || !tets || !partition) {
+    msg = "empty mesh or null pointer";
+    return DD_ERR_ARG;
+  }
+  if (nv >= (int64_t(1) << 21) * 64) {
+    msg = "too many vertices";
+    return DD_ERR_ARG;
+  }
+  P.nv = nv;
+  P.nt = nt;
+  P.tsort.resize(nt * 4);
+  // ---- tetrahedra: range, distinct vertices, volume --------------------
+  for (int64_t t = 0; t < nt; ++t) {
+    int32_t v[4];
+    for (int a = 0; a < 4; ++a) {
+      v[a] = tets[t * 4 + a];
+      if (v[a] < 0 || v[a] >= nv) {
+        msg = "tetrahedron " + std::to_string(t) + " has a vertex index out of range";
+        return DD_ERR_MESH;
+      }
+    }
+    std::sort(v, v + 4);
+    for (int a = 0; a < 3; ++a)
+      if (v[a] == v[a + 1]) {
+        msg = "tetrahedron " + std::to_string(t) + " repeats a vertex";
+        return DD_ERR_MESH;
+      }
+    double d[3][3], scale = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double x = coords[3 * (int64_t)v[a + 1] + c], x0 = coords[3 * (int64_t)v[0] + c];
+        if (!std::isfinite(x) || !std::isfinite(x0)) {
+          msg = "non-finite vertex coordinate";
+          return DD_ERR_NONFINITE;
+        }
+        d[a][c] = x - x0;
+        scale = std::max(scale, std::fabs(d[a][c]));
+      }
+    double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                 d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                 d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+    if (!(std::fabs(det) > 1e-12 * scale * scale * scale)) {
+      msg = "tetrahedron " + std::to_string(t) + " is degenerate (zero volume)";
+      return DD_ERR_MESH;
+    }
+    for (int a = 0; a < 4; ++a) P.tsort[t * 4 + a] = v[a];
+  }
+  // ---- partition ----------------------------------------------------------
+  int32_t nsub = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    if (partition[t] < 0) {
+      msg = "negative subdomain id";
+      return DD_ERR_PARTITION;
+    }
+    nsub = std::max(nsub, partition[t] + 1);
+  }
+  if (nsub > (1 << 20)) {
+    msg = "subdomain id out of range";
+    return DD_ERR_PARTITION;
+  }
+  {
+    std::vector<int64_t> cnt(nsub, 0);
+    for (int64_t t = 0; t < nt; ++t) cnt[partition[t]]++;
+    for (int32_t s = 0; s < nsub; ++s)
+      if (cnt[s] == 0) {
+        msg = "subdomain " + std::to_string(s) + " is empty";
+        return DD_ERR_PARTITION;
+      }
+  }
+  P.nsub = nsub;
+  P.part.assign(partition, partition + nt);
+
+  // ---- canonical edges ----------------------------------------------------------
+  const uint64_t NV = (uint64_t)nv;
+  std::vector<uint64_t> keys(nt * 6);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int e = 0; e < 6; ++e)
+      keys[t * 6 + e] = (uint64_t)P.tsort[t * 4 + LE[e][0]] * NV + P.tsort[t * 4 + LE[e][1]];
+  std::vector<uint64_t> ukeys = keys;
+  sort_unique(ukeys);
+  P.ne = (int64_t)ukeys.size();
+  P.edges.resize(P.ne * 2);
+  for (int64_t e = 0; e < P.ne; ++e) {
+    P.edges[2 * e] = (int32_t)(ukeys[e] / NV);
+    P.edges[2 * e + 1] = (int32_t)(ukeys[e] % NV);
+  }
+  P.tet_edges.resize(nt * 6);
+  for (int64_t i = 0; i < nt * 6; ++i)
+    P.tet_edges[i] = (int32_t)(std::lower_bound(ukeys.begin(), ukeys.end(), keys[i]) - ukeys.begin());
+  keys.clear();
+  keys.shrink_to_fit();
+
+  // ---- boundary faces -> PEC edges and boundary vertices ------------------------
+  {
+    const int LF[4][3] = {{0, 1, 2}, {0, 1, 3}, {0, 2, 3}, {1, 2, 3}};
+    std::vector<uint64_t> fk(nt * 4);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int f = 0; f < 4; ++f)
+        fk[t * 4 + f] = ((uint64_t)P.tsort[t * 4 + LF[f][0]] * NV + P.tsort[t * 4 + LF[f][1]]) * NV +
+                        P.tsort[t * 4 + LF[f][2]];
+    std::sort(fk.begin(), fk.end());
+    P.pec.assign(P.ne, 0);
+    P.node_interior.assign(nv, 1);
+    for (size_t i = 0; i < fk.size();) {
+      size_t j = i;
+      while (j < fk.size() && fk[j] == fk[i]) ++j;
+      if (j - i == 1) {  // boundary face
+        uint64_t k = fk[i];
+        int32_t c = (int32_t)(k % NV), b = (int32_t)((k / NV) % NV), a = (int32_t)(k / NV / NV);
+        int32_t vs[3] = {a, b, c};
+        for (int x = 0; x < 3; ++x) P.node_interior[vs[x]] = 0;
+        const int FE[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+        for (int x = 0; x < 3; ++x) {
+          uint64_t ek = (uint64_t)vs[FE[x][0]] * NV + vs[FE[x][1]];
+          int64_t e = std::lower_bound(ukeys.begin(), ukeys.end(), ek) - ukeys.begin();
+          P.pec[e] = 1;
+        }
+      } else if (j - i > 2) {
+        msg = "a face is shared by more than two tetrahedra";
+        return DD_ERR_MESH;
+      }
+      i = j;
+    }
+  }
+  P.dof.assign(P.ne, -1);
+  P.interior.clear();
+  for (int64_t e = 0; e < P.ne; ++e)
+    if (!P.pec[e]) {
+      P.dof[e] = (int32_t)P.interior.size();
+      P.interior.push_back((int32_t)e);
+    }
+  P.nint = (int64_t)P.interior.size();
+
+  // ---- multiplicity, owner, per-subdomain unknown sets ----------------------------
+  std::vector<uint64_t> sd;  // (subdomain << 32) | unknown
+  sd.reserve(nt * 6);
+  for (int64_t t = 0; t < nt; ++t)
+    for (int e = 0; e < 6; ++e) {
+      int32_t d = P.dof[P.tet_edges[t * 6 + e]];
+      if (d >= 0) sd.push_back(((uint64_t)partition[t] << 32) | (uint32_t)d);
+    }
+  sort_unique(sd);
+  P.mult.assign(P.nint, 0);
+  P.owner.assign(P.nint, INT32_MAX);
+  for (uint64_t k : sd) {
+    int32_t s = (int32_t)(k >> 32), d = (int32_t)(k & 0xffffffffu);
+    P.mult[d]++;
+    P.owner[d] = std::min(P.owner[d], s);
+  }
+  P.max_mult = 0;
+  for (int64_t d = 0; d < P.nint; ++d) P.max_mult = std::max(P.max_mult, P.mult[d]);
+
+  P.subs.assign(nsub, SubInfo());
+  P.local.assign(nsub, {});
+  {
+    std::vector<std::vector<int32_t>> cls[3];
+    for (int c = 0; c < 3; ++c) cls[c].assign(nsub, {});
+    for (uint64_t k : sd) {
+      int32_t s = (int32_t)(k >> 32), d = (int32_t)(k & 0xffffffffu);
+      int c = P.mult[d] == 1 ? 0 : (P.mult[d] == 2 ? 1 : 2);
+      cls[c][s].push_back(d);  // ascending unknown id = ascending edge id
+    }
+    for (int32_t s = 0; s < nsub; ++s) {
+      SubInfo& q = P.subs[s];
+      q.nI = (int32_t)cls[0][s].size();
+      q.nG = (int32_t)cls[1][s].size();
+      q.nC = (int32_t)cls[2][s].size();
+      q.kI = (q.nI + NB - 1) / NB;
+      q.kG = (q.nG + NB - 1) / NB;
+      q.kC = (q.nC + NB - 1) / NB;
+      q.K = q.kI + q.kG + q.kC;
+      auto& L = P.local[s];
+      L.reserve(q.nI + q.nG + q.nC);
+      for (int c = 0; c < 3; ++c) L.insert(L.end(), cls[c][s].begin(), cls[c][s].end());
+    }
+  }
+  sd.clear();
+  sd.shrink_to_fit();
+
+  // ---- multipliers: one per interface unknown -----------------------------------
+  // position lookup per (subdomain, unknown): binary search in the class
+  // segments of the local list
+  auto local_pos = [&](int32_t s, int32_t d) -> int32_t {
+    const SubInfo& q = P.subs[s];
+    const auto& L = P.local[s];
+    int c = P.mult[d] == 1 ? 0 : (P.mult[d] == 2 ? 1 : 2);
+    int32_t b = c == 0 ? 0 : (c == 1 ? q.nI : q.nI + q.nG);
+    int32_t e = c == 0 ? q.nI : (c == 1 ? q.nI + q.nG : q.nI + q.nG + q.nC);
+    auto it = std::lower_bound(L.begin() + b, L.begin() + e, d);
+    return (int32_t)(it - L.begin());
+  };
+  {
+    // subdomains of each interface unknown: scan tets again (cheap)
+    std::vector<int32_t> s0(P.nint, INT32_MAX), s1(P.nint, -1);
+    for (int64_t t = 0; t < nt; ++t)
+      for (int e = 0; e < 6; ++e) {
+        int32_t d = P.dof[P.tet_edges[t * 6 + e]];
+        if (d < 0 || P.mult[d] != 2) continue;
+        s0[d] = std::min(s0[d], partition[t]);
+        s1[d] = std::max(s1[d], partition[t]);
+      }
+    P.lam_dof.clear();
+    for (int64_t d = 0; d < P.nint; ++d)
+      if (P.mult[d] == 2) {
+        P.lam_dof.push_back((int32_t)d);
+        P.lam_s0.push_back(s0[d]);
+        P.lam_s1.push_back(s1[d]);
+        P.lam_p0.push_back(local_pos(s0[d], (int32_t)d));
+        P.lam_p1.push_back(local_pos(s1[d], (int32_t)d));
+      }
+  }
+  P.dof_corner.assign(P.nint, -1);
+  P.corner_dof.clear();
+  for (int64_t d = 0; d < P.nint; ++d)
+    if (P.mult[d] >= 3) {
+      P.dof_corner[d] = (int32_t)P.corner_dof.size();
+      P.corner_dof.push_back((int32_t)d);
+    }
+  return DD_OK;
+}
+
+}  // namespace ddfem

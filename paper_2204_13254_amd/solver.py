@@ -1,0 +1,170 @@
+"""Thin Python front-end over the C ABI: torch tensors provide device memory
+and the stream; the library does all the work."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DD_FP32_REFINE, DD_FP64, Analysis, Info, Options, Stats, check, load
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t: torch.Tensor):
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def analyze(coords, tets, partition):
+    """Host-only partition analysis: (Analysis, per_sub [n_sub, 3])."""
+    lib = load()
+    c, cp = _host(coords, np.float64)
+    t, tp = _host(tets, np.int32)
+    p, pp = _host(partition, np.int32)
+    out = Analysis()
+    check(lib.dd_analyze(len(c), cp, len(t), tp, pp, C.byref(out), None))
+    per = np.zeros((out.n_sub, 3), dtype=np.int32)
+    check(lib.dd_analyze(len(c), cp, len(t), tp, pp, C.byref(out),
+                         per.ctypes.data_as(C.c_void_p)))
+    return out, per
+
+
+def analyze_lambda(coords, tets, partition, n_lambda):
+    lib = load()
+    c, cp = _host(coords, np.float64)
+    t, tp = _host(tets, np.int32)
+    p, pp = _host(partition, np.int32)
+    arrs = [np.zeros(n_lambda, dtype=np.int32) for _ in range(5)]
+    check(lib.dd_analyze_lambda(len(c), cp, len(t), tp, pp,
+                                *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+    return dict(zip(("edge", "sub_lo", "sub_hi", "pos_lo", "pos_hi"), arrs))
+
+
+class DDSolver:
+    """Decomposed Newmark solver on one GPU.
+
+    Arrays crossing the boundary: fields and currents are float64 device
+    tensors [nrhs, n_edges] on canonical edges.
+    """
+
+    def __init__(self, coords, tets, partition, eps, mu=None, dt=0.05, beta=0.25, *,
+                 precision="fp64", nrhs=1, cg_tol=1e-10, cg_max_iter=500, refine_tol=1e-12,
+                 refine_max=10, warm_start=True, check_every=4, stream=None, factor=True):
+        self.lib = load()
+        o = Options()
+        self.lib.dd_default_options(C.byref(o))
+        o.precision = DD_FP32_REFINE if precision == "fp32_refine" else DD_FP64
+        o.nrhs = int(nrhs)
+        o.cg_tol = float(cg_tol)
+        o.cg_max_iter = int(cg_max_iter)
+        o.refine_tol = float(refine_tol)
+        o.refine_max = int(refine_max)
+        o.warm_start = int(bool(warm_start))
+        o.check_every = int(check_every)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        o.stream = C.c_void_p(stream.cuda_stream)
+        self.opt = o
+        c, cp = _host(coords, np.float64)
+        t, tp = _host(tets, np.int32)
+        p, pp = _host(partition, np.int32)
+        e, ep = _host(eps, np.float64)
+        mp = None
+        if mu is not None:
+            m, mp = _host(mu, np.float64)
+        h = C.c_void_p()
+        check(self.lib.dd_setup(C.byref(h), len(c), cp, len(t), tp, pp, ep, mp, float(dt),
+                                float(beta), C.byref(o)))
+        self.h = h
+        self.nrhs = int(nrhs)
+        self.dt = float(dt)
+        inf = Info()
+        check(self.lib.dd_get_info(h, C.byref(inf)))
+        self.info = inf
+        self.n_edges = inf.n_edges
+        self.n_tets = inf.n_tets
+        self.n_vertices = inf.n_vertices
+        self.stats = Stats()
+        if factor:
+            self.factor()
+
+    # ---- lifecycle -----------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- calls ------------------------------------------------------------------------
+    def edges(self):
+        e = np.zeros((self.n_edges, 2), dtype=np.int32)
+        pec = np.zeros(self.n_edges, dtype=np.uint8)
+        check(self.lib.dd_get_edges(self.h, e.ctypes.data_as(C.c_void_p),
+                                    pec.ctypes.data_as(C.c_void_p)))
+        return e, pec.astype(bool)
+
+    def set_eps(self, eps):
+        e, ep = _host(eps, np.float64)
+        check(self.lib.dd_set_eps(self.h, ep))
+
+    def factor(self):
+        check(self.lib.dd_factor(self.h))
+
+    def new_field(self):
+        return torch.zeros((self.nrhs, self.n_edges), dtype=torch.float64, device="cuda")
+
+    def step(self, J_half, J_prev_half, E_n, E_nm1, E_next=None, stats=False, raise_on_error=True):
+        if E_next is None:
+            E_next = self.new_field()
+        rc = self.lib.dd_step(self.h, _dev(J_half), _dev(J_prev_half), _dev(E_n), _dev(E_nm1),
+                              _dev(E_next), C.byref(self.stats) if stats else None)
+        if raise_on_error:
+            check(rc)
+        return E_next
+
+    def solve(self, b, x=None, stats=True):
+        if x is None:
+            x = self.new_field()
+        check(self.lib.dd_solve(self.h, _dev(b), _dev(x), C.byref(self.stats) if stats else None))
+        return x
+
+    def adjoint_step(self, ebar_next, ebar_n, ebar_nm1, E_next, E_n, E_nm1, eps_bar, g_out=None):
+        if g_out is None:
+            g_out = self.new_field()
+        p = lambda t: None if t is None else _dev(t)
+        check(self.lib.dd_adjoint_step(self.h, _dev(ebar_next), p(ebar_n), p(ebar_nm1), _dev(g_out),
+                                       p(E_next), p(E_n), p(E_nm1), p(eps_bar), None))
+        return g_out
+
+    def charge_update(self, J_half, q):
+        check(self.lib.dd_charge_update(self.h, _dev(J_half), _dev(q)))
+
+    def gauss_residual(self, E, q):
+        out = np.zeros(self.nrhs)
+        check(self.lib.dd_gauss_residual(self.h, _dev(E), _dev(q), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def energy(self, E_next, E_n):
+        out = np.zeros(self.nrhs)
+        check(self.lib.dd_energy(self.h, _dev(E_next), _dev(E_n), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def last_stats(self):
+        s = self.stats
+        n = self.nrhs
+        return dict(cg_iters=list(s.cg_iters[:n]), refine_sweeps=s.refine_sweeps,
+                    dd_solves=s.dd_solves, cg_relres=list(s.cg_relres[:n]),
+                    global_relres=list(s.global_relres[:n]))

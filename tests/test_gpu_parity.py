@@ -1,0 +1,180 @@
+"""GPU parity of the decomposed solve (HIP library through the C ABI) against
+the FP64 oracle (the monolithic direct solve), element by element.
+
+The decomposition is exact (Sec. V-A: decomposed and monolithic fields agree
+to near machine precision), so the tolerance is set by the interface CG and
+refinement tolerances: rel. L2 <= 1e-10 in FP64 and <= 1e-8 for FP32 factors
+with FP64 refinement, at every step and for every right-hand side."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.newmark import NewmarkOracle
+from workloads.configs import workload
+from workloads.mesh import cube_mesh
+from workloads.partition import box_partition, rcb_partition
+from workloads.sources import dense_random_source
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(*a, **k):
+    from paper_2204_13254_amd.solver import DDSolver
+    return DDSolver(*a, **k)
+
+
+def relerr(x, y, mask=None):
+    x = np.asarray(x); y = np.asarray(y)
+    num = np.linalg.norm(x - y, axis=-1)
+    den = np.linalg.norm(y, axis=-1)
+    return np.where(den > 0, num / np.where(den > 0, den, 1), num)
+
+
+def _case(n, parts, grade=1.0, eps_seed=None, dt=0.05):
+    c, t, _ = cube_mesh(n, grade)
+    if isinstance(parts, tuple) and parts[0] == "rcb":
+        p = rcb_partition(n, parts[1], parts[2])
+    else:
+        p = box_partition(n, parts)
+    eps = np.ones(len(t)) if eps_seed is None else np.random.default_rng(eps_seed).uniform(1, 4, len(t))
+    return c, t, p, eps
+
+
+def test_edges_match_oracle():
+    c, t, p, eps = _case(4, 2)
+    s = _solver(c, t, p, eps, dt=0.05, factor=False)
+    e, pec = s.edges()
+    o = NewmarkOracle(c, t, dt=0.05, factor=False)
+    assert np.array_equal(e, o.d.edges)
+    assert np.array_equal(pec, o.d.pec)
+
+
+@pytest.mark.parametrize("n,parts,grade,eps_seed,nrhs", [
+    (4, 2, 1.0, None, 1),
+    (6, 3, 1.0, 7, 2),
+    (8, ("rcb", 3, 1), 1.5, 3, 3),
+    (9, (2, 3, 1), 1.0, 5, 1),
+])
+def test_single_solve_fp64(n, parts, grade, eps_seed, nrhs):
+    c, t, p, eps = _case(n, parts, grade, eps_seed)
+    print(f"case n={n} parts={parts} nrhs={nrhs}", flush=True)
+    s = _solver(c, t, p, eps, dt=0.05, nrhs=nrhs, cg_tol=1e-13)
+    o = NewmarkOracle(c, t, eps=eps, dt=0.05)
+    b = np.random.default_rng(1).standard_normal((nrhs, o.d.n_e))
+    b[:, o.d.pec] = 0.0
+    x = s.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+    xr = o.d.extend(o.solve(o.d.restrict(b)))
+    err = relerr(x, xr)
+    assert err.max() <= 1e-10, err
+    assert np.all(x[:, o.d.pec] == 0.0)
+
+
+def _run_dd(s, J):
+    N, nrhs, ne = J.shape
+    Jd = torch.tensor(J, device="cuda")
+    zero = torch.zeros((nrhs, ne), dtype=torch.float64, device="cuda")
+    E = [zero, zero.clone()]   # e^{-1}, e^0
+    Jprev = zero
+    iters = []
+    for n in range(N):
+        E.append(s.step(Jd[n], Jprev, E[-1], E[-2], stats=True))
+        iters.append(s.last_stats()["cg_iters"])
+        Jprev = Jd[n]
+    return torch.stack(E[1:]).cpu().numpy(), iters
+
+
+def test_small_workload_fp64_every_step():
+    """8^3 cavity, 2x2x2 boxes, 10 steps, CG tol 1e-12: <= 1e-10 per step."""
+    w = workload(1)
+    c, t = w.mesh(); p = w.partition()
+    J = w.sources(t, c)
+    s = _solver(c, t, p, w.eps(len(t)), dt=w.dt, beta=w.beta, cg_tol=w.cg_tol)
+    E, iters = _run_dd(s, J)
+    o = NewmarkOracle(c, t, dt=w.dt, beta=w.beta)
+    Eo = o.run(J)
+    err = relerr(E[1:], Eo[1:])
+    print("max rel err", err.max(), "iters", iters, flush=True)
+    assert err.max() <= 1e-10
+
+
+@pytest.mark.parametrize("prec,tol,nrhs", [("fp64", 1e-10, 2), ("fp32_refine", 1e-8, 4)])
+def test_uneven_graded_multi_rhs(prec, tol, nrhs):
+    """Graded 10^3 mesh, 16 uneven recursive-bisection subdomains, random
+    eps, several right-hand sides, 12 steps."""
+    c, t, p, eps = _case(10, ("rcb", 4, 2), grade=1.5, eps_seed=11)
+    dt = 0.03
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, 12, dt, 0.18, 0.05, seed=21, nrhs=nrhs)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, precision=prec,
+                cg_tol=1e-12 if prec == "fp64" else 1e-6, refine_tol=1e-12)
+    E, iters = _run_dd(s, J)
+    Eo = o.run(J)
+    err = relerr(E[1:], Eo[1:])
+    print(prec, "max rel err", err.max(), flush=True)
+    assert err.max() <= tol
+
+
+def test_gauss_law_and_energy_match_oracle():
+    c, t, p, eps = _case(6, 2, eps_seed=4)
+    dt = 0.05
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    N = 8
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.2, 0.06, seed=2, nrhs=2)
+    J[5:] = 0.0
+    s = _solver(c, t, p, eps, dt=dt, nrhs=2, cg_tol=1e-13)
+    E, _ = _run_dd(s, J)
+    q = torch.zeros((2, s.n_vertices), dtype=torch.float64, device="cuda")
+    Jd = torch.tensor(J, device="cuda")
+    qo = o.charge_history(J)
+    for n in range(N):
+        s.charge_update(Jd[n], q)
+        res = s.gauss_residual(torch.tensor(E[n + 1], device="cuda"), q)
+        assert res.max() <= 1e-9 * max(1e-30, np.abs(qo[n + 1]).max())
+    H = s.energy(torch.tensor(E[-1], device="cuda"), torch.tensor(E[-2], device="cuda"))
+    Ho = o.energy(E[-1], E[-2])
+    np.testing.assert_allclose(H, Ho, rtol=1e-12)
+
+
+def test_adjoint_step_matches_oracle():
+    c, t, p, eps = _case(5, 2, eps_seed=6)
+    dt = 0.05
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    N = 6
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.15, 0.05, seed=8)
+    E = o.run(J)
+    rng = np.random.default_rng(3)
+    ebar = rng.standard_normal(E[-1].shape); ebar[:, o.d.pec] = 0.0
+    Jbar_o, epsbar_o = o.adjoint(J, E, ebar)
+    s = _solver(c, t, p, eps, dt=dt, cg_tol=1e-13)
+    dev = lambda a: torch.tensor(a, device="cuda")
+    eb = [torch.zeros((1, o.d.n_e), dtype=torch.float64, device="cuda") for _ in range(N + 1)]
+    eb[N] = dev(ebar)
+    epsbar = torch.zeros(len(t), dtype=torch.float64, device="cuda")
+    g = [None] * (N + 1)
+    for n in range(N - 1, -1, -1):
+        g[n] = s.adjoint_step(eb[n + 1], eb[n], eb[n - 1] if n >= 1 else None, dev(E[n + 1]), dev(E[n]),
+                              dev(E[n - 1]) if n >= 1 else None, epsbar)
+    gn = np.stack([x.cpu().numpy() for x in g[:N]] + [np.zeros_like(ebar)])
+    Jbar = -dt * gn[:N] + dt * gn[1:]
+    assert relerr(Jbar.reshape(-1), Jbar_o.reshape(-1)) <= 1e-9
+    assert relerr(epsbar.cpu().numpy(), epsbar_o) <= 1e-9
+
+
+def test_errors_reported():
+    from paper_2204_13254_amd import DDError
+    c, t, p, eps = _case(4, 2)
+    s = _solver(c, t, p, eps, dt=0.05, factor=False)
+    z = s.new_field()
+    with pytest.raises(DDError, match="DD_ERR_STATE"):
+        s.step(z, z, z, z, z)
+    s2 = _solver(c, t, p, eps, dt=0.05, cg_max_iter=1, cg_tol=1e-14, check_every=1)
+    b = torch.randn((1, s2.n_edges), dtype=torch.float64, device="cuda")
+    with pytest.raises(DDError, match="DD_ERR_NO_CONVERGENCE"):
+        s2.solve(b)
+    # the context stays usable
+    s2.solve(torch.zeros_like(b))
+    with pytest.raises(DDError, match="DD_ERR_ARG"):
+        _solver(c, t, p, -eps, dt=0.05)
+    with pytest.raises(DDError, match="DD_ERR_PARTITION"):
+        _solver(c, t, p + 1, eps, dt=0.05)
