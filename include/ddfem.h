@@ -166,6 +166,22 @@ int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res);
  * per RHS (host out [nrhs]); synchronises. */
 int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out);
 
+/* Per-class timing of the batched tile products, measured with HIP events
+ * recorded on the context's stream around each launch (adds two event
+ * records per launch while enabled).  Classes: */
+enum {
+  DD_PROF_TRAILING = 0, /* interface-block inverse-factor products (CG loop, twice per iteration) */
+  DD_PROF_FULL = 1,     /* full r-block inverse-factor products (pre-solve, recovery) */
+  DD_PROF_COUPLING = 2, /* corner-coupling blocks L_cr / L_cGamma */
+  DD_PROF_COARSE = 3,   /* coarse corner inverse factor */
+  DD_PROF_CLASSES = 4
+};
+/* Returns the accumulated milliseconds and launch counts per class (host
+ * arrays [DD_PROF_CLASSES], either may be NULL) since the last reset, then
+ * sets timing on (enable = 1) or off (0) and resets the counters; enable = -1
+ * only reads.  Synchronises the stream. */
+int dd_profile(void* ctx, int enable, double* ms, int64_t* launches);
+
 void dd_destroy(void* ctx);
 
 /* Message of the last error on this thread ("" if none). */

@@ -60,6 +60,7 @@ SIGNATURES = {
     "dd_charge_update": (C.c_int, [P, P, P]),
     "dd_gauss_residual": (C.c_int, [P, P, P, P]),
     "dd_energy": (C.c_int, [P, P, P, P]),
+    "dd_profile": (C.c_int, [P, C.c_int, P, P]),
     "dd_destroy": (None, [P]),
     "dd_last_error": (C.c_char_p, []),
     "dd_analyze": (C.c_int, [I64, P, I64, P, P, C.POINTER(Analysis), P]),

@@ -75,9 +75,14 @@ static V* dalloc(size_t n, std::vector<void*>& owned) {
 }
 
 struct Items {
-  MvItem* d = nullptr;
+  MvItem* d = nullptr;   // work items (one wave each), longest first
   int64_t n = 0;
+  MvOut* outs = nullptr; // output blocks to reduce (split lists only)
+  int64_t n_out = 0;
+  int64_t n_slots = 0;   // partial slots used (0 = direct writes)
 };
+
+constexpr int kChunkTiles = 16;  // longest tile range of one wave
 
 struct Ctx {
   Plan P;
@@ -100,7 +105,10 @@ struct Ctx {
   double *d_coords = nullptr, *d_mu = nullptr, *d_eps = nullptr, *d_Te = nullptr, *d_Se = nullptr;
   int32_t* d_tsort = nullptr;
   SubDev* d_subs = nullptr;
-  void* d_tiles = nullptr;
+  void* d_tiles = nullptr;   // factor store; operand-order tiles after dd_factor
+  void* d_tilesT = nullptr;  // operand-order transposed tiles
+  void* d_partial_mv = nullptr;
+  int64_t max_slots = 0;
   void* d_scratch = nullptr;
   int64_t* d_scratch_off = nullptr;
   int* d_err = nullptr;
@@ -153,8 +161,17 @@ struct Ctx {
 
   int64_t factor_bytes = 0, trailing_bytes = 0, coupling_bytes = 0, coarse_bytes = 0, full_bytes = 0;
 
+  // optional per-class kernel timing with HIP events on the solve stream
+  bool prof = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_next = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  double prof_ms[DD_PROF_CLASSES] = {0};
+  int64_t prof_n[DD_PROF_CLASSES] = {0};
+
   ~Ctx() {
     if (st) (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : owned) (void)hipFree(p);
     if (h_done) (void)hipHostFree(h_done);
     if (h_partial) (void)hipHostFree(h_partial);
@@ -164,12 +181,39 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-static Items make_items(Ctx& C, std::vector<MvItem> v) {
+// Work list of one batched product: every output block whose tile range is
+// longer than kChunkTiles is split into chunks writing partial slots, then
+// summed by k_mv_reduce.
+static Items make_items(Ctx& C, const std::vector<MvItem>& blocks) {
+  bool split = false;
+  for (const MvItem& b : blocks)
+    if (b.hi - b.lo > kChunkTiles) split = true;
+  std::vector<MvItem> v;
+  std::vector<MvOut> outs;
+  int32_t slot = 0;
+  for (const MvItem& b : blocks) {
+    if (!split) {
+      v.push_back({b.s, b.o, b.lo, b.hi, -1, 0});
+      continue;
+    }
+    int32_t n = std::max(1, (b.hi - b.lo + kChunkTiles - 1) / kChunkTiles);
+    outs.push_back({b.s, b.o, slot, n});
+    for (int32_t c = 0; c < n; ++c) {
+      int32_t lo = b.lo + c * kChunkTiles, hi = std::min(b.hi, lo + kChunkTiles);
+      v.push_back({b.s, b.o, lo, std::max(lo, hi), slot++, 0});
+    }
+  }
   std::stable_sort(v.begin(), v.end(),
                    [](const MvItem& a, const MvItem& b) { return (a.hi - a.lo) > (b.hi - b.lo); });
   Items it;
   it.n = (int64_t)v.size();
   it.d = upload(v, C.owned, C.st);
+  it.n_slots = slot;
+  if (split) {
+    it.n_out = (int64_t)outs.size();
+    it.outs = upload(outs, C.owned, C.st);
+  }
+  C.max_slots = std::max<int64_t>(C.max_slots, slot);
   return it;
 }
 
@@ -217,9 +261,15 @@ static void build_device(Ctx& C, const double* coords) {
     HIPCHK(e);
     C.owned.push_back(p);
     C.d_tiles = p;
+    p = nullptr;
+    e = hipMalloc(&p, std::max<int64_t>(1, C.ntiles) * kTile * wsz);
+    if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation of the transposed store failed"};
+    HIPCHK(e);
+    C.owned.push_back(p);
+    C.d_tilesT = p;
   }
   // algorithmic byte counts (unpadded, packed triangles)
-  C.factor_bytes = C.ntiles * kTile * (int64_t)wsz;
+  C.factor_bytes = 2 * C.ntiles * kTile * (int64_t)wsz;
   for (int s = 0; s < nsub; ++s) {
     const SubInfo& q = P.subs[s];
     int64_t nr = q.nI + q.nG;
@@ -540,6 +590,10 @@ static void build_device(Ctx& C, const double* coords) {
     C.cg_T = make_items(C, gT);
     C.co_N = make_items(C, oN);
     C.co_T = make_items(C, oT);
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<int64_t>(1, C.max_slots) * kTile * C.nrhs * wsz / NB));
+    C.owned.push_back(p);
+    C.d_partial_mv = p;
   }
   // ---- work vectors --------------------------------------------------------------------
   const int nr = C.nrhs;
@@ -632,6 +686,10 @@ static int factor_impl(Ctx& C) {
                          C.d_csrc, C.d_cdest, tiles);
     factor_range<T>(C, C.nsub, 1);
   }
+  if (C.ntiles > 0)
+    hipLaunchKernelGGL(k_pack_tiles<T>, dim3((unsigned)C.ntiles), dim3(256), 0, st, C.ntiles, tiles,
+                       (T*)C.d_tilesT);
+  HIPCHK(hipGetLastError());
   int err = 0;
   HIPCHK(hipMemcpyAsync(&err, C.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -648,16 +706,88 @@ static int factor_impl(Ctx& C) {
 // ---------------------------------------------------------------------------
 // solve
 // ---------------------------------------------------------------------------
+static void prof_resolve(Ctx& C) {
+  if (C.ev_pending.empty()) return;
+  HIPCHK(hipStreamSynchronize(C.st));
+  for (auto& p : C.ev_pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+    C.prof_ms[p.first] += ms;
+    C.prof_n[p.first] += 1;
+  }
+  C.ev_pending.clear();
+  C.ev_next = 0;
+}
+
+static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
+  if (!C.prof) return false;
+  if (C.ev_next + 2 > C.ev_pool.size()) prof_resolve(C);
+  while (C.ev_pool.size() < C.ev_next + 2) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    C.ev_pool.push_back(e);
+  }
+  *a = C.ev_pool[C.ev_next++];
+  *b = C.ev_pool[C.ev_next++];
+  C.ev_pending.push_back({cls, {*a, *b}});
+  HIPCHK(hipEventRecord(*a, C.st));
+  return true;
+}
+
+static int item_class(const Ctx& C, const Items& it) {
+  if (&it == &C.trail_N || &it == &C.trail_T) return DD_PROF_TRAILING;
+  if (&it == &C.full_N || &it == &C.full_T) return DD_PROF_FULL;
+  if (&it == &C.co_N || &it == &C.co_T) return DD_PROF_COARSE;
+  return DD_PROF_COUPLING;
+}
+
+template <class T, int NV, int NB16, int CLS>
+static void mv_launch(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
+                      const int* skip) {
+  const bool split = it.n_out > 0;
+  const T* tiles = (const T*)(trans ? C.d_tilesT : C.d_tiles);
+  hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, C.st, it.n, it.d,
+                     C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, (int)trans,
+                     (T*)C.d_partial_mv, skip);
+  if (split)
+    hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, C.st, it.n_out, it.outs, C.d_subs,
+                       (const T*)C.d_partial_mv, (T*)out, (const T*)add, alpha, C.nrhs, skip);
+}
+
+template <class T, int CLS>
+static void mv_dispatch(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
+                        const int* skip) {
+  const int nr = C.nrhs;
+  if (nr == 1)
+    mv_launch<T, 1, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+  else if (nr == 2)
+    mv_launch<T, 2, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+  else if (nr <= 4)
+    mv_launch<T, 4, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+  else if (nr <= 8)
+    mv_launch<T, 8, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+  else if (nr <= 16)
+    mv_launch<T, 0, 1, CLS>(C, it, trans, in, out, add, alpha, skip);
+  else
+    mv_launch<T, 0, 2, CLS>(C, it, trans, in, out, add, alpha, skip);
+}
+
 template <class T>
 static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
                const int* skip = nullptr) {
   if (it.n == 0) return;
-  if (trans)
-    hipLaunchKernelGGL((k_tile_mv<T, true>), dim3((unsigned)it.n), dim3(256), 0, C.st, it.n, it.d, C.d_subs,
-                       (const T*)C.d_tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, skip);
+  hipEvent_t e0, e1;
+  bool timed = prof_begin(C, item_class(C, it), &e0, &e1);
+  const int cls = item_class(C, it);
+  if (cls == DD_PROF_TRAILING)
+    mv_dispatch<T, DD_PROF_TRAILING>(C, it, trans, in, out, add, alpha, skip);
+  else if (cls == DD_PROF_FULL)
+    mv_dispatch<T, DD_PROF_FULL>(C, it, trans, in, out, add, alpha, skip);
+  else if (cls == DD_PROF_COARSE)
+    mv_dispatch<T, DD_PROF_COARSE>(C, it, trans, in, out, add, alpha, skip);
   else
-    hipLaunchKernelGGL((k_tile_mv<T, false>), dim3((unsigned)it.n), dim3(256), 0, C.st, it.n, it.d, C.d_subs,
-                       (const T*)C.d_tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, skip);
+    mv_dispatch<T, DD_PROF_COUPLING>(C, it, trans, in, out, add, alpha, skip);
+  if (timed) HIPCHK(hipEventRecord(e1, C.st));
 }
 
 // coarse: y rows of Xin (coarse block) -> Xout coarse rows = K_cc^-1 y via
@@ -1145,6 +1275,7 @@ int dd_step(void* ctx, const double* J_half, const double* J_prev_half, const do
   API_BEGIN
   int rc = C.fp32 ? step_impl<float>(C, J_half, J_prev_half, E_n, E_nm1, E_next, stats)
                   : step_impl<double>(C, J_half, J_prev_half, E_n, E_nm1, E_next, stats);
+  prof_resolve(C);
   if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
   return rc;
   API_END
@@ -1264,6 +1395,29 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
                      (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t4, C.g_x, nr);
   dot_to_host(C, C.g_t2, C.g_x, ni, b);
   for (int r = 0; r < nr; ++r) out[r] = a[r] + b[r];
+  return DD_OK;
+  API_END
+}
+
+int dd_profile(void* ctx, int enable, double* ms, int64_t* launches) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  prof_resolve(C);
+  for (int i = 0; i < DD_PROF_CLASSES; ++i) {
+    if (ms) ms[i] = C.prof_ms[i];
+    if (launches) launches[i] = C.prof_n[i];
+  }
+  if (enable >= 0) {
+    C.prof = enable != 0;
+    for (int i = 0; i < DD_PROF_CLASSES; ++i) {
+      C.prof_ms[i] = 0.0;
+      C.prof_n[i] = 0;
+    }
+  }
   return DD_OK;
   API_END
 }

@@ -335,72 +335,245 @@ __global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const 
 
 // --------------------------------------------------------------------------
 // Batched tile products for the solves (the substitutions, applied through
-// the stored inverse factors).  One work item = (subdomain, output block o);
-// the block's contributing tiles are
-//   NOTRANS: (o, j), j in [jlo, jhi)      out_o  = sum_j tile(o,j)   in_j
-//   TRANS  : (i, o), i in [ilo, ihi)      out_o  = sum_i tile(i,o)^T in_i
-// 256 threads = 8 slots of 32 lanes; a slot takes every 8th tile, stages it
-// in LDS, and lane rho accumulates row (NOTRANS) or column (TRANS) rho of
-// the product for all right-hand sides; slots are summed at the end.
-// out_o = (add ? add_o : 0) + alpha * sum.
+// the stored inverse factors).
+//
+// Solve-phase tile layout ("operand order"): logical element (r, c) of a
+// tile sits at ((r/16)*4 + c/8)*128 + (r%16)*8 + c%8, so lane l = 16g + i of
+// a wave reads the 8 consecutive values (row mb*16+i, columns 8g..8g+7) of
+// row block mb as one contiguous 32-byte chunk: a whole tile is one fully
+// coalesced 64-lane sweep.  The store used for products with the tile
+// itself (NOTRANS) holds each tile in this order; a second store holds the
+// transposed tiles in the same order (TRANS).  Within one 16x16x4 MFMA the
+// reduction index of lane group g at step ks is column 8g + ks, so the
+// operand of every lane is a register of its contiguous chunk.
+//
+// One work item = one wave = (subdomain, output block o, tile range
+// [lo, hi)); NOTRANS tiles are (o, m), TRANS tiles (m, o), input block m:
+//     NOTRANS: acc = sum_m tile(o,m) in_m      TRANS: acc = sum_m tile(m,o)^T in_m
+// slot < 0: out_o = (add ? add_o : 0) + alpha acc; slot >= 0: partial[slot]
+// = acc (long ranges are split into chunks and summed by k_mv_reduce in a
+// fixed order, so results are deterministic).
+// Modes: nrhs <= NV uses vector FMAs (lanes of a column group reduced with
+// cross-lane shuffles); nrhs in 9..32 uses MFMA 16x16x4 in 16-wide RHS
+// blocks (NB16 of them).
 // --------------------------------------------------------------------------
 struct MvItem {
   int32_t s, o, lo, hi;  // subdomain, output block, tile range [lo, hi)
+  int32_t slot;          // -1: write the output block; else partial slot
+  int32_t pad_;
 };
 
-template <class T, bool TRANS>
+struct MvOut {
+  int32_t s, o, slot0, nslot;
+};
+
+__device__ __forceinline__ int64_t swz(int r, int c) {
+  return (int64_t)((r >> 4) * 4 + (c >> 3)) * 128 + (r & 15) * 8 + (c & 7);
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output row (within the 16-row block) of accumulator element v of lane l
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+template <class T>
+__device__ __forceinline__ void load_chunk8(const T* __restrict__ p, T* v) {
+  if constexpr (sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+    float4 a = q[0], b = q[1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+    double2 a = q[0], b = q[1], c = q[2], d = q[3];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y;
+  }
+}
+
+// NV > 0: vector path for nrhs <= NV; NV == 0: MFMA path with NB16 RHS blocks.
+// CLS only names the product class in kernel traces (0 interface blocks,
+// 1 full r-blocks, 2 corner coupling, 3 coarse).
+template <class T, int NV, int NB16, int CLS>
 __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* __restrict__ items,
-                                                 const SubDev* __restrict__ subs,
-                                                 const T* __restrict__ tiles, const T* __restrict__ in,
-                                                 T* __restrict__ out, const T* __restrict__ add, T alpha,
-                                                 int nrhs, const int* __restrict__ skip) {
+                                                 const SubDev* __restrict__ subs, const T* __restrict__ tiles,
+                                                 const T* __restrict__ in, T* __restrict__ out,
+                                                 const T* __restrict__ add, T alpha, int nrhs, int trans,
+                                                 T* __restrict__ partial, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int64_t it = blockIdx.x;
-  if (it >= n_items) return;
-  const MvItem w = items[it];
+  const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (wi >= n_items) return;
+  const MvItem w = items[wi];
   const SubDev q = subs[w.s];
-  constexpr int SLOTS = 8;
-  __shared__ T lds[SLOTS][kNB][kNB + 1];
-  const int tid = threadIdx.x;
-  const int slot = tid / kNB, rho = tid % kNB;
-  T acc[kMaxRhs];
+  const int l = threadIdx.x & 63;
+  const int g = l >> 4, i = l & 15;
+  const T* xbase = in + q.row_off * nrhs;
+  constexpr bool MF = NV == 0;
+  constexpr int NA = MF ? 2 * NB16 : 2 * NV;
+  // accumulators: vector path acc[mb*NV + r]; MFMA path acc[mb*NB16 + nb]
+  typename Mfma<T>::acc_t macc[MF ? 2 * NB16 : 1];
+  T vacc[MF ? 1 : NA];
+  if constexpr (MF) {
 #pragma unroll
-  for (int r = 0; r < kMaxRhs; ++r) acc[r] = 0;
-  const int cnt = w.hi - w.lo;
-  for (int base = 0; base < cnt; base += SLOTS) {
-    const int m = base + slot;
-    const bool active = m < cnt;
-    const int ti = TRANS ? (w.lo + m) : w.o;
-    const int tj = TRANS ? w.o : (w.lo + m);
-    __syncthreads();
-    if (active) {
-      const T* tp = tiles + tile_index(q, ti, tj) * kTile;
-      for (int e = rho; e < kTile; e += kNB) lds[slot][e / kNB][e % kNB] = tp[e];
+    for (int a = 0; a < 2 * NB16; ++a) macc[a] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+  } else {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) vacc[a] = 0;
+  }
+  T cur[16], nxt[16];
+  auto tile_ptr = [&](int m) -> const T* {
+    const int ti = trans ? m : w.o, tj = trans ? w.o : m;
+    return tiles + tile_index(q, ti, tj) * kTile;
+  };
+  if (w.lo < w.hi) {
+    const T* tp = tile_ptr(w.lo);
+    load_chunk8(tp + l * 8, cur);
+    load_chunk8(tp + 512 + l * 8, cur + 8);
+  }
+  for (int m = w.lo; m < w.hi; ++m) {
+    if (m + 1 < w.hi) {
+      const T* tp = tile_ptr(m + 1);
+      load_chunk8(tp + l * 8, nxt);
+      load_chunk8(tp + 512 + l * 8, nxt + 8);
     }
-    __syncthreads();
-    if (active) {
-      const int ib = TRANS ? ti : tj;  // input block
-      const T* xp = in + (q.row_off + (int64_t)ib * kNB) * nrhs;
-      for (int kk = 0; kk < kNB; ++kk) {
-        const T a = TRANS ? lds[slot][kk][rho] : lds[slot][rho][kk];
-        const T* xr = xp + kk * nrhs;
+    const T* xb = xbase + (int64_t)m * kNB * nrhs;
+    if constexpr (MF) {
 #pragma unroll
-        for (int r = 0; r < kMaxRhs; ++r)
-          if (r < nrhs) acc[r] += a * xr[r];
+      for (int nb = 0; nb < NB16; ++nb) {
+        const int col = nb * 16 + i;
+        T bv[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) bv[ks] = col < nrhs ? xb[(8 * g + ks) * nrhs + col] : (T)0;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          macc[nb] = Mfma<T>::op(cur[ks], bv[ks], macc[nb]);
+          macc[NB16 + nb] = Mfma<T>::op(cur[8 + ks], bv[ks], macc[NB16 + nb]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const T* xr = xb + (8 * g + ks) * nrhs;
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+          if (r < nrhs) {
+            const T xv = xr[r];
+            vacc[r] += cur[ks] * xv;
+            vacc[NV + r] += cur[8 + ks] * xv;
+          }
+        }
       }
     }
+    if (m + 1 < w.hi) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+    }
   }
-  // reduce the slots through LDS (reuse the tile buffers: SLOTS*NB*(NB+1) >= SLOTS*NB*nrhs)
-  __syncthreads();
-  T* red = &lds[0][0][0];
-  for (int r = 0; r < nrhs; ++r) red[(slot * kNB + rho) * nrhs + r] = acc[r];
-  __syncthreads();
-  T* op = out + (q.row_off + (int64_t)w.o * kNB) * nrhs;
-  const T* adp = add ? add + (q.row_off + (int64_t)w.o * kNB) * nrhs : nullptr;
-  for (int e = tid; e < kNB * nrhs; e += 256) {
+  // ---- epilogue ------------------------------------------------------------
+  T* dst;
+  const T* adp = nullptr;
+  T scale;
+  if (w.slot < 0) {
+    dst = out + (q.row_off + (int64_t)w.o * kNB) * nrhs;
+    if (add) adp = add + (q.row_off + (int64_t)w.o * kNB) * nrhs;
+    scale = alpha;
+  } else {
+    dst = partial + (int64_t)w.slot * kNB * nrhs;
+    scale = (T)1;
+  }
+  if constexpr (MF) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb) {
+        const int col = nb * 16 + i;
+        if (col < nrhs) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = mb * 16 + Mfma<T>::row(l, v);
+            const int64_t o = (int64_t)row * nrhs + col;
+            T val = scale * macc[mb * NB16 + nb][v];
+            if (adp) val += adp[o];
+            dst[o] = val;
+          }
+        }
+      }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      T v = vacc[a];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      vacc[a] = v;
+    }
+    // lane group g writes right-hand sides r with r % 4 == g
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < NV; ++r) {
+        if (r < nrhs && (r & 3) == g) {
+          const int64_t o = (int64_t)(mb * 16 + i) * nrhs + r;
+          T val = scale * vacc[mb * NV + r];
+          if (adp) val += adp[o];
+          dst[o] = val;
+        }
+      }
+  }
+}
+
+// out_o = (add ? add_o : 0) + alpha * sum of the item's partial slots
+template <class T>
+__global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* __restrict__ outs,
+                                                   const SubDev* __restrict__ subs, const T* __restrict__ partial,
+                                                   T* __restrict__ out, const T* __restrict__ add, T alpha,
+                                                   int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  if ((int64_t)blockIdx.x >= n_out) return;
+  const MvOut w = outs[blockIdx.x];
+  const SubDev q = subs[w.s];
+  const int64_t base = (q.row_off + (int64_t)w.o * kNB) * nrhs;
+  for (int e = threadIdx.x; e < kNB * nrhs; e += 256) {
     T s = 0;
-    for (int sl = 0; sl < SLOTS; ++sl) s += red[sl * kNB * nrhs + e];
-    op[e] = (adp ? adp[e] : (T)0) + alpha * s;
+    for (int k = 0; k < w.nslot; ++k) s += partial[(int64_t)(w.slot0 + k) * kNB * nrhs + e];
+    T v = alpha * s;
+    if (add) v += add[base + e];
+    out[base + e] = v;
+  }
+}
+
+// Reorder every tile of a store from row-major into operand order, and
+// write the operand-order transposed copy into tT.
+template <class T>
+__global__ void __launch_bounds__(256) k_pack_tiles(int64_t ntiles, T* __restrict__ tN, T* __restrict__ tT) {
+  const int64_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  __shared__ T a[kNB][kNB + 1];
+  T* p = tN + t * kTile;
+  for (int e = threadIdx.x; e < kTile; e += 256) a[e / kNB][e % kNB] = p[e];
+  __syncthreads();
+  T* q = tT + t * kTile;
+  for (int e = threadIdx.x; e < kTile; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    p[swz(r, c)] = a[r][c];
+    q[swz(r, c)] = a[c][r];
   }
 }
 

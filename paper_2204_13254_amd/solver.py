@@ -162,6 +162,17 @@ class DDSolver:
         check(self.lib.dd_energy(self.h, _dev(E_next), _dev(E_n), out.ctypes.data_as(C.c_void_p)))
         return out
 
+    PROF_CLASSES = ("trailing", "full", "coupling", "coarse")
+
+    def profile(self, enable=-1):
+        """Per-class (ms, launches) of the tile products since the last reset;
+        enable=1/0 turns event timing on/off and resets."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        check(self.lib.dd_profile(self.h, int(enable), ms.ctypes.data_as(C.c_void_p),
+                                  n.ctypes.data_as(C.c_void_p)))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
+
     def last_stats(self):
         s = self.stats
         n = self.nrhs

@@ -178,3 +178,20 @@ def test_errors_reported():
         _solver(c, t, p, -eps, dt=0.05)
     with pytest.raises(DDError, match="DD_ERR_PARTITION"):
         _solver(c, t, p + 1, eps, dt=0.05)
+
+
+@pytest.mark.parametrize("prec,nrhs,tol", [("fp64", 12, 1e-10), ("fp32_refine", 16, 1e-8),
+                                           ("fp32_refine", 20, 1e-8), ("fp64", 5, 1e-10)])
+def test_rhs_block_paths(prec, nrhs, tol):
+    """Every right-hand-side block width of the tile products (vector FMA
+    for <= 8, MFMA 16x16x4 for 9..32) on an uneven partition with corners."""
+    c, t, p, eps = _case(8, ("rcb", 3, 5), grade=1.5, eps_seed=13)
+    dt = 0.04
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, 4, dt, 0.08, 0.03, seed=31, nrhs=nrhs)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, precision=prec,
+                cg_tol=1e-12 if prec == "fp64" else 1e-6)
+    E, _ = _run_dd(s, J)
+    err = relerr(E[1:], o.run(J)[1:])
+    print(prec, nrhs, "max rel err", err.max(), flush=True)
+    assert err.max() <= tol
