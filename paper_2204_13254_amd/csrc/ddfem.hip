@@ -82,7 +82,7 @@ struct Items {
   int64_t n_slots = 0;   // partial slots used (0 = direct writes)
 };
 
-constexpr int kChunkTiles = 16;  // longest tile range of one wave
+constexpr int kChunkTiles = 32;  // longest tile range of one wave
 
 struct Ctx {
   Plan P;
@@ -197,10 +197,11 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks) {
       continue;
     }
     int32_t n = std::max(1, (b.hi - b.lo + kChunkTiles - 1) / kChunkTiles);
+    int32_t oidx = (int32_t)outs.size();
     outs.push_back({b.s, b.o, slot, n});
     for (int32_t c = 0; c < n; ++c) {
       int32_t lo = b.lo + c * kChunkTiles, hi = std::min(b.hi, lo + kChunkTiles);
-      v.push_back({b.s, b.o, lo, std::max(lo, hi), slot++, 0});
+      v.push_back({b.s, b.o, lo, std::max(lo, hi), slot++, oidx});
     }
   }
   std::stable_sort(v.begin(), v.end(),
@@ -800,7 +801,7 @@ static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* s
 
 // F p -> Fp (uses X5..X8)
 template <class T>
-static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip) {
+static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false) {
   const int nr = C.nrhs;
   hipStream_t st = C.st;
   void **X = C.X;
@@ -820,8 +821,8 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip) {
   } else {
     mv<T>(C, C.trail_T, true, X[6], X[8], nullptr, (T)1, skip);
   }
-  hipLaunchKernelGGL(k_lambda_scatter<T>, dim3(nblk(C.nlam * nr)), dim3(256), 0, st, C.nlam, C.d_lrow0,
-                     C.d_lrow1, (const T*)X[8], Fp, nr, skip);
+  hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
+                     (const T*)X[8], Fp, dot ? p : (const double*)nullptr, nr, C.d_partial, skip);
 }
 
 static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, double* out) {
@@ -870,13 +871,13 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
   int status = DD_OK;
   if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
-    hipLaunchKernelGGL(k_lambda_scatter<T>, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
-                       (const T*)X[4], C.d_d, nr, (const int*)nullptr);
+    hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
+                       (const T*)X[4], C.d_d, (const double*)nullptr, nr, C.d_partial, (const int*)nullptr);
     // ---- CG on F lambda = d ----------------------------------------------------
     HIPCHK(hipMemsetAsync(C.d_cg, 0, sizeof(CgState), st));
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
                        C.d_partial, (const int*)nullptr);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
     HIPCHK(hipMemcpyAsync(C.d_res, C.d_d, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (warm && *have_prev) {
       HIPCHK(hipMemcpyAsync(C.d_lam, lam_prev, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -884,7 +885,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
       hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_d, C.d_Fp, C.d_res);
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
                          C.d_partial, (const int*)nullptr);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 3, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 3, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
     } else {
       HIPCHK(hipMemsetAsync(C.d_lam, 0, nl * sizeof(double), st));
     }
@@ -899,15 +900,11 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
     while (!converged && it < C.opt.cg_max_iter) {
       int todo = std::min(chk, C.opt.cg_max_iter - it);
       for (int k = 0; k < todo; ++k) {
-        apply_F<T>(C, C.d_p, C.d_Fp, done);
-        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_p, C.d_Fp, nr,
-                           C.d_partial, done);
-        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
-        hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_p, C.d_Fp,
-                           C.d_lam, C.d_res);
-        hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
-                           C.d_partial, done);
-        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(64), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+        apply_F<T>(C, C.d_p, C.d_Fp, done, true);
+        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+        hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                           C.d_p, C.d_Fp, C.d_lam, C.d_res, C.d_partial);
+        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
         hipLaunchKernelGGL(k_cg_p, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_res, C.d_p);
       }
       it += todo;

@@ -350,9 +350,12 @@ __global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const 
 // One work item = one wave = (subdomain, output block o, tile range
 // [lo, hi)); NOTRANS tiles are (o, m), TRANS tiles (m, o), input block m:
 //     NOTRANS: acc = sum_m tile(o,m) in_m      TRANS: acc = sum_m tile(m,o)^T in_m
-// slot < 0: out_o = (add ? add_o : 0) + alpha acc; slot >= 0: partial[slot]
-// = acc (long ranges are split into chunks and summed by k_mv_reduce in a
-// fixed order, so results are deterministic).
+// slot < 0: out_o = (add ? add_o : 0) + alpha acc.  Long ranges are split
+// into chunks: each chunk writes partial[slot] and k_mv_reduce sums the
+// slots of each output block in slot order (deterministic).  (A last-wave
+// reduction inside this kernel needs device-scope release/acquire fences,
+// which write back / invalidate the per-XCD L2 and cost far more than the
+// extra launch.)
 // Modes: nrhs <= NV uses vector FMAs (lanes of a column group reduced with
 // cross-lane shuffles); nrhs in 9..32 uses MFMA 16x16x4 in 16-wide RHS
 // blocks (NB16 of them).
@@ -360,7 +363,7 @@ __global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const 
 struct MvItem {
   int32_t s, o, lo, hi;  // subdomain, output block, tile range [lo, hi)
   int32_t slot;          // -1: write the output block; else partial slot
-  int32_t pad_;
+  int32_t oidx;          // split items: index of the output block's MvOut
 };
 
 struct MvOut {
@@ -752,7 +755,7 @@ __global__ void k_csr(int mode, int64_t nint, const int64_t* __restrict__ rp, co
 // K8: conjugate gradients on the interface system, per right-hand side.
 // Dot products: fixed-order two-stage reductions (deterministic).
 // --------------------------------------------------------------------------
-constexpr int kDotBlocks = 256;
+constexpr int kDotBlocks = 1024;
 
 __global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double* __restrict__ x,
                                                      const double* __restrict__ y, int nrhs,
@@ -779,6 +782,41 @@ __global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double* __
   }
 }
 
+// Block-level sum of per-thread values s (thread layout tid = lane*nrhs + r)
+// into partial[blockIdx.x][r].
+__device__ __forceinline__ void block_rhs_sum(double s, int nrhs, int lanes_per_rhs, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  red[tid] = s;
+  __syncthreads();
+  if (tid < nrhs) {
+    double t = 0.0;
+    for (int l = 0; l < lanes_per_rhs; ++l) t += red[l * nrhs + tid];
+    partial[blockIdx.x * kMaxRhs + tid] = t;
+  }
+}
+
+// F p = sum_s B_s u_s (each multiplier pulls its two copies, + lo, - hi),
+// fused with the block partials of p . Fp.
+template <class T>
+__global__ void __launch_bounds__(256) k_scatter_dot(int64_t nlam, const int64_t* __restrict__ row0,
+                                                     const int64_t* __restrict__ row1, const T* __restrict__ u,
+                                                     double* __restrict__ Fp, const double* __restrict__ p, int nrhs,
+                                                     double* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lpr = 256 / nrhs;
+  const int tid = threadIdx.x, r = tid % nrhs, lane = tid / nrhs;
+  double s = 0.0;
+  if (lane < lpr) {
+    for (int64_t l = (int64_t)blockIdx.x * lpr + lane; l < nlam; l += (int64_t)gridDim.x * lpr) {
+      const double f = (double)u[row0[l] * nrhs + r] - (double)u[row1[l] * nrhs + r];
+      Fp[l * nrhs + r] = f;
+      if (p) s += p[l * nrhs + r] * f;
+    }
+  }
+  block_rhs_sum(s, nrhs, lpr, partial);
+}
+
 struct CgState {
   double rr[kMaxRhs];      // current r.r
   double rr0[kMaxRhs];     // d.d (relative tolerance reference)
@@ -799,9 +837,21 @@ __global__ void k_cg_scalar(int stage, int nrhs, const double* __restrict__ part
   __shared__ int any_active;
   if (r == 0) any_active = 0;
   __syncthreads();
+  // fixed-order two-level sum of the block partials: thread t sums blocks
+  // t/nrhs, t/nrhs + L, ... of rhs t%nrhs, then lanes are added in order
+  __shared__ double part[256];
+  {
+    const int t = threadIdx.x, lpr = blockDim.x / nrhs, rr = t % nrhs, ln = t / nrhs;
+    double a = 0.0;
+    if (ln < lpr)
+      for (int b = ln; b < kDotBlocks; b += lpr) a += partial[b * kMaxRhs + rr];
+    part[t] = a;
+    __syncthreads();
+  }
   if (r < nrhs) {
+    const int lpr = blockDim.x / nrhs;
     double s = 0.0;
-    for (int b = 0; b < kDotBlocks; ++b) s += partial[b * kMaxRhs + r];
+    for (int ln = 0; ln < lpr; ++ln) s += part[ln * nrhs + r];
     if (stage == 0) {
       st->rr[r] = s;
       st->rr0[r] = s;
@@ -855,6 +905,28 @@ __global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, con
   double a = st->alpha[r];
   lam[i] += a * p[i];
   res[i] -= a * Fp[i];
+}
+
+// lambda += alpha p ; r -= alpha Fp, fused with the block partials of r . r
+__global__ void __launch_bounds__(256) k_cg_xr_dot(int64_t n, int nrhs, const CgState* __restrict__ st,
+                                                   const double* __restrict__ p, const double* __restrict__ Fp,
+                                                   double* __restrict__ lam, double* __restrict__ res,
+                                                   double* __restrict__ partial) {
+  if (st->done) return;
+  const int lpr = 256 / nrhs;
+  const int tid = threadIdx.x, r = tid % nrhs, lane = tid / nrhs;
+  double s = 0.0;
+  if (lane < lpr) {
+    const double a = st->alpha[r];
+    for (int64_t l = (int64_t)blockIdx.x * lpr + lane; l < n; l += (int64_t)gridDim.x * lpr) {
+      const int64_t i = l * nrhs + r;
+      lam[i] += a * p[i];
+      const double rv = res[i] - a * Fp[i];
+      res[i] = rv;
+      s += rv * rv;
+    }
+  }
+  block_rhs_sum(s, nrhs, lpr, partial);
 }
 
 // p = r + beta p for active rhs
