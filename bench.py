@@ -41,7 +41,7 @@ def _beam_worker(args):
     return beam_source(coords, tets, edges, n, 0, dt, 1, steps=steps, **b)[:, 0, :]
 
 
-def make_sources(w, coords, tets, steps, workers):
+def make_sources(w, coords, tets, steps, workers, start_method="fork"):
     import numpy as np
     from workloads.mesh import mesh_edges
     if w.extra.get("source") != "beam":
@@ -50,7 +50,7 @@ def make_sources(w, coords, tets, steps, workers):
     jobs = [(coords, tets, edges, w.n, w.dt, w.extra["beam"], r, list(steps)) for r in range(w.nrhs)]
     if workers > 1:
         import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
+        with mp.get_context(start_method).Pool(min(workers, len(jobs))) as pool:
             parts = pool.map(_beam_worker, jobs)
     else:
         parts = [_beam_worker(j) for j in jobs]

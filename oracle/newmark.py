@@ -74,9 +74,9 @@ class NewmarkOracle:
         d = self.d
         self.A = (d.T + (self.beta * self.dt ** 2) * d.S).tocsc()
         self.B1 = (2.0 * d.T + ((2.0 * self.beta - 1.0) * self.dt ** 2) * d.S).tocsr()
-        self.perm = nested_dissection(self.d)
         self.lu = None
         if factor:
+            self.perm = nested_dissection(self.d)
             Ap = self.A[self.perm][:, self.perm].tocsc()
             # A is SPD: keep the diagonal pivots, so this is a symmetric LU
             # in the given (fill-reducing) order.
