@@ -96,6 +96,31 @@ def cpu_baseline(target_nint, nrhs, seconds_hint=20.0):
     }
 
 
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "ddfem.hip"):
+        with open(os.path.join(ROOT, "paper_2204_13254_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profiles(cls):
+    """Counter-derived HBM bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by
+    the copy-kernel calibration), or None when no summary matches the current
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != kernel_source_sha():
+        return None
+    v = t.get("classes", {}).get(cls)
+    return None if v is None else v.get("bytes_per_launch")
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -116,6 +141,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 512 MiB elementwise copy (read + write of known size) for "
+                         "scaling hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the decomposition is batched inside one "
@@ -221,6 +249,18 @@ def main():
     other = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                  "GBps": (round(algo[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if k in algo and v[1] else None)}
              for k, v in prof.items()}
+
+    # HBM traffic per launch of the dominant class, from committed counter
+    # summaries, valid only for the kernel source they were taken on
+    roof["traffic"] = _traffic_from_profiles(dom)
+
+    if args.calib_copy:
+        x = torch.ones(64 << 20, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
 
     # ---------------- plain FP64 form --------------------------------------------------
     plain = None
