@@ -80,9 +80,12 @@ struct Items {
   MvOut* outs = nullptr; // output blocks to reduce (split lists only)
   int64_t n_out = 0;
   int64_t n_slots = 0;   // partial slots used (0 = direct writes)
+  int32_t* mlist = nullptr;  // tile list (ranges index it), or null for contiguous ranges
 };
 
 constexpr int kChunkTiles = 32;  // longest tile range of one wave
+// coarse lists are few and long; 16-tile chunks measured best (8: +10%, 4: +28%)
+constexpr int kCoarseChunkTiles = 16;
 
 struct Ctx {
   Plan P;
@@ -92,6 +95,7 @@ struct Ctx {
   int nrhs = 1;
   bool fp32 = false;
   bool factored = false;
+  bool coarse_lists = false;  // coarse products use the nonzero-tile lists
   std::vector<void*> owned;
 
   // sizes
@@ -108,7 +112,8 @@ struct Ctx {
   void* d_tiles = nullptr;   // factor store; operand-order tiles after dd_factor
   void* d_tilesT = nullptr;  // operand-order transposed tiles
   void* d_partial_mv = nullptr;
-  int64_t max_slots = 0;
+  int64_t max_slots = 0;        // largest slot count of any work list
+  int64_t partial_slots = 0;    // slots d_partial_mv holds
   void* d_scratch = nullptr;
   int64_t* d_scratch_off = nullptr;
   int* d_err = nullptr;
@@ -181,13 +186,25 @@ struct Ctx {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-// Work list of one batched product: every output block whose tile range is
+// Work list of one batched product.  Every output block whose tile range is
 // longer than kChunkTiles is split into chunks writing partial slots, then
 // summed by k_mv_reduce.
-static Items make_items(Ctx& C, const std::vector<MvItem>& blocks) {
+//
+// Placement: workgroups are dispatched round-robin over the 8 XCDs (group b
+// runs on XCD b % 8) and each XCD has its own L2.  All items of one
+// subdomain read the same input blocks, so subdomains are assigned to XCDs
+// (greedy by tile count) and the list is interleaved so that group b only
+// holds items of XCD b % 8, longest first (measured on par with a single
+// global longest-first list; placing each subdomain's items consecutively
+// was slightly slower).
+// Padding items (s = -1) fill the ragged end.
+constexpr int kXcds = 8;
+constexpr int kWavesPerGroup = 4;
+
+static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = kChunkTiles) {
   bool split = false;
   for (const MvItem& b : blocks)
-    if (b.hi - b.lo > kChunkTiles) split = true;
+    if (b.hi - b.lo > chunk) split = true;
   std::vector<MvItem> v;
   std::vector<MvOut> outs;
   int32_t slot = 0;
@@ -196,19 +213,55 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks) {
       v.push_back({b.s, b.o, b.lo, b.hi, -1, 0});
       continue;
     }
-    int32_t n = std::max(1, (b.hi - b.lo + kChunkTiles - 1) / kChunkTiles);
+    int32_t n = std::max(1, (b.hi - b.lo + chunk - 1) / chunk);
     int32_t oidx = (int32_t)outs.size();
     outs.push_back({b.s, b.o, slot, n});
     for (int32_t c = 0; c < n; ++c) {
-      int32_t lo = b.lo + c * kChunkTiles, hi = std::min(b.hi, lo + kChunkTiles);
+      int32_t lo = b.lo + c * chunk, hi = std::min(b.hi, lo + chunk);
       v.push_back({b.s, b.o, lo, std::max(lo, hi), slot++, oidx});
     }
   }
-  std::stable_sort(v.begin(), v.end(),
-                   [](const MvItem& a, const MvItem& b) { return (a.hi - a.lo) > (b.hi - b.lo); });
+  // XCD assignment: subdomains by greedy load; the coarse block (a single
+  // "subdomain" holding many items, with small shared inputs) round-robin
+  std::vector<int64_t> load_s(C.nsub + 1, 0);
+  for (const MvItem& it : v) load_s[it.s] += it.hi - it.lo + 1;
+  std::vector<int32_t> order(C.nsub);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load_s[a] > load_s[b]; });
+  std::vector<int> xcd_of(C.nsub + 1, 0);
+  int64_t xload[kXcds] = {0};
+  for (int s : order) {
+    int best = 0;
+    for (int x = 1; x < kXcds; ++x)
+      if (xload[x] < xload[best]) best = x;
+    xcd_of[s] = best;
+    xload[best] += load_s[s];
+  }
+  std::vector<std::vector<MvItem>> lists(kXcds);
+  int rr = 0;
+  for (const MvItem& it : v) {
+    int x = it.s < C.nsub ? xcd_of[it.s] : (rr++ % kXcds);
+    lists[x].push_back(it);
+  }
+  size_t groups = 0;
+  // within an XCD: longest first
+  for (auto& L : lists) {
+    std::stable_sort(L.begin(), L.end(), [&](const MvItem& a, const MvItem& b) {
+      return (a.hi - a.lo) > (b.hi - b.lo);
+    });
+    groups = std::max(groups, (L.size() + kWavesPerGroup - 1) / kWavesPerGroup);
+  }
+  std::vector<MvItem> placed(groups * kXcds * kWavesPerGroup, MvItem{-1, 0, 0, 0, -1, 0});
+  for (size_t g = 0; g < groups; ++g)
+    for (int x = 0; x < kXcds; ++x)
+      for (int w = 0; w < kWavesPerGroup; ++w) {
+        size_t k = g * kWavesPerGroup + w;
+        if (k < lists[x].size()) placed[(g * kXcds + x) * kWavesPerGroup + w] = lists[x][k];
+      }
+  if (v.empty()) placed.clear();
   Items it;
-  it.n = (int64_t)v.size();
-  it.d = upload(v, C.owned, C.st);
+  it.n = (int64_t)placed.size();
+  it.d = upload(placed, C.owned, C.st);
   it.n_slots = slot;
   if (split) {
     it.n_out = (int64_t)outs.size();
@@ -595,6 +648,7 @@ static void build_device(Ctx& C, const double* coords) {
     HIPCHK(hipMalloc(&p, std::max<int64_t>(1, C.max_slots) * kTile * C.nrhs * wsz / NB));
     C.owned.push_back(p);
     C.d_partial_mv = p;
+    C.partial_slots = std::max<int64_t>(1, C.max_slots);
   }
   // ---- work vectors --------------------------------------------------------------------
   const int nr = C.nrhs;
@@ -663,6 +717,54 @@ static void factor_range(Ctx& C, int s0, int cnt) {
   HIPCHK(hipGetLastError());
 }
 
+// Replace the coarse work lists by lists of the nonzero tiles of the coarse
+// inverse factor (fixed by the corner order, so built once).
+template <class T>
+static void coarse_tile_lists(Ctx& C) {
+  const SubDev& qc = C.subs_h[C.nsub];
+  const int K = qc.K;
+  const int64_t nt = (int64_t)K * (K + 1) / 2;
+  int32_t* d_nnz = nullptr;
+  HIPCHK(hipMalloc((void**)&d_nnz, nt * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)nt), dim3(256), 0, C.st, qc.tile_off, nt, (const T*)C.d_tiles,
+                     d_nnz);
+  std::vector<int32_t> nnz(nt);
+  HIPCHK(hipMemcpyAsync(nnz.data(), d_nnz, nt * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+  HIPCHK(hipFree(d_nnz));
+  auto at = [&](int i, int j) { return nnz[(int64_t)i * (i + 1) / 2 + j]; };
+  std::vector<int32_t> ln, lt;
+  std::vector<MvItem> bn, bt;
+  int64_t entries = 0;
+  for (int o = 0; o < K; ++o) {
+    int32_t b = (int32_t)ln.size();
+    for (int j = 0; j <= o; ++j)
+      if (at(o, j)) {
+        ln.push_back(j);
+        entries += at(o, j);
+      }
+    bn.push_back({C.nsub, o, b, (int32_t)ln.size(), -1, 0});
+    b = (int32_t)lt.size();
+    for (int i = o; i < K; ++i)
+      if (at(i, o)) lt.push_back(i);
+    bt.push_back({C.nsub, o, b, (int32_t)lt.size(), -1, 0});
+  }
+  // few output blocks: short chunks so that the product fills the device
+  C.co_N = make_items(C, bn, kCoarseChunkTiles);
+  C.co_N.mlist = upload(ln, C.owned, C.st);
+  C.co_T = make_items(C, bt, kCoarseChunkTiles);
+  C.co_T.mlist = upload(lt, C.owned, C.st);
+  C.coarse_bytes = entries * (int64_t)sizeof(T);
+  C.coarse_lists = true;
+  if (C.max_slots > C.partial_slots) {  // short coarse chunks may need more partial slots
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, C.max_slots * kNB * C.nrhs * sizeof(T)));
+    C.owned.push_back(p);
+    C.d_partial_mv = p;
+    C.partial_slots = C.max_slots;
+  }
+}
+
 template <class T>
 static int factor_impl(Ctx& C) {
   Plan& P = C.P;
@@ -691,6 +793,7 @@ static int factor_impl(Ctx& C) {
     hipLaunchKernelGGL(k_pack_tiles<T>, dim3((unsigned)C.ntiles), dim3(256), 0, st, C.ntiles, tiles,
                        (T*)C.d_tilesT);
   HIPCHK(hipGetLastError());
+  if (C.Kc > 0 && !C.coarse_lists) coarse_tile_lists<T>(C);
   int err = 0;
   HIPCHK(hipMemcpyAsync(&err, C.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -749,7 +852,7 @@ static void mv_launch(Ctx& C, const Items& it, bool trans, const void* in, void*
   const T* tiles = (const T*)(trans ? C.d_tilesT : C.d_tiles);
   hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, C.st, it.n, it.d,
                      C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, (int)trans,
-                     (T*)C.d_partial_mv, skip);
+                     (T*)C.d_partial_mv, (const int32_t*)it.mlist, skip);
   if (split)
     hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, C.st, it.n_out, it.outs, C.d_subs,
                        (const T*)C.d_partial_mv, (T*)out, (const T*)add, alpha, C.nrhs, skip);
@@ -1013,16 +1116,16 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
   const int64_t ni = C.P.nint, ne = C.P.ne;
   hipStream_t st = C.st;
   const int64_t n = ni * nr;
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, En, ne, C.g_t1, nr, 1.0);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, Enm1, ne, C.g_t2, nr, 1.0);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, J0, ne, C.g_x, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, En, ne, C.g_t1, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, Enm1, ne, C.g_t2, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J0, ne, C.g_x, nr, 1.0);
   hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 0, ni, C.d_rp, C.d_ci, C.d_vals,
                      (const double*)C.g_t1, (const double*)C.g_t2, (const double*)C.g_t3, (const double*)C.g_x,
                      (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_b,
                      (double*)nullptr, nr);
   int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start != 0, C.d_lam_prev, &C.have_prev, stats);
-  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
+  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
                      Enext, nr, 0, 1.0);
   HIPCHK(hipGetLastError());
   return status;
@@ -1033,10 +1136,10 @@ static int solve_api_impl(Ctx& C, const double* b, double* x, dd_stats* stats) {
   const int nr = C.nrhs;
   const int64_t ni = C.P.nint, ne = C.P.ne;
   hipStream_t st = C.st;
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni * nr)), dim3(256), 0, st, ni, C.d_interior, b, ne, C.g_t1, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, b, ne, C.g_t1, nr,
                      1.0);
   int status = solve_refined<T>(C, C.g_t1, C.g_e, false, nullptr, nullptr, stats);
-  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e, x,
+  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e, x,
                      nr, 0, 1.0);
   HIPCHK(hipGetLastError());
   return status;
@@ -1050,7 +1153,7 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
   const int64_t ni = C.P.nint, ne = C.P.ne;
   hipStream_t st = C.st;
   const int64_t n = ni * nr;
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, ebar_next, ne, C.g_t1, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, ebar_next, ne, C.g_t1, nr,
                      1.0);
   int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start != 0, C.d_lam_prev_adj, &C.have_prev_adj,
                                 stats);
@@ -1060,22 +1163,22 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
                      (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_t2,
                      C.g_t3, nr);
   if (ebar_n)
-    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t2,
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t2,
                        ebar_n, nr, 1, 1.0);
   if (ebar_nm1)
-    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t3,
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t3,
                        ebar_nm1, nr, 1, -1.0);
   if (g_out)
-    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne * nr)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_x,
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_x,
                        g_out, nr, 0, 1.0);
   if (eps_bar) {
     // acc = e^{n+1} - 2 e^n + e^{n-1} in unknown-major layout
-    hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
+    hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
                        1.0);
-    hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
+    hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
                        1.0);
     if (E_nm1)
-      hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_nm1, ne, C.g_t4,
+      hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_nm1, ne, C.g_t4,
                          nr, 1.0);
     hipLaunchKernelGGL(k_second_diff, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t2,
                        (const double*)C.g_t3, (const double*)(E_nm1 ? C.g_t4 : nullptr), C.g_t2);
@@ -1340,7 +1443,7 @@ int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res) 
   API_BEGIN
   const int nr = C.nrhs;
   const int64_t ni = C.P.nint, ne = C.P.ne, nv = C.P.nv;
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni * nr)), dim3(256), 0, C.st, ni, C.d_interior, E, ne, C.g_t1, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, C.st, ni, C.d_interior, E, ne, C.g_t1, nr,
                      1.0);
   hipLaunchKernelGGL(k_csr, dim3(nblk(ni * nr)), dim3(256), 0, C.st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
                      (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
@@ -1371,15 +1474,15 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
   const int64_t ni = C.P.nint, ne = C.P.ne, n = ni * nr;
   hipStream_t st = C.st;
   // g_t1 = (e1 - e0)/dt, g_t2 = (e1 + e0)/2
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t1, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t1, nr,
                      1.0 / C.dt);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
                      1.0 / C.dt);
   hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t1, (const double*)C.g_t3,
                      C.g_t1);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
                      0.5);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(n)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr, 0.5);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr, 0.5);
   hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t3, C.g_t2);
   // T dv -> g_t3 (S dv unused -> g_t4); then S av -> g_x (T av -> g_t4)
   hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,

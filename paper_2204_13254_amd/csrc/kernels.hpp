@@ -337,18 +337,19 @@ __global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const 
 // Batched tile products for the solves (the substitutions, applied through
 // the stored inverse factors).
 //
-// Solve-phase tile layout ("operand order"): logical element (r, c) of a
-// tile sits at ((r/16)*4 + c/8)*128 + (r%16)*8 + c%8, so lane l = 16g + i of
-// a wave reads the 8 consecutive values (row mb*16+i, columns 8g..8g+7) of
-// row block mb as one contiguous 32-byte chunk: a whole tile is one fully
-// coalesced 64-lane sweep.  The store used for products with the tile
+// Solve-phase tile layout ("operand order"): lane l = 16g + i of a wave
+// holds the 8 values (row mb*16+i, columns 8g..8g+7) of row block mb, laid
+// out so that each 16-byte load instruction of the wave reads one contiguous
+// kilobyte (swz / load_chunk8): a whole tile is one fully coalesced sweep.  The store used for products with the tile
 // itself (NOTRANS) holds each tile in this order; a second store holds the
 // transposed tiles in the same order (TRANS).  Within one 16x16x4 MFMA the
 // reduction index of lane group g at step ks is column 8g + ks, so the
 // operand of every lane is a register of its contiguous chunk.
 //
 // One work item = one wave = (subdomain, output block o, tile range
-// [lo, hi)); NOTRANS tiles are (o, m), TRANS tiles (m, o), input block m:
+// [lo, hi)); with a tile list (mlist != null, used for the sparse coarse
+// inverse factor) the range indexes mlist and m = mlist[k].  NOTRANS tiles
+// are (o, m), TRANS tiles (m, o), input block m:
 //     NOTRANS: acc = sum_m tile(o,m) in_m      TRANS: acc = sum_m tile(m,o)^T in_m
 // slot < 0: out_o = (add ? add_o : 0) + alpha acc.  Long ranges are split
 // into chunks: each chunk writes partial[slot] and k_mv_reduce sums the
@@ -370,8 +371,14 @@ struct MvOut {
   int32_t s, o, slot0, nslot;
 };
 
-__device__ __forceinline__ int64_t swz(int r, int c) {
-  return (int64_t)((r >> 4) * 4 + (c >> 3)) * 128 + (r & 15) * 8 + (c & 7);
+// operand-order position of logical element (r, c) of a tile: row block
+// mb = r/16, lane l = 16*(c/8) + r%16, value k = c%8 of that lane, stored
+// as vector q = k/V, component k%V, V = 16/sizeof(T) (see load_chunk8)
+template <class T>
+__device__ __forceinline__ int swz(int r, int c) {
+  constexpr int V = 16 / sizeof(T);
+  const int l = 16 * (c >> 3) + (r & 15), k = c & 7;
+  return (r >> 4) * 512 + (k / V) * 64 * V + l * V + (k % V);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -397,18 +404,25 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
 };
 
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+
+// 8 values of lane l from one row block (512 elements) in operand order:
+// the q-th 16-byte vector of every lane sits at q*64*V + l*V (V = 16/sizeof(T)),
+// so each load instruction of the wave reads one contiguous kilobyte.
+// (Non-temporal hints on these loads were measured slower.)
 template <class T>
-__device__ __forceinline__ void load_chunk8(const T* __restrict__ p, T* v) {
+__device__ __forceinline__ void load_chunk8(const T* __restrict__ blk, int l, T* v) {
   if constexpr (sizeof(T) == 4) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-    float4 a = q[0], b = q[1];
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    const f32x4v* q = reinterpret_cast<const f32x4v*>(blk);
+    f32x4v a = q[l], b = q[64 + l];
+    v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+    v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
   } else {
-    const double2* q = reinterpret_cast<const double2*>(p);
-    double2 a = q[0], b = q[1], c = q[2], d = q[3];
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-    v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y;
+    const f64x2v* q = reinterpret_cast<const f64x2v*>(blk);
+    f64x2v a = q[l], b = q[64 + l], c = q[128 + l], d = q[192 + l];
+    v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+    v[4] = c[0]; v[5] = c[1]; v[6] = d[0]; v[7] = d[1];
   }
 }
 
@@ -420,11 +434,13 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, int nrhs, int trans,
-                                                 T* __restrict__ partial, const int* __restrict__ skip) {
+                                                 T* __restrict__ partial, const int32_t* __restrict__ mlist,
+                                                 const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wi >= n_items) return;
   const MvItem w = items[wi];
+  if (w.s < 0) return;  // padding item
   const SubDev q = subs[w.s];
   const int l = threadIdx.x & 63;
   const int g = l >> 4, i = l & 15;
@@ -441,37 +457,68 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
 #pragma unroll
     for (int a = 0; a < NA; ++a) vacc[a] = 0;
   }
-  T cur[16], nxt[16];
+  // factor values of the current / next tile, and (prefetched together with
+  // them) the input values the lane needs: MFMA path bv[nb][ks] = x[8g+ks][nb*16+i],
+  // vector path (NV <= 2) x[8g+ks][r]; wider vector paths load x inline
+  constexpr bool PX = MF || NV <= 2;
+  constexpr int NX = PX ? 8 * (MF ? NB16 : NV) : 1;
+  T cur[16], nxt[16], xc[NX], xn[NX];
   auto tile_ptr = [&](int m) -> const T* {
     const int ti = trans ? m : w.o, tj = trans ? w.o : m;
     return tiles + tile_index(q, ti, tj) * kTile;
   };
-  if (w.lo < w.hi) {
-    const T* tp = tile_ptr(w.lo);
-    load_chunk8(tp + l * 8, cur);
-    load_chunk8(tp + 512 + l * 8, cur + 8);
-  }
-  for (int m = w.lo; m < w.hi; ++m) {
-    if (m + 1 < w.hi) {
-      const T* tp = tile_ptr(m + 1);
-      load_chunk8(tp + l * 8, nxt);
-      load_chunk8(tp + 512 + l * 8, nxt + 8);
-    }
+  auto load_x = [&](int m, T* xv) {
     const T* xb = xbase + (int64_t)m * kNB * nrhs;
     if constexpr (MF) {
 #pragma unroll
       for (int nb = 0; nb < NB16; ++nb) {
         const int col = nb * 16 + i;
-        T bv[8];
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) bv[ks] = col < nrhs ? xb[(8 * g + ks) * nrhs + col] : (T)0;
+        for (int ks = 0; ks < 8; ++ks) xv[nb * 8 + ks] = col < nrhs ? xb[(8 * g + ks) * nrhs + col] : (T)0;
+      }
+    } else if constexpr (PX) {
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int r = 0; r < NV; ++r) xv[ks * NV + r] = r < nrhs ? xb[(8 * g + ks) * nrhs + r] : (T)0;
+    }
+  };
+  auto mof = [&](int k) -> int { return mlist ? mlist[k] : k; };
+  if (w.lo < w.hi) {
+    const int m0 = mof(w.lo);
+    const T* tp = tile_ptr(m0);
+    load_chunk8(tp, l, cur);
+    load_chunk8(tp + 512, l, cur + 8);
+    load_x(m0, xc);
+  }
+  for (int k = w.lo; k < w.hi; ++k) {
+    const int m = mof(k);
+    if (k + 1 < w.hi) {
+      const int m1 = mof(k + 1);
+      const T* tp = tile_ptr(m1);
+      load_chunk8(tp, l, nxt);
+      load_chunk8(tp + 512, l, nxt + 8);
+      load_x(m1, xn);
+    }
+    if constexpr (MF) {
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb) {
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
-          macc[nb] = Mfma<T>::op(cur[ks], bv[ks], macc[nb]);
-          macc[NB16 + nb] = Mfma<T>::op(cur[8 + ks], bv[ks], macc[NB16 + nb]);
+          macc[nb] = Mfma<T>::op(cur[ks], xc[nb * 8 + ks], macc[nb]);
+          macc[NB16 + nb] = Mfma<T>::op(cur[8 + ks], xc[nb * 8 + ks], macc[NB16 + nb]);
         }
       }
+    } else if constexpr (PX) {
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+          vacc[r] += cur[ks] * xc[ks * NV + r];
+          vacc[NV + r] += cur[8 + ks] * xc[ks * NV + r];
+        }
     } else {
+      const T* xb = xbase + (int64_t)m * kNB * nrhs;
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks) {
         const T* xr = xb + (8 * g + ks) * nrhs;
@@ -485,9 +532,13 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
         }
       }
     }
-    if (m + 1 < w.hi) {
+    if (k + 1 < w.hi) {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) cur[k] = nxt[k];
+      for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+      if constexpr (PX) {
+#pragma unroll
+        for (int u = 0; u < NX; ++u) xc[u] = xn[u];
+      }
     }
   }
   // ---- epilogue ------------------------------------------------------------
@@ -562,6 +613,24 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* _
   }
 }
 
+// Nonzero count of every tile in [t0, t0 + n) (structural zeros of a
+// nested-dissection-ordered factor and of its inverse are exact zeros).
+template <class T>
+__global__ void __launch_bounds__(256) k_tile_nnz(int64_t t0, int64_t n, const T* __restrict__ tiles,
+                                                  int32_t* __restrict__ nnz) {
+  const int64_t t = blockIdx.x;
+  if (t >= n) return;
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const T* p = tiles + (t0 + t) * kTile;
+  int c = 0;
+  for (int e = threadIdx.x; e < kTile; e += 256) c += p[e] != (T)0;
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) nnz[t] = cnt;
+}
+
 // Reorder every tile of a store from row-major into operand order, and
 // write the operand-order transposed copy into tT.
 template <class T>
@@ -575,8 +644,8 @@ __global__ void __launch_bounds__(256) k_pack_tiles(int64_t ntiles, T* __restric
   T* q = tT + t * kTile;
   for (int e = threadIdx.x; e < kTile; e += 256) {
     const int r = e / kNB, c = e % kNB;
-    p[swz(r, c)] = a[r][c];
-    q[swz(r, c)] = a[c][r];
+    p[swz<T>(r, c)] = a[r][c];
+    q[swz<T>(r, c)] = a[c][r];
   }
 }
 
@@ -683,27 +752,52 @@ __global__ void k_collect(int64_t nint, const int64_t* __restrict__ dsrc, const 
 // Layout changes between caller arrays [nrhs][n_edges] and unknown-major
 // [nint][nrhs].
 // --------------------------------------------------------------------------
-__global__ void k_edges_to_int(int64_t nint, const int32_t* __restrict__ interior, const double* __restrict__ src,
-                               int64_t ne, double* __restrict__ dst, int nrhs, double scale) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nint * nrhs) return;
-  int64_t d = i / nrhs;
-  int r = (int)(i % nrhs);
-  dst[i] = scale * src[(int64_t)r * ne + interior[d]];
+// Both are transposes through an LDS tile of 64 rows x nrhs, so global reads
+// and writes are coalesced on both sides.
+__global__ void __launch_bounds__(256) k_edges_to_int(int64_t nint, const int32_t* __restrict__ interior,
+                                                      const double* __restrict__ src, int64_t ne,
+                                                      double* __restrict__ dst, int nrhs, double scale) {
+  __shared__ double tile[64][kMaxRhs + 1];
+  const int64_t d0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * nrhs; e += 256) {
+    const int r = e / 64, dl = e % 64;
+    const int64_t d = d0 + dl;
+    if (d < nint) tile[dl][r] = scale * src[(int64_t)r * ne + interior[d]];
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * nrhs; e += 256) {
+    const int dl = e / nrhs, r = e % nrhs;
+    const int64_t d = d0 + dl;
+    if (d < nint) dst[d * nrhs + r] = tile[dl][r];
+  }
 }
 
-__global__ void k_int_to_edges(int64_t ne, const int32_t* __restrict__ dof, const double* __restrict__ src,
-                               double* __restrict__ dst, int nrhs, int accumulate, double scale) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ne * nrhs) return;
-  int r = (int)(i / ne);
-  int64_t e = i % ne;
-  int32_t d = dof[e];
-  double v = d >= 0 ? scale * src[(int64_t)d * nrhs + r] : 0.0;
-  if (accumulate) {
-    if (d >= 0) dst[i] += v;
-  } else {
-    dst[i] = v;
+__global__ void __launch_bounds__(256) k_int_to_edges(int64_t ne, const int32_t* __restrict__ dof,
+                                                      const double* __restrict__ src, double* __restrict__ dst,
+                                                      int nrhs, int accumulate, double scale) {
+  __shared__ double tile[64][kMaxRhs + 1];
+  const int64_t e0 = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x;
+  for (int k = tid; k < 64 * nrhs; k += 256) {
+    const int el = k / nrhs, r = k % nrhs;
+    const int64_t e = e0 + el;
+    if (e < ne) {
+      const int32_t d = dof[e];
+      tile[el][r] = d >= 0 ? scale * src[(int64_t)d * nrhs + r] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < 64 * nrhs; k += 256) {
+    const int r = k / 64, el = k % 64;
+    const int64_t e = e0 + el;
+    if (e >= ne) continue;
+    const int64_t i = (int64_t)r * ne + e;
+    if (accumulate) {
+      if (dof[e] >= 0) dst[i] += tile[el][r];
+    } else {
+      dst[i] = tile[el][r];
+    }
   }
 }
 

@@ -19,6 +19,109 @@ void sort_unique(std::vector<T>& v) {
 }
 }  // namespace
 
+// Fill-reducing order of the corner unknowns (the coarse problem).  The
+// coarse matrix K_cc = sum_s B_c^T K_s B_c couples every pair of corners of
+// one subdomain.  Recursive coordinate bisection of the corner-edge
+// midpoints gives an edge cut of that graph; the cut-side vertices on the
+// lower side form the separator, ordered after both halves (nested
+// dissection).  Only the fill of the coarse factor and of its inverse
+// depends on this order (the solve stores and streams only nonzero tiles).
+static void order_corners(Plan& P, const double* coords) {
+  const int64_t nc = P.ncorner();
+  if (nc == 0) return;
+  std::vector<std::vector<int32_t>> adj(nc);
+  for (int32_t s = 0; s < P.nsub; ++s) {
+    const SubInfo& q = P.subs[s];
+    const auto& L = P.local[s];
+    for (int32_t a = 0; a < q.nC; ++a) {
+      int32_t I = P.dof_corner[L[q.nI + q.nG + a]];
+      for (int32_t b = 0; b < q.nC; ++b)
+        if (a != b) adj[I].push_back(P.dof_corner[L[q.nI + q.nG + b]]);
+    }
+  }
+  for (auto& v : adj) sort_unique(v);
+  std::vector<double> mid(3 * nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    int32_t e = P.interior[P.corner_dof[c]];
+    for (int k = 0; k < 3; ++k)
+      mid[3 * c + k] = 0.5 * (coords[3 * (int64_t)P.edges[2 * e] + k] + coords[3 * (int64_t)P.edges[2 * e + 1] + k]);
+  }
+  std::vector<int32_t> order;
+  order.reserve(nc);
+  std::vector<uint8_t> side(nc, 0);
+  const size_t leaf = 64;
+  // explicit recursion; a frame orders (left interior, right, separator)
+  struct Frame {
+    std::vector<int32_t> idx;
+    int stage;
+    std::vector<int32_t> right, sep;
+  };
+  std::vector<Frame> st;
+  std::vector<int32_t> all(nc);
+  std::iota(all.begin(), all.end(), 0);
+  st.push_back({all, 0, {}, {}});
+  while (!st.empty()) {
+    Frame& f = st.back();
+    if (f.stage == 0) {
+      if (f.idx.size() <= leaf) {
+        order.insert(order.end(), f.idx.begin(), f.idx.end());
+        st.pop_back();
+        continue;
+      }
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int32_t c : f.idx)
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = std::min(lo[k], mid[3 * c + k]);
+          hi[k] = std::max(hi[k], mid[3 * c + k]);
+        }
+      int ax = 0;
+      for (int k = 1; k < 3; ++k)
+        if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+      std::vector<double> xs;
+      xs.reserve(f.idx.size());
+      for (int32_t c : f.idx) xs.push_back(mid[3 * c + ax]);
+      std::nth_element(xs.begin(), xs.begin() + xs.size() / 2, xs.end());
+      const double med = xs[xs.size() / 2];
+      std::vector<int32_t> left, right;
+      for (int32_t c : f.idx) (mid[3 * c + ax] < med ? left : right).push_back(c);
+      if (left.empty() || right.empty()) {
+        order.insert(order.end(), f.idx.begin(), f.idx.end());
+        st.pop_back();
+        continue;
+      }
+      for (int32_t c : right) side[c] = 2;
+      std::vector<int32_t> lint, sep;
+      for (int32_t c : left) {
+        bool cut = false;
+        for (int32_t d : adj[c])
+          if (side[d] == 2) {
+            cut = true;
+            break;
+          }
+        (cut ? sep : lint).push_back(c);
+      }
+      for (int32_t c : right) side[c] = 0;
+      f.stage = 1;
+      f.right = std::move(right);
+      f.sep = std::move(sep);
+      std::vector<int32_t> l2 = std::move(lint);
+      st.push_back({std::move(l2), 0, {}, {}});
+    } else if (f.stage == 1) {
+      f.stage = 2;
+      std::vector<int32_t> r = std::move(f.right);
+      st.push_back({std::move(r), 0, {}, {}});
+    } else {
+      order.insert(order.end(), f.sep.begin(), f.sep.end());
+      st.pop_back();
+    }
+  }
+  // order[k] = old corner id placed at position k
+  std::vector<int32_t> cd(nc);
+  for (int64_t k = 0; k < nc; ++k) cd[k] = P.corner_dof[order[k]];
+  P.corner_dof = cd;
+  for (int64_t k = 0; k < nc; ++k) P.dof_corner[cd[k]] = (int32_t)k;
+}
+
 int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets,
                const int32_t* partition, Plan& P, std::string& msg) {
   if (nv <= 0 || nt <= 0 || !coords || !tets || !partition) {
@@ -239,6 +342,7 @@ int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets
       P.dof_corner[d] = (int32_t)P.corner_dof.size();
       P.corner_dof.push_back((int32_t)d);
     }
+  order_corners(P, coords);
   return DD_OK;
 }
 

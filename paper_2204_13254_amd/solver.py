@@ -86,15 +86,21 @@ class DDSolver:
         self.h = h
         self.nrhs = int(nrhs)
         self.dt = float(dt)
-        inf = Info()
-        check(self.lib.dd_get_info(h, C.byref(inf)))
-        self.info = inf
+        inf = self.info
         self.n_edges = inf.n_edges
         self.n_tets = inf.n_tets
         self.n_vertices = inf.n_vertices
         self.stats = Stats()
         if factor:
             self.factor()
+
+    @property
+    def info(self):
+        """Sizes and byte counts (the coarse byte count reflects the stored
+        nonzero tiles once the context is factorised)."""
+        inf = Info()
+        check(self.lib.dd_get_info(self.h, C.byref(inf)))
+        return inf
 
     # ---- lifecycle -----------------------------------------------------------------
     def close(self):
