@@ -149,7 +149,9 @@ struct Ctx {
   uint8_t* d_nodeint = nullptr;
   double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
   // work lists
-  Items full_N, full_T, trail_N, trail_T, cr_N, cr_T, cg_N, cg_T, co_N, co_T;
+  // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
+  // trail_*: interface block with Psi_Gamma; co_*: coarse inverse factor
+  Items full_N, full_T, trail_N, trail_T, co_N, co_T;
   // work vectors
   void* X[9] = {};
   int64_t nlam = 0;
@@ -327,9 +329,10 @@ static void build_device(Ctx& C, const double* coords) {
   for (int s = 0; s < nsub; ++s) {
     const SubInfo& q = P.subs[s];
     int64_t nr = q.nI + q.nG;
-    C.trailing_bytes += (int64_t)q.nG * (q.nG + 1) / 2 * wsz;
+    // inverse-factor triangle plus the premultiplied corner rows it carries
+    C.trailing_bytes += ((int64_t)q.nG * (q.nG + 1) / 2 + (int64_t)q.nC * q.nG) * wsz;
     C.coupling_bytes += (int64_t)q.nC * q.nG * wsz;
-    C.full_bytes += nr * (nr + 1) / 2 * wsz;
+    C.full_bytes += (nr * (nr + 1) / 2 + (int64_t)q.nC * nr) * wsz;
   }
   C.coarse_bytes = nc * (nc + 1) / 2 * (int64_t)wsz;
   // scratch rows for the triangular inversion
@@ -611,37 +614,33 @@ static void build_device(Ctx& C, const double* coords) {
   }
   // ---- work lists --------------------------------------------------------------------
   {
-    std::vector<MvItem> fN, fT, tN, tT, rN, rT, gN, gT, oN, oT;
+    // forward passes also produce the corner rows (Psi times the input),
+    // transposed passes run over [o, K) so they include Psi^T (corner inputs)
+    std::vector<MvItem> fN, fT, tN, tT, oN, oT;
     for (int s = 0; s < nsub; ++s) {
       const SubDev& q = C.subs_h[s];
       int kr = q.kI + q.kG;
       for (int o = 0; o < kr; ++o) {
-        fN.push_back({s, o, 0, o + 1});
-        fT.push_back({s, o, o, kr});
-        rT.push_back({s, o, kr, q.K});
-      }
-      for (int o = q.kI; o < kr; ++o) {
-        tN.push_back({s, o, q.kI, o + 1});
-        tT.push_back({s, o, o, kr});
-        gT.push_back({s, o, kr, q.K});
+        fN.push_back({s, o, 0, o + 1, -1, 0});
+        fT.push_back({s, o, o, q.K, -1, 0});
       }
       for (int o = kr; o < q.K; ++o) {
-        rN.push_back({s, o, 0, kr});
-        gN.push_back({s, o, q.kI, kr});
+        fN.push_back({s, o, 0, kr, -1, 0});
+        tN.push_back({s, o, q.kI, kr, -1, 0});
+      }
+      for (int o = q.kI; o < kr; ++o) {
+        tN.push_back({s, o, q.kI, o + 1, -1, 0});
+        tT.push_back({s, o, o, q.K, -1, 0});
       }
     }
     for (int o = 0; o < C.Kc; ++o) {
-      oN.push_back({nsub, o, 0, o + 1});
-      oT.push_back({nsub, o, o, C.Kc});
+      oN.push_back({nsub, o, 0, o + 1, -1, 0});
+      oT.push_back({nsub, o, o, C.Kc, -1, 0});
     }
     C.full_N = make_items(C, fN);
     C.full_T = make_items(C, fT);
     C.trail_N = make_items(C, tN);
     C.trail_T = make_items(C, tT);
-    C.cr_N = make_items(C, rN);
-    C.cr_T = make_items(C, rT);
-    C.cg_N = make_items(C, gN);
-    C.cg_T = make_items(C, gT);
     C.co_N = make_items(C, oN);
     C.co_T = make_items(C, oT);
     void* p = nullptr;
@@ -712,6 +711,14 @@ static void factor_range(Ctx& C, int s0, int cnt) {
     hipLaunchKernelGGL(k_trtri_row<T>, dim3(i, cnt), dim3(256), 0, st, i, s0, (const T*)tiles, C.d_subs,
                        C.d_scratch_off, (T*)C.d_scratch);
     hipLaunchKernelGGL(k_trtri_copy<T>, dim3(i, cnt), dim3(256), 0, st, i, s0, tiles, C.d_subs,
+                       C.d_scratch_off, (const T*)C.d_scratch);
+  }
+  int max_kc = 0;
+  for (int s = s0; s < s0 + cnt; ++s) max_kc = std::max(max_kc, C.subs_h[s].kC);
+  for (int c = 0; c < max_kc && max_kr > 0; ++c) {
+    hipLaunchKernelGGL(k_psi_row<T>, dim3(max_kr, cnt), dim3(256), 0, st, c, s0, (const T*)tiles, C.d_subs,
+                       C.d_scratch_off, (T*)C.d_scratch);
+    hipLaunchKernelGGL(k_psi_copy<T>, dim3(max_kr, cnt), dim3(256), 0, st, c, s0, tiles, C.d_subs,
                        C.d_scratch_off, (const T*)C.d_scratch);
   }
   HIPCHK(hipGetLastError());
@@ -841,56 +848,56 @@ static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
 static int item_class(const Ctx& C, const Items& it) {
   if (&it == &C.trail_N || &it == &C.trail_T) return DD_PROF_TRAILING;
   if (&it == &C.full_N || &it == &C.full_T) return DD_PROF_FULL;
-  if (&it == &C.co_N || &it == &C.co_T) return DD_PROF_COARSE;
-  return DD_PROF_COUPLING;
+  return DD_PROF_COARSE;
 }
 
 template <class T, int NV, int NB16, int CLS>
 static void mv_launch(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
-                      const int* skip) {
+                      const void* add_c, T alpha_c, const int* skip) {
   const bool split = it.n_out > 0;
   const T* tiles = (const T*)(trans ? C.d_tilesT : C.d_tiles);
   hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, C.st, it.n, it.d,
-                     C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, C.nrhs, (int)trans,
-                     (T*)C.d_partial_mv, (const int32_t*)it.mlist, skip);
+                     C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
+                     (int)trans, (T*)C.d_partial_mv, (const int32_t*)it.mlist, skip);
   if (split)
     hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, C.st, it.n_out, it.outs, C.d_subs,
-                       (const T*)C.d_partial_mv, (T*)out, (const T*)add, alpha, C.nrhs, skip);
+                       (const T*)C.d_partial_mv, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
+                       skip);
 }
 
 template <class T, int CLS>
 static void mv_dispatch(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
-                        const int* skip) {
+                        const void* add_c, T alpha_c, const int* skip) {
   const int nr = C.nrhs;
   if (nr == 1)
-    mv_launch<T, 1, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+    mv_launch<T, 1, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr == 2)
-    mv_launch<T, 2, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+    mv_launch<T, 2, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 4)
-    mv_launch<T, 4, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+    mv_launch<T, 4, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 8)
-    mv_launch<T, 8, 0, CLS>(C, it, trans, in, out, add, alpha, skip);
+    mv_launch<T, 8, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 16)
-    mv_launch<T, 0, 1, CLS>(C, it, trans, in, out, add, alpha, skip);
+    mv_launch<T, 0, 1, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
-    mv_launch<T, 0, 2, CLS>(C, it, trans, in, out, add, alpha, skip);
+    mv_launch<T, 0, 2, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
 }
 
+// out = add + alpha * (product) on r-row output blocks, add_c + alpha_c *
+// (product) on corner-row output blocks (forward passes only)
 template <class T>
 static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
-               const int* skip = nullptr) {
+               const int* skip = nullptr, const void* add_c = nullptr, T alpha_c = (T)1) {
   if (it.n == 0) return;
   hipEvent_t e0, e1;
   bool timed = prof_begin(C, item_class(C, it), &e0, &e1);
   const int cls = item_class(C, it);
   if (cls == DD_PROF_TRAILING)
-    mv_dispatch<T, DD_PROF_TRAILING>(C, it, trans, in, out, add, alpha, skip);
+    mv_dispatch<T, DD_PROF_TRAILING>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_FULL)
-    mv_dispatch<T, DD_PROF_FULL>(C, it, trans, in, out, add, alpha, skip);
-  else if (cls == DD_PROF_COARSE)
-    mv_dispatch<T, DD_PROF_COARSE>(C, it, trans, in, out, add, alpha, skip);
+    mv_dispatch<T, DD_PROF_FULL>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
-    mv_dispatch<T, DD_PROF_COUPLING>(C, it, trans, in, out, add, alpha, skip);
+    mv_dispatch<T, DD_PROF_COARSE>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   if (timed) HIPCHK(hipEventRecord(e1, C.st));
 }
 
@@ -902,7 +909,9 @@ static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* s
   mv<T>(C, C.co_T, true, Xtmp, Xout, nullptr, (T)1, skip);
 }
 
-// F p -> Fp (uses X5..X8)
+// F p -> Fp (uses X5..X8):
+//   v = B_s^T p;  [t; y] = [Linv_GG; Psi_G] v;  z = K_cc^-1 sum B_c^T y;
+//   u = [Linv_GG; Psi_G]^T [t; z];  F p = sum B_s u
 template <class T>
 static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false) {
   const int nr = C.nrhs;
@@ -912,18 +921,14 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
                      C.d_glam, p, (T*)X[5], nr, skip);
   mv<T>(C, C.trail_N, false, X[5], X[6], nullptr, (T)1, skip);
   if (C.Kc > 0) {
-    mv<T>(C, C.cg_N, false, X[6], X[6], nullptr, (T)1, skip);
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
                        (const T*)nullptr, nr, skip);
     coarse_solve<T>(C, X[6], X[7], X[5], skip);
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[5], nr, skip);
-    mv<T>(C, C.cg_T, true, X[5], X[7], X[6], (T)1, skip);
-    mv<T>(C, C.trail_T, true, X[7], X[8], nullptr, (T)1, skip);
-  } else {
-    mv<T>(C, C.trail_T, true, X[6], X[8], nullptr, (T)1, skip);
+                       C.d_csccrow, (const T*)X[5], (T*)X[6], (T)1, nr, skip);
   }
+  mv<T>(C, C.trail_T, true, X[6], X[8], nullptr, (T)1, skip);
   hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
                      (const T*)X[8], Fp, dot ? p : (const double*)nullptr, nr, C.d_partial, skip);
 }
@@ -953,20 +958,19 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
   // ---- pre-solve --------------------------------------------------------
   hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
                      (T*)X[0], nr);
-  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one);
-  mv<T>(C, C.cr_N, false, X[1], X[1], X[0], mone);  // corner rows: w_c - L_cr t
+  // r rows: t = Linv_rr w_r;  corner rows: g = w_c - Psi_r w_r
+  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, nullptr, X[0], mone);
   if (C.Kc > 0) {
+    // f_c = sum B_c^T g (coarse rows of X1, kept for the recovery); z0 = K_cc^-1 f_c
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[1], (T*)X[1],
                        (const T*)nullptr, nr, (const int*)nullptr);
     coarse_solve<T>(C, X[1], X[2], X[3], nullptr);
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[3], (T*)X[3], nr, (const int*)nullptr);
-    mv<T>(C, C.cg_T, true, X[3], X[2], X[1], mone);  // t_G - L_cG^T z0
-    mv<T>(C, C.trail_T, true, X[2], X[4], nullptr, one);
-  } else {
-    mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one);
+                       C.d_csccrow, (const T*)X[3], (T*)X[1], mone, nr, (const int*)nullptr);
   }
+  // d-contribution: Linv_GG^T t_G - Psi_G^T z0
+  mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one);
   for (int r = 0; r < nr; ++r) {
     iters[r] = 0;
     relres[r] = 0.0;
@@ -1029,26 +1033,28 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
       *have_prev = true;
     }
     // ---- recovery -------------------------------------------------------------------
+    // [t_l; y] = [Linv_GG; Psi_G] B_s^T lambda
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                        C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, (const int*)nullptr);
     mv<T>(C, C.trail_N, false, X[5], X[6], nullptr, one);
   } else {
-    // no interface: t_l = 0
+    // no interface: t_l = 0, y = 0
     HIPCHK(hipMemsetAsync(X[6], 0, C.rows_total * nr * sizeof(T), st));
   }
   if (C.Kc > 0) {
-    mv<T>(C, C.cg_N, false, X[6], X[6], nullptr, one);
+    // x_c = K_cc^-1 (f_c + sum B_c^T y)  (coarse rows of X5)
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
                        (const T*)X[1], nr, (const int*)nullptr);
     coarse_solve<T>(C, X[6], X[7], X[5], nullptr);
-    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[5], nr, (const int*)nullptr);
   }
+  // x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c: input rows t - [0; t_l], corner rows -x_c
   hipLaunchKernelGGL(k_sub_rows<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_gamma_row,
                      (const T*)X[1], (const T*)X[6], (T*)X[8], nr);
-  mv<T>(C, C.cr_T, true, X[5], X[7], X[8], mone);
-  mv<T>(C, C.full_T, true, X[7], X[5], nullptr, one);
+  if (C.Kc > 0)
+    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
+                       C.d_csccrow, (const T*)X[5], (T*)X[8], mone, nr, (const int*)nullptr);
+  mv<T>(C, C.full_T, true, X[8], X[5], nullptr, one);
   hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
                      (const T*)X[5], x, nr);
   HIPCHK(hipGetLastError());

@@ -322,6 +322,59 @@ __global__ void k_trtri_copy(int i, int s0, T* __restrict__ tiles, const SubDev*
   for (int e = threadIdx.x; e < kTile; e += blockDim.x) dst[e] = src[e];
 }
 
+// Corner coupling premultiplied by the inverse factor: corner tile row
+// i = kr + c becomes Psi(i, j) = sum_{m=j}^{kr-1} L_cr(i, m) Linv(m, j),
+// j < kr (all r rows already inverted), i.e. Psi_r = L_cr Linv_rr.  Then
+// L_cr t = Psi_r w and L_rr^-T L_cr^T z = Psi_r^T z, so the corner products
+// fold into the inverse-factor passes.  Written to scratch, then copied.
+template <class T>
+__global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restrict__ tiles,
+                                                 const SubDev* __restrict__ subs,
+                                                 const int64_t* __restrict__ scratch_off, T* __restrict__ scratch) {
+  const int sidx = s0 + blockIdx.y;
+  const SubDev q = subs[sidx];
+  const int j = blockIdx.x;
+  const int kr = q.kI + q.kG;
+  if (c >= q.kC || j >= kr) return;
+  const int i = kr + c;
+  __shared__ T A[kNB][kNB + 1];
+  __shared__ T B[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int r = tid / 8, c0 = 4 * (tid % 8);
+  T acc[4] = {0, 0, 0, 0};
+  for (int m = j; m < kr; ++m) {
+    const T* ap = tiles + tile_index(q, i, m) * kTile;  // L_cr(i, m)
+    const T* bp = tiles + tile_index(q, m, j) * kTile;  // Linv(m, j)
+    __syncthreads();
+    for (int e = tid; e < kTile; e += 256) {
+      A[e / kNB][e % kNB] = ap[e];
+      B[e / kNB][e % kNB] = bp[e];
+    }
+    __syncthreads();
+    for (int mm = 0; mm < kNB; ++mm) {
+      T av = A[r][mm];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += av * B[mm][c0 + u];
+    }
+  }
+  T* sp = scratch + (scratch_off[sidx] + j) * kTile;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) sp[r * kNB + c0 + u] = acc[u];
+}
+
+template <class T>
+__global__ void k_psi_copy(int c, int s0, T* __restrict__ tiles, const SubDev* __restrict__ subs,
+                           const int64_t* __restrict__ scratch_off, const T* __restrict__ scratch) {
+  const int sidx = s0 + blockIdx.y;
+  const SubDev q = subs[sidx];
+  const int j = blockIdx.x;
+  const int kr = q.kI + q.kG;
+  if (c >= q.kC || j >= kr) return;
+  T* dst = tiles + tile_index(q, kr + c, j) * kTile;
+  const T* src = scratch + (scratch_off[sidx] + j) * kTile;
+  for (int e = threadIdx.x; e < kTile; e += blockDim.x) dst[e] = src[e];
+}
+
 // Coarse corner matrix K_cc = sum_s B_c^T K_s B_c by pull (fixed order).
 template <class T>
 __global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const int64_t* __restrict__ src,
@@ -351,7 +404,8 @@ __global__ void k_pull_coarse(int64_t n, const int64_t* __restrict__ ptr, const 
 // inverse factor) the range indexes mlist and m = mlist[k].  NOTRANS tiles
 // are (o, m), TRANS tiles (m, o), input block m:
 //     NOTRANS: acc = sum_m tile(o,m) in_m      TRANS: acc = sum_m tile(m,o)^T in_m
-// slot < 0: out_o = (add ? add_o : 0) + alpha acc.  Long ranges are split
+// slot < 0: out_o = (add ? add_o : 0) + alpha acc; output blocks in the
+// corner rows (o >= kr) use add_c / alpha_c instead.  Long ranges are split
 // into chunks: each chunk writes partial[slot] and k_mv_reduce sums the
 // slots of each output block in slot order (deterministic).  (A last-wave
 // reduction inside this kernel needs device-scope release/acquire fences,
@@ -433,9 +487,9 @@ template <class T, int NV, int NB16, int CLS>
 __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* __restrict__ items,
                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                  const T* __restrict__ in, T* __restrict__ out,
-                                                 const T* __restrict__ add, T alpha, int nrhs, int trans,
-                                                 T* __restrict__ partial, const int32_t* __restrict__ mlist,
-                                                 const int* __restrict__ skip) {
+                                                 const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
+                                                 T alpha_c, int nrhs, int trans, T* __restrict__ partial,
+                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wi >= n_items) return;
@@ -546,9 +600,12 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
   const T* adp = nullptr;
   T scale;
   if (w.slot < 0) {
+    // corner output rows (o >= kr) take their own alpha / add
+    const bool crow = w.o >= q.kI + q.kG;
+    const T* ad = crow ? add_c : add;
     dst = out + (q.row_off + (int64_t)w.o * kNB) * nrhs;
-    if (add) adp = add + (q.row_off + (int64_t)w.o * kNB) * nrhs;
-    scale = alpha;
+    if (ad) adp = ad + (q.row_off + (int64_t)w.o * kNB) * nrhs;
+    scale = crow ? alpha_c : alpha;
   } else {
     dst = partial + (int64_t)w.slot * kNB * nrhs;
     scale = (T)1;
@@ -597,12 +654,16 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
 template <class T>
 __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* __restrict__ outs,
                                                    const SubDev* __restrict__ subs, const T* __restrict__ partial,
-                                                   T* __restrict__ out, const T* __restrict__ add, T alpha,
-                                                   int nrhs, const int* __restrict__ skip) {
+                                                   T* __restrict__ out, const T* __restrict__ add_r, T alpha_r,
+                                                   const T* __restrict__ add_c, T alpha_c, int nrhs,
+                                                   const int* __restrict__ skip) {
   if (skip && *skip) return;
   if ((int64_t)blockIdx.x >= n_out) return;
   const MvOut w = outs[blockIdx.x];
   const SubDev q = subs[w.s];
+  const bool crow = w.o >= q.kI + q.kG;
+  const T* add = crow ? add_c : add_r;
+  const T alpha = crow ? alpha_c : alpha_r;
   const int64_t base = (q.row_off + (int64_t)w.o * kNB) * nrhs;
   for (int e = threadIdx.x; e < kNB * nrhs; e += 256) {
     T s = 0;
@@ -713,10 +774,10 @@ __global__ void k_coarse_gather(int64_t ncrows, int64_t crow0, const int64_t* __
   y[o] = (T)s;
 }
 
-// Subdomain corner rows <- coarse solution (B_c z); crow = -1 -> 0.
+// Subdomain corner rows <- scale * coarse solution (B_c z); crow = -1 -> 0.
 template <class T>
 __global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, const int64_t* __restrict__ crow,
-                                 const T* __restrict__ z, T* __restrict__ x, int nrhs,
+                                 const T* __restrict__ z, T* __restrict__ x, T scale, int nrhs,
                                  const int* __restrict__ skip) {
   if (skip && *skip) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -724,7 +785,7 @@ __global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, co
   int64_t k = i / nrhs;
   int r = (int)(i % nrhs);
   int64_t c = crow[k];
-  x[rows[k] * nrhs + r] = c >= 0 ? z[c * nrhs + r] : (T)0;
+  x[rows[k] * nrhs + r] = c >= 0 ? scale * z[c * nrhs + r] : (T)0;
 }
 
 // y = a - b on listed rows (t - [0; t_lambda]); rows with flag 0 copy a.
