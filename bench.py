@@ -10,7 +10,8 @@ CG, recovery) and, in the mixed form, FP64 iterative refinement.
 Forms timed:
   * batched mixed (the reported value): 16 RHS per launch, FP32 factors and
     local products, FP64 CG (tol 1e-6) and FP64 refinement to a global
-    relative residual <= 1e-12, CG warm-started from the previous step;
+    relative residual <= 1e-12, CG warm-started from the previous step, CG
+    iteration blocks replayed from captured HIP graphs;
   * plain FP64: one RHS per decomposed solve (16 solves per step), FP64
     factors, CG tol 1e-12, no warm start.
 The factorisation (once per run) is timed separately and excluded from the
@@ -141,6 +142,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--graph", type=int, default=1,
+                    help="replay CG iteration blocks from captured HIP graphs in the timed steps "
+                         "(per-class event timing is then taken on extra eager steps)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB elementwise copy (read + write of known size) for "
                          "scaling hardware traffic counters")
@@ -173,13 +177,14 @@ def main():
 
     import torch
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
+    stream = torch.cuda.Stream(dev)          # default priority; capturable
+    torch.cuda.set_stream(stream)
 
     # ---------------- batched mixed form -------------------------------------
     t0 = time.perf_counter()
     s = DDSolver(coords, tets, part, eps, dt=w.dt, beta=w.beta, precision="fp32_refine", nrhs=w.nrhs,
                  cg_tol=1e-6, refine_tol=1e-12, refine_max=10, warm_start=True, factor=False,
-                 stream=stream)
+                 stream=stream, use_graph=bool(args.graph))
     t_setup = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -205,7 +210,8 @@ def main():
     for n in range(W):
         do_step(n)
     torch.cuda.synchronize()
-    s.profile(1)
+    if not args.graph:
+        s.profile(1)          # event timing of every tile product inside the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for n in range(W, W + K):
@@ -215,6 +221,12 @@ def main():
         gres.append(max(st["global_relres"]))
     torch.cuda.synchronize()
     t_mixed = time.perf_counter() - t0
+    if args.graph:
+        # graphs exclude per-launch events: time the classes on 3 extra eager steps
+        s.profile(1)
+        for n in range(W + K - 3, W + K):
+            do_step(n)
+        torch.cuda.synchronize()
     prof = s.profile(0)
     ms_step = 1e3 * t_mixed / K
     sps = K / t_mixed

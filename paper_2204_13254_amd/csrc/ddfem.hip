@@ -95,6 +95,8 @@ struct Ctx {
   int nrhs = 1;
   bool fp32 = false;
   bool factored = false;
+  hipGraphExec_t cg_graph = nullptr;  // captured block of CG iterations
+  int cg_graph_iters = 0;
   bool coarse_lists = false;  // coarse products use the nonzero-tile lists
   std::vector<void*> owned;
 
@@ -178,6 +180,7 @@ struct Ctx {
 
   ~Ctx() {
     if (st) (void)hipStreamSynchronize(st);
+    if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : owned) (void)hipFree(p);
     if (h_done) (void)hipHostFree(h_done);
@@ -1004,15 +1007,36 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
     HIPCHK(hipMemcpyAsync(C.h_done, done, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     converged = *C.h_done != 0;
+    // one CG iteration; every kernel returns at once when all RHS converged
+    auto iteration = [&]() {
+      apply_F<T>(C, C.d_p, C.d_Fp, done, true);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                         C.d_p, C.d_Fp, C.d_lam, C.d_res, C.d_partial);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_p, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_res, C.d_p);
+    };
+    // the block of chk iterations is captured once (fixed buffers, fixed
+    // arguments) and replayed; needs a capturable (non-default) stream and
+    // no per-launch event timing
+    const bool graph = C.opt.use_graph && st != nullptr && !C.prof;
+    if (graph && (!C.cg_graph || C.cg_graph_iters != chk)) {
+      if (C.cg_graph) HIPCHK(hipGraphExecDestroy(C.cg_graph));
+      C.cg_graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < chk; ++k) iteration();
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamEndCapture(st, &g));
+      HIPCHK(hipGraphInstantiate(&C.cg_graph, g, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(g));
+      C.cg_graph_iters = chk;
+    }
     while (!converged && it < C.opt.cg_max_iter) {
       int todo = std::min(chk, C.opt.cg_max_iter - it);
-      for (int k = 0; k < todo; ++k) {
-        apply_F<T>(C, C.d_p, C.d_Fp, done, true);
-        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
-        hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
-                           C.d_p, C.d_Fp, C.d_lam, C.d_res, C.d_partial);
-        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
-        hipLaunchKernelGGL(k_cg_p, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_res, C.d_p);
+      if (graph && todo == chk) {
+        HIPCHK(hipGraphLaunch(C.cg_graph, st));
+      } else {
+        for (int k = 0; k < todo; ++k) iteration();
       }
       it += todo;
       HIPCHK(hipGetLastError());

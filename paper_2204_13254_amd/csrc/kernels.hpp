@@ -28,6 +28,46 @@ __device__ __forceinline__ int64_t tile_index(const SubDev& q, int i, int j) {
   return q.tile_off + (int64_t)i * (i + 1) / 2 + j;
 }
 
+// 16x16x4 MFMA (f32 / f64).  Operands (checked on the device): lane l gives
+// A[l%16][l/16] and B[l/16][l%16]; accumulator element v of lane l is
+// D[row(l, v)][l%16], with row = 4(l/16) + v for f32 and l/16 + 4v for f64.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output row (within the 16-row block) of accumulator element v of lane l
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+// One wave's 16x16 block (mb, nb) of a 32x32 tile product from LDS tiles:
+// BT ? A B^T : A B, accumulated into acc.
+template <class T, bool BT>
+__device__ __forceinline__ void tile_mma(const T (*A)[kNB + 1], const T (*B)[kNB + 1], int mb, int nb, int l,
+                                         typename Mfma<T>::acc_t& acc) {
+  const int i = l & 15, g = l >> 4;
+#pragma unroll
+  for (int ks = 0; ks < kNB / 4; ++ks) {
+    const T a = A[mb * 16 + i][ks * 4 + g];
+    const T b = BT ? B[nb * 16 + i][ks * 4 + g] : B[ks * 4 + g][nb * 16 + i];
+    acc = Mfma<T>::op(a, b, acc);
+  }
+}
+
 // --------------------------------------------------------------------------
 // K1: element matrices (Sec. II-B-1, Whitney 1-forms), FP64.
 // Te[(ij),(kl)] = eps V/20 [(1+d_ik) g_j.g_l - (1+d_il) g_j.g_k
@@ -193,8 +233,6 @@ __global__ void __launch_bounds__(256) k_potrf(int k, int s0, T* __restrict__ ti
   if (tid == 0 && bad) atomicMin(err, s0 + (int)blockIdx.x);
 }
 
-// C (NB x NB) = op over two LDS tiles; each of 256 threads owns 4 entries
-// (row tid/8, columns 4*(tid%8)..+3).
 template <class T>
 __global__ void __launch_bounds__(256) k_trsm(int k, int s0, T* __restrict__ tiles,
                                               const SubDev* __restrict__ subs) {
@@ -211,15 +249,12 @@ __global__ void __launch_bounds__(256) k_trsm(int k, int s0, T* __restrict__ til
     Dv[e / kNB][e % kNB] = dp[e];
   }
   __syncthreads();
-  const int r = tid / 8, c0 = 4 * (tid % 8);
-  T acc[4] = {0, 0, 0, 0};
-  for (int m = 0; m < kNB; ++m) {
-    T av = A[r][m];
+  // L_ik = A_ik Dinv_k^T on MFMA: wave w computes block (w/2, w%2)
+  const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+  tile_mma<T, true>(A, Dv, mb, nb, l, acc);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] += av * Dv[c0 + u][m];  // (A Dinv^T)[r][c] = sum_m A[r][m] Dinv[c][m]
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) ap[r * kNB + c0 + u] = acc[u];
+  for (int v = 0; v < 4; ++v) ap[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] = acc[v];
 }
 
 template <class T>
@@ -246,15 +281,12 @@ __global__ void __launch_bounds__(256) k_syrk(int k, int s0, T* __restrict__ til
     B[e / kNB][e % kNB] = bp[e];
   }
   __syncthreads();
-  const int r = tid / 8, c0 = 4 * (tid % 8);
-  T acc[4] = {0, 0, 0, 0};
-  for (int m = 0; m < kNB; ++m) {
-    T av = A[r][m];
+  // C_ij -= L_ik L_jk^T on MFMA: wave w computes block (w/2, w%2)
+  const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+  tile_mma<T, true>(A, B, mb, nb, l, acc);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] += av * B[c0 + u][m];
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) cp[r * kNB + c0 + u] -= acc[u];
+  for (int v = 0; v < 4; ++v) cp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] -= acc[v];
 }
 
 // --------------------------------------------------------------------------
@@ -275,8 +307,8 @@ __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __res
   __shared__ T A[kNB][kNB + 1];
   __shared__ T B[kNB][kNB + 1];
   const int tid = threadIdx.x;
-  const int r = tid / 8, c0 = 4 * (tid % 8);
-  T acc[4] = {0, 0, 0, 0};
+  const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
   for (int m = j; m < i; ++m) {
     const T* ap = tiles + tile_index(q, i, m) * kTile;  // L_im
     const T* bp = tiles + tile_index(q, m, j) * kTile;  // Linv_mj
@@ -286,28 +318,20 @@ __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __res
       B[e / kNB][e % kNB] = bp[e];
     }
     __syncthreads();
-    for (int mm = 0; mm < kNB; ++mm) {
-      T av = A[r][mm];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += av * B[mm][c0 + u];
-    }
+    tile_mma<T, false>(A, B, mb, nb, l, acc);
   }
-  // multiply by -Dinv_i
+  // multiply by -Dinv_i (MFMA again, the sum staged in LDS)
   __syncthreads();
   const T* dp = tiles + tile_index(q, i, i) * kTile;
   for (int e = tid; e < kTile; e += 256) A[e / kNB][e % kNB] = dp[e];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) B[r][c0 + u] = acc[u];
+  for (int v = 0; v < 4; ++v) B[mb * 16 + Mfma<T>::row(l, v)][nb * 16 + (l & 15)] = acc[v];
   __syncthreads();
-  T out[4] = {0, 0, 0, 0};
-  for (int mm = 0; mm <= r; ++mm) {
-    T dv = A[r][mm];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) out[u] += dv * B[mm][c0 + u];
-  }
+  typename Mfma<T>::acc_t out = {0, 0, 0, 0};
+  tile_mma<T, false>(A, B, mb, nb, l, out);
   T* sp = scratch + (scratch_off[sidx] + j) * kTile;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) sp[r * kNB + c0 + u] = -out[u];
+  for (int v = 0; v < 4; ++v) sp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] = -out[v];
 }
 
 template <class T>
@@ -340,8 +364,8 @@ __global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restr
   __shared__ T A[kNB][kNB + 1];
   __shared__ T B[kNB][kNB + 1];
   const int tid = threadIdx.x;
-  const int r = tid / 8, c0 = 4 * (tid % 8);
-  T acc[4] = {0, 0, 0, 0};
+  const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
   for (int m = j; m < kr; ++m) {
     const T* ap = tiles + tile_index(q, i, m) * kTile;  // L_cr(i, m)
     const T* bp = tiles + tile_index(q, m, j) * kTile;  // Linv(m, j)
@@ -351,15 +375,11 @@ __global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restr
       B[e / kNB][e % kNB] = bp[e];
     }
     __syncthreads();
-    for (int mm = 0; mm < kNB; ++mm) {
-      T av = A[r][mm];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += av * B[mm][c0 + u];
-    }
+    tile_mma<T, false>(A, B, mb, nb, l, acc);
   }
   T* sp = scratch + (scratch_off[sidx] + j) * kTile;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) sp[r * kNB + c0 + u] = acc[u];
+  for (int v = 0; v < 4; ++v) sp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] = acc[v];
 }
 
 template <class T>
@@ -435,28 +455,6 @@ __device__ __forceinline__ int swz(int r, int c) {
   return (r >> 4) * 512 + (k / V) * 64 * V + l * V + (k % V);
 }
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-template <class T>
-struct Mfma;
-template <>
-struct Mfma<float> {
-  typedef f32x4 acc_t;
-  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // output row (within the 16-row block) of accumulator element v of lane l
-  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-template <>
-struct Mfma<double> {
-  typedef f64x4 acc_t;
-  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
 
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 typedef double f64x2v __attribute__((ext_vector_type(2)));
