@@ -64,7 +64,8 @@ typedef struct {
   int cg_max_iter;    /* cap on CG iterations per solve */
   double refine_tol;  /* relative global residual ||b - A e|| / ||b|| (FP32_REFINE) */
   int refine_max;     /* cap on refinement sweeps (FP32_REFINE) */
-  int warm_start;     /* start CG from the previous solve's multipliers */
+  int warm_start;     /* initial multipliers of a step's first CG solve: 0 zero, 1 the
+                         previous step's, 2 linear extrapolation of the last two steps */
   int use_graph;      /* replay the CG iteration as a captured HIP graph */
   int check_every;    /* CG iterations between host convergence checks (>= 1) */
   void* stream;       /* hipStream_t; NULL = default stream */
@@ -76,6 +77,7 @@ typedef struct {
   int dd_solves;           /* DD solves in the last step (1 + sweeps) */
   double cg_relres[32];    /* final relative interface residual, per RHS */
   double global_relres[32];/* final ||b - A e|| / ||b|| (FP32_REFINE), per RHS */
+  int solve_iters[4];      /* max over RHS of the CG iterations of DD solves 1..4 of the step */
 } dd_stats;
 
 typedef struct {

@@ -26,7 +26,8 @@ class Options(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("cg_iters", C.c_int * 32), ("refine_sweeps", C.c_int), ("dd_solves", C.c_int),
-                ("cg_relres", C.c_double * 32), ("global_relres", C.c_double * 32)]
+                ("cg_relres", C.c_double * 32), ("global_relres", C.c_double * 32),
+                ("solve_iters", C.c_int * 4)]
 
 
 class Info(C.Structure):

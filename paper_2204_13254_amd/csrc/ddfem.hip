@@ -158,8 +158,14 @@ struct Ctx {
   void* X[9] = {};
   int64_t nlam = 0;
   double *d_d = nullptr, *d_lam = nullptr, *d_res = nullptr, *d_p = nullptr, *d_Fp = nullptr;
-  double *d_lam_prev = nullptr, *d_lam_prev_adj = nullptr;
-  bool have_prev = false, have_prev_adj = false;
+  // multipliers of the first solve of the last two steps (forward / adjoint),
+  // for warm starts: previous value, or linear extrapolation 2 l^n - l^{n-1}
+  struct Warm {
+    double* cur = nullptr;
+    double* old = nullptr;
+    int have = 0;
+  };
+  Warm warm_fw, warm_adj;
   double* d_partial = nullptr;
   CgState* d_cg = nullptr;
   int* h_done = nullptr;  // pinned
@@ -669,8 +675,10 @@ static void build_device(Ctx& C, const double* coords) {
   C.d_res = dalloc<double>(nl, C.owned);
   C.d_p = dalloc<double>(nl, C.owned);
   C.d_Fp = dalloc<double>(nl, C.owned);
-  C.d_lam_prev = dalloc<double>(nl, C.owned);
-  C.d_lam_prev_adj = dalloc<double>(nl, C.owned);
+  C.warm_fw.cur = dalloc<double>(nl, C.owned);
+  C.warm_fw.old = dalloc<double>(nl, C.owned);
+  C.warm_adj.cur = dalloc<double>(nl, C.owned);
+  C.warm_adj.old = dalloc<double>(nl, C.owned);
   C.d_partial = dalloc<double>(kDotBlocks * kMaxRhs, C.owned);
   C.d_cg = dalloc<CgState>(1, C.owned);
   HIPCHK(hipHostMalloc((void**)&C.h_done, sizeof(int) * 4, hipHostMallocDefault));
@@ -813,7 +821,7 @@ static int factor_impl(Ctx& C) {
     throw DDError{DD_ERR_NOT_SPD, "non-positive pivot in subdomain " + std::to_string(err)};
   }
   C.factored = true;
-  C.have_prev = C.have_prev_adj = false;
+  C.warm_fw.have = C.warm_adj.have = 0;
   return DD_OK;
 }
 
@@ -952,8 +960,7 @@ static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, dou
 // x = A^-1 b (one decomposed solve, unknown-major [nint][nrhs] FP64).
 // Returns DD_OK or DD_ERR_NO_CONVERGENCE; fills iters/relres.
 template <class T>
-static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* lam_prev, bool* have_prev,
-                         int* iters, double* relres) {
+static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, int* iters, double* relres) {
   const int nr = C.nrhs;
   hipStream_t st = C.st;
   void** X = C.X;
@@ -989,8 +996,12 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
                        C.d_partial, (const int*)nullptr);
     hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
     HIPCHK(hipMemcpyAsync(C.d_res, C.d_d, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (warm && *have_prev) {
-      HIPCHK(hipMemcpyAsync(C.d_lam, lam_prev, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (warm && warm->have > 0) {
+      if (C.opt.warm_start == 2 && warm->have >= 2)
+        hipLaunchKernelGGL(k_extrap, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)warm->cur,
+                           (const double*)warm->old, C.d_lam);
+      else
+        HIPCHK(hipMemcpyAsync(C.d_lam, warm->cur, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
       apply_F<T>(C, C.d_lam, C.d_Fp, nullptr);
       hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_d, C.d_Fp, C.d_res);
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
@@ -1052,9 +1063,10 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
       relres[r] = hs.rr0[r] > 0 ? std::sqrt(hs.rr[r] / hs.rr0[r]) : 0.0;
     }
     if (!converged || hs.breakdown) status = DD_ERR_NO_CONVERGENCE;
-    if (lam_prev) {
-      HIPCHK(hipMemcpyAsync(lam_prev, C.d_lam, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
-      *have_prev = true;
+    if (warm) {
+      std::swap(warm->cur, warm->old);
+      HIPCHK(hipMemcpyAsync(warm->cur, C.d_lam, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+      warm->have = std::min(2, warm->have + 1);
     }
     // ---- recovery -------------------------------------------------------------------
     // [t_l; y] = [Linv_GG; Psi_G] B_s^T lambda
@@ -1087,14 +1099,15 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, bool warm, double* 
 
 // A^-1 b with iterative refinement in the mixed form.  b, x: [nint][nrhs].
 template <class T>
-static int solve_refined(Ctx& C, const double* b, double* x, bool warm, double* lam_prev, bool* have_prev,
-                         dd_stats* stats) {
+static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd_stats* stats) {
   const int nr = C.nrhs;
   const int64_t n = C.P.nint * nr;
   hipStream_t st = C.st;
   int iters[kMaxRhs];
   double relres[kMaxRhs];
-  int status = dd_solve_once<T>(C, b, x, warm, lam_prev, have_prev, iters, relres);
+  int status = dd_solve_once<T>(C, b, x, warm, iters, relres);
+  int solve_iters[4] = {0, 0, 0, 0};
+  for (int r = 0; r < nr; ++r) solve_iters[0] = std::max(solve_iters[0], iters[r]);
   int sweeps = 0;
   double gres[kMaxRhs] = {0};
   if (C.fp32 && C.opt.refine_max > 0) {
@@ -1119,9 +1132,12 @@ static int solve_refined(Ctx& C, const double* b, double* x, bool warm, double* 
       }
       int it2[kMaxRhs];
       double rr2[kMaxRhs];
-      int s2 = dd_solve_once<T>(C, C.g_r, C.g_t4, false, nullptr, nullptr, it2, rr2);
+      int s2 = dd_solve_once<T>(C, C.g_r, C.g_t4, nullptr, it2, rr2);
       if (s2 != DD_OK) status = s2;
-      for (int r = 0; r < nr; ++r) iters[r] += it2[r];
+      for (int r = 0; r < nr; ++r) {
+        iters[r] += it2[r];
+        if (sweeps + 1 < 4) solve_iters[sweeps + 1] = std::max(solve_iters[sweeps + 1], it2[r]);
+      }
       hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t4, x);
       ++sweeps;
     }
@@ -1135,6 +1151,7 @@ static int solve_refined(Ctx& C, const double* b, double* x, bool warm, double* 
     }
     stats->refine_sweeps = sweeps;
     stats->dd_solves = 1 + sweeps;
+    for (int k = 0; k < 4; ++k) stats->solve_iters[k] = solve_iters[k];
   }
   return status;
 }
@@ -1154,7 +1171,7 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
                      (const double*)C.g_t1, (const double*)C.g_t2, (const double*)C.g_t3, (const double*)C.g_x,
                      (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_b,
                      (double*)nullptr, nr);
-  int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start != 0, C.d_lam_prev, &C.have_prev, stats);
+  int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start ? &C.warm_fw : nullptr, stats);
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
                      Enext, nr, 0, 1.0);
   HIPCHK(hipGetLastError());
@@ -1168,7 +1185,7 @@ static int solve_api_impl(Ctx& C, const double* b, double* x, dd_stats* stats) {
   hipStream_t st = C.st;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, b, ne, C.g_t1, nr,
                      1.0);
-  int status = solve_refined<T>(C, C.g_t1, C.g_e, false, nullptr, nullptr, stats);
+  int status = solve_refined<T>(C, C.g_t1, C.g_e, nullptr, stats);
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e, x,
                      nr, 0, 1.0);
   HIPCHK(hipGetLastError());
@@ -1185,8 +1202,7 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
   const int64_t n = ni * nr;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, ebar_next, ne, C.g_t1, nr,
                      1.0);
-  int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start != 0, C.d_lam_prev_adj, &C.have_prev_adj,
-                                stats);
+  int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start ? &C.warm_adj : nullptr, stats);
   // B1 g -> g_t2, A g -> g_t3
   hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 2, ni, C.d_rp, C.d_ci, C.d_vals, (const double*)C.g_x,
                      (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,

@@ -1092,6 +1092,12 @@ __global__ void k_cg_p(int64_t n, int nrhs, const CgState* __restrict__ st, cons
   if (st->active[r]) p[i] = res[i] + st->beta[r] * p[i];
 }
 
+__global__ void k_extrap(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                         double* __restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 2.0 * a[i] - b[i];
+}
+
 __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] += a * x[i];

@@ -67,7 +67,7 @@ class DDSolver:
         o.cg_max_iter = int(cg_max_iter)
         o.refine_tol = float(refine_tol)
         o.refine_max = int(refine_max)
-        o.warm_start = int(bool(warm_start))
+        o.warm_start = int(warm_start)
         o.check_every = int(check_every)
         o.use_graph = int(bool(use_graph))
         if stream is None:
@@ -186,4 +186,4 @@ class DDSolver:
         n = self.nrhs
         return dict(cg_iters=list(s.cg_iters[:n]), refine_sweeps=s.refine_sweeps,
                     dd_solves=s.dd_solves, cg_relres=list(s.cg_relres[:n]),
-                    global_relres=list(s.global_relres[:n]))
+                    global_relres=list(s.global_relres[:n]), solve_iters=list(s.solve_iters))
