@@ -98,6 +98,7 @@ struct Ctx {
   hipGraphExec_t cg_graph = nullptr;  // captured block of CG iterations
   int cg_graph_iters = 0;
   bool coarse_lists = false;  // coarse products use the nonzero-tile lists
+  std::vector<uint8_t> full_pattern;  // nonzero-tile flags the full lists were built from
   std::vector<void*> owned;
 
   // sizes
@@ -625,18 +626,13 @@ static void build_device(Ctx& C, const double* coords) {
   {
     // forward passes also produce the corner rows (Psi times the input),
     // transposed passes run over [o, K) so they include Psi^T (corner inputs)
-    std::vector<MvItem> fN, fT, tN, tT, oN, oT;
+    // (the full r-block lists are built from the nonzero tiles after the
+    // first factorisation)
+    std::vector<MvItem> tN, tT, oN, oT;
     for (int s = 0; s < nsub; ++s) {
       const SubDev& q = C.subs_h[s];
       int kr = q.kI + q.kG;
-      for (int o = 0; o < kr; ++o) {
-        fN.push_back({s, o, 0, o + 1, -1, 0});
-        fT.push_back({s, o, o, q.K, -1, 0});
-      }
-      for (int o = kr; o < q.K; ++o) {
-        fN.push_back({s, o, 0, kr, -1, 0});
-        tN.push_back({s, o, q.kI, kr, -1, 0});
-      }
+      for (int o = kr; o < q.K; ++o) tN.push_back({s, o, q.kI, kr, -1, 0});
       for (int o = q.kI; o < kr; ++o) {
         tN.push_back({s, o, q.kI, o + 1, -1, 0});
         tT.push_back({s, o, o, q.K, -1, 0});
@@ -646,8 +642,6 @@ static void build_device(Ctx& C, const double* coords) {
       oN.push_back({nsub, o, 0, o + 1, -1, 0});
       oT.push_back({nsub, o, o, C.Kc, -1, 0});
     }
-    C.full_N = make_items(C, fN);
-    C.full_T = make_items(C, fT);
     C.trail_N = make_items(C, tN);
     C.trail_T = make_items(C, tT);
     C.co_N = make_items(C, oN);
@@ -735,6 +729,46 @@ static void factor_range(Ctx& C, int s0, int cnt) {
   HIPCHK(hipGetLastError());
 }
 
+// nonzero count of every tile in [t0, t0 + n) of the factor store
+template <class T>
+static std::vector<int32_t> tile_nnz(Ctx& C, int64_t t0, int64_t n) {
+  std::vector<int32_t> nnz(n);
+  if (n == 0) return nnz;
+  int32_t* d_nnz = nullptr;
+  HIPCHK(hipMalloc((void**)&d_nnz, n * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)n), dim3(256), 0, C.st, t0, n, (const T*)C.d_tiles, d_nnz);
+  HIPCHK(hipMemcpyAsync(nnz.data(), d_nnz, n * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+  HIPCHK(hipFree(d_nnz));
+  return nnz;
+}
+
+static void release(Ctx& C, void* p) {
+  if (!p) return;
+  auto it = std::find(C.owned.begin(), C.owned.end(), p);
+  if (it != C.owned.end()) C.owned.erase(it);
+  HIPCHK(hipFree(p));
+}
+
+static void release_items(Ctx& C, Items& it) {
+  release(C, it.d);
+  release(C, it.outs);
+  release(C, it.mlist);
+  it = Items{};
+}
+
+// Split lists with short chunks may need more partial slots than were
+// allocated.  The old buffer stays allocated: a captured graph may use it.
+template <class T>
+static void ensure_partial(Ctx& C) {
+  if (C.max_slots <= C.partial_slots) return;
+  void* p = nullptr;
+  HIPCHK(hipMalloc(&p, C.max_slots * kNB * C.nrhs * sizeof(T)));
+  C.owned.push_back(p);
+  C.d_partial_mv = p;
+  C.partial_slots = C.max_slots;
+}
+
 // Replace the coarse work lists by lists of the nonzero tiles of the coarse
 // inverse factor (fixed by the corner order, so built once).
 template <class T>
@@ -742,14 +776,7 @@ static void coarse_tile_lists(Ctx& C) {
   const SubDev& qc = C.subs_h[C.nsub];
   const int K = qc.K;
   const int64_t nt = (int64_t)K * (K + 1) / 2;
-  int32_t* d_nnz = nullptr;
-  HIPCHK(hipMalloc((void**)&d_nnz, nt * sizeof(int32_t)));
-  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)nt), dim3(256), 0, C.st, qc.tile_off, nt, (const T*)C.d_tiles,
-                     d_nnz);
-  std::vector<int32_t> nnz(nt);
-  HIPCHK(hipMemcpyAsync(nnz.data(), d_nnz, nt * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
-  HIPCHK(hipStreamSynchronize(C.st));
-  HIPCHK(hipFree(d_nnz));
+  std::vector<int32_t> nnz = tile_nnz<T>(C, qc.tile_off, nt);
   auto at = [&](int i, int j) { return nnz[(int64_t)i * (i + 1) / 2 + j]; };
   std::vector<int32_t> ln, lt;
   std::vector<MvItem> bn, bt;
@@ -774,13 +801,55 @@ static void coarse_tile_lists(Ctx& C) {
   C.co_T.mlist = upload(lt, C.owned, C.st);
   C.coarse_bytes = entries * (int64_t)sizeof(T);
   C.coarse_lists = true;
-  if (C.max_slots > C.partial_slots) {  // short coarse chunks may need more partial slots
-    void* p = nullptr;
-    HIPCHK(hipMalloc(&p, C.max_slots * kNB * C.nrhs * sizeof(T)));
-    C.owned.push_back(p);
-    C.d_partial_mv = p;
-    C.partial_slots = C.max_slots;
+  ensure_partial<T>(C);
+}
+
+// Lists of the nonzero tiles of the subdomain inverse factors (with the
+// premultiplied corner rows) for the full forward / transposed passes.  The
+// interior nested-dissection order leaves whole tiles of L_II^-1 zero.  The
+// pattern is checked after every factorisation and the lists rebuilt when it
+// changed, so a tile is skipped only while it is exactly zero.
+template <class T>
+static void full_tile_lists(Ctx& C) {
+  const int64_t nt = C.subs_h[C.nsub].tile_off;  // subdomain tiles come first
+  std::vector<int32_t> nnz = tile_nnz<T>(C, 0, nt);
+  std::vector<uint8_t> pat(nt);
+  for (int64_t t = 0; t < nt; ++t) pat[t] = nnz[t] != 0;
+  if (pat == C.full_pattern && C.full_N.d) return;
+  std::vector<int32_t> ln, lt;
+  std::vector<MvItem> bn, bt;
+  int64_t entries = 0;
+  for (int s = 0; s < C.nsub; ++s) {
+    const SubDev& q = C.subs_h[s];
+    const int kr = q.kI + q.kG;
+    auto at = [&](int i, int j) { return nnz[q.tile_off + (int64_t)i * (i + 1) / 2 + j]; };
+    for (int o = 0; o < q.K; ++o) {
+      int32_t b = (int32_t)ln.size();
+      for (int j = 0; j <= std::min(o, kr - 1); ++j)
+        if (at(o, j)) {
+          ln.push_back(j);
+          entries += at(o, j);
+        }
+      bn.push_back({s, o, b, (int32_t)ln.size(), -1, 0});
+      if (o < kr) {
+        b = (int32_t)lt.size();
+        for (int i = o; i < q.K; ++i)
+          if (at(i, o)) lt.push_back(i);
+        bt.push_back({s, o, b, (int32_t)lt.size(), -1, 0});
+      }
+    }
   }
+  if ((int64_t)ln.size() >= INT32_MAX || (int64_t)lt.size() >= INT32_MAX)
+    throw DDError{DD_ERR_OOM, "tile lists exceed 2^31 entries"};
+  release_items(C, C.full_N);
+  release_items(C, C.full_T);
+  C.full_N = make_items(C, bn);
+  C.full_N.mlist = upload(ln, C.owned, C.st);
+  C.full_T = make_items(C, bt);
+  C.full_T.mlist = upload(lt, C.owned, C.st);
+  C.full_bytes = entries * (int64_t)sizeof(T);
+  C.full_pattern.swap(pat);
+  ensure_partial<T>(C);
 }
 
 template <class T>
@@ -812,6 +881,7 @@ static int factor_impl(Ctx& C) {
                        (T*)C.d_tilesT);
   HIPCHK(hipGetLastError());
   if (C.Kc > 0 && !C.coarse_lists) coarse_tile_lists<T>(C);
+  full_tile_lists<T>(C);
   int err = 0;
   HIPCHK(hipMemcpyAsync(&err, C.d_err, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));

@@ -19,37 +19,17 @@ void sort_unique(std::vector<T>& v) {
 }
 }  // namespace
 
-// Fill-reducing order of the corner unknowns (the coarse problem).  The
-// coarse matrix K_cc = sum_s B_c^T K_s B_c couples every pair of corners of
-// one subdomain.  Recursive coordinate bisection of the corner-edge
-// midpoints gives an edge cut of that graph; the cut-side vertices on the
-// lower side form the separator, ordered after both halves (nested
-// dissection).  Only the fill of the coarse factor and of its inverse
-// depends on this order (the solve stores and streams only nonzero tiles).
-static void order_corners(Plan& P, const double* coords) {
-  const int64_t nc = P.ncorner();
-  if (nc == 0) return;
-  std::vector<std::vector<int32_t>> adj(nc);
-  for (int32_t s = 0; s < P.nsub; ++s) {
-    const SubInfo& q = P.subs[s];
-    const auto& L = P.local[s];
-    for (int32_t a = 0; a < q.nC; ++a) {
-      int32_t I = P.dof_corner[L[q.nI + q.nG + a]];
-      for (int32_t b = 0; b < q.nC; ++b)
-        if (a != b) adj[I].push_back(P.dof_corner[L[q.nI + q.nG + b]]);
-    }
-  }
-  for (auto& v : adj) sort_unique(v);
-  std::vector<double> mid(3 * nc);
-  for (int64_t c = 0; c < nc; ++c) {
-    int32_t e = P.interior[P.corner_dof[c]];
-    for (int k = 0; k < 3; ++k)
-      mid[3 * c + k] = 0.5 * (coords[3 * (int64_t)P.edges[2 * e] + k] + coords[3 * (int64_t)P.edges[2 * e + 1] + k]);
-  }
+// Nested dissection of a point set carrying a graph (items 0..n-1 with
+// coordinates mid[3i..3i+2] and adjacency adj[i]): split at the median
+// coordinate of the widest axis; items of the lower side with a neighbour on
+// the upper side form the separator, ordered after both halves.  Pieces of
+// at most `leaf` items keep their incoming order.  Returns order[k] = item
+// placed at position k.
+static std::vector<int32_t> dissect(int32_t n, const std::vector<double>& mid,
+                                    const std::vector<std::vector<int32_t>>& adj, size_t leaf) {
   std::vector<int32_t> order;
-  order.reserve(nc);
-  std::vector<uint8_t> side(nc, 0);
-  const size_t leaf = 64;
+  order.reserve(n);
+  std::vector<uint8_t> side(n, 0);
   // explicit recursion; a frame orders (left interior, right, separator)
   struct Frame {
     std::vector<int32_t> idx;
@@ -57,7 +37,7 @@ static void order_corners(Plan& P, const double* coords) {
     std::vector<int32_t> right, sep;
   };
   std::vector<Frame> st;
-  std::vector<int32_t> all(nc);
+  std::vector<int32_t> all(n);
   std::iota(all.begin(), all.end(), 0);
   st.push_back({all, 0, {}, {}});
   while (!st.empty()) {
@@ -115,11 +95,86 @@ static void order_corners(Plan& P, const double* coords) {
       st.pop_back();
     }
   }
-  // order[k] = old corner id placed at position k
+  return order;
+}
+
+static void edge_midpoint(const Plan& P, const double* coords, int32_t d, double* m) {
+  int32_t e = P.interior[d];
+  for (int k = 0; k < 3; ++k)
+    m[k] = 0.5 * (coords[3 * (int64_t)P.edges[2 * e] + k] + coords[3 * (int64_t)P.edges[2 * e + 1] + k]);
+}
+
+// Fill-reducing order of the corner unknowns (the coarse problem).  The
+// coarse matrix K_cc = sum_s B_c^T K_s B_c couples every pair of corners of
+// one subdomain; nested dissection of that graph by coordinate bisection of
+// the corner-edge midpoints.  Only the fill of the coarse factor and of its
+// inverse depends on this order (the solve stores and streams only nonzero
+// tiles).
+static void order_corners(Plan& P, const double* coords) {
+  const int64_t nc = P.ncorner();
+  if (nc == 0) return;
+  std::vector<std::vector<int32_t>> adj(nc);
+  for (int32_t s = 0; s < P.nsub; ++s) {
+    const SubInfo& q = P.subs[s];
+    const auto& L = P.local[s];
+    for (int32_t a = 0; a < q.nC; ++a) {
+      int32_t I = P.dof_corner[L[q.nI + q.nG + a]];
+      for (int32_t b = 0; b < q.nC; ++b)
+        if (a != b) adj[I].push_back(P.dof_corner[L[q.nI + q.nG + b]]);
+    }
+  }
+  for (auto& v : adj) sort_unique(v);
+  std::vector<double> mid(3 * nc);
+  for (int64_t c = 0; c < nc; ++c) edge_midpoint(P, coords, P.corner_dof[c], &mid[3 * c]);
+  std::vector<int32_t> order = dissect((int32_t)nc, mid, adj, 64);
   std::vector<int32_t> cd(nc);
   for (int64_t k = 0; k < nc; ++k) cd[k] = P.corner_dof[order[k]];
   P.corner_dof = cd;
   for (int64_t k = 0; k < nc; ++k) P.dof_corner[cd[k]] = (int32_t)k;
+}
+
+// Order of each subdomain's interior block.  The interior unknowns are
+// eliminated first (Sec. III-C); their order changes only the fill of
+// L_rr and of the stored inverse L_rr^-1.  Nested dissection of the local
+// coupling graph (two interior unknowns couple when they share a tet of the
+// subdomain) makes whole tiles of L_II^-1 zero: the inverse factor couples
+// an unknown only to its ancestors in the dissection tree, so the two halves
+// of every dissection stay uncoupled.
+static void order_interiors(Plan& P, const double* coords, const int32_t* partition) {
+  std::vector<int64_t> tptr(P.nsub + 1, 0), tlist(P.nt);
+  for (int64_t t = 0; t < P.nt; ++t) tptr[partition[t] + 1]++;
+  for (int32_t s = 0; s < P.nsub; ++s) tptr[s + 1] += tptr[s];
+  {
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t t = 0; t < P.nt; ++t) tlist[fill[partition[t]]++] = t;
+  }
+  std::vector<int32_t> loc(P.nint, -1);
+  for (int32_t s = 0; s < P.nsub; ++s) {
+    const int32_t nI = P.subs[s].nI;
+    if (nI <= 64) continue;
+    auto& L = P.local[s];
+    for (int32_t a = 0; a < nI; ++a) loc[L[a]] = a;
+    std::vector<std::vector<int32_t>> adj(nI);
+    for (int64_t k = tptr[s]; k < tptr[s + 1]; ++k) {
+      const int64_t t = tlist[k];
+      int32_t li[6];
+      for (int e = 0; e < 6; ++e) {
+        int32_t d = P.dof[P.tet_edges[t * 6 + e]];
+        li[e] = d >= 0 ? loc[d] : -1;
+      }
+      for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b)
+          if (a != b && li[a] >= 0 && li[b] >= 0) adj[li[a]].push_back(li[b]);
+    }
+    for (auto& v : adj) sort_unique(v);
+    std::vector<double> mid(3 * (size_t)nI);
+    for (int32_t a = 0; a < nI; ++a) edge_midpoint(P, coords, L[a], &mid[3 * a]);
+    std::vector<int32_t> order = dissect(nI, mid, adj, 64);
+    std::vector<int32_t> seg(nI);
+    for (int32_t k = 0; k < nI; ++k) seg[k] = L[order[k]];
+    for (int32_t a = 0; a < nI; ++a) loc[L[a]] = -1;
+    std::copy(seg.begin(), seg.end(), L.begin());
+  }
 }
 
 int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets,
@@ -343,6 +398,7 @@ int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets
       P.corner_dof.push_back((int32_t)d);
     }
   order_corners(P, coords);
+  order_interiors(P, coords, partition);
   return DD_OK;
 }
 

@@ -6,7 +6,9 @@
 // signed Boolean map B_r, +1 in the lower subdomain id and -1 in the higher)
 // and those shared by three or more (corners, c; kept primal and gathered
 // by the unsigned map B_c).  Each subdomain orders its unknowns
-// [I | Gamma | c], each class in ascending canonical edge id.
+// [I | Gamma | c]: Gamma and c in ascending canonical edge id, I in a
+// nested-dissection order of the local coupling graph (fill of the stored
+// inverse factor only).
 #pragma once
 
 #include <cstdint>
