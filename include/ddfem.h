@@ -85,8 +85,13 @@ typedef struct {
   int32_t n_sub, n_lambda, n_corner, nrhs, precision, tile;
   int64_t factor_bytes;    /* device bytes of all stored factors */
   int64_t trailing_bytes;  /* bytes of the interface blocks of the inverse factors
-                              (read twice per CG iteration), unpadded */
-  int64_t coupling_bytes;  /* bytes of the corner-interface coupling blocks, unpadded */
+                              with the corner rows Psi_Gamma (pre-solve and
+                              recovery), unpadded */
+  int64_t schur_bytes;     /* bytes of the interface blocks of the local inverses,
+                              M = (K_rr^-1)_GammaGamma stored square (read once
+                              per CG iteration), unpadded */
+  int64_t corner_bytes;    /* bytes of the corner rows Psi_Gamma (read twice per
+                              CG iteration), unpadded */
   int64_t coarse_bytes;    /* bytes of the coarse inverse factor, unpadded */
   int64_t full_bytes;      /* bytes of the full r-block inverse factors, unpadded */
 } dd_info;
@@ -172,11 +177,12 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out);
  * recorded on the context's stream around each launch (adds two event
  * records per launch while enabled).  Classes: */
 enum {
-  DD_PROF_TRAILING = 0, /* interface-block inverse-factor products (CG loop, twice per iteration) */
+  DD_PROF_TRAILING = 0, /* interface-block inverse-factor products (pre-solve, recovery) */
   DD_PROF_FULL = 1,     /* full r-block inverse-factor products (pre-solve, recovery) */
-  DD_PROF_COUPLING = 2, /* corner-coupling blocks L_cr / L_cGamma */
+  DD_PROF_SCHUR = 2,    /* interface blocks of the local inverses, M u (once per CG iteration) */
   DD_PROF_COARSE = 3,   /* coarse corner inverse factor */
-  DD_PROF_CLASSES = 4
+  DD_PROF_CORNER = 4,   /* corner rows Psi_Gamma u and Psi_Gamma^T z (twice per CG iteration) */
+  DD_PROF_CLASSES = 5
 };
 /* Returns the accumulated milliseconds and launch counts per class (host
  * arrays [DD_PROF_CLASSES], either may be NULL) since the last reset, then

@@ -47,6 +47,8 @@ struct DDError {
   } while (0)
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+// grid of a kernel that maps workgroups to XCD-contiguous ranges (multiple of 8)
+static inline unsigned nblk8(int64_t n) { return (nblk(n) + 7u) / 8u * 8u; }
 
 template <class V>
 static V* upload(const std::vector<V>& h, std::vector<void*>& owned, hipStream_t st) {
@@ -81,6 +83,7 @@ struct Items {
   int64_t n_out = 0;
   int64_t n_slots = 0;   // partial slots used (0 = direct writes)
   int32_t* mlist = nullptr;  // tile list (ranges index it), or null for contiguous ranges
+  void* partial = nullptr;   // own partial slots (lists that run beside others), or null
 };
 
 constexpr int kChunkTiles = 32;  // longest tile range of one wave
@@ -91,6 +94,10 @@ struct Ctx {
   Plan P;
   dd_options opt;
   hipStream_t st = nullptr;
+  // side stream: the interface-row products of an F application run there
+  // while the coarse solve (a short chain of small launches) runs on st
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   double dt = 0, beta = 0;
   int nrhs = 1;
   bool fp32 = false;
@@ -114,6 +121,9 @@ struct Ctx {
   SubDev* d_subs = nullptr;
   void* d_tiles = nullptr;   // factor store; operand-order tiles after dd_factor
   void* d_tilesT = nullptr;  // operand-order transposed tiles
+  void* d_msq = nullptr;     // interface blocks of the local inverses, square, operand order
+  int64_t* d_sq_off = nullptr;  // first tile of each subdomain's square block
+  int64_t sq_tiles = 0;
   void* d_partial_mv = nullptr;
   int64_t max_slots = 0;        // largest slot count of any work list
   int64_t partial_slots = 0;    // slots d_partial_mv holds
@@ -154,7 +164,9 @@ struct Ctx {
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
   // trail_*: interface block with Psi_Gamma; co_*: coarse inverse factor
-  Items full_N, full_T, trail_N, trail_T, co_N, co_T;
+  // schur: M u on the interface rows (square store); corner_N / corner_T:
+  // Psi_Gamma u on the corner rows / Psi_Gamma^T z onto the interface rows
+  Items full_N, full_T, trail_N, trail_T, co_N, co_T, schur, corner_N, corner_T;
   // work vectors
   void* X[9] = {};
   int64_t nlam = 0;
@@ -175,7 +187,8 @@ struct Ctx {
   double *g_b = nullptr, *g_e = nullptr, *g_r = nullptr, *g_x = nullptr, *g_t1 = nullptr, *g_t2 = nullptr,
          *g_t3 = nullptr, *g_t4 = nullptr;
 
-  int64_t factor_bytes = 0, trailing_bytes = 0, coupling_bytes = 0, coarse_bytes = 0, full_bytes = 0;
+  int64_t factor_bytes = 0, trailing_bytes = 0, schur_bytes = 0, corner_bytes = 0, coarse_bytes = 0,
+          full_bytes = 0;
 
   // optional per-class kernel timing with HIP events on the solve stream
   bool prof = false;
@@ -187,7 +200,11 @@ struct Ctx {
 
   ~Ctx() {
     if (st) (void)hipStreamSynchronize(st);
+    if (st2) (void)hipStreamSynchronize(st2);
     if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (st2) (void)hipStreamDestroy(st2);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : owned) (void)hipFree(p);
     if (h_done) (void)hipHostFree(h_done);
@@ -333,15 +350,30 @@ static void build_device(Ctx& C, const double* coords) {
     HIPCHK(e);
     C.owned.push_back(p);
     C.d_tilesT = p;
+    std::vector<int64_t> so(nsub);
+    int64_t acc = 0;
+    for (int s = 0; s < nsub; ++s) {
+      so[s] = acc;
+      acc += (int64_t)C.subs_h[s].kG * C.subs_h[s].kG;
+    }
+    C.sq_tiles = acc;
+    C.d_sq_off = upload(so, C.owned, st);
+    p = nullptr;
+    e = hipMalloc(&p, std::max<int64_t>(1, C.sq_tiles) * kTile * wsz);
+    if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation of the interface inverse failed"};
+    HIPCHK(e);
+    C.owned.push_back(p);
+    C.d_msq = p;
   }
   // algorithmic byte counts (unpadded, packed triangles)
-  C.factor_bytes = 2 * C.ntiles * kTile * (int64_t)wsz;
+  C.factor_bytes = (2 * C.ntiles + C.sq_tiles) * kTile * (int64_t)wsz;
   for (int s = 0; s < nsub; ++s) {
     const SubInfo& q = P.subs[s];
     int64_t nr = q.nI + q.nG;
     // inverse-factor triangle plus the premultiplied corner rows it carries
     C.trailing_bytes += ((int64_t)q.nG * (q.nG + 1) / 2 + (int64_t)q.nC * q.nG) * wsz;
-    C.coupling_bytes += (int64_t)q.nC * q.nG * wsz;
+    C.schur_bytes += (int64_t)q.nG * q.nG * wsz;
+    C.corner_bytes += (int64_t)q.nC * q.nG * wsz;
     C.full_bytes += (nr * (nr + 1) / 2 + (int64_t)q.nC * nr) * wsz;
   }
   C.coarse_bytes = nc * (nc + 1) / 2 * (int64_t)wsz;
@@ -628,14 +660,19 @@ static void build_device(Ctx& C, const double* coords) {
     // transposed passes run over [o, K) so they include Psi^T (corner inputs)
     // (the full r-block lists are built from the nonzero tiles after the
     // first factorisation)
-    std::vector<MvItem> tN, tT, oN, oT;
+    std::vector<MvItem> tN, tT, oN, oT, sq, cN, cT;
     for (int s = 0; s < nsub; ++s) {
       const SubDev& q = C.subs_h[s];
       int kr = q.kI + q.kG;
-      for (int o = kr; o < q.K; ++o) tN.push_back({s, o, q.kI, kr, -1, 0});
+      for (int o = kr; o < q.K; ++o) {
+        tN.push_back({s, o, q.kI, kr, -1, 0});
+        cN.push_back({s, o, q.kI, kr, -1, 0});
+      }
       for (int o = q.kI; o < kr; ++o) {
         tN.push_back({s, o, q.kI, o + 1, -1, 0});
         tT.push_back({s, o, o, q.K, -1, 0});
+        sq.push_back({s, o, q.kI, kr, -1, 0});
+        if (q.kC > 0) cT.push_back({s, o, kr, q.K, -1, 0});
       }
     }
     for (int o = 0; o < C.Kc; ++o) {
@@ -644,6 +681,15 @@ static void build_device(Ctx& C, const double* coords) {
     }
     C.trail_N = make_items(C, tN);
     C.trail_T = make_items(C, tT);
+    C.corner_N = make_items(C, cN);
+    C.corner_T = make_items(C, cT);
+    C.schur = make_items(C, sq);
+    if (C.schur.n_slots > 0) {  // runs beside the coarse chain: own partial slots
+      void* q = nullptr;
+      HIPCHK(hipMalloc(&q, C.schur.n_slots * kTile * C.nrhs * wsz / NB));
+      C.owned.push_back(q);
+      C.schur.partial = q;
+    }
     C.co_N = make_items(C, oN);
     C.co_T = make_items(C, oT);
     void* p = nullptr;
@@ -870,6 +916,13 @@ static int factor_impl(Ctx& C) {
                      C.d_Se, C.d_eps, C.d_vals);
   HIPCHK(hipGetLastError());
   factor_range<T>(C, 0, C.nsub);
+  {
+    int max_kg = 0;
+    for (int s = 0; s < C.nsub; ++s) max_kg = std::max(max_kg, C.subs_h[s].kG);
+    if (max_kg > 0)
+      hipLaunchKernelGGL(k_schur_inv<T>, dim3((unsigned)(max_kg * (max_kg + 1) / 2), C.nsub), dim3(256), 0, st, 0,
+                         (const T*)tiles, C.d_subs, C.d_sq_off, (T*)C.d_msq);
+  }
   if (C.Kc > 0) {
     if (C.n_cent)
       hipLaunchKernelGGL(k_pull_coarse<T>, dim3(nblk(C.n_cent)), dim3(256), 0, st, C.n_cent, C.d_cptr,
@@ -928,58 +981,77 @@ static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
 
 static int item_class(const Ctx& C, const Items& it) {
   if (&it == &C.trail_N || &it == &C.trail_T) return DD_PROF_TRAILING;
+  if (&it == &C.schur) return DD_PROF_SCHUR;
+  if (&it == &C.corner_N || &it == &C.corner_T) return DD_PROF_CORNER;
   if (&it == &C.full_N || &it == &C.full_T) return DD_PROF_FULL;
   return DD_PROF_COARSE;
 }
 
 template <class T, int NV, int NB16, int CLS>
-static void mv_launch(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
-                      const void* add_c, T alpha_c, const int* skip) {
+static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const void* in, void* out, const void* add,
+                      T alpha, const void* add_c, T alpha_c, const int* skip) {
   const bool split = it.n_out > 0;
-  const T* tiles = (const T*)(trans ? C.d_tilesT : C.d_tiles);
-  hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, C.st, it.n, it.d,
+  const T* tiles = (const T*)(CLS == DD_PROF_SCHUR ? C.d_msq : (trans ? C.d_tilesT : C.d_tiles));
+  T* partial = (T*)(it.partial ? it.partial : C.d_partial_mv);
+  hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, s, it.n, it.d,
                      C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
-                     (int)trans, (T*)C.d_partial_mv, (const int32_t*)it.mlist, skip);
+                     (int)trans, partial, (const int32_t*)it.mlist, skip, (const int64_t*)C.d_sq_off);
   if (split)
-    hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, C.st, it.n_out, it.outs, C.d_subs,
-                       (const T*)C.d_partial_mv, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
-                       skip);
+    hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, s, it.n_out, it.outs, C.d_subs,
+                       (const T*)partial, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs, skip);
 }
 
 template <class T, int CLS>
-static void mv_dispatch(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
-                        const void* add_c, T alpha_c, const int* skip) {
+static void mv_dispatch(Ctx& C, hipStream_t s, const Items& it, bool trans, const void* in, void* out,
+                        const void* add, T alpha, const void* add_c, T alpha_c, const int* skip) {
   const int nr = C.nrhs;
   if (nr == 1)
-    mv_launch<T, 1, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 1, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr == 2)
-    mv_launch<T, 2, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 2, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 4)
-    mv_launch<T, 4, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 4, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 8)
-    mv_launch<T, 8, 0, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 8, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 16)
-    mv_launch<T, 0, 1, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 0, 1, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
-    mv_launch<T, 0, 2, CLS>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 0, 2, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
 }
 
 // out = add + alpha * (product) on r-row output blocks, add_c + alpha_c *
-// (product) on corner-row output blocks (forward passes only)
+// (product) on corner-row output blocks (forward passes only); side: launch
+// on the side stream (not used while per-class timing is on)
 template <class T>
 static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, const void* add, T alpha,
-               const int* skip = nullptr, const void* add_c = nullptr, T alpha_c = (T)1) {
+               const int* skip = nullptr, const void* add_c = nullptr, T alpha_c = (T)1, bool side = false) {
   if (it.n == 0) return;
   hipEvent_t e0, e1;
   bool timed = prof_begin(C, item_class(C, it), &e0, &e1);
+  hipStream_t s = side ? C.st2 : C.st;
   const int cls = item_class(C, it);
   if (cls == DD_PROF_TRAILING)
-    mv_dispatch<T, DD_PROF_TRAILING>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_dispatch<T, DD_PROF_TRAILING>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_FULL)
-    mv_dispatch<T, DD_PROF_FULL>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_dispatch<T, DD_PROF_FULL>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+  else if (cls == DD_PROF_SCHUR)
+    mv_dispatch<T, DD_PROF_SCHUR>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+  else if (cls == DD_PROF_CORNER)
+    mv_dispatch<T, DD_PROF_CORNER>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
-    mv_dispatch<T, DD_PROF_COARSE>(C, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_dispatch<T, DD_PROF_COARSE>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   if (timed) HIPCHK(hipEventRecord(e1, C.st));
+}
+
+// fork: work queued on st so far is visible to the side stream; join: the
+// side stream's work is visible to everything queued on st afterwards
+static void fork_side(Ctx& C) {
+  HIPCHK(hipEventRecord(C.ev_fork, C.st));
+  HIPCHK(hipStreamWaitEvent(C.st2, C.ev_fork, 0));
+}
+static void join_side(Ctx& C) {
+  HIPCHK(hipEventRecord(C.ev_join, C.st2));
+  HIPCHK(hipStreamWaitEvent(C.st, C.ev_join, 0));
 }
 
 // coarse: y rows of Xin (coarse block) -> Xout coarse rows = K_cc^-1 y via
@@ -991,8 +1063,10 @@ static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* s
 }
 
 // F p -> Fp (uses X5..X8):
-//   v = B_s^T p;  [t; y] = [Linv_GG; Psi_G] v;  z = K_cc^-1 sum B_c^T y;
-//   u = [Linv_GG; Psi_G]^T [t; z];  F p = sum B_s u
+//   v = B_s^T p;  y = Psi_G v (corner rows);  z = K_cc^-1 sum B_c^T y;
+//   u = M v + Psi_G^T z with M = Linv_GG^T Linv_GG;  F p = sum B_s u
+// M v needs only v: it runs on the side stream while the coarse chain runs
+// on st (disjoint rows of X5 / X6 / X8, own partial slots).
 template <class T>
 static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false) {
   const int nr = C.nrhs;
@@ -1000,7 +1074,10 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
   void **X = C.X;
   hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                      C.d_glam, p, (T*)X[5], nr, skip);
-  mv<T>(C, C.trail_N, false, X[5], X[6], nullptr, (T)1, skip);
+  const bool overlap = C.Kc > 0 && !C.prof;
+  if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, (T)1, skip);
+  if (overlap) fork_side(C);
+  mv<T>(C, C.schur, false, X[5], X[8], nullptr, (T)1, skip, nullptr, (T)1, overlap);
   if (C.Kc > 0) {
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
@@ -1009,7 +1086,8 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
                        C.d_csccrow, (const T*)X[5], (T*)X[6], (T)1, nr, skip);
   }
-  mv<T>(C, C.trail_T, true, X[6], X[8], nullptr, (T)1, skip);
+  if (overlap) join_side(C);
+  if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[8], X[8], (T)1, skip);
   hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
                      (const T*)X[8], Fp, dot ? p : (const double*)nullptr, nr, C.d_partial, skip);
 }
@@ -1184,7 +1262,7 @@ static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd
     double bn[kMaxRhs];
     dot_to_host(C, b, b, C.P.nint, bn);
     for (;;) {
-      hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 1, (int64_t)C.P.nint, C.d_rp, C.d_ci, C.d_vals,
+      hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 1, (int64_t)C.P.nint, C.d_rp, C.d_ci, C.d_vals,
                          (const double*)x, (const double*)nullptr, (const double*)nullptr,
                          (const double*)nullptr, b, C.dt, C.beta * C.dt * C.dt,
                          (2 * C.beta - 1) * C.dt * C.dt, C.g_r, (double*)nullptr, nr);
@@ -1237,7 +1315,7 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, Enm1, ne, C.g_t2, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J0, ne, C.g_x, nr, 1.0);
-  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 0, ni, C.d_rp, C.d_ci, C.d_vals,
+  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 0, ni, C.d_rp, C.d_ci, C.d_vals,
                      (const double*)C.g_t1, (const double*)C.g_t2, (const double*)C.g_t3, (const double*)C.g_x,
                      (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_b,
                      (double*)nullptr, nr);
@@ -1274,7 +1352,7 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
                      1.0);
   int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start ? &C.warm_adj : nullptr, stats);
   // B1 g -> g_t2, A g -> g_t3
-  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 2, ni, C.d_rp, C.d_ci, C.d_vals, (const double*)C.g_x,
+  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 2, ni, C.d_rp, C.d_ci, C.d_vals, (const double*)C.g_x,
                      (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                      (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_t2,
                      C.g_t3, nr);
@@ -1379,6 +1457,9 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
   C = new Ctx();
   C->opt = o;
   C->st = (hipStream_t)o.stream;
+  HIPCHK(hipStreamCreateWithFlags(&C->st2, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
   C->dt = dt;
   C->beta = beta;
   C->nrhs = o.nrhs;
@@ -1431,7 +1512,8 @@ int dd_get_info(void* ctx, dd_info* info) {
   info->tile = NB;
   info->factor_bytes = C.factor_bytes;
   info->trailing_bytes = C.trailing_bytes;
-  info->coupling_bytes = C.coupling_bytes;
+  info->schur_bytes = C.schur_bytes;
+  info->corner_bytes = C.corner_bytes;
   info->coarse_bytes = C.coarse_bytes;
   info->full_bytes = C.full_bytes;
   return DD_OK;
@@ -1561,7 +1643,7 @@ int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res) 
   const int64_t ni = C.P.nint, ne = C.P.ne, nv = C.P.nv;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, C.st, ni, C.d_interior, E, ne, C.g_t1, nr,
                      1.0);
-  hipLaunchKernelGGL(k_csr, dim3(nblk(ni * nr)), dim3(256), 0, C.st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+  hipLaunchKernelGGL(k_csr, dim3(nblk8(ni * nr)), dim3(256), 0, C.st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
                      (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                      (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t2, C.g_t3, nr);
   double* d_res = C.d_vres;
@@ -1601,12 +1683,12 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr, 0.5);
   hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t3, C.g_t2);
   // T dv -> g_t3 (S dv unused -> g_t4); then S av -> g_x (T av -> g_t4)
-  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
                      (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                      (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t3, C.g_t4, nr);
   double a[kMaxRhs], b[kMaxRhs];
   dot_to_host(C, C.g_t1, C.g_t3, ni, a);
-  hipLaunchKernelGGL(k_csr, dim3(nblk(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
                      (const double*)C.g_t2, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                      (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t4, C.g_x, nr);
   dot_to_host(C, C.g_t2, C.g_x, ni, b);

@@ -479,15 +479,19 @@ __device__ __forceinline__ void load_chunk8(const T* __restrict__ blk, int l, T*
 }
 
 // NV > 0: vector path for nrhs <= NV; NV == 0: MFMA path with NB16 RHS blocks.
-// CLS only names the product class in kernel traces (0 interface blocks,
-// 1 full r-blocks, 2 corner coupling, 3 coarse).
+// CLS names the product class in kernel traces (0 interface blocks of the
+// inverse factors, 1 full r-blocks, 2 interface blocks of the local inverses,
+// 3 coarse, 4 corner rows).  Class 2 reads a square store: subdomain s holds
+// its kG x kG interface tiles row by row from tile sq_off[s], and the items
+// range over interface tile indices [kI, kI + kG).
 template <class T, int NV, int NB16, int CLS>
 __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* __restrict__ items,
                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
-                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
+                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip,
+                                                 const int64_t* __restrict__ sq_off) {
   if (skip && *skip) return;
   const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wi >= n_items) return;
@@ -516,6 +520,8 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
   constexpr int NX = PX ? 8 * (MF ? NB16 : NV) : 1;
   T cur[16], nxt[16], xc[NX], xn[NX];
   auto tile_ptr = [&](int m) -> const T* {
+    if constexpr (CLS == 2)
+      return tiles + (sq_off[w.s] + (int64_t)(w.o - q.kI) * q.kG + (m - q.kI)) * kTile;
     const int ti = trans ? m : w.o, tj = trans ? w.o : m;
     return tiles + tile_index(q, ti, tj) * kTile;
   };
@@ -688,6 +694,52 @@ __global__ void __launch_bounds__(256) k_tile_nnz(int64_t t0, int64_t n, const T
   atomicAdd(&cnt, c);
   __syncthreads();
   if (threadIdx.x == 0) nnz[t] = cnt;
+}
+
+// Interface block of the local inverse K_rr^-1 = Linv_rr^T Linv_rr (the
+// local inverses stored for the substitutions, Sec. III-C).  Linv_rr is lower
+// triangular with Gamma ordered last in r, so the block is
+// M = Linv_GG^T Linv_GG and the CG loop applies it in one product.  One
+// workgroup per tile (o, m), o >= m (interface tile indices):
+//     M_om = sum_{k >= o} Linv_ko^T Linv_km,
+// written in operand order to tile (o, m) and, transposed, to (m, o) of the
+// subdomain's square block.  Reads the row-major factor store.
+template <class T>
+__global__ void __launch_bounds__(256) k_schur_inv(int s0, const T* __restrict__ tiles,
+                                                   const SubDev* __restrict__ subs,
+                                                   const int64_t* __restrict__ sq_off, T* __restrict__ msq) {
+  const int sidx = s0 + blockIdx.y;
+  const SubDev q = subs[sidx];
+  const int p = blockIdx.x;  // p = o (o + 1) / 2 + m
+  int o = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+  while ((o + 1) * (o + 2) / 2 <= p) ++o;
+  while (o * (o + 1) / 2 > p) --o;
+  const int m = p - o * (o + 1) / 2;
+  if (o >= q.kG) return;
+  __shared__ T A[kNB][kNB + 1];
+  __shared__ T B[kNB][kNB + 1];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
+  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+  for (int k = o; k < q.kG; ++k) {
+    const T* ap = tiles + tile_index(q, q.kI + k, q.kI + o) * kTile;  // Linv_ko
+    const T* bp = tiles + tile_index(q, q.kI + k, q.kI + m) * kTile;  // Linv_km
+    __syncthreads();
+    for (int e = tid; e < kTile; e += 256) {
+      A[e % kNB][e / kNB] = ap[e];  // Linv_ko^T
+      B[e / kNB][e % kNB] = bp[e];
+    }
+    __syncthreads();
+    tile_mma<T, false>(A, B, mb, nb, l, acc);
+  }
+  T* d = msq + (sq_off[sidx] + (int64_t)o * q.kG + m) * kTile;
+  T* dT = msq + (sq_off[sidx] + (int64_t)m * q.kG + o) * kTile;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = mb * 16 + Mfma<T>::row(l, v), c = nb * 16 + (l & 15);
+    d[swz<T>(r, c)] = acc[v];
+    if (o != m) dT[swz<T>(c, r)] = acc[v];
+  }
 }
 
 // Reorder every tile of a store from row-major into operand order, and
@@ -869,26 +921,55 @@ __global__ void __launch_bounds__(256) k_int_to_edges(int64_t ne, const int32_t*
 //   mode 3: y = T x1,  y2 = S x1                  (Gauss law, energy)
 // One thread per (row, rhs); vectors [nint][nrhs].
 // --------------------------------------------------------------------------
-__global__ void k_csr(int mode, int64_t nint, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                      const double2* __restrict__ v, const double* __restrict__ x1, const double* __restrict__ x2,
-                      const double* __restrict__ j1, const double* __restrict__ j2, const double* __restrict__ z,
-                      double dt, double ca, double cb, double* __restrict__ y, double* __restrict__ y2,
-                      int nrhs) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Rows are handed to XCDs in contiguous ranges (workgroup b runs on XCD
+// b % 8): the column gathers of neighbouring rows then hit the same L2.
+// The grid is a multiple of 8 workgroups.
+__device__ __forceinline__ int64_t xcd_contiguous_block() {
+  const int64_t per = gridDim.x / 8;
+  return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+__global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64_t* __restrict__ rp,
+                                             const int32_t* __restrict__ ci, const double2* __restrict__ v,
+                                             const double* __restrict__ x1, const double* __restrict__ x2,
+                                             const double* __restrict__ j1, const double* __restrict__ j2,
+                                             const double* __restrict__ z, double dt, double ca, double cb,
+                                             double* __restrict__ y, double* __restrict__ y2, int nrhs) {
+  const int64_t i = xcd_contiguous_block() * blockDim.x + threadIdx.x;
   if (i >= nint * nrhs) return;
-  int64_t row = i / nrhs;
-  int r = (int)(i % nrhs);
+  const int64_t row = i / nrhs;
+  const int r = (int)(i % nrhs);
   double t1 = 0.0, s1 = 0.0, t2 = 0.0, s2 = 0.0;
-  for (int64_t k = rp[row]; k < rp[row + 1]; ++k) {
-    double2 av = v[k];
-    int64_t c = (int64_t)ci[k] * nrhs + r;
-    double a = x1[c];
-    t1 += av.x * a;
-    s1 += av.y * a;
-    if (mode == 0) {
-      double b = x2[c];
-      t2 += av.x * b;
-      s2 += av.y * b;
+  const int64_t k0 = rp[row], k1 = rp[row + 1];
+  // nonzeros in batches of 8: all index and value loads of a batch are
+  // issued before the gathers (memory-level parallelism); the products are
+  // summed in ascending nonzero order
+  constexpr int B = 8;
+  for (int64_t kb = k0; kb < k1; kb += B) {
+    int32_t c[B];
+    double2 av[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const bool ok = kb + u < k1;
+      c[u] = ok ? ci[kb + u] : -1;
+      av[u] = ok ? v[kb + u] : make_double2(0.0, 0.0);
+    }
+    double a[B], b[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int64_t o = (int64_t)c[u] * nrhs + r;
+      a[u] = c[u] >= 0 ? x1[o] : 0.0;
+      b[u] = (mode == 0 && c[u] >= 0) ? x2[o] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (c[u] < 0) break;
+      t1 += av[u].x * a[u];
+      s1 += av[u].y * a[u];
+      if (mode == 0) {
+        t2 += av[u].x * b[u];
+        s2 += av[u].y * b[u];
+      }
     }
   }
   if (mode == 0) {

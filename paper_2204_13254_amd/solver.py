@@ -170,13 +170,13 @@ class DDSolver:
         check(self.lib.dd_energy(self.h, _dev(E_next), _dev(E_n), out.ctypes.data_as(C.c_void_p)))
         return out
 
-    PROF_CLASSES = ("trailing", "full", "coupling", "coarse")
+    PROF_CLASSES = ("trailing", "full", "schur", "coarse", "corner")
 
     def profile(self, enable=-1):
         """Per-class (ms, launches) of the tile products since the last reset;
         enable=1/0 turns event timing on/off and resets."""
-        ms = np.zeros(4)
-        n = np.zeros(4, dtype=np.int64)
+        ms = np.zeros(len(self.PROF_CLASSES))
+        n = np.zeros(len(self.PROF_CLASSES), dtype=np.int64)
         check(self.lib.dd_profile(self.h, int(enable), ms.ctypes.data_as(C.c_void_p),
                                   n.ctypes.data_as(C.c_void_p)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
