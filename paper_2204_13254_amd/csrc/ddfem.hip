@@ -2,16 +2,18 @@
 //
 // Per-step data flow of the decomposed solve (Sec. III-A, eq. (f1schur);
 // local factors L_rr of [I | Gamma] with the corner rows L_cr and local
-// corner Schur complements K_s; stored inverses Linv = L^-1, Sec. III-C):
+// corner Schur complements K_s).  Stored inverses (Sec. III-C):
+// Linv = L_rr^-1, Psi = L_cr Linv (kept in the corner tile rows), and the
+// interface block of the local inverse M = (K_rr^-1)_GG = Linv_GG^T Linv_GG.
 //   pre-solve : w = owner split of b;  t = Linv_rr w_r;
-//               f_c = sum_s B_c^T (w_c - L_cr t);  z0 = K_cc^-1 f_c;
-//               d = sum_s B_s Linv_GG^T (t_G - L_cG^T z0_s)
+//               f_c = sum_s B_c^T (w_c - Psi_r w_r);  z0 = K_cc^-1 f_c;
+//               d = sum_s B_s (Linv_GG^T t_G - Psi_G^T z0_s)
 //   CG on F lambda = d with
-//               F p = sum_s B_s Linv_GG^T (v + L_cG^T z_s),
-//               v = Linv_GG B_s^T p,  z = K_cc^-1 sum_s B_c^T L_cG v
-//   recovery  : t_l = Linv_GG B_s^T lambda;
-//               x_c = K_cc^-1 (f_c + sum_s B_c^T L_cG t_l);
-//               x_r = Linv_rr^T (t - [0; t_l] - L_cr^T x_c);
+//               F p = sum_s B_s (M v + Psi_G^T z_s),  v = B_s^T p,
+//               z = K_cc^-1 sum_s B_c^T Psi_G v
+//   recovery  : v_l = B_s^T lambda;  t_l = Linv_GG v_l;
+//               x_c = K_cc^-1 (f_c + sum_s B_c^T Psi_G v_l);
+//               x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c;
 //               e = owner's copy.
 #include <hip/hip_runtime.h>
 
@@ -121,9 +123,9 @@ struct Ctx {
   SubDev* d_subs = nullptr;
   void* d_tiles = nullptr;   // factor store; operand-order tiles after dd_factor
   void* d_tilesT = nullptr;  // operand-order transposed tiles
-  void* d_msq = nullptr;     // interface blocks of the local inverses, square, operand order
-  int64_t* d_sq_off = nullptr;  // first tile of each subdomain's square block
-  int64_t sq_tiles = 0;
+  void* d_mtri = nullptr;    // interface blocks of the local inverses, packed lower, operand order
+  int64_t* d_m_off = nullptr;   // first tile of each subdomain's block
+  int64_t m_tiles = 0;
   void* d_partial_mv = nullptr;
   int64_t max_slots = 0;        // largest slot count of any work list
   int64_t partial_slots = 0;    // slots d_partial_mv holds
@@ -164,9 +166,17 @@ struct Ctx {
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
   // trail_*: interface block with Psi_Gamma; co_*: coarse inverse factor
-  // schur: M u on the interface rows (square store); corner_N / corner_T:
-  // Psi_Gamma u on the corner rows / Psi_Gamma^T z onto the interface rows
-  Items full_N, full_T, trail_N, trail_T, co_N, co_T, schur, corner_N, corner_T;
+  // corner_N / corner_T: Psi_Gamma u on the corner rows / Psi_Gamma^T z
+  // onto the interface rows
+  Items full_N, full_T, trail_N, trail_T, co_N, co_T, corner_N, corner_T;
+  // symmetric product M u (panel pairs, partial slots, fixed-order reduce)
+  struct SymList {
+    SymItem* d = nullptr;
+    int64_t n = 0;
+    MvOut* outs = nullptr;
+    int64_t n_out = 0;
+    void* partial = nullptr;
+  } sym;
   // work vectors
   void* X[9] = {};
   int64_t nlam = 0;
@@ -230,6 +240,47 @@ struct Ctx {
 constexpr int kXcds = 8;
 constexpr int kWavesPerGroup = 4;
 
+template <class It, class SubF, class LenF>
+static std::vector<It> place_xcd(int nsub, const std::vector<It>& v, const It& pad, SubF sub, LenF len) {
+  // XCD assignment: subdomains by greedy load; the coarse block (a single
+  // "subdomain" holding many items, with small shared inputs) round-robin
+  std::vector<int64_t> load_s(nsub + 1, 0);
+  for (const It& it : v) load_s[sub(it)] += len(it) + 1;
+  std::vector<int32_t> order(nsub);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load_s[a] > load_s[b]; });
+  std::vector<int> xcd_of(nsub + 1, 0);
+  int64_t xload[kXcds] = {0};
+  for (int s : order) {
+    int best = 0;
+    for (int x = 1; x < kXcds; ++x)
+      if (xload[x] < xload[best]) best = x;
+    xcd_of[s] = best;
+    xload[best] += load_s[s];
+  }
+  std::vector<std::vector<It>> lists(kXcds);
+  int rr = 0;
+  for (const It& it : v) {
+    int x = sub(it) < nsub ? xcd_of[sub(it)] : (rr++ % kXcds);
+    lists[x].push_back(it);
+  }
+  size_t groups = 0;
+  // within an XCD: longest first
+  for (auto& L : lists) {
+    std::stable_sort(L.begin(), L.end(), [&](const It& a, const It& b) { return len(a) > len(b); });
+    groups = std::max(groups, (L.size() + kWavesPerGroup - 1) / kWavesPerGroup);
+  }
+  std::vector<It> placed(groups * kXcds * kWavesPerGroup, pad);
+  for (size_t g = 0; g < groups; ++g)
+    for (int x = 0; x < kXcds; ++x)
+      for (int w = 0; w < kWavesPerGroup; ++w) {
+        size_t k = g * kWavesPerGroup + w;
+        if (k < lists[x].size()) placed[(g * kXcds + x) * kWavesPerGroup + w] = lists[x][k];
+      }
+  if (v.empty()) placed.clear();
+  return placed;
+}
+
 static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = kChunkTiles) {
   bool split = false;
   for (const MvItem& b : blocks)
@@ -250,44 +301,9 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = k
       v.push_back({b.s, b.o, lo, std::max(lo, hi), slot++, oidx});
     }
   }
-  // XCD assignment: subdomains by greedy load; the coarse block (a single
-  // "subdomain" holding many items, with small shared inputs) round-robin
-  std::vector<int64_t> load_s(C.nsub + 1, 0);
-  for (const MvItem& it : v) load_s[it.s] += it.hi - it.lo + 1;
-  std::vector<int32_t> order(C.nsub);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return load_s[a] > load_s[b]; });
-  std::vector<int> xcd_of(C.nsub + 1, 0);
-  int64_t xload[kXcds] = {0};
-  for (int s : order) {
-    int best = 0;
-    for (int x = 1; x < kXcds; ++x)
-      if (xload[x] < xload[best]) best = x;
-    xcd_of[s] = best;
-    xload[best] += load_s[s];
-  }
-  std::vector<std::vector<MvItem>> lists(kXcds);
-  int rr = 0;
-  for (const MvItem& it : v) {
-    int x = it.s < C.nsub ? xcd_of[it.s] : (rr++ % kXcds);
-    lists[x].push_back(it);
-  }
-  size_t groups = 0;
-  // within an XCD: longest first
-  for (auto& L : lists) {
-    std::stable_sort(L.begin(), L.end(), [&](const MvItem& a, const MvItem& b) {
-      return (a.hi - a.lo) > (b.hi - b.lo);
-    });
-    groups = std::max(groups, (L.size() + kWavesPerGroup - 1) / kWavesPerGroup);
-  }
-  std::vector<MvItem> placed(groups * kXcds * kWavesPerGroup, MvItem{-1, 0, 0, 0, -1, 0});
-  for (size_t g = 0; g < groups; ++g)
-    for (int x = 0; x < kXcds; ++x)
-      for (int w = 0; w < kWavesPerGroup; ++w) {
-        size_t k = g * kWavesPerGroup + w;
-        if (k < lists[x].size()) placed[(g * kXcds + x) * kWavesPerGroup + w] = lists[x][k];
-      }
-  if (v.empty()) placed.clear();
+  std::vector<MvItem> placed = place_xcd(
+      C.nsub, v, MvItem{-1, 0, 0, 0, -1, 0}, [](const MvItem& a) { return a.s; },
+      [](const MvItem& a) { return (int64_t)(a.hi - a.lo); });
   Items it;
   it.n = (int64_t)placed.size();
   it.d = upload(placed, C.owned, C.st);
@@ -298,6 +314,41 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = k
   }
   C.max_slots = std::max<int64_t>(C.max_slots, slot);
   return it;
+}
+
+// panel width of the symmetric product (accumulators per wave: 2 PW blocks)
+template <class T>
+constexpr int sym_panel() {
+  return sizeof(T) == 4 ? 4 : 2;
+}
+
+// Work list of the symmetric product: panel pairs (P, Q), P >= Q, of every
+// subdomain's interface tiles; kG * nP partial slots per subdomain.
+static void make_sym_list(Ctx& C, int pw, size_t wsz) {
+  std::vector<SymItem> v;
+  std::vector<MvOut> outs;
+  int64_t slot = 0;
+  for (int s = 0; s < C.nsub; ++s) {
+    const SubDev& q = C.subs_h[s];
+    if (q.kG == 0) continue;
+    const int nP = (q.kG + pw - 1) / pw;
+    for (int P = 0; P < nP; ++P)
+      for (int Q = 0; Q <= P; ++Q) v.push_back({s, P, Q, (int32_t)slot});
+    for (int b = 0; b < q.kG; ++b) outs.push_back({s, q.kI + b, (int32_t)(slot + (int64_t)b * nP), nP});
+    slot += (int64_t)q.kG * nP;
+    if (slot >= INT32_MAX) throw DDError{DD_ERR_OOM, "too many partial slots"};
+  }
+  std::vector<SymItem> placed = place_xcd(
+      C.nsub, v, SymItem{-1, 0, 0, 0}, [](const SymItem& a) { return a.s; },
+      [&](const SymItem& a) { return (int64_t)(a.P == a.Q ? pw * (pw + 1) / 2 : pw * pw); });
+  C.sym.n = (int64_t)placed.size();
+  C.sym.d = upload(placed, C.owned, C.st);
+  C.sym.n_out = (int64_t)outs.size();
+  C.sym.outs = upload(outs, C.owned, C.st);
+  void* p = nullptr;
+  HIPCHK(hipMalloc(&p, std::max<int64_t>(1, slot) * kTile * C.nrhs * wsz / NB));
+  C.owned.push_back(p);
+  C.sym.partial = p;
 }
 
 static void build_device(Ctx& C, const double* coords) {
@@ -350,29 +401,29 @@ static void build_device(Ctx& C, const double* coords) {
     HIPCHK(e);
     C.owned.push_back(p);
     C.d_tilesT = p;
-    std::vector<int64_t> so(nsub);
+    std::vector<int64_t> mo(nsub);
     int64_t acc = 0;
     for (int s = 0; s < nsub; ++s) {
-      so[s] = acc;
-      acc += (int64_t)C.subs_h[s].kG * C.subs_h[s].kG;
+      mo[s] = acc;
+      acc += (int64_t)C.subs_h[s].kG * (C.subs_h[s].kG + 1) / 2;
     }
-    C.sq_tiles = acc;
-    C.d_sq_off = upload(so, C.owned, st);
+    C.m_tiles = acc;
+    C.d_m_off = upload(mo, C.owned, st);
     p = nullptr;
-    e = hipMalloc(&p, std::max<int64_t>(1, C.sq_tiles) * kTile * wsz);
+    e = hipMalloc(&p, std::max<int64_t>(1, C.m_tiles) * kTile * wsz);
     if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation of the interface inverse failed"};
     HIPCHK(e);
     C.owned.push_back(p);
-    C.d_msq = p;
+    C.d_mtri = p;
   }
   // algorithmic byte counts (unpadded, packed triangles)
-  C.factor_bytes = (2 * C.ntiles + C.sq_tiles) * kTile * (int64_t)wsz;
+  C.factor_bytes = (2 * C.ntiles + C.m_tiles) * kTile * (int64_t)wsz;
   for (int s = 0; s < nsub; ++s) {
     const SubInfo& q = P.subs[s];
     int64_t nr = q.nI + q.nG;
     // inverse-factor triangle plus the premultiplied corner rows it carries
     C.trailing_bytes += ((int64_t)q.nG * (q.nG + 1) / 2 + (int64_t)q.nC * q.nG) * wsz;
-    C.schur_bytes += (int64_t)q.nG * q.nG * wsz;
+    C.schur_bytes += (int64_t)q.nG * (q.nG + 1) / 2 * wsz;
     C.corner_bytes += (int64_t)q.nC * q.nG * wsz;
     C.full_bytes += (nr * (nr + 1) / 2 + (int64_t)q.nC * nr) * wsz;
   }
@@ -660,7 +711,7 @@ static void build_device(Ctx& C, const double* coords) {
     // transposed passes run over [o, K) so they include Psi^T (corner inputs)
     // (the full r-block lists are built from the nonzero tiles after the
     // first factorisation)
-    std::vector<MvItem> tN, tT, oN, oT, sq, cN, cT;
+    std::vector<MvItem> tN, tT, oN, oT, cN, cT;
     for (int s = 0; s < nsub; ++s) {
       const SubDev& q = C.subs_h[s];
       int kr = q.kI + q.kG;
@@ -671,7 +722,6 @@ static void build_device(Ctx& C, const double* coords) {
       for (int o = q.kI; o < kr; ++o) {
         tN.push_back({s, o, q.kI, o + 1, -1, 0});
         tT.push_back({s, o, o, q.K, -1, 0});
-        sq.push_back({s, o, q.kI, kr, -1, 0});
         if (q.kC > 0) cT.push_back({s, o, kr, q.K, -1, 0});
       }
     }
@@ -683,13 +733,8 @@ static void build_device(Ctx& C, const double* coords) {
     C.trail_T = make_items(C, tT);
     C.corner_N = make_items(C, cN);
     C.corner_T = make_items(C, cT);
-    C.schur = make_items(C, sq);
-    if (C.schur.n_slots > 0) {  // runs beside the coarse chain: own partial slots
-      void* q = nullptr;
-      HIPCHK(hipMalloc(&q, C.schur.n_slots * kTile * C.nrhs * wsz / NB));
-      C.owned.push_back(q);
-      C.schur.partial = q;
-    }
+    // runs beside the coarse chain: own partial slots
+    make_sym_list(C, C.fp32 ? sym_panel<float>() : sym_panel<double>(), wsz);
     C.co_N = make_items(C, oN);
     C.co_T = make_items(C, oT);
     void* p = nullptr;
@@ -921,7 +966,7 @@ static int factor_impl(Ctx& C) {
     for (int s = 0; s < C.nsub; ++s) max_kg = std::max(max_kg, C.subs_h[s].kG);
     if (max_kg > 0)
       hipLaunchKernelGGL(k_schur_inv<T>, dim3((unsigned)(max_kg * (max_kg + 1) / 2), C.nsub), dim3(256), 0, st, 0,
-                         (const T*)tiles, C.d_subs, C.d_sq_off, (T*)C.d_msq);
+                         (const T*)tiles, C.d_subs, C.d_m_off, (T*)C.d_mtri);
   }
   if (C.Kc > 0) {
     if (C.n_cent)
@@ -981,7 +1026,6 @@ static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
 
 static int item_class(const Ctx& C, const Items& it) {
   if (&it == &C.trail_N || &it == &C.trail_T) return DD_PROF_TRAILING;
-  if (&it == &C.schur) return DD_PROF_SCHUR;
   if (&it == &C.corner_N || &it == &C.corner_T) return DD_PROF_CORNER;
   if (&it == &C.full_N || &it == &C.full_T) return DD_PROF_FULL;
   return DD_PROF_COARSE;
@@ -991,11 +1035,11 @@ template <class T, int NV, int NB16, int CLS>
 static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const void* in, void* out, const void* add,
                       T alpha, const void* add_c, T alpha_c, const int* skip) {
   const bool split = it.n_out > 0;
-  const T* tiles = (const T*)(CLS == DD_PROF_SCHUR ? C.d_msq : (trans ? C.d_tilesT : C.d_tiles));
+  const T* tiles = (const T*)(trans ? C.d_tilesT : C.d_tiles);
   T* partial = (T*)(it.partial ? it.partial : C.d_partial_mv);
   hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, s, it.n, it.d,
                      C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
-                     (int)trans, partial, (const int32_t*)it.mlist, skip, (const int64_t*)C.d_sq_off);
+                     (int)trans, partial, (const int32_t*)it.mlist, skip);
   if (split)
     hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, s, it.n_out, it.outs, C.d_subs,
                        (const T*)partial, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs, skip);
@@ -1034,8 +1078,6 @@ static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, c
     mv_dispatch<T, DD_PROF_TRAILING>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_FULL)
     mv_dispatch<T, DD_PROF_FULL>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
-  else if (cls == DD_PROF_SCHUR)
-    mv_dispatch<T, DD_PROF_SCHUR>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_CORNER)
     mv_dispatch<T, DD_PROF_CORNER>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
@@ -1052,6 +1094,27 @@ static void fork_side(Ctx& C) {
 static void join_side(Ctx& C) {
   HIPCHK(hipEventRecord(C.ev_join, C.st2));
   HIPCHK(hipStreamWaitEvent(C.st, C.ev_join, 0));
+}
+
+// out (interface rows) = M in: the symmetric product and its reduce
+template <class T>
+static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side) {
+  if (C.sym.n == 0) return;
+  hipEvent_t e0, e1;
+  bool timed = prof_begin(C, DD_PROF_SCHUR, &e0, &e1);
+  hipStream_t s = side ? C.st2 : C.st;
+  constexpr int PW = sym_panel<T>();
+  const dim3 grid((unsigned)((C.sym.n + 3) / 4));
+  if (C.nrhs <= 16)
+    hipLaunchKernelGGL((k_symv<T, 1, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,
+                       (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip);
+  else
+    hipLaunchKernelGGL((k_symv<T, 2, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,
+                       (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip);
+  hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)C.sym.n_out), dim3(256), 0, s, C.sym.n_out, C.sym.outs,
+                     C.d_subs, (const T*)C.sym.partial, (T*)out, (const T*)nullptr, (T)1, (const T*)nullptr, (T)1,
+                     C.nrhs, skip);
+  if (timed) HIPCHK(hipEventRecord(e1, C.st));
 }
 
 // coarse: y rows of Xin (coarse block) -> Xout coarse rows = K_cc^-1 y via
@@ -1077,7 +1140,7 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
   const bool overlap = C.Kc > 0 && !C.prof;
   if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, (T)1, skip);
   if (overlap) fork_side(C);
-  mv<T>(C, C.schur, false, X[5], X[8], nullptr, (T)1, skip, nullptr, (T)1, overlap);
+  symv<T>(C, X[5], X[8], skip, overlap);
   if (C.Kc > 0) {
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],

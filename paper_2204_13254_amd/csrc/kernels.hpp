@@ -479,19 +479,15 @@ __device__ __forceinline__ void load_chunk8(const T* __restrict__ blk, int l, T*
 }
 
 // NV > 0: vector path for nrhs <= NV; NV == 0: MFMA path with NB16 RHS blocks.
-// CLS names the product class in kernel traces (0 interface blocks of the
-// inverse factors, 1 full r-blocks, 2 interface blocks of the local inverses,
-// 3 coarse, 4 corner rows).  Class 2 reads a square store: subdomain s holds
-// its kG x kG interface tiles row by row from tile sq_off[s], and the items
-// range over interface tile indices [kI, kI + kG).
+// CLS only names the product class in kernel traces (0 interface blocks of
+// the inverse factors, 1 full r-blocks, 3 coarse, 4 corner rows).
 template <class T, int NV, int NB16, int CLS>
 __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* __restrict__ items,
                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
-                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip,
-                                                 const int64_t* __restrict__ sq_off) {
+                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wi >= n_items) return;
@@ -520,25 +516,33 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
   constexpr int NX = PX ? 8 * (MF ? NB16 : NV) : 1;
   T cur[16], nxt[16], xc[NX], xn[NX];
   auto tile_ptr = [&](int m) -> const T* {
-    if constexpr (CLS == 2)
-      return tiles + (sq_off[w.s] + (int64_t)(w.o - q.kI) * q.kG + (m - q.kI)) * kTile;
     const int ti = trans ? m : w.o, tj = trans ? w.o : m;
     return tiles + tile_index(q, ti, tj) * kTile;
   };
+  // Loads are unconditional (clamped to an in-bounds column, then zeroed
+  // by a select): a masked load compiles to a branch whose other arm waits
+  // for every load in flight, prefetches included.
   auto load_x = [&](int m, T* xv) {
     const T* xb = xbase + (int64_t)m * kNB * nrhs;
     if constexpr (MF) {
 #pragma unroll
       for (int nb = 0; nb < NB16; ++nb) {
         const int col = nb * 16 + i;
+        const int cc = col < nrhs ? col : nrhs - 1;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) xv[nb * 8 + ks] = col < nrhs ? xb[(8 * g + ks) * nrhs + col] : (T)0;
+        for (int ks = 0; ks < 8; ++ks) {
+          const T v = xb[(8 * g + ks) * nrhs + cc];
+          xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
+        }
       }
     } else if constexpr (PX) {
 #pragma unroll
       for (int ks = 0; ks < 8; ++ks)
 #pragma unroll
-        for (int r = 0; r < NV; ++r) xv[ks * NV + r] = r < nrhs ? xb[(8 * g + ks) * nrhs + r] : (T)0;
+        for (int r = 0; r < NV; ++r) {
+          const T v = xb[(8 * g + ks) * nrhs + (r < nrhs ? r : nrhs - 1)];
+          xv[ks * NV + r] = r < nrhs ? v : (T)0;
+        }
     }
   };
   auto mof = [&](int k) -> int { return mlist ? mlist[k] : k; };
@@ -654,6 +658,178 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
   }
 }
 
+// --------------------------------------------------------------------------
+// Symmetric product y = M u with only the lower tiles of M stored (M: the
+// interface block of a subdomain's local inverse).  Every tile is read once
+// and used twice.  Interface tiles are grouped into panels of PW; one wave
+// takes the tiles (o, m), m <= o, of a panel pair (P, Q), P >= Q:
+//     row part     y_o += M_om u_m      (o in panel P)
+//     column part  y_m += M_om^T u_o    (m in panel Q, m < o)
+// accumulated in registers (MFMA 16x16x4, NB16 blocks of 16 RHS; smaller RHS
+// counts are zero-padded).  The column part needs the tile with lanes along
+// its columns: each wave stages the tile in its own LDS area and reads it back
+// transposed (only wave-level ordering is involved).
+// Output block b (interface tile index) gets exactly one partial from every
+// panel j: slot slot0 + b nP + j holds the row part of pair (P(b), j) for
+// j < P(b), the diagonal pair's sum for j = P(b), and the column part of pair
+// (j, P(b)) for j > P(b); k_mv_reduce sums them in panel order.
+// --------------------------------------------------------------------------
+struct SymItem {
+  int32_t s, P, Q;  // subdomain, panel pair (P >= Q)
+  int32_t slot0;    // first partial slot of the subdomain (kG * nP slots)
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class T, int NB16, int PW>
+__global__ void __launch_bounds__(256) k_symv(int64_t n_items, const SymItem* __restrict__ items,
+                                              const SubDev* __restrict__ subs, const int64_t* __restrict__ m_off,
+                                              const T* __restrict__ mt, const T* __restrict__ in,
+                                              T* __restrict__ partial, int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ T lds[4][kNB][kNB + 1];
+  const int wv = threadIdx.x >> 6;
+  const int64_t wi = (int64_t)blockIdx.x * 4 + wv;
+  if (wi >= n_items) return;  // (no workgroup barriers below: waves are independent)
+  const SymItem it = items[wi];
+  if (it.s < 0) return;
+  const SubDev q = subs[it.s];
+  const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+  const int kG = q.kG;
+  const int nP = (kG + PW - 1) / PW;
+  const bool diag = it.P == it.Q;
+  const int o0 = it.P * PW, m0 = it.Q * PW;
+  const T* mb = mt + m_off[it.s] * kTile;
+  const T* xg = in + (q.row_off + (int64_t)q.kI * kNB) * nrhs;
+  T(*sh)[kNB + 1] = lds[wv];
+  using acc_t = typename Mfma<T>::acc_t;
+  acc_t racc[PW][2][NB16], cacc[PW][2][NB16];
+#pragma unroll
+  for (int a = 0; a < PW; ++a)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb) {
+        racc[a][h][nb] = acc_t{0, 0, 0, 0};
+        cacc[a][h][nb] = acc_t{0, 0, 0, 0};
+      }
+  auto valid = [&](int t) -> bool {
+    const int jr = t / PW, jc = t % PW;
+    return o0 + jr < kG && m0 + jc < kG && (!diag || jc <= jr);
+  };
+  auto next_valid = [&](int t) -> int {
+    for (int u = t + 1; u < PW * PW; ++u)
+      if (valid(u)) return u;
+    return -1;
+  };
+  auto tile_of = [&](int t) -> const T* {
+    const int o = o0 + t / PW, m = m0 + t % PW;
+    return mb + ((int64_t)o * (o + 1) / 2 + m) * kTile;
+  };
+  // xv[nb*8 + ks] = u[block b][row 8g + ks][rhs nb*16 + i]
+  // (unconditional loads from a clamped column, as in k_tile_mv)
+  auto load_x = [&](int b, T* xv) {
+    const T* xb = xg + (int64_t)b * kNB * nrhs;
+#pragma unroll
+    for (int nb = 0; nb < NB16; ++nb) {
+      const int col = nb * 16 + i;
+      const int cc = col < nrhs ? col : nrhs - 1;
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const T v = xb[(8 * g + ks) * nrhs + cc];
+        xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
+      }
+    }
+  };
+  T cur[16], nxt[16], xm[8 * NB16], xmn[8 * NB16], xo[8 * NB16], xon[8 * NB16];
+  // tile 0 = (o0, m0) is always valid: o0 < kG and m0 <= o0
+  load_chunk8(tile_of(0), l, cur);
+  load_chunk8(tile_of(0) + 512, l, cur + 8);
+  load_x(m0, xm);
+  load_x(o0, xo);
+#pragma unroll
+  for (int t = 0; t < PW * PW; ++t) {
+    if (!valid(t)) continue;
+    const int jr = t / PW, jc = t % PW;
+    const int tn = next_valid(t);
+    if (tn >= 0) {
+      const T* tp = tile_of(tn);
+      load_chunk8(tp, l, nxt);
+      load_chunk8(tp + 512, l, nxt + 8);
+      load_x(m0 + tn % PW, xmn);
+      load_x(o0 + tn / PW, xon);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        racc[jr][0][nb] = Mfma<T>::op(cur[ks], xm[nb * 8 + ks], racc[jr][0][nb]);
+        racc[jr][1][nb] = Mfma<T>::op(cur[8 + ks], xm[nb * 8 + ks], racc[jr][1][nb]);
+      }
+    if (!diag || jc != jr) {
+      // column part: lane (g, i) needs M(8g + ks, cb*16 + i)
+      wave_lds_sync();
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) sh[h * 16 + i][8 * g + ks] = cur[h * 8 + ks];
+      wave_lds_sync();
+      T tt[16];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) tt[cb * 8 + ks] = sh[8 * g + ks][cb * 16 + i];
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          cacc[jc][0][nb] = Mfma<T>::op(tt[ks], xo[nb * 8 + ks], cacc[jc][0][nb]);
+          cacc[jc][1][nb] = Mfma<T>::op(tt[8 + ks], xo[nb * 8 + ks], cacc[jc][1][nb]);
+        }
+    }
+    if (tn >= 0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+#pragma unroll
+      for (int u = 0; u < 8 * NB16; ++u) {
+        xm[u] = xmn[u];
+        xo[u] = xon[u];
+      }
+    }
+  }
+  // ---- partial blocks ---------------------------------------------------------
+  auto write = [&](int b, int j, const acc_t (&a)[2][NB16], const acc_t (&c)[2][NB16], bool both) {
+    T* dst = partial + (int64_t)(it.slot0 + b * nP + j) * kNB * nrhs;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb) {
+        const int col = nb * 16 + i;
+        if (col < nrhs) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = h * 16 + Mfma<T>::row(l, v);
+            dst[(int64_t)row * nrhs + col] = both ? a[h][nb][v] + c[h][nb][v] : a[h][nb][v];
+          }
+        }
+      }
+  };
+#pragma unroll
+  for (int j = 0; j < PW; ++j) {
+    if (o0 + j < kG) {
+      if (diag)
+        write(o0 + j, it.P, racc[j], cacc[j], true);
+      else
+        write(o0 + j, it.Q, racc[j], racc[j], false);
+    }
+    if (!diag && m0 + j < kG) write(m0 + j, it.P, cacc[j], cacc[j], false);
+  }
+}
+
 // out_o = (add ? add_o : 0) + alpha * sum of the item's partial slots
 template <class T>
 __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* __restrict__ outs,
@@ -699,15 +875,15 @@ __global__ void __launch_bounds__(256) k_tile_nnz(int64_t t0, int64_t n, const T
 // Interface block of the local inverse K_rr^-1 = Linv_rr^T Linv_rr (the
 // local inverses stored for the substitutions, Sec. III-C).  Linv_rr is lower
 // triangular with Gamma ordered last in r, so the block is
-// M = Linv_GG^T Linv_GG and the CG loop applies it in one product.  One
-// workgroup per tile (o, m), o >= m (interface tile indices):
+// M = Linv_GG^T Linv_GG and the CG loop applies it in one symmetric product
+// (k_symv).  One workgroup per tile (o, m), o >= m (interface tile indices):
 //     M_om = sum_{k >= o} Linv_ko^T Linv_km,
-// written in operand order to tile (o, m) and, transposed, to (m, o) of the
-// subdomain's square block.  Reads the row-major factor store.
+// written in operand order to tile o(o+1)/2 + m of the subdomain's packed
+// lower triangle (from tile m_off[s]).  Reads the row-major factor store.
 template <class T>
 __global__ void __launch_bounds__(256) k_schur_inv(int s0, const T* __restrict__ tiles,
                                                    const SubDev* __restrict__ subs,
-                                                   const int64_t* __restrict__ sq_off, T* __restrict__ msq) {
+                                                   const int64_t* __restrict__ m_off, T* __restrict__ msq) {
   const int sidx = s0 + blockIdx.y;
   const SubDev q = subs[sidx];
   const int p = blockIdx.x;  // p = o (o + 1) / 2 + m
@@ -732,13 +908,11 @@ __global__ void __launch_bounds__(256) k_schur_inv(int s0, const T* __restrict__
     __syncthreads();
     tile_mma<T, false>(A, B, mb, nb, l, acc);
   }
-  T* d = msq + (sq_off[sidx] + (int64_t)o * q.kG + m) * kTile;
-  T* dT = msq + (sq_off[sidx] + (int64_t)m * q.kG + o) * kTile;
+  T* d = msq + (m_off[sidx] + (int64_t)o * (o + 1) / 2 + m) * kTile;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int r = mb * 16 + Mfma<T>::row(l, v), c = nb * 16 + (l & 15);
     d[swz<T>(r, c)] = acc[v];
-    if (o != m) dT[swz<T>(c, r)] = acc[v];
   }
 }
 
@@ -951,15 +1125,26 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
 #pragma unroll
     for (int u = 0; u < B; ++u) {
       const bool ok = kb + u < k1;
-      c[u] = ok ? ci[kb + u] : -1;
-      av[u] = ok ? v[kb + u] : make_double2(0.0, 0.0);
+      const int64_t k = ok ? kb + u : k0;  // in-bounds (the row is not empty here)
+      const int32_t cv = ci[k];
+      const double2 vv = v[k];
+      c[u] = ok ? cv : -1;
+      av[u] = ok ? vv : make_double2(0.0, 0.0);
     }
+    // unconditional gathers (padding entries read column 0, then zeroed):
+    // a masked load would branch and wait for all loads in flight
     double a[B], b[B];
 #pragma unroll
     for (int u = 0; u < B; ++u) {
-      const int64_t o = (int64_t)c[u] * nrhs + r;
-      a[u] = c[u] >= 0 ? x1[o] : 0.0;
-      b[u] = (mode == 0 && c[u] >= 0) ? x2[o] : 0.0;
+      const int64_t o = (int64_t)(c[u] >= 0 ? c[u] : 0) * nrhs + r;
+      const double va = x1[o];
+      a[u] = c[u] >= 0 ? va : 0.0;
+      if (mode == 0) {
+        const double vb = x2[o];
+        b[u] = c[u] >= 0 ? vb : 0.0;
+      } else {
+        b[u] = 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < B; ++u) {
