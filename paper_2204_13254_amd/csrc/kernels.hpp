@@ -487,7 +487,8 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
-                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
+                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip,
+                                                 const T* __restrict__ psum, const MvOut* __restrict__ pouts) {
   if (skip && *skip) return;
   const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wi >= n_items) return;
@@ -618,6 +619,16 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
     dst = partial + (int64_t)w.slot * kNB * nrhs;
     scale = (T)1;
   }
+  // psum (direct writes only): add the output block's partial slots
+  // pouts[oidx] (summed in slot order) instead of an add vector
+  const bool ps = psum != nullptr && w.slot < 0;
+  MvOut po{0, 0, 0, 0};
+  if (ps) po = pouts[w.oidx];
+  auto psum_at = [&](int64_t o) -> T {
+    T a = 0;
+    for (int k = 0; k < po.nslot; ++k) a += psum[(int64_t)(po.slot0 + k) * kNB * nrhs + o];
+    return a;
+  };
   if constexpr (MF) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -631,6 +642,7 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
             const int64_t o = (int64_t)row * nrhs + col;
             T val = scale * macc[mb * NB16 + nb][v];
             if (adp) val += adp[o];
+            if (ps) val += psum_at(o);
             dst[o] = val;
           }
         }
@@ -652,6 +664,7 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
           const int64_t o = (int64_t)(mb * 16 + i) * nrhs + r;
           T val = scale * vacc[mb * NV + r];
           if (adp) val += adp[o];
+          if (ps) val += psum_at(o);
           dst[o] = val;
         }
       }
@@ -745,7 +758,9 @@ __global__ void __launch_bounds__(256) k_symv(int64_t n_items, const SymItem* __
       }
     }
   };
-  T cur[16], nxt[16], xm[8 * NB16], xmn[8 * NB16], xo[8 * NB16], xon[8 * NB16];
+  // u_m is prefetched with each tile; u_o only changes with the row (loaded
+  // at its first tile, covered by the row part's MFMAs)
+  T cur[16], nxt[16], xm[8 * NB16], xmn[8 * NB16], xo[8 * NB16];
   // tile 0 = (o0, m0) is always valid: o0 < kG and m0 <= o0
   load_chunk8(tile_of(0), l, cur);
   load_chunk8(tile_of(0) + 512, l, cur + 8);
@@ -755,13 +770,13 @@ __global__ void __launch_bounds__(256) k_symv(int64_t n_items, const SymItem* __
   for (int t = 0; t < PW * PW; ++t) {
     if (!valid(t)) continue;
     const int jr = t / PW, jc = t % PW;
+    if (jc == 0 && jr > 0) load_x(o0 + jr, xo);
     const int tn = next_valid(t);
     if (tn >= 0) {
       const T* tp = tile_of(tn);
       load_chunk8(tp, l, nxt);
       load_chunk8(tp + 512, l, nxt + 8);
       load_x(m0 + tn % PW, xmn);
-      load_x(o0 + tn / PW, xon);
     }
 #pragma unroll
     for (int nb = 0; nb < NB16; ++nb)
@@ -795,10 +810,7 @@ __global__ void __launch_bounds__(256) k_symv(int64_t n_items, const SymItem* __
 #pragma unroll
       for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
 #pragma unroll
-      for (int u = 0; u < 8 * NB16; ++u) {
-        xm[u] = xmn[u];
-        xo[u] = xon[u];
-      }
+      for (int u = 0; u < 8 * NB16; ++u) xm[u] = xmn[u];
     }
   }
   // ---- partial blocks ---------------------------------------------------------
