@@ -1127,10 +1127,11 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
   const int r = (int)(i % nrhs);
   double t1 = 0.0, s1 = 0.0, t2 = 0.0, s2 = 0.0;
   const int64_t k0 = rp[row], k1 = rp[row + 1];
-  // nonzeros in batches of 8: all index and value loads of a batch are
-  // issued before the gathers (memory-level parallelism); the products are
-  // summed in ascending nonzero order
-  constexpr int B = 8;
+  // nonzeros in batches of 4: all index and value loads of a batch are
+  // issued before the gathers (memory-level parallelism; 8 measured slower,
+  // its register use halves the occupancy); the products are summed in
+  // ascending nonzero order
+  constexpr int B = 4;
   for (int64_t kb = k0; kb < k1; kb += B) {
     int32_t c[B];
     double2 av[B];
