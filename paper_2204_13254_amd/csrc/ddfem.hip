@@ -86,9 +86,6 @@ struct Items {
   int64_t n_slots = 0;   // partial slots used (0 = direct writes)
   int32_t* mlist = nullptr;  // tile list (ranges index it), or null for contiguous ranges
   void* partial = nullptr;   // own partial slots (lists that run beside others), or null
-  // direct-write items add the partial slots pouts[oidx] of psum (see k_tile_mv)
-  const void* psum = nullptr;
-  const MvOut* pouts = nullptr;
 };
 
 constexpr int kChunkTiles = 32;  // longest tile range of one wave
@@ -316,19 +313,6 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = k
     it.outs = upload(outs, C.owned, C.st);
   }
   C.max_slots = std::max<int64_t>(C.max_slots, slot);
-  return it;
-}
-
-// make_items for a list whose direct-write items carry their own oidx
-static Items make_items_keep_oidx(Ctx& C, const std::vector<MvItem>& blocks) {
-  for (const MvItem& b : blocks)
-    if (b.hi - b.lo > kChunkTiles) return make_items(C, blocks);
-  std::vector<MvItem> placed = place_xcd(
-      C.nsub, blocks, MvItem{-1, 0, 0, 0, -1, 0}, [](const MvItem& a) { return a.s; },
-      [](const MvItem& a) { return (int64_t)(a.hi - a.lo); });
-  Items it;
-  it.n = (int64_t)placed.size();
-  it.d = upload(placed, C.owned, C.st);
   return it;
 }
 
@@ -738,7 +722,7 @@ static void build_device(Ctx& C, const double* coords) {
       for (int o = q.kI; o < kr; ++o) {
         tN.push_back({s, o, q.kI, o + 1, -1, 0});
         tT.push_back({s, o, o, q.K, -1, 0});
-        cT.push_back({s, o, kr, q.K, -1, 0});  // (empty range when kC = 0)
+        if (q.kC > 0) cT.push_back({s, o, kr, q.K, -1, 0});
       }
     }
     for (int o = 0; o < C.Kc; ++o) {
@@ -750,17 +734,9 @@ static void build_device(Ctx& C, const double* coords) {
     // runs beside the coarse chain: own partial slots
     make_sym_list(C, C.fp32 ? sym_panel<float>() : sym_panel<double>(), wsz);
     C.corner_N = make_items(C, cN);
-    if (C.Kc > 0) {
-      // Psi_Gamma^T z plus the symmetric product's partials: the reduce is
-      // folded into this pass (the sym outputs are listed in the same
-      // subdomain / interface-row order as cT)
-      for (size_t k = 0; k < cT.size(); ++k) cT[k].oidx = (int32_t)k;
-      C.corner_T = make_items_keep_oidx(C, cT);
-      if (C.corner_T.n_out == 0) {
-        C.corner_T.psum = C.sym.partial;
-        C.corner_T.pouts = C.sym.outs;
-      }
-    }
+    // (summing the symmetric partials inside this pass instead of a reduce on
+    // the side stream measured slower: it lengthens the main-stream chain)
+    C.corner_T = make_items(C, cT);
     C.co_N = make_items(C, oN);
     C.co_T = make_items(C, oT);
     void* p = nullptr;
@@ -1065,7 +1041,7 @@ static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const 
   T* partial = (T*)(it.partial ? it.partial : C.d_partial_mv);
   hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, s, it.n, it.d,
                      C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
-                     (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)it.psum, it.pouts);
+                     (int)trans, partial, (const int32_t*)it.mlist, skip);
   if (split)
     hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, s, it.n_out, it.outs, C.d_subs,
                        (const T*)partial, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs, skip);
@@ -1123,9 +1099,8 @@ static void join_side(Ctx& C) {
 }
 
 // out (interface rows) = M in: the symmetric product and its reduce
-// (reduce = false: the partials are summed by the corner pass instead)
 template <class T>
-static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side, bool reduce) {
+static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side) {
   if (C.sym.n == 0) return;
   hipEvent_t e0, e1;
   bool timed = prof_begin(C, DD_PROF_SCHUR, &e0, &e1);
@@ -1138,10 +1113,9 @@ static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side, 
   else
     hipLaunchKernelGGL((k_symv<T, 2, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,
                        (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip);
-  if (reduce)
-    hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)C.sym.n_out), dim3(256), 0, s, C.sym.n_out, C.sym.outs,
-                       C.d_subs, (const T*)C.sym.partial, (T*)out, (const T*)nullptr, (T)1, (const T*)nullptr,
-                       (T)1, C.nrhs, skip);
+  hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)C.sym.n_out), dim3(256), 0, s, C.sym.n_out, C.sym.outs,
+                     C.d_subs, (const T*)C.sym.partial, (T*)out, (const T*)nullptr, (T)1, (const T*)nullptr, (T)1,
+                     C.nrhs, skip);
   if (timed) HIPCHK(hipEventRecord(e1, C.st));
 }
 
@@ -1156,8 +1130,9 @@ static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* s
 // F p -> Fp (uses X5..X8):
 //   v = B_s^T p;  y = Psi_G v (corner rows);  z = K_cc^-1 sum B_c^T y;
 //   u = M v + Psi_G^T z with M = Linv_GG^T Linv_GG;  F p = sum B_s u
-// M v needs only v: it runs on the side stream while the coarse chain runs
-// on st (disjoint rows of X5 / X6 / X8, own partial slots).
+// M v needs only v: it runs on the side stream while the corner rows and
+// the coarse chain run on st (disjoint rows of X5 / X6 / X8, own partial
+// slots).
 template <class T>
 static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false) {
   const int nr = C.nrhs;
@@ -1166,10 +1141,9 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
   hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                      C.d_glam, p, (T*)X[5], nr, skip);
   const bool overlap = C.Kc > 0 && !C.prof;
-  if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, (T)1, skip);
   if (overlap) fork_side(C);
-  const bool fused = C.corner_T.psum != nullptr;
-  symv<T>(C, X[5], X[8], skip, overlap, !fused);
+  symv<T>(C, X[5], X[8], skip, overlap);
+  if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, (T)1, skip);
   if (C.Kc > 0) {
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
@@ -1179,7 +1153,7 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
                        C.d_csccrow, (const T*)X[5], (T*)X[6], (T)1, nr, skip);
   }
   if (overlap) join_side(C);
-  if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[8], fused ? nullptr : X[8], (T)1, skip);
+  if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[8], X[8], (T)1, skip);
   hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
                      (const T*)X[8], Fp, dot ? p : (const double*)nullptr, nr, C.d_partial, skip);
 }

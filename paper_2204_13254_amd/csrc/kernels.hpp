@@ -487,8 +487,7 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
-                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip,
-                                                 const T* __restrict__ psum, const MvOut* __restrict__ pouts) {
+                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (wi >= n_items) return;
@@ -619,16 +618,6 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
     dst = partial + (int64_t)w.slot * kNB * nrhs;
     scale = (T)1;
   }
-  // psum (direct writes only): add the output block's partial slots
-  // pouts[oidx] (summed in slot order) instead of an add vector
-  const bool ps = psum != nullptr && w.slot < 0;
-  MvOut po{0, 0, 0, 0};
-  if (ps) po = pouts[w.oidx];
-  auto psum_at = [&](int64_t o) -> T {
-    T a = 0;
-    for (int k = 0; k < po.nslot; ++k) a += psum[(int64_t)(po.slot0 + k) * kNB * nrhs + o];
-    return a;
-  };
   if constexpr (MF) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -642,7 +631,6 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
             const int64_t o = (int64_t)row * nrhs + col;
             T val = scale * macc[mb * NB16 + nb][v];
             if (adp) val += adp[o];
-            if (ps) val += psum_at(o);
             dst[o] = val;
           }
         }
@@ -664,7 +652,6 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
           const int64_t o = (int64_t)(mb * 16 + i) * nrhs + r;
           T val = scale * vacc[mb * NV + r];
           if (adp) val += adp[o];
-          if (ps) val += psum_at(o);
           dst[o] = val;
         }
       }
