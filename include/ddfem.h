@@ -67,7 +67,8 @@ typedef struct {
   int warm_start;     /* initial multipliers of a step's first CG solve: 0 zero, 1 the
                          previous step's, 2 linear extrapolation of the last two steps */
   int use_graph;      /* replay the CG iteration as a captured HIP graph */
-  int check_every;    /* CG iterations between host convergence checks (>= 1) */
+  int check_every;    /* CG iterations between host convergence checks (>= 1; rounded up
+                         to an even count, the unit a captured graph replays) */
   void* stream;       /* hipStream_t; NULL = default stream */
 } dd_options;
 

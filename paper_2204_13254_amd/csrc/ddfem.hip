@@ -155,7 +155,6 @@ struct Ctx {
   int64_t *d_cgptr = nullptr, *d_cgrows = nullptr;  // coarse gather
   int64_t n_csc = 0;
   int64_t *d_cscrows = nullptr, *d_csccrow = nullptr;  // corner scatter
-  uint8_t* d_gamma_row = nullptr;
   int64_t* d_dsrc = nullptr;
   int32_t *d_interior = nullptr, *d_dof = nullptr, *d_tdof = nullptr;
   // Gauss law adjacency (interior edges only)
@@ -190,6 +189,7 @@ struct Ctx {
   };
   Warm warm_fw, warm_adj;
   double* d_partial = nullptr;
+  double* d_p2 = nullptr;  // p of odd CG iterations (even ones use d_p)
   CgState* d_cg = nullptr;
   int* h_done = nullptr;  // pinned
   double* h_partial = nullptr;  // pinned [kDotBlocks * kMaxRhs]
@@ -601,7 +601,6 @@ static void build_device(Ctx& C, const double* coords) {
   // ---- vector maps -------------------------------------------------------------------
   {
     std::vector<int32_t> rowsrc(C.rows_total, -1);
-    std::vector<uint8_t> gamma_row(C.rows_total, 0);
     std::vector<int64_t> grow;
     std::vector<int32_t> glam;
     std::vector<int64_t> cscrows, csccrow;
@@ -622,7 +621,6 @@ static void build_device(Ctx& C, const double* coords) {
         if (P.owner[d] == s) rowsrc[qd.row_off + P.padded_row(s, p)] = d;
       }
       for (int32_t r = q.kI * NB; r < q.kr() * NB; ++r) {
-        gamma_row[qd.row_off + r] = 1;
         grow.push_back(qd.row_off + r);
         int32_t g = r - q.kI * NB;
         glam.push_back(g < q.nG ? lam_at[s][g] : -1);
@@ -634,7 +632,6 @@ static void build_device(Ctx& C, const double* coords) {
       }
     }
     C.d_rowsrc = upload(rowsrc, C.owned, st);
-    C.d_gamma_row = upload(gamma_row, C.owned, st);
     C.n_grow = (int64_t)grow.size();
     C.d_grow = upload(grow, C.owned, st);
     C.d_glam = upload(glam, C.owned, st);
@@ -720,7 +717,7 @@ static void build_device(Ctx& C, const double* coords) {
         cN.push_back({s, o, q.kI, kr, -1, 0});
       }
       for (int o = q.kI; o < kr; ++o) {
-        tN.push_back({s, o, q.kI, o + 1, -1, 0});
+        tN.push_back({s, o, q.kI, o + 1, -1, 0});  // interface rows only (corner rows: cN)
         tT.push_back({s, o, o, q.K, -1, 0});
         if (q.kC > 0) cT.push_back({s, o, kr, q.K, -1, 0});
       }
@@ -767,6 +764,7 @@ static void build_device(Ctx& C, const double* coords) {
   C.warm_adj.cur = dalloc<double>(nl, C.owned);
   C.warm_adj.old = dalloc<double>(nl, C.owned);
   C.d_partial = dalloc<double>(kDotBlocks * kMaxRhs, C.owned);
+  C.d_p2 = dalloc<double>(nl, C.owned);
   C.d_cg = dalloc<CgState>(1, C.owned);
   HIPCHK(hipHostMalloc((void**)&C.h_done, sizeof(int) * 4, hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&C.h_partial, sizeof(double) * kDotBlocks * kMaxRhs, hipHostMallocDefault));
@@ -1133,13 +1131,16 @@ static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* s
 // M v needs only v: it runs on the side stream while the corner rows and
 // the coarse chain run on st (disjoint rows of X5 / X6 / X8, own partial
 // slots).
+// gathered: X5 already holds v = B_s^T p (the CG iteration writes it while
+// updating p)
 template <class T>
-static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false) {
+static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false, bool gathered = false) {
   const int nr = C.nrhs;
   hipStream_t st = C.st;
   void **X = C.X;
-  hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                     C.d_glam, p, (T*)X[5], nr, skip);
+  if (!gathered)
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                       C.d_glam, p, (T*)X[5], nr, skip);
   const bool overlap = C.Kc > 0 && !C.prof;
   if (overlap) fork_side(C);
   symv<T>(C, X[5], X[8], skip, overlap);
@@ -1208,7 +1209,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     HIPCHK(hipMemsetAsync(C.d_cg, 0, sizeof(CgState), st));
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
                        C.d_partial, (const int*)nullptr);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
     HIPCHK(hipMemcpyAsync(C.d_res, C.d_d, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (warm && warm->have > 0) {
       if (C.opt.warm_start == 2 && warm->have >= 2)
@@ -1220,26 +1221,36 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_d, C.d_Fp, C.d_res);
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
                          C.d_partial, (const int*)nullptr);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 3, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 3, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
     } else {
       HIPCHK(hipMemsetAsync(C.d_lam, 0, nl * sizeof(double), st));
     }
     HIPCHK(hipMemcpyAsync(C.d_p, C.d_res, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // v = B_s^T p for the first F application (later ones are written by
+    // k_cg_p_gather)
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                       C.d_glam, (const double*)C.d_p, (T*)X[5], nr, (const int*)nullptr);
     const int* done = &C.d_cg->done;
     int it = 0;
-    const int chk = std::max(1, C.opt.check_every);
+    // an even block of iterations, so that every replay starts on p = d_p
+    const int chk = std::max(2, (C.opt.check_every + 1) / 2 * 2);
     bool converged = false;
     HIPCHK(hipMemcpyAsync(C.h_done, done, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     converged = *C.h_done != 0;
-    // one CG iteration; every kernel returns at once when all RHS converged
-    auto iteration = [&]() {
-      apply_F<T>(C, C.d_p, C.d_Fp, done, true);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+    // CG iteration k (p alternating between d_p and d_p2); every kernel
+    // returns at once when all RHS have converged
+    auto iteration = [&](int k) {
+      double* pc = (k & 1) ? C.d_p2 : C.d_p;
+      double* pn = (k & 1) ? C.d_p : C.d_p2;
+      apply_F<T>(C, pc, C.d_Fp, done, true, true);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
       hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
-                         C.d_p, C.d_Fp, C.d_lam, C.d_res, C.d_partial);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(256), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
-      hipLaunchKernelGGL(k_cg_p, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, C.d_cg, C.d_res, C.d_p);
+                         (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res, C.d_partial);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_p_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                         C.d_glam, nr, (const CgState*)C.d_cg, (const double*)C.d_res, (const double*)pc, pn,
+                         (T*)X[5]);
     };
     // the block of chk iterations is captured once (fixed buffers, fixed
     // arguments) and replayed; needs a capturable (non-default) stream and
@@ -1249,7 +1260,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       if (C.cg_graph) HIPCHK(hipGraphExecDestroy(C.cg_graph));
       C.cg_graph = nullptr;
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-      for (int k = 0; k < chk; ++k) iteration();
+      for (int k = 0; k < chk; ++k) iteration(k);
       hipGraph_t g = nullptr;
       HIPCHK(hipStreamEndCapture(st, &g));
       HIPCHK(hipGraphInstantiate(&C.cg_graph, g, nullptr, nullptr, 0));
@@ -1258,10 +1269,10 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     }
     while (!converged && it < C.opt.cg_max_iter) {
       int todo = std::min(chk, C.opt.cg_max_iter - it);
-      if (graph && todo == chk) {
+      if (graph && todo == chk && (it & 1) == 0) {
         HIPCHK(hipGraphLaunch(C.cg_graph, st));
       } else {
-        for (int k = 0; k < todo; ++k) iteration();
+        for (int k = 0; k < todo; ++k) iteration(it + k);
       }
       it += todo;
       HIPCHK(hipGetLastError());
@@ -1283,10 +1294,12 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       warm->have = std::min(2, warm->have + 1);
     }
     // ---- recovery -------------------------------------------------------------------
-    // [t_l; y] = [Linv_GG; Psi_G] B_s^T lambda
+    // v_l = B_s^T lambda; interface rows of X1: t - t_l = t - Linv_GG v_l (in
+    // place); y = Psi_G v_l on the corner rows of X6
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                        C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, (const int*)nullptr);
-    mv<T>(C, C.trail_N, false, X[5], X[6], nullptr, one);
+    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
+    if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
   } else {
     // no interface: t_l = 0, y = 0
     HIPCHK(hipMemsetAsync(X[6], 0, C.rows_total * nr * sizeof(T), st));
@@ -1298,13 +1311,12 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
                        (const T*)X[1], nr, (const int*)nullptr);
     coarse_solve<T>(C, X[6], X[7], X[5], nullptr);
   }
-  // x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c: input rows t - [0; t_l], corner rows -x_c
-  hipLaunchKernelGGL(k_sub_rows<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_gamma_row,
-                     (const T*)X[1], (const T*)X[6], (T*)X[8], nr);
+  // x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c: X1 holds t - [0; t_l] on
+  // the r rows; its corner rows get -x_c
   if (C.Kc > 0)
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[8], mone, nr, (const int*)nullptr);
-  mv<T>(C, C.full_T, true, X[8], X[5], nullptr, one);
+                       C.d_csccrow, (const T*)X[5], (T*)X[1], mone, nr, (const int*)nullptr);
+  mv<T>(C, C.full_T, true, X[1], X[5], nullptr, one);
   hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
                      (const T*)X[5], x, nr);
   HIPCHK(hipGetLastError());

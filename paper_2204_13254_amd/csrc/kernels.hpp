@@ -1011,16 +1011,6 @@ __global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, co
   x[rows[k] * nrhs + r] = c >= 0 ? scale * z[c * nrhs + r] : (T)0;
 }
 
-// y = a - b on listed rows (t - [0; t_lambda]); rows with flag 0 copy a.
-template <class T>
-__global__ void k_sub_rows(int64_t rows_total, const uint8_t* __restrict__ gamma_row, const T* __restrict__ a,
-                           const T* __restrict__ b, T* __restrict__ y, int nrhs) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows_total * nrhs) return;
-  int64_t row = i / nrhs;
-  y[i] = gamma_row[row] ? a[i] - b[i] : a[i];
-}
-
 // Global FP64 result of unknown d = the owner's copy (dsrc[d] = row).
 template <class T>
 __global__ void k_collect(int64_t nint, const int64_t* __restrict__ dsrc, const T* __restrict__ x,
@@ -1249,8 +1239,11 @@ struct CgState {
 
 // stage: 0 = init (rr = rr0 = sum), 1 = alpha (pFp = sum), 2 = beta (rr_new = sum),
 //        3 = warm start (rr = sum, convergence flags only)
-__global__ void k_cg_scalar(int stage, int nrhs, const double* __restrict__ partial, CgState* __restrict__ st,
-                            double tol) {
+// One workgroup of kScalarThreads threads (the first level of the sum is
+// kDotBlocks / lanes deep; with 1024 threads a short chain of L2 loads).
+constexpr int kScalarThreads = 1024;
+__global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrhs, const double* __restrict__ partial,
+                                                              CgState* __restrict__ st, double tol) {
   if (stage != 0 && st->done) return;
   const int r = threadIdx.x;
   __shared__ int any_active;
@@ -1258,12 +1251,14 @@ __global__ void k_cg_scalar(int stage, int nrhs, const double* __restrict__ part
   __syncthreads();
   // fixed-order two-level sum of the block partials: thread t sums blocks
   // t/nrhs, t/nrhs + L, ... of rhs t%nrhs, then lanes are added in order
-  __shared__ double part[256];
+  __shared__ double part[kScalarThreads];
   {
     const int t = threadIdx.x, lpr = blockDim.x / nrhs, rr = t % nrhs, ln = t / nrhs;
     double a = 0.0;
-    if (ln < lpr)
+    if (ln < lpr) {
+#pragma unroll 4
       for (int b = ln; b < kDotBlocks; b += lpr) a += partial[b * kMaxRhs + rr];
+    }
     part[t] = a;
     __syncthreads();
   }
@@ -1314,18 +1309,6 @@ __global__ void k_cg_scalar(int stage, int nrhs, const double* __restrict__ part
   if (r == 0) st->done = any_active ? 0 : 1;
 }
 
-// lambda += alpha p ; r -= alpha Fp   (alpha = 0 for inactive rhs)
-__global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, const double* __restrict__ p,
-                        const double* __restrict__ Fp, double* __restrict__ lam, double* __restrict__ res) {
-  if (st->done) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * nrhs) return;
-  int r = (int)(i % nrhs);
-  double a = st->alpha[r];
-  lam[i] += a * p[i];
-  res[i] -= a * Fp[i];
-}
-
 // lambda += alpha p ; r -= alpha Fp, fused with the block partials of r . r
 __global__ void __launch_bounds__(256) k_cg_xr_dot(int64_t n, int nrhs, const CgState* __restrict__ st,
                                                    const double* __restrict__ p, const double* __restrict__ Fp,
@@ -1348,14 +1331,28 @@ __global__ void __launch_bounds__(256) k_cg_xr_dot(int64_t n, int nrhs, const Cg
   block_rhs_sum(s, nrhs, lpr, partial);
 }
 
-// p = r + beta p for active rhs
-__global__ void k_cg_p(int64_t n, int nrhs, const CgState* __restrict__ st, const double* __restrict__ res,
-                       double* __restrict__ p) {
+// p' = r + beta p for the RHS still active after the beta stage (p kept
+// otherwise), written to pnext once per multiplier (from its + copy), and the
+// local interface rows v = B_s^T p' for the next F application.  p alternates
+// between two buffers (a multiplier's two copies would race on one).
+template <class T>
+__global__ void k_cg_p_gather(int64_t ngrow, const int64_t* __restrict__ rows, const int32_t* __restrict__ lamcode,
+                              int nrhs, const CgState* __restrict__ st, const double* __restrict__ res,
+                              const double* __restrict__ pcur, double* __restrict__ pnext, T* __restrict__ v) {
   if (st->done) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * nrhs) return;
-  int r = (int)(i % nrhs);
-  if (st->active[r]) p[i] = res[i] + st->beta[r] * p[i];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ngrow * nrhs) return;
+  const int64_t k = i / nrhs;
+  const int r = (int)(i % nrhs);
+  const int32_t c = lamcode[k];
+  T val = (T)0;
+  if (c >= 0) {
+    const int64_t li = (int64_t)(c >> 1) * nrhs + r;
+    const double pn = st->active[r] ? res[li] + st->beta[r] * pcur[li] : pcur[li];
+    if (!(c & 1)) pnext[li] = pn;
+    val = (T)((c & 1) ? -pn : pn);
+  }
+  v[rows[k] * nrhs + r] = val;
 }
 
 __global__ void k_extrap(int64_t n, const double* __restrict__ a, const double* __restrict__ b,

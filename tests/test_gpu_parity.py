@@ -181,10 +181,13 @@ def test_errors_reported():
 
 
 @pytest.mark.parametrize("prec,nrhs,tol", [("fp64", 12, 1e-10), ("fp32_refine", 16, 1e-8),
-                                           ("fp32_refine", 20, 1e-8), ("fp64", 5, 1e-10)])
+                                           ("fp32_refine", 20, 1e-8), ("fp64", 5, 1e-10),
+                                           ("fp64", 32, 1e-10)])
 def test_rhs_block_paths(prec, nrhs, tol):
     """Every right-hand-side block width of the tile products (vector FMA
-    for <= 8, MFMA 16x16x4 for 9..32) on an uneven partition with corners."""
+    for <= 8, MFMA 16x16x4 for 9..32) and of the symmetric interface product
+    (MFMA, one or two 16-wide RHS blocks) on an uneven partition with
+    corners."""
     c, t, p, eps = _case(8, ("rcb", 3, 5), grade=1.5, eps_seed=13)
     dt = 0.04
     o = NewmarkOracle(c, t, eps=eps, dt=dt)
