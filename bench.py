@@ -324,7 +324,7 @@ def main():
         "config": {"workload": w.name, "mesh": f"{w.n}^3 hexahedra x 6 tetrahedra",
                    "unknowns": int(an.n_interior), "subdomains": int(an.n_sub), "nrhs": w.nrhs,
                    "multipliers": int(an.n_lambda), "corners": int(an.n_corner),
-                   "form": "FP32 factors, FP64 CG tol 1e-6 + FP64 refinement to 1e-12, warm start"},
+                   "form": "FP32 factors, FP64 lumped-preconditioned CG tol 1e-6 + FP64 refinement to 1e-12, warm start"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "rhs_steps_per_s": round(sps * w.nrhs, 3),

@@ -70,6 +70,8 @@ typedef struct {
   int check_every;    /* CG iterations between host convergence checks (>= 1; rounded up
                          to an even count, the unit a captured graph replays) */
   void* stream;       /* hipStream_t; NULL = default stream */
+  int precond;        /* interface CG preconditioner: 0 none, 1 lumped (multiplicity-scaled
+                         interface stiffness, sum_s D B_s A_GammaGamma^(s) B_s^T D, D = 1/2) */
 } dd_options;
 
 typedef struct {
@@ -98,7 +100,8 @@ typedef struct {
 } dd_info;
 
 /* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
- * refine_tol 1e-12, refine_max 10, warm_start 1, use_graph 0, check_every 4. */
+ * refine_tol 1e-12, refine_max 10, warm_start 1, use_graph 0, check_every 4,
+ * precond 1. */
 void dd_default_options(dd_options* opt);
 
 /* Build a solver context (host analysis + device upload + element assembly

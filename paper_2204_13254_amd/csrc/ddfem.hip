@@ -190,6 +190,13 @@ struct Ctx {
   Warm warm_fw, warm_adj;
   double* d_partial = nullptr;
   double* d_p2 = nullptr;  // p of odd CG iterations (even ones use d_p)
+  double* d_z = nullptr;   // preconditioned residual
+  double* d_partial2 = nullptr;  // second partial-sum array (r.r next to r.z)
+  // lumped preconditioner K_lam (CSR in multiplier space) and its pull list
+  int64_t lam_nnz = 0;
+  int64_t *d_lrp = nullptr, *d_lgptr = nullptr;
+  int32_t *d_lci = nullptr, *d_lgcon = nullptr;
+  double* d_lvals = nullptr;
   CgState* d_cg = nullptr;
   int* h_done = nullptr;  // pinned
   double* h_partial = nullptr;  // pinned [kDotBlocks * kMaxRhs]
@@ -647,6 +654,51 @@ static void build_device(Ctx& C, const double* coords) {
     }
     C.d_lrow0 = upload(r0, C.owned, st);
     C.d_lrow1 = upload(r1, C.owned, st);
+    // pattern and pull list of the lumped preconditioner K_lam: the tets of
+    // subdomain s couple the multipliers of its interface edges, with the
+    // signs of B_s (+ in the lower subdomain id)
+    {
+      if (P.nt > INT32_MAX / 72) throw DDError{DD_ERR_ARG, "too many tetrahedra for the preconditioner pull list"};
+      std::vector<int32_t> dlam(P.nint, -1);
+      for (int64_t l = 0; l < C.nlam; ++l) dlam[P.lam_dof[l]] = (int32_t)l;
+      std::vector<std::pair<uint64_t, int32_t>> kp;
+      for (int64_t t = 0; t < P.nt; ++t) {
+        const int32_t sub = P.part[t];
+        for (int a = 0; a < 6; ++a) {
+          const int32_t da = P.dof[P.tet_edges[t * 6 + a]];
+          const int32_t la = da >= 0 ? dlam[da] : -1;
+          if (la < 0) continue;
+          const bool na = P.lam_s0[la] != sub;
+          for (int b = 0; b < 6; ++b) {
+            const int32_t db = P.dof[P.tet_edges[t * 6 + b]];
+            const int32_t lb = db >= 0 ? dlam[db] : -1;
+            if (lb < 0) continue;
+            const bool nb = P.lam_s0[lb] != sub;
+            kp.emplace_back((uint64_t)la * (uint64_t)C.nlam + (uint64_t)lb,
+                            (int32_t)(((t * 36 + a * 6 + b) << 1) | (na != nb ? 1 : 0)));
+          }
+        }
+      }
+      std::sort(kp.begin(), kp.end());
+      std::vector<int64_t> lrp(C.nlam + 1, 0), lgptr{0};
+      std::vector<int32_t> lci, lgcon;
+      lgcon.reserve(kp.size());
+      for (size_t i = 0; i < kp.size();) {
+        size_t j = i;
+        while (j < kp.size() && kp[j].first == kp[i].first) lgcon.push_back(kp[j++].second);
+        lrp[(int64_t)(kp[i].first / (uint64_t)C.nlam) + 1]++;
+        lci.push_back((int32_t)(kp[i].first % (uint64_t)C.nlam));
+        lgptr.push_back((int64_t)lgcon.size());
+        i = j;
+      }
+      for (int64_t l = 0; l < C.nlam; ++l) lrp[l + 1] += lrp[l];
+      C.lam_nnz = (int64_t)lci.size();
+      C.d_lrp = upload(lrp, C.owned, st);
+      C.d_lci = upload(lci, C.owned, st);
+      C.d_lgptr = upload(lgptr, C.owned, st);
+      C.d_lgcon = upload(lgcon, C.owned, st);
+      C.d_lvals = dalloc<double>(C.lam_nnz, C.owned);
+    }
     // coarse gather: corner c <- its subdomain corner rows, ascending subdomain
     std::vector<int64_t> cgptr((int64_t)C.Kc * NB + 1, 0), cgrows;
     std::vector<std::vector<int64_t>> byc(nc);
@@ -765,6 +817,8 @@ static void build_device(Ctx& C, const double* coords) {
   C.warm_adj.old = dalloc<double>(nl, C.owned);
   C.d_partial = dalloc<double>(kDotBlocks * kMaxRhs, C.owned);
   C.d_p2 = dalloc<double>(nl, C.owned);
+  C.d_z = dalloc<double>(nl, C.owned);
+  C.d_partial2 = dalloc<double>(kDotBlocks * kMaxRhs, C.owned);
   C.d_cg = dalloc<CgState>(1, C.owned);
   HIPCHK(hipHostMalloc((void**)&C.h_done, sizeof(int) * 4, hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&C.h_partial, sizeof(double) * kDotBlocks * kMaxRhs, hipHostMallocDefault));
@@ -959,6 +1013,9 @@ static int factor_impl(Ctx& C) {
     hipLaunchKernelGGL(k_pad_diag<T>, dim3(nblk(C.n_pad)), dim3(256), 0, st, C.n_pad, C.d_padpos, tiles);
   hipLaunchKernelGGL(k_pull_csr, dim3(nblk(C.nnz)), dim3(256), 0, st, C.nnz, C.d_gptr, C.d_gcon, C.d_Te,
                      C.d_Se, C.d_eps, C.d_vals);
+  if (C.lam_nnz)
+    hipLaunchKernelGGL(k_pull_lam, dim3(nblk(C.lam_nnz)), dim3(256), 0, st, C.lam_nnz, C.d_lgptr, C.d_lgcon,
+                       C.d_Te, C.d_Se, C.d_eps, C.beta * C.dt * C.dt, C.d_lvals);
   HIPCHK(hipGetLastError());
   factor_range<T>(C, 0, C.nsub);
   {
@@ -1209,7 +1266,8 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     HIPCHK(hipMemsetAsync(C.d_cg, 0, sizeof(CgState), st));
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
                        C.d_partial, (const int*)nullptr);
-    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 0, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+    hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 0, nr, (const double*)C.d_partial,
+                       (const double*)nullptr, C.d_cg, C.opt.cg_tol);
     HIPCHK(hipMemcpyAsync(C.d_res, C.d_d, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (warm && warm->have > 0) {
       if (C.opt.warm_start == 2 && warm->have >= 2)
@@ -1221,11 +1279,20 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_d, C.d_Fp, C.d_res);
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
                          C.d_partial, (const int*)nullptr);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 3, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 3, nr, (const double*)C.d_partial,
+                         (const double*)nullptr, C.d_cg, C.opt.cg_tol);
     } else {
       HIPCHK(hipMemsetAsync(C.d_lam, 0, nl * sizeof(double), st));
     }
-    HIPCHK(hipMemcpyAsync(C.d_p, C.d_res, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // p = z = K_lam r (lumped preconditioner), or p = r
+    const bool pre = C.opt.precond == 1 && C.lam_nnz > 0;
+    if (pre) {
+      hipLaunchKernelGGL(k_lam_precond, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrp, C.d_lci, C.d_lvals,
+                         (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, (const int*)nullptr);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 4, nr, (const double*)C.d_partial,
+                         (const double*)nullptr, C.d_cg, C.opt.cg_tol);
+    }
+    HIPCHK(hipMemcpyAsync(C.d_p, pre ? C.d_z : C.d_res, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
     // v = B_s^T p for the first F application (later ones are written by
     // k_cg_p_gather)
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
@@ -1244,13 +1311,24 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       double* pc = (k & 1) ? C.d_p2 : C.d_p;
       double* pn = (k & 1) ? C.d_p : C.d_p2;
       apply_F<T>(C, pc, C.d_Fp, done, true, true);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 1, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
-      hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
-                         (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res, C.d_partial);
-      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, C.d_partial, C.d_cg, C.opt.cg_tol);
+      hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 1, nr, (const double*)C.d_partial,
+                         (const double*)nullptr, C.d_cg, C.opt.cg_tol);
+      if (pre) {
+        hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                           (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
+        hipLaunchKernelGGL(k_lam_precond, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrp, C.d_lci, C.d_lvals,
+                           (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, done);
+        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
+                           (const double*)C.d_partial2, C.d_cg, C.opt.cg_tol);
+      } else {
+        hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                           (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res, C.d_partial);
+        hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
+                           (const double*)C.d_partial, C.d_cg, C.opt.cg_tol);
+      }
       hipLaunchKernelGGL(k_cg_p_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                         C.d_glam, nr, (const CgState*)C.d_cg, (const double*)C.d_res, (const double*)pc, pn,
-                         (T*)X[5]);
+                         C.d_glam, nr, (const CgState*)C.d_cg, (const double*)(pre ? C.d_z : C.d_res),
+                         (const double*)pc, pn, (T*)X[5]);
     };
     // the block of chk iterations is captured once (fixed buffers, fixed
     // arguments) and replayed; needs a capturable (non-default) stream and
@@ -1499,6 +1577,7 @@ void dd_default_options(dd_options* o) {
   o->use_graph = 0;
   o->check_every = 4;
   o->stream = nullptr;
+  o->precond = 1;
 }
 
 const char* dd_last_error(void) { return g_err.c_str(); }
@@ -1523,6 +1602,7 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
   dd_default_options(&o);
   if (opt) o = *opt;
   if (o.nrhs < 1 || o.nrhs > kMaxRhs) throw DDError{DD_ERR_ARG, "nrhs must be in 1..32"};
+  if (o.precond != 0 && o.precond != 1) throw DDError{DD_ERR_ARG, "precond must be 0 or 1"};
   if (o.precision != DD_FP64 && o.precision != DD_FP32_REFINE) throw DDError{DD_ERR_ARG, "unknown precision"};
   if (!(o.cg_tol > 0) || o.cg_max_iter < 1 || o.check_every < 1 || o.refine_max < 0 || !(o.refine_tol > 0))
     throw DDError{DD_ERR_ARG, "bad solver option"};

@@ -169,6 +169,26 @@ __global__ void k_pull_csr(int64_t nnz, const int64_t* __restrict__ ptr, const i
   vals[e] = make_double2(t, s);
 }
 
+// Lumped preconditioner of the interface CG in multiplier space:
+// K_lam = sum_s D B_s A_GG^(s) B_s^T D with D = 1/2 (each multiplier joins two
+// subdomain copies).  Entry (l, l') sums, over the tets of every subdomain s
+// holding both interface edges, 1/4 sign_s(l) sign_s(l') A_e[a][b] with
+// A_e = eps T_e + beta dt^2 S_e; contrib = (t*36 + a*6 + b) << 1 | negative.
+__global__ void k_pull_lam(int64_t nnz, const int64_t* __restrict__ ptr, const int32_t* __restrict__ contrib,
+                           const double* __restrict__ Te, const double* __restrict__ Se,
+                           const double* __restrict__ eps, double bdt2, double* __restrict__ vals) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  double v = 0.0;
+  for (int64_t c = ptr[e]; c < ptr[e + 1]; ++c) {
+    const int32_t code = contrib[c];
+    const int32_t k = code >> 1;
+    const double a = 0.25 * (eps[k / 36] * Te[k] + bdt2 * Se[k]);
+    v += (code & 1) ? -a : a;
+  }
+  vals[e] = v;
+}
+
 // Unit diagonal on padding rows of every tile store (rows that carry no
 // unknown), so padded blocks factor to the identity.
 template <class T>
@@ -1228,6 +1248,7 @@ __global__ void __launch_bounds__(256) k_scatter_dot(int64_t nlam, const int64_t
 
 struct CgState {
   double rr[kMaxRhs];      // current r.r
+  double rz[kMaxRhs];      // current r.z (z = preconditioned r; r.r without a preconditioner)
   double rr0[kMaxRhs];     // d.d (relative tolerance reference)
   double alpha[kMaxRhs];
   double beta[kMaxRhs];
@@ -1237,12 +1258,14 @@ struct CgState {
   int breakdown;
 };
 
-// stage: 0 = init (rr = rr0 = sum), 1 = alpha (pFp = sum), 2 = beta (rr_new = sum),
-//        3 = warm start (rr = sum, convergence flags only)
+// stage: 0 = init (rr = rr0 = rz = sum A), 1 = alpha = rz / (sum A = p.Fp),
+//        2 = beta (sum A = new r.z, sum B = new r.r), 3 = warm start (rr = rz =
+//        sum A, convergence flags only), 4 = preconditioned start (rz = sum A)
 // One workgroup of kScalarThreads threads (the first level of the sum is
 // kDotBlocks / lanes deep; with 1024 threads a short chain of L2 loads).
 constexpr int kScalarThreads = 1024;
 __global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrhs, const double* __restrict__ partial,
+                                                              const double* __restrict__ partial_b,
                                                               CgState* __restrict__ st, double tol) {
   if (stage != 0 && st->done) return;
   const int r = threadIdx.x;
@@ -1252,31 +1275,39 @@ __global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrh
   // fixed-order two-level sum of the block partials: thread t sums blocks
   // t/nrhs, t/nrhs + L, ... of rhs t%nrhs, then lanes are added in order
   __shared__ double part[kScalarThreads];
-  {
+  auto total = [&](const double* pa) -> double {
     const int t = threadIdx.x, lpr = blockDim.x / nrhs, rr = t % nrhs, ln = t / nrhs;
     double a = 0.0;
     if (ln < lpr) {
 #pragma unroll 4
-      for (int b = ln; b < kDotBlocks; b += lpr) a += partial[b * kMaxRhs + rr];
+      for (int b = ln; b < kDotBlocks; b += lpr) a += pa[b * kMaxRhs + rr];
     }
     part[t] = a;
     __syncthreads();
-  }
+    double v = 0.0;
+    if (t < nrhs)
+      for (int l = 0; l < lpr; ++l) v += part[l * nrhs + t];
+    __syncthreads();
+    return v;
+  };
+  const double s = total(partial);
+  const double sb = stage == 2 ? total(partial_b) : 0.0;
   if (r < nrhs) {
-    const int lpr = blockDim.x / nrhs;
-    double s = 0.0;
-    for (int ln = 0; ln < lpr; ++ln) s += part[ln * nrhs + r];
     if (stage == 0) {
       st->rr[r] = s;
       st->rr0[r] = s;
+      st->rz[r] = s;
       st->iters[r] = 0;
       st->active[r] = s > 0.0 ? 1 : 0;
       st->alpha[r] = 0.0;
       st->beta[r] = 0.0;
     } else if (stage == 3) {
       st->rr[r] = s;
+      st->rz[r] = s;
       st->beta[r] = 0.0;
       if (st->active[r] && s <= tol * tol * st->rr0[r]) st->active[r] = 0;
+    } else if (stage == 4) {
+      st->rz[r] = s;
     } else if (stage == 1) {
       if (st->active[r]) {
         if (!(s > 0.0) || !isfinite(s)) {
@@ -1284,7 +1315,7 @@ __global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrh
           st->alpha[r] = 0.0;
           atomicOr(&st->breakdown, 1);
         } else {
-          st->alpha[r] = st->rr[r] / s;
+          st->alpha[r] = st->rz[r] / s;
         }
       } else {
         st->alpha[r] = 0.0;
@@ -1292,9 +1323,10 @@ __global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrh
     } else {
       if (st->active[r]) {
         st->iters[r] += 1;
-        st->beta[r] = s / st->rr[r];
-        st->rr[r] = s;
-        if (!(s <= tol * tol * st->rr0[r])) {
+        st->beta[r] = s / st->rz[r];
+        st->rz[r] = s;
+        st->rr[r] = sb;
+        if (!(sb <= tol * tol * st->rr0[r])) {
           // keep iterating (also on NaN: caught by the caller's cap)
         } else {
           st->active[r] = 0;
@@ -1331,13 +1363,51 @@ __global__ void __launch_bounds__(256) k_cg_xr_dot(int64_t n, int nrhs, const Cg
   block_rhs_sum(s, nrhs, lpr, partial);
 }
 
-// p' = r + beta p for the RHS still active after the beta stage (p kept
-// otherwise), written to pnext once per multiplier (from its + copy), and the
-// local interface rows v = B_s^T p' for the next F application.  p alternates
-// between two buffers (a multiplier's two copies would race on one).
+// lambda += alpha p ; r -= alpha Fp   (alpha = 0 for inactive rhs)
+__global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, const double* __restrict__ p,
+                        const double* __restrict__ Fp, double* __restrict__ lam, double* __restrict__ res) {
+  if (st->done) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const double a = st->alpha[(int)(i % nrhs)];
+  lam[i] += a * p[i];
+  res[i] -= a * Fp[i];
+}
+
+// z = K_lam r (the lumped preconditioner, CSR in multiplier space), fused
+// with the block partials of r.z (partial) and r.r (partial_b).
+__global__ void __launch_bounds__(256) k_lam_precond(int64_t nlam, const int64_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                     const double* __restrict__ res, double* __restrict__ z, int nrhs,
+                                                     double* __restrict__ partial, double* __restrict__ partial_b,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int lpr = 256 / nrhs;
+  const int tid = threadIdx.x, r = tid % nrhs, lane = tid / nrhs;
+  double sz = 0.0, sr = 0.0;
+  if (lane < lpr) {
+    for (int64_t l = (int64_t)blockIdx.x * lpr + lane; l < nlam; l += (int64_t)gridDim.x * lpr) {
+      double acc = 0.0;
+      for (int64_t k = rp[l]; k < rp[l + 1]; ++k) acc += val[k] * res[(int64_t)ci[k] * nrhs + r];
+      const double rv = res[l * nrhs + r];
+      z[l * nrhs + r] = acc;
+      sz += rv * acc;
+      sr += rv * rv;
+    }
+  }
+  block_rhs_sum(sz, nrhs, lpr, partial);
+  __syncthreads();
+  block_rhs_sum(sr, nrhs, lpr, partial_b);
+}
+
+// p' = base + beta p for the RHS still active after the beta stage (p kept
+// otherwise; base = z, or r without a preconditioner), written to pnext once
+// per multiplier (from its + copy), and the local interface rows
+// v = B_s^T p' for the next F application.  p alternates between two buffers
+// (a multiplier's two copies would race on one).
 template <class T>
 __global__ void k_cg_p_gather(int64_t ngrow, const int64_t* __restrict__ rows, const int32_t* __restrict__ lamcode,
-                              int nrhs, const CgState* __restrict__ st, const double* __restrict__ res,
+                              int nrhs, const CgState* __restrict__ st, const double* __restrict__ base,
                               const double* __restrict__ pcur, double* __restrict__ pnext, T* __restrict__ v) {
   if (st->done) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1348,7 +1418,7 @@ __global__ void k_cg_p_gather(int64_t ngrow, const int64_t* __restrict__ rows, c
   T val = (T)0;
   if (c >= 0) {
     const int64_t li = (int64_t)(c >> 1) * nrhs + r;
-    const double pn = st->active[r] ? res[li] + st->beta[r] * pcur[li] : pcur[li];
+    const double pn = st->active[r] ? base[li] + st->beta[r] * pcur[li] : pcur[li];
     if (!(c & 1)) pnext[li] = pn;
     val = (T)((c & 1) ? -pn : pn);
   }

@@ -57,7 +57,7 @@ class DDSolver:
     def __init__(self, coords, tets, partition, eps, mu=None, dt=0.05, beta=0.25, *,
                  precision="fp64", nrhs=1, cg_tol=1e-10, cg_max_iter=500, refine_tol=1e-12,
                  refine_max=10, warm_start=True, check_every=4, stream=None, factor=True,
-                 use_graph=False):
+                 use_graph=False, precond=1):
         self.lib = load()
         o = Options()
         self.lib.dd_default_options(C.byref(o))
@@ -70,6 +70,7 @@ class DDSolver:
         o.warm_start = int(warm_start)
         o.check_every = int(check_every)
         o.use_graph = int(bool(use_graph))
+        o.precond = int(precond)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -200,6 +200,28 @@ def test_rhs_block_paths(prec, nrhs, tol):
     assert err.max() <= tol
 
 
+@pytest.mark.parametrize("prec,nrhs,tol", [("fp64", 1, 1e-10), ("fp32_refine", 16, 1e-8)])
+def test_preconditioner_on_off(prec, nrhs, tol):
+    """The interface CG with and without the lumped preconditioner reaches
+    the oracle's fields at every step; the preconditioned one in fewer
+    iterations."""
+    c, t, p, eps = _case(8, ("rcb", 3, 5), grade=1.5, eps_seed=13)
+    dt = 0.04
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, 4, dt, 0.08, 0.03, seed=37, nrhs=nrhs)
+    Eo = o.run(J)
+    its = {}
+    for pc in (0, 1):
+        s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, precision=prec,
+                    cg_tol=1e-12 if prec == "fp64" else 1e-6, precond=pc)
+        E, iters = _run_dd(s, J)
+        err = relerr(E[1:], Eo[1:])
+        print(prec, "precond", pc, "max rel err", err.max(), "iterations", iters, flush=True)
+        assert err.max() <= tol
+        its[pc] = sum(sum(x) if isinstance(x, (list, tuple)) else x for x in iters)
+    assert its[1] < its[0]
+
+
 def test_graph_replay_matches_eager():
     """The CG iteration blocks replayed from a captured HIP graph (on a
     non-default stream, with the eager pre-solve / recovery / refinement work
