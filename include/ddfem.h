@@ -91,7 +91,7 @@ typedef struct {
                               with the corner rows Psi_Gamma (pre-solve and
                               recovery), unpadded */
   int64_t schur_bytes;     /* bytes of the interface blocks of the local inverses,
-                              M = (K_rr^-1)_GammaGamma stored square (read once
+                              M = (K_rr^-1)_GammaGamma, packed lower triangle (read once
                               per CG iteration), unpadded */
   int64_t corner_bytes;    /* bytes of the corner rows Psi_Gamma (read twice per
                               CG iteration), unpadded */
@@ -100,7 +100,7 @@ typedef struct {
 } dd_info;
 
 /* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
- * refine_tol 1e-12, refine_max 10, warm_start 1, use_graph 0, check_every 4,
+ * refine_tol 1e-12, refine_max 10, warm_start 0, use_graph 0, check_every 4,
  * precond 1. */
 void dd_default_options(dd_options* opt);
 

@@ -165,7 +165,8 @@ struct Ctx {
   double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
-  // trail_*: interface block with Psi_Gamma; co_*: coarse inverse factor
+  // trail_N: interface rows of Linv_GG (recovery); trail_T: Linv_GG^T with
+  // Psi_Gamma^T (pre-solve); co_*: coarse inverse factor
   // corner_N / corner_T: Psi_Gamma u on the corner rows / Psi_Gamma^T z
   // onto the interface rows
   Items full_N, full_T, trail_N, trail_T, co_N, co_T, corner_N, corner_T;
@@ -1576,7 +1577,7 @@ void dd_default_options(dd_options* o) {
   o->cg_max_iter = 500;
   o->refine_tol = 1e-12;
   o->refine_max = 10;
-  o->warm_start = 1;
+  o->warm_start = 0;  // with the preconditioner a warm start saves no iteration
   o->use_graph = 0;
   o->check_every = 4;
   o->stream = nullptr;

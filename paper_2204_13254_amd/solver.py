@@ -56,7 +56,7 @@ class DDSolver:
 
     def __init__(self, coords, tets, partition, eps, mu=None, dt=0.05, beta=0.25, *,
                  precision="fp64", nrhs=1, cg_tol=1e-10, cg_max_iter=500, refine_tol=1e-12,
-                 refine_max=10, warm_start=True, check_every=4, stream=None, factor=True,
+                 refine_max=10, warm_start=0, check_every=4, stream=None, factor=True,
                  use_graph=False, precond=1):
         self.lib = load()
         o = Options()
