@@ -16,7 +16,11 @@ monolithic solve):
     edge-only wave equation, each step solved with a sparse direct
     factorisation (SuperLU through scipy, a library primitive) (newmark.py);
   * the discrete Gauss law, the discrete energy and the reverse-mode adjoint
-    of the recurrence (newmark.py).
+    of the recurrence (newmark.py);
+  * the particle steps around the solve (Sec. II-A): point location, the
+    exact current mapping of straight paths onto the edges, Whitney
+    interpolation of E and B at points, Faraday's per-tetrahedron update of
+    B and the Adams-Bashforth push (pic.py).
 
 Parity status: every function here is pinned by a test that does not
 re-use its own formula (see tests/test_oracle_*.py).

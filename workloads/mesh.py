@@ -82,3 +82,16 @@ def boundary_edge_mask(coords: np.ndarray, edges: np.ndarray):
         for val in (0.0, 1.0):
             on |= (a[:, ax] == val) & (b[:, ax] == val)
     return on
+
+
+def jittered_cube_mesh(n: int, amp: float, seed: int):
+    """cube_mesh(n) with every vertex strictly inside the cube moved by a
+    seeded uniform offset in [-amp/n, amp/n]^3 (boundary vertices stay, so
+    the outer surface is still the unit cube).  amp <= 0.2 keeps every
+    tetrahedron positively oriented."""
+    coords, tets, hx = cube_mesh(n)
+    rng = np.random.default_rng(seed)
+    inner = np.all((coords > 0.0) & (coords < 1.0), axis=1)
+    coords = coords.copy()
+    coords[inner] += rng.uniform(-amp / n, amp / n, size=(int(inner.sum()), 3))
+    return coords, tets, hx
