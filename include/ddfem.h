@@ -177,6 +177,54 @@ int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res);
  * per RHS (host out [nrhs]); synchronises. */
 int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out);
 
+/* ---- particle steps around the field solve (Sec. II-A) ------------------
+ * Particles are delta shapes: charge measured by the vertex hat functions,
+ * current by the Whitney edge functions.  All pointers are device pointers;
+ * positions and velocities are [n][3] float64 row-major; cell[p] is a
+ * tetrahedron index in the dd_setup order, or -1 for an inactive particle.
+ * Mesh tables for these calls (face neighbours, per-tetrahedron geometry)
+ * are built on the first call (allocates and synchronises once).  Each call
+ * synchronises the context stream to read its counters. */
+
+/* Point location.  On entry cell[p] names a start tetrahedron (-1 or out of
+ * range: tetrahedron 0); on return the tetrahedron holding x[p], found by
+ * walking the straight line from the start cell's centroid across shared
+ * faces, or -1 if that line leaves the mesh (x outside it, or a non-convex
+ * mesh in the way).  *n_outside (may be NULL) = number of such points. */
+int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell, int64_t* n_outside);
+
+/* Exact current mapping of the straight paths xa[p] -> xb[p] (Sec. II-A):
+ *   J[e] += (q[p] / dt) * int_{xa_p}^{xb_p} W_e . dl
+ * J is one right-hand side's row [n_edges] (canonical edges; entries of
+ * conductor edges are written too and ignored by the solve).  cell[p] must
+ * hold xa[p] on entry; on return it holds xb[p].  A path that reaches the
+ * outer boundary deposits up to it and the particle becomes inactive
+ * (cell = -1; counted in *n_absorbed, may be NULL): on a conductor wall the
+ * interior Gauss law stays exact.  Inactive particles are skipped.  The
+ * summation order over particles is not fixed (device atomics), so J is
+ * reproducible to rounding, not bit for bit.  DD_ERR_ARG if a cell index is
+ * out of range or a path crosses more than 65536 faces (both made
+ * inactive). */
+int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, const double* q,
+                   int32_t* cell, double* J, int64_t* n_absorbed);
+
+/* Faraday's law on the face 2-form of B, kept as its constant value in each
+ * tetrahedron: B[t] += alpha * curl(E)|_t with curl W_ij = 2 g_i x g_j
+ * (alpha = -dt for one step).  E: one row [n_edges]; B: [n_tets][3]. */
+int dd_pic_faraday(void* ctx, const double* E, double alpha, double* B);
+
+/* Field interpolation at x[p] in cell[p] (E = sum_e E[e] W_e, B = B[cell])
+ * and one Adams-Bashforth step of x' = v, v' = qm (E + v x B), qm [n] the
+ * charge-to-mass ratios, dt the context's step:
+ *   first != 0: x_new = x + dt v,  v += dt acc   (start step)
+ *   otherwise:  x_new = x + dt (3/2 v - 1/2 v_prev),  v += dt (3/2 acc - 1/2 acc_prev)
+ * hist [n][6] = (v_prev, acc_prev) is overwritten with (v, acc).  x_new must
+ * not overlap x.  Inactive particles keep x (copied to x_new) and v.
+ * DD_ERR_ARG if a cell index is out of range. */
+int dd_pic_push(void* ctx, int64_t n, const double* qm, const double* E, const double* B,
+                const int32_t* cell, const double* x, double* x_new, double* v, double* hist,
+                int first);
+
 /* Per-class timing of the batched tile products, measured with HIP events
  * recorded on the context's stream around each launch (adds two event
  * records per launch while enabled).  Classes: */

@@ -63,6 +63,10 @@ SIGNATURES = {
     "dd_gauss_residual": (C.c_int, [P, P, P, P]),
     "dd_energy": (C.c_int, [P, P, P, P]),
     "dd_profile": (C.c_int, [P, C.c_int, P, P]),
+    "dd_pic_locate": (C.c_int, [P, I64, P, P, P]),
+    "dd_pic_deposit": (C.c_int, [P, I64, P, P, P, P, P, P]),
+    "dd_pic_faraday": (C.c_int, [P, P, D, P]),
+    "dd_pic_push": (C.c_int, [P, I64, P, P, P, P, P, P, P, P, C.c_int]),
     "dd_destroy": (None, [P]),
     "dd_last_error": (C.c_char_p, []),
     "dd_analyze": (C.c_int, [I64, P, I64, P, P, C.POINTER(Analysis), P]),

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddfem.so")
 SOURCES = [os.path.join(HERE, "csrc", "ddfem.hip"), os.path.join(HERE, "csrc", "plan.cpp")]
-HEADERS = [os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(HERE, "csrc", "plan.hpp"),
+HEADERS = [os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(HERE, "csrc", "pic.hpp"),
+           os.path.join(HERE, "csrc", "plan.hpp"),
            os.path.join(ROOT, "include", "ddfem.h")]
 
 FLAGS = [

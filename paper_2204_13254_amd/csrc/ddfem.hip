@@ -29,6 +29,7 @@
 
 #include "ddfem.h"
 #include "kernels.hpp"
+#include "pic.hpp"
 #include "plan.hpp"
 
 namespace ddfem {
@@ -133,6 +134,11 @@ struct Ctx {
   void* d_scratch = nullptr;
   int64_t* d_scratch_off = nullptr;
   int* d_err = nullptr;
+  // particle steps: per-tetrahedron geometry, face neighbours, edges, and
+  // the counters of one launch (built on the first particle call)
+  double* d_pic_geo = nullptr;
+  int32_t *d_pic_nbr = nullptr, *d_pic_tedge = nullptr;
+  unsigned long long* d_pic_cnt = nullptr;
   // local assembly pull
   int64_t n_lent = 0;
   int64_t *d_lptr = nullptr, *d_ldest = nullptr;
@@ -1878,6 +1884,122 @@ int dd_profile(void* ctx, int enable, double* ms, int64_t* launches) {
       C.prof_n[i] = 0;
     }
   }
+  return DD_OK;
+  API_END
+}
+
+// ---- particle steps (Sec. II-A) --------------------------------------------------
+static void pic_prepare(Ctx& C) {
+  if (C.d_pic_geo) return;
+  const Plan& P = C.P;
+  std::vector<int32_t> nbr;
+  std::string msg;
+  if (face_neighbors(P, nbr, msg) != 0) throw DDError{DD_ERR_MESH, msg};
+  C.d_pic_nbr = upload(nbr, C.owned, C.st);
+  C.d_pic_tedge = upload(P.tet_edges, C.owned, C.st);
+  C.d_pic_cnt = dalloc<unsigned long long>(kPicCounters, C.owned);
+  double* geo = dalloc<double>((size_t)P.nt * 12, C.owned);
+  hipLaunchKernelGGL(k_tet_geo, dim3(nblk(P.nt)), dim3(256), 0, C.st, (int64_t)P.nt, C.d_coords, C.d_tsort, geo);
+  HIPCHK(hipGetLastError());
+  C.d_pic_geo = geo;
+}
+
+static void pic_counters(Ctx& C, unsigned long long* out) {
+  HIPCHK(hipMemcpyAsync(out, C.d_pic_cnt, kPicCounters * sizeof(unsigned long long), hipMemcpyDeviceToHost, C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+}
+
+static void pic_zero_counters(Ctx& C) {
+  HIPCHK(hipMemsetAsync(C.d_pic_cnt, 0, kPicCounters * sizeof(unsigned long long), C.st));
+}
+
+int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell, int64_t* n_outside) {
+  if (!ctx || n < 0 || (n > 0 && (!x || !cell))) {
+    g_err = "null argument or negative count";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  pic_zero_counters(C);
+  if (n > 0)
+    hipLaunchKernelGGL(k_pic_walk<false>, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, (const double*)nullptr,
+                       x, (const double*)nullptr, 0.0, cell, (const double*)C.d_pic_geo,
+                       (const int32_t*)C.d_pic_nbr, (const int32_t*)C.d_pic_tedge, (const double*)C.d_coords,
+                       (const int32_t*)C.d_tsort, (double*)nullptr, kPicMaxCross, C.d_pic_cnt);
+  HIPCHK(hipGetLastError());
+  unsigned long long c[kPicCounters];
+  pic_counters(C, c);
+  if (n_outside) *n_outside = (int64_t)(c[kPicLeftMesh] + c[kPicWalkCap]);
+  return DD_OK;
+  API_END
+}
+
+int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, const double* q, int32_t* cell,
+                   double* J, int64_t* n_absorbed) {
+  if (!ctx || n < 0 || !J || (n > 0 && (!xa || !xb || !q || !cell))) {
+    g_err = "null argument or negative count";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  pic_zero_counters(C);
+  if (n > 0)
+    hipLaunchKernelGGL(k_pic_walk<true>, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, xa, xb, q,
+                       1.0 / C.dt, cell, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_nbr,
+                       (const int32_t*)C.d_pic_tedge, (const double*)C.d_coords, (const int32_t*)C.d_tsort, J,
+                       kPicMaxCross, C.d_pic_cnt);
+  HIPCHK(hipGetLastError());
+  unsigned long long c[kPicCounters];
+  pic_counters(C, c);
+  if (n_absorbed) *n_absorbed = (int64_t)c[kPicLeftMesh];
+  if (c[kPicBadCell] || c[kPicWalkCap])
+    throw DDError{DD_ERR_ARG, std::to_string(c[kPicBadCell]) + " particles with a cell index out of range, " +
+                                  std::to_string(c[kPicWalkCap]) + " paths crossing more than " +
+                                  std::to_string(kPicMaxCross) + " faces (those are now inactive)"};
+  return DD_OK;
+  API_END
+}
+
+int dd_pic_faraday(void* ctx, const double* E, double alpha, double* B) {
+  if (!ctx || !E || !B) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  hipLaunchKernelGGL(k_pic_faraday, dim3(nblk(C.P.nt)), dim3(256), 0, C.st, (int64_t)C.P.nt, E, alpha,
+                     (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_tedge, B);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
+  API_END
+}
+
+int dd_pic_push(void* ctx, int64_t n, const double* qm, const double* E, const double* B, const int32_t* cell,
+                const double* x, double* x_new, double* v, double* hist, int first) {
+  if (!ctx || n < 0 || (n > 0 && (!qm || !E || !B || !cell || !x || !x_new || !v || !hist))) {
+    g_err = "null argument or negative count";
+    return DD_ERR_ARG;
+  }
+  if (n > 0 && x_new == x) {
+    g_err = "x_new must not be x";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  pic_zero_counters(C);
+  if (n > 0)
+    hipLaunchKernelGGL(k_pic_push, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, qm, E, B, cell, x, x_new,
+                       v, hist, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_tedge, C.dt, first ? 1 : 0,
+                       C.d_pic_cnt);
+  HIPCHK(hipGetLastError());
+  unsigned long long c[kPicCounters];
+  pic_counters(C, c);
+  if (c[kPicBadCell])
+    throw DDError{DD_ERR_ARG, std::to_string(c[kPicBadCell]) + " particles with a cell index out of range"};
   return DD_OK;
   API_END
 }

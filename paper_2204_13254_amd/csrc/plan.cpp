@@ -402,4 +402,43 @@ int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets
   return DD_OK;
 }
 
+int face_neighbors(const Plan& P, std::vector<int32_t>& nbr, std::string& msg) {
+  struct Face {
+    int32_t a, b, c;  // vertices ascending
+    int32_t slot;     // 4t + opposite local vertex
+  };
+  const int64_t nt = P.nt;
+  std::vector<Face> f((size_t)nt * 4);
+  for (int64_t t = 0; t < nt; ++t) {
+    const int32_t* v = &P.tsort[t * 4];
+    for (int k = 0; k < 4; ++k) {
+      int32_t w[3], m = 0;
+      for (int i = 0; i < 4; ++i)
+        if (i != k) w[m++] = v[i];
+      f[t * 4 + k] = Face{w[0], w[1], w[2], (int32_t)(t * 4 + k)};
+    }
+  }
+  std::sort(f.begin(), f.end(), [](const Face& x, const Face& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.c != y.c) return x.c < y.c;
+    return x.slot < y.slot;
+  });
+  nbr.assign((size_t)nt * 4, -1);
+  for (size_t i = 0; i < f.size();) {
+    size_t j = i;
+    while (j < f.size() && f[j].a == f[i].a && f[j].b == f[i].b && f[j].c == f[i].c) ++j;
+    if (j - i > 2) {
+      msg = "a face is shared by more than two tetrahedra";
+      return DD_ERR_MESH;
+    }
+    if (j - i == 2) {
+      nbr[f[i].slot] = f[i + 1].slot / 4;
+      nbr[f[i + 1].slot] = f[i].slot / 4;
+    }
+    i = j;
+  }
+  return 0;
+}
+
 }  // namespace ddfem

@@ -61,6 +61,11 @@ struct Plan {
   }
 };
 
+// Face neighbours of the sorted tetrahedra: nbr[4t + k] is the tetrahedron
+// that shares the face opposite local vertex k of t, or -1 on the outer
+// boundary.  Returns 0 or DD_ERR_MESH (a face shared by more than two).
+int face_neighbors(const Plan& P, std::vector<int32_t>& nbr, std::string& msg);
+
 // Returns 0 or a dd_status; msg receives the error text.
 int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets,
                const int32_t* partition, Plan& plan, std::string& msg);

@@ -22,6 +22,12 @@ def _dev(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
+def _dev_i32(t: torch.Tensor):
+    if t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
+        raise ValueError("expected a contiguous int32 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
 def analyze(coords, tets, partition):
     """Host-only partition analysis: (Analysis, per_sub [n_sub, 3])."""
     lib = load()
@@ -170,6 +176,63 @@ class DDSolver:
         out = np.zeros(self.nrhs)
         check(self.lib.dd_energy(self.h, _dev(E_next), _dev(E_n), out.ctypes.data_as(C.c_void_p)))
         return out
+
+    # ---- particle steps (dd_pic_*): device tensors, positions [n, 3] ----------
+    @staticmethod
+    def _pts(x, n=None):
+        if x.dim() != 2 or x.shape[1] != 3 or (n is not None and x.shape[0] != n):
+            raise ValueError("expected positions / velocities of shape [n, 3]")
+        return x.shape[0]
+
+    @staticmethod
+    def _len(t, n, name):
+        if t.numel() != n:
+            raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+
+    def pic_locate(self, x, cell=None):
+        """Containing tetrahedron of each point (walk from cell, default 0);
+        returns (cell int32 [n], number of points outside the mesh)."""
+        n = self._pts(x)
+        if cell is None:
+            cell = torch.zeros(n, dtype=torch.int32, device=x.device)
+        self._len(cell, n, "cell")
+        out = C.c_int64(0)
+        check(self.lib.dd_pic_locate(self.h, n, _dev(x), _dev_i32(cell), C.byref(out)))
+        return cell, out.value
+
+    def pic_deposit(self, xa, xb, q, cell, J):
+        """J += exact edge currents of the paths xa -> xb (J: one row
+        [n_edges]); cell is advanced to the end points.  Returns the number of
+        particles absorbed at the outer boundary."""
+        n = self._pts(xa)
+        self._pts(xb, n)
+        self._len(q, n, "q")
+        self._len(cell, n, "cell")
+        self._len(J, self.n_edges, "J")
+        out = C.c_int64(0)
+        check(self.lib.dd_pic_deposit(self.h, xa.shape[0], _dev(xa), _dev(xb), _dev(q), _dev_i32(cell),
+                                      _dev(J), C.byref(out)))
+        return out.value
+
+    def pic_faraday(self, E, alpha, B):
+        """B += alpha * curl E per tetrahedron (E one row [n_edges], B [n_tets, 3])."""
+        self._len(E, self.n_edges, "E")
+        self._len(B, 3 * self.n_tets, "B")
+        check(self.lib.dd_pic_faraday(self.h, _dev(E), float(alpha), _dev(B)))
+
+    def pic_push(self, qm, E, B, cell, x, x_new, v, hist, first):
+        """Interpolate E, B at x and take one Adams-Bashforth step (x_new, v,
+        hist updated in place)."""
+        n = self._pts(x)
+        self._pts(x_new, n)
+        self._pts(v, n)
+        self._len(qm, n, "qm")
+        self._len(cell, n, "cell")
+        self._len(hist, 6 * n, "hist")
+        self._len(E, self.n_edges, "E")
+        self._len(B, 3 * self.n_tets, "B")
+        check(self.lib.dd_pic_push(self.h, x.shape[0], _dev(qm), _dev(E), _dev(B), _dev_i32(cell), _dev(x),
+                                   _dev(x_new), _dev(v), _dev(hist), 1 if first else 0))
 
     PROF_CLASSES = ("trailing", "full", "schur", "coarse", "corner")
 
