@@ -122,6 +122,100 @@ def _traffic_from_profiles(cls):
     return None if v is None else v.get("bytes_per_launch")
 
 
+def pic_leg(s, w, E, steps, dev, log, sort_every=10):
+    """Particle steps on the workload's beam (Sec. II-A): per RHS, Whitney
+    interpolation + Adams-Bashforth push, exact current deposit of the
+    x^n -> x^{n+1} paths and Faraday's update of the per-tetrahedron B;
+    every sort_every steps the particles are put back in cell order.  Times
+    each kernel class with events on the solver's stream."""
+    import numpy as np
+    import torch
+    from workloads.beam import BeamSampler
+    b = w.extra["beam"]
+    nr = w.nrhs
+    P = []          # per RHS: dict of particle arrays
+    for r in range(nr):
+        bs = BeamSampler(w.n, b["particles"], b["radius"], b["vth"], b["vz"], b["q0"], b["seed"] + r)
+        d = {"x": torch.tensor(bs.positions(0.0), device=dev), "v": torch.tensor(bs.v, device=dev),
+             "q": torch.tensor(bs.q, device=dev)}
+        d["qm"] = torch.sign(d["q"]).contiguous()
+        n = d["x"].shape[0]
+        d["hist"] = torch.zeros((n, 6), dtype=torch.float64, device=dev)
+        d["cell"] = s.pic_locate(d["x"])
+        P.append(d)
+    st = s.pic_status()
+    assert not any(st.values()), st
+    keys = ("x", "v", "q", "qm", "hist", "cell")
+    spare = [{k: torch.empty_like(P[r][k]) for k in keys} for r in range(nr)]
+    xn = [torch.empty_like(P[r]["x"]) for r in range(nr)]
+    B = torch.zeros((nr, s.n_tets, 3), dtype=torch.float64, device=dev)
+    J = torch.zeros((nr, s.n_edges), dtype=torch.float64, device=dev)
+    ev = {k: [torch.cuda.Event(enable_timing=True) for _ in range(2 * nr)]
+          for k in ("sort", "push", "deposit", "faraday")}
+    ms = {k: 0.0 for k in ev}
+
+    def reorder(r):
+        perm = s.pic_sort(P[r]["cell"])
+        for k in keys:
+            s.pic_permute(perm, P[r][k], spare[r][k])
+            P[r][k], spare[r][k] = spare[r][k], P[r][k]
+
+    def one(k, timed):
+        J.zero_()
+        sorted_now = k % sort_every == 0
+        for r in range(nr):
+            d = P[r]
+            if sorted_now:
+                e = ev["sort"][2 * r], ev["sort"][2 * r + 1]
+                e[0].record(); reorder(r); e[1].record()
+            e = ev["push"][2 * r], ev["push"][2 * r + 1]
+            e[0].record()
+            s.pic_push(d["qm"], E[r], B[r], d["cell"], d["x"], xn[r], d["v"], d["hist"], k == 0)
+            e[1].record()
+            e = ev["deposit"][2 * r], ev["deposit"][2 * r + 1]
+            e[0].record(); s.pic_deposit(d["x"], xn[r], d["q"], d["cell"], J[r]); e[1].record()
+            e = ev["faraday"][2 * r], ev["faraday"][2 * r + 1]
+            e[0].record(); s.pic_faraday(E[r], -w.dt, B[r]); e[1].record()
+            d["x"], xn[r] = xn[r], d["x"]
+        torch.cuda.synchronize()
+        if timed:
+            for key in ms:
+                if key != "sort" or sorted_now:
+                    ms[key] += sum(ev[key][2 * r].elapsed_time(ev[key][2 * r + 1]) for r in range(nr))
+
+    one(0, False)
+    s.pic_status()                     # reset the counters (synchronises)
+    t0 = time.perf_counter()
+    for k in range(1, 1 + steps):
+        one(k, True)
+    t = time.perf_counter() - t0
+    st = s.pic_status()
+    assert st["walk_cap"] == 0 and st["bad_index"] == 0, st
+    active = sum(int((P[r]["cell"] >= 0).sum().item()) for r in range(nr))
+    npart = sum(P[r]["x"].shape[0] for r in range(nr))
+    # compulsory bytes per particle: push reads x, v, hist, qm, cell and writes
+    # x_new, v, hist; deposit reads both positions, q and the cell and writes
+    # the cell, plus one read + write of every J row; Faraday reads E and B
+    # and writes B once per tetrahedron; ordering reads the cells twice and
+    # writes the permutation, then reads and writes 116 bytes per particle
+    byt = {"push": npart * (24 + 24 + 48 + 8 + 4 + 24 + 24 + 48),
+           "deposit": npart * (24 + 24 + 8 + 4 + 4) + nr * s.n_edges * 16,
+           "faraday": nr * s.n_tets * (48 + 24 + 24),
+           "sort": npart * (4 + 4 + 4 + 2 * 116) * (steps // sort_every)}
+    res = {"particles": npart, "active_at_end": active, "absorbed_in_timed_steps": st["absorbed_or_outside"],
+           "steps_timed": steps, "sort_every": sort_every,
+           "ms_per_step": round(1e3 * t / steps, 3),
+           "particle_steps_per_s": round(npart * steps / t, 1)}
+    for key in ms:
+        avg = ms[key] / steps          # per step, summed over the RHS
+        gbs = byt[key] / steps / (avg * 1e-3) / 1e9 if key == "sort" and avg > 0 else (
+            byt[key] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0)
+        res[key] = {"ms_per_step": round(avg, 3), "GBps_compulsory": round(gbs, 1),
+                    "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    log(f"pic: {res}")
+    return res
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -148,6 +242,9 @@ def main():
     ap.add_argument("--graph", type=int, default=1,
                     help="replay CG iteration blocks from captured HIP graphs in the timed steps "
                          "(per-class event timing is then taken on extra eager steps)")
+    ap.add_argument("--pic-steps", type=int, default=10,
+                    help="time this many particle steps (push, exact deposit, Faraday update for every "
+                         "RHS) on the beam particles of the workload; 0 skips them")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB elementwise copy (read + write of known size) for "
                          "scaling hardware traffic counters")
@@ -276,6 +373,10 @@ def main():
     # summaries, valid only for the kernel source they were taken on
     roof["traffic"] = _traffic_from_profiles(dom)
 
+    pic = None
+    if args.pic_steps > 0 and w.extra.get("source") == "beam":
+        pic = pic_leg(s, w, ring[1], args.pic_steps, dev, log)
+
     if args.calib_copy:
         x = torch.ones(64 << 20, dtype=torch.float64, device=dev)
         y = torch.empty_like(x)
@@ -335,6 +436,7 @@ def main():
         "factor_s": round(t_factor, 3), "setup_s": round(t_setup, 2),
         "kernel_classes": other,
         "plain_fp64": plain,
+        "pic": pic,
         "speedup_vs_plain_fp64": (round(sps / plain["steps_per_s"], 2) if plain else None),
     }
     print(json.dumps(out))

@@ -183,15 +183,27 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out);
  * positions and velocities are [n][3] float64 row-major; cell[p] is a
  * tetrahedron index in the dd_setup order, or -1 for an inactive particle.
  * Mesh tables for these calls (face neighbours, per-tetrahedron geometry)
- * are built on the first call (allocates and synchronises once).  Each call
- * synchronises the context stream to read its counters. */
+ * are built on the first call (allocates and synchronises once).  After
+ * that the particle calls only enqueue work on the context stream: what
+ * they find (absorbed particles, bad indices) goes to device counters that
+ * dd_pic_status reads. */
+
+/* Counters of the particle calls since the last reset:
+ *   counts[0]  particles absorbed at the outer boundary (deposit) and
+ *              points found outside the mesh (locate)
+ *   counts[1]  walks stopped after 65536 faces (particle made inactive)
+ *   counts[2]  cell or permutation indices out of range (made inactive /
+ *              item left unwritten)
+ * counts: host [3] or NULL.  Synchronises the stream; reset != 0 zeroes the
+ * counters afterwards. */
+int dd_pic_status(void* ctx, int64_t* counts, int reset);
 
 /* Point location.  On entry cell[p] names a start tetrahedron (-1 or out of
  * range: tetrahedron 0); on return the tetrahedron holding x[p], found by
  * walking the straight line from the start cell's centroid across shared
  * faces, or -1 if that line leaves the mesh (x outside it, or a non-convex
- * mesh in the way).  *n_outside (may be NULL) = number of such points. */
-int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell, int64_t* n_outside);
+ * mesh in the way; counted in counts[0]). */
+int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell);
 
 /* Exact current mapping of the straight paths xa[p] -> xb[p] (Sec. II-A):
  *   J[e] += (q[p] / dt) * int_{xa_p}^{xb_p} W_e . dl
@@ -199,14 +211,30 @@ int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell, int64_t*
  * conductor edges are written too and ignored by the solve).  cell[p] must
  * hold xa[p] on entry; on return it holds xb[p].  A path that reaches the
  * outer boundary deposits up to it and the particle becomes inactive
- * (cell = -1; counted in *n_absorbed, may be NULL): on a conductor wall the
- * interior Gauss law stays exact.  Inactive particles are skipped.  The
- * summation order over particles is not fixed (device atomics), so J is
- * reproducible to rounding, not bit for bit.  DD_ERR_ARG if a cell index is
- * out of range or a path crosses more than 65536 faces (both made
- * inactive). */
+ * (cell = -1, counts[0]): on a conductor wall the interior Gauss law stays
+ * exact.  Inactive particles are skipped.  The summation order over
+ * particles is not fixed (device atomics), so J is reproducible to rounding,
+ * not bit for bit.  A cell index out of range (counts[2]) or a path crossing
+ * more than 65536 faces (counts[1]) makes the particle inactive. */
 int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, const double* q,
-                   int32_t* cell, double* J, int64_t* n_absorbed);
+                   int32_t* cell, double* J);
+
+/* Order of the particles by cell (counting sort over the tetrahedra):
+ * perm[i] = the particle that goes to place i; cells ascending, inactive
+ * particles (cell -1 or out of range) last, order within one cell
+ * unspecified.  Apply it to every per-particle array (cell included) with
+ * dd_pic_permute.  With particles in cell order the deposit sums the first
+ * pieces of the paths that share a tetrahedron inside a wavefront before its
+ * atomics, and the push's field gathers hit the cache; particles move a
+ * fraction of a cell per step, so an order lasts many steps.
+ * n <= 2^31 - 1. */
+int dd_pic_sort(void* ctx, int64_t n, const int32_t* cell, int32_t* perm);
+
+/* dst[i] = src[perm[i]] for n items of item_bytes bytes (a multiple of 4,
+ * at most 64; 4-byte aligned device arrays that do not overlap).  A perm
+ * entry outside [0, n) leaves that item unwritten (counts[2]). */
+int dd_pic_permute(void* ctx, int64_t n, const int32_t* perm, int item_bytes, const void* src,
+                   void* dst);
 
 /* Faraday's law on the face 2-form of B, kept as its constant value in each
  * tetrahedron: B[t] += alpha * curl(E)|_t with curl W_ij = 2 g_i x g_j
@@ -219,8 +247,8 @@ int dd_pic_faraday(void* ctx, const double* E, double alpha, double* B);
  *   first != 0: x_new = x + dt v,  v += dt acc   (start step)
  *   otherwise:  x_new = x + dt (3/2 v - 1/2 v_prev),  v += dt (3/2 acc - 1/2 acc_prev)
  * hist [n][6] = (v_prev, acc_prev) is overwritten with (v, acc).  x_new must
- * not overlap x.  Inactive particles keep x (copied to x_new) and v.
- * DD_ERR_ARG if a cell index is out of range. */
+ * not overlap x.  Inactive particles keep x (copied to x_new) and v; a
+ * cell index out of range is treated the same way and counted (counts[2]). */
 int dd_pic_push(void* ctx, int64_t n, const double* qm, const double* E, const double* B,
                 const int32_t* cell, const double* x, double* x_new, double* v, double* hist,
                 int first);

@@ -63,9 +63,12 @@ SIGNATURES = {
     "dd_gauss_residual": (C.c_int, [P, P, P, P]),
     "dd_energy": (C.c_int, [P, P, P, P]),
     "dd_profile": (C.c_int, [P, C.c_int, P, P]),
-    "dd_pic_locate": (C.c_int, [P, I64, P, P, P]),
-    "dd_pic_deposit": (C.c_int, [P, I64, P, P, P, P, P, P]),
+    "dd_pic_status": (C.c_int, [P, P, C.c_int]),
+    "dd_pic_locate": (C.c_int, [P, I64, P, P]),
+    "dd_pic_deposit": (C.c_int, [P, I64, P, P, P, P, P]),
     "dd_pic_faraday": (C.c_int, [P, P, D, P]),
+    "dd_pic_sort": (C.c_int, [P, I64, P, P]),
+    "dd_pic_permute": (C.c_int, [P, I64, P, C.c_int, P, P]),
     "dd_pic_push": (C.c_int, [P, I64, P, P, P, P, P, P, P, P, C.c_int]),
     "dd_destroy": (None, [P]),
     "dd_last_error": (C.c_char_p, []),

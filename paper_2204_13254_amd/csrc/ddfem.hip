@@ -139,6 +139,7 @@ struct Ctx {
   double* d_pic_geo = nullptr;
   int32_t *d_pic_nbr = nullptr, *d_pic_tedge = nullptr;
   unsigned long long* d_pic_cnt = nullptr;
+  int32_t *d_pic_count = nullptr, *d_pic_bsum = nullptr;  // ordering by cell: [nt + 1], chunk totals
   // local assembly pull
   int64_t n_lent = 0;
   int64_t *d_lptr = nullptr, *d_ldest = nullptr;
@@ -1898,22 +1899,34 @@ static void pic_prepare(Ctx& C) {
   C.d_pic_nbr = upload(nbr, C.owned, C.st);
   C.d_pic_tedge = upload(P.tet_edges, C.owned, C.st);
   C.d_pic_cnt = dalloc<unsigned long long>(kPicCounters, C.owned);
+  HIPCHK(hipMemsetAsync(C.d_pic_cnt, 0, kPicCounters * sizeof(unsigned long long), C.st));
+  C.d_pic_count = dalloc<int32_t>((size_t)P.nt + 1, C.owned);
+  C.d_pic_bsum = dalloc<int32_t>((size_t)(P.nt + 1 + kScanBlock - 1) / kScanBlock, C.owned);
   double* geo = dalloc<double>((size_t)P.nt * 12, C.owned);
   hipLaunchKernelGGL(k_tet_geo, dim3(nblk(P.nt)), dim3(256), 0, C.st, (int64_t)P.nt, C.d_coords, C.d_tsort, geo);
   HIPCHK(hipGetLastError());
   C.d_pic_geo = geo;
 }
 
-static void pic_counters(Ctx& C, unsigned long long* out) {
-  HIPCHK(hipMemcpyAsync(out, C.d_pic_cnt, kPicCounters * sizeof(unsigned long long), hipMemcpyDeviceToHost, C.st));
+int dd_pic_status(void* ctx, int64_t* counts, int reset) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  unsigned long long c[kPicCounters];
+  HIPCHK(hipMemcpyAsync(c, C.d_pic_cnt, sizeof(c), hipMemcpyDeviceToHost, C.st));
   HIPCHK(hipStreamSynchronize(C.st));
+  if (counts)
+    for (int k = 0; k < kPicCounters; ++k) counts[k] = (int64_t)c[k];
+  if (reset) HIPCHK(hipMemsetAsync(C.d_pic_cnt, 0, sizeof(c), C.st));
+  return DD_OK;
+  API_END
 }
 
-static void pic_zero_counters(Ctx& C) {
-  HIPCHK(hipMemsetAsync(C.d_pic_cnt, 0, kPicCounters * sizeof(unsigned long long), C.st));
-}
-
-int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell, int64_t* n_outside) {
+int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell) {
   if (!ctx || n < 0 || (n > 0 && (!x || !cell))) {
     g_err = "null argument or negative count";
     return DD_ERR_ARG;
@@ -1921,22 +1934,17 @@ int dd_pic_locate(void* ctx, int64_t n, const double* x, int32_t* cell, int64_t*
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
   pic_prepare(C);
-  pic_zero_counters(C);
-  if (n > 0)
-    hipLaunchKernelGGL(k_pic_walk<false>, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, (const double*)nullptr,
-                       x, (const double*)nullptr, 0.0, cell, (const double*)C.d_pic_geo,
-                       (const int32_t*)C.d_pic_nbr, (const int32_t*)C.d_pic_tedge, (const double*)C.d_coords,
-                       (const int32_t*)C.d_tsort, (double*)nullptr, kPicMaxCross, C.d_pic_cnt);
+  if (n == 0) return DD_OK;
+  hipLaunchKernelGGL(k_pic_locate, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, x, cell,
+                     (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_nbr, (const double*)C.d_coords,
+                     (const int32_t*)C.d_tsort, kPicMaxCross, C.d_pic_cnt);
   HIPCHK(hipGetLastError());
-  unsigned long long c[kPicCounters];
-  pic_counters(C, c);
-  if (n_outside) *n_outside = (int64_t)(c[kPicLeftMesh] + c[kPicWalkCap]);
   return DD_OK;
   API_END
 }
 
 int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, const double* q, int32_t* cell,
-                   double* J, int64_t* n_absorbed) {
+                   double* J) {
   if (!ctx || n < 0 || !J || (n > 0 && (!xa || !xb || !q || !cell))) {
     g_err = "null argument or negative count";
     return DD_ERR_ARG;
@@ -1944,20 +1952,56 @@ int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, con
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
   pic_prepare(C);
-  pic_zero_counters(C);
-  if (n > 0)
-    hipLaunchKernelGGL(k_pic_walk<true>, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, xa, xb, q,
-                       1.0 / C.dt, cell, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_nbr,
-                       (const int32_t*)C.d_pic_tedge, (const double*)C.d_coords, (const int32_t*)C.d_tsort, J,
-                       kPicMaxCross, C.d_pic_cnt);
+  if (n == 0) return DD_OK;
+  hipLaunchKernelGGL(k_pic_deposit, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, xa, xb, q, 1.0 / C.dt,
+                     cell, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_nbr,
+                     (const int32_t*)C.d_pic_tedge, J, kPicMaxCross, C.d_pic_cnt);
   HIPCHK(hipGetLastError());
-  unsigned long long c[kPicCounters];
-  pic_counters(C, c);
-  if (n_absorbed) *n_absorbed = (int64_t)c[kPicLeftMesh];
-  if (c[kPicBadCell] || c[kPicWalkCap])
-    throw DDError{DD_ERR_ARG, std::to_string(c[kPicBadCell]) + " particles with a cell index out of range, " +
-                                  std::to_string(c[kPicWalkCap]) + " paths crossing more than " +
-                                  std::to_string(kPicMaxCross) + " faces (those are now inactive)"};
+  return DD_OK;
+  API_END
+}
+
+int dd_pic_sort(void* ctx, int64_t n, const int32_t* cell, int32_t* perm) {
+  if (!ctx || n < 0 || (n > 0 && (!cell || !perm)) || n > INT32_MAX) {
+    g_err = "null argument or count out of range";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  if (n == 0) return DD_OK;
+  const int64_t nt = C.P.nt, m = nt + 1, nb = (m + kScanBlock - 1) / kScanBlock;
+  // a fill kernel, not a memset: this call may be captured into a graph
+  hipLaunchKernelGGL(k_zero_i32, dim3(nblk(m)), dim3(256), 0, C.st, m, C.d_pic_count);
+  hipLaunchKernelGGL(k_cell_hist, dim3(nblk(n)), dim3(256), 0, C.st, n, nt, cell, C.d_pic_count);
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(256), 0, C.st, m, C.d_pic_count, C.d_pic_bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, C.st, nb, C.d_pic_bsum);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk(m)), dim3(256), 0, C.st, m, C.d_pic_count,
+                     (const int32_t*)C.d_pic_bsum);
+  hipLaunchKernelGGL(k_cell_scatter, dim3(nblk(n)), dim3(256), 0, C.st, n, nt, cell, C.d_pic_count, perm);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
+  API_END
+}
+
+int dd_pic_permute(void* ctx, int64_t n, const int32_t* perm, int item_bytes, const void* src, void* dst) {
+  if (!ctx || n < 0 || (n > 0 && (!perm || !src || !dst)) || item_bytes <= 0 || item_bytes > 64 ||
+      item_bytes % 4 != 0) {
+    g_err = "null argument, negative count or item size not a multiple of 4 in [4, 64]";
+    return DD_ERR_ARG;
+  }
+  if (n > 0 && src == dst) {
+    g_err = "src and dst must differ";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  pic_prepare(C);
+  if (n == 0) return DD_OK;
+  const int words = item_bytes / 4;
+  hipLaunchKernelGGL(k_permute, dim3(nblk(n * words)), dim3(256), 0, C.st, n, words, perm, (const uint32_t*)src,
+                     (uint32_t*)dst, C.d_pic_cnt);
+  HIPCHK(hipGetLastError());
   return DD_OK;
   API_END
 }
@@ -1990,16 +2034,11 @@ int dd_pic_push(void* ctx, int64_t n, const double* qm, const double* E, const d
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
   pic_prepare(C);
-  pic_zero_counters(C);
   if (n > 0)
     hipLaunchKernelGGL(k_pic_push, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, qm, E, B, cell, x, x_new,
                        v, hist, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_tedge, C.dt, first ? 1 : 0,
                        C.d_pic_cnt);
   HIPCHK(hipGetLastError());
-  unsigned long long c[kPicCounters];
-  pic_counters(C, c);
-  if (c[kPicBadCell])
-    throw DDError{DD_ERR_ARG, std::to_string(c[kPicBadCell]) + " particles with a cell index out of range"};
   return DD_OK;
   API_END
 }

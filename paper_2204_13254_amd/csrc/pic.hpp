@@ -91,99 +91,275 @@ __device__ __forceinline__ void barycentric(const PicTet& T, const double x[3], 
   l[0] = 1.0 - l[1] - l[2] - l[3];
 }
 
-// Walk the straight line a -> b across shared faces, starting in the
-// tetrahedron that holds a.  In tetrahedron t the line is
-// lam(s) = lam(a) + s (lam(b) - lam(a)); it leaves t at the smallest s where
-// a decreasing lam_k reaches 0, through the face opposite k.  The parameter
-// s never decreases, so rounding at a face cannot send the walk backwards.
-// DEPOSIT: every piece [s0, s1] in t adds q/dt * int W_ij . dl to its six
-// edges; on a straight piece lam_i dlam_j - lam_j dlam_i is constant, so
-// with lam at s0 and dlam = (s1 - s0)(lam(b) - lam(a)) the integral is exact.
-// A line that reaches an outer face stops there (the particle is absorbed:
-// cell = -1); a walk longer than max_cross faces stops with cell = -1 too.
-// Locate mode (!DEPOSIT): a is the centroid of the start cell.
-template <bool DEPOSIT>
-__global__ void __launch_bounds__(256) k_pic_walk(int64_t n, int64_t nt, const double* __restrict__ xa,
-                                                  const double* __restrict__ xb, const double* __restrict__ q,
-                                                  double inv_dt, int32_t* __restrict__ cell,
-                                                  const double* __restrict__ geo, const int32_t* __restrict__ nbr,
-                                                  const int32_t* __restrict__ tedge,
-                                                  const double* __restrict__ coords,
-                                                  const int32_t* __restrict__ tsort, double* __restrict__ J,
-                                                  int max_cross, unsigned long long* __restrict__ cnt) {
+// Exit of the straight line a -> b from tetrahedron T: in T the line is
+// lam(s) = lam(a) + s (lam(b) - lam(a)); it leaves T at the smallest s where
+// a decreasing lam_k reaches 0, through the face opposite k (kx = k), or not
+// before s = 1 (kx = -1).
+__device__ __forceinline__ void line_exit(const PicTet& T, const double a[3], const double b[3], double la[4],
+                                          double d[4], double& s1, int& kx) {
+  double lb[4];
+  barycentric(T, a, la);
+  barycentric(T, b, lb);
+  s1 = 1.0;
+  kx = -1;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    d[k] = lb[k] - la[k];
+    if (d[k] < 0.0) {
+      const double s = la[k] / -d[k];
+      if (s < s1) {
+        s1 = s;
+        kx = k;
+      }
+    }
+  }
+}
+
+// Point location: walk the straight line from the centroid of the start
+// cell (cell[p], or 0 if out of range) to x[p] across shared faces.  The
+// line parameter never decreases, so rounding at a face cannot send the walk
+// backwards.  A line that reaches an outer face gives cell = -1.
+__global__ void __launch_bounds__(256) k_pic_locate(int64_t n, int64_t nt, const double* __restrict__ x,
+                                                    int32_t* __restrict__ cell, const double* __restrict__ geo,
+                                                    const int32_t* __restrict__ nbr,
+                                                    const double* __restrict__ coords,
+                                                    const int32_t* __restrict__ tsort, int max_cross,
+                                                    unsigned long long* __restrict__ cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   int64_t t = cell[p];
-  double a[3], b[3];
-  for (int c = 0; c < 3; ++c) b[c] = xb[3 * p + c];
-  if (DEPOSIT) {
-    if (t < 0) return;  // inactive particle
-    if (t >= nt) {
-      cell[p] = -1;
-      atomicAdd(&cnt[kPicBadCell], 1ull);
-      return;
-    }
-    for (int c = 0; c < 3; ++c) a[c] = xa[3 * p + c];
-  } else {
-    if (t < 0 || t >= nt) t = 0;
-    for (int c = 0; c < 3; ++c) a[c] = 0.0;
-    for (int v = 0; v < 4; ++v) {
-      const int64_t iv = tsort[4 * t + v];
-      for (int c = 0; c < 3; ++c) a[c] += 0.25 * coords[3 * iv + c];
-    }
+  if (t < 0 || t >= nt) t = 0;
+  double a[3] = {0.0, 0.0, 0.0}, b[3];
+  for (int c = 0; c < 3; ++c) b[c] = x[3 * p + c];
+  for (int v = 0; v < 4; ++v) {
+    const int64_t iv = tsort[4 * t + v];
+    for (int c = 0; c < 3; ++c) a[c] += 0.25 * coords[3 * iv + c];
   }
-  const double w = DEPOSIT ? q[p] * inv_dt : 0.0;
   double s0 = 0.0;
   for (int it = 0;; ++it) {
     PicTet T;
     load_tet(geo, t, T);
-    double la[4], lb[4], d[4];
-    barycentric(T, a, la);
-    barycentric(T, b, lb);
-    double s1 = 1.0;
-    int kx = -1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      d[k] = lb[k] - la[k];
-      if (d[k] < 0.0) {
-        const double s = la[k] / -d[k];
-        if (s < s1) {
-          s1 = s;
-          kx = k;
-        }
-      }
-    }
-    if (s1 < s0) s1 = s0;
-    if (DEPOSIT && s1 > s0) {
-      const double c = w * (s1 - s0);
-      double l[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) l[k] = la[k] + s0 * d[k];
-      const int32_t* te = tedge + 6 * t;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) {
-        const int i = kPicEdges[e][0], j = kPicEdges[e][1];
-        unsafeAtomicAdd(J + te[e], c * (l[i] * d[j] - l[j] * d[i]));
-      }
-    }
+    double la[4], d[4], s1;
+    int kx;
+    line_exit(T, a, b, la, d, s1, kx);
     if (kx < 0) {
       cell[p] = (int32_t)t;
       return;
     }
-    s0 = s1;
+    s0 = s1 > s0 ? s1 : s0;
     const int32_t tn = nbr[4 * t + kx];
-    if (tn < 0) {
+    if (tn < 0 || it + 1 >= max_cross) {
       cell[p] = -1;
-      atomicAdd(&cnt[kPicLeftMesh], 1ull);
-      return;
-    }
-    if (it + 1 >= max_cross) {
-      cell[p] = -1;
-      atomicAdd(&cnt[kPicWalkCap], 1ull);
+      atomicAdd(&cnt[tn < 0 ? kPicLeftMesh : kPicWalkCap], 1ull);
       return;
     }
     t = tn;
   }
+}
+
+// Exact current mapping of the straight path xa[p] -> xb[p] (cell[p] holds
+// xa[p]): the walk of k_pic_locate, and every piece [s0, s1] of the path in
+// tetrahedron t adds q/dt * int W_ij . dl to the six edges of t.  On a
+// straight piece lam_i dlam_j - lam_j dlam_i is constant, so with lam at s0
+// and dlam = (s1 - s0)(lam(b) - lam(a)) the integral is exact.
+// The first piece of every path (the start cell) is summed over the lanes of
+// a wavefront that share the tetrahedron (a segmented scan over runs of
+// equal cells, so particles ordered by cell issue one set of atomics per
+// run); later pieces go to the edges directly.  A path that reaches an outer
+// face deposits up to it and the particle becomes inactive (cell = -1); so
+// does a walk longer than max_cross faces.  Inactive particles are skipped.
+__global__ void __launch_bounds__(256) k_pic_deposit(int64_t n, int64_t nt, const double* __restrict__ xa,
+                                                     const double* __restrict__ xb, const double* __restrict__ q,
+                                                     double inv_dt, int32_t* __restrict__ cell,
+                                                     const double* __restrict__ geo,
+                                                     const int32_t* __restrict__ nbr,
+                                                     const int32_t* __restrict__ tedge, double* __restrict__ J,
+                                                     int max_cross, unsigned long long* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int64_t t = p < n ? (int64_t)cell[p] : -1;
+  if (t >= nt) {
+    cell[p] = -1;
+    atomicAdd(&cnt[kPicBadCell], 1ull);
+    t = -1;
+  }
+  const bool act = t >= 0;
+  double a[3], b[3], v[6], w = 0.0, s1 = 1.0;
+  int kx = -1;
+  if (act) {
+    for (int c = 0; c < 3; ++c) {
+      a[c] = xa[3 * p + c];
+      b[c] = xb[3 * p + c];
+    }
+    w = q[p] * inv_dt;
+    PicTet T;
+    load_tet(geo, t, T);
+    double la[4], d[4];
+    line_exit(T, a, b, la, d, s1, kx);
+    if (s1 < 0.0) s1 = 0.0;
+    const double c = w * s1;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int i = kPicEdges[e][0], j = kPicEdges[e][1];
+      v[e] = c * (la[i] * d[j] - la[j] * d[i]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) v[e] = 0.0;
+  }
+  // segmented inclusive scan over runs of equal start cells (inactive lanes
+  // get keys of their own); the last lane of a run holds the run's sum
+  const int key = act ? (int)t : -1 - lane;
+  const int kprev = __shfl_up(key, 1);
+  int f = (lane == 0) || (kprev != key);
+  if (__any(!f)) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      double u[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) u[e] = __shfl_up(v[e], off);
+      const int fu = __shfl_up(f, off);
+      if (lane >= off) {
+        if (!f) {
+#pragma unroll
+          for (int e = 0; e < 6; ++e) v[e] += u[e];
+        }
+        f |= fu;
+      }
+    }
+  }
+  const int knext = __shfl_down(key, 1);
+  if (!act) return;
+  if (lane == 63 || knext != key) {
+    const int32_t* te = tedge + 6 * t;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) unsafeAtomicAdd(J + te[e], v[e]);
+  }
+  double s0 = s1;
+  for (int it = 0; kx >= 0; ++it) {
+    const int32_t tn = nbr[4 * t + kx];
+    if (tn < 0 || it + 1 >= max_cross) {
+      cell[p] = -1;
+      atomicAdd(&cnt[tn < 0 ? kPicLeftMesh : kPicWalkCap], 1ull);
+      return;
+    }
+    t = tn;
+    PicTet T;
+    load_tet(geo, t, T);
+    double la[4], d[4];
+    line_exit(T, a, b, la, d, s1, kx);
+    if (s1 < s0) s1 = s0;
+    if (s1 > s0) {
+      const double c = w * (s1 - s0);
+      const int32_t* te = tedge + 6 * t;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) {
+        const int i = kPicEdges[e][0], j = kPicEdges[e][1];
+        const double li = la[i] + s0 * d[i], lj = la[j] + s0 * d[j];
+        unsafeAtomicAdd(J + te[e], c * (li * d[j] - lj * d[i]));
+      }
+    }
+    s0 = s1;
+  }
+  cell[p] = (int32_t)t;
+}
+
+// ---- ordering particles by cell (counting sort) -------------------------------
+// count[c] (c in [0, nt], nt = inactive) -> exclusive offsets -> scatter.
+__global__ void __launch_bounds__(256) k_cell_hist(int64_t n, int64_t nt, const int32_t* __restrict__ cell,
+                                                   int32_t* __restrict__ count) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int64_t c = cell[p];
+  if (c < 0 || c >= nt) c = nt;
+  atomicAdd(&count[c], 1);
+}
+
+__global__ void __launch_bounds__(256) k_zero_i32(int64_t m, int32_t* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] = 0;
+}
+
+constexpr int kScanPer = 4;                 // elements per thread
+constexpr int kScanBlock = 256 * kScanPer;  // elements per workgroup
+
+// exclusive scan of 256 values held one per thread (all 256 threads call)
+__device__ __forceinline__ int block_exclusive_scan(int s, int* lds) {
+  const int tid = threadIdx.x;
+  lds[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int u = tid >= off ? lds[tid - off] : 0;
+    __syncthreads();
+    lds[tid] += u;
+    __syncthreads();
+  }
+  const int incl = lds[tid];
+  const int total = lds[255];
+  __syncthreads();
+  lds[256] = total;
+  return incl - s;
+}
+
+// in place exclusive scan of each kScanBlock chunk; chunk totals to bsum
+__global__ void __launch_bounds__(256) k_scan_local(int64_t m, int32_t* __restrict__ x, int32_t* __restrict__ bsum) {
+  __shared__ int lds[257];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
+  int v[kScanPer], s = 0;
+  for (int j = 0; j < kScanPer; ++j) {
+    v[j] = base + j < m ? x[base + j] : 0;
+    s += v[j];
+  }
+  int run = block_exclusive_scan(s, lds);
+  for (int j = 0; j < kScanPer; ++j) {
+    if (base + j < m) x[base + j] = run;
+    run += v[j];
+  }
+  if (threadIdx.x == 255) bsum[blockIdx.x] = run;
+}
+
+// in place exclusive scan of the nb chunk totals (one workgroup)
+__global__ void __launch_bounds__(256) k_scan_sums(int64_t nb, int32_t* __restrict__ bsum) {
+  __shared__ int lds[257];
+  int carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += 256) {
+    const int64_t i = c0 + threadIdx.x;
+    const int s = i < nb ? bsum[i] : 0;
+    const int ex = block_exclusive_scan(s, lds);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += lds[256];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(int64_t m, int32_t* __restrict__ x,
+                                                  const int32_t* __restrict__ bsum) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) x[i] += bsum[i / kScanBlock];
+}
+
+__global__ void __launch_bounds__(256) k_cell_scatter(int64_t n, int64_t nt, const int32_t* __restrict__ cell,
+                                                      int32_t* __restrict__ cursor, int32_t* __restrict__ perm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int64_t c = cell[p];
+  if (c < 0 || c >= nt) c = nt;
+  perm[atomicAdd(&cursor[c], 1)] = (int32_t)p;
+}
+
+// dst[i] = src[perm[i]] for items of `words` 32-bit words
+__global__ void __launch_bounds__(256) k_permute(int64_t n, int words, const int32_t* __restrict__ perm,
+                                                 const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                 unsigned long long* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * words) return;
+  const int64_t r = i / words, k = i - r * words;
+  const int64_t s = perm[r];
+  if (s < 0 || s >= n) {
+    if (k == 0) atomicAdd(&cnt[kPicBadCell], 1ull);
+    return;
+  }
+  dst[i] = src[s * words + k];
 }
 
 // B[t] += alpha * curl E in every tetrahedron, curl W_ij = 2 g_i x g_j.

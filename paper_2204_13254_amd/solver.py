@@ -189,30 +189,55 @@ class DDSolver:
         if t.numel() != n:
             raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
 
+    PIC_COUNTERS = ("absorbed_or_outside", "walk_cap", "bad_index")
+
+    def pic_status(self, reset=True):
+        """Device counters of the particle calls since the last reset (syncs)."""
+        c = np.zeros(3, dtype=np.int64)
+        check(self.lib.dd_pic_status(self.h, c.ctypes.data_as(C.c_void_p), int(bool(reset))))
+        return dict(zip(self.PIC_COUNTERS, (int(v) for v in c)))
+
     def pic_locate(self, x, cell=None):
         """Containing tetrahedron of each point (walk from cell, default 0);
-        returns (cell int32 [n], number of points outside the mesh)."""
+        points outside the mesh get -1 (counted in pic_status)."""
         n = self._pts(x)
         if cell is None:
             cell = torch.zeros(n, dtype=torch.int32, device=x.device)
         self._len(cell, n, "cell")
-        out = C.c_int64(0)
-        check(self.lib.dd_pic_locate(self.h, n, _dev(x), _dev_i32(cell), C.byref(out)))
-        return cell, out.value
+        check(self.lib.dd_pic_locate(self.h, n, _dev(x), _dev_i32(cell)))
+        return cell
 
     def pic_deposit(self, xa, xb, q, cell, J):
         """J += exact edge currents of the paths xa -> xb (J: one row
-        [n_edges]); cell is advanced to the end points.  Returns the number of
-        particles absorbed at the outer boundary."""
+        [n_edges]); cell is advanced to the end points (-1 for particles
+        absorbed at the outer boundary, counted in pic_status)."""
         n = self._pts(xa)
         self._pts(xb, n)
         self._len(q, n, "q")
         self._len(cell, n, "cell")
         self._len(J, self.n_edges, "J")
-        out = C.c_int64(0)
-        check(self.lib.dd_pic_deposit(self.h, xa.shape[0], _dev(xa), _dev(xb), _dev(q), _dev_i32(cell),
-                                      _dev(J), C.byref(out)))
-        return out.value
+        check(self.lib.dd_pic_deposit(self.h, n, _dev(xa), _dev(xb), _dev(q), _dev_i32(cell), _dev(J)))
+
+    def pic_sort(self, cell):
+        """Permutation [n] int32 that orders the particles by cell."""
+        n = cell.numel()
+        perm = torch.empty(n, dtype=torch.int32, device=cell.device)
+        check(self.lib.dd_pic_sort(self.h, n, _dev_i32(cell), _dev_i32(perm)))
+        return perm
+
+    def pic_permute(self, perm, src, dst=None):
+        """dst[i] = src[perm[i]] along the first axis (any dtype, contiguous)."""
+        n = perm.numel()
+        if not src.is_contiguous() or src.shape[0] != n or src.device.type != "cuda":
+            raise ValueError("src must be a contiguous device tensor with perm.numel() rows")
+        if dst is None:
+            dst = torch.empty_like(src)
+        if dst.shape != src.shape or dst.dtype != src.dtype or not dst.is_contiguous():
+            raise ValueError("dst must match src")
+        item = src.element_size() * (src.numel() // max(n, 1))
+        check(self.lib.dd_pic_permute(self.h, n, _dev_i32(perm), item, C.c_void_p(src.data_ptr()),
+                                      C.c_void_p(dst.data_ptr())))
+        return dst
 
     def pic_faraday(self, E, alpha, B):
         """B += alpha * curl E per tetrahedron (E one row [n_edges], B [n_tets, 3])."""

@@ -32,6 +32,19 @@ def _solver(c, t, parts, dt=0.05, factor=False, **k):
     return DDSolver(c, t, p, np.ones(len(t)), dt=dt, factor=factor, **k)
 
 
+def _locate(s, x, cell=None):
+    c = s.pic_locate(x, cell)
+    return c, s.pic_status()["absorbed_or_outside"]
+
+
+def _deposit(s, *args):
+    """Deposit, then the number of absorbed particles (no other counter set)."""
+    s.pic_deposit(*args)
+    st = s.pic_status()
+    assert st["walk_cap"] == 0 and st["bad_index"] == 0, st
+    return st["absorbed_or_outside"]
+
+
 def _dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
@@ -64,7 +77,7 @@ def test_locate(jm5):
     s = _solver(c, t, 2)
     rng = np.random.default_rng(0)
     X = np.concatenate([rng.uniform(0.0, 1.0, (3000, 3)), [[1.5, 0.5, 0.5], [0.5, -0.1, 0.5]]])
-    cell, nout = s.pic_locate(_dev(X))
+    cell, nout = _locate(s, _dev(X))
     cell = _host(cell)
     assert nout == 2 and (cell[-2:] == -1).all()
     ref = pic.locate(mesh, X[:-2])
@@ -76,9 +89,9 @@ def test_locate(jm5):
     deep = lam.min(axis=1) > 1e-9
     assert np.array_equal(cell[:-2][deep], ref[deep])
     # start from a given cell, and the empty call
-    cell2, _ = s.pic_locate(_dev(X[:-2]), _dev(ref[::-1].copy(), torch.int32))
+    cell2, _ = _locate(s, _dev(X[:-2]), _dev(ref[::-1].copy(), torch.int32))
     assert np.array_equal(_host(cell2)[deep], ref[deep])
-    e, n0 = s.pic_locate(_dev(np.zeros((0, 3))))
+    e, n0 = _locate(s, _dev(np.zeros((0, 3))))
     assert n0 == 0 and e.numel() == 0
 
 
@@ -98,14 +111,14 @@ def test_deposit_parity(jm5):
     sw = _wall_exit(A, B)                  # paths that hit the wall are cut there
     out = sw < 1.0
     Bc = np.where(out[:, None], A + (B - A) * sw[:, None], B)
-    cell, _ = s.pic_locate(_dev(A))
+    cell, _ = _locate(s, _dev(A))
     cell_h = _host(cell).copy()
     cell_h[5] = -1                         # inactive particle: skipped
     keep = np.ones(m, bool)
     keep[5] = False
     cell = _dev(cell_h, torch.int32)
     J = torch.zeros(s.n_edges, dtype=torch.float64, device="cuda")
-    nabs = s.pic_deposit(_dev(A), _dev(B), _dev(q), cell, J)
+    nabs = _deposit(s, _dev(A), _dev(B), _dev(q), cell, J)
     Jg = _host(J)
     Jo = pic.deposit(mesh, A[keep], Bc[keep], q[keep], dt)
     scale = np.abs(Jo).max()
@@ -123,16 +136,68 @@ def test_deposit_parity(jm5):
     np.testing.assert_array_equal(_host(J), Jg)
 
 
-def test_deposit_bad_cell_is_an_error(jm5):
-    from paper_2204_13254_amd._lib import DDError
+def test_sort_and_permute(jm5):
+    c, t, mesh = jm5
+    s = _solver(c, t, 2)
+    rng = np.random.default_rng(7)
+    n = 20000
+    cells = rng.integers(-1, len(t), n).astype(np.int32)
+    cells[:50] = len(t) + 5                 # out of range: ordered with the inactive ones
+    cd = _dev(cells, torch.int32)
+    perm = _host(s.pic_sort(cd))
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    key = np.where((cells < 0) | (cells >= len(t)), len(t), cells)
+    assert (np.diff(key[perm]) >= 0).all()
+    P = _dev(perm, torch.int32)
+    X = rng.normal(size=(n, 3))
+    H = rng.normal(size=(n, 6))
+    np.testing.assert_array_equal(_host(s.pic_permute(P, _dev(X))), X[perm])
+    np.testing.assert_array_equal(_host(s.pic_permute(P, _dev(H))), H[perm])
+    np.testing.assert_array_equal(_host(s.pic_permute(P, cd)), cells[perm])
+    assert _host(s.pic_sort(_dev(np.zeros(0), torch.int32))).size == 0
+
+
+@pytest.mark.parametrize("order", ["random", "by_cell"])
+def test_deposit_many_per_cell(jm5, order):
+    """Thousands of short paths on 750 tetrahedra (about 4 per start cell):
+    in random order duplicate cells sit in non-adjacent lanes, in cell order
+    they form runs that the wavefront sums before its atomics."""
+    c, t, mesh = jm5
+    dt = 0.02
+    s = _solver(c, t, 2, dt=dt)
+    rng = np.random.default_rng(8)
+    m = 3000
+    A = rng.uniform(0.01, 0.99, (m, 3))
+    B = np.clip(A + rng.normal(0, 0.03, (m, 3)), 0.001, 0.999)
+    q = rng.uniform(-1, 1, m)
+    cell, _ = _locate(s, _dev(A))
+    a, b, qd = _dev(A), _dev(B), _dev(q)
+    if order == "by_cell":
+        perm = s.pic_sort(cell)
+        a, b, qd, cell = (s.pic_permute(perm, z) for z in (a, b, qd, cell))
+        ch = _host(cell)
+        assert (np.diff(ch) >= 0).all() and (np.diff(ch) == 0).mean() > 0.5
+    J = torch.zeros(s.n_edges, dtype=torch.float64, device="cuda")
+    assert _deposit(s, a, b, qd, cell, J) == 0
+    Jo = pic.deposit(mesh, A, B, q, dt)
+    np.testing.assert_allclose(_host(J), Jo, rtol=0, atol=1e-12 * np.abs(Jo).max())
+
+
+def test_bad_indices_are_counted(jm5):
     c, t, mesh = jm5
     s = _solver(c, t, 2)
     x = _dev(np.full((2, 3), 0.5))
     cell = _dev(np.array([0, len(t) + 3]), torch.int32)
     J = torch.zeros(s.n_edges, dtype=torch.float64, device="cuda")
-    with pytest.raises(DDError):
-        s.pic_deposit(x, x, _dev(np.ones(2)), cell, J)
-    assert _host(cell)[1] == -1
+    s.pic_deposit(x, x, _dev(np.ones(2)), cell, J)
+    st = s.pic_status()
+    assert st == {"absorbed_or_outside": 0, "walk_cap": 0, "bad_index": 1}
+    assert _host(cell)[1] == -1 and s.pic_status()["bad_index"] == 0   # reset
+    perm = _dev(np.array([1, 7]), torch.int32)
+    out = torch.full((2,), -5.0, dtype=torch.float64, device="cuda")
+    s.pic_permute(perm, _dev(np.array([3.0, 4.0])), out)
+    assert s.pic_status()["bad_index"] == 1
+    np.testing.assert_array_equal(_host(out), [4.0, -5.0])
 
 
 def test_faraday_parity(jm5):
@@ -158,7 +223,7 @@ def test_push_parity(jm5):
     qm = rng.uniform(-3, 3, m)
     e = rng.normal(size=s.n_edges)
     Bt = rng.normal(size=(len(t), 3))
-    cell, _ = s.pic_locate(_dev(X))
+    cell, _ = _locate(s, _dev(X))
     ch = _host(cell).copy()
     ch[7] = -1
     cell = _dev(ch, torch.int32)
@@ -205,7 +270,7 @@ def test_closed_cycle_with_gauss_law():
     x, v = _dev(X0), _dev(V0)
     hist = torch.zeros((m, 6), dtype=torch.float64, device="cuda")
     xn = torch.empty_like(x)
-    cell, nout = s.pic_locate(x)
+    cell, nout = _locate(s, x)
     assert nout == 0
     Bg = _dev(Bt0)
     e_n = s.new_field(); e_nm1 = s.new_field(); J_prev = s.new_field()
@@ -266,11 +331,11 @@ def test_beam_fullsize_deposit():
     b[:, 2] -= w
     q = bs.q[~wrap]
     print(f"beam paths {len(a)}", flush=True)
-    cell, nout = s.pic_locate(_dev(a))
+    cell, nout = _locate(s, _dev(a))
     assert nout == 0
     cell0 = _host(cell).copy()
     J = torch.zeros(s.n_edges, dtype=torch.float64, device="cuda")
-    nabs = s.pic_deposit(_dev(a), _dev(b), _dev(q), cell, J)
+    nabs = _deposit(s, _dev(a), _dev(b), _dev(q), cell, J)
     assert nabs == 0
     Jg = _host(J)
     edges, _ = s.edges()
@@ -279,6 +344,12 @@ def test_beam_fullsize_deposit():
     K = kuhn_deposit(n, keys, nv1, a, b, q, dt, len(edges))
     scale = np.abs(K).max()
     np.testing.assert_allclose(Jg, K, rtol=0, atol=1e-12 * scale)
+    # the same paths in cell order (long runs of equal start cells)
+    perm = s.pic_sort(_dev(cell0, torch.int32))
+    ad, bd, qd, cd = (s.pic_permute(perm, z) for z in (_dev(a), _dev(b), _dev(q), _dev(cell0, torch.int32)))
+    J2 = torch.zeros(s.n_edges, dtype=torch.float64, device="cuda")
+    assert _deposit(s, ad, bd, qd, cd, J2) == 0
+    np.testing.assert_allclose(_host(J2), K, rtol=0, atol=1e-12 * scale)
     # continuity: dt G^T J = sum_p q_p (lam(b) - lam(a)) at every vertex
     mesh = pic.TetMesh(c, t)
     ce = _host(cell)
