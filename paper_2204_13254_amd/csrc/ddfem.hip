@@ -1953,7 +1953,7 @@ int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, con
   API_BEGIN
   pic_prepare(C);
   if (n == 0) return DD_OK;
-  hipLaunchKernelGGL(k_pic_deposit, dim3(nblk(n)), dim3(256), 0, C.st, n, (int64_t)C.P.nt, xa, xb, q, 1.0 / C.dt,
+  hipLaunchKernelGGL(k_pic_deposit, dim3(nblk(n, kDepThreads)), dim3(kDepThreads), 0, C.st, n, (int64_t)C.P.nt, xa, xb, q, 1.0 / C.dt,
                      cell, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_nbr,
                      (const int32_t*)C.d_pic_tedge, J, kPicMaxCross, C.d_pic_cnt);
   HIPCHK(hipGetLastError());

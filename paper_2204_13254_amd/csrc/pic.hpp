@@ -162,117 +162,125 @@ __global__ void __launch_bounds__(256) k_pic_locate(int64_t n, int64_t nt, const
 // tetrahedron t adds q/dt * int W_ij . dl to the six edges of t.  On a
 // straight piece lam_i dlam_j - lam_j dlam_i is constant, so with lam at s0
 // and dlam = (s1 - s0)(lam(b) - lam(a)) the integral is exact.
-// The first piece of every path (the start cell) is summed over the lanes of
-// a wavefront that share the tetrahedron (a segmented scan over runs of
-// equal cells, so particles ordered by cell issue one set of atomics per
-// run); later pieces go to the edges directly.  A path that reaches an outer
-// face deposits up to it and the particle becomes inactive (cell = -1); so
-// does a walk longer than max_cross faces.  Inactive particles are skipped.
-__global__ void __launch_bounds__(256) k_pic_deposit(int64_t n, int64_t nt, const double* __restrict__ xa,
-                                                     const double* __restrict__ xb, const double* __restrict__ q,
-                                                     double inv_dt, int32_t* __restrict__ cell,
-                                                     const double* __restrict__ geo,
-                                                     const int32_t* __restrict__ nbr,
-                                                     const int32_t* __restrict__ tedge, double* __restrict__ J,
-                                                     int max_cross, unsigned long long* __restrict__ cnt) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+// The contributions of a workgroup are first summed per edge in an LDS hash
+// table (open addressing, kDepProbes probes, then straight to J) and the
+// table is added to J with one atomic per distinct edge: with particles in
+// cell order a workgroup covers a few hexahedra' worth of tetrahedra, so
+// most contributions meet in LDS.  A path that reaches an outer face
+// deposits up to it and the particle becomes inactive (cell = -1); so does a
+// walk longer than max_cross faces.  Inactive particles are skipped.
+constexpr int kDepThreads = 512;
+constexpr int kDepSlotBits = 11;
+constexpr int kDepSlots = 1 << kDepSlotBits;
+constexpr int kDepProbes = 16;
+
+__device__ __forceinline__ void dep_add(int32_t* keys, double* vals, double* __restrict__ J, int32_t e, double v) {
+  unsigned h = ((unsigned)e * 2654435761u) >> (32 - kDepSlotBits);
+  for (int i = 0; i < kDepProbes; ++i) {
+    const int32_t k = atomicCAS(&keys[h], -1, e);
+    if (k == -1 || k == e) {
+      atomicAdd(&vals[h], v);
+      return;
+    }
+    h = (h + 1) & (kDepSlots - 1);
+  }
+  unsafeAtomicAdd(J + e, v);
+}
+
+__device__ __forceinline__ void dep_piece(int32_t* keys, double* vals, double* __restrict__ J,
+                                          const int32_t* __restrict__ te, const double la[4], const double d[4],
+                                          double s0, double c) {
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int i = kPicEdges[e][0], j = kPicEdges[e][1];
+    const double li = la[i] + s0 * d[i], lj = la[j] + s0 * d[j];
+    dep_add(keys, vals, J, te[e], c * (li * d[j] - lj * d[i]));
+  }
+}
+
+__global__ void __launch_bounds__(kDepThreads) k_pic_deposit(int64_t n, int64_t nt, const double* __restrict__ xa,
+                                                             const double* __restrict__ xb,
+                                                             const double* __restrict__ q, double inv_dt,
+                                                             int32_t* __restrict__ cell,
+                                                             const double* __restrict__ geo,
+                                                             const int32_t* __restrict__ nbr,
+                                                             const int32_t* __restrict__ tedge,
+                                                             double* __restrict__ J, int max_cross,
+                                                             unsigned long long* __restrict__ cnt) {
+  __shared__ int32_t keys[kDepSlots];
+  __shared__ double vals[kDepSlots];
+  for (int i = threadIdx.x; i < kDepSlots; i += kDepThreads) {
+    keys[i] = -1;
+    vals[i] = 0.0;
+  }
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * kDepThreads + threadIdx.x;
   int64_t t = p < n ? (int64_t)cell[p] : -1;
   if (t >= nt) {
     cell[p] = -1;
     atomicAdd(&cnt[kPicBadCell], 1ull);
     t = -1;
   }
-  const bool act = t >= 0;
-  double a[3], b[3], v[6], w = 0.0, s1 = 1.0;
-  int kx = -1;
-  if (act) {
+  if (t >= 0) {
+    double a[3], b[3];
     for (int c = 0; c < 3; ++c) {
       a[c] = xa[3 * p + c];
       b[c] = xb[3 * p + c];
     }
-    w = q[p] * inv_dt;
-    PicTet T;
-    load_tet(geo, t, T);
-    double la[4], d[4];
-    line_exit(T, a, b, la, d, s1, kx);
-    if (s1 < 0.0) s1 = 0.0;
-    const double c = w * s1;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      const int i = kPicEdges[e][0], j = kPicEdges[e][1];
-      v[e] = c * (la[i] * d[j] - la[j] * d[i]);
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 6; ++e) v[e] = 0.0;
-  }
-  // segmented inclusive scan over runs of equal start cells (inactive lanes
-  // get keys of their own); the last lane of a run holds the run's sum
-  const int key = act ? (int)t : -1 - lane;
-  const int kprev = __shfl_up(key, 1);
-  int f = (lane == 0) || (kprev != key);
-  if (__any(!f)) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      double u[6];
-#pragma unroll
-      for (int e = 0; e < 6; ++e) u[e] = __shfl_up(v[e], off);
-      const int fu = __shfl_up(f, off);
-      if (lane >= off) {
-        if (!f) {
-#pragma unroll
-          for (int e = 0; e < 6; ++e) v[e] += u[e];
-        }
-        f |= fu;
+    const double w = q[p] * inv_dt;
+    double s0 = 0.0;
+    for (int it = 0;; ++it) {
+      PicTet T;
+      load_tet(geo, t, T);
+      double la[4], d[4], s1;
+      int kx;
+      line_exit(T, a, b, la, d, s1, kx);
+      if (s1 < s0) s1 = s0;
+      if (s1 > s0) dep_piece(keys, vals, J, tedge + 6 * t, la, d, s0, w * (s1 - s0));
+      if (kx < 0) {
+        cell[p] = (int32_t)t;
+        break;
       }
-    }
-  }
-  const int knext = __shfl_down(key, 1);
-  if (!act) return;
-  if (lane == 63 || knext != key) {
-    const int32_t* te = tedge + 6 * t;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) unsafeAtomicAdd(J + te[e], v[e]);
-  }
-  double s0 = s1;
-  for (int it = 0; kx >= 0; ++it) {
-    const int32_t tn = nbr[4 * t + kx];
-    if (tn < 0 || it + 1 >= max_cross) {
-      cell[p] = -1;
-      atomicAdd(&cnt[tn < 0 ? kPicLeftMesh : kPicWalkCap], 1ull);
-      return;
-    }
-    t = tn;
-    PicTet T;
-    load_tet(geo, t, T);
-    double la[4], d[4];
-    line_exit(T, a, b, la, d, s1, kx);
-    if (s1 < s0) s1 = s0;
-    if (s1 > s0) {
-      const double c = w * (s1 - s0);
-      const int32_t* te = tedge + 6 * t;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) {
-        const int i = kPicEdges[e][0], j = kPicEdges[e][1];
-        const double li = la[i] + s0 * d[i], lj = la[j] + s0 * d[j];
-        unsafeAtomicAdd(J + te[e], c * (li * d[j] - lj * d[i]));
+      s0 = s1;
+      const int32_t tn = nbr[4 * t + kx];
+      if (tn < 0 || it + 1 >= max_cross) {
+        cell[p] = -1;
+        atomicAdd(&cnt[tn < 0 ? kPicLeftMesh : kPicWalkCap], 1ull);
+        break;
       }
+      t = tn;
     }
-    s0 = s1;
   }
-  cell[p] = (int32_t)t;
+  __syncthreads();
+  for (int i = threadIdx.x; i < kDepSlots; i += kDepThreads) {
+    const int32_t e = keys[i];
+    if (e >= 0) unsafeAtomicAdd(J + e, vals[i]);
+  }
 }
 
 // ---- ordering particles by cell (counting sort) -------------------------------
 // count[c] (c in [0, nt], nt = inactive) -> exclusive offsets -> scatter.
+// Runs of equal keys in adjacent lanes of a wavefront (particles already
+// close to cell order form long runs): head and tail lane of my run.
+__device__ __forceinline__ void lane_run(int key, int lane, int& head, int& tail) {
+  const int kprev = __shfl_up(key, 1), knext = __shfl_down(key, 1);
+  const unsigned long long heads = __ballot(lane == 0 || kprev != key);
+  const unsigned long long tails = __ballot(lane == 63 || knext != key);
+  head = 63 - __clzll(heads & (~0ull >> (63 - lane)));
+  tail = lane + __ffsll((long long)(tails >> lane)) - 1;
+}
+
+// count[c] += number of particles in cell c (one atomic per run of a wave);
+// inactive particles (cell -1 or out of range) count in c = nt
 __global__ void __launch_bounds__(256) k_cell_hist(int64_t n, int64_t nt, const int32_t* __restrict__ cell,
                                                    int32_t* __restrict__ count) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int64_t c = cell[p];
-  if (c < 0 || c >= nt) c = nt;
-  atomicAdd(&count[c], 1);
+  const int lane = threadIdx.x & 63;
+  int64_t c = p < n ? (int64_t)cell[p] : -2 - lane;
+  if (p < n && (c < 0 || c >= nt)) c = nt;
+  int head, tail;
+  lane_run((int)c, lane, head, tail);
+  if (p < n && lane == tail) atomicAdd(&count[c], tail - head + 1);
 }
 
 __global__ void __launch_bounds__(256) k_zero_i32(int64_t m, int32_t* __restrict__ x) {
@@ -341,10 +349,15 @@ __global__ void __launch_bounds__(256) k_scan_add(int64_t m, int32_t* __restrict
 __global__ void __launch_bounds__(256) k_cell_scatter(int64_t n, int64_t nt, const int32_t* __restrict__ cell,
                                                       int32_t* __restrict__ cursor, int32_t* __restrict__ perm) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  int64_t c = cell[p];
-  if (c < 0 || c >= nt) c = nt;
-  perm[atomicAdd(&cursor[c], 1)] = (int32_t)p;
+  const int lane = threadIdx.x & 63;
+  int64_t c = p < n ? (int64_t)cell[p] : -2 - lane;
+  if (p < n && (c < 0 || c >= nt)) c = nt;
+  int head, tail;
+  lane_run((int)c, lane, head, tail);
+  int base = 0;
+  if (p < n && lane == tail) base = atomicAdd(&cursor[c], tail - head + 1);
+  base = __shfl(base, tail);
+  if (p < n) perm[base + lane - head] = (int32_t)p;
 }
 
 // dst[i] = src[perm[i]] for items of `words` 32-bit words
