@@ -174,13 +174,15 @@ def pic_leg(s, w, E, steps, dev, log, sort_every=10):
             e[1].record()
             e = ev["deposit"][2 * r], ev["deposit"][2 * r + 1]
             e[0].record(); s.pic_deposit(d["x"], xn[r], d["q"], d["cell"], J[r]); e[1].record()
-            e = ev["faraday"][2 * r], ev["faraday"][2 * r + 1]
-            e[0].record(); s.pic_faraday(E[r], -w.dt, B[r]); e[1].record()
             d["x"], xn[r] = xn[r], d["x"]
+        e = ev["faraday"][0], ev["faraday"][1]
+        e[0].record(); s.pic_faraday(E, -w.dt, B); e[1].record()
         torch.cuda.synchronize()
         if timed:
             for key in ms:
-                if key != "sort" or sorted_now:
+                if key == "faraday":
+                    ms[key] += ev[key][0].elapsed_time(ev[key][1])
+                elif key != "sort" or sorted_now:
                     ms[key] += sum(ev[key][2 * r].elapsed_time(ev[key][2 * r + 1]) for r in range(nr))
 
     one(0, False)
@@ -193,14 +195,16 @@ def pic_leg(s, w, E, steps, dev, log, sort_every=10):
     assert st["walk_cap"] == 0 and st["bad_index"] == 0, st
     active = sum(int((P[r]["cell"] >= 0).sum().item()) for r in range(nr))
     npart = sum(P[r]["x"].shape[0] for r in range(nr))
-    # compulsory bytes per particle: push reads x, v, hist, qm, cell and writes
-    # x_new, v, hist; deposit reads both positions, q and the cell and writes
-    # the cell, plus one read + write of every J row; Faraday reads E and B
-    # and writes B once per tetrahedron; ordering reads the cells twice and
-    # writes the permutation, then reads and writes 116 bytes per particle
+    # compulsory bytes: push reads x, v, hist, qm, cell and writes x_new, v,
+    # hist per particle; deposit reads both positions, q and the cell and
+    # writes the cell per particle, plus one read + write of every J row;
+    # Faraday (all rows in one call) reads the geometry and edge list of
+    # every tetrahedron once, every E row once, and reads + writes B; ordering
+    # reads the cells twice and writes the permutation, then reads and writes
+    # 116 bytes per particle
     byt = {"push": npart * (24 + 24 + 48 + 8 + 4 + 24 + 24 + 48),
            "deposit": npart * (24 + 24 + 8 + 4 + 4) + nr * s.n_edges * 16,
-           "faraday": nr * s.n_tets * (48 + 24 + 24),
+           "faraday": s.n_tets * (96 + 24) + nr * (s.n_edges * 8 + s.n_tets * 48),
            "sort": npart * (4 + 4 + 4 + 2 * 116) * (steps // sort_every)}
     res = {"particles": npart, "active_at_end": active, "absorbed_in_timed_steps": st["absorbed_or_outside"],
            "steps_timed": steps, "sort_every": sort_every,

@@ -237,9 +237,10 @@ int dd_pic_permute(void* ctx, int64_t n, const int32_t* perm, int item_bytes, co
                    void* dst);
 
 /* Faraday's law on the face 2-form of B, kept as its constant value in each
- * tetrahedron: B[t] += alpha * curl(E)|_t with curl W_ij = 2 g_i x g_j
- * (alpha = -dt for one step).  E: one row [n_edges]; B: [n_tets][3]. */
-int dd_pic_faraday(void* ctx, const double* E, double alpha, double* B);
+ * tetrahedron: B_r[t] += alpha * curl(E_r)|_t with curl W_ij = 2 g_i x g_j
+ * (alpha = -dt for one step) for rows r < nrows.  E: [nrows][n_edges];
+ * B: [nrows][n_tets][3]. */
+int dd_pic_faraday(void* ctx, int nrows, const double* E, double alpha, double* B);
 
 /* Field interpolation at x[p] in cell[p] (E = sum_e E[e] W_e, B = B[cell])
  * and one Adams-Bashforth step of x' = v, v' = qm (E + v x B), qm [n] the

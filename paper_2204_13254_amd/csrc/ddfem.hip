@@ -2006,16 +2006,16 @@ int dd_pic_permute(void* ctx, int64_t n, const int32_t* perm, int item_bytes, co
   API_END
 }
 
-int dd_pic_faraday(void* ctx, const double* E, double alpha, double* B) {
-  if (!ctx || !E || !B) {
-    g_err = "null argument";
+int dd_pic_faraday(void* ctx, int nrows, const double* E, double alpha, double* B) {
+  if (!ctx || !E || !B || nrows < 1) {
+    g_err = "null argument or nrows < 1";
     return DD_ERR_ARG;
   }
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
   pic_prepare(C);
-  hipLaunchKernelGGL(k_pic_faraday, dim3(nblk(C.P.nt)), dim3(256), 0, C.st, (int64_t)C.P.nt, E, alpha,
-                     (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_tedge, B);
+  hipLaunchKernelGGL(k_pic_faraday, dim3(nblk(C.P.nt)), dim3(256), 0, C.st, (int64_t)C.P.nt, nrows, (int64_t)C.P.ne,
+                     E, alpha, (const double*)C.d_pic_geo, (const int32_t*)C.d_pic_tedge, B);
   HIPCHK(hipGetLastError());
   return DD_OK;
   API_END

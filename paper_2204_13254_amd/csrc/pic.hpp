@@ -375,24 +375,39 @@ __global__ void __launch_bounds__(256) k_permute(int64_t n, int words, const int
   dst[i] = src[s * words + k];
 }
 
-// B[t] += alpha * curl E in every tetrahedron, curl W_ij = 2 g_i x g_j.
-__global__ void __launch_bounds__(256) k_pic_faraday(int64_t nt, const double* __restrict__ E, double alpha,
-                                                     const double* __restrict__ geo,
+// B_r[t] += alpha * curl E_r in every tetrahedron for rows r < nrows
+// (E [nrows][ne], B [nrows][nt][3]), curl W_ij = 2 g_i x g_j.  The six
+// curls of a tetrahedron are formed once and applied to every row.
+__global__ void __launch_bounds__(256) k_pic_faraday(int64_t nt, int nrows, int64_t ne, const double* __restrict__ E,
+                                                     double alpha, const double* __restrict__ geo,
                                                      const int32_t* __restrict__ tedge, double* __restrict__ B) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nt) return;
   PicTet T;
   load_tet(geo, t, T);
-  double c[3] = {0.0, 0.0, 0.0};
+  double cw[6][3];
+  int32_t ed[6];
 #pragma unroll
   for (int e = 0; e < 6; ++e) {
     const int i = kPicEdges[e][0], j = kPicEdges[e][1];
-    const double f = 2.0 * E[tedge[6 * t + e]];
-    c[0] += f * (T.g[i][1] * T.g[j][2] - T.g[i][2] * T.g[j][1]);
-    c[1] += f * (T.g[i][2] * T.g[j][0] - T.g[i][0] * T.g[j][2]);
-    c[2] += f * (T.g[i][0] * T.g[j][1] - T.g[i][1] * T.g[j][0]);
+    ed[e] = tedge[6 * t + e];
+    cw[e][0] = 2.0 * alpha * (T.g[i][1] * T.g[j][2] - T.g[i][2] * T.g[j][1]);
+    cw[e][1] = 2.0 * alpha * (T.g[i][2] * T.g[j][0] - T.g[i][0] * T.g[j][2]);
+    cw[e][2] = 2.0 * alpha * (T.g[i][0] * T.g[j][1] - T.g[i][1] * T.g[j][0]);
   }
-  for (int k = 0; k < 3; ++k) B[3 * t + k] += alpha * c[k];
+  for (int r = 0; r < nrows; ++r) {
+    const double* Er = E + r * ne;
+    double c[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const double f = Er[ed[e]];
+      c[0] += f * cw[e][0];
+      c[1] += f * cw[e][1];
+      c[2] += f * cw[e][2];
+    }
+    double* Br = B + (r * nt + t) * 3;
+    for (int k = 0; k < 3; ++k) Br[k] += c[k];
+  }
 }
 
 // Field interpolation at x in its cell (E = sum_e e_e W_e, B = B[cell]) and

@@ -240,10 +240,12 @@ class DDSolver:
         return dst
 
     def pic_faraday(self, E, alpha, B):
-        """B += alpha * curl E per tetrahedron (E one row [n_edges], B [n_tets, 3])."""
-        self._len(E, self.n_edges, "E")
-        self._len(B, 3 * self.n_tets, "B")
-        check(self.lib.dd_pic_faraday(self.h, _dev(E), float(alpha), _dev(B)))
+        """B += alpha * curl E per tetrahedron; E [n_edges] or [r, n_edges],
+        B [n_tets, 3] or [r, n_tets, 3]."""
+        rows = E.numel() // self.n_edges
+        self._len(E, rows * self.n_edges, "E")
+        self._len(B, 3 * rows * self.n_tets, "B")
+        check(self.lib.dd_pic_faraday(self.h, rows, _dev(E), float(alpha), _dev(B)))
 
     def pic_push(self, qm, E, B, cell, x, x_new, v, hist, first):
         """Interpolate E, B at x and take one Adams-Bashforth step (x_new, v,

@@ -210,6 +210,14 @@ def test_faraday_parity(jm5):
     s.pic_faraday(_dev(e), -0.37, B)
     ref = pic.faraday(mesh, e, B0, -0.37)
     np.testing.assert_allclose(_host(B), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # three right-hand sides in one call
+    e3 = rng.normal(size=(3, s.n_edges))
+    B3 = rng.normal(size=(3, len(t), 3))
+    Bd = _dev(B3)
+    s.pic_faraday(_dev(e3), 0.25, Bd)
+    for r in range(3):
+        ref = pic.faraday(mesh, e3[r], B3[r], 0.25)
+        np.testing.assert_allclose(_host(Bd)[r], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
 
 
 def test_push_parity(jm5):
