@@ -72,6 +72,15 @@ typedef struct {
   void* stream;       /* hipStream_t; NULL = default stream */
   int precond;        /* interface CG preconditioner: 0 none, 1 lumped (multiplicity-scaled
                          interface stiffness, sum_s D B_s A_GammaGamma^(s) B_s^T D, D = 1/2) */
+  int method;         /* interface scheme: 0 dual-primal with one multiplier per interface
+                         edge and CG (Sec. III-A); 1 Robin variant with one multiplier per
+                         side and restarted GMRES (Sec. III-B, edge-only form); cg_tol and
+                         cg_max_iter then bound the GMRES iterations, precond and
+                         warm_start do not apply */
+  double robin_alpha; /* method 1: Robin coefficient alpha of the transmission condition
+                         lam_i + lam_j + 2 alpha M_T x_j = 0 (M_T the tangential mass of the
+                         interface faces); 0 = automatic, (eps h + beta dt^2 / (mu h)) / 2
+                         with h the mean edge length and eps, mu the mean material values */
 } dd_options;
 
 typedef struct {
@@ -101,7 +110,7 @@ typedef struct {
 
 /* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
  * refine_tol 1e-12, refine_max 10, warm_start 0, use_graph 0, check_every 4,
- * precond 1. */
+ * precond 1, method 0, robin_alpha 0. */
 void dd_default_options(dd_options* opt);
 
 /* Build a solver context (host analysis + device upload + element assembly

@@ -21,7 +21,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("nrhs", C.c_int), ("cg_tol", C.c_double),
                 ("cg_max_iter", C.c_int), ("refine_tol", C.c_double), ("refine_max", C.c_int),
                 ("warm_start", C.c_int), ("use_graph", C.c_int), ("check_every", C.c_int),
-                ("stream", C.c_void_p), ("precond", C.c_int)]
+                ("stream", C.c_void_p), ("precond", C.c_int), ("method", C.c_int),
+                ("robin_alpha", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -25,10 +25,12 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ddfem.h"
 #include "kernels.hpp"
+#include "dp2.hpp"
 #include "pic.hpp"
 #include "plan.hpp"
 
@@ -140,6 +142,18 @@ struct Ctx {
   int32_t *d_pic_nbr = nullptr, *d_pic_tedge = nullptr;
   unsigned long long* d_pic_cnt = nullptr;
   int32_t *d_pic_count = nullptr, *d_pic_bsum = nullptr;  // ordering by cell: [nt + 1], chunk totals
+  // Robin dual-primal variant (method 1): one multiplier per side, in the
+  // order of the interface rows (d_grow); R = 2 alpha M_T in side space
+  double robin_alpha = 0.0;
+  int32_t *d_code2 = nullptr, *d_partner2 = nullptr;
+  int64_t* d_rrp = nullptr;
+  int32_t* d_rci = nullptr;
+  double* d_rval = nullptr;
+  int64_t n_radd = 0;            // Robin terms of the local interface blocks (lower triangle, no alpha)
+  int64_t* d_radd_pos = nullptr;
+  double* d_radd_val = nullptr;
+  double *d_gmV = nullptr, *d_gm_u = nullptr, *d_gm_rhs = nullptr, *d_lam2 = nullptr, *d_gm_partial = nullptr;
+  double *d_gm_h = nullptr, *d_gm_tot = nullptr, *d_gm_ss = nullptr, *d_gm_y = nullptr;
   // local assembly pull
   int64_t n_lent = 0;
   int64_t *d_lptr = nullptr, *d_ldest = nullptr;
@@ -1022,6 +1036,9 @@ static int factor_impl(Ctx& C) {
                      C.d_ldest, C.d_Te, C.d_Se, C.d_eps, C.beta * C.dt * C.dt, tiles);
   if (C.n_pad)
     hipLaunchKernelGGL(k_pad_diag<T>, dim3(nblk(C.n_pad)), dim3(256), 0, st, C.n_pad, C.d_padpos, tiles);
+  if (C.n_radd)
+    hipLaunchKernelGGL(k_add_entries<T>, dim3(nblk(C.n_radd)), dim3(256), 0, st, C.n_radd, C.d_radd_pos,
+                       C.d_radd_val, C.robin_alpha, tiles);
   hipLaunchKernelGGL(k_pull_csr, dim3(nblk(C.nnz)), dim3(256), 0, st, C.nnz, C.d_gptr, C.d_gcon, C.d_Te,
                      C.d_Se, C.d_eps, C.d_vals);
   if (C.lam_nnz)
@@ -1201,14 +1218,13 @@ static void coarse_solve(Ctx& C, void* Xin, void* Xtmp, void* Xout, const int* s
 // slots).
 // gathered: X5 already holds v = B_s^T p (the CG iteration writes it while
 // updating p)
+// X8 = M X5 + Psi_G^T z, z = K_cc^-1 sum_s B_c^T Psi_G X5: the local
+// interface response to the interface loads held in the interface rows of X5
 template <class T>
-static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false, bool gathered = false) {
+static void apply_local(Ctx& C, const int* skip) {
   const int nr = C.nrhs;
   hipStream_t st = C.st;
   void **X = C.X;
-  if (!gathered)
-    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_glam, p, (T*)X[5], nr, skip);
   const bool overlap = C.Kc > 0 && !C.prof;
   if (overlap) fork_side(C);
   symv<T>(C, X[5], X[8], skip, overlap);
@@ -1223,8 +1239,178 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
   }
   if (overlap) join_side(C);
   if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[8], X[8], (T)1, skip);
+}
+
+template <class T>
+static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false, bool gathered = false) {
+  const int nr = C.nrhs;
+  hipStream_t st = C.st;
+  void **X = C.X;
+  if (!gathered)
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                       C.d_glam, p, (T*)X[5], nr, skip);
+  apply_local<T>(C, skip);
   hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
                      (const T*)X[8], Fp, dot ? p : (const double*)nullptr, nr, C.d_partial, skip);
+}
+
+// Robin variant: y = G lam = lam + lam(partner side) - R (x_G response of
+// the other side), with the response of every side computed by apply_local
+template <class T>
+static void apply_G(Ctx& C, const double* lam, double* y) {
+  const int nr = C.nrhs;
+  const int64_t n = C.n_grow, nl = n * nr;
+  hipStream_t st = C.st;
+  hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2, lam,
+                     (T*)C.X[5], nr, (const int*)nullptr);
+  apply_local<T>(C, nullptr);
+  hipLaunchKernelGGL(k_side_collect<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2,
+                     (const T*)C.X[8], C.d_gm_u, nr);
+  hipLaunchKernelGGL(k_robin_apply, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval, C.d_partner2,
+                     lam, (const double*)C.d_gm_u, y, nr);
+}
+
+// per-RHS dot products a . b over the side vectors, to the host
+static void side_dots(Ctx& C, const double* a, const double* b, double* out) {
+  const int nr = C.nrhs;
+  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, 1), dim3(256), 0, C.st, C.n_grow, 1, a, (int64_t)0, b, nr,
+                     C.d_gm_partial);
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(kMaxRhs), 0, C.st, 1, nr, kDotBlocks,
+                     (const double*)C.d_gm_partial, C.d_gm_ss, (double*)nullptr);
+  HIPCHK(hipMemcpyAsync(out, C.d_gm_ss, nr * sizeof(double), hipMemcpyDeviceToHost, C.st));
+  HIPCHK(hipStreamSynchronize(C.st));
+}
+
+// Restarted GMRES on G lam = rhs (Sec. III-B's multiplier system for the
+// edge-only unknowns), all right-hand sides in lock step: classical
+// Gram-Schmidt applied twice, Givens rotations on the host per RHS, stop when
+// ||rhs - G lam|| <= tol ||rhs|| for every RHS (or at the iteration cap).
+// The rhs is -R x0 with x0 the interface rows of the pre-solve (X4).
+template <class T>
+static int dp2_gmres(Ctx& C, int* iters, double* relres) {
+  const int nr = C.nrhs;
+  hipStream_t st = C.st;
+  const int64_t n = C.n_grow, nl = n * nr, ldv = nl;
+  const int m = kGmresRestart;
+  double* V = C.d_gmV;
+  auto vec = [&](int k) { return V + (int64_t)k * ldv; };
+  hipLaunchKernelGGL(k_side_collect<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2,
+                     (const T*)C.X[4], C.d_gm_u, nr);
+  hipLaunchKernelGGL(k_robin_apply, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
+                     C.d_partner2, (const double*)nullptr, (const double*)C.d_gm_u, C.d_gm_rhs, nr);
+  HIPCHK(hipMemsetAsync(C.d_lam2, 0, nl * sizeof(double), st));
+  double bnorm[kMaxRhs], ss[kMaxRhs];
+  side_dots(C, C.d_gm_rhs, C.d_gm_rhs, bnorm);
+  bool conv[kMaxRhs];
+  for (int r = 0; r < nr; ++r) {
+    bnorm[r] = std::sqrt(bnorm[r]);
+    conv[r] = !(bnorm[r] > 0.0);
+    iters[r] = 0;
+    relres[r] = 0.0;
+  }
+  std::vector<double> H((size_t)nr * (m + 1) * m), cs((size_t)nr * m), sn((size_t)nr * m), g((size_t)nr * (m + 1));
+  std::vector<double> htot((size_t)(m + 1) * kMaxRhs), y((size_t)m * kMaxRhs);
+  int total = 0;
+  const int cap = C.opt.cg_max_iter;
+  auto all_conv = [&]() {
+    for (int r = 0; r < nr; ++r)
+      if (!conv[r]) return false;
+    return true;
+  };
+  while (!all_conv() && total < cap) {
+    // r0 = rhs - G lam in V_0
+    if (total == 0) {
+      HIPCHK(hipMemcpyAsync(vec(0), C.d_gm_rhs, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+      apply_G<T>(C, C.d_lam2, vec(0));
+      hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs,
+                         (const double*)vec(0), vec(0));
+    }
+    side_dots(C, vec(0), vec(0), ss);
+    hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)vec(0),
+                       (const double*)C.d_gm_ss, vec(0), nr);
+    bool active[kMaxRhs];
+    int cols[kMaxRhs];
+    for (int r = 0; r < nr; ++r) {
+      active[r] = !conv[r];
+      cols[r] = 0;
+      std::fill(g.begin() + (size_t)r * (m + 1), g.begin() + (size_t)(r + 1) * (m + 1), 0.0);
+      g[(size_t)r * (m + 1)] = std::sqrt(std::max(ss[r], 0.0));
+    }
+    int j = 0;
+    for (; j < m && total < cap; ++j) {
+      double* w = vec(j + 1);
+      apply_G<T>(C, vec(j), w);
+      const int nv = j + 1;
+      HIPCHK(hipMemsetAsync(C.d_gm_tot, 0, (size_t)nv * kMaxRhs * sizeof(double), st));
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, (nv + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n, nv,
+                           (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial);
+        hipLaunchKernelGGL(k_mdot_reduce, dim3(nblk(nv * nr)), dim3(256), 0, st, nv, nr, kDotBlocks,
+                           (const double*)C.d_gm_partial, C.d_gm_h, C.d_gm_tot);
+        hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, nv, (const double*)V, ldv,
+                           (const double*)C.d_gm_h, -1.0, w, nr);
+      }
+      HIPCHK(hipMemcpyAsync(htot.data(), C.d_gm_tot, (size_t)nv * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost,
+                            st));
+      side_dots(C, w, w, ss);
+      hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)w,
+                         (const double*)C.d_gm_ss, w, nr);
+      ++total;
+      for (int r = 0; r < nr; ++r) {
+        if (!active[r] || conv[r]) continue;
+        double* h = &H[((size_t)r * m + j) * (m + 1)];  // column j of RHS r
+        for (int i = 0; i <= j; ++i) h[i] = htot[(size_t)i * kMaxRhs + r];
+        h[j + 1] = std::sqrt(std::max(ss[r], 0.0));
+        double* c = &cs[(size_t)r * m];
+        double* sv = &sn[(size_t)r * m];
+        for (int i = 0; i < j; ++i) {
+          const double a = h[i], b = h[i + 1];
+          h[i] = c[i] * a + sv[i] * b;
+          h[i + 1] = -sv[i] * a + c[i] * b;
+        }
+        const double d = std::hypot(h[j], h[j + 1]);
+        c[j] = d > 0.0 ? h[j] / d : 1.0;
+        sv[j] = d > 0.0 ? h[j + 1] / d : 0.0;
+        h[j] = d;
+        h[j + 1] = 0.0;
+        double* gr = &g[(size_t)r * (m + 1)];
+        gr[j + 1] = -sv[j] * gr[j];
+        gr[j] = c[j] * gr[j];
+        cols[r] = j + 1;
+        iters[r] = total;
+        relres[r] = std::fabs(gr[j + 1]) / bnorm[r];
+        if (relres[r] <= C.opt.cg_tol) conv[r] = true;
+      }
+      if (all_conv()) {
+        ++j;
+        break;
+      }
+    }
+    // lam += V y, y from the triangular systems of each RHS's first cols columns
+    int jmax = 0;
+    std::fill(y.begin(), y.end(), 0.0);
+    for (int r = 0; r < nr; ++r) {
+      const int k = cols[r];
+      jmax = std::max(jmax, k);
+      const double* gr = &g[(size_t)r * (m + 1)];
+      for (int i = k - 1; i >= 0; --i) {
+        double v = gr[i];
+        for (int q = i + 1; q < k; ++q) v -= H[((size_t)r * m + q) * (m + 1) + i] * y[(size_t)q * kMaxRhs + r];
+        const double diag = H[((size_t)r * m + i) * (m + 1) + i];
+        y[(size_t)i * kMaxRhs + r] = diag != 0.0 ? v / diag : 0.0;
+      }
+    }
+    if (jmax > 0) {
+      HIPCHK(hipMemcpyAsync(C.d_gm_y, y.data(), (size_t)jmax * kMaxRhs * sizeof(double), hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, jmax, (const double*)V, ldv,
+                         (const double*)C.d_gm_y, 1.0, C.d_lam2, nr);
+      HIPCHK(hipStreamSynchronize(st));
+    }
+    (void)j;
+  }
+  HIPCHK(hipGetLastError());
+  return all_conv() ? DD_OK : DD_ERR_NO_CONVERGENCE;
 }
 
 static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, double* out) {
@@ -1269,7 +1455,15 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     relres[r] = 0.0;
   }
   int status = DD_OK;
-  if (C.nlam > 0) {
+  if (C.nlam > 0 && C.opt.method == 1) {
+    // ---- Robin variant: GMRES on the per-side multipliers, then the same
+    // recovery with each subdomain's own multipliers as interface loads
+    status = dp2_gmres<T>(C, iters, relres);
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
+                       C.d_code2, (const double*)C.d_lam2, (T*)X[5], nr, (const int*)nullptr);
+    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
+    if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
+  } else if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
     hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
                        (const T*)X[4], C.d_d, (const double*)nullptr, nr, C.d_partial, (const int*)nullptr);
@@ -1557,6 +1751,170 @@ using namespace ddfem;
 // ===========================================================================
 // C ABI
 // ===========================================================================
+// ---- Robin variant: side maps, interface face masses, Robin terms ----------------
+// Tangential mass of the three edges (01, 02, 12) of a triangle p0 p1 p2 with
+// vertices in ascending global id: int_F (n x W_a).(n x W_b) dS, where the
+// tangential trace of a Whitney function on F is the triangle's own Whitney
+// function mu_i grad mu_j - mu_j grad mu_i, and int_F mu_a mu_b = A (1 + d_ab) / 12.
+static void face_tangential_mass(const double* p0, const double* p1, const double* p2, double M[3][3]) {
+  double e1[3], e2[3];
+  for (int c = 0; c < 3; ++c) {
+    e1[c] = p1[c] - p0[c];
+    e2[c] = p2[c] - p0[c];
+  }
+  const double a = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+  const double b = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+  const double d = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+  const double det = a * d - b * b;  // |e1 x e2|^2
+  double g[3][3];
+  for (int c = 0; c < 3; ++c) {
+    g[1][c] = (d * e1[c] - b * e2[c]) / det;
+    g[2][c] = (a * e2[c] - b * e1[c]) / det;
+    g[0][c] = -(g[1][c] + g[2][c]);
+  }
+  const double area = 0.5 * std::sqrt(det);
+  auto gg = [&](int i, int j) { return g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2]; };
+  auto mm = [](int i, int j) { return (i == j ? 2.0 : 1.0) / 12.0; };
+  const int LE[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (int A = 0; A < 3; ++A)
+    for (int B = 0; B < 3; ++B) {
+      const int i = LE[A][0], j = LE[A][1], k = LE[B][0], l = LE[B][1];
+      M[A][B] = area * (mm(i, k) * gg(j, l) - mm(i, l) * gg(j, k) - mm(j, k) * gg(i, l) + mm(j, l) * gg(i, k));
+    }
+}
+
+static void build_dp2(Ctx& C, const double* coords, const double* eps, const double* mu) {
+  const Plan& P = C.P;
+  hipStream_t st = C.st;
+  const int nsub = C.nsub;
+  const int nr = C.nrhs;
+  // side index = position in the interface-row list (d_grow)
+  std::vector<int64_t> gbase(nsub + 1, 0);
+  for (int s = 0; s < nsub; ++s) gbase[s + 1] = gbase[s] + (int64_t)(P.subs[s].kr() - P.subs[s].kI) * NB;
+  const int64_t ns = gbase[nsub];
+  if (ns != C.n_grow) throw DDError{DD_ERR_STATE, "interface row count mismatch"};
+  if (ns > INT32_MAX / 2) throw DDError{DD_ERR_ARG, "too many interface rows for the Robin variant"};
+  std::vector<int32_t> code2(ns, -1), partner2(ns, -1);
+  const int64_t nl = P.nlambda();
+  std::vector<int32_t> lam_of_dof(P.nint, -1);
+  std::vector<int64_t> side0(nl), side1(nl);
+  for (int64_t l = 0; l < nl; ++l) {
+    const int s0 = P.lam_s0[l], s1 = P.lam_s1[l];
+    side0[l] = gbase[s0] + (P.lam_p0[l] - P.subs[s0].nI);
+    side1[l] = gbase[s1] + (P.lam_p1[l] - P.subs[s1].nI);
+    code2[side0[l]] = (int32_t)(side0[l] << 1);
+    code2[side1[l]] = (int32_t)(side1[l] << 1);
+    partner2[side0[l]] = (int32_t)side1[l];
+    partner2[side1[l]] = (int32_t)side0[l];
+    lam_of_dof[P.lam_dof[l]] = (int32_t)l;
+  }
+  auto side_in = [&](int64_t l, int s) { return P.lam_s0[l] == s ? side0[l] : side1[l]; };
+  auto row_in = [&](int64_t l, int s) {
+    return P.lam_s0[l] == s ? P.padded_row(s, P.lam_p0[l]) : P.padded_row(s, P.lam_p1[l]);
+  };
+  // alpha: half the sum of the mass and curl-curl scales of an edge unknown,
+  // eps h and beta dt^2 / (mu h), h the mean edge length
+  double hsum = 0.0;
+  for (int64_t e = 0; e < P.ne; ++e) {
+    const double* a = coords + 3 * (int64_t)P.edges[2 * e];
+    const double* b = coords + 3 * (int64_t)P.edges[2 * e + 1];
+    hsum += std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) + (a[2] - b[2]) * (a[2] - b[2]));
+  }
+  const double h = hsum / std::max<int64_t>(1, P.ne);
+  double es = 0.0, ms = 0.0;
+  for (int64_t t = 0; t < P.nt; ++t) {
+    es += eps[t];
+    ms += mu ? mu[t] : 1.0;
+  }
+  es /= std::max<int64_t>(1, P.nt);
+  ms /= std::max<int64_t>(1, P.nt);
+  C.robin_alpha = C.opt.robin_alpha > 0 ? C.opt.robin_alpha : 0.5 * (es * h + C.beta * C.dt * C.dt / (ms * h));
+  // interface faces: R entries (side space) and Robin terms of both local blocks
+  std::vector<int32_t> nbr;
+  std::string msg;
+  if (face_neighbors(P, nbr, msg) != 0) throw DDError{DD_ERR_MESH, msg};
+  std::vector<std::tuple<int64_t, int64_t, double>> R;
+  std::vector<std::pair<int64_t, double>> add;
+  const int LE6[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+  for (int64_t t = 0; t < P.nt; ++t)
+    for (int k = 0; k < 4; ++k) {
+      const int64_t u = nbr[4 * t + k];
+      if (u < 0 || u < t) continue;
+      const int s = P.part[t], j = P.part[u];
+      if (s == j) continue;
+      int L[3], m = 0;
+      for (int i = 0; i < 4; ++i)
+        if (i != k) L[m++] = i;
+      double M[3][3];
+      face_tangential_mass(coords + 3 * (int64_t)P.tsort[4 * t + L[0]], coords + 3 * (int64_t)P.tsort[4 * t + L[1]],
+                           coords + 3 * (int64_t)P.tsort[4 * t + L[2]], M);
+      const int FE[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+      int64_t lam[3];
+      for (int a = 0; a < 3; ++a) {
+        const int32_t d = P.dof[P.tet_edges[6 * t + LE6[L[FE[a][0]]][L[FE[a][1]]]]];
+        lam[a] = d >= 0 ? lam_of_dof[d] : -1;
+      }
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          if (lam[a] < 0 || lam[b] < 0) continue;
+          const double v = M[a][b];
+          R.emplace_back(side_in(lam[a], s), side_in(lam[b], j), 2.0 * C.robin_alpha * v);
+          R.emplace_back(side_in(lam[a], j), side_in(lam[b], s), 2.0 * C.robin_alpha * v);
+          for (int q : {s, j}) {
+            const int32_t ra = row_in(lam[a], q), rb = row_in(lam[b], q);
+            if (ra < rb) continue;
+            const SubDev& qd = C.subs_h[q];
+            const int64_t ti = qd.tile_off + (int64_t)(ra / NB) * (ra / NB + 1) / 2 + rb / NB;
+            add.emplace_back(ti * kTile + (ra % NB) * NB + (rb % NB), v);
+          }
+        }
+    }
+  std::sort(R.begin(), R.end());
+  std::vector<int64_t> rrp(ns + 1, 0);
+  std::vector<int32_t> rci;
+  std::vector<double> rval;
+  for (size_t i = 0; i < R.size();) {
+    size_t k = i;
+    double v = 0.0;
+    while (k < R.size() && std::get<0>(R[k]) == std::get<0>(R[i]) && std::get<1>(R[k]) == std::get<1>(R[i]))
+      v += std::get<2>(R[k++]);
+    rrp[std::get<0>(R[i]) + 1]++;
+    rci.push_back((int32_t)std::get<1>(R[i]));
+    rval.push_back(v);
+    i = k;
+  }
+  for (int64_t i = 0; i < ns; ++i) rrp[i + 1] += rrp[i];
+  std::sort(add.begin(), add.end());
+  std::vector<int64_t> apos;
+  std::vector<double> aval;
+  for (size_t i = 0; i < add.size();) {
+    size_t k = i;
+    double v = 0.0;
+    while (k < add.size() && add[k].first == add[i].first) v += add[k++].second;
+    apos.push_back(add[i].first);
+    aval.push_back(v);
+    i = k;
+  }
+  C.d_code2 = upload(code2, C.owned, st);
+  C.d_partner2 = upload(partner2, C.owned, st);
+  C.d_rrp = upload(rrp, C.owned, st);
+  C.d_rci = upload(rci, C.owned, st);
+  C.d_rval = upload(rval, C.owned, st);
+  C.n_radd = (int64_t)apos.size();
+  C.d_radd_pos = upload(apos, C.owned, st);
+  C.d_radd_val = upload(aval, C.owned, st);
+  const int64_t nv = ns * nr;
+  C.d_gmV = dalloc<double>((size_t)(kGmresRestart + 1) * nv, C.owned);
+  C.d_gm_u = dalloc<double>(nv, C.owned);
+  C.d_gm_rhs = dalloc<double>(nv, C.owned);
+  C.d_lam2 = dalloc<double>(nv, C.owned);
+  C.d_gm_partial = dalloc<double>((size_t)(kGmresRestart + 1) * kDotBlocks * kMaxRhs, C.owned);
+  C.d_gm_h = dalloc<double>((size_t)(kGmresRestart + 1) * kMaxRhs, C.owned);
+  C.d_gm_tot = dalloc<double>((size_t)(kGmresRestart + 1) * kMaxRhs, C.owned);
+  C.d_gm_ss = dalloc<double>(kMaxRhs, C.owned);
+  C.d_gm_y = dalloc<double>((size_t)kGmresRestart * kMaxRhs, C.owned);
+}
+
 #define API_BEGIN try {
 #define API_END                                 \
   }                                             \
@@ -1589,6 +1947,8 @@ void dd_default_options(dd_options* o) {
   o->check_every = 4;
   o->stream = nullptr;
   o->precond = 1;
+  o->method = 0;
+  o->robin_alpha = 0.0;
 }
 
 const char* dd_last_error(void) { return g_err.c_str(); }
@@ -1614,6 +1974,8 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
   if (opt) o = *opt;
   if (o.nrhs < 1 || o.nrhs > kMaxRhs) throw DDError{DD_ERR_ARG, "nrhs must be in 1..32"};
   if (o.precond != 0 && o.precond != 1) throw DDError{DD_ERR_ARG, "precond must be 0 or 1"};
+  if (o.method != 0 && o.method != 1) throw DDError{DD_ERR_ARG, "method must be 0 or 1"};
+  if (!std::isfinite(o.robin_alpha) || o.robin_alpha < 0) throw DDError{DD_ERR_ARG, "robin_alpha must be >= 0"};
   if (o.precision != DD_FP64 && o.precision != DD_FP32_REFINE) throw DDError{DD_ERR_ARG, "unknown precision"};
   if (!(o.cg_tol > 0) || o.cg_max_iter < 1 || o.check_every < 1 || o.refine_max < 0 || !(o.refine_tol > 0))
     throw DDError{DD_ERR_ARG, "bad solver option"};
@@ -1637,6 +1999,7 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
   int rc = build_plan(n_vertices, coords, n_tets, tets, partition, C->P, msg);
   if (rc != DD_OK) throw DDError{rc, msg};
   build_device(*C, coords);
+  if (o.method == 1) build_dp2(*C, coords, eps, mu);
   std::vector<double> mh(n_tets, 1.0);
   if (mu) mh.assign(mu, mu + n_tets);
   HIPCHK(hipMemcpyAsync(C->d_mu, mh.data(), n_tets * sizeof(double), hipMemcpyHostToDevice, C->st));

@@ -1,0 +1,135 @@
+// Device kernels of the Robin dual-primal variant (Sec. III-B, adapted to the
+// edge-only system) and of its GMRES interface solver.
+//
+// Multipliers live per side: every interface row of every subdomain (the
+// kI*NB .. kr*NB rows of its local vector, padding included) is one entry of
+// a "side vector" [n_side][nrhs], in the order of those rows.  Padding rows
+// are inert (code -1, no Robin row, no partner).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ddfem {
+
+constexpr int kGmresRestart = 40;  // Krylov vectors kept before a restart
+
+// tiles[pos[i]] += alpha * val[i]  (Robin term on the interface block, before
+// the factorisation; positions are distinct)
+template <class T>
+__global__ void __launch_bounds__(256) k_add_entries(int64_t n, const int64_t* __restrict__ pos,
+                                                     const double* __restrict__ val, double alpha,
+                                                     T* __restrict__ tiles) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  tiles[pos[i]] = (T)((double)tiles[pos[i]] + alpha * val[i]);
+}
+
+// out[i][r] = u[rows[i]][r] for live sides, 0 for padding
+template <class T>
+__global__ void __launch_bounds__(256) k_side_collect(int64_t n, const int64_t* __restrict__ rows,
+                                                      const int32_t* __restrict__ code, const T* __restrict__ u,
+                                                      double* __restrict__ out, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const int64_t k = i / nrhs;
+  const int r = (int)(i - k * nrhs);
+  out[i] = code[k] >= 0 ? (double)u[rows[k] * nrhs + r] : 0.0;
+}
+
+// Transmission residual of the Robin condition on every side:
+//   y[i] = lam[i] + lam[partner[i]] - sum_k R[i][k] u[k]
+// (R = 2 alpha M_T, columns on the partner's sides); lam == nullptr gives
+// y = -R u.
+__global__ void __launch_bounds__(256) k_robin_apply(int64_t n, const int64_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                     const int32_t* __restrict__ partner,
+                                                     const double* __restrict__ lam, const double* __restrict__ u,
+                                                     double* __restrict__ y, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const int64_t k = i / nrhs;
+  const int r = (int)(i - k * nrhs);
+  double s = 0.0;
+  if (lam) {
+    s = lam[i];
+    const int32_t q = partner[k];
+    if (q >= 0) s += lam[(int64_t)q * nrhs + r];
+  }
+  for (int64_t j = rp[k]; j < rp[k + 1]; ++j) s -= val[j] * u[(int64_t)ci[j] * nrhs + r];
+  y[i] = s;
+}
+
+// Block shares of nv dot products V_k . w per right-hand side:
+// partial[(k * gridDim.x + b) * kMaxRhs + r] (fixed order, no atomics).
+// Workgroup row y takes vectors 8y .. 8y+7, so w is read once per 8 vectors.
+constexpr int kMdotChunk = 8;
+
+__global__ void __launch_bounds__(256) k_mdot(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                              const double* __restrict__ w, int nrhs, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int lpr = 256 / nrhs;
+  const int r = tid % nrhs, lane = tid / nrhs;
+  const int k0 = blockIdx.y * kMdotChunk;
+  const int kn = nv - k0 < kMdotChunk ? nv - k0 : kMdotChunk;
+  double s[kMdotChunk];
+#pragma unroll
+  for (int k = 0; k < kMdotChunk; ++k) s[k] = 0.0;
+  if (lane < lpr)
+    for (int64_t row = (int64_t)blockIdx.x * lpr + lane; row < n; row += (int64_t)gridDim.x * lpr) {
+      const int64_t e = row * nrhs + r;
+      const double x = w[e];
+#pragma unroll
+      for (int k = 0; k < kMdotChunk; ++k)
+        if (k < kn) s[k] += V[(k0 + k) * ldv + e] * x;
+    }
+#pragma unroll
+  for (int k = 0; k < kMdotChunk; ++k) {
+    if (k >= kn) break;
+    red[tid] = s[k];
+    __syncthreads();
+    if (tid < nrhs) {
+      double t = 0.0;
+      for (int l = 0; l < lpr; ++l) t += red[l * nrhs + tid];
+      partial[((int64_t)(k0 + k) * gridDim.x + blockIdx.x) * kMaxRhs + tid] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// h[k][r] = sum_b partial (fixed order); tot[k][r] += h[k][r] if tot
+__global__ void k_mdot_reduce(int nv, int nrhs, int nblocks, const double* __restrict__ partial,
+                              double* __restrict__ h, double* __restrict__ tot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * nrhs) return;
+  const int k = i / nrhs, r = i - k * nrhs;
+  double s = 0.0;
+  for (int b = 0; b < nblocks; ++b) s += partial[((int64_t)k * nblocks + b) * kMaxRhs + r];
+  h[k * kMaxRhs + r] = s;
+  if (tot) tot[k * kMaxRhs + r] += s;
+}
+
+// w[i][r] += sgn * sum_k h[k][r] V_k[i][r]
+__global__ void __launch_bounds__(256) k_mupdate(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ h, double sgn, double* __restrict__ w,
+                                                 int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const int r = (int)(i % nrhs);
+  double s = 0.0;
+  for (int k = 0; k < nv; ++k) s += h[k * kMaxRhs + r] * V[k * ldv + i];
+  w[i] += sgn * s;
+}
+
+// out = w / sqrt(ss[r]) per right-hand side (0 where ss is not positive)
+__global__ void __launch_bounds__(256) k_vnormalize(int64_t n, const double* w, const double* __restrict__ ss,
+                                                    double* out, int nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nrhs) return;
+  const double q = ss[i % nrhs];
+  out[i] = q > 0.0 ? w[i] / sqrt(q) : 0.0;
+}
+
+}  // namespace ddfem

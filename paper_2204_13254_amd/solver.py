@@ -63,7 +63,7 @@ class DDSolver:
     def __init__(self, coords, tets, partition, eps, mu=None, dt=0.05, beta=0.25, *,
                  precision="fp64", nrhs=1, cg_tol=1e-10, cg_max_iter=500, refine_tol=1e-12,
                  refine_max=10, warm_start=0, check_every=4, stream=None, factor=True,
-                 use_graph=False, precond=1):
+                 use_graph=False, precond=1, method="dp1", robin_alpha=0.0):
         self.lib = load()
         o = Options()
         self.lib.dd_default_options(C.byref(o))
@@ -77,6 +77,10 @@ class DDSolver:
         o.check_every = int(check_every)
         o.use_graph = int(bool(use_graph))
         o.precond = int(precond)
+        if method not in ("dp1", "dp2"):
+            raise ValueError("method must be 'dp1' or 'dp2'")
+        o.method = 1 if method == "dp2" else 0
+        o.robin_alpha = float(robin_alpha)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
