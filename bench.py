@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--workload", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--dp2-steps", type=int, default=3,
+                    help="also time this many steps of the Robin variant (one multiplier per side, GMRES); "
+                         "0 skips it")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--warm", type=int, default=0,
@@ -390,6 +393,43 @@ def main():
         del x, y
 
     # ---------------- plain FP64 form --------------------------------------------------
+    # ---------------- Robin variant (one multiplier per side, GMRES) -----------------------
+    dp2 = None
+    if args.dp2_steps > 0:
+        t0 = time.perf_counter()
+        q = DDSolver(coords, tets, part, eps, dt=w.dt, beta=w.beta, precision="fp32_refine", nrhs=w.nrhs,
+                     cg_tol=1e-6, refine_tol=1e-12, refine_max=10, factor=False, stream=stream,
+                     method="dp2", cg_max_iter=400)
+        q.factor()
+        torch.cuda.synchronize()
+        t_q = time.perf_counter() - t0
+        Eq = [zero.clone() for _ in range(3)]
+        qit, qres = [], []
+
+        def dp2_step(k, Jp):
+            q.step(Jd[k], Jp, Eq[1], Eq[0], Eq[2], stats=True)
+            st = q.last_stats()
+            Eq.append(Eq.pop(0))
+            return st
+
+        dp2_step(0, zero)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K2 = min(args.dp2_steps, W + K - 1)
+        for k in range(1, 1 + K2):
+            st = dp2_step(k, Jd[k - 1])
+            qit.append(st["solve_iters"][:1 + st["refine_sweeps"]])
+            qres.append(max(st["global_relres"]))
+        torch.cuda.synchronize()
+        t_dp2 = time.perf_counter() - t0
+        dp2 = {"steps_per_s": round(K2 / t_dp2, 4), "ms_per_step": round(1e3 * t_dp2 / K2, 2),
+               "steps_timed": K2, "gmres_iters_per_step": qit, "max_global_relres": max(qres),
+               "setup_factor_s": round(t_q, 2),
+               "form": "Robin multipliers per side, GMRES(40) tol 1e-6 + FP64 refinement to 1e-12"}
+        log(f"dp2: {dp2}")
+        del q, Eq
+        torch.cuda.empty_cache()
+
     plain = None
     if not args.no_plain and args.plain_steps > 0:
         del s
@@ -440,6 +480,7 @@ def main():
         "factor_s": round(t_factor, 3), "setup_s": round(t_setup, 2),
         "kernel_classes": other,
         "plain_fp64": plain,
+        "robin_dp2": dp2,
         "pic": pic,
         "speedup_vs_plain_fp64": (round(sps / plain["steps_per_s"], 2) if plain else None),
     }
