@@ -1351,11 +1351,18 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
         hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, nv, (const double*)V, ldv,
                            (const double*)C.d_gm_h, -1.0, w, nr);
       }
-      HIPCHK(hipMemcpyAsync(htot.data(), C.d_gm_tot, (size_t)nv * kMaxRhs * sizeof(double), hipMemcpyDeviceToHost,
-                            st));
-      side_dots(C, w, w, ss);
-      hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)w,
-                         (const double*)C.d_gm_ss, w, nr);
+      // |w|^2 into row nv of the coefficient block: one copy and one wait per iteration
+      double* wss = C.d_gm_tot + (size_t)nv * kMaxRhs;
+      hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, 1), dim3(256), 0, st, n, 1, (const double*)w, (int64_t)0,
+                         (const double*)w, nr, C.d_gm_partial);
+      hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(kMaxRhs), 0, st, 1, nr, kDotBlocks,
+                         (const double*)C.d_gm_partial, wss, (double*)nullptr);
+      HIPCHK(hipMemcpyAsync(htot.data(), C.d_gm_tot, (size_t)(nv + 1) * kMaxRhs * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+      hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)w, (const double*)wss, w,
+                         nr);
+      HIPCHK(hipStreamSynchronize(st));
+      for (int r = 0; r < nr; ++r) ss[r] = htot[(size_t)nv * kMaxRhs + r];
       ++total;
       for (int r = 0; r < nr; ++r) {
         if (!active[r] || conv[r]) continue;
