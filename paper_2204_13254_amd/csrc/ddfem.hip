@@ -1275,7 +1275,7 @@ static void side_dots(Ctx& C, const double* a, const double* b, double* out) {
   const int nr = C.nrhs;
   hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, 1), dim3(256), 0, C.st, C.n_grow, 1, a, (int64_t)0, b, nr,
                      C.d_gm_partial);
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(kMaxRhs), 0, C.st, 1, nr, kDotBlocks,
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(256), 0, C.st, 1, nr, kDotBlocks,
                      (const double*)C.d_gm_partial, C.d_gm_ss, (double*)nullptr);
   HIPCHK(hipMemcpyAsync(out, C.d_gm_ss, nr * sizeof(double), hipMemcpyDeviceToHost, C.st));
   HIPCHK(hipStreamSynchronize(C.st));
@@ -1346,7 +1346,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, (nv + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n, nv,
                            (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial);
-        hipLaunchKernelGGL(k_mdot_reduce, dim3(nblk(nv * nr)), dim3(256), 0, st, nv, nr, kDotBlocks,
+        hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(256), 0, st, nv, nr, kDotBlocks,
                            (const double*)C.d_gm_partial, C.d_gm_h, C.d_gm_tot);
         hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, nv, (const double*)V, ldv,
                            (const double*)C.d_gm_h, -1.0, w, nr);
@@ -1355,7 +1355,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
       double* wss = C.d_gm_tot + (size_t)nv * kMaxRhs;
       hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, 1), dim3(256), 0, st, n, 1, (const double*)w, (int64_t)0,
                          (const double*)w, nr, C.d_gm_partial);
-      hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(kMaxRhs), 0, st, 1, nr, kDotBlocks,
+      hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(256), 0, st, 1, nr, kDotBlocks,
                          (const double*)C.d_gm_partial, wss, (double*)nullptr);
       HIPCHK(hipMemcpyAsync(htot.data(), C.d_gm_tot, (size_t)(nv + 1) * kMaxRhs * sizeof(double),
                             hipMemcpyDeviceToHost, st));

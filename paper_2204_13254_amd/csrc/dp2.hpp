@@ -99,16 +99,30 @@ __global__ void __launch_bounds__(256) k_mdot(int64_t n, int nv, const double* _
   }
 }
 
-// h[k][r] = sum_b partial (fixed order); tot[k][r] += h[k][r] if tot
-__global__ void k_mdot_reduce(int nv, int nrhs, int nblocks, const double* __restrict__ partial,
-                              double* __restrict__ h, double* __restrict__ tot) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nv * nrhs) return;
-  const int k = i / nrhs, r = i - k * nrhs;
+// h[k][r] = sum_b partial (fixed order); tot[k][r] += h[k][r] if tot.  One
+// workgroup per k: a power-of-two number of lanes per right-hand side take
+// strided block shares, then a fixed-shape tree in LDS.
+__global__ void __launch_bounds__(256) k_mdot_reduce(int nv, int nrhs, int nblocks, const double* __restrict__ partial,
+                                                     double* __restrict__ h, double* __restrict__ tot) {
+  __shared__ double red[256];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  int lpr = 1;  // lanes per right-hand side: a power of two, so the tree halves evenly
+  while (2 * lpr * nrhs <= 256) lpr *= 2;
+  const int r = tid % nrhs, lane = tid / nrhs;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[((int64_t)k * nblocks + b) * kMaxRhs + r];
-  h[k * kMaxRhs + r] = s;
-  if (tot) tot[k * kMaxRhs + r] += s;
+  if (lane < lpr)
+    for (int b = lane; b < nblocks; b += lpr) s += partial[((int64_t)k * nblocks + b) * kMaxRhs + r];
+  red[tid] = s;
+  __syncthreads();
+  for (int half = lpr / 2; half > 0; half /= 2) {
+    if (lane < half) red[tid] += red[tid + half * nrhs];
+    __syncthreads();
+  }
+  if (tid < nrhs) {
+    h[k * kMaxRhs + tid] = red[tid];
+    if (tot) tot[k * kMaxRhs + tid] += red[tid];
+  }
 }
 
 // w[i][r] += sgn * sum_k h[k][r] V_k[i][r]
