@@ -58,26 +58,29 @@ def make_sources(w, coords, tets, steps, workers, start_method="fork"):
     return np.stack(parts, axis=1)          # [steps, nrhs, n_e]
 
 
-def cpu_baseline(target_nint, nrhs, seconds_hint=20.0):
+def cpu_baseline(target_nint, nrhs, seconds_hint=15.0):
     """The oracle (nested-dissection SuperLU, FP64) on a bounded sample:
-    the 24^3 cavity of the same family, factorisation + a few Newmark steps of
-    `nrhs` right-hand sides.  Scaled to the target size linearly in the
+    the 24^3 cavity of the same family, factorisation + Newmark steps of `nrhs`
+    right-hand sides until about `seconds_hint` seconds have passed.  Scaled to the target size linearly in the
     number of unknowns (optimistic for the CPU: a direct solve grows faster)."""
     import numpy as np
     from oracle.newmark import NewmarkOracle
     from workloads.mesh import cube_mesh
     from workloads.sources import dense_random_source
-    n, dt, steps = 24, 0.008, 3
+    n, dt, max_steps = 24, 0.008, 60
     c, t, _ = cube_mesh(n)
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     t0 = time.perf_counter()
     o = NewmarkOracle(c, t, dt=dt)
     t1 = time.perf_counter()
-    J = o.d.restrict(dense_random_source(o.d.n_e, ~o.d.pec, steps, dt, steps * dt / 2, dt, 7, nrhs=nrhs))
+    J = o.d.restrict(dense_random_source(o.d.n_e, ~o.d.pec, max_steps, dt, 10 * dt, 4 * dt, 7, nrhs=nrhs))
     e_nm1 = np.zeros((nrhs, o.d.n_int)); e_n = e_nm1.copy(); jp = e_nm1.copy()
-    for k in range(steps):
-        e = o.step(e_n, e_nm1, J[k], jp)
-        e_nm1, e_n, jp = e_n, e, J[k]
+    steps = 0
+    # at least 3 steps, then until about seconds_hint of wall time has passed
+    while steps < 3 or (time.perf_counter() - t0 < seconds_hint and steps < max_steps):
+        e = o.step(e_n, e_nm1, J[steps], jp)
+        e_nm1, e_n, jp = e_n, e, J[steps]
+        steps += 1
     t2 = time.perf_counter()
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
