@@ -101,3 +101,66 @@ def test_same_answer_as_first_variant():
     x1 = s1.solve(torch.tensor(bb, device="cuda")).cpu().numpy()
     x2 = s2.solve(torch.tensor(bb, device="cuda")).cpu().numpy()
     assert relerr(x2, x1).max() <= 1e-10
+
+
+@pytest.mark.parametrize("method", ["dp1", "dp2"])
+def test_one_subdomain_and_zero_rhs(method):
+    """Degenerate decompositions: one subdomain (no multipliers, no corners:
+    the stored inverse is the whole solve) and a zero right-hand side."""
+    from paper_2204_13254_amd.solver import DDSolver
+    n = 4
+    c, t, _ = cube_mesh(n)
+    eps = np.random.default_rng(2).uniform(1, 2, len(t))
+    o = NewmarkOracle(c, t, eps=eps, dt=0.05)
+    b = np.random.default_rng(5).standard_normal((2, o.d.n_e))
+    b[:, o.d.pec] = 0.0
+    for parts in (1, 2):
+        s = DDSolver(c, t, box_partition(n, parts), eps, dt=0.05, nrhs=2, cg_tol=1e-13, cg_max_iter=400,
+                     method=method)
+        x = s.solve(torch.tensor(b, device="cuda")).cpu().numpy()
+        assert relerr(x, o.d.extend(o.solve(o.d.restrict(b)))).max() <= 1e-10
+        z = s.solve(torch.zeros((2, o.d.n_e), dtype=torch.float64, device="cuda")).cpu().numpy()
+        assert np.all(z == 0.0)
+
+
+def test_dp2_32_rhs_fp32_refine():
+    """The widest right-hand-side block with the Robin variant."""
+    n, dt, nrhs = 6, 0.04, 32
+    c, t, _ = cube_mesh(n)
+    p = rcb_partition(n, 3, 2)
+    eps = np.ones(len(t))
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, 3, dt, 0.06, 0.03, seed=12, nrhs=nrhs)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, precision="fp32_refine", cg_tol=1e-6, refine_tol=1e-12,
+                cg_max_iter=400)
+    E, its = _run(s, J)
+    err = relerr(E[1:], o.run(J)[1:])
+    print("32 rhs max rel err", err.max(), "iterations", its, flush=True)
+    assert err.max() <= 1e-8
+
+
+def test_dp2_adjoint_step_matches_first_variant():
+    """The reverse step reuses the decomposed solve (A is symmetric); both
+    variants give the same adjoint quantities."""
+    from paper_2204_13254_amd.solver import DDSolver
+    n, dt = 5, 0.05
+    c, t, _ = cube_mesh(n)
+    p = box_partition(n, 2)
+    eps = np.random.default_rng(6).uniform(1, 3, len(t))
+    rng = np.random.default_rng(9)
+    out = {}
+    for method in ("dp1", "dp2"):
+        s = DDSolver(c, t, p, eps, dt=dt, cg_tol=1e-13, cg_max_iter=400, method=method)
+        ne = s.n_edges
+        _, pec = s.edges()
+        vals = rng.standard_normal((4, 1, ne)) if method == "dp1" else vals
+        v = vals.copy()
+        v[:, :, pec.astype(bool)] = 0.0
+        d = [torch.tensor(x, device="cuda") for x in v]
+        eb_n = torch.zeros((1, ne), dtype=torch.float64, device="cuda")
+        eb_m = torch.zeros((1, ne), dtype=torch.float64, device="cuda")
+        epsbar = torch.zeros(len(t), dtype=torch.float64, device="cuda")
+        g = s.adjoint_step(d[0], eb_n, eb_m, d[1], d[2], d[3], epsbar)
+        out[method] = [x.cpu().numpy() for x in (g, eb_n, eb_m, epsbar)]
+    for a, b in zip(out["dp2"], out["dp1"]):
+        assert relerr(a.reshape(1, -1), b.reshape(1, -1)).max() <= 1e-10
