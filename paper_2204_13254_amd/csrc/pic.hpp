@@ -100,19 +100,20 @@ __device__ __forceinline__ void line_exit(const PicTet& T, const double a[3], co
   double lb[4];
   barycentric(T, a, la);
   barycentric(T, b, lb);
-  s1 = 1.0;
+  // smallest la_k / -d_k over decreasing lam_k, compared as cross products
+  // (denominators positive) so that only the chosen face costs a division
+  double num = 1.0, den = 1.0;
   kx = -1;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     d[k] = lb[k] - la[k];
-    if (d[k] < 0.0) {
-      const double s = la[k] / -d[k];
-      if (s < s1) {
-        s1 = s;
-        kx = k;
-      }
+    if (d[k] < 0.0 && la[k] * den < num * -d[k]) {
+      num = la[k];
+      den = -d[k];
+      kx = k;
     }
   }
+  s1 = kx < 0 ? 1.0 : num / den;
 }
 
 // Point location: walk the straight line from the centroid of the start
@@ -166,9 +167,11 @@ __global__ void __launch_bounds__(256) k_pic_locate(int64_t n, int64_t nt, const
 // table (open addressing, kDepProbes probes, then straight to J) and the
 // table is added to J with one atomic per distinct edge: with particles in
 // cell order a workgroup covers a few hexahedra' worth of tetrahedra, so
-// most contributions meet in LDS.  A path that reaches an outer face
-// deposits up to it and the particle becomes inactive (cell = -1); so does a
-// walk longer than max_cross faces.  Inactive particles are skipped.
+// most contributions meet in LDS.  Before that, the first pieces of paths
+// that start in the same cell in adjacent lanes are summed in registers.
+// A path that reaches an outer face deposits up to it and the particle
+// becomes inactive (cell = -1); so does a walk longer than max_cross faces.
+// Inactive particles are skipped.
 constexpr int kDepThreads = 512;
 constexpr int kDepSlotBits = 11;
 constexpr int kDepSlots = 1 << kDepSlotBits;
@@ -215,41 +218,88 @@ __global__ void __launch_bounds__(kDepThreads) k_pic_deposit(int64_t n, int64_t 
   }
   __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * kDepThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63;
   int64_t t = p < n ? (int64_t)cell[p] : -1;
   if (t >= nt) {
     cell[p] = -1;
     atomicAdd(&cnt[kPicBadCell], 1ull);
     t = -1;
   }
-  if (t >= 0) {
-    double a[3], b[3];
+  const bool act = t >= 0;
+  // first piece (in the start cell) of every path
+  double a[3], b[3], v[6], w = 0.0, s1 = 1.0;
+  int kx = -1;
+  if (act) {
     for (int c = 0; c < 3; ++c) {
       a[c] = xa[3 * p + c];
       b[c] = xb[3 * p + c];
     }
-    const double w = q[p] * inv_dt;
-    double s0 = 0.0;
-    for (int it = 0;; ++it) {
-      PicTet T;
-      load_tet(geo, t, T);
-      double la[4], d[4], s1;
-      int kx;
-      line_exit(T, a, b, la, d, s1, kx);
-      if (s1 < s0) s1 = s0;
-      if (s1 > s0) dep_piece(keys, vals, J, tedge + 6 * t, la, d, s0, w * (s1 - s0));
-      if (kx < 0) {
-        cell[p] = (int32_t)t;
-        break;
+    w = q[p] * inv_dt;
+    PicTet T;
+    load_tet(geo, t, T);
+    double la[4], d[4];
+    line_exit(T, a, b, la, d, s1, kx);
+    if (s1 < 0.0) s1 = 0.0;
+    const double c = w * s1;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int i = kPicEdges[e][0], j = kPicEdges[e][1];
+      v[e] = c * (la[i] * d[j] - la[j] * d[i]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) v[e] = 0.0;
+  }
+  // runs of equal start cells in adjacent lanes (particles in cell order)
+  // are summed in registers first (segmented scan; the last lane of a run
+  // holds its sum), so the table sees one insert per run and edge
+  const int key = act ? (int)t : -1 - lane;
+  // both neighbour keys are exchanged by every lane (a shuffle inside a
+  // short-circuited condition would run with its source lane switched off)
+  const int kprev = __shfl_up(key, 1), knext = __shfl_down(key, 1);
+  int f = (lane == 0) || (kprev != key);
+  if (__any(!f)) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      double u[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) u[e] = __shfl_up(v[e], off);
+      const int fu = __shfl_up(f, off);
+      if (lane >= off) {
+        if (!f) {
+#pragma unroll
+          for (int e = 0; e < 6; ++e) v[e] += u[e];
+        }
+        f |= fu;
       }
-      s0 = s1;
+    }
+  }
+  const bool tail = lane == 63 || knext != key;
+  if (act) {
+    if (tail) {
+      const int32_t* te = tedge + 6 * t;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) dep_add(keys, vals, J, te[e], v[e]);
+    }
+    // the rest of the path, piece by piece
+    double s0 = s1;
+    for (int it = 0; kx >= 0; ++it) {
       const int32_t tn = nbr[4 * t + kx];
       if (tn < 0 || it + 1 >= max_cross) {
-        cell[p] = -1;
+        t = -1;
         atomicAdd(&cnt[tn < 0 ? kPicLeftMesh : kPicWalkCap], 1ull);
         break;
       }
       t = tn;
+      PicTet T;
+      load_tet(geo, t, T);
+      double la[4], d[4];
+      line_exit(T, a, b, la, d, s1, kx);
+      if (s1 < s0) s1 = s0;
+      if (s1 > s0) dep_piece(keys, vals, J, tedge + 6 * t, la, d, s0, w * (s1 - s0));
+      s0 = s1;
     }
+    cell[p] = (int32_t)t;
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kDepSlots; i += kDepThreads) {
