@@ -232,8 +232,8 @@ int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, con
  * perm[i] = the particle that goes to place i; cells ascending, inactive
  * particles (cell -1 or out of range) last, order within one cell
  * unspecified.  Apply it to every per-particle array (cell included) with
- * dd_pic_permute.  With particles in cell order the deposit sums the first
- * pieces of the paths that share a tetrahedron inside a wavefront before its
+ * dd_pic_permute.  With particles in cell order the deposit's
+ * contributions to one edge meet in registers and in LDS before its device
  * atomics, and the push's field gathers hit the cache; particles move a
  * fraction of a cell per step, so an order lasts many steps.
  * n <= 2^31 - 1. */
