@@ -125,7 +125,7 @@ def _traffic_from_profiles(cls):
     return None if v is None else v.get("bytes_per_launch")
 
 
-def pic_leg(s, w, E, steps, dev, log, sort_every=10, cycles=5):
+def pic_leg(s, w, E, steps, dev, log, sort_every=10, cycles=5, cpu_sample=0):
     """Particle steps on the workload's beam (Sec. II-A): per RHS, Whitney
     interpolation + Adams-Bashforth push, exact current deposit of the
     x^n -> x^{n+1} paths and Faraday's update of the per-tetrahedron B;
@@ -267,8 +267,44 @@ def pic_leg(s, w, E, steps, dev, log, sort_every=10, cycles=5):
             "gauss_residual_max": gmax, "charge_max": qmax,
             "gauss_relative": (gmax / qmax) if qmax > 0 else None,
             "walk_cap_or_bad_index": st["walk_cap"] + st["bad_index"]}
+    if cpu_sample > 0:
+        res["cpu_baseline"] = pic_cpu_baseline(w, cpu_sample)
     log(f"pic: {res}")
     return res
+
+
+def pic_cpu_baseline(w, m):
+    """The particle-step oracle (brute-force piece search and Whitney
+    interpolation, FP64) on m beam paths of the workload's mesh: deposit +
+    field interpolation + push per particle, as particle steps per second."""
+    import numpy as np
+    from oracle import pic as opic
+    from workloads.beam import BeamSampler
+    b = w.extra["beam"]
+    coords, tets = w.mesh()
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    mesh = opic.TetMesh(coords, tets)
+    t1 = time.perf_counter()
+    bs = BeamSampler(w.n, m, b["radius"], b["vth"], b["vz"], b["q0"], b["seed"])
+    x = bs.positions(0.0)
+    keep = x[:, 2] + bs.v[:, 2] * w.dt < 1.0
+    x, v, q = x[keep], bs.v[keep], bs.q[keep]
+    e = np.zeros(mesh.n_e)
+    cells = opic.locate(mesh, x)
+    E = opic.whitney_field(mesh, e, cells, x)
+    acc = opic.lorentz(np.sign(q), E, np.zeros_like(E), v)
+    xn, vn, _, _ = opic.push_ab2(x, v, acc, None, None, w.dt, True)
+    opic.deposit(mesh, x, xn, q, w.dt)
+    t2 = time.perf_counter()
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    n = len(x)
+    return {"value": round(n / (t2 - t1), 2), "unit": "particle steps/s", "cores": max(1, round(cpu / (t2 - t0))),
+            "kind": "oracle",
+            "sample": (f"particle oracle on {n} beam paths of the {w.n}^3 mesh: location, Whitney "
+                       f"interpolation, AB2 push and brute-force exact deposit, {t2 - t1:.1f} s "
+                       f"(mesh tables {t1 - t0:.1f} s, not counted)")}
 
 
 def _cpu_model():
@@ -433,7 +469,7 @@ def main():
 
     pic = None
     if args.pic_steps > 0 and w.extra.get("source") == "beam":
-        pic = pic_leg(s, w, ring[1], args.pic_steps, dev, log)
+        pic = pic_leg(s, w, ring[1], args.pic_steps, dev, log, cpu_sample=0 if args.no_cpu else 100)
 
     if args.calib_copy:
         x = torch.ones(64 << 20, dtype=torch.float64, device=dev)
