@@ -20,7 +20,10 @@ monolithic solve):
   * the particle steps around the solve (Sec. II-A): point location, the
     exact current mapping of straight paths onto the edges, Whitney
     interpolation of E and B at points, Faraday's per-tetrahedron update of
-    B and the Adams-Bashforth push (pic.py).
+    B and the Adams-Bashforth push (pic.py);
+  * the mixed E/B system on edges and faces (Whitney 2-forms, the discrete
+    curl, the face mass) advanced by the trapezoid rule as one monolithic
+    block solve (mixed.py).
 
 Parity status: every function here is pinned by a test that does not
 re-use its own formula (see tests/test_oracle_*.py).
