@@ -263,6 +263,30 @@ int dd_pic_push(void* ctx, int64_t n, const double* qm, const double* E, const d
                 const int32_t* cell, const double* x, double* x_new, double* v, double* hist,
                 int first);
 
+/* ---- the mixed E/B step (Sec. II-B-1) -------------------------------------
+ * E on edges (Whitney 1-forms), B on faces (Whitney 2-forms, W_ijk =
+ * 2 (lam_i g_j x g_k + lam_j g_k x g_i + lam_k g_i x g_j) for a face with
+ * vertices i < j < k), advanced by the trapezoid rule:
+ *   T (e+ - e)/dt = C^T M (b+ + b)/2 - J^{n+1/2},   (b+ - b)/dt = -C (e+ + e)/2,
+ * C the discrete curl (boundary of face (i,j,k) = (i,j) + (j,k) - (i,k)), M the
+ * 1/mu 2-form mass.  Eliminating b+ leaves (T + dt^2/4 S) e+ = (T - dt^2/4 S) e
+ * + dt C^T M b - dt J, the matrix of the decomposed solve with beta = 1/4, so
+ * the step is one decomposed solve between a face-side right-hand side and
+ * the face update.  Face tables are built on the first call (host sort,
+ * allocations of 8 n_tets (3 + 6 nrhs) bytes). */
+
+/* Canonical faces: *n_faces (may be NULL) and host [n_faces][3] int32 vertex
+ * triples ascending, numbered lexicographically (faces may be NULL). */
+int dd_mixed_faces(void* ctx, int64_t* n_faces, int32_t* faces);
+
+/* One trapezoid step for all nrhs right-hand sides (device pointers):
+ *   J_half [nrhs][n_edges]: J^{n+1/2};  E_n, E_next [nrhs][n_edges];
+ *   B_n, B_next [nrhs][n_faces] (face fluxes; outputs must not alias inputs).
+ * DD_ERR_STATE before dd_factor or unless the context's beta is 1/4;
+ * DD_ERR_NO_CONVERGENCE as for dd_step. */
+int dd_step_mixed(void* ctx, const double* J_half, const double* E_n, const double* B_n,
+                  double* E_next, double* B_next, dd_stats* stats);
+
 /* Per-class timing of the batched tile products, measured with HIP events
  * recorded on the context's stream around each launch (adds two event
  * records per launch while enabled).  Classes: */

@@ -65,6 +65,8 @@ SIGNATURES = {
     "dd_energy": (C.c_int, [P, P, P, P]),
     "dd_profile": (C.c_int, [P, C.c_int, P, P]),
     "dd_pic_status": (C.c_int, [P, P, C.c_int]),
+    "dd_mixed_faces": (C.c_int, [P, P, P]),
+    "dd_step_mixed": (C.c_int, [P, P, P, P, P, P, C.POINTER(Stats)]),
     "dd_pic_locate": (C.c_int, [P, I64, P, P]),
     "dd_pic_deposit": (C.c_int, [P, I64, P, P, P, P, P]),
     "dd_pic_faraday": (C.c_int, [P, C.c_int, P, D, P]),

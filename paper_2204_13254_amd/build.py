@@ -10,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddfem.so")
 SOURCES = [os.path.join(HERE, "csrc", "ddfem.hip"), os.path.join(HERE, "csrc", "plan.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", "kernels.hpp"), os.path.join(HERE, "csrc", "pic.hpp"),
+           os.path.join(HERE, "csrc", "mixed.hpp"), os.path.join(HERE, "csrc", "dp2.hpp"),
            os.path.join(HERE, "csrc", "plan.hpp"),
            os.path.join(ROOT, "include", "ddfem.h")]
 

@@ -32,6 +32,7 @@
 #include "kernels.hpp"
 #include "dp2.hpp"
 #include "pic.hpp"
+#include "mixed.hpp"
 #include "plan.hpp"
 
 namespace ddfem {
@@ -142,6 +143,13 @@ struct Ctx {
   int32_t *d_pic_nbr = nullptr, *d_pic_tedge = nullptr;
   unsigned long long* d_pic_cnt = nullptr;
   int32_t *d_pic_count = nullptr, *d_pic_bsum = nullptr;  // ordering by cell: [nt + 1], chunk totals
+  // mixed E/B step (built on first use): canonical faces, their edges, the
+  // faces of every tetrahedron, and the pull list unknown <- (tet, local edge)
+  int64_t n_faces = 0;
+  std::vector<int32_t> faces_h;  // [nf][3] vertices ascending
+  int32_t *d_tet_faces = nullptr, *d_face_edges = nullptr, *d_e6list = nullptr;
+  int64_t* d_e6ptr = nullptr;
+  double* d_buf6 = nullptr;  // [nt][6][nrhs]
   // Robin dual-primal variant (method 1): one multiplier per side, in the
   // order of the interface rows (d_grow); R = 2 alpha M_T in side space
   double robin_alpha = 0.0;
@@ -1922,6 +1930,115 @@ static void build_dp2(Ctx& C, const double* coords, const double* eps, const dou
   C.d_gm_y = dalloc<double>((size_t)kGmresRestart * kMaxRhs, C.owned);
 }
 
+// ---- particle tables (built on the first particle call) --------------------------
+static void pic_prepare(Ctx& C) {
+  if (C.d_pic_geo) return;
+  const Plan& P = C.P;
+  std::vector<int32_t> nbr;
+  std::string msg;
+  if (face_neighbors(P, nbr, msg) != 0) throw DDError{DD_ERR_MESH, msg};
+  C.d_pic_nbr = upload(nbr, C.owned, C.st);
+  C.d_pic_tedge = upload(P.tet_edges, C.owned, C.st);
+  C.d_pic_cnt = dalloc<unsigned long long>(kPicCounters, C.owned);
+  HIPCHK(hipMemsetAsync(C.d_pic_cnt, 0, kPicCounters * sizeof(unsigned long long), C.st));
+  C.d_pic_count = dalloc<int32_t>((size_t)P.nt + 1, C.owned);
+  C.d_pic_bsum = dalloc<int32_t>((size_t)(P.nt + 1 + kScanBlock - 1) / kScanBlock, C.owned);
+  double* geo = dalloc<double>((size_t)P.nt * 12, C.owned);
+  hipLaunchKernelGGL(k_tet_geo, dim3(nblk(P.nt)), dim3(256), 0, C.st, (int64_t)P.nt, C.d_coords, C.d_tsort, geo);
+  HIPCHK(hipGetLastError());
+  C.d_pic_geo = geo;
+}
+
+// ---- mixed E/B step (Sec. II-B-1, trapezoid rule) ---------------------------------
+static void mixed_prepare(Ctx& C) {
+  if (C.d_tet_faces) return;
+  pic_prepare(C);
+  const Plan& P = C.P;
+  struct Face {
+    int32_t a, b, c;
+    int64_t slot;  // 4t + k (face opposite local vertex k)
+  };
+  std::vector<Face> f((size_t)P.nt * 4);
+  for (int64_t t = 0; t < P.nt; ++t)
+    for (int k = 0; k < 4; ++k) {
+      const int32_t* v = &P.tsort[4 * t];
+      f[4 * t + k] = Face{v[kLocFaces[k][0]], v[kLocFaces[k][1]], v[kLocFaces[k][2]], 4 * t + k};
+    }
+  std::sort(f.begin(), f.end(), [](const Face& x, const Face& y) {
+    if (x.a != y.a) return x.a < y.a;
+    if (x.b != y.b) return x.b < y.b;
+    if (x.c != y.c) return x.c < y.c;
+    return x.slot < y.slot;
+  });
+  std::vector<int32_t> tet_faces((size_t)P.nt * 4), face_edges;
+  C.faces_h.clear();
+  const int LE6[4][4] = {{-1, 0, 1, 2}, {0, -1, 3, 4}, {1, 3, -1, 5}, {2, 4, 5, -1}};
+  for (size_t i = 0; i < f.size();) {
+    size_t j = i;
+    const int64_t id = (int64_t)C.faces_h.size() / 3;
+    if (id > INT32_MAX) throw DDError{DD_ERR_ARG, "too many faces"};
+    while (j < f.size() && f[j].a == f[i].a && f[j].b == f[i].b && f[j].c == f[i].c) tet_faces[f[j++].slot] = (int32_t)id;
+    C.faces_h.insert(C.faces_h.end(), {f[i].a, f[i].b, f[i].c});
+    // edges (ab, bc, ac) from the first tetrahedron holding the face
+    const int64_t t = f[i].slot / 4;
+    const int k = (int)(f[i].slot % 4);
+    const int* L = kLocFaces[k];
+    face_edges.push_back(P.tet_edges[6 * t + LE6[L[0]][L[1]]]);
+    face_edges.push_back(P.tet_edges[6 * t + LE6[L[1]][L[2]]]);
+    face_edges.push_back(P.tet_edges[6 * t + LE6[L[0]][L[2]]]);
+    i = j;
+  }
+  C.n_faces = (int64_t)C.faces_h.size() / 3;
+  // unknown d <- (tet, local edge) entries, tetrahedra ascending
+  std::vector<int64_t> ptr(P.nint + 1, 0);
+  for (int64_t i = 0; i < P.nt * 6; ++i) {
+    const int32_t d = P.dof[P.tet_edges[i]];
+    if (d >= 0) ptr[d + 1]++;
+  }
+  for (int64_t d = 0; d < P.nint; ++d) ptr[d + 1] += ptr[d];
+  std::vector<int32_t> list(ptr[P.nint]);
+  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+  if (P.nt * 6 > INT32_MAX) throw DDError{DD_ERR_ARG, "too many tetrahedra for the mixed step"};
+  for (int64_t i = 0; i < P.nt * 6; ++i) {
+    const int32_t d = P.dof[P.tet_edges[i]];
+    if (d >= 0) list[fill[d]++] = (int32_t)i;
+  }
+  C.d_tet_faces = upload(tet_faces, C.owned, C.st);
+  C.d_face_edges = upload(face_edges, C.owned, C.st);
+  C.d_e6ptr = upload(ptr, C.owned, C.st);
+  C.d_e6list = upload(list, C.owned, C.st);
+  C.d_buf6 = dalloc<double>((size_t)P.nt * 6 * C.nrhs, C.owned);
+}
+
+template <class T>
+static int mixed_step_impl(Ctx& C, const double* J1, const double* En, const double* Bn, double* Enext,
+                           double* Bnext, dd_stats* stats) {
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne, nf = C.n_faces, nt = C.P.nt;
+  hipStream_t st = C.st;
+  const int64_t n = ni * nr;
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, En, ne, C.g_t1, nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
+  // T e -> g_t2, S e -> g_x
+  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
+                     (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
+                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t2, C.g_x, nr);
+  // C^T M b -> g_e (a free buffer until the solve)
+  hipLaunchKernelGGL(k_curlT_face_mass, dim3(nblk(nt)), dim3(256), 0, st, nt, nr, nf, Bn,
+                     (const int32_t*)C.d_tet_faces, (const double*)C.d_pic_geo, (const double*)C.d_mu, C.d_buf6);
+  hipLaunchKernelGGL(k_pull_edge6, dim3(nblk(n)), dim3(256), 0, st, ni, nr, (const int64_t*)C.d_e6ptr,
+                     (const int32_t*)C.d_e6list, (const double*)C.d_buf6, C.g_e);
+  hipLaunchKernelGGL(k_mixed_rhs, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t2, (const double*)C.g_x,
+                     (const double*)C.g_e, (const double*)C.g_t3, C.dt, C.g_b);
+  int status = solve_refined<T>(C, C.g_b, C.g_e, nullptr, stats);
+  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
+                     Enext, nr, 0, 1.0);
+  hipLaunchKernelGGL(k_face_update, dim3(nblk(nf * nr)), dim3(256), 0, st, nf, nr, ne,
+                     (const int32_t*)C.d_face_edges, En, (const double*)Enext, Bn, Bnext, 0.5 * C.dt);
+  HIPCHK(hipGetLastError());
+  return status;
+}
+
 #define API_BEGIN try {
 #define API_END                                 \
   }                                             \
@@ -2260,23 +2377,6 @@ int dd_profile(void* ctx, int enable, double* ms, int64_t* launches) {
 }
 
 // ---- particle steps (Sec. II-A) --------------------------------------------------
-static void pic_prepare(Ctx& C) {
-  if (C.d_pic_geo) return;
-  const Plan& P = C.P;
-  std::vector<int32_t> nbr;
-  std::string msg;
-  if (face_neighbors(P, nbr, msg) != 0) throw DDError{DD_ERR_MESH, msg};
-  C.d_pic_nbr = upload(nbr, C.owned, C.st);
-  C.d_pic_tedge = upload(P.tet_edges, C.owned, C.st);
-  C.d_pic_cnt = dalloc<unsigned long long>(kPicCounters, C.owned);
-  HIPCHK(hipMemsetAsync(C.d_pic_cnt, 0, kPicCounters * sizeof(unsigned long long), C.st));
-  C.d_pic_count = dalloc<int32_t>((size_t)P.nt + 1, C.owned);
-  C.d_pic_bsum = dalloc<int32_t>((size_t)(P.nt + 1 + kScanBlock - 1) / kScanBlock, C.owned);
-  double* geo = dalloc<double>((size_t)P.nt * 12, C.owned);
-  hipLaunchKernelGGL(k_tet_geo, dim3(nblk(P.nt)), dim3(256), 0, C.st, (int64_t)P.nt, C.d_coords, C.d_tsort, geo);
-  HIPCHK(hipGetLastError());
-  C.d_pic_geo = geo;
-}
 
 int dd_pic_status(void* ctx, int64_t* counts, int reset) {
   if (!ctx) {
@@ -2328,6 +2428,49 @@ int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, con
                      (const int32_t*)C.d_pic_tedge, J, kPicMaxCross, C.d_pic_cnt);
   HIPCHK(hipGetLastError());
   return DD_OK;
+  API_END
+}
+
+int dd_mixed_faces(void* ctx, int64_t* n_faces, int32_t* faces) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  mixed_prepare(C);
+  if (n_faces) *n_faces = C.n_faces;
+  if (faces) std::memcpy(faces, C.faces_h.data(), C.faces_h.size() * sizeof(int32_t));
+  return DD_OK;
+  API_END
+}
+
+int dd_step_mixed(void* ctx, const double* J_half, const double* E_n, const double* B_n, double* E_next,
+                  double* B_next, dd_stats* stats) {
+  if (!ctx || !J_half || !E_n || !B_n || !E_next || !B_next) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_step_mixed called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  if (C.beta != 0.25) {
+    g_err = "the mixed step is the trapezoid rule: the context needs beta = 1/4";
+    return DD_ERR_STATE;
+  }
+  if (B_next == B_n || E_next == E_n) {
+    g_err = "outputs must not alias inputs";
+    return DD_ERR_ARG;
+  }
+  API_BEGIN
+  mixed_prepare(C);
+  int rc = C.fp32 ? mixed_step_impl<float>(C, J_half, E_n, B_n, E_next, B_next, stats)
+                  : mixed_step_impl<double>(C, J_half, E_n, B_n, E_next, B_next, stats);
+  prof_resolve(C);
+  if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface solve or refinement did not reach its tolerance";
+  return rc;
   API_END
 }
 

@@ -181,6 +181,35 @@ class DDSolver:
         check(self.lib.dd_energy(self.h, _dev(E_next), _dev(E_n), out.ctypes.data_as(C.c_void_p)))
         return out
 
+    # ---- mixed E/B step (dd_step_mixed) ------------------------------------------
+    def faces(self):
+        """Canonical faces [n_faces, 3] (host int32)."""
+        nf = C.c_int64(0)
+        check(self.lib.dd_mixed_faces(self.h, C.byref(nf), None))
+        f = np.zeros((nf.value, 3), dtype=np.int32)
+        check(self.lib.dd_mixed_faces(self.h, None, f.ctypes.data_as(C.c_void_p)))
+        self.n_faces = nf.value
+        return f
+
+    def new_face_field(self):
+        if not hasattr(self, "n_faces"):
+            self.faces()
+        return torch.zeros((self.nrhs, self.n_faces), dtype=torch.float64, device="cuda")
+
+    def step_mixed(self, J_half, E_n, B_n, E_next=None, B_next=None, stats=False):
+        """One trapezoid step of the mixed E/B system; returns (E_next, B_next)."""
+        if not hasattr(self, "n_faces"):
+            self.faces()
+        E_next = self.new_field() if E_next is None else E_next
+        B_next = self.new_face_field() if B_next is None else B_next
+        for t, n in ((J_half, self.n_edges), (E_n, self.n_edges), (E_next, self.n_edges)):
+            self._len(t, self.nrhs * n, "edge array")
+        for t in (B_n, B_next):
+            self._len(t, self.nrhs * self.n_faces, "face array")
+        check(self.lib.dd_step_mixed(self.h, _dev(J_half), _dev(E_n), _dev(B_n), _dev(E_next), _dev(B_next),
+                                     C.byref(self.stats) if stats else None))
+        return E_next, B_next
+
     # ---- particle steps (dd_pic_*): device tensors, positions [n, 3] ----------
     @staticmethod
     def _pts(x, n=None):
