@@ -325,6 +325,8 @@ def main():
     ap.add_argument("--workload", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--mixed-steps", type=int, default=5,
+                    help="also time this many steps of the mixed E/B form (B on faces); 0 skips them")
     ap.add_argument("--dp2-steps", type=int, default=3,
                     help="also time this many steps of the Robin variant (one multiplier per side, GMRES); "
                          "0 skips it")
@@ -467,6 +469,27 @@ def main():
     # summaries, valid only for the kernel source they were taken on
     roof["traffic"] = _traffic_from_profiles(dom)
 
+    # ---------------- mixed E/B step (faces carry B) on the same solver -----------------
+    mixed = None
+    if args.mixed_steps > 0 and w.beta == 0.25:
+        nf = s.faces().shape[0]
+        Bm = [torch.zeros((w.nrhs, nf), dtype=torch.float64, device=dev) for _ in range(2)]
+        Em = [zero.clone() for _ in range(2)]
+        s.step_mixed(Jd[0], Em[0], Bm[0], Em[1], Bm[1])        # untimed: builds the face tables
+        torch.cuda.synchronize()
+        K3 = min(args.mixed_steps, W + K - 1)
+        t0 = time.perf_counter()
+        for k in range(1, 1 + K3):
+            s.step_mixed(Jd[k], Em[k % 2], Bm[k % 2], Em[(k + 1) % 2], Bm[(k + 1) % 2])
+        torch.cuda.synchronize()
+        t_m = time.perf_counter() - t0
+        mixed = {"steps_per_s": round(K3 / t_m, 4), "ms_per_step": round(1e3 * t_m / K3, 3), "steps_timed": K3,
+                 "faces": int(nf),
+                 "form": "B on faces (Whitney 2-forms), trapezoid rule; eliminated edge system through the "
+                         "same decomposed solve, then the face update"}
+        log(f"mixed E/B: {mixed}")
+        del Bm, Em
+
     pic = None
     if args.pic_steps > 0 and w.extra.get("source") == "beam":
         pic = pic_leg(s, w, ring[1], args.pic_steps, dev, log, cpu_sample=0 if args.no_cpu else 100)
@@ -568,6 +591,7 @@ def main():
         "kernel_classes": other,
         "plain_fp64": plain,
         "robin_dp2": dp2,
+        "mixed_eb": mixed,
         "pic": pic,
         "speedup_vs_plain_fp64": (round(sps / plain["steps_per_s"], 2) if plain else None),
     }
