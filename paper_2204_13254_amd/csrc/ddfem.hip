@@ -150,6 +150,7 @@ struct Ctx {
   int32_t *d_tet_faces = nullptr, *d_face_edges = nullptr, *d_e6list = nullptr;
   int64_t* d_e6ptr = nullptr;
   double* d_buf6 = nullptr;  // [nt][6][nrhs]
+  double* d_bt = nullptr;    // face fluxes [nf][nrhs]
   // Robin dual-primal variant (method 1): one multiplier per side, in the
   // order of the interface rows (d_grow); R = 2 alpha M_T in side space
   double robin_alpha = 0.0;
@@ -2008,6 +2009,7 @@ static void mixed_prepare(Ctx& C) {
   C.d_e6ptr = upload(ptr, C.owned, C.st);
   C.d_e6list = upload(list, C.owned, C.st);
   C.d_buf6 = dalloc<double>((size_t)P.nt * 6 * C.nrhs, C.owned);
+  C.d_bt = dalloc<double>((size_t)C.n_faces * C.nrhs, C.owned);
 }
 
 template <class T>
@@ -2024,7 +2026,8 @@ static int mixed_step_impl(Ctx& C, const double* J1, const double* En, const dou
                      (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
                      (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t2, C.g_x, nr);
   // C^T M b -> g_e (a free buffer until the solve)
-  hipLaunchKernelGGL(k_curlT_face_mass, dim3(nblk(nt)), dim3(256), 0, st, nt, nr, nf, Bn,
+  hipLaunchKernelGGL(k_rhs_major_to_item, dim3(nblk(nf * nr)), dim3(256), 0, st, nf, nr, Bn, C.d_bt);
+  hipLaunchKernelGGL(k_curlT_face_mass, dim3(nblk(nt * nr)), dim3(256), 0, st, nt, nr, (const double*)C.d_bt,
                      (const int32_t*)C.d_tet_faces, (const double*)C.d_pic_geo, (const double*)C.d_mu, C.d_buf6);
   hipLaunchKernelGGL(k_pull_edge6, dim3(nblk(n)), dim3(256), 0, st, ni, nr, (const int64_t*)C.d_e6ptr,
                      (const int32_t*)C.d_e6list, (const double*)C.d_buf6, C.g_e);

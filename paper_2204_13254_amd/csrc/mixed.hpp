@@ -19,18 +19,32 @@ namespace ddfem {
 constexpr int kLocFaces[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
 constexpr int kLocCurl[4][6] = {{0, 0, 0, 1, -1, 1}, {0, 1, -1, 0, 0, 1}, {1, 0, -1, 0, 1, 0}, {1, -1, 0, 1, 0, 0}};
 
+// Bt[f][r] = B[r][f]: face fluxes unknown-major, so that the right-hand
+// sides of one face are one contiguous line for the per-tetrahedron kernel
+__global__ void __launch_bounds__(256) k_rhs_major_to_item(int64_t nf, int nrhs, const double* __restrict__ B,
+                                                           double* __restrict__ Bt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nf * nrhs) return;
+  const int64_t f = i / nrhs;
+  const int r = (int)(i - f * nrhs);
+  Bt[i] = B[(int64_t)r * nf + f];
+}
+
 // out[(t*6 + a)*nrhs + r] = sum_f C[f][a] (M_t b_t)_f with M_t the 1/mu
 // 2-form mass of tetrahedron t:
 //   M[F][G] = (4/mu) sum_{a in F, b in G} V (1 + d_ab) / 20 c_a^F . c_b^G,
 // W_F = 2 sum_{a in F} lam_a c_a^F, c_i = g_j x g_k, c_j = g_k x g_i,
-// c_k = g_i x g_j for F = (i, j, k).  B is [nrhs][nf].
-__global__ void __launch_bounds__(256) k_curlT_face_mass(int64_t nt, int nrhs, int64_t nf,
-                                                         const double* __restrict__ B,
+// c_k = g_i x g_j for F = (i, j, k).  One thread per (tetrahedron, RHS), RHS
+// fastest, so that every store of a wave fills whole lines; each RHS thread
+// of a tetrahedron forms the 4x4 mass itself.  Bt is [nf][nrhs].
+__global__ void __launch_bounds__(256) k_curlT_face_mass(int64_t nt, int nrhs, const double* __restrict__ Bt,
                                                          const int32_t* __restrict__ tet_faces,
                                                          const double* __restrict__ geo,
                                                          const double* __restrict__ mu, double* __restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nt) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt * nrhs) return;
+  const int64_t t = i / nrhs;
+  const int r = (int)(i - t * nrhs);
   PicTet T;
   load_tet(geo, t, T);
   const double(*g)[3] = T.g;
@@ -49,38 +63,34 @@ __global__ void __launch_bounds__(256) k_curlT_face_mass(int64_t nt, int nrhs, i
       c[F][m][2] = g[u][0] * g[v][1] - g[u][1] * g[v][0];
     }
   }
-  double M[4][4];
-  const double s = 4.0 * vol / (20.0 * mu[t]);
+  double b[4];
 #pragma unroll
-  for (int F = 0; F < 4; ++F)
+  for (int F = 0; F < 4; ++F) b[F] = Bt[(int64_t)tet_faces[4 * t + F] * nrhs + r];
+  const double s = 4.0 * vol / (20.0 * mu[t]);
+  double m[4];
+#pragma unroll
+  for (int F = 0; F < 4; ++F) {
+    double acc = 0.0;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-      double acc = 0.0;
+      double mfg = 0.0;
 #pragma unroll
-      for (int m = 0; m < 3; ++m)
+      for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const double w = kLocFaces[F][m] == kLocFaces[G][k] ? 2.0 : 1.0;
-          acc += w * (c[F][m][0] * c[G][k][0] + c[F][m][1] * c[G][k][1] + c[F][m][2] * c[G][k][2]);
+          const double w = kLocFaces[F][p] == kLocFaces[G][k] ? 2.0 : 1.0;
+          mfg += w * (c[F][p][0] * c[G][k][0] + c[F][p][1] * c[G][k][1] + c[F][p][2] * c[G][k][2]);
         }
-      M[F][G] = s * acc;
+      acc += mfg * b[G];
     }
-  int32_t tf[4];
+    m[F] = s * acc;
+  }
 #pragma unroll
-  for (int F = 0; F < 4; ++F) tf[F] = tet_faces[4 * t + F];
-  for (int r = 0; r < nrhs; ++r) {
-    double b[4], m[4];
+  for (int a = 0; a < 6; ++a) {
+    double v = 0.0;
 #pragma unroll
-    for (int F = 0; F < 4; ++F) b[F] = B[(int64_t)r * nf + tf[F]];
-#pragma unroll
-    for (int F = 0; F < 4; ++F) m[F] = M[F][0] * b[0] + M[F][1] * b[1] + M[F][2] * b[2] + M[F][3] * b[3];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      double v = 0.0;
-#pragma unroll
-      for (int F = 0; F < 4; ++F) v += kLocCurl[F][a] * m[F];
-      out[(t * 6 + a) * nrhs + r] = v;
-    }
+    for (int F = 0; F < 4; ++F) v += kLocCurl[F][a] * m[F];
+    out[(t * 6 + a) * nrhs + r] = v;
   }
 }
 
