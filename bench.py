@@ -346,8 +346,8 @@ def main():
                          "scaling hardware traffic counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the decomposition is batched inside one "
-              "device); multi-GPU sharding is a design note, not implemented.", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (every subdomain is batched inside one device); "
+              "sharding the subdomains over several GPUs is designed but not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
