@@ -420,7 +420,7 @@ def main():
     if args.graph:
         # graphs exclude per-launch events: time the classes on 3 extra eager steps
         s.profile(1)
-        for n in range(W + K - 3, W + K):
+        for n in range(max(0, W + K - 3), W + K):
             do_step(n)
         torch.cuda.synchronize()
     prof = s.profile(0)
@@ -471,7 +471,7 @@ def main():
 
     # ---------------- mixed E/B step (faces carry B) on the same solver -----------------
     mixed = None
-    if args.mixed_steps > 0 and w.beta == 0.25:
+    if args.mixed_steps > 0 and w.beta == 0.25 and W + K >= 2:
         nf = s.faces().shape[0]
         Bm = [torch.zeros((w.nrhs, nf), dtype=torch.float64, device=dev) for _ in range(2)]
         Em = [zero.clone() for _ in range(2)]
@@ -505,7 +505,7 @@ def main():
     # ---------------- plain FP64 form --------------------------------------------------
     # ---------------- Robin variant (one multiplier per side, GMRES) -----------------------
     dp2 = None
-    if args.dp2_steps > 0:
+    if args.dp2_steps > 0 and W + K >= 2:
         t0 = time.perf_counter()
         q = DDSolver(coords, tets, part, eps, dt=w.dt, beta=w.beta, precision="fp32_refine", nrhs=w.nrhs,
                      cg_tol=1e-6, refine_tol=1e-12, refine_max=10, factor=False, stream=stream,
@@ -541,7 +541,7 @@ def main():
         torch.cuda.empty_cache()
 
     plain = None
-    if not args.no_plain and args.plain_steps > 0:
+    if not args.no_plain and min(args.plain_steps, W + K - 1) > 0:
         del s
         torch.cuda.empty_cache()
         t0 = time.perf_counter()
@@ -551,7 +551,7 @@ def main():
         torch.cuda.synchronize()
         t_pf = time.perf_counter() - t0
         E = [zero.clone() for _ in range(3)]
-        P = args.plain_steps
+        P = min(args.plain_steps, W + K - 1)
         pit = []
 
         def plain_step(n, Jp):
