@@ -161,7 +161,7 @@ struct Ctx {
   int64_t n_radd = 0;            // Robin terms of the local interface blocks (lower triangle, no alpha)
   int64_t* d_radd_pos = nullptr;
   double* d_radd_val = nullptr;
-  double *d_gmV = nullptr, *d_gm_u = nullptr, *d_gm_rhs = nullptr, *d_lam2 = nullptr, *d_gm_partial = nullptr;
+  double *d_gmV = nullptr, *d_gm_rhs = nullptr, *d_lam2 = nullptr, *d_gm_partial = nullptr;
   double *d_gm_h = nullptr, *d_gm_tot = nullptr, *d_gm_ss = nullptr, *d_gm_y = nullptr;
   // local assembly pull
   int64_t n_lent = 0;
@@ -1273,10 +1273,8 @@ static void apply_G(Ctx& C, const double* lam, double* y) {
   hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2, lam,
                      (T*)C.X[5], nr, (const int*)nullptr);
   apply_local<T>(C, nullptr);
-  hipLaunchKernelGGL(k_side_collect<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2,
-                     (const T*)C.X[8], C.d_gm_u, nr);
-  hipLaunchKernelGGL(k_robin_apply, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval, C.d_partner2,
-                     lam, (const double*)C.d_gm_u, y, nr);
+  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
+                     C.d_partner2, lam, C.d_grow, (const T*)C.X[8], y, nr);
 }
 
 // per-RHS dot products a . b over the side vectors, to the host
@@ -1303,10 +1301,8 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
   const int m = kGmresRestart;
   double* V = C.d_gmV;
   auto vec = [&](int k) { return V + (int64_t)k * ldv; };
-  hipLaunchKernelGGL(k_side_collect<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2,
-                     (const T*)C.X[4], C.d_gm_u, nr);
-  hipLaunchKernelGGL(k_robin_apply, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
-                     C.d_partner2, (const double*)nullptr, (const double*)C.d_gm_u, C.d_gm_rhs, nr);
+  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
+                     C.d_partner2, (const double*)nullptr, C.d_grow, (const T*)C.X[4], C.d_gm_rhs, nr);
   HIPCHK(hipMemsetAsync(C.d_lam2, 0, nl * sizeof(double), st));
   double bnorm[kMaxRhs], ss[kMaxRhs];
   side_dots(C, C.d_gm_rhs, C.d_gm_rhs, bnorm);
@@ -1346,8 +1342,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
       std::fill(g.begin() + (size_t)r * (m + 1), g.begin() + (size_t)(r + 1) * (m + 1), 0.0);
       g[(size_t)r * (m + 1)] = std::sqrt(std::max(ss[r], 0.0));
     }
-    int j = 0;
-    for (; j < m && total < cap; ++j) {
+    for (int j = 0; j < m && total < cap; ++j) {
       double* w = vec(j + 1);
       apply_G<T>(C, vec(j), w);
       const int nv = j + 1;
@@ -1398,10 +1393,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
         relres[r] = std::fabs(gr[j + 1]) / bnorm[r];
         if (relres[r] <= C.opt.cg_tol) conv[r] = true;
       }
-      if (all_conv()) {
-        ++j;
-        break;
-      }
+      if (all_conv()) break;
     }
     // lam += V y, y from the triangular systems of each RHS's first cols columns
     int jmax = 0;
@@ -1423,7 +1415,6 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
                          (const double*)C.d_gm_y, 1.0, C.d_lam2, nr);
       HIPCHK(hipStreamSynchronize(st));
     }
-    (void)j;
   }
   HIPCHK(hipGetLastError());
   return all_conv() ? DD_OK : DD_ERR_NO_CONVERGENCE;
@@ -1921,7 +1912,6 @@ static void build_dp2(Ctx& C, const double* coords, const double* eps, const dou
   C.d_radd_val = upload(aval, C.owned, st);
   const int64_t nv = ns * nr;
   C.d_gmV = dalloc<double>((size_t)(kGmresRestart + 1) * nv, C.owned);
-  C.d_gm_u = dalloc<double>(nv, C.owned);
   C.d_gm_rhs = dalloc<double>(nv, C.owned);
   C.d_lam2 = dalloc<double>(nv, C.owned);
   C.d_gm_partial = dalloc<double>((size_t)(kGmresRestart + 1) * kDotBlocks * kMaxRhs, C.owned);

@@ -26,27 +26,17 @@ __global__ void __launch_bounds__(256) k_add_entries(int64_t n, const int64_t* _
   tiles[pos[i]] = (T)((double)tiles[pos[i]] + alpha * val[i]);
 }
 
-// out[i][r] = u[rows[i]][r] for live sides, 0 for padding
-template <class T>
-__global__ void __launch_bounds__(256) k_side_collect(int64_t n, const int64_t* __restrict__ rows,
-                                                      const int32_t* __restrict__ code, const T* __restrict__ u,
-                                                      double* __restrict__ out, int nrhs) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * nrhs) return;
-  const int64_t k = i / nrhs;
-  const int r = (int)(i - k * nrhs);
-  out[i] = code[k] >= 0 ? (double)u[rows[k] * nrhs + r] : 0.0;
-}
-
 // Transmission residual of the Robin condition on every side:
 //   y[i] = lam[i] + lam[partner[i]] - sum_k R[i][k] u[k]
-// (R = 2 alpha M_T, columns on the partner's sides); lam == nullptr gives
-// y = -R u.
+// (R = 2 alpha M_T, columns on the partner's sides), with the interface
+// response u of side k read straight from its local row rows[k] of U;
+// lam == nullptr gives y = -R u.
+template <class T>
 __global__ void __launch_bounds__(256) k_robin_apply(int64_t n, const int64_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const int32_t* __restrict__ partner,
-                                                     const double* __restrict__ lam, const double* __restrict__ u,
-                                                     double* __restrict__ y, int nrhs) {
+                                                     const double* __restrict__ lam, const int64_t* __restrict__ rows,
+                                                     const T* __restrict__ U, double* __restrict__ y, int nrhs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
   const int64_t k = i / nrhs;
@@ -57,7 +47,7 @@ __global__ void __launch_bounds__(256) k_robin_apply(int64_t n, const int64_t* _
     const int32_t q = partner[k];
     if (q >= 0) s += lam[(int64_t)q * nrhs + r];
   }
-  for (int64_t j = rp[k]; j < rp[k + 1]; ++j) s -= val[j] * u[(int64_t)ci[j] * nrhs + r];
+  for (int64_t j = rp[k]; j < rp[k + 1]; ++j) s -= val[j] * (double)U[rows[ci[j]] * nrhs + r];
   y[i] = s;
 }
 
