@@ -1328,8 +1328,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
       HIPCHK(hipMemcpyAsync(vec(0), C.d_gm_rhs, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
       apply_G<T>(C, C.d_lam2, vec(0));
-      hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs,
-                         (const double*)vec(0), vec(0));
+      hipLaunchKernelGGL(k_rsub, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs, vec(0));
     }
     side_dots(C, vec(0), vec(0), ss);
     hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)vec(0),
@@ -2321,11 +2320,11 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
   const int64_t ni = C.P.nint, ne = C.P.ne, n = ni * nr;
   hipStream_t st = C.st;
   // g_t1 = (e1 - e0)/dt, g_t2 = (e1 + e0)/2
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t1, nr,
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t4, nr,
                      1.0 / C.dt);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
                      1.0 / C.dt);
-  hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t1, (const double*)C.g_t3,
+  hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t4, (const double*)C.g_t3,
                      C.g_t1);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
                      0.5);

@@ -127,6 +127,12 @@ __global__ void __launch_bounds__(256) k_mupdate(int64_t n, int nv, const double
   w[i] += sgn * s;
 }
 
+// y = a - y in place (restart residual: y holds G lam on entry)
+__global__ void __launch_bounds__(256) k_rsub(int64_t n, const double* __restrict__ a, double* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] - y[i];
+}
+
 // out = w / sqrt(ss[r]) per right-hand side (0 where ss is not positive)
 __global__ void __launch_bounds__(256) k_vnormalize(int64_t n, const double* w, const double* __restrict__ ss,
                                                     double* out, int nrhs) {
