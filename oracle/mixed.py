@@ -52,15 +52,18 @@ def canonical_faces(tets):
 
 def curl_incidence(edges, faces):
     """C [n_f, n_e]: +1 on edges (a,b) and (b,c), -1 on (a,c) of face (a,b,c)."""
+    edges = np.asarray(edges, dtype=np.int64)
+    faces = np.asarray(faces, dtype=np.int64)
     nv = int(max(edges.max(), faces.max())) + 1
-    ekey = {int(a) * nv + int(b): i for i, (a, b) in enumerate(edges)}
-    rows, cols, vals = [], [], []
-    for f, (a, b, c) in enumerate(faces):
-        for (p, q), s in (((a, b), 1.0), ((b, c), 1.0), ((a, c), -1.0)):
-            rows.append(f)
-            cols.append(ekey[int(p) * nv + int(q)])
-            vals.append(s)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(len(faces), len(edges)))
+    ekey = edges[:, 0] * nv + edges[:, 1]                  # ascending (canonical order)
+    a, b, c = faces[:, 0], faces[:, 1], faces[:, 2]
+    cols = [np.searchsorted(ekey, p * nv + q) for p, q in ((a, b), (b, c), (a, c))]
+    for k, (p, q) in zip(cols, ((a, b), (b, c), (a, c))):
+        assert np.array_equal(ekey[k], p * nv + q)
+    nf = len(faces)
+    rows = np.tile(np.arange(nf), 3)
+    vals = np.concatenate([np.ones(nf), np.ones(nf), -np.ones(nf)])
+    return sp.csr_matrix((vals, (rows, np.concatenate(cols))), shape=(nf, len(edges)))
 
 
 def face_mass_elements(coords, tets, mu=None):
@@ -90,7 +93,7 @@ class MixedOracle:
     """Monolithic trapezoid step of the mixed system; e on the interior
     edges (PEC edges zero), b on all faces."""
 
-    def __init__(self, coords, tets, eps=None, mu=None, dt=0.05):
+    def __init__(self, coords, tets, eps=None, mu=None, dt=0.05, factor=True):
         self.d = Discretisation(coords, tets, eps, mu)
         d = self.d
         self.dt = float(dt)
@@ -106,9 +109,11 @@ class MixedOracle:
         self.M.sum_duplicates()
         dt = self.dt
         CtM = (self.C.T @ self.M).tocsr()
-        K = sp.bmat([[d.T / dt, -0.5 * CtM], [0.5 * self.C, sp.identity(self.n_f) / dt]], format="csc")
-        self.lu = spla.splu(K)
         self.CtM = CtM
+        self.lu = None
+        if factor:
+            K = sp.bmat([[d.T / dt, -0.5 * CtM], [0.5 * self.C, sp.identity(self.n_f) / dt]], format="csc")
+            self.lu = spla.splu(K)
 
     def step(self, e, b, J):
         """One step for e [nrhs, n_int], b [nrhs, n_f], J [nrhs, n_int]."""
@@ -133,6 +138,26 @@ class MixedOracle:
             Es.append(d.extend(e))
             Bs.append(b.copy())
         return np.stack(Es), np.stack(Bs)
+
+    # ---- properties for solutions computed elsewhere (any size) -----------------
+    def eliminated_residual(self, E_next, E_n, B_n, J_half):
+        """Per-RHS ||A e+ - r|| / ||r|| of the edge equation left after
+        eliminating b+, A = T + dt^2/4 S, r = (T - dt^2/4 S) e + dt C^T M b - dt J
+        (full edge arrays for E and J, face arrays for B)."""
+        d, dt = self.d, self.dt
+        e1, e0, J = d.restrict(E_next), d.restrict(E_n), d.restrict(J_half)
+        q = 0.25 * dt * dt
+        r = (d.T @ e0.T).T - q * (d.S @ e0.T).T + dt * (self.CtM @ np.asarray(B_n).T).T - dt * J
+        res = (d.T @ e1.T).T + q * (d.S @ e1.T).T - r
+        nr = np.linalg.norm(r, axis=1)
+        return np.linalg.norm(res, axis=1) / np.where(nr > 0, nr, 1.0)
+
+    def face_update_residual(self, E_next, E_n, B_n, B_next):
+        """max |b+ - b + dt/2 C (e+ + e)| per RHS."""
+        d = self.d
+        s = d.restrict(E_next) + d.restrict(E_n)
+        res = np.asarray(B_next) - np.asarray(B_n) + 0.5 * self.dt * (self.C @ s.T).T
+        return np.abs(res).max(axis=1)
 
     def energy(self, E_edges, B):
         """(e^T T e + b^T M b) / 2 per RHS."""

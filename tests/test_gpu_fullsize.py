@@ -54,11 +54,12 @@ def test_cavity24_fp64_100_steps_every_step():
     assert err.max() <= w.check_tol
 
 
-def _property_check(w, J, steps):
+def _property_check(w, J, steps, method="dp1"):
     from paper_2204_13254_amd.solver import DDSolver
     c, t = w.mesh(); p = w.partition(); eps = w.eps(len(t))
     s = DDSolver(c, t, p, eps, dt=w.dt, beta=w.beta, precision=w.precision, nrhs=w.nrhs,
-                 cg_tol=w.cg_tol, refine_tol=w.refine_tol, warm_start=True)
+                 cg_tol=w.cg_tol, refine_tol=w.refine_tol, warm_start=method == "dp1", method=method,
+                 cg_max_iter=400)
     E, st = _run(s, J)
     print(w.name, "CG iters", [x["cg_iters"][:2] for x in st], "sweeps", [x["refine_sweeps"] for x in st],
           flush=True)
@@ -101,3 +102,45 @@ def test_cavity64_beam16_properties():
     # the device is already initialised in this process: spawn fresh workers
     J = bench.make_sources(w, c, t, range(steps), min(16, os.cpu_count() or 1), start_method="spawn")
     _property_check(w, J, steps)
+
+
+def _beam_sources(w, steps):
+    import bench
+    c, t = w.mesh()
+    # the device is already initialised in this process: spawn fresh workers
+    return bench.make_sources(w, c, t, range(steps), min(16, os.cpu_count() or 1), start_method="spawn")
+
+
+def test_cavity64_beam16_robin_properties():
+    """The Robin variant (per-side multipliers, GMRES) at the bench size."""
+    w = workload(5)
+    _property_check(w, _beam_sources(w, 2), 2, method="dp2")
+
+
+def test_cavity64_beam16_mixed_properties():
+    """The mixed E/B step at the bench size: the eliminated edge equation and
+    the face update, both assembled by the mixed oracle (any-size
+    properties), over two steps from a nonzero divergence-free B."""
+    from oracle.mixed import MixedOracle
+    from paper_2204_13254_amd.solver import DDSolver
+    w = workload(5)
+    c, t = w.mesh(); p = w.partition(); eps = w.eps(len(t))
+    J = _beam_sources(w, 2)
+    o = MixedOracle(c, t, eps=eps, dt=w.dt, factor=False)
+    s = DDSolver(c, t, p, eps, dt=w.dt, beta=0.25, precision=w.precision, nrhs=w.nrhs, cg_tol=w.cg_tol,
+                 refine_tol=w.refine_tol)
+    assert np.array_equal(s.faces(), o.faces)
+    rng = np.random.default_rng(3)
+    b0 = np.ascontiguousarray((o.C @ rng.normal(size=(o.d.n_int, w.nrhs))).T) * 1e-3
+    E = [np.zeros((w.nrhs, o.d.n_e))]
+    B = [b0]
+    Ed, Bd = torch.zeros((w.nrhs, o.d.n_e), dtype=torch.float64, device="cuda"), torch.tensor(b0, device="cuda")
+    Jd = torch.tensor(J, device="cuda")
+    for k in range(2):
+        Ed, Bd = s.step_mixed(Jd[k], Ed, Bd)
+        E.append(Ed.cpu().numpy()); B.append(Bd.cpu().numpy())
+        rel = o.eliminated_residual(E[-1], E[-2], B[-2], J[k])
+        fres = o.face_update_residual(E[-1], E[-2], B[-2], B[-1])
+        print(f"mixed step {k}: eliminated residual {rel.max():.2e}, face update {fres.max():.2e}", flush=True)
+        assert rel.max() <= 1e-11
+        assert fres.max() <= 1e-12 * np.abs(B[-1]).max()

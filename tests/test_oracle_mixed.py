@@ -100,3 +100,19 @@ def test_eliminating_b_gives_newmark_quarter():
     En = NewmarkOracle(c, t, eps=eps, dt=dt, beta=0.25).run(J)
     assert np.abs(Em - En).max() <= 1e-11 * np.abs(En).max()
     assert np.abs(En).max() > 1e-3
+
+
+def test_property_checks_vanish_on_oracle_steps(jm):
+    """The any-size properties used at full size: zero (to rounding) on the
+    oracle's own steps, large for a perturbed field."""
+    c, t, mu = jm
+    o = MixedOracle(c, t, mu=mu, dt=0.1)
+    rng = np.random.default_rng(8)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, 3, 0.1, 0.15, 0.05, seed=6, nrhs=2)
+    E, B = o.run(J)
+    for k in range(3):
+        assert o.eliminated_residual(E[k + 1], E[k], B[k], J[k]).max() <= 1e-12
+        assert o.face_update_residual(E[k + 1], E[k], B[k], B[k + 1]).max() <= 1e-13 * np.abs(B[k + 1]).max()
+    bad = E[2] + 1e-6 * rng.normal(size=E[2].shape) * (~o.d.pec)
+    assert o.eliminated_residual(bad, E[1], B[1], J[1]).max() > 1e-8
+    assert o.face_update_residual(bad, E[1], B[1], B[2]).max() > 1e-9
