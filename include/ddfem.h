@@ -133,6 +133,9 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
 /* Sizes of a context. */
 int dd_get_info(void* ctx, dd_info* info);
 
+/* Number of canonical edges (the length of every field and current row). */
+int dd_num_edges(void* ctx, int64_t* n_edges);
+
 /* Canonical edges: host [n_edges][2] int32 (v_lo, v_hi) and host [n_edges]
  * uint8 PEC flags.  Either pointer may be NULL. */
 int dd_get_edges(void* ctx, int32_t* edges, uint8_t* is_pec);

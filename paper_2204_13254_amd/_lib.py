@@ -55,6 +55,7 @@ SIGNATURES = {
     "dd_setup": (C.c_int, [C.POINTER(C.c_void_p), I64, P, I64, P, P, P, P, D, D, C.POINTER(Options)]),
     "dd_get_info": (C.c_int, [P, C.POINTER(Info)]),
     "dd_get_edges": (C.c_int, [P, P, P]),
+    "dd_num_edges": (C.c_int, [P, P]),
     "dd_set_eps": (C.c_int, [P, P]),
     "dd_factor": (C.c_int, [P]),
     "dd_step": (C.c_int, [P, P, P, P, P, P, C.POINTER(Stats)]),

@@ -2167,6 +2167,15 @@ int dd_get_info(void* ctx, dd_info* info) {
   return DD_OK;
 }
 
+int dd_num_edges(void* ctx, int64_t* n_edges) {
+  if (!ctx || !n_edges) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  *n_edges = ((Ctx*)ctx)->P.ne;
+  return DD_OK;
+}
+
 int dd_get_edges(void* ctx, int32_t* edges, uint8_t* is_pec) {
   if (!ctx) {
     g_err = "null context";
