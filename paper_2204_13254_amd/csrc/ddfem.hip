@@ -1612,6 +1612,44 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   return status;
 }
 
+// The global (T, S) product of k_csr (modes there): one thread per (row,
+// RHS) for up to 4 RHS, the cooperative row groups for 5..32.
+template <int G, int NB, int MODE>
+static void csr_coop_launch(Ctx& C, hipStream_t st, const double* x1, const double* x2, const double* j1,
+                            const double* j2, const double* z, double ca, double cb, double* y, double* y2) {
+  const int64_t ni = C.P.nint;
+  hipLaunchKernelGGL((k_csr_coop<G, NB, MODE>), dim3(nblk8(ni * G)), dim3(256), 0, st, ni, C.d_rp, C.d_ci, C.d_vals,
+                     x1, x2, j1, j2, z, C.dt, ca, cb, y, y2, C.nrhs);
+}
+
+template <int G, int NB>
+static void csr_coop_mode(Ctx& C, hipStream_t st, int mode, const double* x1, const double* x2, const double* j1,
+                          const double* j2, const double* z, double ca, double cb, double* y, double* y2) {
+  if (mode == 0)
+    csr_coop_launch<G, NB, 0>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+  else if (mode == 1)
+    csr_coop_launch<G, NB, 1>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+  else if (mode == 2)
+    csr_coop_launch<G, NB, 2>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+  else
+    csr_coop_launch<G, NB, 3>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+}
+
+static void csr_launch(Ctx& C, hipStream_t st, int mode, const double* x1, const double* x2, const double* j1,
+                       const double* j2, const double* z, double ca, double cb, double* y, double* y2) {
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint;
+  if (nr <= 4)
+    hipLaunchKernelGGL(k_csr, dim3(nblk8(ni * nr)), dim3(256), 0, st, mode, ni, C.d_rp, C.d_ci, C.d_vals, x1, x2, j1,
+                       j2, z, C.dt, ca, cb, y, y2, nr);
+  else if (nr <= 8)
+    csr_coop_mode<8, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2);
+  else if (nr <= 16)
+    csr_coop_mode<16, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2);
+  else
+    csr_coop_mode<32, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2);
+}
+
 // A^-1 b with iterative refinement in the mixed form.  b, x: [nint][nrhs].
 template <class T>
 static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd_stats* stats) {
@@ -1629,10 +1667,8 @@ static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd
     double bn[kMaxRhs];
     dot_to_host(C, b, b, C.P.nint, bn);
     for (;;) {
-      hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 1, (int64_t)C.P.nint, C.d_rp, C.d_ci, C.d_vals,
-                         (const double*)x, (const double*)nullptr, (const double*)nullptr,
-                         (const double*)nullptr, b, C.dt, C.beta * C.dt * C.dt,
-                         (2 * C.beta - 1) * C.dt * C.dt, C.g_r, (double*)nullptr, nr);
+      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
+                 C.g_r, nullptr);
       double rn[kMaxRhs];
       dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
       bool ok = true;
@@ -1682,10 +1718,8 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, Enm1, ne, C.g_t2, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J0, ne, C.g_x, nr, 1.0);
-  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 0, ni, C.d_rp, C.d_ci, C.d_vals,
-                     (const double*)C.g_t1, (const double*)C.g_t2, (const double*)C.g_t3, (const double*)C.g_x,
-                     (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_b,
-                     (double*)nullptr, nr);
+  csr_launch(C, st, 0, C.g_t1, C.g_t2, C.g_t3, C.g_x, nullptr, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
+             C.g_b, nullptr);
   int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start ? &C.warm_fw : nullptr, stats);
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
                      Enext, nr, 0, 1.0);
@@ -1719,10 +1753,8 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
                      1.0);
   int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start ? &C.warm_adj : nullptr, stats);
   // B1 g -> g_t2, A g -> g_t3
-  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 2, ni, C.d_rp, C.d_ci, C.d_vals, (const double*)C.g_x,
-                     (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, C.dt, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt, C.g_t2,
-                     C.g_t3, nr);
+  csr_launch(C, st, 2, C.g_x, nullptr, nullptr, nullptr, nullptr, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
+             C.g_t2, C.g_t3);
   if (ebar_n)
     hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_t2,
                        ebar_n, nr, 1, 1.0);
@@ -2011,9 +2043,7 @@ static int mixed_step_impl(Ctx& C, const double* J1, const double* En, const dou
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, En, ne, C.g_t1, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
   // T e -> g_t2, S e -> g_x
-  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
-                     (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t2, C.g_x, nr);
+  csr_launch(C, st, 3, C.g_t1, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_x);
   // C^T M b -> g_e (a free buffer until the solve)
   hipLaunchKernelGGL(k_rhs_major_to_item, dim3(nblk(nf * nr)), dim3(256), 0, st, nf, nr, Bn, C.d_bt);
   hipLaunchKernelGGL(k_curlT_face_mass, dim3(nblk(nt * nr)), dim3(256), 0, st, nt, nr, (const double*)C.d_bt,
@@ -2300,9 +2330,7 @@ int dd_gauss_residual(void* ctx, const double* E, const double* q, double* res) 
   const int64_t ni = C.P.nint, ne = C.P.ne, nv = C.P.nv;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, C.st, ni, C.d_interior, E, ne, C.g_t1, nr,
                      1.0);
-  hipLaunchKernelGGL(k_csr, dim3(nblk8(ni * nr)), dim3(256), 0, C.st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
-                     (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t2, C.g_t3, nr);
+  csr_launch(C, C.st, 3, C.g_t1, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_t3);
   double* d_res = C.d_vres;
   hipLaunchKernelGGL(k_gauss, dim3(nblk(nv * nr)), dim3(256), 0, C.st, nv, C.d_vptr, C.d_vedge, C.d_nodeint,
                      C.d_dof, (const double*)C.g_t2, q, nr, d_res);
@@ -2340,14 +2368,10 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr, 0.5);
   hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t3, C.g_t2);
   // T dv -> g_t3 (S dv unused -> g_t4); then S av -> g_x (T av -> g_t4)
-  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
-                     (const double*)C.g_t1, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t3, C.g_t4, nr);
+  csr_launch(C, st, 3, C.g_t1, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t3, C.g_t4);
   double a[kMaxRhs], b[kMaxRhs];
   dot_to_host(C, C.g_t1, C.g_t3, ni, a);
-  hipLaunchKernelGGL(k_csr, dim3(nblk8(n)), dim3(256), 0, st, 3, ni, C.d_rp, C.d_ci, C.d_vals,
-                     (const double*)C.g_t2, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr,
-                     (const double*)nullptr, C.dt, 0.0, 0.0, C.g_t4, C.g_x, nr);
+  csr_launch(C, st, 3, C.g_t2, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t4, C.g_x);
   dot_to_host(C, C.g_t2, C.g_x, ni, b);
   for (int r = 0; r < nr; ++r) out[r] = a[r] + b[r];
   return DD_OK;

@@ -1180,6 +1180,126 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
   }
 }
 
+// Cooperative form of k_csr for 5..32 right-hand sides: the G lanes of a row
+// (G = 8, 16 or 32 >= nrhs; lanes past nrhs only help with the loads) first
+// load a batch of NB of the row's index/value pairs in one round trip and
+// stage them in LDS; every lane of the row then reads them back as
+// broadcasts and issues all gathers of the batch together (in chunks of 4
+// up to the wave's longest row).  Rows of the edge
+// matrices of tetrahedral meshes hold up to about 20 nonzeros, one batch of
+// NB = 20.
+// Each row lies inside one wavefront, so only the wave synchronises on LDS;
+// the trip count of the batch loop is the wave's maximum, so the wave stays
+// converged.  The products are summed in ascending nonzero order, as in
+// k_csr.  MODE is k_csr's mode, fixed at compile time so that no gather
+// sits in a branch.
+template <int G, int NB, int MODE>
+__global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const double2* __restrict__ v,
+                                                  const double* __restrict__ x1, const double* __restrict__ x2,
+                                                  const double* __restrict__ j1, const double* __restrict__ j2,
+                                                  const double* __restrict__ z, double dt, double ca, double cb,
+                                                  double* __restrict__ y, double* __restrict__ y2, int nrhs) {
+  static_assert(G == 8 || G == 16 || G == 32, "lanes per row");
+  static_assert(NB % 4 == 0, "index reads of four");
+  constexpr int E = (NB + G - 1) / G;  // staged nonzeros per lane
+  constexpr int ROWS = 256 / G;         // rows per workgroup
+  __shared__ int4 s_c[ROWS * NB / 4];
+  __shared__ double2 s_v[ROWS * NB];
+  const int64_t blk = xcd_contiguous_block();
+  if (blk * (256 / G) >= nint) return;  // whole workgroup past the last row
+  const int64_t i = blk * 256 + threadIdx.x;
+  const int lr = (int)(i % G);
+  const int64_t row_raw = i / G;
+  const bool live = row_raw < nint && lr < nrhs;
+  const int64_t row = row_raw < nint ? row_raw : nint - 1;
+  const int rr = lr < nrhs ? lr : nrhs - 1;  // column of the gathers
+  const int gb = ((int)threadIdx.x / G) * NB;  // this row's LDS slots
+  int32_t* sc = reinterpret_cast<int32_t*>(s_c);
+  const int64_t k0 = rp[row], k1 = rp[row + 1];
+  int nbat = (int)((k1 - k0 + NB - 1) / NB);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) nbat = max(nbat, __shfl_xor(nbat, off));
+  double t1 = 0.0, s1 = 0.0, t2 = 0.0, s2 = 0.0;
+  for (int bi = 0; bi < nbat; ++bi) {
+    const int64_t kb = k0 + (int64_t)bi * NB;
+    // nonzeros of this batch in the wave's longest row (uniform): chunks of
+    // gathers past it are skipped
+    int wcnt = (int)(k1 - kb < NB ? (k1 - kb > 0 ? k1 - kb : 0) : NB);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) wcnt = max(wcnt, __shfl_xor(wcnt, off));
+    wcnt = __builtin_amdgcn_readfirstlane(wcnt);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int slot = e * G + lr;
+      const int64_t k = kb + slot;
+      const int64_t kc = k < k1 ? k : (k1 > k0 ? k0 : 0);  // in bounds (nnz > 0)
+      const int32_t cv = ci[kc];
+      const double2 vv = v[kc];
+      // padding: the row's first column with a zero value (adds an exact
+      // zero for finite x, and reads nothing outside the row's own columns)
+      if (slot < NB) {
+        sc[gb + slot] = cv;
+        s_v[gb + slot] = k < k1 ? vv : make_double2(0.0, 0.0);
+      }
+    }
+    wave_lds_sync();
+    // gathers in chunks of 4 up to the wave's longest row, plain loads (no
+    // select to wait on; each chunk reads its 4 columns from LDS just
+    // before); all chunks go out before the first product waits.  MODE 0
+    // gathers its second vector in a second round.
+    auto gather = [&](const double* __restrict__ xv, double (&a)[NB]) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) a[u] = 0.0;
+#pragma unroll
+      for (int q = 0; q < NB / 4; ++q) {
+        if (wcnt > 4 * q) {
+          const int4 c4 = s_c[gb / 4 + q];
+          a[4 * q] = xv[(int64_t)c4.x * nrhs + rr];
+          a[4 * q + 1] = xv[(int64_t)c4.y * nrhs + rr];
+          a[4 * q + 2] = xv[(int64_t)c4.z * nrhs + rr];
+          a[4 * q + 3] = xv[(int64_t)c4.w * nrhs + rr];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    double a[NB];
+    gather(x1, a);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const double2 vv = s_v[gb + u];
+      t1 += vv.x * a[u];
+      s1 += vv.y * a[u];
+    }
+    if constexpr (MODE == 0) {
+      // a compiler-only fence that the first round's products feed: the
+      // second round's loads stay after them (register pressure)
+      __asm__ volatile("" : "+v"(t1), "+v"(s1)::"memory");
+      gather(x2, a);
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const double2 vv = s_v[gb + u];
+        t2 += vv.x * a[u];
+        s2 += vv.y * a[u];
+      }
+    }
+    wave_lds_sync();  // the next batch overwrites this row's slots
+  }
+  if (!live) return;
+  const int64_t o = row * nrhs + lr;
+  if constexpr (MODE == 0) {
+    y[o] = (2.0 * t1 + cb * s1) - (t2 + ca * s2) - dt * (j1[o] - j2[o]);
+  } else if constexpr (MODE == 1) {
+    y[o] = z[o] - (t1 + ca * s1);
+  } else if constexpr (MODE == 2) {
+    y[o] = 2.0 * t1 + cb * s1;
+    y2[o] = t1 + ca * s1;
+  } else {
+    y[o] = t1;
+    y2[o] = s1;
+  }
+}
+
 // --------------------------------------------------------------------------
 // K8: conjugate gradients on the interface system, per right-hand side.
 // Dot products: fixed-order two-stage reductions (deterministic).
@@ -1376,23 +1496,75 @@ __global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, con
 
 // z = K_lam r (the lumped preconditioner, CSR in multiplier space), fused
 // with the block partials of r.z (partial) and r.r (partial_b).
-__global__ void __launch_bounds__(256) k_lam_precond(int64_t nlam, const int64_t* __restrict__ rp,
+__global__ void __launch_bounds__(256, 4) k_lam_precond(int64_t nlam, const int64_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const double* __restrict__ res, double* __restrict__ z, int nrhs,
                                                      double* __restrict__ partial, double* __restrict__ partial_b,
                                                      const int* __restrict__ skip) {
   if (skip && *skip) return;
+  // Each lane keeps RU rows of its grid-stride sequence in flight and loads
+  // up to KB nonzeros of each before the gathers (unconditional loads from
+  // clamped indices; padding entries are zeroed at the products), so a pass
+  // costs three round trips for RU rows.  Rows, and the nonzeros in a row,
+  // are summed in the order of the plain loop.
+  constexpr int RU = 2, KB = 12;
   const int lpr = 256 / nrhs;
   const int tid = threadIdx.x, r = tid % nrhs, lane = tid / nrhs;
+  const int64_t stride = (int64_t)gridDim.x * lpr;
   double sz = 0.0, sr = 0.0;
   if (lane < lpr) {
-    for (int64_t l = (int64_t)blockIdx.x * lpr + lane; l < nlam; l += (int64_t)gridDim.x * lpr) {
-      double acc = 0.0;
-      for (int64_t k = rp[l]; k < rp[l + 1]; ++k) acc += val[k] * res[(int64_t)ci[k] * nrhs + r];
-      const double rv = res[l * nrhs + r];
-      z[l * nrhs + r] = acc;
-      sz += rv * acc;
-      sr += rv * rv;
+    for (int64_t l0 = (int64_t)blockIdx.x * lpr + lane; l0 < nlam; l0 += RU * stride) {
+      int64_t ka[RU], kz[RU];
+      double rv[RU], acc[RU];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        const int64_t lc = l < nlam ? l : nlam - 1;
+        const int64_t a0 = rp[lc], a1 = rp[lc + 1];
+        const double x = res[lc * nrhs + r];
+        ka[j] = a0;
+        kz[j] = l < nlam ? a1 : a0;  // rows past the end are empty
+        rv[j] = x;
+        acc[j] = 0.0;
+      }
+      int nb = 0;
+#pragma unroll
+      for (int j = 0; j < RU; ++j) nb = max(nb, (int)((kz[j] - ka[j] + KB - 1) / KB));
+      for (int bi = 0; bi < nb; ++bi) {
+        int32_t c[RU][KB];
+        double v[RU][KB], x[RU][KB];
+#pragma unroll
+        for (int j = 0; j < RU; ++j)
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            const int64_t k = ka[j] + (int64_t)bi * KB + u;
+            const int64_t kc = k < kz[j] ? k : 0;  // in bounds (the matrix is not empty here)
+            c[j][u] = ci[kc];
+            v[j][u] = val[kc];
+          }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < RU; ++j)
+#pragma unroll
+          for (int u = 0; u < KB; ++u) x[j][u] = res[(int64_t)c[j][u] * nrhs + r];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < RU; ++j)
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            const int64_t k = ka[j] + (int64_t)bi * KB + u;
+            acc[j] += (k < kz[j] ? v[j][u] : 0.0) * x[j][u];
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        if (l < nlam) {
+          z[l * nrhs + r] = acc[j];
+          sz += rv[j] * acc[j];
+          sr += rv[j] * rv[j];
+        }
+      }
     }
   }
   block_rhs_sum(sz, nrhs, lpr, partial);

@@ -115,16 +115,19 @@ def test_uneven_graded_multi_rhs(prec, tol, nrhs):
     assert err.max() <= tol
 
 
-def test_gauss_law_and_energy_match_oracle():
+# right-hand-side counts 2, 6, 12 and 24 take the per-thread sparse (T, S)
+# product and its cooperative forms with 8, 16 and 32 lanes per row
+@pytest.mark.parametrize("nrhs", [2, 6, 12, 24])
+def test_gauss_law_and_energy_match_oracle(nrhs):
     c, t, p, eps = _case(6, 2, eps_seed=4)
     dt = 0.05
     o = NewmarkOracle(c, t, eps=eps, dt=dt)
     N = 8
-    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.2, 0.06, seed=2, nrhs=2)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.2, 0.06, seed=2, nrhs=nrhs)
     J[5:] = 0.0
-    s = _solver(c, t, p, eps, dt=dt, nrhs=2, cg_tol=1e-13)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, cg_tol=1e-13)
     E, _ = _run_dd(s, J)
-    q = torch.zeros((2, s.n_vertices), dtype=torch.float64, device="cuda")
+    q = torch.zeros((nrhs, s.n_vertices), dtype=torch.float64, device="cuda")
     Jd = torch.tensor(J, device="cuda")
     qo = o.charge_history(J)
     for n in range(N):
@@ -136,19 +139,20 @@ def test_gauss_law_and_energy_match_oracle():
     np.testing.assert_allclose(H, Ho, rtol=1e-12)
 
 
-def test_adjoint_step_matches_oracle():
+@pytest.mark.parametrize("nrhs", [1, 6, 12, 24])
+def test_adjoint_step_matches_oracle(nrhs):
     c, t, p, eps = _case(5, 2, eps_seed=6)
     dt = 0.05
     o = NewmarkOracle(c, t, eps=eps, dt=dt)
     N = 6
-    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.15, 0.05, seed=8)
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.15, 0.05, seed=8, nrhs=nrhs)
     E = o.run(J)
     rng = np.random.default_rng(3)
     ebar = rng.standard_normal(E[-1].shape); ebar[:, o.d.pec] = 0.0
     Jbar_o, epsbar_o = o.adjoint(J, E, ebar)
-    s = _solver(c, t, p, eps, dt=dt, cg_tol=1e-13)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, cg_tol=1e-13)
     dev = lambda a: torch.tensor(a, device="cuda")
-    eb = [torch.zeros((1, o.d.n_e), dtype=torch.float64, device="cuda") for _ in range(N + 1)]
+    eb = [torch.zeros((nrhs, o.d.n_e), dtype=torch.float64, device="cuda") for _ in range(N + 1)]
     eb[N] = dev(ebar)
     epsbar = torch.zeros(len(t), dtype=torch.float64, device="cuda")
     g = [None] * (N + 1)
