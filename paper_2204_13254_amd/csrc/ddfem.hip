@@ -209,7 +209,7 @@ struct Ctx {
     void* partial = nullptr;
   } sym;
   // work vectors
-  void* X[9] = {};
+  void* X[10] = {};
   int64_t nlam = 0;
   double *d_d = nullptr, *d_lam = nullptr, *d_res = nullptr, *d_p = nullptr, *d_Fp = nullptr;
   // multipliers of the first solve of the last two steps (forward / adjoint),
@@ -849,7 +849,7 @@ static void build_device(Ctx& C, const double* coords) {
   }
   // ---- work vectors --------------------------------------------------------------------
   const int nr = C.nrhs;
-  for (int i = 0; i < 9; ++i) {
+  for (int i = 0; i < 10; ++i) {
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, std::max<int64_t>(1, C.rows_total) * nr * wsz);
     if (e == hipErrorOutOfMemory) throw DDError{DD_ERR_OOM, "device allocation failed"};
@@ -1267,9 +1267,14 @@ static void apply_local(Ctx& C, const int* skip) {
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
                        C.d_csccrow, (const T*)X[5], (T*)X[6], (T)1, nr, skip);
   }
+  // Psi_G^T z goes to its own buffer (rows of subdomains without corners
+  // stay zero from setup), so it does not wait for M v; consumers add X9
+  if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[9], nullptr, (T)1, skip);
   if (overlap) join_side(C);
-  if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[8], X[8], (T)1, skip);
 }
+
+// the second part of the local response (X9) when there is one
+static const void* corner_part(const Ctx& C) { return C.Kc > 0 ? C.X[9] : nullptr; }
 
 template <class T>
 static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool dot = false, bool gathered = false) {
@@ -1281,7 +1286,8 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
                        C.d_glam, p, (T*)X[5], nr, skip);
   apply_local<T>(C, skip);
   hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
-                     (const T*)X[8], Fp, dot ? p : (const double*)nullptr, nr, C.d_partial, skip);
+                     (const T*)X[8], (const T*)corner_part(C), Fp, dot ? p : (const double*)nullptr, nr,
+                     C.d_partial, skip);
 }
 
 // Robin variant: y = G lam = lam + lam(partner side) - R (x_G response of
@@ -1295,7 +1301,7 @@ static void apply_G(Ctx& C, const double* lam, double* y) {
                      (T*)C.X[5], nr, (const int*)nullptr);
   apply_local<T>(C, nullptr);
   hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
-                     C.d_partner2, lam, C.d_grow, (const T*)C.X[8], y, nr);
+                     C.d_partner2, lam, C.d_grow, (const T*)C.X[8], (const T*)corner_part(C), y, nr);
 }
 
 // per-RHS dot products a . b over the side vectors, to the host
@@ -1323,7 +1329,8 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
   double* V = C.d_gmV;
   auto vec = [&](int k) { return V + (int64_t)k * ldv; };
   hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
-                     C.d_partner2, (const double*)nullptr, C.d_grow, (const T*)C.X[4], C.d_gm_rhs, nr);
+                     C.d_partner2, (const double*)nullptr, C.d_grow, (const T*)C.X[4], (const T*)nullptr,
+                     C.d_gm_rhs, nr);
   HIPCHK(hipMemsetAsync(C.d_lam2, 0, nl * sizeof(double), st));
   double bnorm[kMaxRhs], ss[kMaxRhs];
   side_dots(C, C.d_gm_rhs, C.d_gm_rhs, bnorm);
@@ -1493,7 +1500,8 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   } else if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
     hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
-                       (const T*)X[4], C.d_d, (const double*)nullptr, nr, C.d_partial, (const int*)nullptr);
+                       (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, nr, C.d_partial,
+                       (const int*)nullptr);
     // ---- CG on F lambda = d ----------------------------------------------------
     HIPCHK(hipMemsetAsync(C.d_cg, 0, sizeof(CgState), st));
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,

@@ -36,7 +36,8 @@ __global__ void __launch_bounds__(256) k_robin_apply(int64_t n, const int64_t* _
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const int32_t* __restrict__ partner,
                                                      const double* __restrict__ lam, const int64_t* __restrict__ rows,
-                                                     const T* __restrict__ U, double* __restrict__ y, int nrhs) {
+                                                     const T* __restrict__ U, const T* __restrict__ U2,
+                                                     double* __restrict__ y, int nrhs) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
   const int64_t k = i / nrhs;
@@ -47,7 +48,11 @@ __global__ void __launch_bounds__(256) k_robin_apply(int64_t n, const int64_t* _
     const int32_t q = partner[k];
     if (q >= 0) s += lam[(int64_t)q * nrhs + r];
   }
-  for (int64_t j = rp[k]; j < rp[k + 1]; ++j) s -= val[j] * (double)U[rows[ci[j]] * nrhs + r];
+  for (int64_t j = rp[k]; j < rp[k + 1]; ++j) {
+    const int64_t x = rows[ci[j]] * nrhs + r;
+    const T u = U2 ? (T)(U[x] + U2[x]) : U[x];
+    s -= val[j] * (double)u;
+  }
   y[i] = s;
 }
 

@@ -1347,10 +1347,14 @@ __device__ __forceinline__ void block_rhs_sum(double s, int nrhs, int lanes_per_
 
 // F p = sum_s B_s u_s (each multiplier pulls its two copies, + lo, - hi),
 // fused with the block partials of p . Fp.
+// u2 (may be null) is added to u first, in T: the local response split
+// over two buffers (the symmetric product and the corner coupling, written
+// by different streams).
 template <class T>
 __global__ void __launch_bounds__(256) k_scatter_dot(int64_t nlam, const int64_t* __restrict__ row0,
                                                      const int64_t* __restrict__ row1, const T* __restrict__ u,
-                                                     double* __restrict__ Fp, const double* __restrict__ p, int nrhs,
+                                                     const T* __restrict__ u2, double* __restrict__ Fp,
+                                                     const double* __restrict__ p, int nrhs,
                                                      double* __restrict__ partial, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int lpr = 256 / nrhs;
@@ -1358,7 +1362,10 @@ __global__ void __launch_bounds__(256) k_scatter_dot(int64_t nlam, const int64_t
   double s = 0.0;
   if (lane < lpr) {
     for (int64_t l = (int64_t)blockIdx.x * lpr + lane; l < nlam; l += (int64_t)gridDim.x * lpr) {
-      const double f = (double)u[row0[l] * nrhs + r] - (double)u[row1[l] * nrhs + r];
+      const int64_t a = row0[l] * nrhs + r, b = row1[l] * nrhs + r;
+      const T ua = u2 ? (T)(u[a] + u2[a]) : u[a];
+      const T ub = u2 ? (T)(u[b] + u2[b]) : u[b];
+      const double f = (double)ua - (double)ub;
       Fp[l * nrhs + r] = f;
       if (p) s += p[l * nrhs + r] * f;
     }
