@@ -1102,7 +1102,8 @@ __global__ void __launch_bounds__(256) k_int_to_edges(int64_t ne, const int32_t*
 //   mode 1: y = z - A x1                          (refinement residual)
 //   mode 2: y = B1 x1, y2 = A x1                  (adjoint application)
 //   mode 3: y = T x1,  y2 = S x1                  (Gauss law, energy)
-// One thread per (row, rhs); vectors [nint][nrhs].
+// One thread per (row, rhs); vectors [nint][nrhs].  Used for up to 4 RHS;
+// k_csr_coop below computes the same for 5..32.
 // --------------------------------------------------------------------------
 // Rows are handed to XCDs in contiguous ranges (workgroup b runs on XCD
 // b % 8): the column gathers of neighbouring rows then hit the same L2.
