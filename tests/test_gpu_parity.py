@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 from oracle.newmark import NewmarkOracle
 from workloads.configs import workload
-from workloads.mesh import cube_mesh
+from workloads.mesh import centred_cube_mesh, cube_mesh
 from workloads.partition import box_partition, rcb_partition
 from workloads.sources import dense_random_source
 
@@ -246,3 +246,30 @@ def test_graph_replay_matches_eager():
         out[g] = (E, iters)
     assert np.array_equal(out[True][0], out[False][0])
     assert out[True][1] == out[False][1]
+
+
+@pytest.mark.parametrize("prec,nrhs,tol", [("fp64", 3, 1e-10), ("fp64", 6, 1e-10),
+                                           ("fp32_refine", 16, 1e-8), ("fp64", 24, 1e-10)])
+def test_long_rows_centred_mesh(prec, nrhs, tol):
+    """Cubes cut into 12 tetrahedra around their centres: edge-matrix rows of
+    up to 25 nonzeros, so the sparse (T, S) products take more than one batch
+    of a row's nonzeros, in every lane-group width.  Steps, the energy and the
+    Gauss law against the oracle."""
+    n = 4
+    c, t, _ = centred_cube_mesh(n)
+    p = np.repeat(box_partition(n, 2)[::6], 12)
+    eps = np.random.default_rng(17).uniform(1, 3, len(t))
+    dt = 0.04
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    rows = np.diff((abs(o.d.T) + abs(o.d.S)).tocsr().indptr)
+    assert rows.max() > 20
+    N = 6
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.1, 0.04, seed=19, nrhs=nrhs)
+    Eo = o.run(J)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, precision=prec,
+                cg_tol=1e-13 if prec == "fp64" else 1e-6, refine_tol=1e-12)
+    E, _ = _run_dd(s, J)
+    for k in range(1, N + 1):
+        assert relerr(E[k], Eo[k]).max() <= tol, k
+    H = s.energy(torch.tensor(E[-1], device="cuda"), torch.tensor(E[-2], device="cuda"))
+    np.testing.assert_allclose(H, o.energy(E[-1], E[-2]), rtol=1e-12)

@@ -95,3 +95,49 @@ def jittered_cube_mesh(n: int, amp: float, seed: int):
     coords = coords.copy()
     coords[inner] += rng.uniform(-amp / n, amp / n, size=(int(inner.sum()), 3))
     return coords, tets, hx
+
+
+def centred_cube_mesh(n: int):
+    """The n^3 hexahedra each cut into 12 tetrahedra around an added centre
+    vertex: every face is split into two triangles along the diagonal through
+    its vertex of smallest id (the same choice from both sides, so the mesh
+    is conforming), and each triangle is joined to the centre.  Edges meet
+    more tetrahedra than in the Kuhn split, so rows of the edge matrices are
+    longer (up to the high 20s).
+
+    Returns (coords, tets, hex_of_tet); centre of hexahedron h has vertex id
+    (n+1)^3 + h; tetrahedra of hexahedron h are 12h .. 12h+11.
+    """
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    coords, _, _ = cube_mesh(n)
+    hi, hj, hk = hex_ijk(n)
+    centres = np.stack([hi + 0.5, hj + 0.5, hk + 0.5], axis=1) / n
+    coords = np.concatenate([coords, centres])
+    nv0 = (n + 1) ** 3
+    # faces of a unit cube as corner offsets in cyclic order
+    faces = (
+        ((0, 0, 0), (0, 1, 0), (0, 1, 1), (0, 0, 1)),
+        ((1, 0, 0), (1, 1, 0), (1, 1, 1), (1, 0, 1)),
+        ((0, 0, 0), (1, 0, 0), (1, 0, 1), (0, 0, 1)),
+        ((0, 1, 0), (1, 1, 0), (1, 1, 1), (0, 1, 1)),
+        ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)),
+        ((0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)),
+    )
+    n_hex = n ** 3
+    tets = np.empty((n_hex, 12, 4), dtype=np.int64)
+    c = nv0 + np.arange(n_hex)
+    t = 0
+    for f in faces:
+        q = np.stack([vertex_id(hi + a, hj + b, hk + d, n) for a, b, d in f], axis=1)  # [n_hex, 4]
+        m = np.argmin(q, axis=1)                      # diagonal through the smallest id
+        rows = np.arange(n_hex)
+        v0 = q[rows, m]
+        v1 = q[rows, (m + 1) % 4]
+        v2 = q[rows, (m + 2) % 4]
+        v3 = q[rows, (m + 3) % 4]
+        tets[:, t] = np.stack([c, v0, v1, v2], axis=1)
+        tets[:, t + 1] = np.stack([c, v0, v2, v3], axis=1)
+        t += 2
+    tets = tets.reshape(n_hex * 12, 4).astype(np.int32)
+    return coords, tets, np.repeat(np.arange(n_hex, dtype=np.int64), 12)
