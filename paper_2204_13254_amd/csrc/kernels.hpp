@@ -864,9 +864,20 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* _
   const T* add = crow ? add_c : add_r;
   const T alpha = crow ? alpha_c : alpha_r;
   const int64_t base = (q.row_off + (int64_t)w.o * kNB) * nrhs;
+  const int64_t stride = (int64_t)kNB * nrhs;
   for (int e = threadIdx.x; e < kNB * nrhs; e += 256) {
+    const T* pp = partial + (int64_t)w.slot0 * stride + e;
     T s = 0;
-    for (int k = 0; k < w.nslot; ++k) s += partial[(int64_t)(w.slot0 + k) * kNB * nrhs + e];
+    int k = 0;
+    // eight loads in flight before their adds (same order of the sum)
+    for (; k + 8 <= w.nslot; k += 8) {
+      T p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = pp[(int64_t)(k + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += p[u];
+    }
+    for (; k < w.nslot; ++k) s += pp[(int64_t)k * stride];
     T v = alpha * s;
     if (add) v += add[base + e];
     out[base + e] = v;
