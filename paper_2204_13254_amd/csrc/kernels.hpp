@@ -868,15 +868,17 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* _
   for (int e = threadIdx.x; e < kNB * nrhs; e += 256) {
     const T* pp = partial + (int64_t)w.slot0 * stride + e;
     T s = 0;
-    // eight loads in flight before their adds, the last batch from clamped
-    // (valid) slots whose values are not added; the sum keeps slot order
+    // up to eight loads in flight before their adds (n is uniform: scalar
+    // branches, no wasted loads); the sum keeps slot order
     for (int k = 0; k < w.nslot; k += 8) {
+      const int n = min(8, w.nslot - k);
       T p[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) p[u] = pp[(int64_t)min(k + u, w.nslot - 1) * stride];
+      for (int u = 0; u < 8; ++u)
+        if (u < n) p[u] = pp[(int64_t)(k + u) * stride];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (k + u < w.nslot) s += p[u];
+        if (u < n) s += p[u];
     }
     T v = alpha * s;
     if (add) v += add[base + e];
