@@ -103,7 +103,7 @@ def centred_cube_mesh(n: int):
     its vertex of smallest id (the same choice from both sides, so the mesh
     is conforming), and each triangle is joined to the centre.  Edges meet
     more tetrahedra than in the Kuhn split, so rows of the edge matrices are
-    longer (up to the high 20s).
+    longer: up to 25 nonzeros, against 19 for the Kuhn split.
 
     Returns (coords, tets, hex_of_tet); centre of hexahedron h has vertex id
     (n+1)^3 + h; tetrahedra of hexahedron h are 12h .. 12h+11.
