@@ -340,6 +340,12 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = k
       continue;
     }
     int32_t n = std::max(1, (b.hi - b.lo + chunk - 1) / chunk);
+    if (n == 1) {
+      // a row that fits one wave writes its output directly (no partial)
+      v.push_back({b.s, b.o, b.lo, b.hi, -1, 0});
+      chunk_of.push_back(0);
+      continue;
+    }
     int32_t oidx = (int32_t)outs.size();
     outs.push_back({b.s, b.o, slot, n});
     for (int32_t c = 0; c < n; ++c) {
