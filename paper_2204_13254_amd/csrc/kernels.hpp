@@ -1373,15 +1373,39 @@ __global__ void __launch_bounds__(256) k_scatter_dot(int64_t nlam, const int64_t
   if (skip && *skip) return;
   const int lpr = 256 / nrhs;
   const int tid = threadIdx.x, r = tid % nrhs, lane = tid / nrhs;
+  // RU multipliers of the lane's grid-stride sequence in flight at once
+  // (indices, then gathers; reads past the end are clamped and not used);
+  // the dot is summed in the order of the plain loop
+  constexpr int RU = 4;
+  const int64_t stride = (int64_t)gridDim.x * lpr;
   double s = 0.0;
   if (lane < lpr) {
-    for (int64_t l = (int64_t)blockIdx.x * lpr + lane; l < nlam; l += (int64_t)gridDim.x * lpr) {
-      const int64_t a = row0[l] * nrhs + r, b = row1[l] * nrhs + r;
-      const T ua = u2 ? (T)(u[a] + u2[a]) : u[a];
-      const T ub = u2 ? (T)(u[b] + u2[b]) : u[b];
-      const double f = (double)ua - (double)ub;
-      Fp[l * nrhs + r] = f;
-      if (p) s += p[l * nrhs + r] * f;
+    for (int64_t l0 = (int64_t)blockIdx.x * lpr + lane; l0 < nlam; l0 += RU * stride) {
+      int64_t a[RU], b[RU], lc[RU];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        lc[j] = l < nlam ? l : nlam - 1;
+        a[j] = row0[lc[j]] * nrhs + r;
+        b[j] = row1[lc[j]] * nrhs + r;
+      }
+      T ua[RU], ub[RU];
+      double pv[RU];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        ua[j] = u2 ? (T)(u[a[j]] + u2[a[j]]) : u[a[j]];
+        ub[j] = u2 ? (T)(u[b[j]] + u2[b[j]]) : u[b[j]];
+        pv[j] = p ? p[lc[j] * nrhs + r] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        if (l < nlam) {
+          const double f = (double)ua[j] - (double)ub[j];
+          Fp[l * nrhs + r] = f;
+          if (p) s += pv[j] * f;
+        }
+      }
     }
   }
   block_rhs_sum(s, nrhs, lpr, partial);
