@@ -273,3 +273,28 @@ def test_long_rows_centred_mesh(prec, nrhs, tol):
         assert relerr(E[k], Eo[k]).max() <= tol, k
     H = s.energy(torch.tensor(E[-1], device="cuda"), torch.tensor(E[-2], device="cuda"))
     np.testing.assert_allclose(H, o.energy(E[-1], E[-2]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("parts,prec,nrhs,method,tol", [((2, 1, 1), "fp64", 2, "dp1", 1e-10),
+                                                       ((3, 1, 1), "fp32_refine", 16, "dp1", 1e-8),
+                                                       ((3, 1, 1), "fp64", 6, "dp2", 1e-10)])
+def test_slabs_without_corners(parts, prec, nrhs, method, tol):
+    """Slab partitions: every interface edge is shared by two subdomains, so
+    there are no corners and no coarse problem; the interface solve runs
+    without the corner passes (first variant) or with GMRES (Robin)."""
+    from paper_2204_13254_amd.solver import analyze
+    n = 6
+    c, t, _ = cube_mesh(n)
+    p = box_partition(n, parts)
+    assert analyze(c, t, p)[1][:, 2].max() == 0
+    eps = np.random.default_rng(23).uniform(1, 3, len(t))
+    dt = 0.05
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    N = 5
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.12, 0.04, seed=29, nrhs=nrhs)
+    Eo = o.run(J)
+    s = _solver(c, t, p, eps, dt=dt, nrhs=nrhs, precision=prec, method=method, cg_max_iter=400,
+                cg_tol=1e-13 if prec == "fp64" else 1e-6, refine_tol=1e-12)
+    E, _ = _run_dd(s, J)
+    for k in range(1, N + 1):
+        assert relerr(E[k], Eo[k]).max() <= tol, k
