@@ -95,7 +95,7 @@ struct Items {
 constexpr int kChunkTiles = 32;  // longest tile range of one wave
 // coarse lists are few and long; 16-tile chunks measured best (8: +10%, 4: +28%)
 constexpr int kCoarseChunkTiles = 16;
-constexpr int kFullChunkTiles = 48;
+constexpr int kFullChunkTiles = 96;
 
 struct Ctx {
   Plan P;
@@ -1047,8 +1047,9 @@ static void full_tile_lists(Ctx& C) {
     throw DDError{DD_ERR_OOM, "tile lists exceed 2^31 entries"};
   release_items(C, C.full_N);
   release_items(C, C.full_T);
-  // 48-tile chunks: most rows stay in one wave (32: +3% from the extra
-  // reduce traffic, 64: +1% from the longest waves)
+  // 96-tile chunks: rows of the bench subdomains stay in one wave and write
+  // their outputs directly (at 64^3 per pass: 48 tiles 1.465 ms, 64 1.444,
+  // 80 1.432, 96 1.430, 128 1.432)
   C.full_N = make_items(C, bn, kFullChunkTiles, true);
   C.full_N.mlist = upload(ln, C.owned, C.st);
   C.full_T = make_items(C, bt, kFullChunkTiles, true);
