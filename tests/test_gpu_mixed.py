@@ -91,3 +91,29 @@ def test_mixed_needs_quarter_beta():
     z = s.new_field()
     with pytest.raises(DDError, match="DD_ERR_STATE"):
         s.step_mixed(z, z, s.new_face_field())
+
+
+def test_mixed_steps_on_slabs():
+    """Slab partition (no corners, no coarse problem): the mixed step against
+    the oracle in FP64."""
+    from paper_2204_13254_amd.solver import DDSolver
+    n = 5
+    c, t, _ = cube_mesh(n)
+    p = box_partition(n, (3, 1, 1))
+    rng = np.random.default_rng(41)
+    eps = rng.uniform(1, 3, len(t))
+    mu = rng.uniform(1, 2, len(t))
+    dt = 0.04
+    s = DDSolver(c, t, p, eps, mu, dt=dt, beta=0.25, nrhs=2, cg_tol=1e-13, cg_max_iter=400)
+    o = MixedOracle(c, t, eps=eps, mu=mu, dt=dt)
+    N = 5
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.12, 0.04, seed=43, nrhs=2)
+    b0 = np.ascontiguousarray((o.C @ rng.normal(size=(o.d.n_int, 2))).T)
+    Eo, Bo = o.run(J, None, b0)
+    E = torch.zeros((2, o.d.n_e), dtype=torch.float64, device="cuda")
+    B = torch.tensor(b0, device="cuda")
+    Jd = torch.tensor(J, device="cuda")
+    for k in range(N):
+        E, B = s.step_mixed(Jd[k], E, B)
+        assert relerr(E.cpu().numpy(), Eo[k + 1]).max() <= 1e-10
+        assert relerr(B.cpu().numpy(), Bo[k + 1]).max() <= 1e-10

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 from oracle import pic
 from oracle.newmark import NewmarkOracle
 from workloads.beam import BeamSampler, deposit as kuhn_deposit
-from workloads.mesh import cube_mesh, jittered_cube_mesh, mesh_edges
+from workloads.mesh import centred_cube_mesh, cube_mesh, jittered_cube_mesh, mesh_edges
 from workloads.partition import box_partition
 from workloads.sources import dense_random_source
 
@@ -385,3 +385,37 @@ def test_beam_fullsize_deposit():
         s.pic_deposit(_dev(a[p:p + 1]), _dev(b[p:p + 1]), _dev(q[p:p + 1]), c1, J1)
         Jo = pic.deposit(mesh, a[p], b[p], q[p], dt)
         np.testing.assert_allclose(_host(J1), Jo, rtol=0, atol=1e-12 * np.abs(Jo).max())
+
+
+def test_locate_and_deposit_on_centred_mesh():
+    """Another topology: cubes cut into 12 tetrahedra around their centres
+    (vertices shared by up to 24 tetrahedra, centre vertices by 12).  Location
+    and the exact deposit of long paths (crossing many cells, through the
+    added centres' neighbourhoods) against the brute-force oracle."""
+    from paper_2204_13254_amd.solver import DDSolver
+    n = 4
+    c, t, _ = centred_cube_mesh(n)
+    mesh = pic.TetMesh(c, t)
+    p = np.repeat(box_partition(n, 2)[::6], 12)
+    dt = 0.05
+    s = DDSolver(c, t, p, np.ones(len(t)), dt=dt, factor=False)
+    rng = np.random.default_rng(31)
+    m = 300
+    A = rng.uniform(0.03, 0.97, (m, 3))
+    d = rng.normal(size=(m, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    B = A + d * rng.uniform(0.0, 0.5, m)[:, None]
+    sw = _wall_exit(A, B)
+    out = sw < 1.0
+    Bc = np.where(out[:, None], A + (B - A) * sw[:, None], B)
+    q = rng.uniform(-1, 1, m)
+    cell, nout = _locate(s, _dev(A))
+    ch = _host(cell)
+    assert nout == 0
+    lam = np.array([mesh.lam(x, np.array([k]))[0] for x, k in zip(A, ch)])
+    assert lam.min() >= -1e-12
+    J = torch.zeros(s.n_edges, dtype=torch.float64, device="cuda")
+    nabs = _deposit(s, _dev(A), _dev(B), _dev(q), cell, J)
+    Jo = pic.deposit(mesh, A, Bc, q, dt)
+    np.testing.assert_allclose(_host(J), Jo, rtol=0, atol=1e-12 * np.abs(Jo).max())
+    assert nabs == int(out.sum()) and out.sum() > 10
