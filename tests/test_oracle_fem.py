@@ -151,6 +151,21 @@ def test_curl_grad_zero(n, grade):
     assert abs(d.T @ G).max() > 1e-3 * abs(d.T).max()
 
 
+def test_de_rham_on_centred_mesh():
+    """The same two facts on another topology (cubes cut into 12 tetrahedra
+    around an added centre): S G = 0, and dim ker S = number of interior
+    vertices = (n-1)^3 grid vertices + n^3 centres."""
+    from workloads.mesh import centred_cube_mesh
+    n = 3
+    c, t, _ = centred_cube_mesh(n)
+    rng = np.random.default_rng(5)
+    d = Discretisation(c, t, eps=rng.uniform(1, 4, len(t)), mu=rng.uniform(0.5, 2, len(t)))
+    G = d.gradient()
+    assert abs(d.S @ G).max() <= 1e-13 * abs(d.S).max()
+    w = np.linalg.eigvalsh(Discretisation(c, t).S.toarray())
+    assert (np.abs(w) < 1e-10 * w.max()).sum() == (n - 1) ** 3 + n ** 3
+
+
 def test_kernel_dimension():
     """dim ker S = number of interior vertices = (n-1)^3."""
     n = 3

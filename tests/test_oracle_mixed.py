@@ -32,6 +32,18 @@ def test_curl_curl_from_face_mass(jm):
     assert np.abs(S2 - S).max() <= 1e-12 * np.abs(S).max()
 
 
+def test_curl_curl_from_face_mass_centred_mesh():
+    """S = C^T M C also on the centred-cube topology (faces of 12-tetrahedron
+    cubes, diagonals chosen by the smallest vertex id)."""
+    from workloads.mesh import centred_cube_mesh
+    c, t, _ = centred_cube_mesh(2)
+    mu = np.random.default_rng(9).uniform(1, 2, len(t))
+    o = MixedOracle(c, t, mu=mu, dt=0.1, factor=False)
+    S2 = (o.C.T @ o.M @ o.C).toarray()
+    S = o.d.S.toarray()
+    assert np.abs(S2 - S).max() <= 1e-12 * np.abs(S).max()
+
+
 def test_divergence_of_curl_is_zero(jm):
     c, t, mu = jm
     faces, tf = canonical_faces(t)
