@@ -13,7 +13,7 @@ import pytest
 
 from oracle import pic
 from workloads.beam import deposit as kuhn_deposit
-from workloads.mesh import cube_mesh, jittered_cube_mesh
+from workloads.mesh import centred_cube_mesh, cube_mesh, jittered_cube_mesh
 
 
 @pytest.fixture(scope="module")
@@ -89,10 +89,19 @@ def test_deposit_along_an_edge_is_unit(jmesh):
         np.testing.assert_allclose(J, ref, rtol=0, atol=1e-12)
 
 
-def test_deposit_discrete_continuity(jmesh):
+@pytest.fixture(scope="module")
+def cmesh():
+    c, t, _ = centred_cube_mesh(3)
+    return pic.TetMesh(c, t)
+
+
+@pytest.mark.parametrize("which", ["jittered", "centred"])
+def test_deposit_discrete_continuity(jmesh, cmesh, which):
     """dt * sum_{e at k} sign(e, k) J_e = q (lam_k(b) - lam_k(a)) at every
     vertex k (sign +1 at the higher end): the charge that leaves the
-    hat function of k is the current through the edges at k."""
+    hat function of k is the current through the edges at k.  Also on the
+    centred-cube topology (vertices in up to 24 tetrahedra)."""
+    jmesh = jmesh if which == "jittered" else cmesh
     rng = np.random.default_rng(3)
     m = 30
     A = _inside_points(rng, m)
