@@ -34,28 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def _beam_worker(args):
-    coords, tets, edges, n, dt, beam, r, steps = args
-    from workloads.beam import beam_source
-    b = dict(beam)
-    b["seed"] = beam["seed"] + r
-    return beam_source(coords, tets, edges, n, 0, dt, 1, steps=steps, **b)[:, 0, :]
-
-
 def make_sources(w, coords, tets, steps, workers, start_method="fork"):
-    import numpy as np
-    from workloads.mesh import mesh_edges
-    if w.extra.get("source") != "beam":
-        return w.sources(tets, coords, N=max(steps) + 1)[list(steps)]
-    edges = mesh_edges(tets)
-    jobs = [(coords, tets, edges, w.n, w.dt, w.extra["beam"], r, list(steps)) for r in range(w.nrhs)]
-    if workers > 1:
-        import multiprocessing as mp
-        with mp.get_context(start_method).Pool(min(workers, len(jobs))) as pool:
-            parts = pool.map(_beam_worker, jobs)
-    else:
-        parts = [_beam_worker(j) for j in jobs]
-    return np.stack(parts, axis=1)          # [steps, nrhs, n_e]
+    return w.sources_for_steps(tets, coords, steps, workers, start_method)
 
 
 def cpu_baseline(target_nint, nrhs, seconds_hint=15.0):

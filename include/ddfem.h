@@ -81,7 +81,15 @@ typedef struct {
                          lam_i + lam_j + 2 alpha M_T x_j = 0 (M_T the tangential mass of the
                          interface faces); 0 = automatic, (eps h + beta dt^2 / (mu h)) / 2
                          with h the mean edge length and eps, mu the mean material values */
+  int diagnostics;    /* per-step checks of dd_step, reported in its stats; 0 = none;
+                         bit 0 (DD_DIAG_GAUSS): the context accumulates the nodal charge
+                         q^{n+1} = q^n + dt G^T J^{n+1/2} and evaluates the discrete Gauss
+                         law G^T T e^{n+1} + q^{n+1} at every interior vertex (Sec. IV-B,
+                         charge conservation); bit 1 (DD_DIAG_ENERGY): the discrete energy
+                         H^{n+1/2} of (e^{n+1}, e^n) */
 } dd_options;
+
+enum { DD_DIAG_GAUSS = 1, DD_DIAG_ENERGY = 2 };
 
 typedef struct {
   int cg_iters[32];        /* CG iterations of the last solve, per RHS */
@@ -90,7 +98,19 @@ typedef struct {
   double cg_relres[32];    /* final relative interface residual, per RHS */
   double global_relres[32];/* final ||b - A e|| / ||b|| (FP32_REFINE), per RHS */
   int solve_iters[4];      /* max over RHS of the CG iterations of DD solves 1..4 of the step */
+  int diagnostics;         /* the dd_options.diagnostics bits the fields below were computed for */
+  double gauss_residual[32];/* DD_DIAG_GAUSS: max over interior vertices of |G^T T e^{n+1} + q^{n+1}| */
+  double charge_max[32];   /* DD_DIAG_GAUSS: max over vertices of |q^{n+1}| (the scale of the above) */
+  double energy[32];       /* DD_DIAG_ENERGY: H^{n+1/2} = |e^{n+1}-e^n|_T^2/dt^2 + |(e^{n+1}+e^n)/2|_S^2 */
 } dd_stats;
+
+/* Mesh of a context: host arrays, read during the call only. */
+typedef struct {
+  int64_t n_vertices;
+  const double* coords;    /* [n_vertices][3] float64 */
+  int64_t n_tets;
+  const int32_t* tets;     /* [n_tets][4] int32, any vertex order */
+} dd_mesh;
 
 typedef struct {
   int64_t n_edges, n_interior, n_tets, n_vertices;
@@ -110,7 +130,7 @@ typedef struct {
 
 /* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
  * refine_tol 1e-12, refine_max 10, warm_start 0, use_graph 0, check_every 4,
- * precond 1, method 0, robin_alpha 0. */
+ * precond 1, method 0, robin_alpha 0, diagnostics 0. */
 void dd_default_options(dd_options* opt);
 
 /* Build a solver context (host analysis + device upload + element assembly
@@ -118,16 +138,15 @@ void dd_default_options(dd_options* opt);
  * s; an edge shared by two subdomains is an interface edge (one Lagrange
  * multiplier, +1 in the lower subdomain id, -1 in the higher); an edge shared
  * by three or more is a corner (a primal unknown of the coarse problem).
- *   coords    host [n_vertices][3] float64
- *   tets      host [n_tets][4] int32 (any vertex order)
+ *   mesh      vertices and tetrahedra (host arrays, see dd_mesh)
  *   partition host [n_tets] int32 in [0, n_sub), every id used
  *   eps, mu   host [n_tets] float64 relative permittivity / permeability
  *             (> 0, finite); mu may be NULL (= 1)
  *   dt, beta  time step and Newmark beta (> 0, finite)
+ * The accumulated nodal charge of DD_DIAG_GAUSS starts at zero.
  * Errors: DD_ERR_ARG, DD_ERR_MESH, DD_ERR_PARTITION, DD_ERR_NONFINITE,
  * DD_ERR_HIP, DD_ERR_OOM.  On error *out is NULL. */
-int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tets,
-             const int32_t* tets, const int32_t* partition, const double* eps,
+int dd_setup(void** out, const dd_mesh* mesh, const int32_t* partition, const double* eps,
              const double* mu, double dt, double beta, const dd_options* opt);
 
 /* Sizes of a context. */
@@ -140,9 +159,11 @@ int dd_num_edges(void* ctx, int64_t* n_edges);
  * uint8 PEC flags.  Either pointer may be NULL. */
 int dd_get_edges(void* ctx, int32_t* edges, uint8_t* is_pec);
 
-/* Replace the per-tetrahedron permittivity (host [n_tets] float64);
- * dd_factor must be called again before the next solve. */
-int dd_set_eps(void* ctx, const double* eps);
+/* Replace the per-tetrahedron permittivity ([n_tets] float64, a host array,
+ * or a device array if on_device != 0; validated on the host either way:
+ * DD_ERR_NONFINITE / DD_ERR_ARG for a non-finite or non-positive entry);
+ * dd_factor must be called again before the next solve.  Synchronises. */
+int dd_set_eps(void* ctx, const double* eps, int on_device);
 
 /* Element matrices, per-subdomain assembly [I | Gamma | c], partial Cholesky
  * of the r = I u Gamma block with the local corner Schur complement
@@ -150,15 +171,21 @@ int dd_set_eps(void* ctx, const double* eps);
  * triangular factors (the stored local inverses of Sec. III-C), assembly and
  * factorisation of the coarse corner matrix K_cc = sum_s B_c^T K_s B_c
  * (eq. (F1uc)).  Synchronises the stream.  DD_ERR_NOT_SPD names the first
- * subdomain with a non-positive pivot. */
+ * subdomain with a non-positive or non-finite pivot (for instance material
+ * values whose matrix entries overflow the factor precision); the context
+ * then refuses solves (DD_ERR_STATE) until a dd_factor succeeds. */
 int dd_factor(void* ctx);
 
 /* One Newmark step for all nrhs right-hand sides (device pointers):
  *   J_half, J_prev_half  [nrhs][n_edges]: J^{n+1/2}, J^{n-1/2}
  *   E_n, E_nm1           [nrhs][n_edges]: e^n, e^{n-1}
  *   E_next               [nrhs][n_edges]: e^{n+1} (output; may not alias inputs)
- * stats: host pointer or NULL.  DD_ERR_NO_CONVERGENCE leaves E_next holding
- * the last iterate and the context usable. */
+ * stats: host pointer or NULL; with dd_options.diagnostics set it also
+ * receives the Gauss residual and/or the energy of this step (the charge
+ * update runs whether stats is given or not).  DD_ERR_NO_CONVERGENCE leaves
+ * E_next holding the last iterate and the context usable.
+ * DD_ERR_NONFINITE: the right-hand side assembled from the inputs has a
+ * non-finite entry (its RHS is named in the message). */
 int dd_step(void* ctx, const double* J_half, const double* J_prev_half,
             const double* E_n, const double* E_nm1, double* E_next, dd_stats* stats);
 
@@ -167,17 +194,28 @@ int dd_step(void* ctx, const double* J_half, const double* J_prev_half,
 int dd_solve(void* ctx, const double* b, double* x, dd_stats* stats);
 
 /* One reverse step of the recurrence (A is symmetric, so the factors are
- * reused).  With ebar_next the total adjoint of e^{n+1}:
+ * reused; the reverse of the three-level Newmark form of Sec. II-B-2).
+ * With ebar_next the total adjoint of e^{n+1}:
  *   g = A^{-1} ebar_next;  ebar_n += (2A - dt^2 S) g;  ebar_nm1 -= A g;
  *   eps_bar[k] -= g . T_k (e^{n+1} - 2 e^n + e^{n-1})   (T_k: unit-eps mass)
- * summed over the right-hand sides.  All pointers are device pointers;
- * arrays are [nrhs][n_edges] except eps_bar [n_tets] (accumulated).
- * ebar_nm1 or eps_bar may be NULL (skipped).  E_nm1 NULL means e^{n-1} = 0. */
+ * summed over the right-hand sides, and, because the load of step n is
+ * -dt (J^{n+1/2} - J^{n-1/2}):
+ *   Jbar_half += -dt g   (adjoint of J^{n+1/2}),  Jbar_prev_half += dt g
+ * on the unknowns (conductor entries are left as they are).  All pointers
+ * are device pointers; arrays are [nrhs][n_edges] except eps_bar [n_tets]
+ * (accumulated).  ebar_n, ebar_nm1, g_out, eps_bar, Jbar_half and
+ * Jbar_prev_half may be NULL (skipped).  E_nm1 NULL means e^{n-1} = 0. */
 int dd_adjoint_step(void* ctx, const double* ebar_next, double* ebar_n, double* ebar_nm1,
                     double* g_out, const double* E_next, const double* E_n,
-                    const double* E_nm1, double* eps_bar, dd_stats* stats);
+                    const double* E_nm1, double* eps_bar, double* Jbar_half,
+                    double* Jbar_prev_half, dd_stats* stats);
 
-/* Discrete Gauss law (Sec. V-B charge conservation), device pointers:
+/* Accumulated nodal charge of DD_DIAG_GAUSS: q (device [nrhs][n_vertices]
+ * float64, entries of boundary vertices ignored) or NULL for zero; set it
+ * to the charge of the state e^n that the next dd_step starts from. */
+int dd_set_charge(void* ctx, const double* q);
+
+/* Discrete Gauss law (Sec. IV-B charge conservation), device pointers:
  *   dd_charge_update:  q += dt * G^T J_half   (q [nrhs][n_vertices], entries
  *                      of boundary vertices stay 0; G: +1 at the higher-id end)
  *   dd_gauss_residual: res[r] = max_k |(G^T T e + q)_k| over interior vertices
@@ -321,8 +359,7 @@ typedef struct {
 
 /* Partition analysis of Sec. III (interior / interface / corner classes).
  * per_sub (host [n_sub][3] int32, may be NULL) receives n_I, n_Gamma, n_c. */
-int dd_analyze(int64_t n_vertices, const double* coords, int64_t n_tets,
-               const int32_t* tets, const int32_t* partition, dd_analysis* out,
+int dd_analyze(const dd_mesh* mesh, const int32_t* partition, dd_analysis* out,
                int32_t* per_sub);
 
 /* Interface map of the same analysis: for each multiplier l (host arrays
@@ -330,8 +367,7 @@ int dd_analyze(int64_t n_vertices, const double* coords, int64_t n_tets,
  * positions of the edge in their local orders (0-based within the
  * [I | Gamma | c] order, unpadded).  The multiplier enters subdomain lo with
  * +1 and hi with -1. */
-int dd_analyze_lambda(int64_t n_vertices, const double* coords, int64_t n_tets,
-                      const int32_t* tets, const int32_t* partition,
+int dd_analyze_lambda(const dd_mesh* mesh, const int32_t* partition,
                       int32_t* edge, int32_t* sub_lo, int32_t* sub_hi,
                       int32_t* pos_lo, int32_t* pos_hi);
 

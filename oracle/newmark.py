@@ -65,9 +65,75 @@ def nested_dissection(d, leaf=2):
     return perm
 
 
+def mass_lower_bound(d):
+    """Certified lower bound on the smallest eigenvalue of A = T + c S (c >= 0).
+
+    S is a sum of positive semidefinite element matrices, so x.A x >= x.T x.
+    With x_k the six entries of x on the edges of tetrahedron k (zero on
+    conductor edges), x.T x = sum_k eps_k x_k.T_k x_k >= sum_k eps_k
+    lam_min(T_k) |x_k|^2, and every unknown lies on at least one
+    tetrahedron, so sum_k |x_k|^2 >= |x|^2.  Hence
+    lam_min(A) >= min_k eps_k lam_min(T_k) (T_k the unit-eps element mass).
+    """
+    lam = np.linalg.eigvalsh(d.unit_mass_elements())[:, 0]
+    return float((d.eps * lam).min())
+
+
+def pcg(A, b, x0=None, tol=1e-13, maxit=5000):
+    """Conjugate gradients with the diagonal (Jacobi) preconditioner for the
+    SPD matrix A and the columns of b [n, k], each column with its own
+    step lengths; a column stops changing once its recursively updated
+    residual is below tol ||b_col||.  The result is then re-checked with a
+    freshly computed residual b - A x, and the iteration restarted from x
+    while that true residual is above tol (at most 5 restarts).
+
+    Returns (x [n, k], iterations, true relative residuals [k])."""
+    A = A.tocsr()
+    b = np.asarray(b, dtype=np.float64)
+    dinv = 1.0 / A.diagonal()
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    bn = np.linalg.norm(b, axis=0)
+    bn = np.where(bn > 0, bn, 1.0)
+    total = 0
+    for _restart in range(6):
+        r = b - A @ x
+        rel = np.linalg.norm(r, axis=0) / bn
+        if (rel <= tol).all():
+            break
+        active = rel > tol
+        z = dinv[:, None] * r
+        p = z.copy()
+        rz = np.einsum("ij,ij->j", r, z)
+        for _ in range(maxit):
+            Ap = A @ p
+            pAp = np.einsum("ij,ij->j", p, Ap)
+            alpha = np.where(active, rz / np.where(pAp > 0, pAp, 1.0), 0.0)
+            x += alpha * p
+            r -= alpha * Ap
+            total += 1
+            active &= np.linalg.norm(r, axis=0) > tol * bn
+            if not active.any():
+                break
+            z = dinv[:, None] * r
+            rz_new = np.einsum("ij,ij->j", r, z)
+            beta = np.where(active, rz_new / np.where(rz != 0, rz, 1.0), 0.0)
+            p = z + beta * p
+            rz = rz_new
+    rel = np.linalg.norm(b - A @ x, axis=0) / bn
+    return x, total, rel
+
+
 class NewmarkOracle:
+    """The monolithic recurrence.  solver="direct" factorises A once
+    (SuperLU in a nested-dissection order); solver="pcg" solves every step
+    with Jacobi-preconditioned conjugate gradients to a true relative
+    residual of pcg_tol, for meshes whose factor does not fit a host, and
+    records after each solve the certified error bound
+    ||x - A^-1 b|| / ||x|| <= ||b - A x|| / (lam_lo ||x||), lam_lo from
+    mass_lower_bound."""
+
     def __init__(self, coords, tets, eps=None, mu=None, dt=0.05, beta=0.25,
-                 factor=True):
+                 factor=True, solver="direct", pcg_tol=1e-13):
         self.d = Discretisation(coords, tets, eps, mu)
         self.dt = float(dt)
         self.beta = float(beta)
@@ -75,7 +141,15 @@ class NewmarkOracle:
         self.A = (d.T + (self.beta * self.dt ** 2) * d.S).tocsc()
         self.B1 = (2.0 * d.T + ((2.0 * self.beta - 1.0) * self.dt ** 2) * d.S).tocsr()
         self.lu = None
-        if factor:
+        self.solver = solver
+        self.pcg_tol = float(pcg_tol)
+        self.solve_log = []          # pcg: (iterations, max true relres, max error bound)
+        if solver == "pcg":
+            self.A = self.A.tocsr()
+            self.lam_lo = mass_lower_bound(d)
+        elif solver != "direct":
+            raise ValueError(solver)
+        elif factor:
             self.perm = nested_dissection(self.d)
             Ap = self.A[self.perm][:, self.perm].tocsc()
             # A is SPD: keep the diagonal pivots, so this is a symmetric LU
@@ -89,15 +163,23 @@ class NewmarkOracle:
         return ((self.B1 @ e_n.T).T - (self.A @ e_nm1.T).T
                 - self.dt * (J_half - J_prev_half))
 
-    def solve(self, b):
-        """A^-1 b for b [nrhs, n_int]."""
+    def solve(self, b, x0=None):
+        """A^-1 b for b [nrhs, n_int]; x0 (same shape) is the pcg start."""
+        if self.solver == "pcg":
+            x, it, rel = pcg(self.A, np.asarray(b).T, None if x0 is None else np.asarray(x0).T,
+                             self.pcg_tol)
+            xn = np.linalg.norm(x, axis=0)
+            rn = rel * np.linalg.norm(np.asarray(b), axis=1)
+            bound = np.where(xn > 0, rn / (self.lam_lo * np.where(xn > 0, xn, 1.0)), 0.0)
+            self.solve_log.append((it, float(rel.max()), float(bound.max())))
+            return np.ascontiguousarray(x.T)
         bp = np.ascontiguousarray(np.asarray(b).T[self.perm])
         x = np.empty_like(bp)
         x[self.perm] = self.lu.solve(bp)
         return x.T
 
     def step(self, e_n, e_nm1, J_half, J_prev_half):
-        return self.solve(self.rhs(e_n, e_nm1, J_half, J_prev_half))
+        return self.solve(self.rhs(e_n, e_nm1, J_half, J_prev_half), x0=e_n)
 
     def run(self, J_half_edges):
         """Full history.  J_half_edges [N, nrhs, n_e] (J^{n+1/2}, n = 0..N-1).

@@ -22,13 +22,23 @@ class Options(C.Structure):
                 ("cg_max_iter", C.c_int), ("refine_tol", C.c_double), ("refine_max", C.c_int),
                 ("warm_start", C.c_int), ("use_graph", C.c_int), ("check_every", C.c_int),
                 ("stream", C.c_void_p), ("precond", C.c_int), ("method", C.c_int),
-                ("robin_alpha", C.c_double)]
+                ("robin_alpha", C.c_double), ("diagnostics", C.c_int)]
+
+
+DD_DIAG_GAUSS, DD_DIAG_ENERGY = 1, 2
 
 
 class Stats(C.Structure):
     _fields_ = [("cg_iters", C.c_int * 32), ("refine_sweeps", C.c_int), ("dd_solves", C.c_int),
                 ("cg_relres", C.c_double * 32), ("global_relres", C.c_double * 32),
-                ("solve_iters", C.c_int * 4)]
+                ("solve_iters", C.c_int * 4), ("diagnostics", C.c_int),
+                ("gauss_residual", C.c_double * 32), ("charge_max", C.c_double * 32),
+                ("energy", C.c_double * 32)]
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_vertices", C.c_int64), ("coords", C.c_void_p), ("n_tets", C.c_int64),
+                ("tets", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -52,15 +62,16 @@ D = C.c_double
 
 SIGNATURES = {
     "dd_default_options": (None, [C.POINTER(Options)]),
-    "dd_setup": (C.c_int, [C.POINTER(C.c_void_p), I64, P, I64, P, P, P, P, D, D, C.POINTER(Options)]),
+    "dd_setup": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(Mesh), P, P, P, D, D, C.POINTER(Options)]),
     "dd_get_info": (C.c_int, [P, C.POINTER(Info)]),
     "dd_get_edges": (C.c_int, [P, P, P]),
     "dd_num_edges": (C.c_int, [P, P]),
-    "dd_set_eps": (C.c_int, [P, P]),
+    "dd_set_eps": (C.c_int, [P, P, C.c_int]),
+    "dd_set_charge": (C.c_int, [P, P]),
     "dd_factor": (C.c_int, [P]),
     "dd_step": (C.c_int, [P, P, P, P, P, P, C.POINTER(Stats)]),
     "dd_solve": (C.c_int, [P, P, P, C.POINTER(Stats)]),
-    "dd_adjoint_step": (C.c_int, [P, P, P, P, P, P, P, P, P, C.POINTER(Stats)]),
+    "dd_adjoint_step": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, C.POINTER(Stats)]),
     "dd_charge_update": (C.c_int, [P, P, P]),
     "dd_gauss_residual": (C.c_int, [P, P, P, P]),
     "dd_energy": (C.c_int, [P, P, P, P]),
@@ -76,8 +87,8 @@ SIGNATURES = {
     "dd_pic_push": (C.c_int, [P, I64, P, P, P, P, P, P, P, P, C.c_int]),
     "dd_destroy": (None, [P]),
     "dd_last_error": (C.c_char_p, []),
-    "dd_analyze": (C.c_int, [I64, P, I64, P, P, C.POINTER(Analysis), P]),
-    "dd_analyze_lambda": (C.c_int, [I64, P, I64, P, P, P, P, P, P, P]),
+    "dd_analyze": (C.c_int, [C.POINTER(Mesh), P, C.POINTER(Analysis), P]),
+    "dd_analyze_lambda": (C.c_int, [C.POINTER(Mesh), P, P, P, P, P, P]),
 }
 
 _lib = None

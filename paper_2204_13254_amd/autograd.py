@@ -9,10 +9,11 @@ NewmarkDD.apply(J, eps, solver, checkpoint_every) -> E^N
 Forward keeps only (e^m, e^{m-1}) at every checkpoint_every-th step.  The
 backward pass replays each segment forward from its checkpoint and runs the
 hand-written adjoint step of the library (dd_adjoint_step, which reuses the
-symmetric factors):
+symmetric factors and accumulates every gradient itself):
     g^n = A^-1 ebar^{n+1};  ebar^n += (2A - dt^2 S) g^n;  ebar^{n-1} -= A g^n;
     eps_bar_k -= g^n . T_k (e^{n+1} - 2 e^n + e^{n-1});
-    Jbar^{n+1/2} = -dt g^n + dt g^{n+1}   (g^N = 0).
+    Jbar^{n+1/2} += -dt g^n,  Jbar^{n-1/2} += dt g^n.
+This module only orders the calls (checkpoints, replays, buffers).
 """
 from __future__ import annotations
 
@@ -64,11 +65,10 @@ class NewmarkDD(torch.autograd.Function):
         s, k = ctx.solver, ctx.k
         _set_eps(s, eps)
         N = J.shape[0]
-        dt = s.dt
         zero = torch.zeros_like(J[0])
         eps_bar = torch.zeros(s.n_tets, dtype=torch.float64, device=J.device)
-        g = [None] * (N + 1)
-        g[N] = zero
+        Jbar = torch.zeros_like(J)
+        g_buf = torch.empty_like(zero)
         # ebar buffers for the current window: ebar[n] accumulates until step n-1 is processed
         ebar = {N: gE.contiguous().clone(), N - 1: zero.clone()}
         starts = list(range(0, N, k))
@@ -82,8 +82,8 @@ class NewmarkDD(torch.autograd.Function):
                     ebar[n - 1] = zero.clone()
                 e_next, e_n = hist[n + 1 - m + 1], hist[n - m + 1]
                 e_nm1 = hist[n - m] if n >= 1 else None
-                g[n] = s.adjoint_step(ebar[n + 1], ebar[n], ebar[n - 1] if n >= 1 else None,
-                                      e_next, e_n, e_nm1, eps_bar)
+                s.adjoint_step(ebar[n + 1], ebar[n], ebar[n - 1] if n >= 1 else None,
+                               e_next, e_n, e_nm1, eps_bar, g_out=g_buf,
+                               Jbar_half=Jbar[n], Jbar_prev_half=Jbar[n - 1] if n >= 1 else None)
                 del ebar[n + 1]
-        Jbar = torch.stack([-dt * g[n] + dt * g[n + 1] for n in range(N)])
         return Jbar, eps_bar.to(eps.device, eps.dtype), None, None

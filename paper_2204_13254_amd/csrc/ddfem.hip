@@ -193,6 +193,8 @@ struct Ctx {
   int32_t* d_vedge = nullptr;
   uint8_t* d_nodeint = nullptr;
   double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
+  double* d_q = nullptr;     // accumulated nodal charge of the per-step check, [nrhs][nv]
+  double* d_gmax = nullptr;  // per-block maxima of the per-step check, [nrhs][kGaussBlocks][2]
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
   // trail_N: interface rows of Linv_GG (recovery); trail_T: Linv_GG^T with
@@ -812,6 +814,9 @@ static void build_device(Ctx& C, const double* coords) {
     C.d_vedge = upload(vedge, C.owned, st);
     C.d_nodeint = upload(P.node_interior, C.owned, st);
     C.d_vres = dalloc<double>(P.nv * C.nrhs, C.owned);
+    C.d_q = dalloc<double>(P.nv * C.nrhs, C.owned);
+    HIPCHK(hipMemsetAsync(C.d_q, 0, P.nv * C.nrhs * sizeof(double), st));
+    C.d_gmax = dalloc<double>((size_t)kGaussBlocks * kMaxRhs * 2, C.owned);
   }
   // ---- work lists --------------------------------------------------------------------
   {
@@ -1108,7 +1113,7 @@ static int factor_impl(Ctx& C) {
   if (err != INT32_MAX) {
     C.factored = false;
     if (err == C.nsub) throw DDError{DD_ERR_NOT_SPD, "coarse corner matrix is not positive definite"};
-    throw DDError{DD_ERR_NOT_SPD, "non-positive pivot in subdomain " + std::to_string(err)};
+    throw DDError{DD_ERR_NOT_SPD, "non-positive or non-finite pivot in subdomain " + std::to_string(err)};
   }
   C.factored = true;
   C.warm_fw.have = C.warm_adj.have = 0;
@@ -1690,24 +1695,36 @@ static void csr_launch(Ctx& C, hipStream_t st, int mode, const double* x1, const
 }
 
 // A^-1 b with iterative refinement in the mixed form.  b, x: [nint][nrhs].
+// what names the input of b in the message of a non-finite load.  With
+// tx != nullptr the mixed form also leaves T x of the returned iterate there
+// (from its last residual) and *tx_done is set; otherwise *tx_done = false.
 template <class T>
-static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd_stats* stats) {
+static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd_stats* stats,
+                         const char* what = "b", double* tx = nullptr, bool* tx_done = nullptr) {
   const int nr = C.nrhs;
   const int64_t n = C.P.nint * nr;
   hipStream_t st = C.st;
   int iters[kMaxRhs];
   double relres[kMaxRhs];
+  if (tx_done) *tx_done = false;
+  // |b|^2 per RHS before the solve: the reference of the refinement, and a
+  // non-finite load is reported instead of being iterated on
+  double bn[kMaxRhs];
+  dot_to_host(C, b, b, C.P.nint, bn);
+  for (int r = 0; r < nr; ++r)
+    if (!std::isfinite(bn[r]))
+      throw DDError{DD_ERR_NONFINITE, std::string("non-finite entry in the load of right-hand side ") +
+                                          std::to_string(r) + " (" + what + ")"};
   int status = dd_solve_once<T>(C, b, x, warm, iters, relres);
   int solve_iters[4] = {0, 0, 0, 0};
   for (int r = 0; r < nr; ++r) solve_iters[0] = std::max(solve_iters[0], iters[r]);
   int sweeps = 0;
   double gres[kMaxRhs] = {0};
   if (C.fp32 && C.opt.refine_max > 0) {
-    double bn[kMaxRhs];
-    dot_to_host(C, b, b, C.P.nint, bn);
+    if (tx_done) *tx_done = tx != nullptr;
     for (;;) {
       csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
-                 C.g_r, nullptr);
+                 C.g_r, tx);
       double rn[kMaxRhs];
       dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
       bool ok = true;
@@ -1746,6 +1763,24 @@ static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd
   return status;
 }
 
+// H^{n+1/2} = |e1 - e0|_T^2 / dt^2 + |(e1 + e0)/2|_S^2 per RHS (host out
+// [nrhs]) for unknown-major e1, e0, which must not be g_t3, g_t4, g_x or g_r
+// (used as scratch).  Synchronises.
+static void energy_int(Ctx& C, const double* e1, const double* e0, double* out) {
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, n = ni * nr;
+  hipStream_t st = C.st;
+  hipLaunchKernelGGL(k_diff_avg, dim3(nblk(n)), dim3(256), 0, st, n, e1, e0, 1.0 / C.dt, C.g_t3, C.g_t4);
+  double a[kMaxRhs], b[kMaxRhs];
+  // T dv -> g_x (S dv -> g_r, unused); dv . T dv
+  csr_launch(C, st, 3, C.g_t3, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_x, C.g_r);
+  dot_to_host(C, C.g_t3, C.g_x, ni, a);
+  // S av -> g_r (T av -> g_x, unused); av . S av
+  csr_launch(C, st, 3, C.g_t4, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_x, C.g_r);
+  dot_to_host(C, C.g_t4, C.g_r, ni, b);
+  for (int r = 0; r < nr; ++r) out[r] = a[r] + b[r];
+}
+
 template <class T>
 static int step_impl(Ctx& C, const double* J1, const double* J0, const double* En, const double* Enm1,
                      double* Enext, dd_stats* stats) {
@@ -1759,9 +1794,41 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J0, ne, C.g_x, nr, 1.0);
   csr_launch(C, st, 0, C.g_t1, C.g_t2, C.g_t3, C.g_x, nullptr, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
              C.g_b, nullptr);
-  int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start ? &C.warm_fw : nullptr, stats);
+  // g_t2 (e^{n-1}) is free once the load is assembled: the refinement's last
+  // residual leaves T e^{n+1} there for the Gauss check
+  const bool gauss = (C.opt.diagnostics & DD_DIAG_GAUSS) != 0;
+  bool have_tx = false;
+  int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start ? &C.warm_fw : nullptr, stats,
+                                "J, E_n or E_nm1", gauss ? C.g_t2 : nullptr, &have_tx);
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
                      Enext, nr, 0, 1.0);
+  if (gauss) {
+    // q^{n+1} = q^n + dt G^T J^{n+1/2}, then max |G^T T e^{n+1} + q^{n+1}|
+    hipLaunchKernelGGL(k_charge, dim3(nblk(C.P.nv * nr)), dim3(256), 0, st, (int64_t)C.P.nv, C.d_vptr, C.d_vedge,
+                       C.d_nodeint, J1, ne, C.dt, C.d_q, nr);
+    if (stats) {
+      if (!have_tx)
+        csr_launch(C, st, 3, C.g_e, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_t3);
+      hipLaunchKernelGGL(k_gauss_max, dim3(kGaussBlocks, nr), dim3(256), 0, st, (int64_t)C.P.nv, C.d_vptr,
+                         C.d_vedge, C.d_nodeint, C.d_dof, (const double*)C.g_t2, (const double*)C.d_q, nr,
+                         C.d_gmax);
+      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * kGaussBlocks * nr * 2, hipMemcpyDeviceToHost,
+                            st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int r = 0; r < nr; ++r) {
+        double g = 0.0, qm = 0.0;
+        for (int b = 0; b < kGaussBlocks; ++b) {
+          const double gb = C.h_partial[(r * kGaussBlocks + b) * 2], qb = C.h_partial[(r * kGaussBlocks + b) * 2 + 1];
+          g = (gb != gb || g != g) ? NAN : std::max(g, gb);
+          qm = std::max(qm, qb);
+        }
+        stats->gauss_residual[r] = g;
+        stats->charge_max[r] = qm;
+      }
+    }
+  }
+  if (stats && (C.opt.diagnostics & DD_DIAG_ENERGY)) energy_int(C, C.g_e, C.g_t1, stats->energy);
+  if (stats) stats->diagnostics = C.opt.diagnostics & (DD_DIAG_GAUSS | DD_DIAG_ENERGY);
   HIPCHK(hipGetLastError());
   return status;
 }
@@ -1773,7 +1840,7 @@ static int solve_api_impl(Ctx& C, const double* b, double* x, dd_stats* stats) {
   hipStream_t st = C.st;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, b, ne, C.g_t1, nr,
                      1.0);
-  int status = solve_refined<T>(C, C.g_t1, C.g_e, nullptr, stats);
+  int status = solve_refined<T>(C, C.g_t1, C.g_e, nullptr, stats, "b");
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e, x,
                      nr, 0, 1.0);
   HIPCHK(hipGetLastError());
@@ -1783,14 +1850,14 @@ static int solve_api_impl(Ctx& C, const double* b, double* x, dd_stats* stats) {
 template <class T>
 static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double* ebar_nm1, double* g_out,
                         const double* E_next, const double* E_n, const double* E_nm1, double* eps_bar,
-                        dd_stats* stats) {
+                        double* Jbar_half, double* Jbar_prev_half, dd_stats* stats) {
   const int nr = C.nrhs;
   const int64_t ni = C.P.nint, ne = C.P.ne;
   hipStream_t st = C.st;
   const int64_t n = ni * nr;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, ebar_next, ne, C.g_t1, nr,
                      1.0);
-  int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start ? &C.warm_adj : nullptr, stats);
+  int status = solve_refined<T>(C, C.g_t1, C.g_x, C.opt.warm_start ? &C.warm_adj : nullptr, stats, "ebar_next");
   // B1 g -> g_t2, A g -> g_t3
   csr_launch(C, st, 2, C.g_x, nullptr, nullptr, nullptr, nullptr, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
              C.g_t2, C.g_t3);
@@ -1803,6 +1870,13 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
   if (g_out)
     hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_x,
                        g_out, nr, 0, 1.0);
+  // the load of step n is -dt (J^{n+1/2} - J^{n-1/2})
+  if (Jbar_half)
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_x,
+                       Jbar_half, nr, 1, -C.dt);
+  if (Jbar_prev_half)
+    hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_x,
+                       Jbar_prev_half, nr, 1, C.dt);
   if (eps_bar) {
     // acc = e^{n+1} - 2 e^n + e^{n-1} in unknown-major layout
     hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
@@ -2134,15 +2208,15 @@ void dd_default_options(dd_options* o) {
   o->precond = 1;
   o->method = 0;
   o->robin_alpha = 0.0;
+  o->diagnostics = 0;
 }
 
 const char* dd_last_error(void) { return g_err.c_str(); }
 
 static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tets, const int32_t* tets,
-             const int32_t* partition, const double* eps, const double* mu, double dt, double beta,
-             const dd_options* opt) {
+int dd_setup(void** out, const dd_mesh* mesh, const int32_t* partition, const double* eps, const double* mu,
+             double dt, double beta, const dd_options* opt) {
   g_err.clear();
   if (!out) {
     g_err = "out is NULL";
@@ -2151,7 +2225,10 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
   *out = nullptr;
   Ctx* C = nullptr;
   API_BEGIN
-  if (!coords || !tets || !partition || !eps) throw DDError{DD_ERR_ARG, "null input pointer"};
+  if (!mesh || !mesh->coords || !mesh->tets || !partition || !eps) throw DDError{DD_ERR_ARG, "null input pointer"};
+  const int64_t n_vertices = mesh->n_vertices, n_tets = mesh->n_tets;
+  const double* coords = mesh->coords;
+  const int32_t* tets = mesh->tets;
   if (!std::isfinite(dt) || !std::isfinite(beta)) throw DDError{DD_ERR_NONFINITE, "non-finite dt or beta"};
   if (!(dt > 0) || !(beta > 0)) throw DDError{DD_ERR_ARG, "dt and beta must be positive"};
   dd_options o;
@@ -2164,6 +2241,7 @@ int dd_setup(void** out, int64_t n_vertices, const double* coords, int64_t n_tet
   if (o.precision != DD_FP64 && o.precision != DD_FP32_REFINE) throw DDError{DD_ERR_ARG, "unknown precision"};
   if (!(o.cg_tol > 0) || o.cg_max_iter < 1 || o.check_every < 1 || o.refine_max < 0 || !(o.refine_tol > 0))
     throw DDError{DD_ERR_ARG, "bad solver option"};
+  if (o.diagnostics & ~(DD_DIAG_GAUSS | DD_DIAG_ENERGY)) throw DDError{DD_ERR_ARG, "unknown diagnostics bit"};
   for (int64_t t = 0; t < n_tets; ++t) {
     if (!std::isfinite(eps[t]) || (mu && !std::isfinite(mu[t])))
       throw DDError{DD_ERR_NONFINITE, "non-finite eps or mu at tetrahedron " + std::to_string(t)};
@@ -2256,13 +2334,21 @@ int dd_get_edges(void* ctx, int32_t* edges, uint8_t* is_pec) {
   return DD_OK;
 }
 
-int dd_set_eps(void* ctx, const double* eps) {
-  if (!ctx || !eps) {
+int dd_set_eps(void* ctx, const double* eps_in, int on_device) {
+  if (!ctx || !eps_in) {
     g_err = "null argument";
     return DD_ERR_ARG;
   }
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
+  std::vector<double> staged;
+  const double* eps = eps_in;
+  if (on_device) {
+    staged.resize(C.P.nt);
+    HIPCHK(hipMemcpyAsync(staged.data(), eps_in, C.P.nt * sizeof(double), hipMemcpyDeviceToHost, C.st));
+    HIPCHK(hipStreamSynchronize(C.st));
+    eps = staged.data();
+  }
   for (int64_t t = 0; t < C.P.nt; ++t) {
     if (!std::isfinite(eps[t])) throw DDError{DD_ERR_NONFINITE, "non-finite eps"};
     if (!(eps[t] > 0)) throw DDError{DD_ERR_ARG, "eps must be positive"};
@@ -2324,7 +2410,7 @@ int dd_solve(void* ctx, const double* b, double* x, dd_stats* stats) {
 
 int dd_adjoint_step(void* ctx, const double* ebar_next, double* ebar_n, double* ebar_nm1, double* g_out,
                     const double* E_next, const double* E_n, const double* E_nm1, double* eps_bar,
-                    dd_stats* stats) {
+                    double* Jbar_half, double* Jbar_prev_half, dd_stats* stats) {
   if (!ctx || !ebar_next || (eps_bar && (!E_next || !E_n))) {
     g_err = "null argument";
     return DD_ERR_ARG;
@@ -2335,11 +2421,29 @@ int dd_adjoint_step(void* ctx, const double* ebar_next, double* ebar_n, double* 
     return DD_ERR_STATE;
   }
   API_BEGIN
-  int rc = C.fp32 ? adjoint_impl<float>(C, ebar_next, ebar_n, ebar_nm1, g_out, E_next, E_n, E_nm1, eps_bar, stats)
+  int rc = C.fp32 ? adjoint_impl<float>(C, ebar_next, ebar_n, ebar_nm1, g_out, E_next, E_n, E_nm1, eps_bar,
+                                        Jbar_half, Jbar_prev_half, stats)
                   : adjoint_impl<double>(C, ebar_next, ebar_n, ebar_nm1, g_out, E_next, E_n, E_nm1, eps_bar,
-                                         stats);
+                                         Jbar_half, Jbar_prev_half, stats);
   if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
   return rc;
+  API_END
+}
+
+int dd_set_charge(void* ctx, const double* q) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  const int64_t n = C.P.nv * C.nrhs;
+  if (q)
+    HIPCHK(hipMemcpyAsync(C.d_q, q, n * sizeof(double), hipMemcpyDeviceToDevice, C.st));
+  else
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, C.st, n, 0.0, C.d_q);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
   API_END
 }
 
@@ -2393,26 +2497,12 @@ int dd_energy(void* ctx, const double* E_next, const double* E_n, double* out) {
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
   const int nr = C.nrhs;
-  const int64_t ni = C.P.nint, ne = C.P.ne, n = ni * nr;
-  hipStream_t st = C.st;
-  // g_t1 = (e1 - e0)/dt, g_t2 = (e1 + e0)/2
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t4, nr,
-                     1.0 / C.dt);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr,
-                     1.0 / C.dt);
-  hipLaunchKernelGGL(k_sub, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.g_t4, (const double*)C.g_t3,
-                     C.g_t1);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_next, ne, C.g_t2, nr,
-                     0.5);
-  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, E_n, ne, C.g_t3, nr, 0.5);
-  hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t3, C.g_t2);
-  // T dv -> g_t3 (S dv unused -> g_t4); then S av -> g_x (T av -> g_t4)
-  csr_launch(C, st, 3, C.g_t1, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t3, C.g_t4);
-  double a[kMaxRhs], b[kMaxRhs];
-  dot_to_host(C, C.g_t1, C.g_t3, ni, a);
-  csr_launch(C, st, 3, C.g_t2, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t4, C.g_x);
-  dot_to_host(C, C.g_t2, C.g_x, ni, b);
-  for (int r = 0; r < nr; ++r) out[r] = a[r] + b[r];
+  const int64_t ni = C.P.nint, ne = C.P.ne;
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, C.st, ni, C.d_interior, E_next, ne, C.g_t1,
+                     nr, 1.0);
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, C.st, ni, C.d_interior, E_n, ne, C.g_t2, nr,
+                     1.0);
+  energy_int(C, C.g_t1, C.g_t2, out);
   return DD_OK;
   API_END
 }
@@ -2622,17 +2712,16 @@ int dd_pic_push(void* ctx, int64_t n, const double* qm, const double* E, const d
 
 void dd_destroy(void* ctx) { delete (Ctx*)ctx; }
 
-int dd_analyze(int64_t n_vertices, const double* coords, int64_t n_tets, const int32_t* tets,
-               const int32_t* partition, dd_analysis* out, int32_t* per_sub) {
+int dd_analyze(const dd_mesh* mesh, const int32_t* partition, dd_analysis* out, int32_t* per_sub) {
   g_err.clear();
-  if (!out) {
-    g_err = "out is NULL";
+  if (!out || !mesh) {
+    g_err = "out or mesh is NULL";
     return DD_ERR_ARG;
   }
   API_BEGIN
   Plan P;
   std::string msg;
-  int rc = build_plan(n_vertices, coords, n_tets, tets, partition, P, msg);
+  int rc = build_plan(mesh->n_vertices, mesh->coords, mesh->n_tets, mesh->tets, partition, P, msg);
   if (rc != DD_OK) throw DDError{rc, msg};
   std::memset(out, 0, sizeof(*out));
   out->n_edges = P.ne;
@@ -2654,14 +2743,17 @@ int dd_analyze(int64_t n_vertices, const double* coords, int64_t n_tets, const i
   API_END
 }
 
-int dd_analyze_lambda(int64_t n_vertices, const double* coords, int64_t n_tets, const int32_t* tets,
-                      const int32_t* partition, int32_t* edge, int32_t* sub_lo, int32_t* sub_hi, int32_t* pos_lo,
-                      int32_t* pos_hi) {
+int dd_analyze_lambda(const dd_mesh* mesh, const int32_t* partition, int32_t* edge, int32_t* sub_lo,
+                      int32_t* sub_hi, int32_t* pos_lo, int32_t* pos_hi) {
   g_err.clear();
+  if (!mesh) {
+    g_err = "mesh is NULL";
+    return DD_ERR_ARG;
+  }
   API_BEGIN
   Plan P;
   std::string msg;
-  int rc = build_plan(n_vertices, coords, n_tets, tets, partition, P, msg);
+  int rc = build_plan(mesh->n_vertices, mesh->coords, mesh->n_tets, mesh->tets, partition, P, msg);
   if (rc != DD_OK) throw DDError{rc, msg};
   for (int64_t l = 0; l < P.nlambda(); ++l) {
     if (edge) edge[l] = P.interior[P.lam_dof[l]];

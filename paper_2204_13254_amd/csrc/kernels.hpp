@@ -1112,7 +1112,8 @@ __global__ void __launch_bounds__(256) k_int_to_edges(int64_t ne, const int32_t*
 // K4: Newmark right-hand side and residuals with the global CSR of (T, S);
 // ca = beta dt^2 (A = T + ca S), cb = (2 beta - 1) dt^2 (B1 = 2T + cb S).
 //   mode 0: y = B1 x1 - A x2 - dt (j1 - j2)       (Newmark right-hand side)
-//   mode 1: y = z - A x1                          (refinement residual)
+//   mode 1: y = z - A x1, and y2 = T x1 if y2 != 0 (refinement residual;
+//           T x1 feeds the Gauss-law check of the final iterate)
 //   mode 2: y = B1 x1, y2 = A x1                  (adjoint application)
 //   mode 3: y = T x1,  y2 = S x1                  (Gauss law, energy)
 // One thread per (row, rhs); vectors [nint][nrhs].  Used for up to 4 RHS;
@@ -1185,6 +1186,7 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
     y[i] = (2.0 * t1 + cb * s1) - (t2 + ca * s2) - dt * (j1[i] - j2[i]);
   } else if (mode == 1) {
     y[i] = z[i] - (t1 + ca * s1);
+    if (y2) y2[i] = t1;
   } else if (mode == 2) {
     y[i] = 2.0 * t1 + cb * s1;
     y2[i] = t1 + ca * s1;
@@ -1305,6 +1307,7 @@ __global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* _
     y[o] = (2.0 * t1 + cb * s1) - (t2 + ca * s2) - dt * (j1[o] - j2[o]);
   } else if constexpr (MODE == 1) {
     y[o] = z[o] - (t1 + ca * s1);
+    if (y2) y2[o] = t1;
   } else if constexpr (MODE == 2) {
     y[o] = 2.0 * t1 + cb * s1;
     y2[o] = t1 + ca * s1;
@@ -1653,6 +1656,21 @@ __global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double
   if (i < n) y[i] += a * x[i];
 }
 
+__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+// dv = (a - b) * s, av = (a + b) / 2 (the energy's difference and average)
+__global__ void k_diff_avg(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double s,
+                           double* __restrict__ dv, double* __restrict__ av) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = a[i], y = b[i];
+  dv[i] = (x - y) * s;
+  av[i] = 0.5 * (x + y);
+}
+
 __global__ void k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = a[i] - b[i];
@@ -1731,6 +1749,55 @@ __global__ void k_gauss(int64_t nv, const int64_t* __restrict__ vptr, const int3
     if (d >= 0) s += (code & 1 ? -1.0 : 1.0) * Tx[(int64_t)d * nrhs + r];
   }
   res[i] = s + q[i];
+}
+
+
+// Per-RHS maxima over vertices of |G^T (T e) + q| (interior vertices) and of
+// |q|, for the per-step check: grid (kGaussBlocks, nrhs); block (b, r)
+// strides over vertices v = b, b + kGaussBlocks*256, ... and writes its two
+// maxima to out[(r * kGaussBlocks + b) * 2 + {0, 1}].  Tx is [nint][nrhs],
+// q is [nrhs][nv].
+constexpr int kGaussBlocks = 64;
+__global__ void __launch_bounds__(256) k_gauss_max(int64_t nv, const int64_t* __restrict__ vptr,
+                                                   const int32_t* __restrict__ vedge,
+                                                   const uint8_t* __restrict__ node_int,
+                                                   const int32_t* __restrict__ dof, const double* __restrict__ Tx,
+                                                   const double* __restrict__ q, int nrhs, double* __restrict__ out) {
+  const int r = blockIdx.y;
+  double mres = 0.0, mq = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)kGaussBlocks * 256) {
+    const double qv = q[(int64_t)r * nv + v];
+    mq = fmax(mq, fabs(qv));
+    if (!node_int[v]) continue;
+    double s = 0.0;
+    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+      const int32_t code = vedge[k];
+      const int32_t d = dof[code >> 1];
+      if (d >= 0) s += (code & 1 ? -1.0 : 1.0) * Tx[(int64_t)d * nrhs + r];
+    }
+    const double g = s + qv;
+    // a NaN residual stays visible in the maximum
+    if (g != g)
+      mres = g;
+    else if (mres == mres)
+      mres = fmax(mres, fabs(g));
+  }
+  __shared__ double red[2][256];
+  red[0][threadIdx.x] = mres;
+  red[1][threadIdx.x] = mq;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double a = red[0][threadIdx.x], b = red[0][threadIdx.x + w];
+      red[0][threadIdx.x] = (a != a) ? a : ((b != b) ? b : fmax(a, b));
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[((int64_t)r * kGaussBlocks + blockIdx.x) * 2] = red[0][0];
+    out[((int64_t)r * kGaussBlocks + blockIdx.x) * 2 + 1] = red[1][0];
+  }
 }
 
 }  // namespace ddfem

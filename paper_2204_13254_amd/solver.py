@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DD_FP32_REFINE, DD_FP64, Analysis, Info, Options, Stats, check, load
+from ._lib import DD_FP32_REFINE, DD_FP64, Analysis, Info, Mesh, Options, Stats, check, load
 
 
 def _host(a, dtype):
@@ -28,28 +28,31 @@ def _dev_i32(t: torch.Tensor):
     return C.c_void_p(t.data_ptr())
 
 
+def _mesh(coords, tets):
+    """dd_mesh over contiguous host copies (returned to keep them alive)."""
+    c, cp = _host(coords, np.float64)
+    t, tp = _host(tets, np.int32)
+    return Mesh(len(c), cp, len(t), tp), (c, t)
+
+
 def analyze(coords, tets, partition):
     """Host-only partition analysis: (Analysis, per_sub [n_sub, 3])."""
     lib = load()
-    c, cp = _host(coords, np.float64)
-    t, tp = _host(tets, np.int32)
+    m, keep = _mesh(coords, tets)
     p, pp = _host(partition, np.int32)
     out = Analysis()
-    check(lib.dd_analyze(len(c), cp, len(t), tp, pp, C.byref(out), None))
+    check(lib.dd_analyze(C.byref(m), pp, C.byref(out), None))
     per = np.zeros((out.n_sub, 3), dtype=np.int32)
-    check(lib.dd_analyze(len(c), cp, len(t), tp, pp, C.byref(out),
-                         per.ctypes.data_as(C.c_void_p)))
+    check(lib.dd_analyze(C.byref(m), pp, C.byref(out), per.ctypes.data_as(C.c_void_p)))
     return out, per
 
 
 def analyze_lambda(coords, tets, partition, n_lambda):
     lib = load()
-    c, cp = _host(coords, np.float64)
-    t, tp = _host(tets, np.int32)
+    m, keep = _mesh(coords, tets)
     p, pp = _host(partition, np.int32)
     arrs = [np.zeros(n_lambda, dtype=np.int32) for _ in range(5)]
-    check(lib.dd_analyze_lambda(len(c), cp, len(t), tp, pp,
-                                *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
+    check(lib.dd_analyze_lambda(C.byref(m), pp, *[a.ctypes.data_as(C.c_void_p) for a in arrs]))
     return dict(zip(("edge", "sub_lo", "sub_hi", "pos_lo", "pos_hi"), arrs))
 
 
@@ -63,7 +66,7 @@ class DDSolver:
     def __init__(self, coords, tets, partition, eps, mu=None, dt=0.05, beta=0.25, *,
                  precision="fp64", nrhs=1, cg_tol=1e-10, cg_max_iter=500, refine_tol=1e-12,
                  refine_max=10, warm_start=0, check_every=4, stream=None, factor=True,
-                 use_graph=False, precond=1, method="dp1", robin_alpha=0.0):
+                 use_graph=False, precond=1, method="dp1", robin_alpha=0.0, diagnostics=0):
         self.lib = load()
         o = Options()
         self.lib.dd_default_options(C.byref(o))
@@ -81,21 +84,20 @@ class DDSolver:
             raise ValueError("method must be 'dp1' or 'dp2'")
         o.method = 1 if method == "dp2" else 0
         o.robin_alpha = float(robin_alpha)
+        o.diagnostics = int(diagnostics)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
         o.stream = C.c_void_p(stream.cuda_stream)
         self.opt = o
-        c, cp = _host(coords, np.float64)
-        t, tp = _host(tets, np.int32)
+        mesh, keep = _mesh(coords, tets)
         p, pp = _host(partition, np.int32)
         e, ep = _host(eps, np.float64)
         mp = None
         if mu is not None:
             m, mp = _host(mu, np.float64)
         h = C.c_void_p()
-        check(self.lib.dd_setup(C.byref(h), len(c), cp, len(t), tp, pp, ep, mp, float(dt),
-                                float(beta), C.byref(o)))
+        check(self.lib.dd_setup(C.byref(h), C.byref(mesh), pp, ep, mp, float(dt), float(beta), C.byref(o)))
         self.h = h
         self.nrhs = int(nrhs)
         self.dt = float(dt)
@@ -136,8 +138,18 @@ class DDSolver:
         return e, pec.astype(bool)
 
     def set_eps(self, eps):
-        e, ep = _host(eps, np.float64)
-        check(self.lib.dd_set_eps(self.h, ep))
+        """eps: host array, or a float64 device tensor (validated by the
+        library on the host either way)."""
+        if isinstance(eps, torch.Tensor) and eps.device.type == "cuda":
+            check(self.lib.dd_set_eps(self.h, _dev(eps), 1))
+        else:
+            e, ep = _host(eps, np.float64)
+            check(self.lib.dd_set_eps(self.h, ep, 0))
+
+    def set_charge(self, q=None):
+        """Accumulated nodal charge of the per-step Gauss check: device
+        tensor [nrhs, n_vertices], or None for zero."""
+        check(self.lib.dd_set_charge(self.h, None if q is None else _dev(q)))
 
     def factor(self):
         check(self.lib.dd_factor(self.h))
@@ -160,12 +172,16 @@ class DDSolver:
         check(self.lib.dd_solve(self.h, _dev(b), _dev(x), C.byref(self.stats) if stats else None))
         return x
 
-    def adjoint_step(self, ebar_next, ebar_n, ebar_nm1, E_next, E_n, E_nm1, eps_bar, g_out=None):
+    def adjoint_step(self, ebar_next, ebar_n, ebar_nm1, E_next, E_n, E_nm1, eps_bar, g_out=None,
+                     Jbar_half=None, Jbar_prev_half=None):
+        """One reverse step (dd_adjoint_step); the library accumulates
+        -dt g into Jbar_half and +dt g into Jbar_prev_half when given."""
         if g_out is None:
             g_out = self.new_field()
         p = lambda t: None if t is None else _dev(t)
         check(self.lib.dd_adjoint_step(self.h, _dev(ebar_next), p(ebar_n), p(ebar_nm1), _dev(g_out),
-                                       p(E_next), p(E_n), p(E_nm1), p(eps_bar), None))
+                                       p(E_next), p(E_n), p(E_nm1), p(eps_bar), p(Jbar_half),
+                                       p(Jbar_prev_half), None))
         return g_out
 
     def charge_update(self, J_half, q):
@@ -308,6 +324,13 @@ class DDSolver:
     def last_stats(self):
         s = self.stats
         n = self.nrhs
-        return dict(cg_iters=list(s.cg_iters[:n]), refine_sweeps=s.refine_sweeps,
-                    dd_solves=s.dd_solves, cg_relres=list(s.cg_relres[:n]),
-                    global_relres=list(s.global_relres[:n]), solve_iters=list(s.solve_iters))
+        d = dict(cg_iters=list(s.cg_iters[:n]), refine_sweeps=s.refine_sweeps,
+                 dd_solves=s.dd_solves, cg_relres=list(s.cg_relres[:n]),
+                 global_relres=list(s.global_relres[:n]), solve_iters=list(s.solve_iters),
+                 diagnostics=s.diagnostics)
+        if s.diagnostics & 1:
+            d["gauss_residual"] = list(s.gauss_residual[:n])
+            d["charge_max"] = list(s.charge_max[:n])
+        if s.diagnostics & 2:
+            d["energy"] = list(s.energy[:n])
+        return d

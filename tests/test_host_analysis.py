@@ -36,16 +36,24 @@ def _analysis(c, t, p):
     return analyze(c, t, p)
 
 
-@pytest.mark.parametrize("k,expect", [
-    (1, (4184, 3032, 8, 480, 24)),
-    (2, (102024, 91656, 64, 13824, 648)),
+# (n_e, N_int, subdomains, n_lambda, n_c) and the min-max of n_r = n_I + n_Gamma
+# per subdomain, as tabulated for the five workloads in the design survey
+# (computed there by independent scripts)
+@pytest.mark.parametrize("k,expect,nr_range", [
+    (1, (4184, 3032, 8, 480, 24), (436, 436)),
+    (2, (102024, 91656, 64, 13824, 648), (1494, 1782)),
+    pytest.param(3, (795024, 753552, 512, 124115, 11934), (394, 4474), marks=pytest.mark.slow),
+    pytest.param(4, (238688, 220256, 64, 25344, 864), (3560, 4088), marks=pytest.mark.slow),
+    pytest.param(5, (1872064, 1798336, 1000, 297216, 15552), (1494, 2779), marks=pytest.mark.slow),
 ])
-def test_counts_of_workloads(k, expect):
+def test_counts_of_workloads(k, expect, nr_range):
     w = workload(k)
     c, t = w.mesh()
     a, per = _analysis(c, t, w.partition())
     assert (a.n_edges, a.n_interior, a.n_sub, a.n_lambda, a.n_corner) == expect
     assert a.max_multiplicity == 4
+    nr = per[:, 0] + per[:, 1]
+    assert (int(nr.min()), int(nr.max())) == nr_range
 
 
 def _brute_classes(c, t, p):
@@ -83,13 +91,37 @@ def test_classes_and_lambda_map_brute_force(n, parts):
     for l, e in enumerate(gam):
         lo, hi = sorted(subs_of[e])
         assert (L["sub_lo"][l], L["sub_hi"][l]) == (lo, hi)
-    # positions: interface rows come after the interior rows of each subdomain
-    assert np.all(L["pos_lo"] >= per[L["sub_lo"], 0])
-    assert np.all(L["pos_lo"] < per[L["sub_lo"], 0] + per[L["sub_lo"], 1])
-    # B_s jump of a continuous field vanishes: each multiplier sees the same
-    # edge from both sides (+1 lo, -1 hi), so sum_s B_s R_s e = e - e = 0
-    x = np.random.default_rng(0).standard_normal(d.n_e)
-    assert np.allclose(x[L["edge"]] - x[L["edge"]], 0.0)
+    # positions: the interface block of a subdomain follows its interior
+    # block and lists its interface edges in ascending canonical id, so the
+    # brute-force interface list of each subdomain maps (sub, pos) back to
+    # an edge; both sides of every multiplier must name its edge
+    gam_of = [sorted(e for e in gam if s in subs_of[e]) for s in range(a.n_sub)]
+    for side in ("lo", "hi"):
+        sub, pos = L["sub_" + side], L["pos_" + side]
+        off = pos - per[sub, 0]
+        assert np.all(off >= 0) and np.all(off < per[sub, 1])
+        back = np.array([gam_of[s_][o] for s_, o in zip(sub, off)])
+        assert np.array_equal(back, L["edge"])
+
+    # restriction R_s of an edge field to each subdomain's interface rows
+    def restrict(x):
+        return [x[np.array(g, dtype=np.int64)] if g else np.zeros(0) for g in gam_of]
+
+    def jump(xs):    # sum_s B_s x_s: +1 in the lower subdomain id, -1 in the higher
+        lo = np.array([xs[s_][o] for s_, o in zip(L["sub_lo"], L["pos_lo"] - per[L["sub_lo"], 0])])
+        hi = np.array([xs[s_][o] for s_, o in zip(L["sub_hi"], L["pos_hi"] - per[L["sub_hi"], 0])])
+        return lo - hi
+
+    # a continuous field has no jump; a field torn in one subdomain jumps by
+    # exactly the tear on that subdomain's multipliers, with its sign
+    x = np.random.default_rng(0).integers(-1000, 1000, d.n_e).astype(np.float64)   # exact sums
+    assert np.array_equal(jump(restrict(x)), np.zeros(a.n_lambda))
+    xs = restrict(x)
+    s_t = int(L["sub_hi"][0])
+    xs[s_t] = xs[s_t] + 1.0
+    j = jump(xs)
+    np.testing.assert_array_equal(j, np.where(L["sub_hi"] == s_t, -1.0, 0.0)
+                                  + np.where(L["sub_lo"] == s_t, 1.0, 0.0))
 
 
 def test_rejects_bad_inputs(lib):

@@ -148,3 +148,60 @@ def test_adjoint_central_differences():
         fd = (loss(eps0 + h * de, J + h * dJ)[0] - loss(eps0 - h * de, J - h * dJ)[0]) / (2 * h)
         ad = np.dot(eps_bar, de) + np.sum(Jbar * dJ)
         assert abs(fd - ad) <= 1e-6 * max(abs(fd), abs(ad)), (fd, ad)
+
+
+# ---- the iterative path for meshes whose factor does not fit a host --------
+def test_mass_lower_bound_is_a_lower_bound():
+    """The certified bound min_k eps_k lam_min(T_k) never exceeds the true
+    smallest eigenvalue of A (dense eigenvalues, brute force on small
+    meshes, uniform and graded, with per-tet eps), and is not vacuous."""
+    from oracle.newmark import mass_lower_bound
+    for n, grade, seed, dt in ((3, 1.0, None, 0.05), (3, 1.5, 4, 0.1), (4, 1.0, 2, 0.02)):
+        o = _oracle(n, dt=dt, seed=seed, grade=grade)
+        lo = mass_lower_bound(o.d)
+        lam = np.linalg.eigvalsh(o.A.toarray())[0]
+        tmin = np.linalg.eigvalsh(o.d.T.toarray())[0]
+        assert 0 < lo <= tmin <= lam
+        assert lo >= 1e-3 * lam
+
+
+@pytest.mark.parametrize("n,grade,seed", [(8, 1.0, None), (10, 1.5, 3)])
+def test_pcg_matches_direct_over_steps(n, grade, seed):
+    """Jacobi PCG (tolerance 1e-13) against the nested-dissection SuperLU
+    solve over 12 Newmark steps with 3 right-hand sides, and its certified
+    error bound against the actual error of every solve."""
+    c, t, _ = cube_mesh(n, grade)
+    eps = None if seed is None else np.random.default_rng(seed).uniform(1, 4, len(t))
+    od = NewmarkOracle(c, t, eps=eps, dt=0.04, beta=0.25)
+    oi = NewmarkOracle(c, t, eps=eps, dt=0.04, beta=0.25, solver="pcg", pcg_tol=1e-13)
+    N = 12
+    J = dense_random_source(od.d.n_e, ~od.d.pec, N, 0.04, 0.2, 0.08, seed=11, nrhs=3)
+    Ed = od.run(J)
+    Ei = oi.run(J)
+    for k in range(1, N + 1):
+        err = np.linalg.norm(Ei[k] - Ed[k], axis=1) / np.linalg.norm(Ed[k], axis=1)
+        assert err.max() <= 1e-11, (k, err)
+    # the bound of one solve covers its actual error
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal((3, od.d.n_int))
+    xd = od.solve(b)
+    xi = oi.solve(b)
+    actual = (np.linalg.norm(xi - xd, axis=1) / np.linalg.norm(xd, axis=1)).max()
+    it, rel, bound = oi.solve_log[-1]
+    assert rel <= 1e-13 and actual <= bound <= 1e-9, (actual, bound)
+
+
+def test_pcg_bound_reports_a_loose_solve():
+    """A solve stopped early reports a residual and a bound that cover the
+    error it really has (the bound is what the full-size fixtures rely on)."""
+    from oracle.newmark import pcg
+    o = _oracle(6, dt=0.05, seed=1)
+    oi = NewmarkOracle(o.d.coords, o.d.tets, eps=o.d.eps, dt=0.05, solver="pcg", pcg_tol=1e-4)
+    b = np.random.default_rng(3).standard_normal((2, o.d.n_int))
+    xd = o.solve(b)
+    xi = oi.solve(b)
+    actual = (np.linalg.norm(xi - xd, axis=1) / np.linalg.norm(xd, axis=1)).max()
+    it, rel, bound = oi.solve_log[-1]
+    assert 1e-10 < actual <= bound
+    x, _, rel2 = pcg(o.A, b.T, tol=1e-4)
+    assert rel2.max() <= 1e-4

@@ -51,6 +51,25 @@ class Workload:
     def mu(self, n_t):
         return np.ones(n_t)
 
+    def sources_for_steps(self, tets, coords, steps, workers=1, start_method="fork"):
+        """J_half [len(steps), nrhs, n_e] for the given step indices.  Beam
+        currents (one deposit of every particle path per step and RHS) are
+        spread over `workers` processes, one right-hand side per task; use
+        start_method="spawn" in a process that has initialised a GPU."""
+        steps = list(steps)
+        if self.extra.get("source") != "beam":
+            return self.sources(tets, coords, N=max(steps) + 1)[steps]
+        edges = _mesh.mesh_edges(tets)
+        jobs = [(coords, tets, edges, self.n, self.dt, self.extra["beam"], r, steps)
+                for r in range(self.nrhs)]
+        if workers > 1:
+            import multiprocessing as mp
+            with mp.get_context(start_method).Pool(min(workers, len(jobs))) as pool:
+                parts = pool.map(_beam_rhs, jobs)
+        else:
+            parts = [_beam_rhs(j) for j in jobs]
+        return np.stack(parts, axis=1)
+
     def sources(self, tets, coords, N=None):
         """J_half [N, nrhs, n_e] for the first N steps (default: all)."""
         N = self.N if N is None else N
@@ -71,6 +90,15 @@ class Workload:
             return beam.beam_source(coords, tets, edges, self.n, N, self.dt,
                                     self.nrhs, **ex["beam"])
         raise ValueError(kind)
+
+
+def _beam_rhs(args):
+    """Beam currents of one right-hand side (a process-pool task)."""
+    coords, tets, edges, n, dt, beam, r, steps = args
+    from .beam import beam_source
+    b = dict(beam)
+    b["seed"] = beam["seed"] + r
+    return beam_source(coords, tets, edges, n, 0, dt, 1, steps=steps, **b)[:, 0, :]
 
 
 def workload(k: int) -> Workload:
