@@ -6,7 +6,7 @@ of the benchmark use it.  It shares no code with the HIP library; the two
 see the same seeded input arrays (from the `workloads` package) and nothing
 else.
 
-What it computes (the paper's Sec. V-A states that the decomposed fields
+What it computes (the paper's Sec. IV-A states that the decomposed fields
 equal the monolithic ones to near machine precision, so the oracle is the
 monolithic solve):
   * its own canonical edge numbering and PEC classification (fem.py);

@@ -5,7 +5,7 @@ closed forms and invariants of the scheme:
   * without sources the discrete energy H^{n+1/2} is constant (beta = 1/4,
     the unconditionally stable choice);
   * the discrete Gauss law G^T T e^n + q^n = 0 holds to rounding for the
-    time-integrated current of Sec. II-A (charge conservation, Sec. V-B);
+    time-integrated current of Sec. II-A (charge conservation, Sec. IV-B);
   * the direct solve agrees with a dense LAPACK solve;
   * the adjoint passes the dot-product test and central differences."""
 import numpy as np
