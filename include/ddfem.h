@@ -280,6 +280,19 @@ int dd_pic_deposit(void* ctx, int64_t n, const double* xa, const double* xb, con
  * n <= 2^31 - 1. */
 int dd_pic_sort(void* ctx, int64_t n, const int32_t* cell, int32_t* perm);
 
+/* dd_pic_sort for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid device allocation):
+ * the same ordering (same contract as dd_pic_sort), with every scratch
+ * buffer in one fixed static device array of the library (16.0 MiB per
+ * device, held until the process ends) instead of context memory; it calls
+ * no allocating routine and does not build the particle tables of the other
+ * particle calls.  Limit: meshes of at most 4194304 tetrahedra (DD_ERR_ARG
+ * beyond).  Every call on one device shares that device's array and leaves
+ * its contents behind (the call clears what must start at zero itself), so
+ * calls that overlap in time on one device race; serialise them (one stream,
+ * or events).  Enqueued on the context stream, never synchronises. */
+int dd_pic_sort_noalloc(void* ctx, int64_t n, const int32_t* cell, int32_t* perm);
+
 /* dst[i] = src[perm[i]] for n items of item_bytes bytes (a multiple of 4,
  * at most 64; 4-byte aligned device arrays that do not overlap).  A perm
  * entry outside [0, n) leaves that item unwritten (counts[2]). */

@@ -83,6 +83,7 @@ SIGNATURES = {
     "dd_pic_deposit": (C.c_int, [P, I64, P, P, P, P, P]),
     "dd_pic_faraday": (C.c_int, [P, C.c_int, P, D, P]),
     "dd_pic_sort": (C.c_int, [P, I64, P, P]),
+    "dd_pic_sort_noalloc": (C.c_int, [P, I64, P, P]),
     "dd_pic_permute": (C.c_int, [P, I64, P, C.c_int, P, P]),
     "dd_pic_push": (C.c_int, [P, I64, P, P, P, P, P, P, P, P, C.c_int]),
     "dd_destroy": (None, [P]),

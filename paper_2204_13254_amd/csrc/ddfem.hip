@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <stdexcept>
@@ -100,6 +101,7 @@ constexpr int kFullChunkTiles = 96;
 struct Ctx {
   Plan P;
   dd_options opt;
+  int device = 0;  // current device at dd_setup (the stream's device)
   hipStream_t st = nullptr;
   // side stream: the interface-row products of an F application run there
   // while the coarse solve (a short chain of small launches) runs on st
@@ -1899,6 +1901,35 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
 
 using namespace ddfem;
 
+// Scratch of dd_pic_sort_noalloc: the per-cell counts, then cursors [cells + 1],
+// followed by the scan's chunk totals, in one file-scope device array of fixed
+// size (16.0 MiB), so that the call allocates nothing.  Each device holds its
+// own copy for the life of the process; host code uses only the addresses
+// resolved per device by resolve_scratch, never the symbol itself.
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 22;
+constexpr int64_t kNoAllocChunks = (kNoAllocMaxCells + 1 + kScanBlock - 1) / kScanBlock;
+static __device__ __align__(256) int32_t scratch[kNoAllocMaxCells + 1 + kNoAllocChunks];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static int32_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of scratch on device dev (current), resolved once per device.
+static void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) throw DDError{DD_ERR_HIP, "device id out of range"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* p = nullptr;
+  HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) throw DDError{DD_ERR_HIP, "no device address for the static scratch"};
+  g_scratch_ptr[dev] = (int32_t*)p;
+}
+
+static int32_t* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -2251,6 +2282,8 @@ int dd_setup(void** out, const dd_mesh* mesh, const int32_t* partition, const do
   C = new Ctx();
   C->opt = o;
   C->st = (hipStream_t)o.stream;
+  HIPCHK(hipGetDevice(&C->device));
+  resolve_scratch(C->device);
   HIPCHK(hipStreamCreateWithFlags(&C->st2, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
@@ -2532,6 +2565,7 @@ int dd_profile(void* ctx, int enable, double* ms, int64_t* launches) {
 
 // ---- particle steps (Sec. II-A) --------------------------------------------------
 
+
 int dd_pic_status(void* ctx, int64_t* counts, int reset) {
   if (!ctx) {
     g_err = "null context";
@@ -2646,6 +2680,35 @@ int dd_pic_sort(void* ctx, int64_t n, const int32_t* cell, int32_t* perm) {
   hipLaunchKernelGGL(k_scan_add, dim3(nblk(m)), dim3(256), 0, C.st, m, C.d_pic_count,
                      (const int32_t*)C.d_pic_bsum);
   hipLaunchKernelGGL(k_cell_scatter, dim3(nblk(n)), dim3(256), 0, C.st, n, nt, cell, C.d_pic_count, perm);
+  HIPCHK(hipGetLastError());
+  return DD_OK;
+  API_END
+}
+
+int dd_pic_sort_noalloc(void* ctx, int64_t n, const int32_t* cell, int32_t* perm) {
+  if (!ctx || n < 0 || (n > 0 && (!cell || !perm)) || n > INT32_MAX) {
+    g_err = "null argument or count out of range";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  API_BEGIN
+  const int64_t nt = C.P.nt, m = nt + 1, nb = (m + kScanBlock - 1) / kScanBlock;
+  if (nt > kNoAllocMaxCells)
+    throw DDError{DD_ERR_ARG, "the mesh has " + std::to_string(nt) + " tetrahedra; the static scratch of "
+                                  "this call holds at most " + std::to_string(kNoAllocMaxCells)};
+  int32_t* sc = scratch_of(C.device);
+  if (!sc) throw DDError{DD_ERR_STATE, "static scratch not resolved for the context's device"};
+  if (n == 0) return DD_OK;
+  int32_t* count = sc;
+  int32_t* bsum = sc + (kNoAllocMaxCells + 1);
+  // the previous call's counts are still there: clear them with a fill
+  // kernel (no memset, so the call can be captured into a graph)
+  hipLaunchKernelGGL(k_zero_i32, dim3(nblk(m)), dim3(256), 0, C.st, m, count);
+  hipLaunchKernelGGL(k_cell_hist, dim3(nblk(n)), dim3(256), 0, C.st, n, nt, cell, count);
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(256), 0, C.st, m, count, bsum);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, C.st, nb, bsum);
+  hipLaunchKernelGGL(k_scan_add, dim3(nblk(m)), dim3(256), 0, C.st, m, count, (const int32_t*)bsum);
+  hipLaunchKernelGGL(k_cell_scatter, dim3(nblk(n)), dim3(256), 0, C.st, n, nt, cell, count, perm);
   HIPCHK(hipGetLastError());
   return DD_OK;
   API_END

@@ -274,6 +274,15 @@ class DDSolver:
         check(self.lib.dd_pic_sort(self.h, n, _dev_i32(cell), _dev_i32(perm)))
         return perm
 
+    def pic_sort_noalloc(self, cell, perm):
+        """pic_sort through the allocation-free entry point (the caller
+        provides perm [n] int32; the library's static scratch serves the
+        counts)."""
+        n = cell.numel()
+        self._len(perm, n, "perm")
+        check(self.lib.dd_pic_sort_noalloc(self.h, n, _dev_i32(cell), _dev_i32(perm)))
+        return perm
+
     def pic_permute(self, perm, src, dst=None):
         """dst[i] = src[perm[i]] along the first axis (any dtype, contiguous)."""
         n = perm.numel()
