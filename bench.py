@@ -38,11 +38,12 @@ def make_sources(w, coords, tets, steps, workers, start_method="fork"):
     return w.sources_for_steps(tets, coords, steps, workers, start_method)
 
 
-def cpu_baseline(target_nint, nrhs, seconds_hint=15.0):
-    """The oracle (nested-dissection SuperLU, FP64) on a bounded sample:
-    the 24^3 cavity of the same family, factorisation + Newmark steps of `nrhs`
-    right-hand sides until about `seconds_hint` seconds have passed.  Scaled to the target size linearly in the
-    number of unknowns (optimistic for the CPU: a direct solve grows faster)."""
+def cpu_baseline_direct24(target_nint, nrhs, seconds_hint=10.0):
+    """Context only: the oracle's direct solve (nested-dissection SuperLU,
+    FP64) on the 24^3 cavity of the same family, factorisation + Newmark
+    steps of `nrhs` right-hand sides for about `seconds_hint` seconds, scaled
+    to the target size linearly in the unknown count (optimistic for a direct
+    solve, whose cost grows faster)."""
     import numpy as np
     from oracle.newmark import NewmarkOracle
     from workloads.mesh import cube_mesh
@@ -56,7 +57,6 @@ def cpu_baseline(target_nint, nrhs, seconds_hint=15.0):
     J = o.d.restrict(dense_random_source(o.d.n_e, ~o.d.pec, max_steps, dt, 10 * dt, 4 * dt, 7, nrhs=nrhs))
     e_nm1 = np.zeros((nrhs, o.d.n_int)); e_n = e_nm1.copy(); jp = e_nm1.copy()
     steps = 0
-    # at least 3 steps, then until about seconds_hint of wall time has passed
     while steps < 3 or (time.perf_counter() - t0 < seconds_hint and steps < max_steps):
         e = o.step(e_n, e_nm1, J[steps], jp)
         e_nm1, e_n, jp = e_n, e, J[steps]
@@ -64,18 +64,43 @@ def cpu_baseline(target_nint, nrhs, seconds_hint=15.0):
     t2 = time.perf_counter()
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    wall = t2 - t0
     step_s = (t2 - t1) / steps
-    per_step = (t1 - t0) / 200.0 + step_s           # factor amortised over a 200-step run
-    sps = 1.0 / per_step
-    scaled = sps * o.d.n_int / target_nint
+    sps = 1.0 / ((t1 - t0) / 200.0 + step_s)
+    return {"value": sps * o.d.n_int / target_nint, "unit": "steps/s", "cores": max(1, round(cpu / (t2 - t0))),
+            "sample": (f"direct oracle on the 24^3 cavity ({o.d.n_int} unknowns), {nrhs} RHS: factor "
+                       f"{t1 - t0:.1f} s + {steps} steps at {step_s:.2f} s/step; scaled by the unknown ratio "
+                       f"{o.d.n_int}/{target_nint}")}
+
+
+def cpu_baseline(w, coords, tets, J0, rhs_sample=4):
+    """The oracle at the benchmarked workload itself: assembly of the global
+    system plus the first Newmark step of `rhs_sample` of the right-hand
+    sides, each solved by its Jacobi-PCG path to a true relative residual of
+    1e-13 (the path that reaches this size on a host; one thread: sparse
+    products and vector updates).  steps/s for all nrhs right-hand sides =
+    1 / (assembly / 200 steps + step time x nrhs / rhs_sample)."""
+    import numpy as np
+    from oracle.newmark import NewmarkOracle
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    o = NewmarkOracle(coords, tets, eps=w.eps(len(tets)), dt=w.dt, beta=w.beta, solver="pcg", pcg_tol=1e-13)
+    t1 = time.perf_counter()
+    k = min(rhs_sample, w.nrhs)
+    z = np.zeros((k, o.d.n_int))
+    o.step(z, z, o.d.restrict(J0[:k]), z)
+    t2 = time.perf_counter()
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    step_all = (t2 - t1) * w.nrhs / k
+    per_step = (t1 - t0) / 200.0 + step_all
+    it = o.solve_log[-1][0]
     return {
-        "value": scaled, "unit": "steps/s", "cores": max(1, round(cpu / wall)), "kind": "oracle",
-        "sample": (f"oracle on the 24^3 cavity ({o.d.n_int} unknowns), {nrhs} RHS: factor "
-                   f"{t1 - t0:.1f} s + {steps} steps at {step_s:.2f} s/step = {sps:.3f} steps/s "
-                   f"(factor amortised over 200 steps); value scaled to the target size by the "
-                   f"unknown ratio {o.d.n_int}/{target_nint} (linear, optimistic for the CPU)"),
-        "wall_s": wall, "cpu_s": cpu, "host": os.uname().nodename,
+        "value": 1.0 / per_step, "unit": "steps/s", "cores": max(1, round(cpu / (t2 - t0))), "kind": "oracle",
+        "sample": (f"oracle at the benchmarked size ({o.d.n_int} unknowns): assembly {t1 - t0:.1f} s "
+                   f"(amortised over 200 steps) + the first Newmark step of {k} of the {w.nrhs} RHS, "
+                   f"{it} Jacobi-PCG iterations to a true relative residual of 1e-13, {t2 - t1:.1f} s, "
+                   f"scaled x{w.nrhs / k:g} to all RHS"),
+        "wall_s": t2 - t0, "cpu_s": cpu, "host": os.uname().nodename,
         "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
     }
 
@@ -287,6 +312,165 @@ def pic_cpu_baseline(w, m):
                        f"(mesh tables {t1 - t0:.1f} s, not counted)")}
 
 
+def timed_steps(s, Jd, W, K, nrhs, dev, profile_eager=True):
+    """W untimed then K timed Newmark steps of all right-hand sides from
+    e^0 = e^-1 = 0, every output kept in device memory (the timed loop reads
+    nothing back but the per-step stats, which carry the Gauss check).
+    Then, with profile_eager, 3 extra eager steps with per-class event
+    timing (graph replays have no per-launch events)."""
+    import torch
+    zero = torch.zeros((nrhs, s.n_edges), dtype=torch.float64, device=dev)
+    E = [zero, zero.clone()]                 # e^-1, e^0, then e^1 .. e^{W+K}
+    for _ in range(W + K):
+        E.append(torch.empty_like(zero))
+    out = {"iters": [], "sweeps": [], "global_relres": [], "gauss_rel": []}
+
+    def do_step(n):
+        s.step(Jd[n], Jd[n - 1] if n else zero, E[n + 1], E[n], E[n + 2], stats=True)
+        return s.last_stats()
+
+    for n in range(W):
+        do_step(n)
+    torch.cuda.synchronize()
+    if not profile_eager:
+        s.profile(1)          # event timing of every tile product inside the timed steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(W, W + K):
+        st = do_step(n)
+        out["iters"].append(st["solve_iters"][:1 + st["refine_sweeps"]])
+        out["sweeps"].append(st["refine_sweeps"])
+        out["global_relres"].append(max(st["global_relres"]))
+        if "gauss_residual" in st:
+            out["gauss_rel"].append(max(g / q if q > 0 else g for g, q in
+                                        zip(st["gauss_residual"], st["charge_max"])))
+    torch.cuda.synchronize()
+    out["seconds"] = time.perf_counter() - t0
+    if profile_eager:
+        spare = [torch.empty_like(zero) for _ in range(3)]
+        s.profile(1)
+        for n in range(max(0, W + K - 3), W + K):
+            s.step(Jd[n], Jd[n - 1] if n else zero, E[n + 1], E[n], spare[n % 3], stats=True)
+        torch.cuda.synchronize()
+    out["profile"] = s.profile(0)
+    out["outputs"] = E[2:]
+    if not out["gauss_rel"]:
+        out["gauss_rel"] = [float("nan")]
+    return out
+
+
+def oracle_parity(w, outputs, W, log):
+    """Every step's fields against the oracle's reference samples of this
+    workload (tests/golden/fullsize_<workload>.npz, written by the
+    oracle-only script beside it), for the steps the file covers: relative
+    L2 error on the sampled edges and of the whole field estimated from the
+    Gaussian sketches, max over RHS; None if the workload has no file."""
+    import numpy as np
+    from workloads.probes import sketch_vectors
+    path = os.path.join(ROOT, "tests", "golden", f"fullsize_{w.name}.npz")
+    if not os.path.exists(path):
+        return None
+    fx = np.load(path, allow_pickle=False)
+    n_fx = min(int(fx["steps"]), len(outputs))
+    G = sketch_vectors(int(fx["n_edges"]), int(fx["sketches"]), int(fx["sketch_seed"]))
+    samp, sk = [], []
+    for k in range(n_fx):
+        E = outputs[k].cpu().numpy()
+        ref = fx["val"][k]
+        samp.append(float((np.linalg.norm(E[:, fx["idx"][k]] - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()))
+        d = E @ G.T - fx["sketch"][k]
+        sk.append(float((np.sqrt(np.mean(d * d, axis=1)) / fx["norm"][k]).max()))
+    timed = slice(W, n_fx)
+    res = {"fixture": os.path.relpath(path, ROOT), "steps_compared": n_fx,
+           "max_rel_l2_sampled": max(samp), "max_rel_l2_sketched": max(sk),
+           "max_rel_l2_sampled_timed_steps": max(samp[timed]) if n_fx > W else None,
+           "max_rel_l2_sketched_timed_steps": max(sk[timed]) if n_fx > W else None,
+           "oracle_error_bound_max": float(fx["log"][:, 2].max()),
+           "per_step_sampled": [float(f"{x:.3e}") for x in samp]}
+    log(f"oracle parity: {res}")
+    return res
+
+
+def roofline(s, per, nrhs, prof):
+    """The dominant tile-product class of one step (largest event-timed
+    total) against the HBM peak, plus every class's figures."""
+    import numpy as np
+    inf = s.info
+    wsz = 4 if inf.precision == 1 else 8
+    nG = per[:, 1].astype(np.int64)
+    nI = per[:, 0].astype(np.int64)
+    nC = per[:, 2].astype(np.int64)
+    vec = {   # one read of the input block rows and one write of the output rows
+        "trailing": 2 * int(nG.sum()) * nrhs * wsz,
+        "full": 2 * int((nI + nG).sum()) * nrhs * wsz,
+        "schur": 2 * int(nG.sum()) * nrhs * wsz,
+        "corner": int((nG + nC).sum()) * nrhs * wsz,
+        "coarse": 2 * int(inf.n_corner) * nrhs * wsz,
+    }
+    algo = {
+        "trailing": inf.trailing_bytes + vec["trailing"],
+        "full": inf.full_bytes + vec["full"],
+        "schur": inf.schur_bytes + vec["schur"],
+        "corner": inf.corner_bytes + vec["corner"],
+        "coarse": inf.coarse_bytes + vec["coarse"],
+    }
+    label = {"trailing": "interface blocks of the inverse factors",
+             "full": "full inverse factors", "schur": "interface blocks of the local inverses, M u",
+             "corner": "corner rows Psi_Gamma", "coarse": "coarse inverse factor"}
+    dom = max(algo, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    avg_ms = dom_ms / max(1, dom_n)
+    achieved = algo[dom] / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": f"{'k_symv' if dom == 'schur' else 'k_tile_mv'} ({label[dom]})",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": int(algo[dom]), "avg_launch_ms": round(avg_ms, 4),
+            "launches": dom_n}
+    other = {k: {"ms_total": round(v[0], 3), "launches": v[1],
+                 "GBps": (round(algo[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if k in algo and v[1] else None)}
+             for k, v in prof.items()}
+    return roof, other
+
+
+def graded_leg(args, dev, stream, log):
+    """The uneven workload: graded 48^3 cavity, 512 bisection subdomains of
+    336-3969 hexahedra, 32 right-hand sides, the headline form (FP32
+    factors, FP64 CG 1e-6 + refinement to 1e-12, graphs, Gauss check):
+    steps/s, the dominant class's roofline and parity with the oracle's
+    reference samples."""
+    import torch
+    from paper_2204_13254_amd.solver import DDSolver, analyze
+    from workloads.configs import workload
+    w = workload(3)
+    c, t = w.mesh()
+    p = w.partition()
+    _, per = analyze(c, t, p)
+    W, K = 2, args.graded_steps
+    Jd = torch.tensor(w.sources(t, c, N=W + K), device=dev)
+    t0 = time.perf_counter()
+    g = DDSolver(c, t, p, w.eps(len(t)), dt=w.dt, beta=w.beta, precision="fp32_refine", nrhs=w.nrhs,
+                 cg_tol=1e-6, refine_tol=1e-12, refine_max=10, factor=False, stream=stream, use_graph=True,
+                 cg_max_iter=400, diagnostics=1)
+    g.factor()
+    torch.cuda.synchronize()
+    t_sf = time.perf_counter() - t0
+    tuning = g.autotune() if args.tune else None
+    run = timed_steps(g, Jd, W, K, w.nrhs, dev)
+    roof, other = roofline(g, per, w.nrhs, run["profile"])
+    res = {"workload": w.name, "steps_per_s": round(K / run["seconds"], 4),
+           "ms_per_step": round(1e3 * run["seconds"] / K, 3), "steps_timed": K, "warmup": W,
+           "nrhs": w.nrhs, "subdomains": int(len(per)), "setup_factor_s": round(t_sf, 2),
+           "n_r_range": [int((per[:, 0] + per[:, 1]).min()), int((per[:, 0] + per[:, 1]).max())],
+           "cg_iters_per_step": run["iters"], "max_global_relres": max(run["global_relres"]),
+           "max_gauss_over_charge": max(run["gauss_rel"]),
+           "roofline": roof, "kernel_classes": other, "tuning": tuning,
+           "oracle_parity": oracle_parity(w, run["outputs"], W, log)}
+    log(f"graded: {res}")
+    del g, run, Jd
+    torch.cuda.empty_cache()
+    return res
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -321,6 +505,12 @@ def main():
     ap.add_argument("--pic-steps", type=int, default=10,
                     help="time this many particle steps (push, exact deposit, Faraday update for every "
                          "RHS) on the beam particles of the workload; 0 skips them")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="choose the work-list shapes with the library's autotuner (timed search) after the "
+                         "factorisation; 0 keeps the defaults")
+    ap.add_argument("--graded-steps", type=int, default=5,
+                    help="also time this many steps of the uneven graded 48^3 workload (512 subdomains, "
+                         "32 RHS); 0 skips it")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 512 MiB elementwise copy (read + write of known size) for "
                          "scaling hardware traffic counters")
@@ -348,8 +538,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         t0 = time.perf_counter()
-        cpu = cpu_baseline(an.n_interior, w.nrhs)
+        cpu = cpu_baseline(w, coords, tets, J[0])
         log(f"cpu baseline {time.perf_counter() - t0:.1f} s: {cpu['sample']}")
+        t0 = time.perf_counter()
+        cpu["direct_24_extrapolated"] = cpu_baseline_direct24(an.n_interior, w.nrhs)
+        log(f"direct oracle (context) {time.perf_counter() - t0:.1f} s")
 
     import torch
     dev = torch.device("cuda:0")
@@ -360,7 +553,7 @@ def main():
     t0 = time.perf_counter()
     s = DDSolver(coords, tets, part, eps, dt=w.dt, beta=w.beta, precision="fp32_refine", nrhs=w.nrhs,
                  cg_tol=1e-6, refine_tol=1e-12, refine_max=10, warm_start=args.warm, factor=False,
-                 stream=stream, use_graph=bool(args.graph))
+                 stream=stream, use_graph=bool(args.graph), diagnostics=1)
     t_setup = time.perf_counter() - t0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -368,86 +561,31 @@ def main():
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
     log(f"mixed: setup {t_setup:.1f} s, factor {t_factor:.2f} s")
+    t0 = time.perf_counter()
+    tuning = s.autotune() if args.tune else None
+    if tuning:
+        tuning["seconds"] = round(time.perf_counter() - t0, 2)
+        log(f"autotuner: {tuning}")
     Jd = torch.tensor(J, device=dev)
     del J
-    zero = torch.zeros((w.nrhs, s.n_edges), dtype=torch.float64, device=dev)
-    ring = [zero.clone() for _ in range(3)]   # E^{n-1}, E^n, E^{n+1}
-    Jprev = zero
-    iters, sweeps, gres = [], [], []
-
-    def do_step(n):
-        nonlocal Jprev
-        s.step(Jd[n], Jprev, ring[1], ring[0], ring[2], stats=True)
-        st = s.last_stats()
-        ring.append(ring.pop(0))       # rotate: old E^{n-1} buffer becomes the next output
-        Jprev = Jd[n]
-        return st
-
-    for n in range(W):
-        do_step(n)
-    torch.cuda.synchronize()
-    if not args.graph:
-        s.profile(1)          # event timing of every tile product inside the timed steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for n in range(W, W + K):
-        st = do_step(n)
-        iters.append(st["solve_iters"][:1 + st["refine_sweeps"]])
-        sweeps.append(st["refine_sweeps"])
-        gres.append(max(st["global_relres"]))
-    torch.cuda.synchronize()
-    t_mixed = time.perf_counter() - t0
-    if args.graph:
-        # graphs exclude per-launch events: time the classes on 3 extra eager steps
-        s.profile(1)
-        for n in range(max(0, W + K - 3), W + K):
-            do_step(n)
-        torch.cuda.synchronize()
-    prof = s.profile(0)
+    run = timed_steps(s, Jd, W, K, w.nrhs, dev, profile_eager=bool(args.graph))
+    t_mixed, prof = run["seconds"], run["profile"]
+    run_gauss = run["gauss_rel"]
+    iters, sweeps, gres = run["iters"], run["sweeps"], run["global_relres"]
     ms_step = 1e3 * t_mixed / K
     sps = K / t_mixed
-    log(f"mixed: {ms_step:.2f} ms/step, CG iters/step {iters}, sweeps {sweeps}, max relres {max(gres):.2e}")
+    log(f"mixed: {ms_step:.2f} ms/step, CG iters/step {iters}, sweeps {sweeps}, max relres {max(gres):.2e}, "
+        f"max Gauss/charge {max(run['gauss_rel']):.2e}")
     log(f"profile: {prof}")
-
-    # ---------------- roofline of the dominant kernel class ----------------------
-    inf = s.info
-    wsz = 4
-    nG = per[:, 1].astype(np.int64)
-    nI = per[:, 0].astype(np.int64)
-    nC = per[:, 2].astype(np.int64)
-    vec = {   # one read of the input block rows and one write of the output rows
-        "trailing": 2 * int(nG.sum()) * w.nrhs * wsz,
-        "full": 2 * int((nI + nG).sum()) * w.nrhs * wsz,
-        "schur": 2 * int(nG.sum()) * w.nrhs * wsz,
-        "corner": int((nG + nC).sum()) * w.nrhs * wsz,
-        "coarse": 2 * int(inf.n_corner) * w.nrhs * wsz,
-    }
-    algo = {
-        "trailing": inf.trailing_bytes + vec["trailing"],
-        "full": inf.full_bytes + vec["full"],
-        "schur": inf.schur_bytes + vec["schur"],
-        "corner": inf.corner_bytes + vec["corner"],
-        "coarse": inf.coarse_bytes + vec["coarse"],
-    }
-    label = {"trailing": "interface blocks of the inverse factors",
-             "full": "full inverse factors", "schur": "interface blocks of the local inverses, M u",
-             "corner": "corner rows Psi_Gamma", "coarse": "coarse inverse factor"}
-    dom = max(algo, key=lambda k: prof[k][0])
-    dom_ms, dom_n = prof[dom]
-    avg_ms = dom_ms / max(1, dom_n)
-    achieved = algo[dom] / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": f"k_tile_mv ({label[dom]})",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch": int(algo[dom]), "avg_launch_ms": round(avg_ms, 4),
-            "launches": dom_n}
-    other = {k: {"ms_total": round(v[0], 3), "launches": v[1],
-                 "GBps": (round(algo[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if k in algo and v[1] else None)}
-             for k, v in prof.items()}
-
-    # HBM traffic per launch of the dominant class, from committed counter
-    # summaries, valid only for the kernel source they were taken on
-    roof["traffic"] = _traffic_from_profiles(dom)
+    parity = oracle_parity(w, run["outputs"], W, log)
+    zero = torch.zeros((w.nrhs, s.n_edges), dtype=torch.float64, device=dev)
+    last = run["outputs"][-1]
+    del run
+    roof, other = roofline(s, per, w.nrhs, prof)
+    if roof["kernel"].startswith("k_tile_mv (full"):
+        # HBM traffic per launch of the dominant class, from committed counter
+        # summaries, valid only for the kernel source they were taken on
+        roof["traffic"] = _traffic_from_profiles("full")
 
     # ---------------- mixed E/B step (faces carry B) on the same solver -----------------
     mixed = None
@@ -472,7 +610,7 @@ def main():
 
     pic = None
     if args.pic_steps > 0 and w.extra.get("source") == "beam":
-        pic = pic_leg(s, w, ring[1], args.pic_steps, dev, log, cpu_sample=0 if args.no_cpu else 100)
+        pic = pic_leg(s, w, last, args.pic_steps, dev, log, cpu_sample=0 if args.no_cpu else 100)
 
     if args.calib_copy:
         x = torch.ones(64 << 20, dtype=torch.float64, device=dev)
@@ -520,6 +658,10 @@ def main():
         del q, Eq
         torch.cuda.empty_cache()
 
+    graded = None
+    if args.graded_steps > 0 and args.workload == 5:
+        graded = graded_leg(args, dev, stream, log)
+
     plain = None
     if not args.no_plain and min(args.plain_steps, W + K - 1) > 0:
         del s
@@ -566,6 +708,10 @@ def main():
         "rhs_steps_per_s": round(sps * w.nrhs, 3),
         "cg_iters_per_step": iters, "refine_sweeps_per_step": sweeps,
         "max_global_relres": max(gres),
+        "max_gauss_over_charge": max(run_gauss),
+        "oracle_parity": parity,
+        "tuning": tuning,
+        "graded48": graded,
         "cg_iters_per_s": round(sum(sum(x) for x in iters) / t_mixed, 1),
         "factor_s": round(t_factor, 3), "setup_s": round(t_setup, 2),
         "kernel_classes": other,

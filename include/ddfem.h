@@ -87,7 +87,22 @@ typedef struct {
                          law G^T T e^{n+1} + q^{n+1} at every interior vertex (Sec. IV-B,
                          charge conservation); bit 1 (DD_DIAG_ENERGY): the discrete energy
                          H^{n+1/2} of (e^{n+1}, e^n) */
+  const char* tune_cache; /* path of the work-list tuning cache (JSON lines), or NULL: with a
+                         path, the first successful dd_factor runs dd_autotune with it
+                         (string copied at dd_setup) */
 } dd_options;
+
+/* Work-list shapes of the batched products and what the tuner measured
+ * (ms per solve's products of the class; *_default: with the shapes before
+ * tuning). */
+typedef struct {
+  int chunk;          /* longest tile range of one wave: interface-block and corner-row lists */
+  int coarse_chunk;   /* the same for the coarse inverse-factor lists */
+  int full_chunk;     /* the same for the full r-block lists */
+  int full_bucket;    /* length buckets of the full lists' workgroup placement */
+  int from_cache;     /* 1: read from the cache, no timing */
+  double full_ms, full_ms_default, coarse_ms, coarse_ms_default, trailing_ms, trailing_ms_default;
+} dd_tuning;
 
 enum { DD_DIAG_GAUSS = 1, DD_DIAG_ENERGY = 2 };
 
@@ -130,7 +145,7 @@ typedef struct {
 
 /* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
  * refine_tol 1e-12, refine_max 10, warm_start 0, use_graph 0, check_every 4,
- * precond 1, method 0, robin_alpha 0, diagnostics 0. */
+ * precond 1, method 0, robin_alpha 0, diagnostics 0, tune_cache NULL. */
 void dd_default_options(dd_options* opt);
 
 /* Build a solver context (host analysis + device upload + element assembly
@@ -175,6 +190,17 @@ int dd_set_eps(void* ctx, const double* eps, int on_device);
  * values whose matrix entries overflow the factor precision); the context
  * then refuses solves (DD_ERR_STATE) until a dd_factor succeeds. */
 int dd_factor(void* ctx);
+
+/* Autotuner of the batched launches (every subdomain and right-hand side in
+ * one launch per product class; work items of at most `chunk` tiles, placed
+ * per XCD).  With cache_path (JSON lines, one object per tuning) holding an
+ * entry for this context's key (device, precision, nrhs, subdomain tile
+ * shapes, nonzero-tile pattern) the entry is applied; otherwise every
+ * candidate shape of each class is timed with HIP events on the context
+ * stream (the products of one decomposed solve, median of 5), the fastest
+ * is applied and, given a path, appended to the cache.  Needs a factorised
+ * context (DD_ERR_STATE); synchronises; out may be NULL. */
+int dd_autotune(void* ctx, const char* cache_path, dd_tuning* out);
 
 /* One Newmark step for all nrhs right-hand sides (device pointers):
  *   J_half, J_prev_half  [nrhs][n_edges]: J^{n+1/2}, J^{n-1/2}

@@ -54,14 +54,33 @@ def pec_mask(coords, edges):
     return m
 
 
+def _inv3(D):
+    """Inverse and determinant of 3x3 matrices [n, 3, 3] by cofactors (any
+    float dtype: LAPACK has no extended precision)."""
+    a = D
+    cof = np.empty_like(a)
+    for i in range(3):
+        for j in range(3):
+            r = [k for k in range(3) if k != i]
+            c = [k for k in range(3) if k != j]
+            m = a[:, r[0], c[0]] * a[:, r[1], c[1]] - a[:, r[0], c[1]] * a[:, r[1], c[0]]
+            cof[:, i, j] = m if (i + j) % 2 == 0 else -m
+    det = np.einsum("nj,nj->n", a[:, 0, :], cof[:, 0, :])
+    return cof.transpose(0, 2, 1) / det[:, None, None], det
+
+
 def barycentric_gradients(coords, tets):
-    """Gradients g[t, i] of lam_i (constant per tetrahedron) and volumes."""
+    """Gradients g[t, i] of lam_i (constant per tetrahedron) and volumes, in
+    the dtype of coords (float64 through LAPACK, others by cofactors)."""
     st = sort_tets(tets)
     x = coords[st]                      # [n_t, 4, 3]
     D = (x[:, 1:, :] - x[:, :1, :]).transpose(0, 2, 1)   # columns x_i - x_0
-    det = np.linalg.det(D)
-    Dinv = np.linalg.inv(D)             # rows = grad lam_1..3
-    g = np.empty((len(st), 4, 3))
+    if D.dtype == np.float64:
+        det = np.linalg.det(D)
+        Dinv = np.linalg.inv(D)         # rows = grad lam_1..3
+    else:
+        Dinv, det = _inv3(D)
+    g = np.empty((len(st), 4, 3), dtype=D.dtype)
     g[:, 1:, :] = Dinv
     g[:, 0, :] = -Dinv.sum(axis=1)
     vol = np.abs(det) / 6.0
@@ -77,14 +96,15 @@ def element_matrices(coords, tets, eps=None, mu=None):
     """
     g, vol = barycentric_gradients(coords, tets)
     nt = len(vol)
-    eps = np.ones(nt) if eps is None else np.asarray(eps, dtype=np.float64)
-    mu = np.ones(nt) if mu is None else np.asarray(mu, dtype=np.float64)
+    dt_ = vol.dtype
+    eps = np.ones(nt, dtype=dt_) if eps is None else np.asarray(eps, dtype=dt_)
+    mu = np.ones(nt, dtype=dt_) if mu is None else np.asarray(mu, dtype=dt_)
     gg = np.einsum("tad,tbd->tab", g, g)      # g_a . g_b
-    Te = np.zeros((nt, 6, 6))
-    Se = np.zeros((nt, 6, 6))
+    Te = np.zeros((nt, 6, 6), dtype=dt_)
+    Se = np.zeros((nt, 6, 6), dtype=dt_)
 
     def m(a, b):                               # integral lam_a lam_b / V
-        return (2.0 if a == b else 1.0) / 20.0
+        return dt_.type(2.0 if a == b else 1.0) / dt_.type(20.0)
 
     for A, (i, j) in enumerate(LOCAL_EDGES):
         cij = np.cross(g[:, i], g[:, j])
@@ -99,8 +119,9 @@ def element_matrices(coords, tets, eps=None, mu=None):
 class Discretisation:
     """Edges, unknown numbering and assembled global matrices of one mesh."""
 
-    def __init__(self, coords, tets, eps=None, mu=None):
-        self.coords = np.asarray(coords, dtype=np.float64)
+    def __init__(self, coords, tets, eps=None, mu=None, dtype=np.float64):
+        self.dtype = np.dtype(dtype)
+        self.coords = np.asarray(coords, dtype=self.dtype)
         self.tets = np.asarray(tets)
         self.edges, self.tet_edges = canonical_edges(self.tets)
         self.n_e = len(self.edges)
@@ -110,8 +131,8 @@ class Discretisation:
         self.dof = np.full(self.n_e, -1, dtype=np.int64)   # edge -> unknown
         self.dof[self.interior] = np.arange(self.n_int)
         nt = len(self.tets)
-        self.eps = np.ones(nt) if eps is None else np.asarray(eps, np.float64)
-        self.mu = np.ones(nt) if mu is None else np.asarray(mu, np.float64)
+        self.eps = np.ones(nt, self.dtype) if eps is None else np.asarray(eps, self.dtype)
+        self.mu = np.ones(nt, self.dtype) if mu is None else np.asarray(mu, self.dtype)
         self.Te, self.Se = element_matrices(self.coords, self.tets, self.eps, self.mu)
         self.T = self._assemble(self.Te)
         self.S = self._assemble(self.Se)
@@ -165,6 +186,6 @@ class Discretisation:
     def extend(self, x_int):
         """[..., n_int] -> [..., n_e] with PEC entries 0."""
         x_int = np.asarray(x_int)
-        out = np.zeros(x_int.shape[:-1] + (self.n_e,))
+        out = np.zeros(x_int.shape[:-1] + (self.n_e,), dtype=x_int.dtype)
         out[..., self.interior] = x_int
         return out

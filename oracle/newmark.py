@@ -134,9 +134,14 @@ class NewmarkOracle:
 
     def __init__(self, coords, tets, eps=None, mu=None, dt=0.05, beta=0.25,
                  factor=True, solver="direct", pcg_tol=1e-13):
-        self.d = Discretisation(coords, tets, eps, mu)
-        self.dt = float(dt)
-        self.beta = float(beta)
+        # solver="extended": the recurrence and the assembly in 80-bit
+        # extended precision (numpy longdouble), each step solved by the FP64
+        # factor refined on the extended-precision residual (for finite
+        # differences whose rounding floor must sit below FP64's)
+        ld = solver == "extended"
+        self.d = Discretisation(coords, tets, eps, mu, dtype=np.longdouble if ld else np.float64)
+        self.dt = np.longdouble(dt) if ld else float(dt)
+        self.beta = np.longdouble(beta) if ld else float(beta)
         d = self.d
         self.A = (d.T + (self.beta * self.dt ** 2) * d.S).tocsc()
         self.B1 = (2.0 * d.T + ((2.0 * self.beta - 1.0) * self.dt ** 2) * d.S).tocsr()
@@ -147,11 +152,11 @@ class NewmarkOracle:
         if solver == "pcg":
             self.A = self.A.tocsr()
             self.lam_lo = mass_lower_bound(d)
-        elif solver != "direct":
+        elif solver not in ("direct", "extended"):
             raise ValueError(solver)
         elif factor:
             self.perm = nested_dissection(self.d)
-            Ap = self.A[self.perm][:, self.perm].tocsc()
+            Ap = self.A[self.perm][:, self.perm].astype(np.float64).tocsc()
             # A is SPD: keep the diagonal pivots, so this is a symmetric LU
             # in the given (fill-reducing) order.
             self.lu = spla.splu(Ap, permc_spec="NATURAL", diag_pivot_thresh=0.0,
@@ -173,10 +178,36 @@ class NewmarkOracle:
             bound = np.where(xn > 0, rn / (self.lam_lo * np.where(xn > 0, xn, 1.0)), 0.0)
             self.solve_log.append((it, float(rel.max()), float(bound.max())))
             return np.ascontiguousarray(x.T)
+        if self.solver == "extended":
+            return self._solve_refined(np.asarray(b, dtype=np.longdouble))
         bp = np.ascontiguousarray(np.asarray(b).T[self.perm])
         x = np.empty_like(bp)
         x[self.perm] = self.lu.solve(bp)
         return x.T
+
+    def _lu_solve(self, b):
+        """FP64 factor applied to [nrhs, n_int] (any dtype in, float64 out)."""
+        bp = np.ascontiguousarray(np.asarray(b, dtype=np.float64).T[self.perm])
+        x = np.empty_like(bp)
+        x[self.perm] = self.lu.solve(bp)
+        return x.T
+
+    def _solve_refined(self, b):
+        """Iterative refinement to the extended-precision residual: x = LU^-1 b,
+        then x += LU^-1 (b - A x) with the residual in longdouble, until it
+        stops shrinking (each sweep gains the factor's ~1e-14)."""
+        x = self._lu_solve(b).astype(np.longdouble)
+        bn = np.linalg.norm(b.astype(np.float64), axis=1)
+        prev = np.inf
+        for _ in range(8):
+            r = b - (self.A @ x.T).T
+            rn = float(np.max(np.linalg.norm(r.astype(np.float64), axis=1) / np.where(bn > 0, bn, 1.0)))
+            if rn == 0.0 or rn >= 0.5 * prev:
+                break
+            prev = rn
+            x = x + self._lu_solve(r).astype(np.longdouble)
+        self.solve_log.append((0, rn, 0.0))
+        return x
 
     def step(self, e_n, e_nm1, J_half, J_prev_half):
         return self.solve(self.rhs(e_n, e_nm1, J_half, J_prev_half), x0=e_n)
@@ -187,11 +218,11 @@ class NewmarkOracle:
         Returns E [N+1, nrhs, n_e] with E[0] = e^0 = 0 and E[n] = e^n.
         """
         d = self.d
-        J = d.restrict(J_half_edges)
+        J = d.restrict(np.asarray(J_half_edges, dtype=d.dtype))
         N, nrhs, _ = J.shape
-        e = np.zeros((N + 1, nrhs, d.n_int))
-        e_nm1 = np.zeros((nrhs, d.n_int))
-        J_prev = np.zeros((nrhs, d.n_int))
+        e = np.zeros((N + 1, nrhs, d.n_int), dtype=d.dtype)
+        e_nm1 = np.zeros((nrhs, d.n_int), dtype=d.dtype)
+        J_prev = np.zeros((nrhs, d.n_int), dtype=d.dtype)
         for n in range(N):
             e[n + 1] = self.step(e[n], e_nm1, J[n], J_prev)
             e_nm1 = e[n]

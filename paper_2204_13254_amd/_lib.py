@@ -22,7 +22,14 @@ class Options(C.Structure):
                 ("cg_max_iter", C.c_int), ("refine_tol", C.c_double), ("refine_max", C.c_int),
                 ("warm_start", C.c_int), ("use_graph", C.c_int), ("check_every", C.c_int),
                 ("stream", C.c_void_p), ("precond", C.c_int), ("method", C.c_int),
-                ("robin_alpha", C.c_double), ("diagnostics", C.c_int)]
+                ("robin_alpha", C.c_double), ("diagnostics", C.c_int), ("tune_cache", C.c_char_p)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("chunk", C.c_int), ("coarse_chunk", C.c_int), ("full_chunk", C.c_int),
+                ("full_bucket", C.c_int), ("from_cache", C.c_int), ("full_ms", C.c_double),
+                ("full_ms_default", C.c_double), ("coarse_ms", C.c_double), ("coarse_ms_default", C.c_double),
+                ("trailing_ms", C.c_double), ("trailing_ms_default", C.c_double)]
 
 
 DD_DIAG_GAUSS, DD_DIAG_ENERGY = 1, 2
@@ -69,6 +76,7 @@ SIGNATURES = {
     "dd_set_eps": (C.c_int, [P, P, C.c_int]),
     "dd_set_charge": (C.c_int, [P, P]),
     "dd_factor": (C.c_int, [P]),
+    "dd_autotune": (C.c_int, [P, C.c_char_p, C.POINTER(Tuning)]),
     "dd_step": (C.c_int, [P, P, P, P, P, P, C.POINTER(Stats)]),
     "dd_solve": (C.c_int, [P, P, P, C.POINTER(Stats)]),
     "dd_adjoint_step": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, C.POINTER(Stats)]),

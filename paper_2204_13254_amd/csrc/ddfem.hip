@@ -93,10 +93,15 @@ struct Items {
   void* partial = nullptr;   // own partial slots (lists that run beside others), or null
 };
 
-constexpr int kChunkTiles = 32;  // longest tile range of one wave
-// coarse lists are few and long; 16-tile chunks measured best (8: +10%, 4: +28%)
-constexpr int kCoarseChunkTiles = 16;
-constexpr int kFullChunkTiles = 96;
+// Work-list shapes (longest tile range of one wave per product class, and
+// the length buckets of the full passes).  Defaults measured on the 64^3
+// box workload; dd_autotune picks them per context by timing candidates.
+struct Tuning {
+  int chunk = 32;         // interface-block and corner-row lists
+  int coarse_chunk = 16;  // coarse lists: few and long (8: +10%, 4: +28% at 64^3)
+  int full_chunk = 96;    // full r-block lists
+  int full_bucket = 8;    // length buckets of the full lists' placement
+};
 
 struct Ctx {
   Plan P;
@@ -114,6 +119,13 @@ struct Ctx {
   hipGraphExec_t cg_graph = nullptr;  // captured block of CG iterations
   int cg_graph_iters = 0;
   bool coarse_lists = false;  // coarse products use the nonzero-tile lists
+  Tuning tuning;
+  std::string tune_cache;     // dd_options.tune_cache, copied at setup ("" = none)
+  bool tune_applied = false;  // dd_factor has run the tuner (or read its cache) once
+  // output blocks of every product class (host), kept so that the work lists
+  // can be rebuilt with other chunk lengths
+  std::vector<MvItem> blk_trail_N, blk_trail_T, blk_corner_N, blk_corner_T, blk_co_N, blk_co_T, blk_full_N,
+      blk_full_T;
   std::vector<uint8_t> full_pattern;  // nonzero-tile flags the full lists were built from
   std::vector<void*> owned;
 
@@ -329,7 +341,7 @@ static std::vector<It> place_xcd(int nsub, const std::vector<It>& v, const It& p
   return placed;
 }
 
-static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = kChunkTiles, bool grouped = false) {
+static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk, bool grouped = false, int bucket = 1) {
   bool split = false;
   for (const MvItem& b : blocks)
     if (b.hi - b.lo > chunk) split = true;
@@ -373,7 +385,7 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk = k
   }
   std::vector<MvItem> placed = place_xcd(
       C.nsub, v, MvItem{-1, 0, 0, 0, -1, 0}, [](const MvItem& a) { return a.s; },
-      [](const MvItem& a) { return (int64_t)(a.hi - a.lo); }, grouped ? 8 : 1);
+      [](const MvItem& a) { return (int64_t)(a.hi - a.lo); }, grouped ? bucket : 1);
   Items it;
   it.n = (int64_t)placed.size();
   it.d = upload(placed, C.owned, C.st);
@@ -844,16 +856,20 @@ static void build_device(Ctx& C, const double* coords) {
       oN.push_back({nsub, o, 0, o + 1, -1, 0});
       oT.push_back({nsub, o, o, C.Kc, -1, 0});
     }
-    C.trail_N = make_items(C, tN);
-    C.trail_T = make_items(C, tT);
+    C.trail_N = make_items(C, tN, C.tuning.chunk);
+    C.trail_T = make_items(C, tT, C.tuning.chunk);
     // runs beside the coarse chain: own partial slots
     make_sym_list(C, C.fp32 ? sym_panel<float>() : sym_panel<double>(), wsz);
-    C.corner_N = make_items(C, cN);
+    C.corner_N = make_items(C, cN, C.tuning.chunk);
     // (summing the symmetric partials inside this pass instead of a reduce on
     // the side stream measured slower: it lengthens the main-stream chain)
-    C.corner_T = make_items(C, cT);
-    C.co_N = make_items(C, oN);
-    C.co_T = make_items(C, oT);
+    C.corner_T = make_items(C, cT, C.tuning.chunk);
+    C.co_N = make_items(C, oN, C.tuning.chunk);
+    C.co_T = make_items(C, oT, C.tuning.chunk);
+    C.blk_trail_N.swap(tN);
+    C.blk_trail_T.swap(tT);
+    C.blk_corner_N.swap(cN);
+    C.blk_corner_T.swap(cT);
     void* p = nullptr;
     HIPCHK(hipMalloc(&p, std::max<int64_t>(1, C.max_slots) * kTile * C.nrhs * wsz / NB));
     C.owned.push_back(p);
@@ -1006,10 +1022,14 @@ static void coarse_tile_lists(Ctx& C) {
     bt.push_back({C.nsub, o, b, (int32_t)lt.size(), -1, 0});
   }
   // few output blocks: short chunks so that the product fills the device
-  C.co_N = make_items(C, bn, kCoarseChunkTiles);
+  release_items(C, C.co_N);
+  release_items(C, C.co_T);
+  C.co_N = make_items(C, bn, C.tuning.coarse_chunk);
   C.co_N.mlist = upload(ln, C.owned, C.st);
-  C.co_T = make_items(C, bt, kCoarseChunkTiles);
+  C.co_T = make_items(C, bt, C.tuning.coarse_chunk);
   C.co_T.mlist = upload(lt, C.owned, C.st);
+  C.blk_co_N.swap(bn);
+  C.blk_co_T.swap(bt);
   C.coarse_bytes = entries * (int64_t)sizeof(T);
   C.coarse_lists = true;
   ensure_partial<T>(C);
@@ -1057,14 +1077,19 @@ static void full_tile_lists(Ctx& C) {
   // 96-tile chunks: rows of the bench subdomains stay in one wave and write
   // their outputs directly (at 64^3 per pass: 48 tiles 1.465 ms, 64 1.444,
   // 80 1.432, 96 1.430, 128 1.432)
-  C.full_N = make_items(C, bn, kFullChunkTiles, true);
+  C.full_N = make_items(C, bn, C.tuning.full_chunk, true, C.tuning.full_bucket);
   C.full_N.mlist = upload(ln, C.owned, C.st);
-  C.full_T = make_items(C, bt, kFullChunkTiles, true);
+  C.full_T = make_items(C, bt, C.tuning.full_chunk, true, C.tuning.full_bucket);
   C.full_T.mlist = upload(lt, C.owned, C.st);
+  C.blk_full_N.swap(bn);
+  C.blk_full_T.swap(bt);
   C.full_bytes = entries * (int64_t)sizeof(T);
   C.full_pattern.swap(pat);
   ensure_partial<T>(C);
 }
+
+template <class T>
+static void autotune(Ctx& C, const char* cache, dd_tuning* out);
 
 template <class T>
 static int factor_impl(Ctx& C) {
@@ -1119,6 +1144,7 @@ static int factor_impl(Ctx& C) {
   }
   C.factored = true;
   C.warm_fw.have = C.warm_adj.have = 0;
+  if (!C.tune_cache.empty() && !C.tune_applied) autotune<T>(C, C.tune_cache.c_str(), nullptr);
   return DD_OK;
 }
 
@@ -1897,6 +1923,239 @@ static int adjoint_impl(Ctx& C, const double* ebar_next, double* ebar_n, double*
   return status;
 }
 
+// ---------------------------------------------------------------------------
+// autotuner of the work-list shapes
+// ---------------------------------------------------------------------------
+// Rebuild the work lists of the classes in `which` (1: interface blocks and
+// corner rows, 2: coarse, 4: full r-blocks) with the current tuning.  The
+// tile lists (mlist) do not depend on the chunking and are kept.  The
+// captured CG graph holds the old lists, so it is dropped (recaptured on the
+// next solve).
+template <class T>
+static void rebuild_lists(Ctx& C, int which) {
+  auto remake = [&](Items& it, const std::vector<MvItem>& blk, int chunk, bool grouped, int bucket) {
+    int32_t* ml = it.mlist;
+    it.mlist = nullptr;
+    release_items(C, it);
+    it = make_items(C, blk, chunk, grouped, bucket);
+    it.mlist = ml;
+  };
+  if (C.cg_graph) {
+    HIPCHK(hipStreamSynchronize(C.st));
+    HIPCHK(hipGraphExecDestroy(C.cg_graph));
+    C.cg_graph = nullptr;
+  }
+  HIPCHK(hipStreamSynchronize(C.st));
+  if (which & 1) {
+    remake(C.trail_N, C.blk_trail_N, C.tuning.chunk, false, 1);
+    remake(C.trail_T, C.blk_trail_T, C.tuning.chunk, false, 1);
+    remake(C.corner_N, C.blk_corner_N, C.tuning.chunk, false, 1);
+    remake(C.corner_T, C.blk_corner_T, C.tuning.chunk, false, 1);
+  }
+  if ((which & 2) && C.coarse_lists) {
+    remake(C.co_N, C.blk_co_N, C.tuning.coarse_chunk, false, 1);
+    remake(C.co_T, C.blk_co_T, C.tuning.coarse_chunk, false, 1);
+  }
+  if ((which & 4) && C.full_N.d) {
+    remake(C.full_N, C.blk_full_N, C.tuning.full_chunk, true, C.tuning.full_bucket);
+    remake(C.full_T, C.blk_full_T, C.tuning.full_chunk, true, C.tuning.full_bucket);
+  }
+  ensure_partial<T>(C);
+}
+
+// Cache key of a tuning: device, precision, RHS count and a hash of the
+// subdomain tile shapes and the nonzero-tile pattern of the full lists.
+static std::string tune_key(const Ctx& C) {
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, C.device));
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xff;
+      h *= 1099511628211ull;
+    }
+  };
+  for (const SubDev& q : C.subs_h) {
+    mix((uint64_t)q.kI);
+    mix((uint64_t)q.kG);
+    mix((uint64_t)q.kC);
+  }
+  for (uint8_t b : C.full_pattern) mix(b);
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s/%s/nrhs%d/nsub%d/%016llx", prop.gcnArchName, C.fp32 ? "fp32" : "fp64",
+                C.nrhs, C.nsub, (unsigned long long)h);
+  return buf;
+}
+
+// The integer value of "name": in one line of the cache, or -1.
+static long json_int(const std::string& line, const char* name) {
+  const std::string k = std::string("\"") + name + "\":";
+  size_t p = line.find(k);
+  if (p == std::string::npos) return -1;
+  return std::strtol(line.c_str() + p + k.size(), nullptr, 10);
+}
+
+// Look the key up in the cache (JSON lines: one object per tuning).
+static bool tune_cache_read(const std::string& path, const std::string& key, Tuning& t) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char buf[4096];
+  bool found = false;
+  const std::string kq = "\"key\": \"" + key + "\"";
+  while (std::fgets(buf, sizeof buf, f)) {
+    std::string line(buf);
+    if (line.find(kq) == std::string::npos) continue;
+    Tuning c;
+    long v[4] = {json_int(line, "chunk"), json_int(line, "coarse_chunk"), json_int(line, "full_chunk"),
+                 json_int(line, "full_bucket")};
+    if (v[0] < 1 || v[1] < 1 || v[2] < 1 || v[3] < 1 || v[0] > 4096 || v[1] > 4096 || v[2] > 4096 || v[3] > 4096)
+      continue;
+    c.chunk = (int)v[0];
+    c.coarse_chunk = (int)v[1];
+    c.full_chunk = (int)v[2];
+    c.full_bucket = (int)v[3];
+    t = c;
+    found = true;  // the last entry for a key wins
+  }
+  std::fclose(f);
+  return found;
+}
+
+static void tune_cache_append(const std::string& path, const std::string& key, const Tuning& t,
+                              const dd_tuning& r) {
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) throw DDError{DD_ERR_ARG, "cannot open the tuning cache " + path + " for writing"};
+  std::fprintf(f,
+               "{\"key\": \"%s\", \"chunk\": %d, \"coarse_chunk\": %d, \"full_chunk\": %d, "
+               "\"full_bucket\": %d, \"full_ms\": %.5f, \"full_ms_default\": %.5f, \"coarse_ms\": %.5f, "
+               "\"coarse_ms_default\": %.5f, \"trailing_ms\": %.5f, \"trailing_ms_default\": %.5f}\n",
+               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, r.full_ms, r.full_ms_default,
+               r.coarse_ms, r.coarse_ms_default, r.trailing_ms, r.trailing_ms_default);
+  std::fclose(f);
+}
+
+// Time every candidate shape of each product class (the products of one DD
+// solve, on zero vectors: the time does not depend on the values), keep the
+// fastest, and leave the lists built with it.  Per class: the median of 5
+// timed repetitions after a warm-up, with HIP events on the context stream.
+template <class T>
+static void autotune_impl(Ctx& C, dd_tuning* out) {
+  hipStream_t st = C.st;
+  const T one = 1, mone = -1;
+  const size_t vb = (size_t)std::max<int64_t>(1, C.rows_total) * C.nrhs * sizeof(T);
+  for (int i = 0; i < 8; ++i) HIPCHK(hipMemsetAsync(C.X[i], 0, vb, st));
+  hipEvent_t ev[6];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  struct Guard {
+    hipEvent_t* e;
+    ~Guard() {
+      for (int i = 0; i < 6; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  auto timed = [&](auto&& fn) -> double {
+    fn();
+    float ms[5];
+    for (int r = 0; r < 5; ++r) {
+      HIPCHK(hipEventRecord(ev[0], st));
+      fn();
+      HIPCHK(hipEventRecord(ev[1], st));
+      HIPCHK(hipEventSynchronize(ev[1]));
+      HIPCHK(hipEventElapsedTime(&ms[r], ev[0], ev[1]));
+    }
+    std::sort(ms, ms + 5);
+    return ms[2];
+  };
+  void** X = C.X;
+  auto full = [&] {
+    mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, nullptr, X[0], mone);
+    mv<T>(C, C.full_T, true, X[1], X[5], nullptr, one);
+  };
+  auto coarse = [&] { coarse_solve<T>(C, X[6], X[7], X[5], nullptr); };
+  auto trailing = [&] {
+    mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one);
+    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
+    mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
+    mv<T>(C, C.corner_T, true, X[6], X[8], nullptr, one);
+  };
+  const bool prof = C.prof;
+  C.prof = false;
+  Tuning best = C.tuning;
+  dd_tuning r{};
+  // full passes: chunk length x placement bucket
+  if (C.full_N.d) {
+    r.full_ms_default = r.full_ms = timed(full);
+    for (int fc : {48, 64, 96, 128, 192})
+      for (int b : {1, 4, 8, 16}) {
+        C.tuning.full_chunk = fc;
+        C.tuning.full_bucket = b;
+        rebuild_lists<T>(C, 4);
+        const double t = timed(full);
+        if (t < r.full_ms) {
+          r.full_ms = t;
+          best.full_chunk = fc;
+          best.full_bucket = b;
+        }
+      }
+  }
+  C.tuning = best;
+  rebuild_lists<T>(C, 4);
+  if (C.Kc > 0 && C.coarse_lists) {
+    r.coarse_ms_default = r.coarse_ms = timed(coarse);
+    for (int cc : {8, 12, 16, 24, 32, 48}) {
+      C.tuning.coarse_chunk = cc;
+      rebuild_lists<T>(C, 2);
+      const double t = timed(coarse);
+      if (t < r.coarse_ms) {
+        r.coarse_ms = t;
+        best.coarse_chunk = cc;
+      }
+    }
+  }
+  C.tuning = best;
+  rebuild_lists<T>(C, 2);
+  r.trailing_ms_default = r.trailing_ms = timed(trailing);
+  for (int ch : {16, 24, 32, 48, 64}) {
+    C.tuning.chunk = ch;
+    rebuild_lists<T>(C, 1);
+    const double t = timed(trailing);
+    if (t < r.trailing_ms) {
+      r.trailing_ms = t;
+      best.chunk = ch;
+    }
+  }
+  C.tuning = best;
+  rebuild_lists<T>(C, 1);
+  C.prof = prof;
+  r.chunk = best.chunk;
+  r.coarse_chunk = best.coarse_chunk;
+  r.full_chunk = best.full_chunk;
+  r.full_bucket = best.full_bucket;
+  if (out) *out = r;
+}
+
+// dd_autotune: cached tuning if the cache has the key, else a timed search
+// (appended to the cache when one is given).
+template <class T>
+static void autotune(Ctx& C, const char* cache, dd_tuning* out) {
+  const std::string key = tune_key(C);
+  dd_tuning r{};
+  Tuning t;
+  if (cache && *cache && tune_cache_read(cache, key, t)) {
+    C.tuning = t;
+    rebuild_lists<T>(C, 7);
+    r.chunk = t.chunk;
+    r.coarse_chunk = t.coarse_chunk;
+    r.full_chunk = t.full_chunk;
+    r.full_bucket = t.full_bucket;
+    r.from_cache = 1;
+  } else {
+    autotune_impl<T>(C, &r);
+    if (cache && *cache) tune_cache_append(cache, key, C.tuning, r);
+  }
+  C.tune_applied = true;
+  if (out) *out = r;
+}
+
 }  // namespace ddfem
 
 using namespace ddfem;
@@ -2282,6 +2541,8 @@ int dd_setup(void** out, const dd_mesh* mesh, const int32_t* partition, const do
   C = new Ctx();
   C->opt = o;
   C->st = (hipStream_t)o.stream;
+  if (o.tune_cache) C->tune_cache = o.tune_cache;
+  C->opt.tune_cache = nullptr;  // the caller's string is not kept
   HIPCHK(hipGetDevice(&C->device));
   resolve_scratch(C->device);
   HIPCHK(hipStreamCreateWithFlags(&C->st2, hipStreamNonBlocking));
@@ -2389,6 +2650,25 @@ int dd_set_eps(void* ctx, const double* eps_in, int on_device) {
   HIPCHK(hipMemcpyAsync(C.d_eps, eps, C.P.nt * sizeof(double), hipMemcpyHostToDevice, C.st));
   HIPCHK(hipStreamSynchronize(C.st));
   C.factored = false;
+  return DD_OK;
+  API_END
+}
+
+int dd_autotune(void* ctx, const char* cache_path, dd_tuning* out) {
+  if (!ctx) {
+    g_err = "null context";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_autotune called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  API_BEGIN
+  if (C.fp32)
+    autotune<float>(C, cache_path, out);
+  else
+    autotune<double>(C, cache_path, out);
   return DD_OK;
   API_END
 }

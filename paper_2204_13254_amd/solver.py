@@ -8,7 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DD_FP32_REFINE, DD_FP64, Analysis, Info, Mesh, Options, Stats, check, load
+from ._lib import DD_FP32_REFINE, DD_FP64, Analysis, Info, Mesh, Options, Stats, Tuning, check, load
 
 
 def _host(a, dtype):
@@ -66,7 +66,8 @@ class DDSolver:
     def __init__(self, coords, tets, partition, eps, mu=None, dt=0.05, beta=0.25, *,
                  precision="fp64", nrhs=1, cg_tol=1e-10, cg_max_iter=500, refine_tol=1e-12,
                  refine_max=10, warm_start=0, check_every=4, stream=None, factor=True,
-                 use_graph=False, precond=1, method="dp1", robin_alpha=0.0, diagnostics=0):
+                 use_graph=False, precond=1, method="dp1", robin_alpha=0.0, diagnostics=0,
+                 tune_cache=None):
         self.lib = load()
         o = Options()
         self.lib.dd_default_options(C.byref(o))
@@ -85,6 +86,7 @@ class DDSolver:
         o.method = 1 if method == "dp2" else 0
         o.robin_alpha = float(robin_alpha)
         o.diagnostics = int(diagnostics)
+        o.tune_cache = None if tune_cache is None else str(tune_cache).encode()
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -153,6 +155,13 @@ class DDSolver:
 
     def factor(self):
         check(self.lib.dd_factor(self.h))
+
+    def autotune(self, cache=None):
+        """Tune the work-list shapes (dd_autotune); returns them and the
+        measured times as a dict."""
+        t = Tuning()
+        check(self.lib.dd_autotune(self.h, None if cache is None else str(cache).encode(), C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
 
     def new_field(self):
         return torch.zeros((self.nrhs, self.n_edges), dtype=torch.float64, device="cuda")
