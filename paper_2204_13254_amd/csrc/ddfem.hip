@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -101,6 +102,7 @@ struct Tuning {
   int coarse_chunk = 16;  // coarse lists: few and long (8: +10%, 4: +28% at 64^3)
   int full_chunk = 96;    // full r-block lists
   int full_bucket = 8;    // length buckets of the full lists' placement
+  int full_persist = 0;   // full passes: workgroups of a persistent grid (0: one per work group)
 };
 
 struct Ctx {
@@ -118,6 +120,15 @@ struct Ctx {
   bool factored = false;
   hipGraphExec_t cg_graph = nullptr;  // captured block of CG iterations
   int cg_graph_iters = 0;
+  // captured refined solve of a step (pre-solve, CG, recovery, residual
+  // checks and gated sweeps; FP32 factors with refinement, first variant):
+  // CG iterations per solve and sweeps it holds, the last step's needs
+  hipGraphExec_t step_graph = nullptr;
+  int step_iters = 0, step_sweeps = 0;
+  int need_iters = 0, need_sweeps = 0;
+  RefineState* d_rs = nullptr;
+  RefineState* h_rs = nullptr;   // pinned
+  double* d_rpart = nullptr;     // partial sums of the refinement norms [kDotBlocks][kMaxRhs]
   bool coarse_lists = false;  // coarse products use the nonzero-tile lists
   Tuning tuning;
   std::string tune_cache;     // dd_options.tune_cache, copied at setup ("" = none)
@@ -207,8 +218,8 @@ struct Ctx {
   int32_t* d_vedge = nullptr;
   uint8_t* d_nodeint = nullptr;
   double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
-  double* d_q = nullptr;     // accumulated nodal charge of the per-step check, [nrhs][nv]
-  double* d_gmax = nullptr;  // per-block maxima of the per-step check, [nrhs][kGaussBlocks][2]
+  double* d_q = nullptr;     // accumulated nodal charge of the per-step check, [nv][nrhs]
+  double* d_gmax = nullptr;  // maxima of the per-step check: [kGaussBlocks][nrhs][2], then [nrhs][2]
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
   // trail_N: interface rows of Linv_GG (recovery); trail_T: Linv_GG^T with
@@ -267,6 +278,8 @@ struct Ctx {
     if (st) (void)hipStreamSynchronize(st);
     if (st2) (void)hipStreamSynchronize(st2);
     if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
+    if (step_graph) (void)hipGraphExecDestroy(step_graph);
+    if (h_rs) (void)hipHostFree(h_rs);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (st2) (void)hipStreamDestroy(st2);
@@ -830,7 +843,7 @@ static void build_device(Ctx& C, const double* coords) {
     C.d_vres = dalloc<double>(P.nv * C.nrhs, C.owned);
     C.d_q = dalloc<double>(P.nv * C.nrhs, C.owned);
     HIPCHK(hipMemsetAsync(C.d_q, 0, P.nv * C.nrhs * sizeof(double), st));
-    C.d_gmax = dalloc<double>((size_t)kGaussBlocks * kMaxRhs * 2, C.owned);
+    C.d_gmax = dalloc<double>((size_t)(kGaussBlocks + 1) * kMaxRhs * 2, C.owned);
   }
   // ---- work lists --------------------------------------------------------------------
   {
@@ -904,6 +917,9 @@ static void build_device(Ctx& C, const double* coords) {
   C.d_cg = dalloc<CgState>(1, C.owned);
   HIPCHK(hipHostMalloc((void**)&C.h_cg, sizeof(CgState), hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&C.h_partial, sizeof(double) * kDotBlocks * kMaxRhs, hipHostMallocDefault));
+  C.d_rs = dalloc<RefineState>(1, C.owned);
+  HIPCHK(hipHostMalloc((void**)&C.h_rs, sizeof(RefineState), hipHostMallocDefault));
+  C.d_rpart = dalloc<double>((size_t)kDotBlocks * kMaxRhs, C.owned);
   const int64_t ng = std::max<int64_t>(1, P.nint) * nr;
   C.g_b = dalloc<double>(ng, C.owned);
   C.g_e = dalloc<double>(ng, C.owned);
@@ -914,6 +930,15 @@ static void build_device(Ctx& C, const double* coords) {
   C.g_t3 = dalloc<double>(ng, C.owned);
   C.g_t4 = dalloc<double>(ng, C.owned);
   HIPCHK(hipStreamSynchronize(st));
+}
+
+// Drop the captured graphs (they hold work lists, buffers and iteration
+// counts that are about to change); the next solve captures them again.
+static void drop_graphs(Ctx& C) {
+  if (C.cg_graph) HIPCHK(hipGraphExecDestroy(C.cg_graph));
+  if (C.step_graph) HIPCHK(hipGraphExecDestroy(C.step_graph));
+  C.cg_graph = nullptr;
+  C.step_graph = nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -1096,6 +1121,11 @@ static int factor_impl(Ctx& C) {
   Plan& P = C.P;
   hipStream_t st = C.st;
   T* tiles = (T*)C.d_tiles;
+  // the work lists may change with the factor's nonzero pattern: captured
+  // solves are dropped, and the next step runs eagerly to size its capture
+  HIPCHK(hipStreamSynchronize(st));
+  drop_graphs(C);
+  C.need_iters = C.need_sweeps = 0;
   HIPCHK(hipMemsetAsync(tiles, 0, std::max<int64_t>(1, C.ntiles) * kTile * sizeof(T), st));
   int big = INT32_MAX;
   HIPCHK(hipMemcpyAsync(C.d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
@@ -1192,7 +1222,11 @@ static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const 
   const bool split = it.n_out > 0;
   const T* tiles = (const T*)(trans ? C.d_tilesT : C.d_tiles);
   T* partial = (T*)(it.partial ? it.partial : C.d_partial_mv);
-  hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)((it.n + 3) / 4)), dim3(256), 0, s, it.n, it.d,
+  // work groups come in multiples of 8 (one per XCD); a persistent grid is
+  // a multiple of 8 too, so each workgroup stays on its groups' XCD
+  int64_t grid = (it.n + 3) / 4;
+  if (CLS == DD_PROF_FULL && C.tuning.full_persist > 0) grid = std::min<int64_t>(grid, C.tuning.full_persist);
+  hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
                      C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
                      (int)trans, partial, (const int32_t*)it.mlist, skip);
   if (split)
@@ -1502,28 +1536,37 @@ static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, dou
 
 // x = A^-1 b (one decomposed solve, unknown-major [nint][nrhs] FP64).
 // Returns DD_OK or DD_ERR_NO_CONVERGENCE; fills iters/relres.
+// Captured form (fixed_iters > 0, inside a stream capture): exactly
+// fixed_iters CG iterations (kernels return at once after convergence), no
+// host synchronisation and no warm start; every kernel is skipped while
+// *gate != 0; the CG state is snapshotted into C.d_rs slot `slot` and
+// iters/relres are not filled (read back with the step).
 template <class T>
-static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, int* iters, double* relres) {
+static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, int* iters, double* relres,
+                         const int* gate = nullptr, int fixed_iters = 0, int slot = 0) {
   const int nr = C.nrhs;
   hipStream_t st = C.st;
   void** X = C.X;
   const T one = 1, mone = -1;
   // ---- pre-solve --------------------------------------------------------
+  const bool captured = fixed_iters > 0;
+  if (captured && (warm || C.opt.method == 1))
+    throw DDError{DD_ERR_STATE, "captured solve: no warm start, first variant only"};
   hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
-                     (T*)X[0], nr);
+                     (T*)X[0], nr, gate);
   // r rows: t = Linv_rr w_r;  corner rows: g = w_c - Psi_r w_r
-  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, nullptr, X[0], mone);
+  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, gate, X[0], mone);
   if (C.Kc > 0) {
     // f_c = sum B_c^T g (coarse rows of X1, kept for the recovery); z0 = K_cc^-1 f_c
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[1], (T*)X[1],
-                       (const T*)nullptr, nr, (const int*)nullptr);
-    coarse_solve<T>(C, X[1], X[2], X[3], nullptr);
+                       (const T*)nullptr, nr, gate);
+    coarse_solve<T>(C, X[1], X[2], X[3], gate);
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[3], (T*)X[1], mone, nr, (const int*)nullptr);
+                       C.d_csccrow, (const T*)X[3], (T*)X[1], mone, nr, gate);
   }
   // d-contribution: Linv_GG^T t_G - Psi_G^T z0
-  mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one);
+  mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one, gate);
   for (int r = 0; r < nr; ++r) {
     iters[r] = 0;
     relres[r] = 0.0;
@@ -1540,15 +1583,13 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   } else if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
     hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
-                       (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, nr, C.d_partial,
-                       (const int*)nullptr);
-    // ---- CG on F lambda = d ----------------------------------------------------
-    HIPCHK(hipMemsetAsync(C.d_cg, 0, sizeof(CgState), st));
+                       (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, nr, C.d_partial, gate);
+    // ---- CG on F lambda = d (stage 0 of k_cg_scalar resets the whole state) ----
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
-                       C.d_partial, (const int*)nullptr);
+                       C.d_partial, gate);
     hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 0, nr, (const double*)C.d_partial,
-                       (const double*)nullptr, C.d_cg, C.opt.cg_tol);
-    HIPCHK(hipMemcpyAsync(C.d_res, C.d_d, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+                       (const double*)nullptr, C.d_cg, C.opt.cg_tol, gate);
+    hipLaunchKernelGGL(k_copy, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_d, C.d_res, gate);
     if (warm && warm->have > 0) {
       if (C.opt.warm_start == 2 && warm->have >= 2)
         hipLaunchKernelGGL(k_extrap, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)warm->cur,
@@ -1560,23 +1601,24 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
                          C.d_partial, (const int*)nullptr);
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 3, nr, (const double*)C.d_partial,
-                         (const double*)nullptr, C.d_cg, C.opt.cg_tol);
+                         (const double*)nullptr, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
     } else {
-      HIPCHK(hipMemsetAsync(C.d_lam, 0, nl * sizeof(double), st));
+      hipLaunchKernelGGL(k_zero<double>, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_lam, gate);
     }
     // p = z = K_lam r (lumped preconditioner), or p = r
     const bool pre = C.opt.precond == 1 && C.lam_nnz > 0;
     if (pre) {
       hipLaunchKernelGGL(k_lam_precond, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrp, C.d_lci, C.d_lvals,
-                         (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, (const int*)nullptr);
+                         (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, gate);
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 4, nr, (const double*)C.d_partial,
-                         (const double*)nullptr, C.d_cg, C.opt.cg_tol);
+                         (const double*)nullptr, C.d_cg, C.opt.cg_tol, gate);
     }
-    HIPCHK(hipMemcpyAsync(C.d_p, pre ? C.d_z : C.d_res, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_copy, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)(pre ? C.d_z : C.d_res), C.d_p,
+                       gate);
     // v = B_s^T p for the first F application (later ones are written by
     // k_cg_p_gather)
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_glam, (const double*)C.d_p, (T*)X[5], nr, (const int*)nullptr);
+                       C.d_glam, (const double*)C.d_p, (T*)X[5], nr, gate);
     const int* done = &C.d_cg->done;
     int it = 0;
     // an even block of iterations, so that every replay starts on p = d_p
@@ -1591,28 +1633,35 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       double* pn = (k & 1) ? C.d_p : C.d_p2;
       apply_F<T>(C, pc, C.d_Fp, done, true, true);
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 1, nr, (const double*)C.d_partial,
-                         (const double*)nullptr, C.d_cg, C.opt.cg_tol);
+                         (const double*)nullptr, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
       if (pre) {
         hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
                            (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
         hipLaunchKernelGGL(k_lam_precond, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrp, C.d_lci, C.d_lvals,
                            (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, done);
         hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
-                           (const double*)C.d_partial2, C.d_cg, C.opt.cg_tol);
+                           (const double*)C.d_partial2, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
       } else {
         hipLaunchKernelGGL(k_cg_xr_dot, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
                            (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res, C.d_partial);
         hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
-                           (const double*)C.d_partial, C.d_cg, C.opt.cg_tol);
+                           (const double*)C.d_partial, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
       }
       hipLaunchKernelGGL(k_cg_p_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                          C.d_glam, nr, (const CgState*)C.d_cg, (const double*)(pre ? C.d_z : C.d_res),
                          (const double*)pc, pn, (T*)X[5]);
     };
+    // captured step: a fixed number of iterations, the state snapshotted
+    if (captured) {
+      for (int k = 0; k < fixed_iters; ++k) iteration(k);
+      hipLaunchKernelGGL(k_cg_snapshot, dim3(1), dim3(64), 0, st, slot, nr, (const CgState*)C.d_cg, C.d_rs, gate);
+      converged = true;
+      have_state = true;
+    }
     // the block of chk iterations is captured once (fixed buffers, fixed
     // arguments) and replayed; needs a capturable (non-default) stream and
     // no per-launch event timing
-    const bool graph = C.opt.use_graph && st != nullptr && !C.prof;
+    const bool graph = !captured && C.opt.use_graph && st != nullptr && !C.prof;
     if (graph && (!C.cg_graph || C.cg_graph_iters != chk)) {
       if (C.cg_graph) HIPCHK(hipGraphExecDestroy(C.cg_graph));
       C.cg_graph = nullptr;
@@ -1624,7 +1673,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       HIPCHK(hipGraphDestroy(g));
       C.cg_graph_iters = chk;
     }
-    while (!converged && it < C.opt.cg_max_iter) {
+    while (!captured && !converged && it < C.opt.cg_max_iter) {
       int todo = std::min(chk, C.opt.cg_max_iter - it);
       if (graph && todo == chk && (it & 1) == 0) {
         HIPCHK(hipGraphLaunch(C.cg_graph, st));
@@ -1643,12 +1692,14 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       HIPCHK(hipMemcpyAsync(C.h_cg, C.d_cg, sizeof(CgState), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
     }
-    const CgState& hs = *C.h_cg;
-    for (int r = 0; r < nr; ++r) {
-      iters[r] = hs.iters[r];
-      relres[r] = hs.rr0[r] > 0 ? std::sqrt(hs.rr[r] / hs.rr0[r]) : 0.0;
+    if (!captured) {
+      const CgState& hs = *C.h_cg;
+      for (int r = 0; r < nr; ++r) {
+        iters[r] = hs.iters[r];
+        relres[r] = hs.rr0[r] > 0 ? std::sqrt(hs.rr[r] / hs.rr0[r]) : 0.0;
+      }
+      if (!converged || hs.breakdown) status = DD_ERR_NO_CONVERGENCE;
     }
-    if (!converged || hs.breakdown) status = DD_ERR_NO_CONVERGENCE;
     if (warm) {
       std::swap(warm->cur, warm->old);
       HIPCHK(hipMemcpyAsync(warm->cur, C.d_lam, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1658,28 +1709,31 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     // v_l = B_s^T lambda; interface rows of X1: t - t_l = t - Linv_GG v_l (in
     // place); y = Psi_G v_l on the corner rows of X6
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, (const int*)nullptr);
-    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
-    if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
+                       C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, gate);
+    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone, gate);
+    if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one, gate);
   } else {
     // no interface: t_l = 0, y = 0
-    HIPCHK(hipMemsetAsync(X[6], 0, C.rows_total * nr * sizeof(T), st));
+    hipLaunchKernelGGL(k_zero<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total * nr, (T*)X[6],
+                       gate);
+    if (captured)
+      hipLaunchKernelGGL(k_cg_snapshot, dim3(1), dim3(64), 0, st, slot, nr, (const CgState*)C.d_cg, C.d_rs, gate);
   }
   if (C.Kc > 0) {
     // x_c = K_cc^-1 (f_c + sum B_c^T y)  (coarse rows of X5)
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
                        (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
-                       (const T*)X[1], nr, (const int*)nullptr);
-    coarse_solve<T>(C, X[6], X[7], X[5], nullptr);
+                       (const T*)X[1], nr, gate);
+    coarse_solve<T>(C, X[6], X[7], X[5], gate);
   }
   // x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c: X1 holds t - [0; t_l] on
   // the r rows; its corner rows get -x_c
   if (C.Kc > 0)
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[1], mone, nr, (const int*)nullptr);
-  mv<T>(C, C.full_T, true, X[1], X[5], nullptr, one);
+                       C.d_csccrow, (const T*)X[5], (T*)X[1], mone, nr, gate);
+  mv<T>(C, C.full_T, true, X[1], X[5], nullptr, one, gate);
   hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
-                     (const T*)X[5], x, nr);
+                     (const T*)X[5], x, nr, gate);
   HIPCHK(hipGetLastError());
   return status;
 }
@@ -1688,38 +1742,91 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
 // RHS) for up to 4 RHS, the cooperative row groups for 5..32.
 template <int G, int NB, int MODE>
 static void csr_coop_launch(Ctx& C, hipStream_t st, const double* x1, const double* x2, const double* j1,
-                            const double* j2, const double* z, double ca, double cb, double* y, double* y2) {
+                            const double* j2, const double* z, double ca, double cb, double* y, double* y2,
+                            const int* skip) {
   const int64_t ni = C.P.nint;
   hipLaunchKernelGGL((k_csr_coop<G, NB, MODE>), dim3(nblk8(ni * G)), dim3(256), 0, st, ni, C.d_rp, C.d_ci, C.d_vals,
-                     x1, x2, j1, j2, z, C.dt, ca, cb, y, y2, C.nrhs);
+                     x1, x2, j1, j2, z, C.dt, ca, cb, y, y2, C.nrhs, skip);
 }
 
 template <int G, int NB>
 static void csr_coop_mode(Ctx& C, hipStream_t st, int mode, const double* x1, const double* x2, const double* j1,
-                          const double* j2, const double* z, double ca, double cb, double* y, double* y2) {
+                          const double* j2, const double* z, double ca, double cb, double* y, double* y2,
+                          const int* skip) {
   if (mode == 0)
-    csr_coop_launch<G, NB, 0>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_launch<G, NB, 0>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
   else if (mode == 1)
-    csr_coop_launch<G, NB, 1>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_launch<G, NB, 1>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
   else if (mode == 2)
-    csr_coop_launch<G, NB, 2>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_launch<G, NB, 2>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
   else
-    csr_coop_launch<G, NB, 3>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_launch<G, NB, 3>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
 }
 
 static void csr_launch(Ctx& C, hipStream_t st, int mode, const double* x1, const double* x2, const double* j1,
-                       const double* j2, const double* z, double ca, double cb, double* y, double* y2) {
+                       const double* j2, const double* z, double ca, double cb, double* y, double* y2,
+                       const int* skip = nullptr) {
   const int nr = C.nrhs;
   const int64_t ni = C.P.nint;
   if (nr <= 4)
     hipLaunchKernelGGL(k_csr, dim3(nblk8(ni * nr)), dim3(256), 0, st, mode, ni, C.d_rp, C.d_ci, C.d_vals, x1, x2, j1,
-                       j2, z, C.dt, ca, cb, y, y2, nr);
+                       j2, z, C.dt, ca, cb, y, y2, nr, skip);
   else if (nr <= 8)
-    csr_coop_mode<8, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_mode<8, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
   else if (nr <= 16)
-    csr_coop_mode<16, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_mode<16, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
   else
-    csr_coop_mode<32, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2);
+    csr_coop_mode<32, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+}
+
+
+// The refined solve of a step as one captured graph (x = A^-1 b, b and x
+// internal buffers): |b|^2; solve 0; then for each captured sweep k the
+// residual b - A x (FP64), its norm and the check against refine_tol on the
+// device, the correction solve and x += delta, all skipped once the check
+// passes; a last residual and check.  Each solve runs `iters` CG iterations
+// (the kernels return at once after convergence).  One read-back after the
+// graph gives the norms, the checks and every solve's CG state.  The
+// graph replaces C.step_graph.
+template <class T>
+static void capture_step(Ctx& C, const double* b, double* x, double* tx, int iters, int sweeps) {
+  hipStream_t st = C.st;
+  const int nr = C.nrhs;
+  const int64_t n = C.P.nint * nr;
+  const double ca = C.beta * C.dt * C.dt, cb = (2 * C.beta - 1) * C.dt * C.dt;
+  int it_dummy[kMaxRhs];
+  double rr_dummy[kMaxRhs];
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    int* gate = reinterpret_cast<int*>(reinterpret_cast<char*>(C.d_rs) + offsetof(RefineState, gate));
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.P.nint, b, b, nr, C.d_rpart,
+                       (const int*)nullptr);
+    hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_rpart, C.d_rs);
+    dd_solve_once<T>(C, b, x, nullptr, it_dummy, rr_dummy, gate, iters, 0);
+    for (int k = 1; k <= sweeps + 1; ++k) {
+      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx, gate + (k - 1));
+      hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.P.nint, (const double*)C.g_r,
+                         (const double*)C.g_r, nr, C.d_rpart, (const int*)(gate + (k - 1)));
+      hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(kScalarThreads), 0, st, k, nr, (const double*)C.d_rpart,
+                         C.opt.refine_tol, C.d_rs, C.d_cg);
+      if (k > sweeps) break;
+      dd_solve_once<T>(C, C.g_r, C.g_t4, nullptr, it_dummy, rr_dummy, gate + k, iters, k);
+      hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t4, x,
+                         (const int*)(gate + k));
+    }
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(st, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamEndCapture(st, &g));
+  hipError_t e = hipGraphInstantiate(&C.step_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(e);
+  C.step_iters = iters;
+  C.step_sweeps = sweeps;
 }
 
 // A^-1 b with iterative refinement in the mixed form.  b, x: [nint][nrhs].
@@ -1728,54 +1835,121 @@ static void csr_launch(Ctx& C, hipStream_t st, int mode, const double* x1, const
 // (from its last residual) and *tx_done is set; otherwise *tx_done = false.
 template <class T>
 static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd_stats* stats,
-                         const char* what = "b", double* tx = nullptr, bool* tx_done = nullptr) {
+                         const char* what = "b", double* tx = nullptr, bool* tx_done = nullptr,
+                         bool step = false) {
   const int nr = C.nrhs;
   const int64_t n = C.P.nint * nr;
   hipStream_t st = C.st;
-  int iters[kMaxRhs];
-  double relres[kMaxRhs];
-  if (tx_done) *tx_done = false;
-  // |b|^2 per RHS before the solve: the reference of the refinement, and a
-  // non-finite load is reported instead of being iterated on
-  double bn[kMaxRhs];
-  dot_to_host(C, b, b, C.P.nint, bn);
-  for (int r = 0; r < nr; ++r)
-    if (!std::isfinite(bn[r]))
-      throw DDError{DD_ERR_NONFINITE, std::string("non-finite entry in the load of right-hand side ") +
-                                          std::to_string(r) + " (" + what + ")"};
-  int status = dd_solve_once<T>(C, b, x, warm, iters, relres);
+  const double ca = C.beta * C.dt * C.dt, cb = (2 * C.beta - 1) * C.dt * C.dt;
+  int iters[kMaxRhs] = {0};
+  double relres[kMaxRhs] = {0};
   int solve_iters[4] = {0, 0, 0, 0};
-  for (int r = 0; r < nr; ++r) solve_iters[0] = std::max(solve_iters[0], iters[r]);
   int sweeps = 0;
   double gres[kMaxRhs] = {0};
-  if (C.fp32 && C.opt.refine_max > 0) {
-    if (tx_done) *tx_done = tx != nullptr;
-    for (;;) {
-      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, C.beta * C.dt * C.dt, (2 * C.beta - 1) * C.dt * C.dt,
-                 C.g_r, tx);
+  double bn[kMaxRhs];
+  int status = DD_OK;
+  bool ok = false;  // the refinement residual is below refine_tol for every RHS
+  auto nonfinite = [&](const double* v) {
+    for (int r = 0; r < nr; ++r)
+      if (!std::isfinite(v[r]))
+        throw DDError{DD_ERR_NONFINITE, std::string("non-finite entry in the load of right-hand side ") +
+                                            std::to_string(r) + " (" + what + ")"};
+  };
+  const bool refine = C.fp32 && C.opt.refine_max > 0;
+  if (tx_done) *tx_done = refine && tx != nullptr;
+  // The step as one captured graph once an eager step has shown how many CG
+  // iterations and sweeps it needs (first variant, no warm start, a
+  // capturable stream, no per-launch timing)
+  const bool graph = step && refine && !warm && C.opt.method == 0 && C.nlam > 0 && C.opt.use_graph &&
+                     st != nullptr && !C.prof && C.need_iters > 0;
+  if (graph) {
+    const int I = std::min(C.opt.cg_max_iter, C.need_iters);
+    const int S = std::min({C.need_sweeps, C.opt.refine_max, kMaxGraphSweeps});
+    if (!C.step_graph || C.step_iters != I || C.step_sweeps != S) {
+      if (C.step_graph) HIPCHK(hipGraphExecDestroy(C.step_graph));
+      C.step_graph = nullptr;
+      capture_step<T>(C, b, x, tx, I, S);
+    }
+    HIPCHK(hipGraphLaunch(C.step_graph, st));
+    HIPCHK(hipMemcpyAsync(C.h_rs, C.d_rs, sizeof(RefineState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const RefineState& R = *C.h_rs;
+    for (int r = 0; r < nr; ++r) bn[r] = R.bn[r];
+    nonfinite(bn);
+    int need_it = 0;
+    bool capped = false;
+    for (int k = 0; k <= S; ++k) {
+      if (!R.ran[k]) break;
+      if (k > 0) ++sweeps;
+      for (int r = 0; r < nr; ++r) {
+        iters[r] += R.iters[k][r];
+        relres[r] = R.rr0[k][r] > 0 ? std::sqrt(R.rr[k][r] / R.rr0[k][r]) : 0.0;
+        need_it = std::max(need_it, R.iters[k][r]);
+        if (k < 4) solve_iters[k] = std::max(solve_iters[k], R.iters[k][r]);
+      }
+      if (R.breakdown[k]) status = DD_ERR_NO_CONVERGENCE;
+      if (!R.done[k]) capped = true;  // stopped at I iterations: the refinement carries on
+    }
+    for (int k = S; k >= 0; --k)
+      if (R.checked[k]) {
+        for (int r = 0; r < nr; ++r) gres[r] = R.gres[k][r];
+        break;
+      }
+    ok = R.gate[S + 1] != 0;
+    C.need_iters = capped ? std::min(C.opt.cg_max_iter, 2 * I) : std::max(need_it, 1);
+    // g_r holds b - A x of the last iterate whenever the last check failed
+  } else {
+    // |b|^2 per RHS before the solve: the reference of the refinement, and a
+    // non-finite load is reported instead of being iterated on
+    dot_to_host(C, b, b, C.P.nint, bn);
+    nonfinite(bn);
+    status = dd_solve_once<T>(C, b, x, warm, iters, relres);
+    for (int r = 0; r < nr; ++r) solve_iters[0] = std::max(solve_iters[0], iters[r]);
+    if (refine) {
+      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx);
       double rn[kMaxRhs];
       dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
-      bool ok = true;
+      ok = true;
       for (int r = 0; r < nr; ++r) {
         gres[r] = bn[r] > 0 ? std::sqrt(rn[r] / bn[r]) : 0.0;
         if (!(gres[r] <= C.opt.refine_tol)) ok = false;
       }
-      if (ok) break;
-      if (sweeps >= C.opt.refine_max) {
-        status = DD_ERR_NO_CONVERGENCE;
-        break;
-      }
-      int it2[kMaxRhs];
-      double rr2[kMaxRhs];
-      int s2 = dd_solve_once<T>(C, C.g_r, C.g_t4, nullptr, it2, rr2);
-      if (s2 != DD_OK) status = s2;
-      for (int r = 0; r < nr; ++r) {
-        iters[r] += it2[r];
-        if (sweeps + 1 < 4) solve_iters[sweeps + 1] = std::max(solve_iters[sweeps + 1], it2[r]);
-      }
-      hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t4, x);
-      ++sweeps;
     }
+  }
+  // eager sweeps: all of them without the graph, those beyond it with it
+  while (refine && !ok) {
+    if (sweeps >= C.opt.refine_max) {
+      status = DD_ERR_NO_CONVERGENCE;
+      break;
+    }
+    int it2[kMaxRhs];
+    double rr2[kMaxRhs];
+    int s2 = dd_solve_once<T>(C, C.g_r, C.g_t4, nullptr, it2, rr2);
+    if (s2 != DD_OK) status = s2;
+    for (int r = 0; r < nr; ++r) {
+      iters[r] += it2[r];
+      if (sweeps + 1 < 4) solve_iters[sweeps + 1] = std::max(solve_iters[sweeps + 1], it2[r]);
+    }
+    hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t4, x,
+                       (const int*)nullptr);
+    ++sweeps;
+    csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx);
+    double rn[kMaxRhs];
+    dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
+    ok = true;
+    for (int r = 0; r < nr; ++r) {
+      gres[r] = bn[r] > 0 ? std::sqrt(rn[r] / bn[r]) : 0.0;
+      if (!(gres[r] <= C.opt.refine_tol)) ok = false;
+    }
+  }
+  if (step && refine) {
+    // what the captured form of the next step must hold
+    if (!graph) {
+      int m = 1;
+      for (int k = 0; k < 4; ++k) m = std::max(m, solve_iters[k]);
+      C.need_iters = m;
+    }
+    C.need_sweeps = sweeps;
   }
   if (stats) {
     std::memset(stats, 0, sizeof(dd_stats));
@@ -1827,31 +2001,27 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
   const bool gauss = (C.opt.diagnostics & DD_DIAG_GAUSS) != 0;
   bool have_tx = false;
   int status = solve_refined<T>(C, C.g_b, C.g_e, C.opt.warm_start ? &C.warm_fw : nullptr, stats,
-                                "J, E_n or E_nm1", gauss ? C.g_t2 : nullptr, &have_tx);
+                                "J, E_n or E_nm1", gauss ? C.g_t2 : nullptr, &have_tx, true);
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
                      Enext, nr, 0, 1.0);
   if (gauss) {
-    // q^{n+1} = q^n + dt G^T J^{n+1/2}, then max |G^T T e^{n+1} + q^{n+1}|
-    hipLaunchKernelGGL(k_charge, dim3(nblk(C.P.nv * nr)), dim3(256), 0, st, (int64_t)C.P.nv, C.d_vptr, C.d_vedge,
-                       C.d_nodeint, J1, ne, C.dt, C.d_q, nr);
+    // q^{n+1} = q^n + dt G^T J^{n+1/2}, with max |G^T T e^{n+1} + q^{n+1}|
+    // when the stats are asked for (T e^{n+1} from the last refinement
+    // residual, or its own product in the FP64 form)
+    // (g_t3 still holds J^{n+1/2} per unknown, converted for the load)
+    if (stats && !have_tx) csr_launch(C, st, 3, C.g_e, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_r);
+    hipLaunchKernelGGL(k_gauss_step, dim3(kGaussBlocks), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
+                       C.d_vedge, C.d_nodeint, C.d_dof, (const double*)C.g_t3, C.dt,
+                       stats ? (const double*)C.g_t2 : nullptr, C.d_q, stats ? C.d_gmax : nullptr);
     if (stats) {
-      if (!have_tx)
-        csr_launch(C, st, 3, C.g_e, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_t3);
-      hipLaunchKernelGGL(k_gauss_max, dim3(kGaussBlocks, nr), dim3(256), 0, st, (int64_t)C.P.nv, C.d_vptr,
-                         C.d_vedge, C.d_nodeint, C.d_dof, (const double*)C.g_t2, (const double*)C.d_q, nr,
-                         C.d_gmax);
-      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * kGaussBlocks * nr * 2, hipMemcpyDeviceToHost,
-                            st));
+      hipLaunchKernelGGL(k_gauss_reduce, dim3(1), dim3(256), 0, st, nr, (const double*)C.d_gmax,
+                         C.d_gmax + (size_t)kGaussBlocks * kMaxRhs * 2);
+      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax + (size_t)kGaussBlocks * kMaxRhs * 2, sizeof(double) * nr * 2,
+                            hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       for (int r = 0; r < nr; ++r) {
-        double g = 0.0, qm = 0.0;
-        for (int b = 0; b < kGaussBlocks; ++b) {
-          const double gb = C.h_partial[(r * kGaussBlocks + b) * 2], qb = C.h_partial[(r * kGaussBlocks + b) * 2 + 1];
-          g = (gb != gb || g != g) ? NAN : std::max(g, gb);
-          qm = std::max(qm, qb);
-        }
-        stats->gauss_residual[r] = g;
-        stats->charge_max[r] = qm;
+        stats->gauss_residual[r] = C.h_partial[2 * r];
+        stats->charge_max[r] = C.h_partial[2 * r + 1];
       }
     }
   }
@@ -1940,12 +2110,8 @@ static void rebuild_lists(Ctx& C, int which) {
     it = make_items(C, blk, chunk, grouped, bucket);
     it.mlist = ml;
   };
-  if (C.cg_graph) {
-    HIPCHK(hipStreamSynchronize(C.st));
-    HIPCHK(hipGraphExecDestroy(C.cg_graph));
-    C.cg_graph = nullptr;
-  }
   HIPCHK(hipStreamSynchronize(C.st));
+  drop_graphs(C);
   if (which & 1) {
     remake(C.trail_N, C.blk_trail_N, C.tuning.chunk, false, 1);
     remake(C.trail_T, C.blk_trail_T, C.tuning.chunk, false, 1);
@@ -2008,12 +2174,15 @@ static bool tune_cache_read(const std::string& path, const std::string& key, Tun
     Tuning c;
     long v[4] = {json_int(line, "chunk"), json_int(line, "coarse_chunk"), json_int(line, "full_chunk"),
                  json_int(line, "full_bucket")};
+    const long fp = json_int(line, "full_persist");
     if (v[0] < 1 || v[1] < 1 || v[2] < 1 || v[3] < 1 || v[0] > 4096 || v[1] > 4096 || v[2] > 4096 || v[3] > 4096)
       continue;
     c.chunk = (int)v[0];
     c.coarse_chunk = (int)v[1];
     c.full_chunk = (int)v[2];
     c.full_bucket = (int)v[3];
+    // a persistent grid must be a multiple of 8 workgroups (absent or bad: none)
+    c.full_persist = (fp > 0 && fp % 8 == 0 && fp <= (1L << 24)) ? (int)fp : 0;
     t = c;
     found = true;  // the last entry for a key wins
   }
@@ -2027,10 +2196,11 @@ static void tune_cache_append(const std::string& path, const std::string& key, c
   if (!f) throw DDError{DD_ERR_ARG, "cannot open the tuning cache " + path + " for writing"};
   std::fprintf(f,
                "{\"key\": \"%s\", \"chunk\": %d, \"coarse_chunk\": %d, \"full_chunk\": %d, "
-               "\"full_bucket\": %d, \"full_ms\": %.5f, \"full_ms_default\": %.5f, \"coarse_ms\": %.5f, "
-               "\"coarse_ms_default\": %.5f, \"trailing_ms\": %.5f, \"trailing_ms_default\": %.5f}\n",
-               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, r.full_ms, r.full_ms_default,
-               r.coarse_ms, r.coarse_ms_default, r.trailing_ms, r.trailing_ms_default);
+               "\"full_bucket\": %d, \"full_persist\": %d, \"full_ms\": %.5f, \"full_ms_default\": %.5f, "
+               "\"coarse_ms\": %.5f, \"coarse_ms_default\": %.5f, \"trailing_ms\": %.5f, "
+               "\"trailing_ms_default\": %.5f}\n",
+               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, t.full_persist, r.full_ms,
+               r.full_ms_default, r.coarse_ms, r.coarse_ms_default, r.trailing_ms, r.trailing_ms_default);
   std::fclose(f);
 }
 
@@ -2099,6 +2269,18 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   }
   C.tuning = best;
   rebuild_lists<T>(C, 4);
+  // then a persistent grid for the chosen full lists
+  if (C.full_N.d) {
+    for (int pg : {1024, 2048, 4096, 8192}) {
+      C.tuning.full_persist = pg;
+      const double t = timed(full);
+      if (t < r.full_ms) {
+        r.full_ms = t;
+        best.full_persist = pg;
+      }
+    }
+    C.tuning = best;
+  }
   if (C.Kc > 0 && C.coarse_lists) {
     r.coarse_ms_default = r.coarse_ms = timed(coarse);
     for (int cc : {8, 12, 16, 24, 32, 48}) {
@@ -2130,6 +2312,7 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   r.coarse_chunk = best.coarse_chunk;
   r.full_chunk = best.full_chunk;
   r.full_bucket = best.full_bucket;
+  r.full_persist = best.full_persist;
   if (out) *out = r;
 }
 
@@ -2147,6 +2330,7 @@ static void autotune(Ctx& C, const char* cache, dd_tuning* out) {
     r.coarse_chunk = t.coarse_chunk;
     r.full_chunk = t.full_chunk;
     r.full_bucket = t.full_bucket;
+    r.full_persist = t.full_persist;
     r.from_cache = 1;
   } else {
     autotune_impl<T>(C, &r);
@@ -2751,10 +2935,7 @@ int dd_set_charge(void* ctx, const double* q) {
   Ctx& C = *(Ctx*)ctx;
   API_BEGIN
   const int64_t n = C.P.nv * C.nrhs;
-  if (q)
-    HIPCHK(hipMemcpyAsync(C.d_q, q, n * sizeof(double), hipMemcpyDeviceToDevice, C.st));
-  else
-    hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, C.st, n, 0.0, C.d_q);
+  hipLaunchKernelGGL(k_charge_set, dim3(nblk(n)), dim3(256), 0, C.st, (int64_t)C.P.nv, C.nrhs, q, C.d_q);
   HIPCHK(hipGetLastError());
   return DD_OK;
   API_END

@@ -509,173 +509,181 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
                                                  const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int64_t wi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wi >= n_items) return;
-  const MvItem w = items[wi];
-  if (w.s < 0) return;  // padding item
-  const SubDev q = subs[w.s];
-  const int l = threadIdx.x & 63;
-  const int g = l >> 4, i = l & 15;
-  const T* xbase = in + q.row_off * nrhs;
-  constexpr bool MF = NV == 0;
-  constexpr int NA = MF ? 2 * NB16 : 2 * NV;
-  // accumulators: vector path acc[mb*NV + r]; MFMA path acc[mb*NB16 + nb]
-  typename Mfma<T>::acc_t macc[MF ? 2 * NB16 : 1];
-  T vacc[MF ? 1 : NA];
-  if constexpr (MF) {
-#pragma unroll
-    for (int a = 0; a < 2 * NB16; ++a) macc[a] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  } else {
-#pragma unroll
-    for (int a = 0; a < NA; ++a) vacc[a] = 0;
-  }
-  // factor values of the current / next tile, and (prefetched together with
-  // them) the input values the lane needs: MFMA path bv[nb][ks] = x[8g+ks][nb*16+i],
-  // vector path (NV <= 2) x[8g+ks][r]; wider vector paths load x inline
-  constexpr bool PX = MF || NV <= 2;
-  constexpr int NX = PX ? 8 * (MF ? NB16 : NV) : 1;
-  T cur[16], nxt[16], xc[NX], xn[NX];
-  auto tile_ptr = [&](int m) -> const T* {
-    const int ti = trans ? m : w.o, tj = trans ? w.o : m;
-    return tiles + tile_index(q, ti, tj) * kTile;
-  };
-  // Loads are unconditional (clamped to an in-bounds column, then zeroed
-  // by a select): a masked load compiles to a branch whose other arm waits
-  // for every load in flight, prefetches included.
-  auto load_x = [&](int m, T* xv) {
-    const T* xb = xbase + (int64_t)m * kNB * nrhs;
+  // Work groups of 4 items (one per wave); workgroup b takes groups b,
+  // b + gridDim.x, ...: one pass over the list with as many workgroups as
+  // groups, or a persistent grid (a multiple of 8, so that every group a
+  // workgroup takes was placed on that workgroup's XCD).  No workgroup
+  // barriers: the waves of a workgroup are independent.
+  const int64_t ngroups = (n_items + 3) / 4;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t wi = grp * 4 + (threadIdx.x >> 6);
+    if (wi >= n_items) continue;
+    const MvItem w = items[wi];
+    if (w.s < 0) continue;  // padding item
+    const SubDev q = subs[w.s];
+    const int l = threadIdx.x & 63;
+    const int g = l >> 4, i = l & 15;
+    const T* xbase = in + q.row_off * nrhs;
+    constexpr bool MF = NV == 0;
+    constexpr int NA = MF ? 2 * NB16 : 2 * NV;
+    // accumulators: vector path acc[mb*NV + r]; MFMA path acc[mb*NB16 + nb]
+    typename Mfma<T>::acc_t macc[MF ? 2 * NB16 : 1];
+    T vacc[MF ? 1 : NA];
     if constexpr (MF) {
 #pragma unroll
-      for (int nb = 0; nb < NB16; ++nb) {
-        const int col = nb * 16 + i;
-        const int cc = col < nrhs ? col : nrhs - 1;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-          const T v = xb[(8 * g + ks) * nrhs + cc];
-          xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
-        }
-      }
-    } else if constexpr (PX) {
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-        for (int r = 0; r < NV; ++r) {
-          const T v = xb[(8 * g + ks) * nrhs + (r < nrhs ? r : nrhs - 1)];
-          xv[ks * NV + r] = r < nrhs ? v : (T)0;
-        }
-    }
-  };
-  auto mof = [&](int k) -> int { return mlist ? mlist[k] : k; };
-  if (w.lo < w.hi) {
-    const int m0 = mof(w.lo);
-    const T* tp = tile_ptr(m0);
-    load_chunk8(tp, l, cur);
-    load_chunk8(tp + 512, l, cur + 8);
-    load_x(m0, xc);
-  }
-  for (int k = w.lo; k < w.hi; ++k) {
-    const int m = mof(k);
-    if (k + 1 < w.hi) {
-      const int m1 = mof(k + 1);
-      const T* tp = tile_ptr(m1);
-      load_chunk8(tp, l, nxt);
-      load_chunk8(tp + 512, l, nxt + 8);
-      load_x(m1, xn);
-    }
-    if constexpr (MF) {
-#pragma unroll
-      for (int nb = 0; nb < NB16; ++nb) {
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-          macc[nb] = Mfma<T>::op(cur[ks], xc[nb * 8 + ks], macc[nb]);
-          macc[NB16 + nb] = Mfma<T>::op(cur[8 + ks], xc[nb * 8 + ks], macc[NB16 + nb]);
-        }
-      }
-    } else if constexpr (PX) {
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks)
-#pragma unroll
-        for (int r = 0; r < NV; ++r) {
-          vacc[r] += cur[ks] * xc[ks * NV + r];
-          vacc[NV + r] += cur[8 + ks] * xc[ks * NV + r];
-        }
+      for (int a = 0; a < 2 * NB16; ++a) macc[a] = typename Mfma<T>::acc_t{0, 0, 0, 0};
     } else {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) vacc[a] = 0;
+    }
+    // factor values of the current / next tile, and (prefetched together with
+    // them) the input values the lane needs: MFMA path bv[nb][ks] = x[8g+ks][nb*16+i],
+    // vector path (NV <= 2) x[8g+ks][r]; wider vector paths load x inline
+    constexpr bool PX = MF || NV <= 2;
+    constexpr int NX = PX ? 8 * (MF ? NB16 : NV) : 1;
+    T cur[16], nxt[16], xc[NX], xn[NX];
+    auto tile_ptr = [&](int m) -> const T* {
+      const int ti = trans ? m : w.o, tj = trans ? w.o : m;
+      return tiles + tile_index(q, ti, tj) * kTile;
+    };
+    // Loads are unconditional (clamped to an in-bounds column, then zeroed
+    // by a select): a masked load compiles to a branch whose other arm waits
+    // for every load in flight, prefetches included.
+    auto load_x = [&](int m, T* xv) {
       const T* xb = xbase + (int64_t)m * kNB * nrhs;
+      if constexpr (MF) {
 #pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        const T* xr = xb + (8 * g + ks) * nrhs;
+        for (int nb = 0; nb < NB16; ++nb) {
+          const int col = nb * 16 + i;
+          const int cc = col < nrhs ? col : nrhs - 1;
 #pragma unroll
-        for (int r = 0; r < NV; ++r) {
-          if (r < nrhs) {
-            const T xv = xr[r];
-            vacc[r] += cur[ks] * xv;
-            vacc[NV + r] += cur[8 + ks] * xv;
+          for (int ks = 0; ks < 8; ++ks) {
+            const T v = xb[(8 * g + ks) * nrhs + cc];
+            xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
+          }
+        }
+      } else if constexpr (PX) {
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+          for (int r = 0; r < NV; ++r) {
+            const T v = xb[(8 * g + ks) * nrhs + (r < nrhs ? r : nrhs - 1)];
+            xv[ks * NV + r] = r < nrhs ? v : (T)0;
+          }
+      }
+    };
+    auto mof = [&](int k) -> int { return mlist ? mlist[k] : k; };
+    if (w.lo < w.hi) {
+      const int m0 = mof(w.lo);
+      const T* tp = tile_ptr(m0);
+      load_chunk8(tp, l, cur);
+      load_chunk8(tp + 512, l, cur + 8);
+      load_x(m0, xc);
+    }
+    for (int k = w.lo; k < w.hi; ++k) {
+      const int m = mof(k);
+      if (k + 1 < w.hi) {
+        const int m1 = mof(k + 1);
+        const T* tp = tile_ptr(m1);
+        load_chunk8(tp, l, nxt);
+        load_chunk8(tp + 512, l, nxt + 8);
+        load_x(m1, xn);
+      }
+      if constexpr (MF) {
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb) {
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            macc[nb] = Mfma<T>::op(cur[ks], xc[nb * 8 + ks], macc[nb]);
+            macc[NB16 + nb] = Mfma<T>::op(cur[8 + ks], xc[nb * 8 + ks], macc[NB16 + nb]);
+          }
+        }
+      } else if constexpr (PX) {
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+          for (int r = 0; r < NV; ++r) {
+            vacc[r] += cur[ks] * xc[ks * NV + r];
+            vacc[NV + r] += cur[8 + ks] * xc[ks * NV + r];
+          }
+      } else {
+        const T* xb = xbase + (int64_t)m * kNB * nrhs;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          const T* xr = xb + (8 * g + ks) * nrhs;
+#pragma unroll
+          for (int r = 0; r < NV; ++r) {
+            if (r < nrhs) {
+              const T xv = xr[r];
+              vacc[r] += cur[ks] * xv;
+              vacc[NV + r] += cur[8 + ks] * xv;
+            }
           }
         }
       }
-    }
-    if (k + 1 < w.hi) {
+      if (k + 1 < w.hi) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
-      if constexpr (PX) {
+        for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+        if constexpr (PX) {
 #pragma unroll
-        for (int u = 0; u < NX; ++u) xc[u] = xn[u];
+          for (int u = 0; u < NX; ++u) xc[u] = xn[u];
+        }
       }
     }
-  }
-  // ---- epilogue ------------------------------------------------------------
-  T* dst;
-  const T* adp = nullptr;
-  T scale;
-  if (w.slot < 0) {
-    // corner output rows (o >= kr) take their own alpha / add
-    const bool crow = w.o >= q.kI + q.kG;
-    const T* ad = crow ? add_c : add;
-    dst = out + (q.row_off + (int64_t)w.o * kNB) * nrhs;
-    if (ad) adp = ad + (q.row_off + (int64_t)w.o * kNB) * nrhs;
-    scale = crow ? alpha_c : alpha;
-  } else {
-    dst = partial + (int64_t)w.slot * kNB * nrhs;
-    scale = (T)1;
-  }
-  if constexpr (MF) {
+    // ---- epilogue ------------------------------------------------------------
+    T* dst;
+    const T* adp = nullptr;
+    T scale;
+    if (w.slot < 0) {
+      // corner output rows (o >= kr) take their own alpha / add
+      const bool crow = w.o >= q.kI + q.kG;
+      const T* ad = crow ? add_c : add;
+      dst = out + (q.row_off + (int64_t)w.o * kNB) * nrhs;
+      if (ad) adp = ad + (q.row_off + (int64_t)w.o * kNB) * nrhs;
+      scale = crow ? alpha_c : alpha;
+    } else {
+      dst = partial + (int64_t)w.slot * kNB * nrhs;
+      scale = (T)1;
+    }
+    if constexpr (MF) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+      for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int nb = 0; nb < NB16; ++nb) {
-        const int col = nb * 16 + i;
-        if (col < nrhs) {
+        for (int nb = 0; nb < NB16; ++nb) {
+          const int col = nb * 16 + i;
+          if (col < nrhs) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = mb * 16 + Mfma<T>::row(l, v);
-            const int64_t o = (int64_t)row * nrhs + col;
-            T val = scale * macc[mb * NB16 + nb][v];
+            for (int v = 0; v < 4; ++v) {
+              const int row = mb * 16 + Mfma<T>::row(l, v);
+              const int64_t o = (int64_t)row * nrhs + col;
+              T val = scale * macc[mb * NB16 + nb][v];
+              if (adp) val += adp[o];
+              dst[o] = val;
+            }
+          }
+        }
+    } else {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        T v = vacc[a];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        vacc[a] = v;
+      }
+      // lane group g writes right-hand sides r with r % 4 == g
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+          if (r < nrhs && (r & 3) == g) {
+            const int64_t o = (int64_t)(mb * 16 + i) * nrhs + r;
+            T val = scale * vacc[mb * NV + r];
             if (adp) val += adp[o];
             dst[o] = val;
           }
         }
-      }
-  } else {
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      T v = vacc[a];
-      v += __shfl_xor(v, 16);
-      v += __shfl_xor(v, 32);
-      vacc[a] = v;
     }
-    // lane group g writes right-hand sides r with r % 4 == g
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < NV; ++r) {
-        if (r < nrhs && (r & 3) == g) {
-          const int64_t o = (int64_t)(mb * 16 + i) * nrhs + r;
-          T val = scale * vacc[mb * NV + r];
-          if (adp) val += adp[o];
-          dst[o] = val;
-        }
-      }
-  }
+  }  // groups
 }
 
 // --------------------------------------------------------------------------
@@ -973,7 +981,9 @@ __global__ void __launch_bounds__(256) k_pack_tiles(int64_t ntiles, T* __restric
 // (src[row] = unknown id if this subdomain owns it, else -1).
 template <class T>
 __global__ void k_split(int64_t rows, const int32_t* __restrict__ src, const double* __restrict__ b,
-                        T* __restrict__ w, int nrhs) {
+                        T* __restrict__ w, int nrhs,
+                        const int* __restrict__ skip) {
+  if (skip && *skip) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows * nrhs) return;
   int64_t row = i / nrhs;
@@ -1047,7 +1057,8 @@ __global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, co
 // Global FP64 result of unknown d = the owner's copy (dsrc[d] = row).
 template <class T>
 __global__ void k_collect(int64_t nint, const int64_t* __restrict__ dsrc, const T* __restrict__ x,
-                          double* __restrict__ e, int nrhs) {
+                          double* __restrict__ e, int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nint * nrhs) return;
   int64_t d = i / nrhs;
@@ -1132,7 +1143,9 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
                                              const double* __restrict__ x1, const double* __restrict__ x2,
                                              const double* __restrict__ j1, const double* __restrict__ j2,
                                              const double* __restrict__ z, double dt, double ca, double cb,
-                                             double* __restrict__ y, double* __restrict__ y2, int nrhs) {
+                                             double* __restrict__ y, double* __restrict__ y2, int nrhs,
+                                             const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t i = xcd_contiguous_block() * blockDim.x + threadIdx.x;
   if (i >= nint * nrhs) return;
   const int64_t row = i / nrhs;
@@ -1215,8 +1228,10 @@ __global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* _
                                                   const double* __restrict__ x1, const double* __restrict__ x2,
                                                   const double* __restrict__ j1, const double* __restrict__ j2,
                                                   const double* __restrict__ z, double dt, double ca, double cb,
-                                                  double* __restrict__ y, double* __restrict__ y2, int nrhs) {
+                                                  double* __restrict__ y, double* __restrict__ y2, int nrhs,
+                                                  const int* __restrict__ skip) {
   static_assert(G == 8 || G == 16 || G == 32, "lanes per row");
+  if (skip && *skip) return;
   static_assert(NB % 4 == 0, "index reads of four");
   constexpr int E = (NB + G - 1) / G;  // staged nonzeros per lane
   constexpr int ROWS = 256 / G;         // rows per workgroup
@@ -1434,7 +1449,9 @@ struct CgState {
 constexpr int kScalarThreads = 1024;
 __global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrhs, const double* __restrict__ partial,
                                                               const double* __restrict__ partial_b,
-                                                              CgState* __restrict__ st, double tol) {
+                                                              CgState* __restrict__ st, double tol,
+                                                              const int* __restrict__ gate) {
+  if (gate && *gate) return;
   if (stage != 0 && st->done) return;
   const int r = threadIdx.x;
   __shared__ int any_active;
@@ -1460,6 +1477,7 @@ __global__ void __launch_bounds__(kScalarThreads) k_cg_scalar(int stage, int nrh
   };
   const double s = total(partial);
   const double sb = stage == 2 ? total(partial_b) : 0.0;
+  if (stage == 0 && r == 0) st->breakdown = 0;  // stage 0 resets the whole state
   if (r < nrhs) {
     if (stage == 0) {
       st->rr[r] = s;
@@ -1651,9 +1669,27 @@ __global__ void k_extrap(int64_t n, const double* __restrict__ a, const double* 
   if (i < n) y[i] = 2.0 * a[i] - b[i];
 }
 
-__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+__global__ void k_axpy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y,
+                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] += a * x[i];
+}
+
+// y = x, and a typed zero fill, both gated (used in place of memcpy /
+// memset so that a captured step can skip them)
+__global__ void k_copy(int64_t n, const double* __restrict__ x, double* __restrict__ y,
+                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
+}
+
+template <class T>
+__global__ void k_zero(int64_t n, T* __restrict__ y, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)0;
 }
 
 __global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
@@ -1752,51 +1788,190 @@ __global__ void k_gauss(int64_t nv, const int64_t* __restrict__ vptr, const int3
 }
 
 
-// Per-RHS maxima over vertices of |G^T (T e) + q| (interior vertices) and of
-// |q|, for the per-step check: grid (kGaussBlocks, nrhs); block (b, r)
-// strides over vertices v = b, b + kGaussBlocks*256, ... and writes its two
-// maxima to out[(r * kGaussBlocks + b) * 2 + {0, 1}].  Tx is [nint][nrhs],
-// q is [nrhs][nv].
-constexpr int kGaussBlocks = 64;
-__global__ void __launch_bounds__(256) k_gauss_max(int64_t nv, const int64_t* __restrict__ vptr,
-                                                   const int32_t* __restrict__ vedge,
-                                                   const uint8_t* __restrict__ node_int,
-                                                   const int32_t* __restrict__ dof, const double* __restrict__ Tx,
-                                                   const double* __restrict__ q, int nrhs, double* __restrict__ out) {
-  const int r = blockIdx.y;
+// Per-step Gauss check (Sec. IV-B): the charge update q += dt G^T J^{n+1/2}
+// and the maxima over vertices of |G^T (T e^{n+1}) + q| (interior vertices)
+// and |q|, in one pass over the vertex-edge lists.  Thread (v, r) =
+// (t / nrhs, t % nrhs) of a workgroup of bs = 256 - 256 % nrhs threads
+// (whole vertices, the right-hand sides of a vertex in neighbouring lanes:
+// shared edge lists, contiguous J, Tx and q rows); workgroups stride over
+// vertices.  J and Tx are per unknown [nint][nrhs] (Tx nullptr: charge
+// update only), q [nv][nrhs].  Block b writes its maxima to
+// out[(b * nrhs + r) * 2 + {0, 1}]; k_gauss_reduce folds the blocks.
+constexpr int kGaussBlocks = 1024;
+__device__ __forceinline__ double nan_max(double a, double b) {
+  return (a != a || b != b) ? NAN : fmax(a, b);
+}
+
+__global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const int64_t* __restrict__ vptr,
+                                                    const int32_t* __restrict__ vedge,
+                                                    const uint8_t* __restrict__ node_int,
+                                                    const int32_t* __restrict__ dof, const double* __restrict__ J,
+                                                    double dt, const double* __restrict__ Tx,
+                                                    double* __restrict__ q, double* __restrict__ out) {
+  const int bs = 256 - 256 % nrhs, vpb = bs / nrhs;
+  const int t = threadIdx.x, r = t % nrhs;
   double mres = 0.0, mq = 0.0;
-  for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)kGaussBlocks * 256) {
-    const double qv = q[(int64_t)r * nv + v];
-    mq = fmax(mq, fabs(qv));
-    if (!node_int[v]) continue;
-    double s = 0.0;
-    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
-      const int32_t code = vedge[k];
-      const int32_t d = dof[code >> 1];
-      if (d >= 0) s += (code & 1 ? -1.0 : 1.0) * Tx[(int64_t)d * nrhs + r];
+  if (t < bs) {
+    for (int64_t v = (int64_t)blockIdx.x * vpb + t / nrhs; v < nv; v += (int64_t)gridDim.x * vpb) {
+      if (!node_int[v]) continue;  // the charge of boundary vertices stays 0
+      double sj = 0.0, st = 0.0;
+      for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+        const int32_t code = vedge[k];
+        const int32_t e = code >> 1;
+        const double sg = (code & 1) ? -1.0 : 1.0;
+        const int32_t d = dof[e];
+        if (d < 0) continue;  // (the lists hold unknowns only)
+        sj += sg * J[(int64_t)d * nrhs + r];
+        if (Tx) st += sg * Tx[(int64_t)d * nrhs + r];
+      }
+      const int64_t o = v * nrhs + r;
+      const double qn = q[o] + dt * sj;
+      q[o] = qn;
+      mq = fmax(mq, fabs(qn));
+      mres = nan_max(mres, fabs(st + qn));
     }
-    const double g = s + qv;
-    // a NaN residual stays visible in the maximum
-    if (g != g)
-      mres = g;
-    else if (mres == mres)
-      mres = fmax(mres, fabs(g));
   }
+  if (!out) return;
   __shared__ double red[2][256];
-  red[0][threadIdx.x] = mres;
-  red[1][threadIdx.x] = mq;
+  red[0][t] = mres;
+  red[1][t] = mq;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      const double a = red[0][threadIdx.x], b = red[0][threadIdx.x + w];
-      red[0][threadIdx.x] = (a != a) ? a : ((b != b) ? b : fmax(a, b));
-      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+  if (t < nrhs) {
+    double a = red[0][t], b = red[1][t];
+    for (int u = t + nrhs; u < bs; u += nrhs) {
+      a = nan_max(a, red[0][u]);
+      b = fmax(b, red[1][u]);
+    }
+    out[((int64_t)blockIdx.x * nrhs + t) * 2] = a;
+    out[((int64_t)blockIdx.x * nrhs + t) * 2 + 1] = b;
+  }
+}
+
+// Fold the kGaussBlocks per-block maxima into out[r * 2 + {0, 1}].
+__global__ void __launch_bounds__(256) k_gauss_reduce(int nrhs, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+  __shared__ double red[2][256];
+  for (int r = 0; r < nrhs; ++r) {
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < kGaussBlocks; k += 256) {
+      a = nan_max(a, part[((int64_t)k * nrhs + r) * 2]);
+      b = fmax(b, part[((int64_t)k * nrhs + r) * 2 + 1]);
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        red[0][threadIdx.x] = nan_max(red[0][threadIdx.x], red[0][threadIdx.x + w]);
+        red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      out[r * 2] = red[0][0];
+      out[r * 2 + 1] = red[1][0];
     }
     __syncthreads();
   }
+}
+
+// q [nv][nrhs] <- src [nrhs][nv] (or 0 with src == nullptr)
+__global__ void k_charge_set(int64_t nv, int nrhs, const double* __restrict__ src, double* __restrict__ q) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv * nrhs) return;
+  const int64_t v = i / nrhs;
+  const int r = (int)(i % nrhs);
+  q[i] = src ? src[(int64_t)r * nv + v] : 0.0;
+}
+
+// --------------------------------------------------------------------------
+// Device-side bookkeeping of a captured refined step (FP32 factors, FP64
+// refinement): the initial |b|^2, the relative residual after every solve,
+// the gates that skip the sweeps no longer needed, and a snapshot of each
+// solve's CG state, read back once after the step.
+// --------------------------------------------------------------------------
+constexpr int kMaxGraphSweeps = 4;
+struct RefineState {
+  double bn[kMaxRhs];                              // |b|^2 per RHS
+  double gres[kMaxGraphSweeps + 1][kMaxRhs];       // |b - A x| / |b| after solves 0..S
+  int gate[kMaxGraphSweeps + 2];                   // gate[k] = 1: sweep k (and all after) skipped
+  int checked[kMaxGraphSweeps + 1];                // gres[k] was computed
+  int ran[kMaxGraphSweeps + 1];                    // solve k ran
+  int iters[kMaxGraphSweeps + 1][kMaxRhs];
+  double rr[kMaxGraphSweeps + 1][kMaxRhs], rr0[kMaxGraphSweeps + 1][kMaxRhs];
+  int done[kMaxGraphSweeps + 1], breakdown[kMaxGraphSweeps + 1];
+};
+
+// fixed-order sum of the kDotBlocks partials of rhs r ([kDotBlocks][kMaxRhs])
+__device__ double partial_total(const double* __restrict__ pa, int nrhs, double* part) {
+  const int t = threadIdx.x, lpr = blockDim.x / nrhs, rr = t % nrhs, ln = t / nrhs;
+  double a = 0.0;
+  if (ln < lpr)
+    for (int b = ln; b < kDotBlocks; b += lpr) a += pa[b * kMaxRhs + rr];
+  part[t] = a;
+  __syncthreads();
+  double v = 0.0;
+  if (t < nrhs)
+    for (int l = 0; l < lpr; ++l) v += part[l * nrhs + t];
+  __syncthreads();
+  return v;
+}
+
+// clear the state; bn from the partials of b . b; gate[0] = 0
+__global__ void __launch_bounds__(kScalarThreads) k_refine_init(int nrhs, const double* __restrict__ partial,
+                                                                RefineState* __restrict__ rs) {
+  __shared__ double part[kScalarThreads];
+  int* w = reinterpret_cast<int*>(rs);
+  for (size_t k = threadIdx.x; k < sizeof(RefineState) / sizeof(int); k += blockDim.x) w[k] = 0;
+  __syncthreads();
+  const double s = partial_total(partial, nrhs, part);
+  if ((int)threadIdx.x < nrhs) rs->bn[threadIdx.x] = s;
+}
+
+// after solve k-1 (k >= 1): gres[k-1] = |r| / |b| from the partials of r . r,
+// gate[k] = 1 when every RHS meets tol (the CG state is then marked done, so
+// the gated solve's CG kernels return at once); a closed gate stays closed
+__global__ void __launch_bounds__(kScalarThreads) k_refine_check(int k, int nrhs, const double* __restrict__ partial,
+                                                                 double tol, RefineState* __restrict__ rs,
+                                                                 CgState* __restrict__ cg) {
+  __shared__ double part[kScalarThreads];
+  __shared__ int all_ok;
+  if (rs->gate[k - 1]) {
+    if (threadIdx.x == 0) rs->gate[k] = 1;
+    return;
+  }
+  if (threadIdx.x == 0) all_ok = 1;
+  __syncthreads();
+  const double s = partial_total(partial, nrhs, part);
+  const int r = threadIdx.x;
+  if (r < nrhs) {
+    const double bn = rs->bn[r];
+    const double g = bn > 0.0 ? sqrt(s / bn) : 0.0;
+    rs->gres[k - 1][r] = g;
+    if (!(g <= tol)) atomicAnd(&all_ok, 0);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    out[((int64_t)r * kGaussBlocks + blockIdx.x) * 2] = red[0][0];
-    out[((int64_t)r * kGaussBlocks + blockIdx.x) * 2 + 1] = red[1][0];
+    rs->checked[k - 1] = 1;
+    rs->gate[k] = all_ok;
+    if (all_ok) cg->done = 1;
+  }
+}
+
+// snapshot of solve k's CG state (skipped with the solve)
+__global__ void k_cg_snapshot(int k, int nrhs, const CgState* __restrict__ cg, RefineState* __restrict__ rs,
+                              const int* __restrict__ gate) {
+  if (gate && *gate) return;
+  const int r = threadIdx.x;
+  if (r < nrhs) {
+    rs->iters[k][r] = cg->iters[r];
+    rs->rr[k][r] = cg->rr[r];
+    rs->rr0[k][r] = cg->rr0[r];
+  }
+  if (r == 0) {
+    rs->ran[k] = 1;
+    rs->done[k] = cg->done;
+    rs->breakdown[k] = cg->breakdown;
   }
 }
 

@@ -333,6 +333,43 @@ def test_graph_replay_matches_eager():
     assert out[True][1] == out[False][1]
 
 
+def test_captured_step_adapts_its_budget():
+    """The refined step as one captured graph: sized by the previous step's
+    CG iterations and sweeps, so a step that needs more than the capture
+    holds (here: zero sources first, capture sized for 1 iteration and no
+    sweep, then a pulse) finishes its refinement eagerly and re-sizes the
+    next capture.  Every step against the oracle; the captured steps of a
+    steady run give the same fields bit for bit as eager launches."""
+    c, t, p, eps = _case(8, ("rcb", 3, 5), grade=1.5, eps_seed=13)
+    dt = 0.04
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    N = 9
+    J = dense_random_source(o.d.n_e, ~o.d.pec, N, dt, 0.2, 0.05, seed=43, nrhs=16)
+    J[:3] = 0.0
+    Eo = o.run(J)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = _solver(c, t, p, eps, dt=dt, nrhs=16, precision="fp32_refine", cg_tol=1e-6, use_graph=True,
+                    stream=st)
+        E, iters = _run_dd(s, J)
+    st.synchronize()
+    for k in range(4, N + 1):
+        assert relerr(E[k], Eo[k]).max() <= 1e-8, k
+    assert np.abs(E[:4]).max() == 0.0
+    # steady run: captured (use_graph) and eager steps agree bit for bit
+    J2 = dense_random_source(o.d.n_e, ~o.d.pec, 6, dt, 0.1, 0.05, seed=47, nrhs=16)
+    out = {}
+    for g in (False, True):
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            s = _solver(c, t, p, eps, dt=dt, nrhs=16, precision="fp32_refine", cg_tol=1e-6, use_graph=g,
+                        stream=st)
+            out[g] = _run_dd(s, J2)
+        st.synchronize()
+    assert np.array_equal(out[True][0], out[False][0])
+    assert out[True][1] == out[False][1]
+
+
 @pytest.mark.parametrize("prec,nrhs,tol", [("fp64", 3, 1e-10), ("fp64", 6, 1e-10),
                                            ("fp32_refine", 16, 1e-8), ("fp64", 24, 1e-10)])
 def test_long_rows_centred_mesh(prec, nrhs, tol):

@@ -76,7 +76,8 @@ def test_tuner_search_cache_and_parity(tmp_path):
 
 def test_odd_shapes_from_cache_keep_parity(tmp_path):
     """Short chunks split almost every row into partial slots (reduced in a
-    fixed order), in every product class."""
+    fixed order), in every product class, and a 16-workgroup persistent grid
+    walks all work groups of the full passes."""
     from paper_2204_13254_amd.solver import DDSolver
     c, t, p, eps = _case()
     dt = 0.03
@@ -89,7 +90,7 @@ def test_odd_shapes_from_cache_keep_parity(tmp_path):
     key = json.loads(probe.read_text().splitlines()[0])["key"]
     odd = tmp_path / "odd.jsonl"
     odd.write_text(json.dumps({"key": key, "chunk": 2, "coarse_chunk": 3, "full_chunk": 4,
-                               "full_bucket": 1}) + "\n")
+                               "full_bucket": 1, "full_persist": 16}) + "\n")
     r = s.autotune(odd)
-    assert r["from_cache"] == 1 and (r["chunk"], r["full_chunk"]) == (2, 4)
+    assert r["from_cache"] == 1 and (r["chunk"], r["full_chunk"], r["full_persist"]) == (2, 4, 16)
     assert _err(_steps(s, J), Eo) <= 1e-10
