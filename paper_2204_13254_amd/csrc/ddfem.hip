@@ -219,7 +219,8 @@ struct Ctx {
   uint8_t* d_nodeint = nullptr;
   double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
   double* d_q = nullptr;     // accumulated nodal charge of the per-step check, [nv][nrhs]
-  double* d_gmax = nullptr;  // maxima of the per-step check: [kGaussBlocks][nrhs][2], then [nrhs][2]
+  double* d_gmax = nullptr;  // maxima of the per-step check [nrhs][2] (as bit patterns)
+  int32_t* d_vdof = nullptr; // vertex -> unknowns (d << 1 | tail), the lists of d_vedge
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
   // trail_N: interface rows of Linv_GG (recovery); trail_T: Linv_GG^T with
@@ -843,7 +844,10 @@ static void build_device(Ctx& C, const double* coords) {
     C.d_vres = dalloc<double>(P.nv * C.nrhs, C.owned);
     C.d_q = dalloc<double>(P.nv * C.nrhs, C.owned);
     HIPCHK(hipMemsetAsync(C.d_q, 0, P.nv * C.nrhs * sizeof(double), st));
-    C.d_gmax = dalloc<double>((size_t)(kGaussBlocks + 1) * kMaxRhs * 2, C.owned);
+    C.d_gmax = dalloc<double>((size_t)kMaxRhs * 2, C.owned);
+    std::vector<int32_t> vdof(vedge.size());
+    for (size_t k = 0; k < vedge.size(); ++k) vdof[k] = (P.dof[vedge[k] >> 1] << 1) | (vedge[k] & 1);
+    C.d_vdof = upload(vdof, C.owned, st);
   }
   // ---- work lists --------------------------------------------------------------------
   {
@@ -2010,14 +2014,14 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
     // residual, or its own product in the FP64 form)
     // (g_t3 still holds J^{n+1/2} per unknown, converted for the load)
     if (stats && !have_tx) csr_launch(C, st, 3, C.g_e, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_r);
-    hipLaunchKernelGGL(k_gauss_step, dim3(kGaussBlocks), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
-                       C.d_vedge, C.d_nodeint, C.d_dof, (const double*)C.g_t3, C.dt,
-                       stats ? (const double*)C.g_t2 : nullptr, C.d_q, stats ? C.d_gmax : nullptr);
+    unsigned long long* gmax = stats ? (unsigned long long*)C.d_gmax : nullptr;
+    if (gmax) hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, st, (int64_t)2 * nr, C.d_gmax, (const int*)nullptr);
+    const int vpb = (256 - 256 % nr) / nr;
+    hipLaunchKernelGGL(k_gauss_step, dim3(nblk(C.P.nv, vpb)), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
+                       C.d_vdof, C.d_nodeint, (const double*)C.g_t3, C.dt, stats ? (const double*)C.g_t2 : nullptr,
+                       C.d_q, gmax);
     if (stats) {
-      hipLaunchKernelGGL(k_gauss_reduce, dim3(1), dim3(256), 0, st, nr, (const double*)C.d_gmax,
-                         C.d_gmax + (size_t)kGaussBlocks * kMaxRhs * 2);
-      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax + (size_t)kGaussBlocks * kMaxRhs * 2, sizeof(double) * nr * 2,
-                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * nr * 2, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       for (int r = 0; r < nr; ++r) {
         stats->gauss_residual[r] = C.h_partial[2 * r];

@@ -1790,46 +1790,42 @@ __global__ void k_gauss(int64_t nv, const int64_t* __restrict__ vptr, const int3
 
 // Per-step Gauss check (Sec. IV-B): the charge update q += dt G^T J^{n+1/2}
 // and the maxima over vertices of |G^T (T e^{n+1}) + q| (interior vertices)
-// and |q|, in one pass over the vertex-edge lists.  Thread (v, r) =
-// (t / nrhs, t % nrhs) of a workgroup of bs = 256 - 256 % nrhs threads
-// (whole vertices, the right-hand sides of a vertex in neighbouring lanes:
-// shared edge lists, contiguous J, Tx and q rows); workgroups stride over
-// vertices.  J and Tx are per unknown [nint][nrhs] (Tx nullptr: charge
-// update only), q [nv][nrhs].  Block b writes its maxima to
-// out[(b * nrhs + r) * 2 + {0, 1}]; k_gauss_reduce folds the blocks.
-constexpr int kGaussBlocks = 1024;
+// and |q|.  Thread (v, r) = (t / nrhs, t % nrhs) of a workgroup of bs = 256 -
+// 256 % nrhs threads (whole vertices, the right-hand sides of a vertex in
+// neighbouring lanes: shared lists, contiguous J, Tx and q rows).  vdof
+// lists the unknowns at each vertex (d << 1 | tail).  J and Tx are per
+// unknown [nint][nrhs] (Tx nullptr: charge update only), q [nv][nrhs].  The
+// maxima of a workgroup go to out[r * 2 + {0, 1}] by an integer atomic max
+// on the bit patterns (order-free, exact for non-negative doubles, and a NaN
+// residual wins), so out must be zero before the launch.
 __device__ __forceinline__ double nan_max(double a, double b) {
   return (a != a || b != b) ? NAN : fmax(a, b);
 }
 
 __global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const int64_t* __restrict__ vptr,
-                                                    const int32_t* __restrict__ vedge,
+                                                    const int32_t* __restrict__ vdof,
                                                     const uint8_t* __restrict__ node_int,
-                                                    const int32_t* __restrict__ dof, const double* __restrict__ J,
-                                                    double dt, const double* __restrict__ Tx,
-                                                    double* __restrict__ q, double* __restrict__ out) {
+                                                    const double* __restrict__ J, double dt,
+                                                    const double* __restrict__ Tx, double* __restrict__ q,
+                                                    unsigned long long* __restrict__ out) {
   const int bs = 256 - 256 % nrhs, vpb = bs / nrhs;
   const int t = threadIdx.x, r = t % nrhs;
+  const int64_t v = (int64_t)blockIdx.x * vpb + t / nrhs;
   double mres = 0.0, mq = 0.0;
-  if (t < bs) {
-    for (int64_t v = (int64_t)blockIdx.x * vpb + t / nrhs; v < nv; v += (int64_t)gridDim.x * vpb) {
-      if (!node_int[v]) continue;  // the charge of boundary vertices stays 0
-      double sj = 0.0, st = 0.0;
-      for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
-        const int32_t code = vedge[k];
-        const int32_t e = code >> 1;
-        const double sg = (code & 1) ? -1.0 : 1.0;
-        const int32_t d = dof[e];
-        if (d < 0) continue;  // (the lists hold unknowns only)
-        sj += sg * J[(int64_t)d * nrhs + r];
-        if (Tx) st += sg * Tx[(int64_t)d * nrhs + r];
-      }
-      const int64_t o = v * nrhs + r;
-      const double qn = q[o] + dt * sj;
-      q[o] = qn;
-      mq = fmax(mq, fabs(qn));
-      mres = nan_max(mres, fabs(st + qn));
+  if (t < bs && v < nv && node_int[v]) {  // the charge of boundary vertices stays 0
+    double sj = 0.0, st = 0.0;
+    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
+      const int32_t code = vdof[k];
+      const int64_t d = code >> 1;
+      const double sg = (code & 1) ? -1.0 : 1.0;
+      sj += sg * J[d * nrhs + r];
+      if (Tx) st += sg * Tx[d * nrhs + r];
     }
+    const int64_t o = v * nrhs + r;
+    const double qn = q[o] + dt * sj;
+    q[o] = qn;
+    mq = fabs(qn);
+    mres = fabs(st + qn);
   }
   if (!out) return;
   __shared__ double red[2][256];
@@ -1842,36 +1838,8 @@ __global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const 
       a = nan_max(a, red[0][u]);
       b = fmax(b, red[1][u]);
     }
-    out[((int64_t)blockIdx.x * nrhs + t) * 2] = a;
-    out[((int64_t)blockIdx.x * nrhs + t) * 2 + 1] = b;
-  }
-}
-
-// Fold the kGaussBlocks per-block maxima into out[r * 2 + {0, 1}].
-__global__ void __launch_bounds__(256) k_gauss_reduce(int nrhs, const double* __restrict__ part,
-                                                      double* __restrict__ out) {
-  __shared__ double red[2][256];
-  for (int r = 0; r < nrhs; ++r) {
-    double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < kGaussBlocks; k += 256) {
-      a = nan_max(a, part[((int64_t)k * nrhs + r) * 2]);
-      b = fmax(b, part[((int64_t)k * nrhs + r) * 2 + 1]);
-    }
-    red[0][threadIdx.x] = a;
-    red[1][threadIdx.x] = b;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) {
-        red[0][threadIdx.x] = nan_max(red[0][threadIdx.x], red[0][threadIdx.x + w]);
-        red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + w]);
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      out[r * 2] = red[0][0];
-      out[r * 2 + 1] = red[1][0];
-    }
-    __syncthreads();
+    atomicMax(&out[2 * t], (unsigned long long)__double_as_longlong(a));
+    atomicMax(&out[2 * t + 1], (unsigned long long)__double_as_longlong(b));
   }
 }
 
