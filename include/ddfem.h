@@ -102,6 +102,8 @@ typedef struct {
   int full_bucket;    /* length buckets of the full lists' workgroup placement */
   int full_persist;   /* full passes: workgroups of a persistent grid that walks the work
                          groups (a multiple of 8), or 0 for one workgroup per work group */
+  int full_pair;      /* full passes: 1 = each wave computes two output block rows over the
+                         union of their tile lists, loading each input block once (9..32 RHS) */
   int from_cache;     /* 1: read from the cache, no timing */
   double full_ms, full_ms_default, coarse_ms, coarse_ms_default, trailing_ms, trailing_ms_default;
 } dd_tuning;

@@ -92,6 +92,7 @@ struct Items {
   int64_t n_slots = 0;   // partial slots used (0 = direct writes)
   int32_t* mlist = nullptr;  // tile list (ranges index it), or null for contiguous ranges
   void* partial = nullptr;   // own partial slots (lists that run beside others), or null
+  bool pair = false;         // row-pair items (k_tile_mv2)
 };
 
 // Work-list shapes (longest tile range of one wave per product class, and
@@ -103,6 +104,7 @@ struct Tuning {
   int full_chunk = 96;    // full r-block lists
   int full_bucket = 8;    // length buckets of the full lists' placement
   int full_persist = 0;   // full passes: workgroups of a persistent grid (0: one per work group)
+  int full_pair = 0;      // full passes: two output rows per wave sharing the input loads (9..32 RHS)
 };
 
 struct Ctx {
@@ -137,6 +139,8 @@ struct Ctx {
   // can be rebuilt with other chunk lengths
   std::vector<MvItem> blk_trail_N, blk_trail_T, blk_corner_N, blk_corner_T, blk_co_N, blk_co_T, blk_full_N,
       blk_full_T;
+  std::vector<int32_t> ml_full_N, ml_full_T;  // the full passes' per-row tile lists (host)
+  void* d_zero_tile = nullptr;                // one zero tile (row-pair lists)
   std::vector<uint8_t> full_pattern;  // nonzero-tile flags the full lists were built from
   std::vector<void*> owned;
 
@@ -365,24 +369,27 @@ static Items make_items(Ctx& C, const std::vector<MvItem>& blocks, int chunk, bo
   int32_t slot = 0;
   for (const MvItem& b : blocks) {
     if (!split) {
-      v.push_back({b.s, b.o, b.lo, b.hi, -1, 0});
+      v.push_back({b.s, b.o, b.lo, b.hi, -1, 0, b.o2, -1});
       chunk_of.push_back(0);
       continue;
     }
     int32_t n = std::max(1, (b.hi - b.lo + chunk - 1) / chunk);
     if (n == 1) {
       // a row that fits one wave writes its output directly (no partial)
-      v.push_back({b.s, b.o, b.lo, b.hi, -1, 0});
+      v.push_back({b.s, b.o, b.lo, b.hi, -1, 0, b.o2, -1});
       chunk_of.push_back(0);
       continue;
     }
+    // n partial slots per output block (2n for a row pair: o's, then o2's)
     int32_t oidx = (int32_t)outs.size();
     outs.push_back({b.s, b.o, slot, n});
+    if (b.o2 >= 0) outs.push_back({b.s, b.o2, slot + n, n});
     for (int32_t c = 0; c < n; ++c) {
       int32_t lo = b.lo + c * chunk, hi = std::min(b.hi, lo + chunk);
-      v.push_back({b.s, b.o, lo, std::max(lo, hi), slot++, oidx});
+      v.push_back({b.s, b.o, lo, std::max(lo, hi), slot + c, oidx, b.o2, b.o2 >= 0 ? slot + n + c : -1});
       chunk_of.push_back(c);
     }
+    slot += b.o2 >= 0 ? 2 * n : n;
   }
   if (grouped && split) {
     // chunk-major inside a subdomain, so that neighbouring rows (similar
@@ -1064,6 +1071,58 @@ static void coarse_tile_lists(Ctx& C) {
   ensure_partial<T>(C);
 }
 
+// Work items of the full passes from the per-row tile lists, single rows or
+// row pairs (C.tuning.full_pair, 9..32 RHS): rows 2k and 2k+1 of a subdomain
+// walk the union of their lists, flagged per entry (kPairMask).  At 64^3
+// 96-tile chunks keep every single row in one wave (48 tiles: 1.465 ms per
+// pass, 64: 1.444, 80: 1.432, 96: 1.430, 128: 1.432).
+template <class T>
+static void build_full_items(Ctx& C) {
+  release_items(C, C.full_N);
+  release_items(C, C.full_T);
+  const bool pair = C.tuning.full_pair && C.nrhs > 8;
+  auto make = [&](const std::vector<MvItem>& blk, const std::vector<int32_t>& ml, Items& it) {
+    if (!pair) {
+      it = make_items(C, blk, C.tuning.full_chunk, true, C.tuning.full_bucket);
+      it.mlist = upload(ml, C.owned, C.st);
+      return;
+    }
+    std::vector<int32_t> pl;
+    std::vector<MvItem> pb;
+    for (size_t k = 0; k < blk.size(); ++k) {
+      const MvItem& a = blk[k];
+      const bool has2 = k + 1 < blk.size() && blk[k + 1].s == a.s;
+      const int32_t b0 = (int32_t)pl.size();
+      if (!has2) {
+        for (int32_t e = a.lo; e < a.hi; ++e) pl.push_back(ml[e] | (1 << 29));
+        pb.push_back({a.s, a.o, b0, (int32_t)pl.size(), -1, 0});
+        continue;
+      }
+      const MvItem& b = blk[k + 1];
+      int32_t i = a.lo, j = b.lo;
+      while (i < a.hi || j < b.hi) {  // merge of two ascending lists
+        const int32_t ma = i < a.hi ? ml[i] : INT32_MAX, mb = j < b.hi ? ml[j] : INT32_MAX;
+        const int32_t m = std::min(ma, mb);
+        pl.push_back(m | (ma == m ? 1 << 29 : 0) | (mb == m ? 1 << 30 : 0));
+        if (ma == m) ++i;
+        if (mb == m) ++j;
+      }
+      pb.push_back({a.s, a.o, b0, (int32_t)pl.size(), -1, 0, b.o, -1});
+      ++k;
+    }
+    it = make_items(C, pb, C.tuning.full_chunk, true, C.tuning.full_bucket);
+    it.mlist = upload(pl, C.owned, C.st);
+    it.pair = true;
+  };
+  if (pair && !C.d_zero_tile) {
+    C.d_zero_tile = dalloc<T>(kTile, C.owned);
+    HIPCHK(hipMemsetAsync(C.d_zero_tile, 0, kTile * sizeof(T), C.st));
+  }
+  make(C.blk_full_N, C.ml_full_N, C.full_N);
+  make(C.blk_full_T, C.ml_full_T, C.full_T);
+  ensure_partial<T>(C);
+}
+
 // Lists of the nonzero tiles of the subdomain inverse factors (with the
 // premultiplied corner rows) for the full forward / transposed passes.  The
 // interior nested-dissection order leaves whole tiles of L_II^-1 zero.  The
@@ -1101,20 +1160,13 @@ static void full_tile_lists(Ctx& C) {
   }
   if ((int64_t)ln.size() >= INT32_MAX || (int64_t)lt.size() >= INT32_MAX)
     throw DDError{DD_ERR_OOM, "tile lists exceed 2^31 entries"};
-  release_items(C, C.full_N);
-  release_items(C, C.full_T);
-  // 96-tile chunks: rows of the bench subdomains stay in one wave and write
-  // their outputs directly (at 64^3 per pass: 48 tiles 1.465 ms, 64 1.444,
-  // 80 1.432, 96 1.430, 128 1.432)
-  C.full_N = make_items(C, bn, C.tuning.full_chunk, true, C.tuning.full_bucket);
-  C.full_N.mlist = upload(ln, C.owned, C.st);
-  C.full_T = make_items(C, bt, C.tuning.full_chunk, true, C.tuning.full_bucket);
-  C.full_T.mlist = upload(lt, C.owned, C.st);
   C.blk_full_N.swap(bn);
   C.blk_full_T.swap(bt);
+  C.ml_full_N.swap(ln);
+  C.ml_full_T.swap(lt);
   C.full_bytes = entries * (int64_t)sizeof(T);
   C.full_pattern.swap(pat);
-  ensure_partial<T>(C);
+  build_full_items<T>(C);
 }
 
 template <class T>
@@ -1230,9 +1282,21 @@ static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const 
   // a multiple of 8 too, so each workgroup stays on its groups' XCD
   int64_t grid = (it.n + 3) / 4;
   if (CLS == DD_PROF_FULL && C.tuning.full_persist > 0) grid = std::min<int64_t>(grid, C.tuning.full_persist);
-  hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
-                     C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
-                     (int)trans, partial, (const int32_t*)it.mlist, skip);
+  if constexpr (NV == 0) {
+    if (it.pair) {
+      hipLaunchKernelGGL((k_tile_mv2<T, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d, C.d_subs,
+                         tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
+                         (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
+    } else {
+      hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
+                         C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c,
+                         C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip);
+    }
+  } else {
+    hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
+                       C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c,
+                       C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip);
+  }
   if (split)
     hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, s, it.n_out, it.outs, C.d_subs,
                        (const T*)partial, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs, skip);
@@ -2126,10 +2190,7 @@ static void rebuild_lists(Ctx& C, int which) {
     remake(C.co_N, C.blk_co_N, C.tuning.coarse_chunk, false, 1);
     remake(C.co_T, C.blk_co_T, C.tuning.coarse_chunk, false, 1);
   }
-  if ((which & 4) && C.full_N.d) {
-    remake(C.full_N, C.blk_full_N, C.tuning.full_chunk, true, C.tuning.full_bucket);
-    remake(C.full_T, C.blk_full_T, C.tuning.full_chunk, true, C.tuning.full_bucket);
-  }
+  if ((which & 4) && C.full_N.d) build_full_items<T>(C);
   ensure_partial<T>(C);
 }
 
@@ -2179,7 +2240,9 @@ static bool tune_cache_read(const std::string& path, const std::string& key, Tun
     long v[4] = {json_int(line, "chunk"), json_int(line, "coarse_chunk"), json_int(line, "full_chunk"),
                  json_int(line, "full_bucket")};
     const long fp = json_int(line, "full_persist");
-    if (v[0] < 1 || v[1] < 1 || v[2] < 1 || v[3] < 1 || v[0] > 4096 || v[1] > 4096 || v[2] > 4096 || v[3] > 4096)
+    const long fpair = json_int(line, "full_pair");
+    if (v[0] < 1 || v[1] < 1 || v[2] < 1 || v[3] < 1 || v[0] > 4096 || v[1] > 4096 || v[2] > 4096 ||
+        v[3] > (1 << 20))
       continue;
     c.chunk = (int)v[0];
     c.coarse_chunk = (int)v[1];
@@ -2187,6 +2250,7 @@ static bool tune_cache_read(const std::string& path, const std::string& key, Tun
     c.full_bucket = (int)v[3];
     // a persistent grid must be a multiple of 8 workgroups (absent or bad: none)
     c.full_persist = (fp > 0 && fp % 8 == 0 && fp <= (1L << 24)) ? (int)fp : 0;
+    c.full_pair = fpair == 1 ? 1 : 0;
     t = c;
     found = true;  // the last entry for a key wins
   }
@@ -2200,10 +2264,11 @@ static void tune_cache_append(const std::string& path, const std::string& key, c
   if (!f) throw DDError{DD_ERR_ARG, "cannot open the tuning cache " + path + " for writing"};
   std::fprintf(f,
                "{\"key\": \"%s\", \"chunk\": %d, \"coarse_chunk\": %d, \"full_chunk\": %d, "
-               "\"full_bucket\": %d, \"full_persist\": %d, \"full_ms\": %.5f, \"full_ms_default\": %.5f, "
+               "\"full_bucket\": %d, \"full_persist\": %d, \"full_pair\": %d, \"full_ms\": %.5f, "
+               "\"full_ms_default\": %.5f, "
                "\"coarse_ms\": %.5f, \"coarse_ms_default\": %.5f, \"trailing_ms\": %.5f, "
                "\"trailing_ms_default\": %.5f}\n",
-               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, t.full_persist, r.full_ms,
+               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, t.full_persist, t.full_pair, r.full_ms,
                r.full_ms_default, r.coarse_ms, r.coarse_ms_default, r.trailing_ms, r.trailing_ms_default);
   std::fclose(f);
 }
@@ -2258,8 +2323,10 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   // full passes: chunk length x placement bucket
   if (C.full_N.d) {
     r.full_ms_default = r.full_ms = timed(full);
+    // (bucket 1 << 20: one bucket, so each XCD takes its subdomains one
+    // after the other in the given order, rows in order)
     for (int fc : {48, 64, 96, 128, 192})
-      for (int b : {1, 4, 8, 16}) {
+      for (int b : {1, 4, 8, 16, 1 << 20}) {
         C.tuning.full_chunk = fc;
         C.tuning.full_bucket = b;
         rebuild_lists<T>(C, 4);
@@ -2273,7 +2340,25 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   }
   C.tuning = best;
   rebuild_lists<T>(C, 4);
-  // then a persistent grid for the chosen full lists
+  // row pairs (two output rows per wave), then a persistent grid
+  if (C.full_N.d && C.nrhs > 8) {
+    for (int fc : {32, 48, 64, 96})
+      for (int b : {best.full_bucket, 1 << 20}) {
+        C.tuning.full_pair = 1;
+        C.tuning.full_chunk = fc;
+        C.tuning.full_bucket = b;
+        rebuild_lists<T>(C, 4);
+        const double t = timed(full);
+        if (t < r.full_ms) {
+          r.full_ms = t;
+          best.full_pair = 1;
+          best.full_chunk = fc;
+          best.full_bucket = b;
+        }
+      }
+    C.tuning = best;
+    rebuild_lists<T>(C, 4);
+  }
   if (C.full_N.d) {
     for (int pg : {1024, 2048, 4096, 8192}) {
       C.tuning.full_persist = pg;
@@ -2317,6 +2402,7 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   r.full_chunk = best.full_chunk;
   r.full_bucket = best.full_bucket;
   r.full_persist = best.full_persist;
+  r.full_pair = best.full_pair;
   if (out) *out = r;
 }
 
@@ -2335,6 +2421,7 @@ static void autotune(Ctx& C, const char* cache, dd_tuning* out) {
     r.full_chunk = t.full_chunk;
     r.full_bucket = t.full_bucket;
     r.full_persist = t.full_persist;
+    r.full_pair = t.full_pair;
     r.from_cache = 1;
   } else {
     autotune_impl<T>(C, &r);

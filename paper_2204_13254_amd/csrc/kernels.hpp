@@ -459,7 +459,13 @@ struct MvItem {
   int32_t s, o, lo, hi;  // subdomain, output block, tile range [lo, hi)
   int32_t slot;          // -1: write the output block; else partial slot
   int32_t oidx;          // split items: index of the output block's MvOut
+  int32_t o2 = -1;       // row-pair lists: second output block (-1: none)
+  int32_t slot2 = -1;    // its partial slot (-1: write it directly)
 };
+
+// Row-pair tile lists: entry = m | (tile (o, m) present) << 29 | (tile (o2,
+// m) present) << 30 (for the transposed pass: tiles (m, o) and (m, o2)).
+constexpr int32_t kPairMask = (1 << 29) - 1;
 
 struct MvOut {
   int32_t s, o, slot0, nslot;
@@ -680,6 +686,130 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
             T val = scale * vacc[mb * NV + r];
             if (adp) val += adp[o];
             dst[o] = val;
+          }
+        }
+    }
+  }  // groups
+}
+
+// Row-pair form of k_tile_mv for the full passes (MFMA path, 9..32 RHS):
+// one wave computes the output blocks o and o2 of one subdomain over the
+// union of their tile lists, so each input block is loaded once for both
+// rows (the input loads cost about as much as a tile's own once they are
+// not shared).  An entry's absent tile is read from `zero`, one zero tile
+// (cached after its first use).  Split items write partial slots w.slot
+// (block o) and w.slot2 (block o2), as k_tile_mv does.
+template <class T, int NB16, int CLS>
+__global__ void __launch_bounds__(256) k_tile_mv2(int64_t n_items, const MvItem* __restrict__ items,
+                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
+                                                  const T* __restrict__ in, T* __restrict__ out,
+                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
+                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
+                                                  const int32_t* __restrict__ mlist, const int* __restrict__ skip,
+                                                  const T* __restrict__ zero) {
+  if (skip && *skip) return;
+  const int64_t ngroups = (n_items + 3) / 4;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t wi = grp * 4 + (threadIdx.x >> 6);
+    if (wi >= n_items) continue;
+    const MvItem w = items[wi];
+    if (w.s < 0) continue;  // padding item
+    const SubDev q = subs[w.s];
+    const int l = threadIdx.x & 63;
+    const int g = l >> 4, i = l & 15;
+    const T* xbase = in + q.row_off * nrhs;
+    const bool two = w.o2 >= 0;
+    using acc_t = typename Mfma<T>::acc_t;
+    acc_t acc[2][2 * NB16];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int a = 0; a < 2 * NB16; ++a) acc[p][a] = acc_t{0, 0, 0, 0};
+    // tiles of the current / next entry for both rows, and the input block
+    T cur[2][16], nxt[2][16], xc[8 * NB16], xn[8 * NB16];
+    auto tptr = [&](int o, int m, bool present) -> const T* {
+      if (!present) return zero;
+      const int ti = trans ? m : o, tj = trans ? o : m;
+      return tiles + tile_index(q, ti, tj) * kTile;
+    };
+    auto load_x = [&](int m, T* xv) {
+      const T* xb = xbase + (int64_t)m * kNB * nrhs;
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb) {
+        const int col = nb * 16 + i;
+        const int cc = col < nrhs ? col : nrhs - 1;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+          const T v = xb[(8 * g + ks) * nrhs + cc];
+          xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
+        }
+      }
+    };
+    auto load_entry = [&](int k, T (&t)[2][16], T* xv) {
+      const int32_t e = mlist[k];
+      const int m = e & kPairMask;
+      const T* pa = tptr(w.o, m, (e >> 29) & 1);
+      const T* pb = tptr(two ? w.o2 : w.o, m, two && ((e >> 30) & 1));
+      load_chunk8(pa, l, t[0]);
+      load_chunk8(pa + 512, l, t[0] + 8);
+      load_chunk8(pb, l, t[1]);
+      load_chunk8(pb + 512, l, t[1] + 8);
+      load_x(m, xv);
+    };
+    if (w.lo < w.hi) load_entry(w.lo, cur, xc);
+    for (int k = w.lo; k < w.hi; ++k) {
+      if (k + 1 < w.hi) load_entry(k + 1, nxt, xn);
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            acc[p][nb] = Mfma<T>::op(cur[p][ks], xc[nb * 8 + ks], acc[p][nb]);
+            acc[p][NB16 + nb] = Mfma<T>::op(cur[p][8 + ks], xc[nb * 8 + ks], acc[p][NB16 + nb]);
+          }
+      if (k + 1 < w.hi) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int u = 0; u < 16; ++u) cur[p][u] = nxt[p][u];
+#pragma unroll
+        for (int u = 0; u < 8 * NB16; ++u) xc[u] = xn[u];
+      }
+    }
+    // ---- epilogue: both output blocks ------------------------------------
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p == 1 && !two) break;
+      const int o = p ? w.o2 : w.o;
+      const int slot = p ? w.slot2 : w.slot;
+      T* dst;
+      const T* adp = nullptr;
+      T scale;
+      if (slot < 0) {
+        const bool crow = o >= q.kI + q.kG;
+        const T* ad = crow ? add_c : add;
+        dst = out + (q.row_off + (int64_t)o * kNB) * nrhs;
+        if (ad) adp = ad + (q.row_off + (int64_t)o * kNB) * nrhs;
+        scale = crow ? alpha_c : alpha;
+      } else {
+        dst = partial + (int64_t)slot * kNB * nrhs;
+        scale = (T)1;
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb) {
+          const int col = nb * 16 + i;
+          if (col < nrhs) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = mb * 16 + Mfma<T>::row(l, v);
+              const int64_t oo = (int64_t)row * nrhs + col;
+              T val = scale * acc[p][mb * NB16 + nb][v];
+              if (adp) val += adp[oo];
+              dst[oo] = val;
+            }
           }
         }
     }

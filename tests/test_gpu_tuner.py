@@ -94,3 +94,27 @@ def test_odd_shapes_from_cache_keep_parity(tmp_path):
     r = s.autotune(odd)
     assert r["from_cache"] == 1 and (r["chunk"], r["full_chunk"], r["full_persist"]) == (2, 4, 16)
     assert _err(_steps(s, J), Eo) <= 1e-10
+
+
+@pytest.mark.parametrize("chunk", [3, 96])
+def test_row_pair_full_passes(tmp_path, chunk):
+    """Two output rows per wave over the union of their tile lists (absent
+    tiles read from a zero tile), split into 3-entry chunks or whole, with
+    16 and 24 right-hand sides (one and two 16-wide MFMA blocks)."""
+    from paper_2204_13254_amd.solver import DDSolver
+    c, t, p, eps = _case()
+    dt = 0.03
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    for nrhs, prec, tol in ((16, "fp32_refine", 1e-8), (24, "fp64", 1e-10)):
+        J = dense_random_source(o.d.n_e, ~o.d.pec, 3, dt, 0.05, 0.03, seed=13, nrhs=nrhs)
+        Eo = o.run(J)
+        s = DDSolver(c, t, p, eps, dt=dt, precision=prec, nrhs=nrhs, cg_tol=1e-6 if prec != "fp64" else 1e-12)
+        probe = tmp_path / f"probe{nrhs}.jsonl"
+        s.autotune(probe)
+        key = json.loads(probe.read_text().splitlines()[0])["key"]
+        f = tmp_path / f"pair{nrhs}.jsonl"
+        f.write_text(json.dumps({"key": key, "chunk": 32, "coarse_chunk": 16, "full_chunk": chunk,
+                                 "full_bucket": 8, "full_pair": 1}) + "\n")
+        r = s.autotune(f)
+        assert r["full_pair"] == 1
+        assert _err(_steps(s, J), Eo) <= tol, (nrhs, chunk)
