@@ -102,8 +102,11 @@ typedef struct {
   int full_bucket;    /* length buckets of the full lists' workgroup placement */
   int full_persist;   /* full passes: workgroups of a persistent grid that walks the work
                          groups (a multiple of 8), or 0 for one workgroup per work group */
-  int full_pair;      /* full passes: 1 = each wave computes two output block rows over the
-                         union of their tile lists, loading each input block once (9..32 RHS) */
+  int full_pair;      /* full passes, 9..32 RHS: 1 = each wave computes two output block rows
+                         over the union of their tile lists, loading each input block once;
+                         2 = eight rows per workgroup, the input block shared through LDS */
+  int full_quarter;   /* full passes: 1 = the lanes of all-zero 16 x 16 quarters of a tile
+                         read a cached zero tile instead of memory */
   int from_cache;     /* 1: read from the cache, no timing */
   double full_ms, full_ms_default, coarse_ms, coarse_ms_default, trailing_ms, trailing_ms_default;
 } dd_tuning;

@@ -28,7 +28,7 @@ class Options(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("chunk", C.c_int), ("coarse_chunk", C.c_int), ("full_chunk", C.c_int),
                 ("full_bucket", C.c_int), ("full_persist", C.c_int), ("full_pair", C.c_int),
-                ("from_cache", C.c_int),
+                ("full_quarter", C.c_int), ("from_cache", C.c_int),
                 ("full_ms", C.c_double),
                 ("full_ms_default", C.c_double), ("coarse_ms", C.c_double), ("coarse_ms_default", C.c_double),
                 ("trailing_ms", C.c_double), ("trailing_ms_default", C.c_double)]

@@ -93,6 +93,7 @@ struct Items {
   int32_t* mlist = nullptr;  // tile list (ranges index it), or null for contiguous ranges
   void* partial = nullptr;   // own partial slots (lists that run beside others), or null
   bool pair = false;         // row-pair items (k_tile_mv2)
+  bool oct = false;          // row-octet workgroup items (k_tile_mv8)
 };
 
 // Work-list shapes (longest tile range of one wave per product class, and
@@ -104,7 +105,9 @@ struct Tuning {
   int full_chunk = 96;    // full r-block lists
   int full_bucket = 8;    // length buckets of the full lists' placement
   int full_persist = 0;   // full passes: workgroups of a persistent grid (0: one per work group)
-  int full_pair = 0;      // full passes: two output rows per wave sharing the input loads (9..32 RHS)
+  int full_pair = 0;      // full passes, 9..32 RHS: 1 = two output rows per wave sharing the input
+                          // loads; 2 = eight rows per workgroup sharing them through LDS
+  int full_quarter = 1;   // full passes: lanes of all-zero 16 x 16 tile quarters read the zero tile
 };
 
 struct Ctx {
@@ -319,7 +322,7 @@ constexpr int kWavesPerGroup = 4;
 
 template <class It, class SubF, class LenF>
 static std::vector<It> place_xcd(int nsub, const std::vector<It>& v, const It& pad, SubF sub, LenF len,
-                                 int bucket = 1) {
+                                 int bucket = 1, int per_group = kWavesPerGroup) {
   // XCD assignment: subdomains by greedy load; the coarse block (a single
   // "subdomain" holding many items, with small shared inputs) round-robin
   std::vector<int64_t> load_s(nsub + 1, 0);
@@ -346,14 +349,14 @@ static std::vector<It> place_xcd(int nsub, const std::vector<It>& v, const It& p
   // within an XCD: longest first
   for (auto& L : lists) {
     std::stable_sort(L.begin(), L.end(), [&](const It& a, const It& b) { return len(a) / bucket > len(b) / bucket; });
-    groups = std::max(groups, (L.size() + kWavesPerGroup - 1) / kWavesPerGroup);
+    groups = std::max(groups, (L.size() + per_group - 1) / per_group);
   }
-  std::vector<It> placed(groups * kXcds * kWavesPerGroup, pad);
+  std::vector<It> placed(groups * kXcds * per_group, pad);
   for (size_t g = 0; g < groups; ++g)
     for (int x = 0; x < kXcds; ++x)
-      for (int w = 0; w < kWavesPerGroup; ++w) {
-        size_t k = g * kWavesPerGroup + w;
-        if (k < lists[x].size()) placed[(g * kXcds + x) * kWavesPerGroup + w] = lists[x][k];
+      for (int w = 0; w < per_group; ++w) {
+        size_t k = g * per_group + w;
+        if (k < lists[x].size()) placed[(g * kXcds + x) * per_group + w] = lists[x][k];
       }
   if (v.empty()) placed.clear();
   return placed;
@@ -994,13 +997,18 @@ static void factor_range(Ctx& C, int s0, int cnt) {
 
 // nonzero count of every tile in [t0, t0 + n) of the factor store
 template <class T>
-static std::vector<int32_t> tile_nnz(Ctx& C, int64_t t0, int64_t n) {
+// (and, with qmask, the nonzero 16 x 16 quarters of every tile, operand order)
+static std::vector<int32_t> tile_nnz(Ctx& C, int64_t t0, int64_t n, std::vector<int32_t>* qmask = nullptr) {
   std::vector<int32_t> nnz(n);
+  if (qmask) qmask->assign(n, 0);
   if (n == 0) return nnz;
   int32_t* d_nnz = nullptr;
-  HIPCHK(hipMalloc((void**)&d_nnz, n * sizeof(int32_t)));
-  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)n), dim3(256), 0, C.st, t0, n, (const T*)C.d_tiles, d_nnz);
+  HIPCHK(hipMalloc((void**)&d_nnz, 2 * n * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)n), dim3(256), 0, C.st, t0, n, (const T*)C.d_tiles, d_nnz,
+                     qmask ? d_nnz + n : (int32_t*)nullptr);
   HIPCHK(hipMemcpyAsync(nnz.data(), d_nnz, n * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
+  if (qmask)
+    HIPCHK(hipMemcpyAsync(qmask->data(), d_nnz + n, n * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
   HIPCHK(hipStreamSynchronize(C.st));
   HIPCHK(hipFree(d_nnz));
   return nnz;
@@ -1081,7 +1089,52 @@ static void build_full_items(Ctx& C) {
   release_items(C, C.full_N);
   release_items(C, C.full_T);
   const bool pair = C.tuning.full_pair && C.nrhs > 8;
-  auto make = [&](const std::vector<MvItem>& blk, const std::vector<int32_t>& ml, Items& it) {
+  const bool oct = pair && C.tuning.full_pair == 2;
+  auto make_oct = [&](const std::vector<MvItem>& blk, const std::vector<int32_t>& ml, Items& it) {
+    std::vector<int32_t> ol;
+    std::vector<MvItem> ob;
+    for (size_t k = 0; k < blk.size();) {
+      size_t n = 1;
+      while (n < 8 && k + n < blk.size() && blk[k + n].s == blk[k].s) ++n;
+      std::vector<int32_t> pos(n);
+      for (size_t j = 0; j < n; ++j) pos[j] = blk[k + j].lo;
+      const int32_t b0 = (int32_t)ol.size();
+      for (;;) {  // merge of n ascending lists, one flag bit per row
+        int32_t m = INT32_MAX;
+        for (size_t j = 0; j < n; ++j)
+          if (pos[j] < blk[k + j].hi) m = std::min(m, ml[pos[j]] & kListMask);
+        if (m == INT32_MAX) break;
+        int32_t e = m;
+        for (size_t j = 0; j < n; ++j)
+          if (pos[j] < blk[k + j].hi && (ml[pos[j]] & kListMask) == m) {
+            e |= 1 << (23 + j);
+            ++pos[j];
+          }
+        ol.push_back(e);
+      }
+      ob.push_back({blk[k].s, blk[k].o, b0, (int32_t)ol.size(), -1, 0, (int32_t)n, -1});
+      k += n;
+    }
+    std::vector<MvItem> placed = place_xcd(
+        C.nsub, ob, MvItem{-1, 0, 0, 0, -1, 0}, [](const MvItem& a) { return a.s; },
+        [](const MvItem& a) { return (int64_t)(a.hi - a.lo); }, C.tuning.full_bucket, 1);
+    it.n = (int64_t)placed.size();
+    it.d = upload(placed, C.owned, C.st);
+    it.mlist = upload(ol, C.owned, C.st);
+    it.oct = true;
+  };
+  auto make = [&](const std::vector<MvItem>& blk, const std::vector<int32_t>& ml_all, Items& it) {
+    // zero-quarter flags only when the tuning asks for them
+    std::vector<int32_t> stripped;
+    if (!C.tuning.full_quarter) {
+      stripped.resize(ml_all.size());
+      for (size_t k = 0; k < ml_all.size(); ++k) stripped[k] = ml_all[k] & kListMask;
+    }
+    const std::vector<int32_t>& ml = C.tuning.full_quarter ? ml_all : stripped;
+    if (oct) {
+      make_oct(blk, ml, it);
+      return;
+    }
     if (!pair) {
       it = make_items(C, blk, C.tuning.full_chunk, true, C.tuning.full_bucket);
       it.mlist = upload(ml, C.owned, C.st);
@@ -1093,17 +1146,23 @@ static void build_full_items(Ctx& C) {
       const MvItem& a = blk[k];
       const bool has2 = k + 1 < blk.size() && blk[k + 1].s == a.s;
       const int32_t b0 = (int32_t)pl.size();
+      // single-row entry m | zero quarters << 25 -> pair entry fields
+      auto mm = [&](int32_t e) { return e & kListMask; };
+      auto qz = [&](int32_t e) { return (e >> 25) & 15; };
       if (!has2) {
-        for (int32_t e = a.lo; e < a.hi; ++e) pl.push_back(ml[e] | (1 << 29));
+        for (int32_t e = a.lo; e < a.hi; ++e) pl.push_back(mm(ml[e]) | qz(ml[e]) << 21 | (1 << 29));
         pb.push_back({a.s, a.o, b0, (int32_t)pl.size(), -1, 0});
         continue;
       }
       const MvItem& b = blk[k + 1];
       int32_t i = a.lo, j = b.lo;
       while (i < a.hi || j < b.hi) {  // merge of two ascending lists
-        const int32_t ma = i < a.hi ? ml[i] : INT32_MAX, mb = j < b.hi ? ml[j] : INT32_MAX;
+        const int32_t ma = i < a.hi ? mm(ml[i]) : INT32_MAX, mb = j < b.hi ? mm(ml[j]) : INT32_MAX;
         const int32_t m = std::min(ma, mb);
-        pl.push_back(m | (ma == m ? 1 << 29 : 0) | (mb == m ? 1 << 30 : 0));
+        int32_t e = m;
+        if (ma == m) e |= qz(ml[i]) << 21 | (1 << 29);
+        if (mb == m) e |= qz(ml[j]) << 25 | (1 << 30);
+        pl.push_back(e);
         if (ma == m) ++i;
         if (mb == m) ++j;
       }
@@ -1114,7 +1173,7 @@ static void build_full_items(Ctx& C) {
     it.mlist = upload(pl, C.owned, C.st);
     it.pair = true;
   };
-  if (pair && !C.d_zero_tile) {
+  if (!C.d_zero_tile) {
     C.d_zero_tile = dalloc<T>(kTile, C.owned);
     HIPCHK(hipMemsetAsync(C.d_zero_tile, 0, kTile * sizeof(T), C.st));
   }
@@ -1131,29 +1190,39 @@ static void build_full_items(Ctx& C) {
 template <class T>
 static void full_tile_lists(Ctx& C) {
   const int64_t nt = C.subs_h[C.nsub].tile_off;  // subdomain tiles come first
-  std::vector<int32_t> nnz = tile_nnz<T>(C, 0, nt);
+  std::vector<int32_t> qm;
+  std::vector<int32_t> nnz = tile_nnz<T>(C, 0, nt, &qm);
   std::vector<uint8_t> pat(nt);
-  for (int64_t t = 0; t < nt; ++t) pat[t] = nnz[t] != 0;
+  for (int64_t t = 0; t < nt; ++t) pat[t] = (uint8_t)(nnz[t] != 0 ? 16 | qm[t] : 0);
   if (pat == C.full_pattern && C.full_N.d) return;
+  // zero quarters of a listed tile, in the layout of the store read: the
+  // transposed store swaps the off-diagonal quarters
+  auto zq = [&](int64_t t, bool transposed) -> int32_t {
+    int32_t z = ~qm[t] & 15;
+    if (transposed) z = (z & 9) | ((z & 2) << 1) | ((z & 4) >> 1);
+    return z;
+  };
   std::vector<int32_t> ln, lt;
   std::vector<MvItem> bn, bt;
   int64_t entries = 0;
   for (int s = 0; s < C.nsub; ++s) {
     const SubDev& q = C.subs_h[s];
     const int kr = q.kI + q.kG;
-    auto at = [&](int i, int j) { return nnz[q.tile_off + (int64_t)i * (i + 1) / 2 + j]; };
+    auto tid = [&](int i, int j) { return q.tile_off + (int64_t)i * (i + 1) / 2 + j; };
+    auto at = [&](int i, int j) { return nnz[tid(i, j)]; };
+    if (q.K >= kPairMask) throw DDError{DD_ERR_OOM, "too many tile rows in a subdomain"};
     for (int o = 0; o < q.K; ++o) {
       int32_t b = (int32_t)ln.size();
       for (int j = 0; j <= std::min(o, kr - 1); ++j)
         if (at(o, j)) {
-          ln.push_back(j);
+          ln.push_back(j | zq(tid(o, j), false) << 25);
           entries += at(o, j);
         }
       bn.push_back({s, o, b, (int32_t)ln.size(), -1, 0});
       if (o < kr) {
         b = (int32_t)lt.size();
         for (int i = o; i < q.K; ++i)
-          if (at(i, o)) lt.push_back(i);
+          if (at(i, o)) lt.push_back(i | zq(tid(i, o), true) << 25);
         bt.push_back({s, o, b, (int32_t)lt.size(), -1, 0});
       }
     }
@@ -1283,19 +1352,25 @@ static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const 
   int64_t grid = (it.n + 3) / 4;
   if (CLS == DD_PROF_FULL && C.tuning.full_persist > 0) grid = std::min<int64_t>(grid, C.tuning.full_persist);
   if constexpr (NV == 0) {
-    if (it.pair) {
+    if (it.oct) {
+      int64_t g8 = it.n;  // one workgroup per item (a multiple of 8)
+      if (C.tuning.full_persist > 0) g8 = std::min<int64_t>(g8, C.tuning.full_persist);
+      hipLaunchKernelGGL((k_tile_mv8<T, NB16, CLS>), dim3((unsigned)g8), dim3(256), 0, s, it.n, it.d, C.d_subs,
+                         tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
+                         (int)trans, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
+    } else if (it.pair) {
       hipLaunchKernelGGL((k_tile_mv2<T, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d, C.d_subs,
                          tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
                          (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
     } else {
       hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
                          C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c,
-                         C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip);
+                         C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
     }
   } else {
     hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
                        C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c,
-                       C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip);
+                       C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
   }
   if (split)
     hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)it.n_out), dim3(256), 0, s, it.n_out, it.outs, C.d_subs,
@@ -2250,7 +2325,8 @@ static bool tune_cache_read(const std::string& path, const std::string& key, Tun
     c.full_bucket = (int)v[3];
     // a persistent grid must be a multiple of 8 workgroups (absent or bad: none)
     c.full_persist = (fp > 0 && fp % 8 == 0 && fp <= (1L << 24)) ? (int)fp : 0;
-    c.full_pair = fpair == 1 ? 1 : 0;
+    c.full_pair = (fpair == 1 || fpair == 2) ? (int)fpair : 0;
+    c.full_quarter = json_int(line, "full_quarter") == 0 ? 0 : 1;
     t = c;
     found = true;  // the last entry for a key wins
   }
@@ -2264,11 +2340,13 @@ static void tune_cache_append(const std::string& path, const std::string& key, c
   if (!f) throw DDError{DD_ERR_ARG, "cannot open the tuning cache " + path + " for writing"};
   std::fprintf(f,
                "{\"key\": \"%s\", \"chunk\": %d, \"coarse_chunk\": %d, \"full_chunk\": %d, "
-               "\"full_bucket\": %d, \"full_persist\": %d, \"full_pair\": %d, \"full_ms\": %.5f, "
+               "\"full_bucket\": %d, \"full_persist\": %d, \"full_pair\": %d, \"full_quarter\": %d, "
+               "\"full_ms\": %.5f, "
                "\"full_ms_default\": %.5f, "
                "\"coarse_ms\": %.5f, \"coarse_ms_default\": %.5f, \"trailing_ms\": %.5f, "
                "\"trailing_ms_default\": %.5f}\n",
-               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, t.full_persist, t.full_pair, r.full_ms,
+               key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, t.full_persist, t.full_pair,
+               t.full_quarter, r.full_ms,
                r.full_ms_default, r.coarse_ms, r.coarse_ms_default, r.trailing_ms, r.trailing_ms_default);
   std::fclose(f);
 }
@@ -2340,6 +2418,18 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   }
   C.tuning = best;
   rebuild_lists<T>(C, 4);
+  // reading whole tiles, zero quarters included
+  if (C.full_N.d) {
+    C.tuning.full_quarter = 0;
+    rebuild_lists<T>(C, 4);
+    const double t = timed(full);
+    if (t < r.full_ms) {
+      r.full_ms = t;
+      best.full_quarter = 0;
+    }
+    C.tuning = best;
+    rebuild_lists<T>(C, 4);
+  }
   // row pairs (two output rows per wave), then a persistent grid
   if (C.full_N.d && C.nrhs > 8) {
     for (int fc : {32, 48, 64, 96})
@@ -2356,6 +2446,18 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
           best.full_bucket = b;
         }
       }
+    // eight rows per workgroup (not split; the chunk does not apply)
+    for (int b : {best.full_bucket, 1 << 20}) {
+      C.tuning.full_pair = 2;
+      C.tuning.full_bucket = b;
+      rebuild_lists<T>(C, 4);
+      const double t = timed(full);
+      if (t < r.full_ms) {
+        r.full_ms = t;
+        best.full_pair = 2;
+        best.full_bucket = b;
+      }
+    }
     C.tuning = best;
     rebuild_lists<T>(C, 4);
   }
@@ -2403,6 +2505,7 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   r.full_bucket = best.full_bucket;
   r.full_persist = best.full_persist;
   r.full_pair = best.full_pair;
+  r.full_quarter = best.full_quarter;
   if (out) *out = r;
 }
 
@@ -2422,6 +2525,7 @@ static void autotune(Ctx& C, const char* cache, dd_tuning* out) {
     r.full_bucket = t.full_bucket;
     r.full_persist = t.full_persist;
     r.full_pair = t.full_pair;
+    r.full_quarter = t.full_quarter;
     r.from_cache = 1;
   } else {
     autotune_impl<T>(C, &r);

@@ -463,9 +463,15 @@ struct MvItem {
   int32_t slot2 = -1;    // its partial slot (-1: write it directly)
 };
 
-// Row-pair tile lists: entry = m | (tile (o, m) present) << 29 | (tile (o2,
-// m) present) << 30 (for the transposed pass: tiles (m, o) and (m, o2)).
-constexpr int32_t kPairMask = (1 << 29) - 1;
+// Full-pass tile lists flag the 16 x 16 quarters of a tile that are all
+// zero (bit 2 * row half + column half, the layout of the store read), so
+// that the lanes of such a quarter read the cached zero tile instead of
+// memory.  Single-row lists: entry = m | zero quarters << 25.  Row-pair
+// lists: entry = m | zero quarters of (o, m) << 21 | of (o2, m) << 25 |
+// (tile (o, m) present) << 29 | (tile (o2, m) present) << 30 (transposed
+// pass: tiles (m, o) and (m, o2)).
+constexpr int32_t kListMask = (1 << 25) - 1;
+constexpr int32_t kPairMask = (1 << 21) - 1;
 
 struct MvOut {
   int32_t s, o, slot0, nslot;
@@ -513,7 +519,8 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
-                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip) {
+                                                 const int32_t* __restrict__ mlist, const int* __restrict__ skip,
+                                                 const T* __restrict__ zero) {
   if (skip && *skip) return;
   // Work groups of 4 items (one per wave); workgroup b takes groups b,
   // b + gridDim.x, ...: one pass over the list with as many workgroups as
@@ -578,22 +585,26 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
           }
       }
     };
-    auto mof = [&](int k) -> int { return mlist ? mlist[k] : k; };
+    auto ent = [&](int k) -> int32_t { return mlist ? mlist[k] : k; };
+    // a lane reads the zero tile for the quarters flagged all-zero (lane
+    // group g holds columns 8g..8g+7: column half g / 2)
+    auto load_tile = [&](int32_t e, T* c) {
+      const T* tp = tile_ptr(e & kListMask);
+      const int zq = (e >> 25) & 15, ch = g >> 1;
+      load_chunk8(((zq >> ch) & 1) ? zero : tp, l, c);
+      load_chunk8((((zq >> (2 + ch)) & 1) ? zero : tp) + 512, l, c + 8);
+    };
     if (w.lo < w.hi) {
-      const int m0 = mof(w.lo);
-      const T* tp = tile_ptr(m0);
-      load_chunk8(tp, l, cur);
-      load_chunk8(tp + 512, l, cur + 8);
-      load_x(m0, xc);
+      const int32_t e0 = ent(w.lo);
+      load_tile(e0, cur);
+      load_x(e0 & kListMask, xc);
     }
     for (int k = w.lo; k < w.hi; ++k) {
-      const int m = mof(k);
+      const int m = ent(k) & kListMask;
       if (k + 1 < w.hi) {
-        const int m1 = mof(k + 1);
-        const T* tp = tile_ptr(m1);
-        load_chunk8(tp, l, nxt);
-        load_chunk8(tp + 512, l, nxt + 8);
-        load_x(m1, xn);
+        const int32_t e1 = ent(k + 1);
+        load_tile(e1, nxt);
+        load_x(e1 & kListMask, xn);
       }
       if constexpr (MF) {
 #pragma unroll
@@ -745,15 +756,17 @@ __global__ void __launch_bounds__(256) k_tile_mv2(int64_t n_items, const MvItem*
         }
       }
     };
+    const int ch = g >> 1;  // column half of this lane's values
     auto load_entry = [&](int k, T (&t)[2][16], T* xv) {
       const int32_t e = mlist[k];
       const int m = e & kPairMask;
+      const int za = (e >> 21) & 15, zb = (e >> 25) & 15;
       const T* pa = tptr(w.o, m, (e >> 29) & 1);
       const T* pb = tptr(two ? w.o2 : w.o, m, two && ((e >> 30) & 1));
-      load_chunk8(pa, l, t[0]);
-      load_chunk8(pa + 512, l, t[0] + 8);
-      load_chunk8(pb, l, t[1]);
-      load_chunk8(pb + 512, l, t[1] + 8);
+      load_chunk8(((za >> ch) & 1) ? zero : pa, l, t[0]);
+      load_chunk8((((za >> (2 + ch)) & 1) ? zero : pa) + 512, l, t[0] + 8);
+      load_chunk8(((zb >> ch) & 1) ? zero : pb, l, t[1]);
+      load_chunk8((((zb >> (2 + ch)) & 1) ? zero : pb) + 512, l, t[1] + 8);
       load_x(m, xv);
     };
     if (w.lo < w.hi) load_entry(w.lo, cur, xc);
@@ -814,6 +827,143 @@ __global__ void __launch_bounds__(256) k_tile_mv2(int64_t n_items, const MvItem*
         }
     }
   }  // groups
+}
+
+// Row-octet form for the full passes (MFMA path, 9..32 RHS): a workgroup
+// item covers up to 8 consecutive output rows o .. o + w.o2 - 1 of one
+// subdomain over the union of their tile lists; each entry's input block is
+// staged once in LDS (transposed: a lane's 8 reduction values are
+// contiguous) and used by all four waves, wave v computing rows o + 2v and
+// o + 2v + 1.  Entry = m | (tile of row o + j present) << (23 + j); an absent
+// tile reads `zero`.  Double-buffered LDS, one workgroup barrier per entry;
+// outputs are written directly (octet items are not split).
+constexpr int32_t kOctMask = (1 << 23) - 1;
+template <class T, int NB16, int CLS>
+__global__ void __launch_bounds__(256) k_tile_mv8(int64_t n_items, const MvItem* __restrict__ items,
+                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
+                                                  const T* __restrict__ in, T* __restrict__ out,
+                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
+                                                  T alpha_c, int nrhs, int trans, const int32_t* __restrict__ mlist,
+                                                  const int* __restrict__ skip, const T* __restrict__ zero) {
+  if (skip && *skip) return;
+  constexpr int LP = kNB + 4;            // LDS pitch of one RHS column (16-byte multiple)
+  constexpr int XPER = (kNB * 16 * NB16 + 255) / 256;
+  __shared__ __align__(16) T xs[2][16 * NB16][LP];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+  const int t = threadIdx.x;
+  using acc_t = typename Mfma<T>::acc_t;
+  for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const MvItem w = items[it];
+    if (w.s < 0 || w.lo >= w.hi) continue;  // uniform over the workgroup
+    const SubDev q = subs[w.s];
+    const T* xbase = in + q.row_off * nrhs;
+    const int ra = 2 * wv, rb = 2 * wv + 1;  // this wave's rows within the octet
+    acc_t acc[2][2 * NB16];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int a = 0; a < 2 * NB16; ++a) acc[p][a] = acc_t{0, 0, 0, 0};
+    T cur[2][16], nxt[2][16], xr[XPER];
+    auto tptr = [&](int j, int m, int32_t e) -> const T* {
+      if (j >= w.o2 || !((e >> (23 + j)) & 1)) return zero;
+      const int o = w.o + j;
+      const int ti = trans ? m : o, tj = trans ? o : m;
+      return tiles + tile_index(q, ti, tj) * kTile;
+    };
+    auto load_tiles = [&](int32_t e, T (&c)[2][16]) {
+      const int m = e & kOctMask;
+      const T* pa = tptr(ra, m, e);
+      const T* pb = tptr(rb, m, e);
+      load_chunk8(pa, l, c[0]);
+      load_chunk8(pa + 512, l, c[0] + 8);
+      load_chunk8(pb, l, c[1]);
+      load_chunk8(pb + 512, l, c[1] + 8);
+    };
+    // input block m ([32 rows][nrhs], row-major) -> registers -> LDS [col][row]
+    auto stage_load = [&](int32_t e) {
+      const T* xb = xbase + (int64_t)(e & kOctMask) * kNB * nrhs;
+#pragma unroll
+      for (int j = 0; j < XPER; ++j) {
+        const int idx = t + 256 * j;
+        const int cl = idx < kNB * nrhs ? idx : 0;
+        const T v = xb[cl];
+        xr[j] = idx < kNB * nrhs ? v : (T)0;
+      }
+    };
+    auto stage_store = [&](int buf) {
+#pragma unroll
+      for (int j = 0; j < XPER; ++j) {
+        const int idx = t + 256 * j;
+        if (idx < kNB * nrhs) xs[buf][idx % nrhs][idx / nrhs] = xr[j];
+      }
+    };
+    int32_t e = mlist[w.lo];
+    stage_load(e);
+    load_tiles(e, cur);
+    stage_store(0);
+    __syncthreads();
+    for (int k = w.lo; k < w.hi; ++k) {
+      const int buf = (k - w.lo) & 1;
+      const bool more = k + 1 < w.hi;
+      if (more) {
+        e = mlist[k + 1];
+        stage_load(e);
+        load_tiles(e, nxt);
+      }
+      T xv[8 * NB16];
+#pragma unroll
+      for (int nb = 0; nb < NB16; ++nb) {
+        const int col = nb * 16 + i;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) xv[nb * 8 + ks] = col < nrhs ? xs[buf][col][8 * g + ks] : (T)0;
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            acc[p][nb] = Mfma<T>::op(cur[p][ks], xv[nb * 8 + ks], acc[p][nb]);
+            acc[p][NB16 + nb] = Mfma<T>::op(cur[p][8 + ks], xv[nb * 8 + ks], acc[p][NB16 + nb]);
+          }
+      if (more) stage_store(buf ^ 1);
+      __syncthreads();
+      if (more) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int u = 0; u < 16; ++u) cur[p][u] = nxt[p][u];
+      }
+    }
+    // ---- epilogue: this wave's two rows ----------------------------------
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int j = p ? rb : ra;
+      if (j >= w.o2) continue;
+      const int o = w.o + j;
+      const bool crow = o >= q.kI + q.kG;
+      const T* ad = crow ? add_c : add;
+      T* dst = out + (q.row_off + (int64_t)o * kNB) * nrhs;
+      const T* adp = ad ? ad + (q.row_off + (int64_t)o * kNB) * nrhs : nullptr;
+      const T scale = crow ? alpha_c : alpha;
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb) {
+          const int col = nb * 16 + i;
+          if (col < nrhs) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = mb * 16 + Mfma<T>::row(l, v);
+              const int64_t oo = (int64_t)row * nrhs + col;
+              T val = scale * acc[p][mb * NB16 + nb][v];
+              if (adp) val += adp[oo];
+              dst[oo] = val;
+            }
+          }
+        }
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1028,18 +1178,30 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* _
 // nested-dissection-ordered factor and of its inverse are exact zeros).
 template <class T>
 __global__ void __launch_bounds__(256) k_tile_nnz(int64_t t0, int64_t n, const T* __restrict__ tiles,
-                                                  int32_t* __restrict__ nnz) {
+                                                  int32_t* __restrict__ nnz, int32_t* __restrict__ qmask) {
   const int64_t t = blockIdx.x;
   if (t >= n) return;
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
+  // nonzeros of the tile (operand order), and per 16 x 16 quarter (bit 2 *
+  // row half + column half set when the quarter holds a nonzero)
+  __shared__ int cnt[5];
+  if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
   __syncthreads();
+  constexpr int V = 16 / sizeof(T);
   const T* p = tiles + (t0 + t) * kTile;
-  int c = 0;
-  for (int e = threadIdx.x; e < kTile; e += 256) c += p[e] != (T)0;
-  atomicAdd(&cnt, c);
+  int c[4] = {0, 0, 0, 0};
+  for (int e = threadIdx.x; e < kTile; e += 256) {
+    const int lane = ((e % 512) % (64 * V)) / V;  // lane 16 (c / 8) + r % 16 of swz
+    c[(e / 512) * 2 + (lane >> 5)] += p[e] != (T)0;
+  }
+  for (int q = 0; q < 4; ++q) {
+    atomicAdd(&cnt[q], c[q]);
+    atomicAdd(&cnt[4], c[q]);
+  }
   __syncthreads();
-  if (threadIdx.x == 0) nnz[t] = cnt;
+  if (threadIdx.x == 0) {
+    nnz[t] = cnt[4];
+    if (qmask) qmask[t] = (cnt[0] > 0) | (cnt[1] > 0) << 1 | (cnt[2] > 0) << 2 | (cnt[3] > 0) << 3;
+  }
 }
 
 // Interface block of the local inverse K_rr^-1 = Linv_rr^T Linv_rr (the

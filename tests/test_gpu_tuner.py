@@ -96,11 +96,15 @@ def test_odd_shapes_from_cache_keep_parity(tmp_path):
     assert _err(_steps(s, J), Eo) <= 1e-10
 
 
-@pytest.mark.parametrize("chunk", [3, 96])
-def test_row_pair_full_passes(tmp_path, chunk):
-    """Two output rows per wave over the union of their tile lists (absent
-    tiles read from a zero tile), split into 3-entry chunks or whole, with
-    16 and 24 right-hand sides (one and two 16-wide MFMA blocks)."""
+@pytest.mark.parametrize("pair,chunk,persist,quarter", [(1, 3, 0, 1), (1, 96, 0, 1), (2, 96, 0, 1), (2, 96, 16, 1),
+                                                        (0, 96, 0, 0), (0, 5, 0, 1), (1, 96, 0, 0)])
+def test_row_pair_full_passes(tmp_path, pair, chunk, persist, quarter):
+    """Two output rows per wave (pair 1) or eight rows per workgroup sharing
+    each input block through LDS (pair 2) over the union of their tile lists
+    (absent tiles read from a zero tile); pairs split into 3-entry chunks or
+    whole, octets on a 16-workgroup persistent grid too; all-zero tile
+    quarters read from the zero tile or from memory; with 16 and 24
+    right-hand sides (one and two 16-wide MFMA blocks)."""
     from paper_2204_13254_amd.solver import DDSolver
     c, t, p, eps = _case()
     dt = 0.03
@@ -114,7 +118,8 @@ def test_row_pair_full_passes(tmp_path, chunk):
         key = json.loads(probe.read_text().splitlines()[0])["key"]
         f = tmp_path / f"pair{nrhs}.jsonl"
         f.write_text(json.dumps({"key": key, "chunk": 32, "coarse_chunk": 16, "full_chunk": chunk,
-                                 "full_bucket": 8, "full_pair": 1}) + "\n")
+                                 "full_bucket": 8, "full_pair": pair, "full_persist": persist,
+                                 "full_quarter": quarter}) + "\n")
         r = s.autotune(f)
-        assert r["full_pair"] == 1
+        assert (r["full_pair"], r["full_persist"], r["full_quarter"]) == (pair, persist, quarter)
         assert _err(_steps(s, J), Eo) <= tol, (nrhs, chunk)
