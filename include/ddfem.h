@@ -167,7 +167,8 @@ void dd_default_options(dd_options* opt);
  *   dt, beta  time step and Newmark beta (> 0, finite)
  * The accumulated nodal charge of DD_DIAG_GAUSS starts at zero.
  * Errors: DD_ERR_ARG, DD_ERR_MESH, DD_ERR_PARTITION, DD_ERR_NONFINITE,
- * DD_ERR_HIP, DD_ERR_OOM.  On error *out is NULL. */
+ * DD_ERR_HIP, DD_ERR_OOM (also for a subdomain or coarse block of more than
+ * 8193 32-row tiles).  On error *out is NULL. */
 int dd_setup(void** out, const dd_mesh* mesh, const int32_t* partition, const double* eps,
              const double* mu, double dt, double beta, const dd_options* opt);
 

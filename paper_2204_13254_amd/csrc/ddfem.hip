@@ -119,6 +119,12 @@ struct Ctx {
   // while the coarse solve (a short chain of small launches) runs on st
   hipStream_t st2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the factorisation's kernel sequence, captured once on two internal
+  // streams (fa: subdomains, fb: coarse block) and replayed; ordered after
+  // and before the caller's stream by ev_fa / ev_fb
+  hipStream_t fa = nullptr, fb = nullptr;
+  hipEvent_t ev_fa = nullptr, ev_fb = nullptr, ev_ffork = nullptr, ev_fjoin = nullptr;
+  hipGraphExec_t factor_graph = nullptr;
   double dt = 0, beta = 0;
   int nrhs = 1;
   bool fp32 = false;
@@ -168,6 +174,10 @@ struct Ctx {
   int64_t partial_slots = 0;    // slots d_partial_mv holds
   void* d_scratch = nullptr;
   int64_t* d_scratch_off = nullptr;
+  // per factor-store tile: L tile nonzero / inverse tile nonzero (every flag
+  // a factorization reads it has written before)
+  uint8_t* d_nzl = nullptr;
+  uint8_t* d_nzi = nullptr;
   int* d_err = nullptr;
   // particle steps: per-tetrahedron geometry, face neighbours, edges, and
   // the counters of one launch (built on the first particle call)
@@ -285,6 +295,13 @@ struct Ctx {
   ~Ctx() {
     if (st) (void)hipStreamSynchronize(st);
     if (st2) (void)hipStreamSynchronize(st2);
+    if (fa) (void)hipStreamSynchronize(fa);
+    if (fb) (void)hipStreamSynchronize(fb);
+    if (factor_graph) (void)hipGraphExecDestroy(factor_graph);
+    for (hipEvent_t e : {ev_fa, ev_fb, ev_ffork, ev_fjoin})
+      if (e) (void)hipEventDestroy(e);
+    if (fa) (void)hipStreamDestroy(fa);
+    if (fb) (void)hipStreamDestroy(fb);
     if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
     if (step_graph) (void)hipGraphExecDestroy(step_graph);
     if (h_rs) (void)hipHostFree(h_rs);
@@ -493,6 +510,9 @@ static void build_device(Ctx& C, const double* coords) {
   C.ntiles = toff;
   C.rows_total = roff;
   const size_t wsz = C.fp32 ? 4 : 8;
+  for (const SubDev& q : C.subs_h)
+    if (q.K - 1 > kColList)
+      throw DDError{DD_ERR_OOM, "a factor block has more than " + std::to_string(kColList + 1) + " tile rows"};
   C.d_subs = upload(C.subs_h, C.owned, st);
   {
     void* p = nullptr;
@@ -507,6 +527,8 @@ static void build_device(Ctx& C, const double* coords) {
     HIPCHK(e);
     C.owned.push_back(p);
     C.d_tilesT = p;
+    C.d_nzl = dalloc<uint8_t>(std::max<int64_t>(1, C.ntiles), C.owned);
+    C.d_nzi = dalloc<uint8_t>(std::max<int64_t>(1, C.ntiles), C.owned);
     std::vector<int64_t> mo(nsub);
     int64_t acc = 0;
     for (int s = 0; s < nsub; ++s) {
@@ -958,9 +980,13 @@ static void drop_graphs(Ctx& C) {
 // ---------------------------------------------------------------------------
 // factor
 // ---------------------------------------------------------------------------
+// dynamic LDS of a tile-chain kernel: the list of up to n term indices
+static inline unsigned chain_lds(int n) { return (unsigned)(std::max(n, 2) * sizeof(uint16_t) + 15) & ~15u; }
+
+// Blocked Cholesky of the [I|Gamma] rows of blocks s0 .. s0+cnt-1 (corner
+// rows get L_cr and the Schur complement K_s = A_cc - L_cr L_cr^T).
 template <class T>
-static void factor_range(Ctx& C, int s0, int cnt) {
-  hipStream_t st = C.st;
+static void factor_chol(Ctx& C, int s0, int cnt, hipStream_t st) {
   T* tiles = (T*)C.d_tiles;
   int max_kr = 0;
   for (int s = s0; s < s0 + cnt; ++s)
@@ -971,24 +997,39 @@ static void factor_range(Ctx& C, int s0, int cnt) {
       const SubDev& q = C.subs_h[s];
       if (k < q.kI + q.kG) tmax = std::max(tmax, q.K - k - 1);
     }
-    hipLaunchKernelGGL(k_potrf<T>, dim3(cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs, C.d_err);
+    hipLaunchKernelGGL(k_potrf<T>, dim3(cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs, C.d_err,
+                       C.d_nzl, C.d_nzi);
     if (tmax > 0) {
-      hipLaunchKernelGGL(k_trsm<T>, dim3(tmax, cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs);
-      int64_t np = (int64_t)tmax * (tmax + 1) / 2;
-      hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)np, cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs);
+      hipLaunchKernelGGL(k_trsm<T>, dim3(tmax, cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs, C.d_nzl);
+      // pairs of nonzero column tiles, strided over at most 64K workgroups
+      // (2048 for one block: its nonzero pairs per step are a few thousand)
+      const int64_t np = (int64_t)tmax * (tmax + 1) / 2;
+      const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>({np, 65536 / cnt, 2048}));
+      hipLaunchKernelGGL(k_syrk<T>, dim3(gx, cnt), dim3(256), 0, st, k, s0, tiles, C.d_subs,
+                         (const uint8_t*)C.d_nzl);
     }
   }
+  HIPCHK(hipGetLastError());
+}
+
+// Inverse factor Linv_rr row by row, then Psi = L_cr Linv_rr.
+template <class T>
+static void factor_inv(Ctx& C, int s0, int cnt, hipStream_t st) {
+  T* tiles = (T*)C.d_tiles;
+  int max_kr = 0;
+  for (int s = s0; s < s0 + cnt; ++s)
+    max_kr = std::max(max_kr, C.subs_h[s].kI + C.subs_h[s].kG);
   for (int i = 1; i < max_kr; ++i) {
-    hipLaunchKernelGGL(k_trtri_row<T>, dim3(i, cnt), dim3(256), 0, st, i, s0, (const T*)tiles, C.d_subs,
-                       C.d_scratch_off, (T*)C.d_scratch);
+    hipLaunchKernelGGL(k_trtri_row<T>, dim3(i, cnt), dim3(256), chain_lds(i), st, i, s0, (const T*)tiles, C.d_subs,
+                       C.d_scratch_off, (T*)C.d_scratch, (const uint8_t*)C.d_nzl, C.d_nzi);
     hipLaunchKernelGGL(k_trtri_copy<T>, dim3(i, cnt), dim3(256), 0, st, i, s0, tiles, C.d_subs,
                        C.d_scratch_off, (const T*)C.d_scratch);
   }
   int max_kc = 0;
   for (int s = s0; s < s0 + cnt; ++s) max_kc = std::max(max_kc, C.subs_h[s].kC);
   for (int c = 0; c < max_kc && max_kr > 0; ++c) {
-    hipLaunchKernelGGL(k_psi_row<T>, dim3(max_kr, cnt), dim3(256), 0, st, c, s0, (const T*)tiles, C.d_subs,
-                       C.d_scratch_off, (T*)C.d_scratch);
+    hipLaunchKernelGGL(k_psi_row<T>, dim3(max_kr, cnt), dim3(256), chain_lds(max_kr), st, c, s0, (const T*)tiles, C.d_subs,
+                       C.d_scratch_off, (T*)C.d_scratch, (const uint8_t*)C.d_nzl, (const uint8_t*)C.d_nzi);
     hipLaunchKernelGGL(k_psi_copy<T>, dim3(max_kr, cnt), dim3(256), 0, st, c, s0, tiles, C.d_subs,
                        C.d_scratch_off, (const T*)C.d_scratch);
   }
@@ -1004,7 +1045,7 @@ static std::vector<int32_t> tile_nnz(Ctx& C, int64_t t0, int64_t n, std::vector<
   if (n == 0) return nnz;
   int32_t* d_nnz = nullptr;
   HIPCHK(hipMalloc((void**)&d_nnz, 2 * n * sizeof(int32_t)));
-  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)n), dim3(256), 0, C.st, t0, n, (const T*)C.d_tiles, d_nnz,
+  hipLaunchKernelGGL(k_tile_nnz<T>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, C.st, t0, n, (const T*)C.d_tiles, d_nnz,
                      qmask ? d_nnz + n : (int32_t*)nullptr);
   HIPCHK(hipMemcpyAsync(nnz.data(), d_nnz, n * sizeof(int32_t), hipMemcpyDeviceToHost, C.st));
   if (qmask)
@@ -1241,19 +1282,20 @@ static void full_tile_lists(Ctx& C) {
 template <class T>
 static void autotune(Ctx& C, const char* cache, dd_tuning* out);
 
+// The factorisation's kernels (element matrices, local assembly, blocked
+// Cholesky, inverse factors, coarse block on the side stream, packing), in
+// launch order on st and side; captured once per context and replayed.
 template <class T>
-static int factor_impl(Ctx& C) {
+static void factor_sequence(Ctx& C, hipStream_t st, hipStream_t side) {
   Plan& P = C.P;
-  hipStream_t st = C.st;
   T* tiles = (T*)C.d_tiles;
-  // the work lists may change with the factor's nonzero pattern: captured
-  // solves are dropped, and the next step runs eagerly to size its capture
-  HIPCHK(hipStreamSynchronize(st));
-  drop_graphs(C);
-  C.need_iters = C.need_sweeps = 0;
-  HIPCHK(hipMemsetAsync(tiles, 0, std::max<int64_t>(1, C.ntiles) * kTile * sizeof(T), st));
-  int big = INT32_MAX;
-  HIPCHK(hipMemcpyAsync(C.d_err, &big, sizeof(int), hipMemcpyHostToDevice, st));
+  // (fills by kernel: the sequence is captured into a graph)
+  {
+    const int64_t n16 = std::max<int64_t>(1, C.ntiles) * kTile * (int64_t)sizeof(T) / 16;
+    hipLaunchKernelGGL(k_clear16, dim3((unsigned)std::min<int64_t>(nblk(n16), 65536)), dim3(256), 0, st, n16,
+                       (uint4*)tiles);
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, C.d_err, (int)INT32_MAX);
+  }
   hipLaunchKernelGGL(k_element, dim3(nblk(P.nt)), dim3(256), 0, st, (int64_t)P.nt, C.d_coords, C.d_tsort,
                      C.d_mu, C.d_Te, C.d_Se);
   hipLaunchKernelGGL(k_pull_local<T>, dim3(nblk(C.n_lent)), dim3(256), 0, st, C.n_lent, C.d_lptr, C.d_lcon,
@@ -1269,23 +1311,65 @@ static int factor_impl(Ctx& C) {
     hipLaunchKernelGGL(k_pull_lam, dim3(nblk(C.lam_nnz)), dim3(256), 0, st, C.lam_nnz, C.d_lgptr, C.d_lgcon,
                        C.d_Te, C.d_Se, C.d_eps, C.beta * C.dt * C.dt, C.d_lvals);
   HIPCHK(hipGetLastError());
-  factor_range<T>(C, 0, C.nsub);
+  factor_chol<T>(C, 0, C.nsub, st);
+  // The coarse matrix needs only the subdomains' Schur corner blocks: its
+  // assembly and factorisation (a chain of small launches) run on the side
+  // stream while the subdomains' inverse factors are formed on st.  The two
+  // touch disjoint tiles (corner blocks are read; r rows, corner rows of the
+  // r columns and the coarse block are written) and disjoint scratch rows.
+  if (C.Kc > 0) HIPCHK(hipEventRecord(C.ev_ffork, st));
+  factor_inv<T>(C, 0, C.nsub, st);
   {
     int max_kg = 0;
     for (int s = 0; s < C.nsub; ++s) max_kg = std::max(max_kg, C.subs_h[s].kG);
     if (max_kg > 0)
-      hipLaunchKernelGGL(k_schur_inv<T>, dim3((unsigned)(max_kg * (max_kg + 1) / 2), C.nsub), dim3(256), 0, st, 0,
-                         (const T*)tiles, C.d_subs, C.d_m_off, (T*)C.d_mtri);
+      hipLaunchKernelGGL(k_schur_inv<T>, dim3((unsigned)(max_kg * (max_kg + 1) / 2), C.nsub), dim3(256),
+                         chain_lds(max_kg), st, 0,
+                         (const T*)tiles, C.d_subs, C.d_m_off, (T*)C.d_mtri, (const uint8_t*)C.d_nzi);
   }
   if (C.Kc > 0) {
+    HIPCHK(hipStreamWaitEvent(side, C.ev_ffork, 0));
     if (C.n_cent)
-      hipLaunchKernelGGL(k_pull_coarse<T>, dim3(nblk(C.n_cent)), dim3(256), 0, st, C.n_cent, C.d_cptr,
+      hipLaunchKernelGGL(k_pull_coarse<T>, dim3(nblk(C.n_cent)), dim3(256), 0, side, C.n_cent, C.d_cptr,
                          C.d_csrc, C.d_cdest, tiles);
-    factor_range<T>(C, C.nsub, 1);
+    factor_chol<T>(C, C.nsub, 1, side);
+    factor_inv<T>(C, C.nsub, 1, side);
+    HIPCHK(hipEventRecord(C.ev_fjoin, side));
+    HIPCHK(hipStreamWaitEvent(st, C.ev_fjoin, 0));
   }
   if (C.ntiles > 0)
     hipLaunchKernelGGL(k_pack_tiles<T>, dim3((unsigned)C.ntiles), dim3(256), 0, st, C.ntiles, tiles,
                        (T*)C.d_tilesT);
+  HIPCHK(hipGetLastError());
+}
+
+template <class T>
+static int factor_impl(Ctx& C) {
+  hipStream_t st = C.st;
+  // the work lists may change with the factor's nonzero pattern: captured
+  // solves are dropped, and the next step runs eagerly to size its capture
+  HIPCHK(hipStreamSynchronize(st));
+  drop_graphs(C);
+  C.need_iters = C.need_sweeps = 0;
+  HIPCHK(hipEventRecord(C.ev_fa, st));
+  HIPCHK(hipStreamWaitEvent(C.fa, C.ev_fa, 0));
+  if (!C.factor_graph) {
+    HIPCHK(hipStreamBeginCapture(C.fa, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      factor_sequence<T>(C, C.fa, C.fb);
+    } catch (...) {
+      (void)hipStreamEndCapture(C.fa, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(C.fa, &g));
+    HIPCHK(hipGraphInstantiate(&C.factor_graph, g, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(g));
+  }
+  HIPCHK(hipGraphLaunch(C.factor_graph, C.fa));
+  HIPCHK(hipEventRecord(C.ev_fb, C.fa));
+  HIPCHK(hipStreamWaitEvent(st, C.ev_fb, 0));
   HIPCHK(hipGetLastError());
   if (C.Kc > 0 && !C.coarse_lists) coarse_tile_lists<T>(C);
   full_tile_lists<T>(C);
@@ -2925,6 +3009,10 @@ int dd_setup(void** out, const dd_mesh* mesh, const int32_t* partition, const do
   HIPCHK(hipGetDevice(&C->device));
   resolve_scratch(C->device);
   HIPCHK(hipStreamCreateWithFlags(&C->st2, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&C->fa, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&C->fb, hipStreamNonBlocking));
+  for (hipEvent_t* e : {&C->ev_fa, &C->ev_fb, &C->ev_ffork, &C->ev_fjoin})
+    HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
   C->dt = dt;

@@ -68,6 +68,68 @@ __device__ __forceinline__ void tile_mma(const T (*A)[kNB + 1], const T (*B)[kNB
   }
 }
 
+// List, in increasing order, of the m in [m0, m1) with ok(m), built by the
+// whole 256-thread workgroup with ballots (list holds m1 - m0 entries, m1 <=
+// 65536); returns the count.  Every thread must call it.
+template <class Ok>
+__device__ __forceinline__ int chain_list(int m0, int m1, Ok ok, uint16_t* list, int* wcnt) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  int nn = 0;
+  for (int b0 = m0; b0 < m1; b0 += 256) {
+    const int m = b0 + tid;
+    const bool nz = m < m1 && ok(m);
+    const unsigned long long bal = __ballot(nz);
+    if (l == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = nn;
+    for (int x = 0; x < w; ++x) off += wcnt[x];
+    if (nz) list[off + __popcll(bal & ((1ull << l) - 1ull))] = (uint16_t)m;
+    nn += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  return nn;
+}
+
+// acc += sum over the listed m of A_m B_m (B_m^T with BT; A_m staged
+// transposed with AT), ptr(m, a, b) giving the two tiles.  The next term's
+// tiles are loaded into registers while the current product runs.
+template <class T, bool AT, bool BT, class Ptr>
+__device__ __forceinline__ void chain_mma(const uint16_t* list, int nn, Ptr ptr, T (*A)[kNB + 1],
+                                          T (*B)[kNB + 1], typename Mfma<T>::acc_t& acc) {
+  constexpr int E = kTile / 256;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
+  if (nn == 0) return;
+  T ra[E], rb[E];
+  const T* ap;
+  const T* bp;
+  ptr((int)list[0], ap, bp);
+#pragma unroll
+  for (int u = 0; u < E; ++u) {
+    ra[u] = ap[tid + 256 * u];
+    rb[u] = bp[tid + 256 * u];
+  }
+  for (int t = 0; t < nn; ++t) {
+    __syncthreads();  // the previous product has read A and B
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int e = tid + 256 * u;
+      if (AT) A[e % kNB][e / kNB] = ra[u];
+      else A[e / kNB][e % kNB] = ra[u];
+      B[e / kNB][e % kNB] = rb[u];
+    }
+    __syncthreads();
+    if (t + 1 < nn) {
+      ptr((int)list[t + 1], ap, bp);
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        ra[u] = ap[tid + 256 * u];
+        rb[u] = bp[tid + 256 * u];
+      }
+    }
+    tile_mma<T, BT>(A, B, mb, nb, l, acc);
+  }
+}
+
 // --------------------------------------------------------------------------
 // K1: element matrices (Sec. II-B-1, Whitney 1-forms), FP64.
 // Te[(ij),(kl)] = eps V/20 [(1+d_ik) g_j.g_l - (1+d_il) g_j.g_k
@@ -208,54 +270,92 @@ __global__ void k_pad_diag(int64_t n, const int64_t* __restrict__ pos, T* __rest
 // --------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(256) k_potrf(int k, int s0, T* __restrict__ tiles,
-                                               const SubDev* __restrict__ subs, int* __restrict__ err) {
+                                               const SubDev* __restrict__ subs, int* __restrict__ err,
+                                               uint8_t* __restrict__ nzl, uint8_t* __restrict__ nzi) {
   const SubDev q = subs[s0 + blockIdx.x];
   if (k >= q.kI + q.kG) return;
+  if (threadIdx.x == 0) nzl[tile_index(q, k, k)] = nzi[tile_index(q, k, k)] = 1;
   __shared__ double a[kNB][kNB + 1];
-  __shared__ double li[kNB][kNB + 1];
-  __shared__ int bad;
+  __shared__ double x[kNB][kNB + 1];
+  __shared__ double piv[kNB];
   T* tp = tiles + tile_index(q, k, k) * kTile;
   const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int e = tid; e < kTile; e += 256) a[e / kNB][e % kNB] = (double)tp[e];
+  // thread (rb, c) = (tid / 32, tid % 32) owns entries (rb + 8 u, c), u < 4,
+  // kept in registers; LDS holds what other threads read
+  constexpr int U = kTile / 256;
+  const int c = tid & 31, rb = tid >> 5;
+  double v[U], xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = rb + 8 * u;
+    v[u] = (double)tp[r * kNB + c];
+    a[r][c] = v[u];
+    xv[u] = r == c ? 1.0 : 0.0;
+    x[r][c] = xv[u];
+  }
   __syncthreads();
+  // Right-looking elimination with unscaled columns: step j subtracts
+  // a_rj a_cj / d_j from the trailing entries (c > j, r >= c) while column j
+  // is only read; the owners of column j + 1 publish it for the next step, so
+  // one barrier per column.  d_j = pivot; every thread reads the same pivot
+  // and takes the same decision on it.
+  int bad = 0;
   for (int j = 0; j < kNB; ++j) {
-    if (tid == 0) {
-      double d = a[j][j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
-      }
-      a[j][j] = sqrt(d);
+    double d = a[j][j];
+    const double acj = a[c][j];
+    double arj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) arj[u] = a[rb + 8 * u][j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      bad = 1;
+      d = 1.0;
     }
-    __syncthreads();
-    if (tid > j && tid < kNB) a[tid][j] /= a[j][j];
-    __syncthreads();
-    for (int e = tid; e < kTile; e += 256) {
-      int r = e / kNB, c = e % kNB;
-      if (c > j && r >= c) a[r][c] -= a[r][j] * a[c][j];
+    const double f = acj / d;
+    if (tid == 0) piv[j] = d;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = rb + 8 * u;
+      if (c > j && r >= c) v[u] -= arj[u] * f;
+      if (c == j + 1) a[r][c] = v[u];
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular factor, one column per thread
-  if (tid < kNB) {
-    const int c = tid;
-    for (int r = 0; r < c; ++r) li[r][c] = 0.0;
-    li[c][c] = 1.0 / a[c][c];
-    for (int r = c + 1; r < kNB; ++r) {
-      double s = 0.0;
-      for (int m = c; m < r; ++m) s += a[r][m] * li[m][c];
-      li[r][c] = -s / a[r][r];
-    }
+  // L = unscaled columns / sqrt(d)
+  const double sd = sqrt(piv[c]);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = rb + 8 * u;
+    a[r][c] = r < c ? 0.0 : (r == c ? sd : v[u] / sd);
   }
   __syncthreads();
-  for (int e = tid; e < kTile; e += 256) tp[e] = (T)li[e / kNB][e % kNB];
+  // L^-1 by forward substitution on the identity, all columns at once: at
+  // step m row m is complete up to its division by L_mm, and the rows below
+  // take L_rm X_mc / L_mm; the owners of row m + 1 publish it (again one
+  // barrier per step)
+  for (int m = 0; m < kNB; ++m) {
+    const double g = x[m][c] / a[m][m];
+    double arm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) arm[u] = a[rb + 8 * u][m];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = rb + 8 * u;
+      if (r > m && c <= m) xv[u] -= arm[u] * g;
+      if (r == m + 1) x[r][c] = xv[u];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int r = rb + 8 * u;
+    tp[r * kNB + c] = (T)(c <= r ? xv[u] / a[r][r] : 0.0);
+  }
   if (tid == 0 && bad) atomicMin(err, s0 + (int)blockIdx.x);
 }
 
 template <class T>
 __global__ void __launch_bounds__(256) k_trsm(int k, int s0, T* __restrict__ tiles,
-                                              const SubDev* __restrict__ subs) {
+                                              const SubDev* __restrict__ subs, uint8_t* __restrict__ nzl) {
   const SubDev q = subs[s0 + blockIdx.y];
   const int i = k + 1 + blockIdx.x;
   if (k >= q.kI + q.kG || i >= q.K) return;
@@ -275,38 +375,67 @@ __global__ void __launch_bounds__(256) k_trsm(int k, int s0, T* __restrict__ til
   tile_mma<T, true>(A, Dv, mb, nb, l, acc);
 #pragma unroll
   for (int v = 0; v < 4; ++v) ap[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] = acc[v];
+  // nonzero flag of L_ik (a zero tile takes no part in later products)
+  const int nz = __syncthreads_or(acc[0] != (T)0 || acc[1] != (T)0 || acc[2] != (T)0 || acc[3] != (T)0);
+  if (tid == 0) nzl[tile_index(q, i, k)] = (uint8_t)(nz != 0);
 }
 
+// Tile rows of one factor column held by the trailing-update kernel's list.
+constexpr int kColList = 8192;
+
+// Trailing update of step k over the nonzero tiles of column k only: every
+// workgroup of a subdomain compacts the rows i > k with L_ik != 0 into an LDS
+// list, then takes the pairs (a >= b) of that list strided by the grid's x
+// size: C_ij -= L_ik L_jk^T.  (A grid over all pairs would dispatch one
+// workgroup per trailing tile per step, nearly all of them on zero tiles of
+// the nested-dissection order.)  Requires K - k - 1 <= kColList.
 template <class T>
 __global__ void __launch_bounds__(256) k_syrk(int k, int s0, T* __restrict__ tiles,
-                                              const SubDev* __restrict__ subs) {
+                                              const SubDev* __restrict__ subs, const uint8_t* __restrict__ nzl) {
   const SubDev q = subs[s0 + blockIdx.y];
   if (k >= q.kI + q.kG) return;
-  const int64_t p = blockIdx.x;
   const int Tn = q.K - k - 1;
-  if (p >= (int64_t)Tn * (Tn + 1) / 2) return;
-  int ii = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(ii + 1) * (ii + 2) / 2 <= p) ++ii;
-  while ((int64_t)ii * (ii + 1) / 2 > p) --ii;
-  const int jj = (int)(p - (int64_t)ii * (ii + 1) / 2);
-  const int i = k + 1 + ii, j = k + 1 + jj;
+  __shared__ uint16_t list[kColList];
+  __shared__ int wcnt[4];
   __shared__ T A[kNB][kNB + 1];
   __shared__ T B[kNB][kNB + 1];
-  const T* ap = tiles + tile_index(q, i, k) * kTile;
-  const T* bp = tiles + tile_index(q, j, k) * kTile;
-  T* cp = tiles + tile_index(q, i, j) * kTile;
   const int tid = threadIdx.x;
-  for (int e = tid; e < kTile; e += 256) {
-    A[e / kNB][e % kNB] = ap[e];
-    B[e / kNB][e % kNB] = bp[e];
-  }
-  __syncthreads();
-  // C_ij -= L_ik L_jk^T on MFMA: wave w computes block (w/2, w%2)
   const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
-  typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-  tile_mma<T, true>(A, B, mb, nb, l, acc);
+  int nn = 0;
+  for (int b0 = 0; b0 < Tn; b0 += 256) {
+    const int ii = b0 + tid;
+    const bool nz = ii < Tn && nzl[tile_index(q, k + 1 + ii, k)];
+    const unsigned long long bal = __ballot(nz);
+    if (l == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = nn;
+    for (int x = 0; x < w; ++x) off += wcnt[x];
+    if (nz) list[off + __popcll(bal & ((1ull << l) - 1ull))] = (uint16_t)ii;
+    nn += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+  const int64_t npair = (int64_t)nn * (nn + 1) / 2;
+  for (int64_t p = blockIdx.x; p < npair; p += gridDim.x) {
+    int a = (int)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(a + 1) * (a + 2) / 2 <= p) ++a;
+    while ((int64_t)a * (a + 1) / 2 > p) --a;
+    const int bb = (int)(p - (int64_t)a * (a + 1) / 2);
+    const int i = k + 1 + list[a], j = k + 1 + list[bb];
+    const T* ap = tiles + tile_index(q, i, k) * kTile;
+    const T* bp = tiles + tile_index(q, j, k) * kTile;
+    T* cp = tiles + tile_index(q, i, j) * kTile;
+    __syncthreads();
+    for (int e = tid; e < kTile; e += 256) {
+      A[e / kNB][e % kNB] = ap[e];
+      B[e / kNB][e % kNB] = bp[e];
+    }
+    __syncthreads();
+    // C_ij -= L_ik L_jk^T on MFMA: wave w computes block (w/2, w%2)
+    typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+    tile_mma<T, true>(A, B, mb, nb, l, acc);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) cp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] -= acc[v];
+    for (int v = 0; v < 4; ++v) cp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] -= acc[v];
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -318,7 +447,8 @@ template <class T>
 __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __restrict__ tiles,
                                                    const SubDev* __restrict__ subs,
                                                    const int64_t* __restrict__ scratch_off,
-                                                   T* __restrict__ scratch) {
+                                                   T* __restrict__ scratch, const uint8_t* __restrict__ nzl,
+                                                   uint8_t* __restrict__ nzi) {
   const int sidx = s0 + blockIdx.y;
   const SubDev q = subs[sidx];
   const int j = blockIdx.x;
@@ -329,17 +459,18 @@ __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __res
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
   typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-  for (int m = j; m < i; ++m) {
-    const T* ap = tiles + tile_index(q, i, m) * kTile;  // L_im
-    const T* bp = tiles + tile_index(q, m, j) * kTile;  // Linv_mj
-    __syncthreads();
-    for (int e = tid; e < kTile; e += 256) {
-      A[e / kNB][e % kNB] = ap[e];
-      B[e / kNB][e % kNB] = bp[e];
-    }
-    __syncthreads();
-    tile_mma<T, false>(A, B, mb, nb, l, acc);
-  }
+  // terms with a zero L_im or Linv_mj are skipped
+  extern __shared__ uint16_t list[];
+  __shared__ int wcnt[4];
+  const int nn = chain_list(
+      j, i, [&](int m) { return nzl[tile_index(q, i, m)] && nzi[tile_index(q, m, j)]; }, list, wcnt);
+  chain_mma<T, false, false>(
+      list, nn,
+      [&](int m, const T*& ap, const T*& bp) {
+        ap = tiles + tile_index(q, i, m) * kTile;  // L_im
+        bp = tiles + tile_index(q, m, j) * kTile;  // Linv_mj
+      },
+      A, B, acc);
   // multiply by -Dinv_i (MFMA again, the sum staged in LDS)
   __syncthreads();
   const T* dp = tiles + tile_index(q, i, i) * kTile;
@@ -352,6 +483,9 @@ __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __res
   T* sp = scratch + (scratch_off[sidx] + j) * kTile;
 #pragma unroll
   for (int v = 0; v < 4; ++v) sp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] = -out[v];
+  // Linv_ij's flag (rows below i read it; row i's own terms do not)
+  const int nz = __syncthreads_or(out[0] != (T)0 || out[1] != (T)0 || out[2] != (T)0 || out[3] != (T)0);
+  if (tid == 0) nzi[tile_index(q, i, j)] = (uint8_t)(nz != 0);
 }
 
 template <class T>
@@ -374,7 +508,8 @@ __global__ void k_trtri_copy(int i, int s0, T* __restrict__ tiles, const SubDev*
 template <class T>
 __global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restrict__ tiles,
                                                  const SubDev* __restrict__ subs,
-                                                 const int64_t* __restrict__ scratch_off, T* __restrict__ scratch) {
+                                                 const int64_t* __restrict__ scratch_off, T* __restrict__ scratch,
+                                                 const uint8_t* __restrict__ nzl, const uint8_t* __restrict__ nzi) {
   const int sidx = s0 + blockIdx.y;
   const SubDev q = subs[sidx];
   const int j = blockIdx.x;
@@ -386,17 +521,17 @@ __global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restr
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
   typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-  for (int m = j; m < kr; ++m) {
-    const T* ap = tiles + tile_index(q, i, m) * kTile;  // L_cr(i, m)
-    const T* bp = tiles + tile_index(q, m, j) * kTile;  // Linv(m, j)
-    __syncthreads();
-    for (int e = tid; e < kTile; e += 256) {
-      A[e / kNB][e % kNB] = ap[e];
-      B[e / kNB][e % kNB] = bp[e];
-    }
-    __syncthreads();
-    tile_mma<T, false>(A, B, mb, nb, l, acc);
-  }
+  extern __shared__ uint16_t list[];
+  __shared__ int wcnt[4];
+  const int nn = chain_list(
+      j, kr, [&](int m) { return nzl[tile_index(q, i, m)] && nzi[tile_index(q, m, j)]; }, list, wcnt);
+  chain_mma<T, false, false>(
+      list, nn,
+      [&](int m, const T*& ap, const T*& bp) {
+        ap = tiles + tile_index(q, i, m) * kTile;  // L_cr(i, m)
+        bp = tiles + tile_index(q, m, j) * kTile;  // Linv(m, j)
+      },
+      A, B, acc);
   T* sp = scratch + (scratch_off[sidx] + j) * kTile;
 #pragma unroll
   for (int v = 0; v < 4; ++v) sp[(mb * 16 + Mfma<T>::row(l, v)) * kNB + nb * 16 + (l & 15)] = acc[v];
@@ -1179,28 +1314,35 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* _
 template <class T>
 __global__ void __launch_bounds__(256) k_tile_nnz(int64_t t0, int64_t n, const T* __restrict__ tiles,
                                                   int32_t* __restrict__ nnz, int32_t* __restrict__ qmask) {
-  const int64_t t = blockIdx.x;
+  // one wave per tile: nonzeros of the tile (operand order), and per 16 x 16
+  // quarter (bit 2 * row half + column half set when the quarter holds a
+  // nonzero).  Lane l's 16-byte load k covers entries e = V (l + 64 k), whose
+  // operand lane is l, so the quarter is 2 (e / 512) + l / 32: per-lane
+  // counts and a shuffle sum per quarter, no atomics.
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= n) return;
-  // nonzeros of the tile (operand order), and per 16 x 16 quarter (bit 2 *
-  // row half + column half set when the quarter holds a nonzero)
-  __shared__ int cnt[5];
-  if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
-  __syncthreads();
   constexpr int V = 16 / sizeof(T);
-  const T* p = tiles + (t0 + t) * kTile;
-  int c[4] = {0, 0, 0, 0};
-  for (int e = threadIdx.x; e < kTile; e += 256) {
-    const int lane = ((e % 512) % (64 * V)) / V;  // lane 16 (c / 8) + r % 16 of swz
-    c[(e / 512) * 2 + (lane >> 5)] += p[e] != (T)0;
+  constexpr int L = kTile / (64 * V);  // loads per lane
+  constexpr int P = 512 / (64 * V);    // loads per 512-entry half
+  const int l = threadIdx.x & 63;
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  const vec_t* p = (const vec_t*)(tiles + (t0 + t) * kTile) + l;
+  int a[2] = {0, 0};  // this lane's nonzeros in the row halves
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    const vec_t v = p[64 * k];
+#pragma unroll
+    for (int j = 0; j < V; ++j) a[k / P] += v[j] != (T)0;
   }
-  for (int q = 0; q < 4; ++q) {
-    atomicAdd(&cnt[q], c[q]);
-    atomicAdd(&cnt[4], c[q]);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    nnz[t] = cnt[4];
-    if (qmask) qmask[t] = (cnt[0] > 0) | (cnt[1] > 0) << 1 | (cnt[2] > 0) << 2 | (cnt[3] > 0) << 3;
+  // quarter 2 h + l / 32: sum over the lanes of each column half
+  int c[4] = {l < 32 ? a[0] : 0, l < 32 ? 0 : a[0], l < 32 ? a[1] : 0, l < 32 ? 0 : a[1]};
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c[q] += __shfl_xor(c[q], o);
+  if (l == 0) {
+    nnz[t] = c[0] + c[1] + c[2] + c[3];
+    if (qmask) qmask[t] = (c[0] > 0) | (c[1] > 0) << 1 | (c[2] > 0) << 2 | (c[3] > 0) << 3;
   }
 }
 
@@ -1215,7 +1357,8 @@ __global__ void __launch_bounds__(256) k_tile_nnz(int64_t t0, int64_t n, const T
 template <class T>
 __global__ void __launch_bounds__(256) k_schur_inv(int s0, const T* __restrict__ tiles,
                                                    const SubDev* __restrict__ subs,
-                                                   const int64_t* __restrict__ m_off, T* __restrict__ msq) {
+                                                   const int64_t* __restrict__ m_off, T* __restrict__ msq,
+                                                   const uint8_t* __restrict__ nzi) {
   const int sidx = s0 + blockIdx.y;
   const SubDev q = subs[sidx];
   const int p = blockIdx.x;  // p = o (o + 1) / 2 + m
@@ -1229,17 +1372,19 @@ __global__ void __launch_bounds__(256) k_schur_inv(int s0, const T* __restrict__
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, mb = w >> 1, nb = w & 1;
   typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
-  for (int k = o; k < q.kG; ++k) {
-    const T* ap = tiles + tile_index(q, q.kI + k, q.kI + o) * kTile;  // Linv_ko
-    const T* bp = tiles + tile_index(q, q.kI + k, q.kI + m) * kTile;  // Linv_km
-    __syncthreads();
-    for (int e = tid; e < kTile; e += 256) {
-      A[e % kNB][e / kNB] = ap[e];  // Linv_ko^T
-      B[e / kNB][e % kNB] = bp[e];
-    }
-    __syncthreads();
-    tile_mma<T, false>(A, B, mb, nb, l, acc);
-  }
+  extern __shared__ uint16_t list[];
+  __shared__ int wcnt[4];
+  const int nn = chain_list(
+      o, q.kG,
+      [&](int k) { return nzi[tile_index(q, q.kI + k, q.kI + o)] && nzi[tile_index(q, q.kI + k, q.kI + m)]; },
+      list, wcnt);
+  chain_mma<T, true, false>(
+      list, nn,
+      [&](int k, const T*& ap, const T*& bp) {
+        ap = tiles + tile_index(q, q.kI + k, q.kI + o) * kTile;  // Linv_ko (staged transposed)
+        bp = tiles + tile_index(q, q.kI + k, q.kI + m) * kTile;  // Linv_km
+      },
+      A, B, acc);
   T* d = msq + (m_off[sidx] + (int64_t)o * (o + 1) / 2 + m) * kTile;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -1982,6 +2127,17 @@ __global__ void k_zero(int64_t n, T* __restrict__ y, const int* __restrict__ ski
   if (skip && *skip) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = (T)0;
+}
+
+// y[0 .. n16) = 0 in 16-byte stores (grid-stride)
+__global__ void k_clear16(int64_t n16, uint4* __restrict__ y) {
+  const uint4 z = {0u, 0u, 0u, 0u};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = z;
+}
+
+__global__ void k_set_int(int* __restrict__ p, int v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
 __global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
