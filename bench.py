@@ -105,12 +105,29 @@ def cpu_baseline(w, coords, tets, J0, rhs_sample=4):
     }
 
 
+# The source text that decides what the full-pass tile product moves: the
+# tile-product kernels, the work lists they are given (XCD placement, items,
+# full-pass lists) and their launch.  Counter summaries taken on other text
+# are not used.
+_FULL_PASS_SOURCE = (
+    ("kernels.hpp", "// Batched tile products for the solves", "// Symmetric product y = M u"),
+    ("ddfem.hip", "template <class It, class SubF, class LenF>", "static void make_sym_list("),
+    ("ddfem.hip", "static void build_full_items(", "static void autotune(Ctx& C, const char* cache"),
+    ("ddfem.hip", "static void mv_launch(", "static void mv_dispatch("),
+)
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "ddfem.hip"):
-        with open(os.path.join(ROOT, "paper_2204_13254_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f, a, b in _FULL_PASS_SOURCE:
+        with open(os.path.join(ROOT, "paper_2204_13254_amd", "csrc", f)) as fh:
+            text = fh.read()
+        i = text.find(a)
+        j = text.find(b, i + 1) if i >= 0 else -1
+        if i < 0 or j < 0:
+            raise RuntimeError(f"full-pass source marker not found in {f}: {a if i < 0 else b!r}")
+        h.update(text[i:j].encode())
     return h.hexdigest()[:16]
 
 

@@ -198,13 +198,17 @@ struct Ctx {
   double robin_alpha = 0.0;
   int32_t *d_code2 = nullptr, *d_partner2 = nullptr;
   int64_t* d_rrp = nullptr;
-  int32_t* d_rci = nullptr;
   double* d_rval = nullptr;
   int64_t n_radd = 0;            // Robin terms of the local interface blocks (lower triangle, no alpha)
   int64_t* d_radd_pos = nullptr;
   double* d_radd_val = nullptr;
   double *d_gmV = nullptr, *d_gm_rhs = nullptr, *d_lam2 = nullptr, *d_gm_partial = nullptr;
-  double *d_gm_h = nullptr, *d_gm_tot = nullptr, *d_gm_ss = nullptr, *d_gm_y = nullptr;
+  double *d_gm_h = nullptr, *d_gm_tot = nullptr, *d_gm_y = nullptr, *d_gm_wpart = nullptr;
+  double *d_gm_H = nullptr, *d_gm_cs = nullptr, *d_gm_sn = nullptr, *d_gm_g = nullptr;
+  int64_t* d_rrow = nullptr;            // local row of every R column (side -> row)
+  GmState* d_gm_st = nullptr;
+  GmState* h_gm_st = nullptr;           // pinned copy of the GMRES state
+  std::vector<hipGraphExec_t> gm_graphs;  // captured blocks of GMRES iterations
   // local assembly pull
   int64_t n_lent = 0;
   int64_t *d_lptr = nullptr, *d_ldest = nullptr;
@@ -236,7 +240,8 @@ struct Ctx {
   uint8_t* d_nodeint = nullptr;
   double* d_vres = nullptr;  // [nv][nrhs] Gauss residual
   double* d_q = nullptr;     // accumulated nodal charge of the per-step check, [nv][nrhs]
-  double* d_gmax = nullptr;  // maxima of the per-step check [nrhs][2] (as bit patterns)
+  double* d_gmax = nullptr;   // maxima of the per-step check [nrhs][2]
+  double* d_gpart = nullptr;  // their workgroup shares [kGaussBlocks][2 kMaxRhs]
   int32_t* d_vdof = nullptr; // vertex -> unknowns (d << 1 | tail), the lists of d_vedge
   // work lists
   // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
@@ -304,6 +309,9 @@ struct Ctx {
     if (fb) (void)hipStreamDestroy(fb);
     if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
     if (step_graph) (void)hipGraphExecDestroy(step_graph);
+    for (hipGraphExec_t g : gm_graphs)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (h_gm_st) (void)hipHostFree(h_gm_st);
     if (h_rs) (void)hipHostFree(h_rs);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -877,6 +885,7 @@ static void build_device(Ctx& C, const double* coords) {
     C.d_q = dalloc<double>(P.nv * C.nrhs, C.owned);
     HIPCHK(hipMemsetAsync(C.d_q, 0, P.nv * C.nrhs * sizeof(double), st));
     C.d_gmax = dalloc<double>((size_t)kMaxRhs * 2, C.owned);
+    C.d_gpart = dalloc<double>((size_t)kGaussBlocks * kMaxRhs * 2, C.owned);
     std::vector<int32_t> vdof(vedge.size());
     for (size_t k = 0; k < vedge.size(); ++k) vdof[k] = (P.dof[vedge[k] >> 1] << 1) | (vedge[k] & 1);
     C.d_vdof = upload(vdof, C.owned, st);
@@ -975,6 +984,10 @@ static void drop_graphs(Ctx& C) {
   if (C.step_graph) HIPCHK(hipGraphExecDestroy(C.step_graph));
   C.cg_graph = nullptr;
   C.step_graph = nullptr;
+  for (hipGraphExec_t& g : C.gm_graphs) {
+    if (g) HIPCHK(hipGraphExecDestroy(g));
+    g = nullptr;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1592,35 +1605,85 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
 }
 
 // Robin variant: y = G lam = lam + lam(partner side) - R (x_G response of
-// the other side), with the response of every side computed by apply_local
+// the other side), with the response of every side computed by apply_local;
+// every kernel returns at once while *skip != 0
 template <class T>
-static void apply_G(Ctx& C, const double* lam, double* y) {
+static void apply_G(Ctx& C, const double* lam, double* y, const int* skip) {
   const int nr = C.nrhs;
   const int64_t n = C.n_grow, nl = n * nr;
   hipStream_t st = C.st;
   hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2, lam,
-                     (T*)C.X[5], nr, (const int*)nullptr);
-  apply_local<T>(C, nullptr);
-  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
-                     C.d_partner2, lam, C.d_grow, (const T*)C.X[8], (const T*)corner_part(C), y, nr);
+                     (T*)C.X[5], nr, skip);
+  apply_local<T>(C, skip);
+  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow, C.d_rval,
+                     C.d_partner2, lam, (const T*)C.X[8], (const T*)corner_part(C), y, nr, skip);
 }
 
-// per-RHS dot products a . b over the side vectors, to the host
-static void side_dots(Ctx& C, const double* a, const double* b, double* out) {
+// the two projections of classical Gram-Schmidt (k_gm_project), for nv <= KMAX
+template <bool FIRST>
+static void gm_project(Ctx& C, int nv, double* w, const int* stop) {
   const int nr = C.nrhs;
-  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, 1), dim3(256), 0, C.st, C.n_grow, 1, a, (int64_t)0, b, nr,
-                     C.d_gm_partial);
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(256), 0, C.st, 1, nr, kDotBlocks,
-                     (const double*)C.d_gm_partial, C.d_gm_ss, (double*)nullptr);
-  HIPCHK(hipMemcpyAsync(out, C.d_gm_ss, nr * sizeof(double), hipMemcpyDeviceToHost, C.st));
-  HIPCHK(hipStreamSynchronize(C.st));
+  const int64_t n = C.n_grow, ldv = n * nr;
+  hipStream_t st = C.st;
+  const double* V = C.d_gmV;
+  const double* ss = C.d_gm_st->ss;
+  double* part = FIRST ? C.d_gm_partial : nullptr;
+#define DD_GM_PROJECT(K)                                                                                      \
+  hipLaunchKernelGGL((k_gm_project<K, FIRST>), dim3(kDotBlocks), dim3(256), 0, st, n, nv, V, ldv,             \
+                     (const double*)C.d_gm_h, w, nr, part, ss, stop)
+  if (nv <= 8)
+    DD_GM_PROJECT(8);
+  else if (nv <= 16)
+    DD_GM_PROJECT(16);
+  else if (nv <= 24)
+    DD_GM_PROJECT(24);
+  else if (nv <= 32)
+    DD_GM_PROJECT(32);
+  else
+    DD_GM_PROJECT(kGmresRestart);
+#undef DD_GM_PROJECT
+}
+
+// iteration j of the device GMRES (basis V_0 .. V_j, new vector w = V_{j+1}):
+// w = G V_j; classical Gram-Schmidt applied twice, in three passes over the
+// basis (the dots of the first projection; its update fused with the dots of
+// the second; the second update fused with the normalisation, whose norm
+// |w''|^2 = |w'|^2 - |h2|^2 comes from the second dots); the Givens update
+// of every open RHS in between.  Every kernel returns at once once the solve
+// has stopped.
+template <class T>
+static void gmres_iteration(Ctx& C, int j) {
+  const int nr = C.nrhs, m = kGmresRestart;
+  hipStream_t st = C.st;
+  const int64_t n = C.n_grow, nl = n * nr, ldv = nl;
+  double* V = C.d_gmV;
+  double* w = V + (int64_t)(j + 1) * ldv;
+  GmState* gs = C.d_gm_st;
+  const int* stop = &gs->stop;
+  apply_G<T>(C, V + (int64_t)j * ldv, w, stop);
+  // h1 = [V_0 .. V_j, w]^T w (the last entry, |w|^2, is not used)
+  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, (j + 2 + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n, j + 2,
+                     (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial, stop);
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(j + 2), dim3(256), 0, st, j + 2, nr, kDotBlocks,
+                     (const double*)C.d_gm_partial, C.d_gm_h, C.d_gm_tot, 1, stop);
+  // w' = w - V h1 with h2 = V^T w' and |w'|^2
+  gm_project<true>(C, j + 1, w, stop);
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(j + 2), dim3(256), 0, st, j + 2, nr, kDotBlocks,
+                     (const double*)C.d_gm_partial, C.d_gm_h, C.d_gm_tot, 0, stop);
+  hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(kScalarThreads), 0, st, j, nr, (const double*)C.d_gm_h,
+                     (const double*)C.d_gm_tot, gs, C.d_gm_H, C.d_gm_cs, C.d_gm_sn, C.d_gm_g, m, C.opt.cg_tol,
+                     C.opt.cg_max_iter, stop);
+  // w'' = (w' - V h2) / |w''|
+  gm_project<false>(C, j + 1, w, stop);
 }
 
 // Restarted GMRES on G lam = rhs (Sec. III-B's multiplier system for the
-// edge-only unknowns), all right-hand sides in lock step: classical
-// Gram-Schmidt applied twice, Givens rotations on the host per RHS, stop when
-// ||rhs - G lam|| <= tol ||rhs|| for every RHS (or at the iteration cap).
-// The rhs is -R x0 with x0 the interface rows of the pre-solve (X4).
+// edge-only unknowns), all right-hand sides in lock step, with its scalar
+// work on the device (k_gm_*): the host launches blocks of check_every
+// iterations (replayed from captured graphs when the stream allows) and reads
+// the small state back once per block.  Stop when ||rhs - G lam|| <= tol
+// ||rhs|| for every RHS (or at the iteration cap).  The rhs is -R x0 with x0
+// the interface rows of the pre-solve (X4).
 template <class T>
 static int dp2_gmres(Ctx& C, int* iters, double* relres) {
   const int nr = C.nrhs;
@@ -1628,124 +1691,86 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
   const int64_t n = C.n_grow, nl = n * nr, ldv = nl;
   const int m = kGmresRestart;
   double* V = C.d_gmV;
-  auto vec = [&](int k) { return V + (int64_t)k * ldv; };
-  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rci, C.d_rval,
-                     C.d_partner2, (const double*)nullptr, C.d_grow, (const T*)C.X[4], (const T*)nullptr,
-                     C.d_gm_rhs, nr);
-  HIPCHK(hipMemsetAsync(C.d_lam2, 0, nl * sizeof(double), st));
-  double bnorm[kMaxRhs], ss[kMaxRhs];
-  side_dots(C, C.d_gm_rhs, C.d_gm_rhs, bnorm);
-  bool conv[kMaxRhs];
-  for (int r = 0; r < nr; ++r) {
-    bnorm[r] = std::sqrt(bnorm[r]);
-    conv[r] = !(bnorm[r] > 0.0);
-    iters[r] = 0;
-    relres[r] = 0.0;
-  }
-  std::vector<double> H((size_t)nr * (m + 1) * m), cs((size_t)nr * m), sn((size_t)nr * m), g((size_t)nr * (m + 1));
-  std::vector<double> htot((size_t)(m + 1) * kMaxRhs), y((size_t)m * kMaxRhs);
-  int total = 0;
+  GmState* gs = C.d_gm_st;
   const int cap = C.opt.cg_max_iter;
-  auto all_conv = [&]() {
-    for (int r = 0; r < nr; ++r)
-      if (!conv[r]) return false;
-    return true;
+  const int chk = std::max(1, std::min(C.opt.check_every, m));
+  const int nblocks = (m + chk - 1) / chk;
+  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow, C.d_rval,
+                     C.d_partner2, (const double*)nullptr, (const T*)C.X[4], (const T*)nullptr, C.d_gm_rhs, nr,
+                     (const int*)nullptr);
+  hipLaunchKernelGGL(k_zero<double>, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_lam2, (const int*)nullptr);
+  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, n, (const double*)C.d_gm_rhs,
+                     (const double*)C.d_gm_rhs, nr, C.d_gm_wpart, (const int*)nullptr);
+  hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_gm_wpart, gs);
+  auto read_state = [&]() {
+    HIPCHK(hipMemcpyAsync(C.h_gm_st, gs, sizeof(GmState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
   };
-  while (!all_conv() && total < cap) {
-    // r0 = rhs - G lam in V_0
-    if (total == 0) {
-      HIPCHK(hipMemcpyAsync(vec(0), C.d_gm_rhs, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
+  read_state();
+  const bool graph = C.opt.use_graph && st != nullptr && !C.prof;
+  if (graph && (int)C.gm_graphs.size() != nblocks) {
+    for (hipGraphExec_t g : C.gm_graphs)
+      if (g) HIPCHK(hipGraphExecDestroy(g));
+    C.gm_graphs.assign(nblocks, nullptr);
+  }
+  while (!C.h_gm_st->stop) {
+    // r0 = rhs - G lam in V_0 (lam = 0 on the first cycle), |r0| e_1, V_0 = r0 / |r0|
+    if (C.h_gm_st->total == 0) {
+      hipLaunchKernelGGL(k_copy, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs, V,
+                         (const int*)nullptr);
     } else {
-      apply_G<T>(C, C.d_lam2, vec(0));
-      hipLaunchKernelGGL(k_rsub, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs, vec(0));
+      apply_G<T>(C, C.d_lam2, V, nullptr);
+      hipLaunchKernelGGL(k_rsub, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs, V);
     }
-    side_dots(C, vec(0), vec(0), ss);
-    hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)vec(0),
-                       (const double*)C.d_gm_ss, vec(0), nr);
-    bool active[kMaxRhs];
-    int cols[kMaxRhs];
-    for (int r = 0; r < nr; ++r) {
-      active[r] = !conv[r];
-      cols[r] = 0;
-      std::fill(g.begin() + (size_t)r * (m + 1), g.begin() + (size_t)(r + 1) * (m + 1), 0.0);
-      g[(size_t)r * (m + 1)] = std::sqrt(std::max(ss[r], 0.0));
-    }
-    for (int j = 0; j < m && total < cap; ++j) {
-      double* w = vec(j + 1);
-      apply_G<T>(C, vec(j), w);
-      const int nv = j + 1;
-      HIPCHK(hipMemsetAsync(C.d_gm_tot, 0, (size_t)nv * kMaxRhs * sizeof(double), st));
-      for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, (nv + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n, nv,
-                           (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial);
-        hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(256), 0, st, nv, nr, kDotBlocks,
-                           (const double*)C.d_gm_partial, C.d_gm_h, C.d_gm_tot);
-        hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, nv, (const double*)V, ldv,
-                           (const double*)C.d_gm_h, -1.0, w, nr);
-      }
-      // |w|^2 into row nv of the coefficient block: one copy and one wait per iteration
-      double* wss = C.d_gm_tot + (size_t)nv * kMaxRhs;
-      hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, 1), dim3(256), 0, st, n, 1, (const double*)w, (int64_t)0,
-                         (const double*)w, nr, C.d_gm_partial);
-      hipLaunchKernelGGL(k_mdot_reduce, dim3(1), dim3(256), 0, st, 1, nr, kDotBlocks,
-                         (const double*)C.d_gm_partial, wss, (double*)nullptr);
-      HIPCHK(hipMemcpyAsync(htot.data(), C.d_gm_tot, (size_t)(nv + 1) * kMaxRhs * sizeof(double),
-                            hipMemcpyDeviceToHost, st));
-      hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)w, (const double*)wss, w,
-                         nr);
-      HIPCHK(hipStreamSynchronize(st));
-      for (int r = 0; r < nr; ++r) ss[r] = htot[(size_t)nv * kMaxRhs + r];
-      ++total;
-      for (int r = 0; r < nr; ++r) {
-        if (!active[r] || conv[r]) continue;
-        double* h = &H[((size_t)r * m + j) * (m + 1)];  // column j of RHS r
-        for (int i = 0; i <= j; ++i) h[i] = htot[(size_t)i * kMaxRhs + r];
-        h[j + 1] = std::sqrt(std::max(ss[r], 0.0));
-        double* c = &cs[(size_t)r * m];
-        double* sv = &sn[(size_t)r * m];
-        for (int i = 0; i < j; ++i) {
-          const double a = h[i], b = h[i + 1];
-          h[i] = c[i] * a + sv[i] * b;
-          h[i + 1] = -sv[i] * a + c[i] * b;
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, n, (const double*)V, (const double*)V, nr,
+                       C.d_gm_wpart, (const int*)nullptr);
+    hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_gm_wpart, gs,
+                       C.d_gm_g, m, cap);
+    hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)V, (const double*)gs->ss,
+                       V, nr, (const int*)nullptr);
+    for (int b = 0; b < nblocks; ++b) {
+      const int j0 = b * chk, j1 = std::min(m, j0 + chk);
+      if (graph) {
+        if (!C.gm_graphs[b]) {
+          HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          hipGraph_t g = nullptr;
+          try {
+            for (int j = j0; j < j1; ++j) gmres_iteration<T>(C, j);
+          } catch (...) {
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          HIPCHK(hipStreamEndCapture(st, &g));
+          hipError_t e = hipGraphInstantiate(&C.gm_graphs[b], g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          HIPCHK(e);
         }
-        const double d = std::hypot(h[j], h[j + 1]);
-        c[j] = d > 0.0 ? h[j] / d : 1.0;
-        sv[j] = d > 0.0 ? h[j + 1] / d : 0.0;
-        h[j] = d;
-        h[j + 1] = 0.0;
-        double* gr = &g[(size_t)r * (m + 1)];
-        gr[j + 1] = -sv[j] * gr[j];
-        gr[j] = c[j] * gr[j];
-        cols[r] = j + 1;
-        iters[r] = total;
-        relres[r] = std::fabs(gr[j + 1]) / bnorm[r];
-        if (relres[r] <= C.opt.cg_tol) conv[r] = true;
+        HIPCHK(hipGraphLaunch(C.gm_graphs[b], st));
+      } else {
+        for (int j = j0; j < j1; ++j) gmres_iteration<T>(C, j);
       }
-      if (all_conv()) break;
+      HIPCHK(hipGetLastError());
+      read_state();
+      if (C.h_gm_st->stop) break;
     }
     // lam += V y, y from the triangular systems of each RHS's first cols columns
-    int jmax = 0;
-    std::fill(y.begin(), y.end(), 0.0);
-    for (int r = 0; r < nr; ++r) {
-      const int k = cols[r];
-      jmax = std::max(jmax, k);
-      const double* gr = &g[(size_t)r * (m + 1)];
-      for (int i = k - 1; i >= 0; --i) {
-        double v = gr[i];
-        for (int q = i + 1; q < k; ++q) v -= H[((size_t)r * m + q) * (m + 1) + i] * y[(size_t)q * kMaxRhs + r];
-        const double diag = H[((size_t)r * m + i) * (m + 1) + i];
-        y[(size_t)i * kMaxRhs + r] = diag != 0.0 ? v / diag : 0.0;
-      }
-    }
-    if (jmax > 0) {
-      HIPCHK(hipMemcpyAsync(C.d_gm_y, y.data(), (size_t)jmax * kMaxRhs * sizeof(double), hipMemcpyHostToDevice, st));
-      hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, jmax, (const double*)V, ldv,
-                         (const double*)C.d_gm_y, 1.0, C.d_lam2, nr);
-      HIPCHK(hipStreamSynchronize(st));
-    }
+    hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(kScalarThreads), 0, st, nr, gs, (const double*)C.d_gm_H,
+                       (const double*)C.d_gm_g, C.d_gm_y, m);
+    hipLaunchKernelGGL(k_mupdate, dim3(nblk(nl)), dim3(256), 0, st, n, m, (const double*)V, ldv,
+                       (const double*)C.d_gm_y, 1.0, C.d_lam2, nr, (const int*)&gs->jmax);
+    // a cycle that ran out of columns restarts unless the cap is reached
+    if (!C.h_gm_st->stop && C.h_gm_st->total >= cap) break;
   }
   HIPCHK(hipGetLastError());
-  return all_conv() ? DD_OK : DD_ERR_NO_CONVERGENCE;
+  const GmState& hs = *C.h_gm_st;
+  bool all = true;
+  for (int r = 0; r < nr; ++r) {
+    iters[r] = hs.iters[r];
+    relres[r] = hs.relres[r];
+    if (!hs.conv[r]) all = false;
+  }
+  return all ? DD_OK : DD_ERR_NO_CONVERGENCE;
 }
 
 static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, double* out) {
@@ -2237,12 +2262,13 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
     // residual, or its own product in the FP64 form)
     // (g_t3 still holds J^{n+1/2} per unknown, converted for the load)
     if (stats && !have_tx) csr_launch(C, st, 3, C.g_e, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_r);
-    unsigned long long* gmax = stats ? (unsigned long long*)C.d_gmax : nullptr;
-    if (gmax) hipLaunchKernelGGL(k_zero<double>, dim3(1), dim3(64), 0, st, (int64_t)2 * nr, C.d_gmax, (const int*)nullptr);
+    double* gpart = stats ? C.d_gpart : nullptr;
     const int vpb = (256 - 256 % nr) / nr;
-    hipLaunchKernelGGL(k_gauss_step, dim3(nblk(C.P.nv, vpb)), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGaussBlocks, nblk(C.P.nv, vpb)));
+    hipLaunchKernelGGL(k_gauss_step, dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
                        C.d_vdof, C.d_nodeint, (const double*)C.g_t3, C.dt, stats ? (const double*)C.g_t2 : nullptr,
-                       C.d_q, gmax);
+                       C.d_q, gpart);
+    if (stats) hipLaunchKernelGGL(k_gauss_max, dim3(1), dim3(64), 0, st, (int)gb, nr, (const double*)C.d_gpart, C.d_gmax);
     if (stats) {
       HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * nr * 2, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -2802,7 +2828,16 @@ static void build_dp2(Ctx& C, const double* coords, const double* eps, const dou
   C.d_code2 = upload(code2, C.owned, st);
   C.d_partner2 = upload(partner2, C.owned, st);
   C.d_rrp = upload(rrp, C.owned, st);
-  C.d_rci = upload(rci, C.owned, st);
+  {
+    // the local row of every column's side (the side order is that of d_grow)
+    std::vector<int64_t> row_of(ns);
+    for (int s = 0; s < nsub; ++s)
+      for (int64_t x = gbase[s]; x < gbase[s + 1]; ++x)
+        row_of[x] = C.subs_h[s].row_off + (int64_t)P.subs[s].kI * NB + (x - gbase[s]);
+    std::vector<int64_t> rrow(rci.size());
+    for (size_t j = 0; j < rci.size(); ++j) rrow[j] = row_of[rci[j]];
+    C.d_rrow = upload(rrow, C.owned, st);
+  }
   C.d_rval = upload(rval, C.owned, st);
   C.n_radd = (int64_t)apos.size();
   C.d_radd_pos = upload(apos, C.owned, st);
@@ -2814,8 +2849,14 @@ static void build_dp2(Ctx& C, const double* coords, const double* eps, const dou
   C.d_gm_partial = dalloc<double>((size_t)(kGmresRestart + 1) * kDotBlocks * kMaxRhs, C.owned);
   C.d_gm_h = dalloc<double>((size_t)(kGmresRestart + 1) * kMaxRhs, C.owned);
   C.d_gm_tot = dalloc<double>((size_t)(kGmresRestart + 1) * kMaxRhs, C.owned);
-  C.d_gm_ss = dalloc<double>(kMaxRhs, C.owned);
   C.d_gm_y = dalloc<double>((size_t)kGmresRestart * kMaxRhs, C.owned);
+  C.d_gm_wpart = dalloc<double>((size_t)kDotBlocks * kMaxRhs, C.owned);  // |rhs|^2, |r0|^2 block shares
+  C.d_gm_H = dalloc<double>((size_t)nr * kGmresRestart * (kGmresRestart + 1), C.owned);
+  C.d_gm_cs = dalloc<double>((size_t)nr * kGmresRestart, C.owned);
+  C.d_gm_sn = dalloc<double>((size_t)nr * kGmresRestart, C.owned);
+  C.d_gm_g = dalloc<double>((size_t)nr * (kGmresRestart + 1), C.owned);
+  C.d_gm_st = dalloc<GmState>(1, C.owned);
+  HIPCHK(hipHostMalloc((void**)&C.h_gm_st, sizeof(GmState), hipHostMallocDefault));
 }
 
 // ---- particle tables (built on the first particle call) --------------------------

@@ -2240,12 +2240,14 @@ __global__ void k_gauss(int64_t nv, const int64_t* __restrict__ vptr, const int3
 // and the maxima over vertices of |G^T (T e^{n+1}) + q| (interior vertices)
 // and |q|.  Thread (v, r) = (t / nrhs, t % nrhs) of a workgroup of bs = 256 -
 // 256 % nrhs threads (whole vertices, the right-hand sides of a vertex in
-// neighbouring lanes: shared lists, contiguous J, Tx and q rows).  vdof
-// lists the unknowns at each vertex (d << 1 | tail).  J and Tx are per
-// unknown [nint][nrhs] (Tx nullptr: charge update only), q [nv][nrhs].  The
-// maxima of a workgroup go to out[r * 2 + {0, 1}] by an integer atomic max
-// on the bit patterns (order-free, exact for non-negative doubles, and a NaN
-// residual wins), so out must be zero before the launch.
+// neighbouring lanes: shared lists, contiguous J, Tx and q rows); the grid
+// of kGaussBlocks workgroups strides over the vertices.  vdof lists the
+// unknowns at each vertex (d << 1 | tail).  J and Tx are per unknown
+// [nint][nrhs] (Tx nullptr: charge update only), q [nv][nrhs].  With part,
+// the maxima of each workgroup go to part[blockIdx.x][2 r + {0, 1}] and
+// k_gauss_max takes the maxima over workgroups (a NaN residual wins).
+constexpr int kGaussBlocks = 1024;
+
 __device__ __forceinline__ double nan_max(double a, double b) {
   return (a != a || b != b) ? NAN : fmax(a, b);
 }
@@ -2255,27 +2257,44 @@ __global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const 
                                                     const uint8_t* __restrict__ node_int,
                                                     const double* __restrict__ J, double dt,
                                                     const double* __restrict__ Tx, double* __restrict__ q,
-                                                    unsigned long long* __restrict__ out) {
+                                                    double* __restrict__ part) {
   const int bs = 256 - 256 % nrhs, vpb = bs / nrhs;
   const int t = threadIdx.x, r = t % nrhs;
-  const int64_t v = (int64_t)blockIdx.x * vpb + t / nrhs;
   double mres = 0.0, mq = 0.0;
-  if (t < bs && v < nv && node_int[v]) {  // the charge of boundary vertices stays 0
+  for (int64_t v = (int64_t)blockIdx.x * vpb + t / nrhs; t < bs && v < nv; v += (int64_t)gridDim.x * vpb) {
+    if (!node_int[v]) continue;  // the charge of boundary vertices stays 0
     double sj = 0.0, st = 0.0;
-    for (int64_t k = vptr[v]; k < vptr[v + 1]; ++k) {
-      const int32_t code = vdof[k];
-      const int64_t d = code >> 1;
-      const double sg = (code & 1) ? -1.0 : 1.0;
-      sj += sg * J[d * nrhs + r];
-      if (Tx) st += sg * Tx[d * nrhs + r];
+    // batches of GB incident unknowns: their codes first, then all their
+    // value loads in flight at once (reads past the list end are clamped
+    // and not used), summed in list order
+    constexpr int GB = 8;
+    const int64_t k0 = vptr[v], k1 = vptr[v + 1];
+    for (int64_t kb = k0; kb < k1; kb += GB) {
+      int32_t code[GB];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) code[u] = vdof[kb + u < k1 ? kb + u : k1 - 1];
+      double jv[GB], tv[GB];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int64_t o = (int64_t)(code[u] >> 1) * nrhs + r;
+        jv[u] = J[o];
+        tv[u] = Tx ? Tx[o] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < GB; ++u)
+        if (kb + u < k1) {
+          const double sg = (code[u] & 1) ? -1.0 : 1.0;
+          sj += sg * jv[u];
+          st += sg * tv[u];
+        }
     }
     const int64_t o = v * nrhs + r;
     const double qn = q[o] + dt * sj;
     q[o] = qn;
-    mq = fabs(qn);
-    mres = fabs(st + qn);
+    mq = fmax(mq, fabs(qn));
+    mres = nan_max(mres, fabs(st + qn));
   }
-  if (!out) return;
+  if (!part) return;
   __shared__ double red[2][256];
   red[0][t] = mres;
   red[1][t] = mq;
@@ -2286,9 +2305,19 @@ __global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const 
       a = nan_max(a, red[0][u]);
       b = fmax(b, red[1][u]);
     }
-    atomicMax(&out[2 * t], (unsigned long long)__double_as_longlong(a));
-    atomicMax(&out[2 * t + 1], (unsigned long long)__double_as_longlong(b));
+    part[(int64_t)blockIdx.x * 2 * kMaxRhs + 2 * t] = a;
+    part[(int64_t)blockIdx.x * 2 * kMaxRhs + 2 * t + 1] = b;
   }
+}
+
+// out[2 r + {0, 1}] = the maxima of the nb workgroups' part rows
+__global__ void __launch_bounds__(64) k_gauss_max(int nb, int nrhs, const double* __restrict__ part,
+                                                  double* __restrict__ out) {
+  const int t = threadIdx.x;
+  if (t >= 2 * nrhs) return;
+  double m = 0.0;
+  for (int b = 0; b < nb; ++b) m = (t & 1) ? fmax(m, part[(int64_t)b * 2 * kMaxRhs + t]) : nan_max(m, part[(int64_t)b * 2 * kMaxRhs + t]);
+  out[t] = m;
 }
 
 // q [nv][nrhs] <- src [nrhs][nv] (or 0 with src == nullptr)
