@@ -109,6 +109,15 @@ typedef struct {
                          read a cached zero tile instead of memory */
   int from_cache;     /* 1: read from the cache, no timing */
   double full_ms, full_ms_default, coarse_ms, coarse_ms_default, trailing_ms, trailing_ms_default;
+  int sym_persist;    /* symmetric product of the interface operator: workgroups of a persistent
+                         grid (a multiple of 8), or 0 for one workgroup per four work items; a
+                         smaller grid leaves wave slots to the corner and coarse chain that runs
+                         beside it */
+  double local_ms, local_ms_default;  /* one local response (symmetric product beside the
+                         corner and coarse chain), tuned and before tuning */
+  int sym_pw;         /* symmetric product, FP32 factors: 2 = panels of two interface blocks (half
+                         the accumulators per wave, twice the partial slots), 0 = four; FP64
+                         factors always use two */
 } dd_tuning;
 
 enum { DD_DIAG_GAUSS = 1, DD_DIAG_ENERGY = 2 };

@@ -31,7 +31,9 @@ class Tuning(C.Structure):
                 ("full_quarter", C.c_int), ("from_cache", C.c_int),
                 ("full_ms", C.c_double),
                 ("full_ms_default", C.c_double), ("coarse_ms", C.c_double), ("coarse_ms_default", C.c_double),
-                ("trailing_ms", C.c_double), ("trailing_ms_default", C.c_double)]
+                ("trailing_ms", C.c_double), ("trailing_ms_default", C.c_double),
+                ("sym_persist", C.c_int), ("local_ms", C.c_double), ("local_ms_default", C.c_double),
+                ("sym_pw", C.c_int)]
 
 
 DD_DIAG_GAUSS, DD_DIAG_ENERGY = 1, 2

@@ -108,6 +108,10 @@ struct Tuning {
   int full_pair = 0;      // full passes, 9..32 RHS: 1 = two output rows per wave sharing the input
                           // loads; 2 = eight rows per workgroup sharing them through LDS
   int full_quarter = 1;   // full passes: lanes of all-zero 16 x 16 tile quarters read the zero tile
+  int sym_pw = 0;         // symmetric product: panel width (FP32: 2 or 4; 0 = 4; FP64: always 2)
+  int sym_persist = 0;    // symmetric product: workgroups of a persistent grid (a multiple of 8), so
+                          // that the corner and coarse chain beside it keeps free wave slots;
+                          // 0 = one workgroup per four items
 };
 
 struct Ctx {
@@ -257,6 +261,7 @@ struct Ctx {
     MvOut* outs = nullptr;
     int64_t n_out = 0;
     void* partial = nullptr;
+    int pw = 0;  // panel width the list was built for
   } sym;
   // work vectors
   void* X[10] = {};
@@ -453,9 +458,23 @@ constexpr int sym_panel() {
   return sizeof(T) == 4 ? 4 : 2;
 }
 
+static void release(Ctx& C, void* p);
+
+// panel width of the symmetric product for the context's precision and tuning
+static int sym_width(const Ctx& C) {
+  if (!C.fp32) return sym_panel<double>();
+  return C.tuning.sym_pw == 2 ? 2 : sym_panel<float>();
+}
+
 // Work list of the symmetric product: panel pairs (P, Q), P >= Q, of every
-// subdomain's interface tiles; kG * nP partial slots per subdomain.
+// subdomain's interface tiles; kG * nP partial slots per subdomain.  A
+// previous list (another panel width) is released.
 static void make_sym_list(Ctx& C, int pw, size_t wsz) {
+  release(C, C.sym.d);
+  release(C, C.sym.outs);
+  release(C, C.sym.partial);
+  C.sym = Ctx::SymList{};
+  C.sym.pw = pw;
   std::vector<SymItem> v;
   std::vector<MvOut> outs;
   int64_t slot = 0;
@@ -917,7 +936,7 @@ static void build_device(Ctx& C, const double* coords) {
     C.trail_N = make_items(C, tN, C.tuning.chunk);
     C.trail_T = make_items(C, tT, C.tuning.chunk);
     // runs beside the coarse chain: own partial slots
-    make_sym_list(C, C.fp32 ? sym_panel<float>() : sym_panel<double>(), wsz);
+    make_sym_list(C, sym_width(C), wsz);
     C.corner_N = make_items(C, cN, C.tuning.chunk);
     // (summing the symmetric partials inside this pass instead of a reduce on
     // the side stream measured slower: it lengthens the main-stream chain)
@@ -1532,14 +1551,24 @@ static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side) 
   hipEvent_t e0, e1;
   bool timed = prof_begin(C, DD_PROF_SCHUR, &e0, &e1);
   hipStream_t s = side ? C.st2 : C.st;
-  constexpr int PW = sym_panel<T>();
-  const dim3 grid((unsigned)((C.sym.n + 3) / 4));
-  if (C.nrhs <= 16)
-    hipLaunchKernelGGL((k_symv<T, 1, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,
-                       (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip);
-  else
-    hipLaunchKernelGGL((k_symv<T, 2, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,
-                       (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip);
+  int64_t ng = (C.sym.n + 3) / 4;
+  if (C.tuning.sym_persist > 0) ng = std::min<int64_t>(ng, C.tuning.sym_persist);
+  const dim3 grid((unsigned)ng);
+#define DD_SYMV(NB16, PW)                                                                                     \
+  hipLaunchKernelGGL((k_symv<T, NB16, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,      \
+                     (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip)
+  if (sizeof(T) == 4 && C.sym.pw == 4) {
+    if (C.nrhs <= 16)
+      DD_SYMV(1, 4);
+    else
+      DD_SYMV(2, 4);
+  } else {
+    if (C.nrhs <= 16)
+      DD_SYMV(1, 2);
+    else
+      DD_SYMV(2, 2);
+  }
+#undef DD_SYMV
   hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)C.sym.n_out), dim3(256), 0, s, C.sym.n_out, C.sym.outs,
                      C.d_subs, (const T*)C.sym.partial, (T*)out, (const T*)nullptr, (T)1, (const T*)nullptr, (T)1,
                      C.nrhs, skip);
@@ -1786,6 +1815,15 @@ static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, dou
   }
 }
 
+// z = K_lam r (the lumped preconditioner) with the r.z and r.r partials:
+// two rows in flight per lane, their nonzeros in batches of 8 (batches of
+// 12 held more registers than four waves per SIMD allow and spilled: 19.65
+// against 19.40 ms/step; one row of 12: 19.75; four rows of 6: 20.02)
+static void lam_precond(Ctx& C, const int* skip) {
+  hipLaunchKernelGGL((k_lam_precond<2, 8>), dim3(kDotBlocks), dim3(256), 0, C.st, C.nlam, C.d_lrp, C.d_lci,
+                     C.d_lvals, (const double*)C.d_res, C.d_z, C.nrhs, C.d_partial, C.d_partial2, skip);
+}
+
 // x = A^-1 b (one decomposed solve, unknown-major [nint][nrhs] FP64).
 // Returns DD_OK or DD_ERR_NO_CONVERGENCE; fills iters/relres.
 // Captured form (fixed_iters > 0, inside a stream capture): exactly
@@ -1860,15 +1898,14 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     // p = z = K_lam r (lumped preconditioner), or p = r
     const bool pre = C.opt.precond == 1 && C.lam_nnz > 0;
     if (pre) {
-      hipLaunchKernelGGL(k_lam_precond, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrp, C.d_lci, C.d_lvals,
-                         (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, gate);
+      lam_precond(C, gate);
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 4, nr, (const double*)C.d_partial,
                          (const double*)nullptr, C.d_cg, C.opt.cg_tol, gate);
     }
     hipLaunchKernelGGL(k_copy, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)(pre ? C.d_z : C.d_res), C.d_p,
                        gate);
-    // v = B_s^T p for the first F application (later ones are written by
-    // k_cg_p_gather)
+    // v = B_s^T p for the first F application, padding rows zeroed (later
+    // ones are written by k_cg_p_scatter, which leaves padding rows alone)
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                        C.d_glam, (const double*)C.d_p, (T*)X[5], nr, gate);
     const int* done = &C.d_cg->done;
@@ -1889,8 +1926,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       if (pre) {
         hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
                            (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
-        hipLaunchKernelGGL(k_lam_precond, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrp, C.d_lci, C.d_lvals,
-                           (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, done);
+        lam_precond(C, done);
         hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
                            (const double*)C.d_partial2, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
       } else {
@@ -1899,9 +1935,11 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
         hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
                            (const double*)C.d_partial, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
       }
-      hipLaunchKernelGGL(k_cg_p_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                         C.d_glam, nr, (const CgState*)C.d_cg, (const double*)(pre ? C.d_z : C.d_res),
-                         (const double*)pc, pn, (T*)X[5]);
+      // p' and v = B_s^T p' in multiplier order (a gather over the interface
+      // rows computed each p' twice: 19.65 against 19.40 ms/step)
+      hipLaunchKernelGGL(k_cg_p_scatter<T>, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1, nr,
+                         (const CgState*)C.d_cg, (const double*)(pre ? C.d_z : C.d_res), (const double*)pc, pn,
+                         (T*)X[5]);
     };
     // captured step: a fixed number of iterations, the state snapshotted
     if (captured) {
@@ -2376,6 +2414,7 @@ static void rebuild_lists(Ctx& C, int which) {
     remake(C.co_T, C.blk_co_T, C.tuning.coarse_chunk, false, 1);
   }
   if ((which & 4) && C.full_N.d) build_full_items<T>(C);
+  if ((which & 8) && C.sym.pw != sym_width(C)) make_sym_list(C, sym_width(C), sizeof(T));
   ensure_partial<T>(C);
 }
 
@@ -2437,6 +2476,9 @@ static bool tune_cache_read(const std::string& path, const std::string& key, Tun
     c.full_persist = (fp > 0 && fp % 8 == 0 && fp <= (1L << 24)) ? (int)fp : 0;
     c.full_pair = (fpair == 1 || fpair == 2) ? (int)fpair : 0;
     c.full_quarter = json_int(line, "full_quarter") == 0 ? 0 : 1;
+    const long sp = json_int(line, "sym_persist");
+    c.sym_persist = (sp > 0 && sp % 8 == 0 && sp <= (1L << 24)) ? (int)sp : 0;
+    c.sym_pw = json_int(line, "sym_pw") == 2 ? 2 : 0;
     t = c;
     found = true;  // the last entry for a key wins
   }
@@ -2451,12 +2493,13 @@ static void tune_cache_append(const std::string& path, const std::string& key, c
   std::fprintf(f,
                "{\"key\": \"%s\", \"chunk\": %d, \"coarse_chunk\": %d, \"full_chunk\": %d, "
                "\"full_bucket\": %d, \"full_persist\": %d, \"full_pair\": %d, \"full_quarter\": %d, "
+               "\"sym_pw\": %d, \"sym_persist\": %d, \"local_ms\": %.5f, \"local_ms_default\": %.5f, "
                "\"full_ms\": %.5f, "
                "\"full_ms_default\": %.5f, "
                "\"coarse_ms\": %.5f, \"coarse_ms_default\": %.5f, \"trailing_ms\": %.5f, "
                "\"trailing_ms_default\": %.5f}\n",
                key.c_str(), t.chunk, t.coarse_chunk, t.full_chunk, t.full_bucket, t.full_persist, t.full_pair,
-               t.full_quarter, r.full_ms,
+               t.full_quarter, t.sym_pw, t.sym_persist, r.local_ms, r.local_ms_default, r.full_ms,
                r.full_ms_default, r.coarse_ms, r.coarse_ms_default, r.trailing_ms, r.trailing_ms_default);
   std::fclose(f);
 }
@@ -2608,6 +2651,35 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   }
   C.tuning = best;
   rebuild_lists<T>(C, 1);
+  // the local response of one interface-operator application: the
+  // symmetric product on the side stream beside the corner and coarse chain
+  // (a persistent grid of the symmetric product leaves the chain free slots)
+  if (C.sym.n > 0 && C.Kc > 0) {
+    auto local = [&] { apply_local<T>(C, nullptr); };
+    r.local_ms_default = r.local_ms = timed(local);
+    if (C.fp32) {
+      // panel width 2: half the accumulators per wave (more waves per SIMD),
+      // twice the partial slots
+      C.tuning.sym_pw = 2;
+      rebuild_lists<T>(C, 8);
+      const double t = timed(local);
+      if (t < r.local_ms) {
+        r.local_ms = t;
+        best.sym_pw = 2;
+      }
+      C.tuning = best;
+      rebuild_lists<T>(C, 8);
+    }
+    for (int pg : {256, 512, 768, 1024, 1536, 2048}) {
+      C.tuning.sym_persist = pg;
+      const double t = timed(local);
+      if (t < r.local_ms) {
+        r.local_ms = t;
+        best.sym_persist = pg;
+      }
+    }
+    C.tuning = best;
+  }
   C.prof = prof;
   r.chunk = best.chunk;
   r.coarse_chunk = best.coarse_chunk;
@@ -2616,6 +2688,8 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   r.full_persist = best.full_persist;
   r.full_pair = best.full_pair;
   r.full_quarter = best.full_quarter;
+  r.sym_persist = best.sym_persist;
+  r.sym_pw = best.sym_pw;
   if (out) *out = r;
 }
 
@@ -2628,7 +2702,7 @@ static void autotune(Ctx& C, const char* cache, dd_tuning* out) {
   Tuning t;
   if (cache && *cache && tune_cache_read(cache, key, t)) {
     C.tuning = t;
-    rebuild_lists<T>(C, 7);
+    rebuild_lists<T>(C, 15);
     r.chunk = t.chunk;
     r.coarse_chunk = t.coarse_chunk;
     r.full_chunk = t.full_chunk;
@@ -2636,6 +2710,8 @@ static void autotune(Ctx& C, const char* cache, dd_tuning* out) {
     r.full_persist = t.full_persist;
     r.full_pair = t.full_pair;
     r.full_quarter = t.full_quarter;
+    r.sym_persist = t.sym_persist;
+    r.sym_pw = t.sym_pw;
     r.from_cache = 1;
   } else {
     autotune_impl<T>(C, &r);

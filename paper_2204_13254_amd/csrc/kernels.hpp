@@ -1136,140 +1136,143 @@ __global__ void __launch_bounds__(256) k_symv(int64_t n_items, const SymItem* __
   if (skip && *skip) return;
   __shared__ T lds[4][kNB][kNB + 1];
   const int wv = threadIdx.x >> 6;
-  const int64_t wi = (int64_t)blockIdx.x * 4 + wv;
-  if (wi >= n_items) return;  // (no workgroup barriers below: waves are independent)
-  const SymItem it = items[wi];
-  if (it.s < 0) return;
-  const SubDev q = subs[it.s];
-  const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
-  const int kG = q.kG;
-  const int nP = (kG + PW - 1) / PW;
-  const bool diag = it.P == it.Q;
-  const int o0 = it.P * PW, m0 = it.Q * PW;
-  const T* mb = mt + m_off[it.s] * kTile;
-  const T* xg = in + (q.row_off + (int64_t)q.kI * kNB) * nrhs;
-  T(*sh)[kNB + 1] = lds[wv];
-  using acc_t = typename Mfma<T>::acc_t;
-  acc_t racc[PW][2][NB16], cacc[PW][2][NB16];
+  // one item per wave; a grid smaller than the item groups walks them
+  // (groups b, b + G, ...: G a multiple of 8 keeps a workgroup on its XCD).
+  // No workgroup barriers below: waves are independent.
+  for (int64_t wi = (int64_t)blockIdx.x * 4 + wv; wi < n_items; wi += (int64_t)gridDim.x * 4) {
+    const SymItem it = items[wi];
+    if (it.s < 0) continue;
+    const SubDev q = subs[it.s];
+    const int l = threadIdx.x & 63, g = l >> 4, i = l & 15;
+    const int kG = q.kG;
+    const int nP = (kG + PW - 1) / PW;
+    const bool diag = it.P == it.Q;
+    const int o0 = it.P * PW, m0 = it.Q * PW;
+    const T* mb = mt + m_off[it.s] * kTile;
+    const T* xg = in + (q.row_off + (int64_t)q.kI * kNB) * nrhs;
+    T(*sh)[kNB + 1] = lds[wv];
+    using acc_t = typename Mfma<T>::acc_t;
+    acc_t racc[PW][2][NB16], cacc[PW][2][NB16];
 #pragma unroll
-  for (int a = 0; a < PW; ++a)
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int nb = 0; nb < NB16; ++nb) {
-        racc[a][h][nb] = acc_t{0, 0, 0, 0};
-        cacc[a][h][nb] = acc_t{0, 0, 0, 0};
-      }
-  auto valid = [&](int t) -> bool {
-    const int jr = t / PW, jc = t % PW;
-    return o0 + jr < kG && m0 + jc < kG && (!diag || jc <= jr);
-  };
-  auto next_valid = [&](int t) -> int {
-    for (int u = t + 1; u < PW * PW; ++u)
-      if (valid(u)) return u;
-    return -1;
-  };
-  auto tile_of = [&](int t) -> const T* {
-    const int o = o0 + t / PW, m = m0 + t % PW;
-    return mb + ((int64_t)o * (o + 1) / 2 + m) * kTile;
-  };
-  // xv[nb*8 + ks] = u[block b][row 8g + ks][rhs nb*16 + i]
-  // (unconditional loads from a clamped column, as in k_tile_mv)
-  auto load_x = [&](int b, T* xv) {
-    const T* xb = xg + (int64_t)b * kNB * nrhs;
-#pragma unroll
-    for (int nb = 0; nb < NB16; ++nb) {
-      const int col = nb * 16 + i;
-      const int cc = col < nrhs ? col : nrhs - 1;
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        const T v = xb[(8 * g + ks) * nrhs + cc];
-        xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
-      }
-    }
-  };
-  // u_m is prefetched with each tile; u_o only changes with the row (loaded
-  // at its first tile, covered by the row part's MFMAs)
-  T cur[16], nxt[16], xm[8 * NB16], xmn[8 * NB16], xo[8 * NB16];
-  // tile 0 = (o0, m0) is always valid: o0 < kG and m0 <= o0
-  load_chunk8(tile_of(0), l, cur);
-  load_chunk8(tile_of(0) + 512, l, cur + 8);
-  load_x(m0, xm);
-  load_x(o0, xo);
-#pragma unroll
-  for (int t = 0; t < PW * PW; ++t) {
-    if (!valid(t)) continue;
-    const int jr = t / PW, jc = t % PW;
-    if (jc == 0 && jr > 0) load_x(o0 + jr, xo);
-    const int tn = next_valid(t);
-    if (tn >= 0) {
-      const T* tp = tile_of(tn);
-      load_chunk8(tp, l, nxt);
-      load_chunk8(tp + 512, l, nxt + 8);
-      load_x(m0 + tn % PW, xmn);
-    }
-#pragma unroll
-    for (int nb = 0; nb < NB16; ++nb)
-#pragma unroll
-      for (int ks = 0; ks < 8; ++ks) {
-        racc[jr][0][nb] = Mfma<T>::op(cur[ks], xm[nb * 8 + ks], racc[jr][0][nb]);
-        racc[jr][1][nb] = Mfma<T>::op(cur[8 + ks], xm[nb * 8 + ks], racc[jr][1][nb]);
-      }
-    if (!diag || jc != jr) {
-      // column part: lane (g, i) needs M(8g + ks, cb*16 + i)
-      wave_lds_sync();
+    for (int a = 0; a < PW; ++a)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) sh[h * 16 + i][8 * g + ks] = cur[h * 8 + ks];
-      wave_lds_sync();
-      T tt[16];
+        for (int nb = 0; nb < NB16; ++nb) {
+          racc[a][h][nb] = acc_t{0, 0, 0, 0};
+          cacc[a][h][nb] = acc_t{0, 0, 0, 0};
+        }
+    auto valid = [&](int t) -> bool {
+      const int jr = t / PW, jc = t % PW;
+      return o0 + jr < kG && m0 + jc < kG && (!diag || jc <= jr);
+    };
+    auto next_valid = [&](int t) -> int {
+      for (int u = t + 1; u < PW * PW; ++u)
+        if (valid(u)) return u;
+      return -1;
+    };
+    auto tile_of = [&](int t) -> const T* {
+      const int o = o0 + t / PW, m = m0 + t % PW;
+      return mb + ((int64_t)o * (o + 1) / 2 + m) * kTile;
+    };
+    // xv[nb*8 + ks] = u[block b][row 8g + ks][rhs nb*16 + i]
+    // (unconditional loads from a clamped column, as in k_tile_mv)
+    auto load_x = [&](int b, T* xv) {
+      const T* xb = xg + (int64_t)b * kNB * nrhs;
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
+      for (int nb = 0; nb < NB16; ++nb) {
+        const int col = nb * 16 + i;
+        const int cc = col < nrhs ? col : nrhs - 1;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) tt[cb * 8 + ks] = sh[8 * g + ks][cb * 16 + i];
+        for (int ks = 0; ks < 8; ++ks) {
+          const T v = xb[(8 * g + ks) * nrhs + cc];
+          xv[nb * 8 + ks] = col < nrhs ? v : (T)0;
+        }
+      }
+    };
+    // u_m is prefetched with each tile; u_o only changes with the row (loaded
+    // at its first tile, covered by the row part's MFMAs)
+    T cur[16], nxt[16], xm[8 * NB16], xmn[8 * NB16], xo[8 * NB16];
+    // tile 0 = (o0, m0) is always valid: o0 < kG and m0 <= o0
+    load_chunk8(tile_of(0), l, cur);
+    load_chunk8(tile_of(0) + 512, l, cur + 8);
+    load_x(m0, xm);
+    load_x(o0, xo);
+#pragma unroll
+    for (int t = 0; t < PW * PW; ++t) {
+      if (!valid(t)) continue;
+      const int jr = t / PW, jc = t % PW;
+      if (jc == 0 && jr > 0) load_x(o0 + jr, xo);
+      const int tn = next_valid(t);
+      if (tn >= 0) {
+        const T* tp = tile_of(tn);
+        load_chunk8(tp, l, nxt);
+        load_chunk8(tp + 512, l, nxt + 8);
+        load_x(m0 + tn % PW, xmn);
+      }
 #pragma unroll
       for (int nb = 0; nb < NB16; ++nb)
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks) {
-          cacc[jc][0][nb] = Mfma<T>::op(tt[ks], xo[nb * 8 + ks], cacc[jc][0][nb]);
-          cacc[jc][1][nb] = Mfma<T>::op(tt[8 + ks], xo[nb * 8 + ks], cacc[jc][1][nb]);
+          racc[jr][0][nb] = Mfma<T>::op(cur[ks], xm[nb * 8 + ks], racc[jr][0][nb]);
+          racc[jr][1][nb] = Mfma<T>::op(cur[8 + ks], xm[nb * 8 + ks], racc[jr][1][nb]);
         }
+      if (!diag || jc != jr) {
+        // column part: lane (g, i) needs M(8g + ks, cb*16 + i)
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) sh[h * 16 + i][8 * g + ks] = cur[h * 8 + ks];
+        wave_lds_sync();
+        T tt[16];
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) tt[cb * 8 + ks] = sh[8 * g + ks][cb * 16 + i];
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            cacc[jc][0][nb] = Mfma<T>::op(tt[ks], xo[nb * 8 + ks], cacc[jc][0][nb]);
+            cacc[jc][1][nb] = Mfma<T>::op(tt[8 + ks], xo[nb * 8 + ks], cacc[jc][1][nb]);
+          }
+      }
+      if (tn >= 0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+#pragma unroll
+        for (int u = 0; u < 8 * NB16; ++u) xm[u] = xmn[u];
+      }
     }
-    if (tn >= 0) {
+    // ---- partial blocks ---------------------------------------------------------
+    auto write = [&](int b, int j, const acc_t (&a)[2][NB16], const acc_t (&c)[2][NB16], bool both) {
+      T* dst = partial + (int64_t)(it.slot0 + b * nP + j) * kNB * nrhs;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int u = 0; u < 8 * NB16; ++u) xm[u] = xmn[u];
-    }
-  }
-  // ---- partial blocks ---------------------------------------------------------
-  auto write = [&](int b, int j, const acc_t (&a)[2][NB16], const acc_t (&c)[2][NB16], bool both) {
-    T* dst = partial + (int64_t)(it.slot0 + b * nP + j) * kNB * nrhs;
+        for (int nb = 0; nb < NB16; ++nb) {
+          const int col = nb * 16 + i;
+          if (col < nrhs) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int nb = 0; nb < NB16; ++nb) {
-        const int col = nb * 16 + i;
-        if (col < nrhs) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = h * 16 + Mfma<T>::row(l, v);
-            dst[(int64_t)row * nrhs + col] = both ? a[h][nb][v] + c[h][nb][v] : a[h][nb][v];
+            for (int v = 0; v < 4; ++v) {
+              const int row = h * 16 + Mfma<T>::row(l, v);
+              dst[(int64_t)row * nrhs + col] = both ? a[h][nb][v] + c[h][nb][v] : a[h][nb][v];
+            }
           }
         }
-      }
-  };
+    };
 #pragma unroll
-  for (int j = 0; j < PW; ++j) {
-    if (o0 + j < kG) {
-      if (diag)
-        write(o0 + j, it.P, racc[j], cacc[j], true);
-      else
-        write(o0 + j, it.Q, racc[j], racc[j], false);
+    for (int j = 0; j < PW; ++j) {
+      if (o0 + j < kG) {
+        if (diag)
+          write(o0 + j, it.P, racc[j], cacc[j], true);
+        else
+          write(o0 + j, it.Q, racc[j], racc[j], false);
+      }
+      if (!diag && m0 + j < kG) write(m0 + j, it.P, cacc[j], cacc[j], false);
     }
-    if (!diag && m0 + j < kG) write(m0 + j, it.P, cacc[j], cacc[j], false);
-  }
+  }  // items
 }
 
 // out_o = (add ? add_o : 0) + alpha * sum of the item's partial slots
@@ -1999,6 +2002,7 @@ __global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, con
 
 // z = K_lam r (the lumped preconditioner, CSR in multiplier space), fused
 // with the block partials of r.z (partial) and r.r (partial_b).
+template <int RU, int KB>
 __global__ void __launch_bounds__(256, 4) k_lam_precond(int64_t nlam, const int64_t* __restrict__ rp,
                                                      const int32_t* __restrict__ ci, const double* __restrict__ val,
                                                      const double* __restrict__ res, double* __restrict__ z, int nrhs,
@@ -2010,7 +2014,6 @@ __global__ void __launch_bounds__(256, 4) k_lam_precond(int64_t nlam, const int6
   // clamped indices; padding entries are zeroed at the products), so a pass
   // costs three round trips for RU rows.  Rows, and the nonzeros in a row,
   // are summed in the order of the plain loop.
-  constexpr int RU = 2, KB = 12;
   const int lpr = 256 / nrhs;
   const int tid = threadIdx.x, r = tid % nrhs, lane = tid / nrhs;
   const int64_t stride = (int64_t)gridDim.x * lpr;
@@ -2076,28 +2079,25 @@ __global__ void __launch_bounds__(256, 4) k_lam_precond(int64_t nlam, const int6
 }
 
 // p' = base + beta p for the RHS still active after the beta stage (p kept
-// otherwise; base = z, or r without a preconditioner), written to pnext once
-// per multiplier (from its + copy), and the local interface rows
-// v = B_s^T p' for the next F application.  p alternates between two buffers
-// (a multiplier's two copies would race on one).
+// otherwise; base = z, or r without a preconditioner), once per multiplier
+// (coalesced reads and writes of the multiplier vectors), then v = B_s^T p'
+// scattered to its two interface rows, + in the lower subdomain (row0) and
+// - in the higher (row1).  p alternates between two buffers.  Interface
+// rows without a multiplier (padding) are not written: they keep the zeros
+// of the solve's first gather (k_lambda_gather).
 template <class T>
-__global__ void k_cg_p_gather(int64_t ngrow, const int64_t* __restrict__ rows, const int32_t* __restrict__ lamcode,
-                              int nrhs, const CgState* __restrict__ st, const double* __restrict__ base,
-                              const double* __restrict__ pcur, double* __restrict__ pnext, T* __restrict__ v) {
+__global__ void k_cg_p_scatter(int64_t nlam, const int64_t* __restrict__ row0, const int64_t* __restrict__ row1,
+                               int nrhs, const CgState* __restrict__ st, const double* __restrict__ base,
+                               const double* __restrict__ pcur, double* __restrict__ pnext, T* __restrict__ v) {
   if (st->done) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ngrow * nrhs) return;
-  const int64_t k = i / nrhs;
-  const int r = (int)(i % nrhs);
-  const int32_t c = lamcode[k];
-  T val = (T)0;
-  if (c >= 0) {
-    const int64_t li = (int64_t)(c >> 1) * nrhs + r;
-    const double pn = st->active[r] ? base[li] + st->beta[r] * pcur[li] : pcur[li];
-    if (!(c & 1)) pnext[li] = pn;
-    val = (T)((c & 1) ? -pn : pn);
-  }
-  v[rows[k] * nrhs + r] = val;
+  if (i >= nlam * nrhs) return;
+  const int64_t l = i / nrhs;
+  const int r = (int)(i - l * nrhs);
+  const double pn = st->active[r] ? base[i] + st->beta[r] * pcur[i] : pcur[i];
+  pnext[i] = pn;
+  v[row0[l] * nrhs + r] = (T)pn;
+  v[row1[l] * nrhs + r] = (T)(-pn);
 }
 
 __global__ void k_extrap(int64_t n, const double* __restrict__ a, const double* __restrict__ b,

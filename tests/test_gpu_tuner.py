@@ -76,8 +76,9 @@ def test_tuner_search_cache_and_parity(tmp_path):
 
 def test_odd_shapes_from_cache_keep_parity(tmp_path):
     """Short chunks split almost every row into partial slots (reduced in a
-    fixed order), in every product class, and a 16-workgroup persistent grid
-    walks all work groups of the full passes."""
+    fixed order), in every product class, a 16-workgroup persistent grid
+    walks all work groups of the full passes, and an 8-workgroup one all
+    panel pairs of the symmetric product."""
     from paper_2204_13254_amd.solver import DDSolver
     c, t, p, eps = _case()
     dt = 0.03
@@ -90,9 +91,10 @@ def test_odd_shapes_from_cache_keep_parity(tmp_path):
     key = json.loads(probe.read_text().splitlines()[0])["key"]
     odd = tmp_path / "odd.jsonl"
     odd.write_text(json.dumps({"key": key, "chunk": 2, "coarse_chunk": 3, "full_chunk": 4,
-                               "full_bucket": 1, "full_persist": 16}) + "\n")
+                               "full_bucket": 1, "full_persist": 16, "sym_persist": 8}) + "\n")
     r = s.autotune(odd)
     assert r["from_cache"] == 1 and (r["chunk"], r["full_chunk"], r["full_persist"]) == (2, 4, 16)
+    assert r["sym_persist"] == 8
     assert _err(_steps(s, J), Eo) <= 1e-10
 
 
@@ -123,3 +125,27 @@ def test_row_pair_full_passes(tmp_path, pair, chunk, persist, quarter):
         r = s.autotune(f)
         assert (r["full_pair"], r["full_persist"], r["full_quarter"]) == (pair, persist, quarter)
         assert _err(_steps(s, J), Eo) <= tol, (nrhs, chunk)
+
+
+def test_symmetric_product_shapes(tmp_path):
+    """The interface operator's symmetric product with panels of two
+    interface blocks (twice the partial slots) on a 16-workgroup persistent
+    grid, with 16 and 24 right-hand sides (one and two 16-wide MFMA blocks),
+    FP32 factors with refinement, against the oracle."""
+    from paper_2204_13254_amd.solver import DDSolver
+    c, t, p, eps = _case()
+    dt = 0.03
+    o = NewmarkOracle(c, t, eps=eps, dt=dt)
+    for nrhs in (16, 24):
+        J = dense_random_source(o.d.n_e, ~o.d.pec, 3, dt, 0.05, 0.03, seed=17, nrhs=nrhs)
+        Eo = o.run(J)
+        s = DDSolver(c, t, p, eps, dt=dt, precision="fp32_refine", nrhs=nrhs, cg_tol=1e-6)
+        probe = tmp_path / f"probe{nrhs}.jsonl"
+        s.autotune(probe)
+        key = json.loads(probe.read_text().splitlines()[0])["key"]
+        f = tmp_path / f"sym{nrhs}.jsonl"
+        f.write_text(json.dumps({"key": key, "chunk": 32, "coarse_chunk": 16, "full_chunk": 96,
+                                 "full_bucket": 8, "sym_pw": 2, "sym_persist": 16}) + "\n")
+        r = s.autotune(f)
+        assert r["from_cache"] == 1 and (r["sym_pw"], r["sym_persist"]) == (2, 16)
+        assert _err(_steps(s, J), Eo) <= 1e-8, nrhs
