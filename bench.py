@@ -419,10 +419,11 @@ def roofline(s, per, nrhs, prof):
     nC = per[:, 2].astype(np.int64)
     vec = {   # one read of the input block rows and one write of the output rows
         "trailing": 2 * int(nG.sum()) * nrhs * wsz,
-        "full": 2 * int((nI + nG).sum()) * nrhs * wsz,
+        "full": 2 * int(nI.sum()) * nrhs * wsz,
         "schur": 2 * int(nG.sum()) * nrhs * wsz,
         "corner": int((nG + nC).sum()) * nrhs * wsz,
         "coarse": 2 * int(inf.n_corner) * nrhs * wsz,
+        "cross": int((nI + nG + nC).sum()) * nrhs * wsz,
     }
     algo = {
         "trailing": inf.trailing_bytes + vec["trailing"],
@@ -430,10 +431,12 @@ def roofline(s, per, nrhs, prof):
         "schur": inf.schur_bytes + vec["schur"],
         "corner": inf.corner_bytes + vec["corner"],
         "coarse": inf.coarse_bytes + vec["coarse"],
+        "cross": inf.cross_bytes + vec["cross"],
     }
     label = {"trailing": "interface blocks of the inverse factors",
-             "full": "full inverse factors", "schur": "interface blocks of the local inverses, M u",
-             "corner": "corner rows Psi_Gamma", "coarse": "coarse inverse factor"}
+             "full": "interior inverse factors L_II^-1", "schur": "interface blocks of the local inverses, M u",
+             "corner": "corner rows Psi_Gamma", "coarse": "coarse inverse factor",
+             "cross": "couplings L_GammaI, L_cI to the interior"}
     dom = max(algo, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_ms = dom_ms / max(1, dom_n)
@@ -442,7 +445,7 @@ def roofline(s, per, nrhs, prof):
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": int(algo[dom]), "avg_launch_ms": round(avg_ms, 4),
-            "launches": dom_n}
+            "launches": dom_n, "class": dom}
     other = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                  "GBps": (round(algo[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if k in algo and v[1] else None)}
              for k, v in prof.items()}
@@ -599,10 +602,10 @@ def main():
     last = run["outputs"][-1]
     del run
     roof, other = roofline(s, per, w.nrhs, prof)
-    if roof["kernel"].startswith("k_tile_mv (full"):
+    if roof["class"] in ("full", "cross"):
         # HBM traffic per launch of the dominant class, from committed counter
         # summaries, valid only for the kernel source they were taken on
-        roof["traffic"] = _traffic_from_profiles("full")
+        roof["traffic"] = _traffic_from_profiles(roof["class"])
 
     # ---------------- mixed E/B step (faces carry B) on the same solver -----------------
     mixed = None

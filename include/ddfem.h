@@ -156,7 +156,10 @@ typedef struct {
   int64_t corner_bytes;    /* bytes of the corner rows Psi_Gamma (read twice per
                               CG iteration), unpadded */
   int64_t coarse_bytes;    /* bytes of the coarse inverse factor, unpadded */
-  int64_t full_bytes;      /* bytes of the full r-block inverse factors, unpadded */
+  int64_t full_bytes;      /* bytes of the interior blocks L_II^-1 (their nonzero tiles' nonzero
+                              entries once factored; dense before) */
+  int64_t cross_bytes;     /* bytes of the couplings L_GammaI and L_cI of the interface and
+                              corner rows to the interior (nonzero entries once factored) */
 } dd_info;
 
 /* Fill *opt with defaults: DD_FP64, nrhs 1, cg_tol 1e-10, cg_max_iter 500,
@@ -389,11 +392,13 @@ int dd_step_mixed(void* ctx, const double* J_half, const double* E_n, const doub
  * records per launch while enabled).  Classes: */
 enum {
   DD_PROF_TRAILING = 0, /* interface-block inverse-factor products (pre-solve, recovery) */
-  DD_PROF_FULL = 1,     /* full r-block inverse-factor products (pre-solve, recovery) */
+  DD_PROF_FULL = 1,     /* interior inverse-factor products L_II^-1, L_II^-T (pre-solve, recovery) */
   DD_PROF_SCHUR = 2,    /* interface blocks of the local inverses, M u (once per CG iteration) */
   DD_PROF_COARSE = 3,   /* coarse corner inverse factor */
   DD_PROF_CORNER = 4,   /* corner rows Psi_Gamma u and Psi_Gamma^T z (twice per CG iteration) */
-  DD_PROF_CLASSES = 5
+  DD_PROF_CROSS = 5,    /* couplings L_GammaI, L_cI of interface and corner rows to the interior
+                           (pre-solve, recovery) */
+  DD_PROF_CLASSES = 6
 };
 /* Returns the accumulated milliseconds and launch counts per class (host
  * arrays [DD_PROF_CLASSES], either may be NULL) since the last reset, then

@@ -58,7 +58,7 @@ class Info(C.Structure):
                 ("n_corner", C.c_int32), ("nrhs", C.c_int32), ("precision", C.c_int32),
                 ("tile", C.c_int32), ("factor_bytes", C.c_int64), ("trailing_bytes", C.c_int64),
                 ("schur_bytes", C.c_int64), ("corner_bytes", C.c_int64), ("coarse_bytes", C.c_int64),
-                ("full_bytes", C.c_int64)]
+                ("full_bytes", C.c_int64), ("cross_bytes", C.c_int64)]
 
 
 class Analysis(C.Structure):

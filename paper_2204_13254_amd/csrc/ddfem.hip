@@ -151,8 +151,10 @@ struct Ctx {
   // output blocks of every product class (host), kept so that the work lists
   // can be rebuilt with other chunk lengths
   std::vector<MvItem> blk_trail_N, blk_trail_T, blk_corner_N, blk_corner_T, blk_co_N, blk_co_T, blk_full_N,
-      blk_full_T;
-  std::vector<int32_t> ml_full_N, ml_full_T;  // the full passes' per-row tile lists (host)
+      blk_full_T, blk_cross_N, blk_cross_T;
+  // per-row tile lists (host) of the I x I passes (L_II^-1) and of the
+  // [Gamma; c] x I passes (L_GI, L_cI)
+  std::vector<int32_t> ml_full_N, ml_full_T, ml_cross_N, ml_cross_T;
   void* d_zero_tile = nullptr;                // one zero tile (row-pair lists)
   std::vector<uint8_t> full_pattern;  // nonzero-tile flags the full lists were built from
   std::vector<void*> owned;
@@ -253,7 +255,7 @@ struct Ctx {
   // Psi_Gamma^T (pre-solve); co_*: coarse inverse factor
   // corner_N / corner_T: Psi_Gamma u on the corner rows / Psi_Gamma^T z
   // onto the interface rows
-  Items full_N, full_T, trail_N, trail_T, co_N, co_T, corner_N, corner_T;
+  Items full_N, full_T, cross_N, cross_T, trail_N, trail_T, co_N, co_T, corner_N, corner_T;
   // symmetric product M u (panel pairs, partial slots, fixed-order reduce)
   struct SymList {
     SymItem* d = nullptr;
@@ -292,7 +294,7 @@ struct Ctx {
          *g_t3 = nullptr, *g_t4 = nullptr;
 
   int64_t factor_bytes = 0, trailing_bytes = 0, schur_bytes = 0, corner_bytes = 0, coarse_bytes = 0,
-          full_bytes = 0;
+          full_bytes = 0, cross_bytes = 0;
 
   // optional per-class kernel timing with HIP events on the solve stream
   bool prof = false;
@@ -580,7 +582,10 @@ static void build_device(Ctx& C, const double* coords) {
     C.trailing_bytes += ((int64_t)q.nG * (q.nG + 1) / 2 + (int64_t)q.nC * q.nG) * wsz;
     C.schur_bytes += (int64_t)q.nG * (q.nG + 1) / 2 * wsz;
     C.corner_bytes += (int64_t)q.nC * q.nG * wsz;
-    C.full_bytes += (nr * (nr + 1) / 2 + (int64_t)q.nC * nr) * wsz;
+    // (before the nonzero-tile lists exist: dense I x I and [Gamma; c] x I)
+    C.full_bytes += ((int64_t)q.nI * (q.nI + 1) / 2) * wsz;
+    C.cross_bytes += ((int64_t)(q.nG + q.nC) * q.nI) * wsz;
+    (void)nr;
   }
   C.coarse_bytes = nc * (nc + 1) / 2 * (int64_t)wsz;
   // scratch rows for the triangular inversion
@@ -1161,6 +1166,8 @@ template <class T>
 static void build_full_items(Ctx& C) {
   release_items(C, C.full_N);
   release_items(C, C.full_T);
+  release_items(C, C.cross_N);
+  release_items(C, C.cross_T);
   const bool pair = C.tuning.full_pair && C.nrhs > 8;
   const bool oct = pair && C.tuning.full_pair == 2;
   auto make_oct = [&](const std::vector<MvItem>& blk, const std::vector<int32_t>& ml, Items& it) {
@@ -1252,14 +1259,17 @@ static void build_full_items(Ctx& C) {
   }
   make(C.blk_full_N, C.ml_full_N, C.full_N);
   make(C.blk_full_T, C.ml_full_T, C.full_T);
+  make(C.blk_cross_N, C.ml_cross_N, C.cross_N);
+  make(C.blk_cross_T, C.ml_cross_T, C.cross_T);
   ensure_partial<T>(C);
 }
 
-// Lists of the nonzero tiles of the subdomain inverse factors (with the
-// premultiplied corner rows) for the full forward / transposed passes.  The
-// interior nested-dissection order leaves whole tiles of L_II^-1 zero.  The
-// pattern is checked after every factorisation and the lists rebuilt when it
-// changed, so a tile is skipped only while it is exactly zero.
+// Lists of the nonzero tiles of the r-block columns of I for the forward /
+// transposed passes: the I x I block (L_II^-1, "full") and the [Gamma; c] x I
+// block (L_GI and L_cI, "cross").  The interior nested-dissection order
+// leaves whole tiles of L_II^-1 zero, and L_GI, L_cI keep the factor's
+// sparsity.  The pattern is checked after every factorisation and the lists
+// rebuilt when it changed, so a tile is skipped only while it is exactly zero.
 template <class T>
 static void full_tile_lists(Ctx& C) {
   const int64_t nt = C.subs_h[C.nsub].tile_off;  // subdomain tiles come first
@@ -1275,38 +1285,52 @@ static void full_tile_lists(Ctx& C) {
     if (transposed) z = (z & 9) | ((z & 2) << 1) | ((z & 4) >> 1);
     return z;
   };
-  std::vector<int32_t> ln, lt;
-  std::vector<MvItem> bn, bt;
-  int64_t entries = 0;
+  std::vector<int32_t> ln, lt, xn, xt;
+  std::vector<MvItem> bn, bt, cn, ct;
+  int64_t entries = 0, xentries = 0;
   for (int s = 0; s < C.nsub; ++s) {
     const SubDev& q = C.subs_h[s];
-    const int kr = q.kI + q.kG;
+    const int kI = q.kI;
     auto tid = [&](int i, int j) { return q.tile_off + (int64_t)i * (i + 1) / 2 + j; };
     auto at = [&](int i, int j) { return nnz[tid(i, j)]; };
     if (q.K >= kPairMask) throw DDError{DD_ERR_OOM, "too many tile rows in a subdomain"};
+    if (kI == 0) continue;
+    // forward: I rows over I columns; [Gamma; c] rows over I columns
     for (int o = 0; o < q.K; ++o) {
-      int32_t b = (int32_t)ln.size();
-      for (int j = 0; j <= std::min(o, kr - 1); ++j)
+      const bool irow = o < kI;
+      std::vector<int32_t>& L = irow ? ln : xn;
+      int32_t b = (int32_t)L.size();
+      for (int j = 0; j <= std::min(o, kI - 1); ++j)
         if (at(o, j)) {
-          ln.push_back(j | zq(tid(o, j), false) << 25);
-          entries += at(o, j);
+          L.push_back(j | zq(tid(o, j), false) << 25);
+          (irow ? entries : xentries) += at(o, j);
         }
-      bn.push_back({s, o, b, (int32_t)ln.size(), -1, 0});
-      if (o < kr) {
-        b = (int32_t)lt.size();
-        for (int i = o; i < q.K; ++i)
-          if (at(i, o)) lt.push_back(i | zq(tid(i, o), true) << 25);
-        bt.push_back({s, o, b, (int32_t)lt.size(), -1, 0});
-      }
+      (irow ? bn : cn).push_back({s, o, b, (int32_t)L.size(), -1, 0});
+    }
+    // transposed: I outputs over the I rows, and over the [Gamma; c] rows
+    for (int o = 0; o < kI; ++o) {
+      int32_t b = (int32_t)lt.size();
+      for (int i = o; i < kI; ++i)
+        if (at(i, o)) lt.push_back(i | zq(tid(i, o), true) << 25);
+      bt.push_back({s, o, b, (int32_t)lt.size(), -1, 0});
+      b = (int32_t)xt.size();
+      for (int i = kI; i < q.K; ++i)
+        if (at(i, o)) xt.push_back(i | zq(tid(i, o), true) << 25);
+      ct.push_back({s, o, b, (int32_t)xt.size(), -1, 0});
     }
   }
-  if ((int64_t)ln.size() >= INT32_MAX || (int64_t)lt.size() >= INT32_MAX)
-    throw DDError{DD_ERR_OOM, "tile lists exceed 2^31 entries"};
+  for (const auto* v : {&ln, &lt, &xn, &xt})
+    if ((int64_t)v->size() >= INT32_MAX) throw DDError{DD_ERR_OOM, "tile lists exceed 2^31 entries"};
   C.blk_full_N.swap(bn);
   C.blk_full_T.swap(bt);
   C.ml_full_N.swap(ln);
   C.ml_full_T.swap(lt);
+  C.blk_cross_N.swap(cn);
+  C.blk_cross_T.swap(ct);
+  C.ml_cross_N.swap(xn);
+  C.ml_cross_T.swap(xt);
   C.full_bytes = entries * (int64_t)sizeof(T);
+  C.cross_bytes = xentries * (int64_t)sizeof(T);
   C.full_pattern.swap(pat);
   build_full_items<T>(C);
 }
@@ -1454,6 +1478,7 @@ static int item_class(const Ctx& C, const Items& it) {
   if (&it == &C.trail_N || &it == &C.trail_T) return DD_PROF_TRAILING;
   if (&it == &C.corner_N || &it == &C.corner_T) return DD_PROF_CORNER;
   if (&it == &C.full_N || &it == &C.full_T) return DD_PROF_FULL;
+  if (&it == &C.cross_N || &it == &C.cross_T) return DD_PROF_CROSS;
   return DD_PROF_COARSE;
 }
 
@@ -1466,7 +1491,8 @@ static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const 
   // work groups come in multiples of 8 (one per XCD); a persistent grid is
   // a multiple of 8 too, so each workgroup stays on its groups' XCD
   int64_t grid = (it.n + 3) / 4;
-  if (CLS == DD_PROF_FULL && C.tuning.full_persist > 0) grid = std::min<int64_t>(grid, C.tuning.full_persist);
+  if ((CLS == DD_PROF_FULL || CLS == DD_PROF_CROSS) && C.tuning.full_persist > 0)
+    grid = std::min<int64_t>(grid, C.tuning.full_persist);
   if constexpr (NV == 0) {
     if (it.oct) {
       int64_t g8 = it.n;  // one workgroup per item (a multiple of 8)
@@ -1526,6 +1552,8 @@ static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, c
     mv_dispatch<T, DD_PROF_TRAILING>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_FULL)
     mv_dispatch<T, DD_PROF_FULL>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+  else if (cls == DD_PROF_CROSS)
+    mv_dispatch<T, DD_PROF_CROSS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_CORNER)
     mv_dispatch<T, DD_PROF_CORNER>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
@@ -1815,6 +1843,33 @@ static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, dou
   }
 }
 
+// The r-block substitutions of a DD solve through the factor store's column
+// blocks (L_rr^-1 = [L_II^-1, 0; -L_GG^-1 L_GI L_II^-1, L_GG^-1]):
+// forward_r: X0 (w, corner rows w_c) -> X1 = [L_rr^-1 w_r; w_c - L_cr L_rr^-1
+// w_r] with X2 as scratch; transposed_r: X1 = [t'; -x_c] with x_c in X5's
+// coarse rows -> X5 r rows = L_rr^-T (t' - L_cr^T x_c), X2 as scratch.
+template <class T>
+static void forward_r(Ctx& C, const int* gate) {
+  void** X = C.X;
+  const T one = 1, mone = -1;
+  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, gate);
+  mv<T>(C, C.cross_N, false, X[1], X[2], X[0], mone, gate, X[0], mone);
+  mv<T>(C, C.trail_N, false, X[2], X[1], nullptr, one, gate, X[2], mone);
+}
+
+template <class T>
+static void transposed_r(Ctx& C, const int* gate) {
+  void** X = C.X;
+  const T one = 1, mone = -1;
+  const int nr = C.nrhs;
+  mv<T>(C, C.trail_T, true, X[1], X[5], nullptr, one, gate);
+  if (C.Kc > 0)
+    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, C.st, C.n_csc, C.d_cscrows,
+                       C.d_csccrow, (const T*)X[5], (T*)X[5], one, nr, gate);
+  mv<T>(C, C.cross_T, true, X[5], X[2], X[1], mone, gate);
+  mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one, gate);
+}
+
 // z = K_lam r (the lumped preconditioner) with the r.z and r.r partials:
 // two rows in flight per lane, their nonzeros in batches of 8 (batches of
 // 12 held more registers than four waves per SIMD allow and spilled: 19.65
@@ -1844,8 +1899,13 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     throw DDError{DD_ERR_STATE, "captured solve: no warm start, first variant only"};
   hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
                      (T*)X[0], nr, gate);
-  // r rows: t = Linv_rr w_r;  corner rows: g = w_c - Psi_r w_r
-  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, gate, X[0], mone);
+  // r rows: t = L_rr^-1 w_r;  corner rows: g = w_c - L_cr t, as three products
+  // over the column blocks of the factor store:
+  //   t_I = L_II^-1 w_I                                  (X1, I rows)
+  //   y_G = w_G - L_GI t_I,  g' = w_c - L_cI t_I        (X2, Gamma and corner rows)
+  //   t_G = L_GG^-1 y_G,     g = g' - Psi_G y_G          (X1, Gamma and corner rows)
+  // (L_cG t_G = L_cG L_GG^-1 y_G = Psi_G y_G)
+  forward_r<T>(C, gate);
   if (C.Kc > 0) {
     // f_c = sum B_c^T g (coarse rows of X1, kept for the recovery); z0 = K_cc^-1 f_c
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
@@ -2016,12 +2076,14 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
                        (const T*)X[1], nr, gate);
     coarse_solve<T>(C, X[6], X[7], X[5], gate);
   }
-  // x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c: X1 holds t - [0; t_l] on
-  // the r rows; its corner rows get -x_c
+  // x_r = L_rr^-T (t' - L_cr^T x_c), t' = t - [0; t_l] (the r rows of X1):
+  //   x_G = L_GG^-T t'_G - Psi_G^T x_c                   (X5, Gamma rows; X1's corner rows get -x_c)
+  //   v_I = t_I - L_GI^T x_G - L_cI^T x_c                (X2, I rows; X5's corner rows get x_c)
+  //   x_I = L_II^-T v_I                                  (X5, I rows)
   if (C.Kc > 0)
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
                        C.d_csccrow, (const T*)X[5], (T*)X[1], mone, nr, gate);
-  mv<T>(C, C.full_T, true, X[1], X[5], nullptr, one, gate);
+  transposed_r<T>(C, gate);
   hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
                      (const T*)X[5], x, nr, gate);
   HIPCHK(hipGetLastError());
@@ -2306,7 +2368,7 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
     hipLaunchKernelGGL(k_gauss_step, dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
                        C.d_vdof, C.d_nodeint, (const double*)C.g_t3, C.dt, stats ? (const double*)C.g_t2 : nullptr,
                        C.d_q, gpart);
-    if (stats) hipLaunchKernelGGL(k_gauss_max, dim3(1), dim3(64), 0, st, (int)gb, nr, (const double*)C.d_gpart, C.d_gmax);
+    if (stats) hipLaunchKernelGGL(k_gauss_max, dim3(1), dim3(1024), 0, st, (int)gb, nr, (const double*)C.d_gpart, C.d_gmax);
     if (stats) {
       HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * nr * 2, hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -2537,8 +2599,10 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   };
   void** X = C.X;
   auto full = [&] {
-    mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, nullptr, X[0], mone);
-    mv<T>(C, C.full_T, true, X[1], X[5], nullptr, one);
+    mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one);
+    mv<T>(C, C.cross_N, false, X[1], X[2], X[0], mone, nullptr, X[0], mone);
+    mv<T>(C, C.cross_T, true, X[5], X[2], X[1], mone);
+    mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one);
   };
   auto coarse = [&] { coarse_solve<T>(C, X[6], X[7], X[5], nullptr); };
   auto trailing = [&] {
@@ -3189,6 +3253,7 @@ int dd_get_info(void* ctx, dd_info* info) {
   info->corner_bytes = C.corner_bytes;
   info->coarse_bytes = C.coarse_bytes;
   info->full_bytes = C.full_bytes;
+  info->cross_bytes = C.cross_bytes;
   return DD_OK;
 }
 

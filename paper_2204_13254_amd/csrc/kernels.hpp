@@ -439,9 +439,15 @@ __global__ void __launch_bounds__(256) k_syrk(int k, int s0, T* __restrict__ til
 }
 
 // --------------------------------------------------------------------------
-// Inversion of the r-block Cholesky factor, one block row at a time:
-// Linv_ij = -Dinv_i sum_{m=j}^{i-1} L_im Linv_mj  (rows < i already inverted,
-// row i still holds L), written to a scratch row, then copied back.
+// Inversion of the diagonal blocks of the r-block Cholesky factor, one block
+// row at a time: Linv_ij = -Dinv_i sum_{m=j}^{i-1} L_im Linv_mj (rows < i
+// already inverted, row i still holds L), written to a scratch row, then
+// copied back.  Only the I x I block (L_II^-1) and the Gamma x Gamma block
+// (L_GG^-1) are inverted; the coupling L_GI stays as the factor left it, so
+// that L_rr^-1 w = [L_II^-1 w_I ; L_GG^-1 (w_G - L_GI L_II^-1 w_I)] is applied
+// as three products (L_GI has far fewer nonzero tiles than the Gamma x I
+// block of L_rr^-1, which is dense).  A block with kG = 0 (the coarse block)
+// is inverted whole.
 // --------------------------------------------------------------------------
 template <class T>
 __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __restrict__ tiles,
@@ -454,6 +460,7 @@ __global__ void __launch_bounds__(256) k_trtri_row(int i, int s0, const T* __res
   const int j = blockIdx.x;
   const int kr = q.kI + q.kG;
   if (i >= kr || j >= i) return;
+  if (i >= q.kI && j < q.kI) return;  // L_GI is kept
   __shared__ T A[kNB][kNB + 1];
   __shared__ T B[kNB][kNB + 1];
   const int tid = threadIdx.x;
@@ -495,16 +502,18 @@ __global__ void k_trtri_copy(int i, int s0, T* __restrict__ tiles, const SubDev*
   const SubDev q = subs[sidx];
   const int j = blockIdx.x;
   if (i >= q.kI + q.kG || j >= i) return;
+  if (i >= q.kI && j < q.kI) return;  // L_GI is kept
   T* dst = tiles + tile_index(q, i, j) * kTile;
   const T* src = scratch + (scratch_off[sidx] + j) * kTile;
   for (int e = threadIdx.x; e < kTile; e += blockDim.x) dst[e] = src[e];
 }
 
-// Corner coupling premultiplied by the inverse factor: corner tile row
-// i = kr + c becomes Psi(i, j) = sum_{m=j}^{kr-1} L_cr(i, m) Linv(m, j),
-// j < kr (all r rows already inverted), i.e. Psi_r = L_cr Linv_rr.  Then
-// L_cr t = Psi_r w and L_rr^-T L_cr^T z = Psi_r^T z, so the corner products
-// fold into the inverse-factor passes.  Written to scratch, then copied.
+// Corner coupling premultiplied by the interface inverse factor: in corner
+// tile row i = kr + c the Gamma columns become Psi_G(i, j) = sum_{m=j}^{kr-1}
+// L_cG(i, m) Linv_GG(m, j), kI <= j < kr, i.e. Psi_G = L_cG L_GG^-1 (with
+// t = L_rr^-1 w, L_cG t_G = Psi_G y_G for y_G = w_G - L_GI t_I); the I columns
+// keep L_cI.  A block with kG = 0 (the coarse block) has no corner rows.
+// Written to scratch, then copied.
 template <class T>
 __global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restrict__ tiles,
                                                  const SubDev* __restrict__ subs,
@@ -514,7 +523,7 @@ __global__ void __launch_bounds__(256) k_psi_row(int c, int s0, const T* __restr
   const SubDev q = subs[sidx];
   const int j = blockIdx.x;
   const int kr = q.kI + q.kG;
-  if (c >= q.kC || j >= kr) return;
+  if (c >= q.kC || j >= kr || j < q.kI) return;
   const int i = kr + c;
   __shared__ T A[kNB][kNB + 1];
   __shared__ T B[kNB][kNB + 1];
@@ -544,7 +553,7 @@ __global__ void k_psi_copy(int c, int s0, T* __restrict__ tiles, const SubDev* _
   const SubDev q = subs[sidx];
   const int j = blockIdx.x;
   const int kr = q.kI + q.kG;
-  if (c >= q.kC || j >= kr) return;
+  if (c >= q.kC || j >= kr || j < q.kI) return;
   T* dst = tiles + tile_index(q, kr + c, j) * kTile;
   const T* src = scratch + (scratch_off[sidx] + j) * kTile;
   for (int e = threadIdx.x; e < kTile; e += blockDim.x) dst[e] = src[e];
@@ -989,7 +998,7 @@ __global__ void __launch_bounds__(256) k_tile_mv8(int64_t n_items, const MvItem*
   using acc_t = typename Mfma<T>::acc_t;
   for (int64_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const MvItem w = items[it];
-    if (w.s < 0 || w.lo >= w.hi) continue;  // uniform over the workgroup
+    if (w.s < 0) continue;  // uniform over the workgroup
     const SubDev q = subs[w.s];
     const T* xbase = in + q.row_off * nrhs;
     const int ra = 2 * wv, rb = 2 * wv + 1;  // this wave's rows within the octet
@@ -1032,42 +1041,44 @@ __global__ void __launch_bounds__(256) k_tile_mv8(int64_t n_items, const MvItem*
         if (idx < kNB * nrhs) xs[buf][idx % nrhs][idx / nrhs] = xr[j];
       }
     };
-    int32_t e = mlist[w.lo];
-    stage_load(e);
-    load_tiles(e, cur);
-    stage_store(0);
-    __syncthreads();
-    for (int k = w.lo; k < w.hi; ++k) {
-      const int buf = (k - w.lo) & 1;
-      const bool more = k + 1 < w.hi;
-      if (more) {
-        e = mlist[k + 1];
-        stage_load(e);
-        load_tiles(e, nxt);
-      }
-      T xv[8 * NB16];
-#pragma unroll
-      for (int nb = 0; nb < NB16; ++nb) {
-        const int col = nb * 16 + i;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) xv[nb * 8 + ks] = col < nrhs ? xs[buf][col][8 * g + ks] : (T)0;
-      }
-#pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int nb = 0; nb < NB16; ++nb)
-#pragma unroll
-          for (int ks = 0; ks < 8; ++ks) {
-            acc[p][nb] = Mfma<T>::op(cur[p][ks], xv[nb * 8 + ks], acc[p][nb]);
-            acc[p][NB16 + nb] = Mfma<T>::op(cur[p][8 + ks], xv[nb * 8 + ks], acc[p][NB16 + nb]);
-          }
-      if (more) stage_store(buf ^ 1);
+    if (w.lo < w.hi) {  // (an empty octet writes add + 0: uniform over the workgroup)
+      int32_t e = mlist[w.lo];
+      stage_load(e);
+      load_tiles(e, cur);
+      stage_store(0);
       __syncthreads();
-      if (more) {
+      for (int k = w.lo; k < w.hi; ++k) {
+        const int buf = (k - w.lo) & 1;
+        const bool more = k + 1 < w.hi;
+        if (more) {
+          e = mlist[k + 1];
+          stage_load(e);
+          load_tiles(e, nxt);
+        }
+        T xv[8 * NB16];
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb) {
+          const int col = nb * 16 + i;
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) xv[nb * 8 + ks] = col < nrhs ? xs[buf][col][8 * g + ks] : (T)0;
+        }
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-          for (int u = 0; u < 16; ++u) cur[p][u] = nxt[p][u];
+          for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+              acc[p][nb] = Mfma<T>::op(cur[p][ks], xv[nb * 8 + ks], acc[p][nb]);
+              acc[p][NB16 + nb] = Mfma<T>::op(cur[p][8 + ks], xv[nb * 8 + ks], acc[p][NB16 + nb]);
+            }
+        if (more) stage_store(buf ^ 1);
+        __syncthreads();
+        if (more) {
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int u = 0; u < 16; ++u) cur[p][u] = nxt[p][u];
+        }
       }
     }
     // ---- epilogue: this wave's two rows ----------------------------------
@@ -2310,14 +2321,34 @@ __global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const 
   }
 }
 
-// out[2 r + {0, 1}] = the maxima of the nb workgroups' part rows
-__global__ void __launch_bounds__(64) k_gauss_max(int nb, int nrhs, const double* __restrict__ part,
-                                                  double* __restrict__ out) {
-  const int t = threadIdx.x;
-  if (t >= 2 * nrhs) return;
+// out[2 r + {0, 1}] = the maxima of the nb workgroups' part rows: one
+// workgroup of 1024 threads, value t = tid % 64 over the rows g, g + 16, ...
+// of group g = tid / 64 (independent loads, eight in flight), then the 16
+// group maxima through LDS (order-free: maxima)
+__global__ void __launch_bounds__(1024) k_gauss_max(int nb, int nrhs, const double* __restrict__ part,
+                                                    double* __restrict__ out) {
+  __shared__ double gm[16][64];
+  const int t = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const bool res = (t & 1) == 0;  // even values: residual maxima (NaN wins)
   double m = 0.0;
-  for (int b = 0; b < nb; ++b) m = (t & 1) ? fmax(m, part[(int64_t)b * 2 * kMaxRhs + t]) : nan_max(m, part[(int64_t)b * 2 * kMaxRhs + t]);
-  out[t] = m;
+  if (t < 2 * nrhs) {
+    for (int b0 = g; b0 < nb; b0 += 16 * 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int b = b0 + 16 * u;
+        v[u] = b < nb ? part[(int64_t)b * 2 * kMaxRhs + t] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m = res ? nan_max(m, v[u]) : fmax(m, v[u]);
+    }
+  }
+  gm[g][t] = m;
+  __syncthreads();
+  if (g == 0 && t < 2 * nrhs) {
+    for (int k = 1; k < 16; ++k) m = res ? nan_max(m, gm[k][t]) : fmax(m, gm[k][t]);
+    out[t] = m;
+  }
 }
 
 // q [nv][nrhs] <- src [nrhs][nv] (or 0 with src == nullptr)

@@ -328,7 +328,7 @@ class DDSolver:
         check(self.lib.dd_pic_push(self.h, x.shape[0], _dev(qm), _dev(E), _dev(B), _dev_i32(cell), _dev(x),
                                    _dev(x_new), _dev(v), _dev(hist), 1 if first else 0))
 
-    PROF_CLASSES = ("trailing", "full", "schur", "coarse", "corner")
+    PROF_CLASSES = ("trailing", "full", "schur", "coarse", "corner", "cross")
 
     def profile(self, enable=-1):
         """Per-class (ms, launches) of the tile products since the last reset;
