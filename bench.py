@@ -105,28 +105,37 @@ def cpu_baseline(w, coords, tets, J0, rhs_sample=4):
     }
 
 
-# The source text that decides what the full-pass tile product moves: the
-# tile-product kernels, the work lists they are given (XCD placement, items,
-# full-pass lists) and their launch.  Counter summaries taken on other text
-# are not used.
-_FULL_PASS_SOURCE = (
-    ("kernels.hpp", "// Batched tile products for the solves", "// Symmetric product y = M u"),
-    ("ddfem.hip", "template <class It, class SubF, class LenF>", "static void make_sym_list("),
-    ("ddfem.hip", "static void build_full_items(", "static void autotune(Ctx& C, const char* cache"),
-    ("ddfem.hip", "static void mv_launch(", "static void mv_dispatch("),
-)
+# The source text that decides what a product class moves: for the r-block
+# passes ("full", "cross") the tile-product kernels, the work lists they are
+# given (XCD placement, items, the per-row tile lists) and their launch; for
+# the symmetric product ("schur") its kernel, its work list and its launch.
+# Counter summaries taken on other text are not used.
+_CLASS_SOURCE = {
+    "full": (
+        ("kernels.hpp", "// Batched tile products for the solves", "// Symmetric product y = M u"),
+        ("ddfem.hip", "template <class It, class SubF, class LenF>", "static void make_sym_list("),
+        ("ddfem.hip", "static void build_full_items(", "static void autotune(Ctx& C, const char* cache"),
+        ("ddfem.hip", "static void mv_launch(", "static void mv_dispatch("),
+    ),
+    "schur": (
+        ("kernels.hpp", "// Symmetric product y = M u", "// out_o = (add ? add_o : 0) + alpha * sum"),
+        ("ddfem.hip", "template <class It, class SubF, class LenF>", "static void build_device("),
+        ("ddfem.hip", "static void symv(", "// coarse: y rows of Xin"),
+    ),
+}
+_CLASS_SOURCE["cross"] = _CLASS_SOURCE["full"]
 
 
-def kernel_source_sha():
+def kernel_source_sha(cls="full"):
     import hashlib
     h = hashlib.sha256()
-    for f, a, b in _FULL_PASS_SOURCE:
+    for f, a, b in _CLASS_SOURCE[cls]:
         with open(os.path.join(ROOT, "paper_2204_13254_amd", "csrc", f)) as fh:
             text = fh.read()
         i = text.find(a)
         j = text.find(b, i + 1) if i >= 0 else -1
         if i < 0 or j < 0:
-            raise RuntimeError(f"full-pass source marker not found in {f}: {a if i < 0 else b!r}")
+            raise RuntimeError(f"{cls} source marker not found in {f}: {a if i < 0 else b!r}")
         h.update(text[i:j].encode())
     return h.hexdigest()[:16]
 
@@ -141,10 +150,10 @@ def _traffic_from_profiles(cls):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != kernel_source_sha():
-        return None
     v = t.get("classes", {}).get(cls)
-    return None if v is None else v.get("bytes_per_launch")
+    if v is None or v.get("source_sha") != kernel_source_sha(cls):
+        return None
+    return v.get("bytes_per_launch")
 
 
 def pic_leg(s, w, E, steps, dev, log, sort_every=10, cycles=5, cpu_sample=0):
@@ -602,7 +611,7 @@ def main():
     last = run["outputs"][-1]
     del run
     roof, other = roofline(s, per, w.nrhs, prof)
-    if roof["class"] in ("full", "cross"):
+    if roof["class"] in _CLASS_SOURCE:
         # HBM traffic per launch of the dominant class, from committed counter
         # summaries, valid only for the kernel source they were taken on
         roof["traffic"] = _traffic_from_profiles(roof["class"])

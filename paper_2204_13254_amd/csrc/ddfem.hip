@@ -1929,7 +1929,6 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                        C.d_code2, (const double*)C.d_lam2, (T*)X[5], nr, (const int*)nullptr);
     mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
-    if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
   } else if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
     hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
@@ -2057,22 +2056,23 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     }
     // ---- recovery -------------------------------------------------------------------
     // v_l = B_s^T lambda; interface rows of X1: t - t_l = t - Linv_GG v_l (in
-    // place); y = Psi_G v_l on the corner rows of X6
+    // place); its corner rows: y = Psi_G v_l (the same pass)
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
                        C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, gate);
     mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone, gate);
-    if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one, gate);
   } else {
-    // no interface: t_l = 0, y = 0
+    // no interface: t_l = 0, y = 0 (X6, whose corner rows the coarse gather reads)
     hipLaunchKernelGGL(k_zero<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total * nr, (T*)X[6],
                        gate);
     if (captured)
       hipLaunchKernelGGL(k_cg_snapshot, dim3(1), dim3(64), 0, st, slot, nr, (const CgState*)C.d_cg, C.d_rs, gate);
   }
   if (C.Kc > 0) {
-    // x_c = K_cc^-1 (f_c + sum B_c^T y)  (coarse rows of X5)
+    // x_c = K_cc^-1 (f_c + sum B_c^T y)  (coarse rows of X5; y on the corner
+    // rows of X1, written by the interface recovery pass, or of X6 = 0)
+    const void* ysrc = C.nlam > 0 ? X[1] : X[6];
     hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
-                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
+                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)ysrc, (T*)X[6],
                        (const T*)X[1], nr, gate);
     coarse_solve<T>(C, X[6], X[7], X[5], gate);
   }
