@@ -341,18 +341,21 @@ def pic_cpu_baseline(w, m):
 def timed_steps(s, Jd, W, K, nrhs, dev, profile_eager=True):
     """W untimed then K timed Newmark steps of all right-hand sides from
     e^0 = e^-1 = 0, every output kept in device memory (the timed loop reads
-    nothing back but the per-step stats, which carry the Gauss check).
-    Then, with profile_eager, 3 extra eager steps with per-class event
-    timing (graph replays have no per-launch events)."""
+    nothing back but the per-step stats, which carry the Gauss check).  The
+    steps advance the context's resident state (dd_step_resident): each
+    step takes J^{n+1/2} and writes e^{n+1} in edge order.  Then, with
+    profile_eager, 3 extra eager dd_step calls with per-class event timing
+    (graph replays have no per-launch events)."""
     import torch
     zero = torch.zeros((nrhs, s.n_edges), dtype=torch.float64, device=dev)
     E = [zero, zero.clone()]                 # e^-1, e^0, then e^1 .. e^{W+K}
     for _ in range(W + K):
         E.append(torch.empty_like(zero))
     out = {"iters": [], "sweeps": [], "global_relres": [], "gauss_rel": []}
+    s.state_set()                            # e^0 = e^-1 = 0, J^{-1/2} = 0
 
     def do_step(n):
-        s.step(Jd[n], Jd[n - 1] if n else zero, E[n + 1], E[n], E[n + 2], stats=True)
+        s.step_resident(Jd[n], E[n + 2], stats=True)
         return s.last_stats()
 
     for n in range(W):

@@ -222,6 +222,29 @@ int dd_factor(void* ctx);
  * context (DD_ERR_STATE); synchronises; out may be NULL. */
 int dd_autotune(void* ctx, const char* cache_path, dd_tuning* out);
 
+/* Resident Newmark state (for callers that advance the fields step after
+ * step, as a PIC loop does): the context keeps e^n, e^{n-1} and J^{n-1/2}
+ * in its own unknown-major layout together with the products T e and S e of
+ * both iterates (Sec. II-B-2: the load of step n needs exactly these), so a
+ * dd_step_resident converts only J^{n+1/2} and e^{n+1} and assembles its
+ * load without a sparse product; the products of the new iterate come from
+ * the refinement's last residual.  Each state belongs to its context; a new
+ * factorisation (dd_factor, dd_set_eps) recomputes the stored products.
+ *
+ * dd_state_set: load the state from device arrays [nrhs][n_edges] E_n = e^n,
+ * E_nm1 = e^{n-1}, J_prev_half = J^{n-1/2}; each may be NULL for zero (the
+ * state before the first step, reading of Sec. II-B-2: e^0 = e^{-1} = 0).
+ * A context whose state was never set starts from zero.  Needs a factorised
+ * context (DD_ERR_STATE).
+ * dd_step_resident: one Newmark step of the state with J_half = J^{n+1/2}
+ * (device [nrhs][n_edges]); writes e^{n+1} to E_next (device [nrhs][n_edges])
+ * and advances the state (e^{n+1}, e^n, J^{n+1/2}).  The result equals
+ * dd_step's for the same fields; stats, diagnostics and errors as for
+ * dd_step (on DD_ERR_NO_CONVERGENCE the state advances to the last
+ * iterate).  Calls on one context are not reentrant. */
+int dd_state_set(void* ctx, const double* E_n, const double* E_nm1, const double* J_prev_half);
+int dd_step_resident(void* ctx, const double* J_half, double* E_next, dd_stats* stats);
+
 /* One Newmark step for all nrhs right-hand sides (device pointers):
  *   J_half, J_prev_half  [nrhs][n_edges]: J^{n+1/2}, J^{n-1/2}
  *   E_n, E_nm1           [nrhs][n_edges]: e^n, e^{n-1}

@@ -82,6 +82,8 @@ SIGNATURES = {
     "dd_factor": (C.c_int, [P]),
     "dd_autotune": (C.c_int, [P, C.c_char_p, C.POINTER(Tuning)]),
     "dd_step": (C.c_int, [P, P, P, P, P, P, C.POINTER(Stats)]),
+    "dd_state_set": (C.c_int, [P, P, P, P]),
+    "dd_step_resident": (C.c_int, [P, P, P, C.POINTER(Stats)]),
     "dd_solve": (C.c_int, [P, P, P, C.POINTER(Stats)]),
     "dd_adjoint_step": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, C.POINTER(Stats)]),
     "dd_charge_update": (C.c_int, [P, P, P]),

@@ -138,8 +138,24 @@ struct Ctx {
   // captured refined solve of a step (pre-solve, CG, recovery, residual
   // checks and gated sweeps; FP32 factors with refinement, first variant):
   // CG iterations per solve and sweeps it holds, the last step's needs
-  hipGraphExec_t step_graph = nullptr;
-  int step_iters = 0, step_sweeps = 0;
+  // (two of them, keyed by their buffers: the resident step alternates its
+  // output slots)
+  struct StepGraph {
+    hipGraphExec_t g = nullptr;
+    const double* b = nullptr;
+    double *x = nullptr, *tx = nullptr, *sx = nullptr;
+    int iters = 0, sweeps = 0;
+    uint64_t used = 0;
+  } step_graphs[2];
+  uint64_t step_clock = 0;
+  // resident Newmark state of dd_step_resident, unknown-major [nint][nrhs]:
+  // slot rs_p holds e^n, the other e^{n-1}, each with its products T e and
+  // S e; rs_j holds J^{n-1/2}.  rs_stale: the products predate the current
+  // matrices (a new factorisation or permittivity).
+  double *rs_e[2] = {nullptr, nullptr}, *rs_te[2] = {nullptr, nullptr}, *rs_se[2] = {nullptr, nullptr};
+  double* rs_j = nullptr;
+  int rs_p = 0;
+  bool rs_alloc = false, rs_stale = false;
   int need_iters = 0, need_sweeps = 0;
   RefineState* d_rs = nullptr;
   RefineState* h_rs = nullptr;   // pinned
@@ -315,7 +331,8 @@ struct Ctx {
     if (fa) (void)hipStreamDestroy(fa);
     if (fb) (void)hipStreamDestroy(fb);
     if (cg_graph) (void)hipGraphExecDestroy(cg_graph);
-    if (step_graph) (void)hipGraphExecDestroy(step_graph);
+    for (auto& sg : step_graphs)
+      if (sg.g) (void)hipGraphExecDestroy(sg.g);
     for (hipGraphExec_t g : gm_graphs)
       if (g) (void)hipGraphExecDestroy(g);
     if (h_gm_st) (void)hipHostFree(h_gm_st);
@@ -1005,9 +1022,11 @@ static void build_device(Ctx& C, const double* coords) {
 // counts that are about to change); the next solve captures them again.
 static void drop_graphs(Ctx& C) {
   if (C.cg_graph) HIPCHK(hipGraphExecDestroy(C.cg_graph));
-  if (C.step_graph) HIPCHK(hipGraphExecDestroy(C.step_graph));
   C.cg_graph = nullptr;
-  C.step_graph = nullptr;
+  for (auto& sg : C.step_graphs) {
+    if (sg.g) HIPCHK(hipGraphExecDestroy(sg.g));
+    sg = Ctx::StepGraph{};
+  }
   for (hipGraphExec_t& g : C.gm_graphs) {
     if (g) HIPCHK(hipGraphExecDestroy(g));
     g = nullptr;
@@ -1439,6 +1458,7 @@ static int factor_impl(Ctx& C) {
   }
   C.factored = true;
   C.warm_fw.have = C.warm_adj.have = 0;
+  C.rs_stale = C.rs_alloc;  // the resident state's products predate these matrices
   if (!C.tune_cache.empty() && !C.tune_applied) autotune<T>(C, C.tune_cache.c_str(), nullptr);
   return DD_OK;
 }
@@ -2095,40 +2115,40 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
 template <int G, int NB, int MODE>
 static void csr_coop_launch(Ctx& C, hipStream_t st, const double* x1, const double* x2, const double* j1,
                             const double* j2, const double* z, double ca, double cb, double* y, double* y2,
-                            const int* skip) {
+                            const int* skip, double* y3) {
   const int64_t ni = C.P.nint;
   hipLaunchKernelGGL((k_csr_coop<G, NB, MODE>), dim3(nblk8(ni * G)), dim3(256), 0, st, ni, C.d_rp, C.d_ci, C.d_vals,
-                     x1, x2, j1, j2, z, C.dt, ca, cb, y, y2, C.nrhs, skip);
+                     x1, x2, j1, j2, z, C.dt, ca, cb, y, y2, C.nrhs, skip, y3);
 }
 
 template <int G, int NB>
 static void csr_coop_mode(Ctx& C, hipStream_t st, int mode, const double* x1, const double* x2, const double* j1,
                           const double* j2, const double* z, double ca, double cb, double* y, double* y2,
-                          const int* skip) {
+                          const int* skip, double* y3) {
   if (mode == 0)
-    csr_coop_launch<G, NB, 0>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_launch<G, NB, 0>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
   else if (mode == 1)
-    csr_coop_launch<G, NB, 1>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_launch<G, NB, 1>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
   else if (mode == 2)
-    csr_coop_launch<G, NB, 2>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_launch<G, NB, 2>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
   else
-    csr_coop_launch<G, NB, 3>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_launch<G, NB, 3>(C, st, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
 }
 
 static void csr_launch(Ctx& C, hipStream_t st, int mode, const double* x1, const double* x2, const double* j1,
                        const double* j2, const double* z, double ca, double cb, double* y, double* y2,
-                       const int* skip = nullptr) {
+                       const int* skip = nullptr, double* y3 = nullptr) {
   const int nr = C.nrhs;
   const int64_t ni = C.P.nint;
   if (nr <= 4)
     hipLaunchKernelGGL(k_csr, dim3(nblk8(ni * nr)), dim3(256), 0, st, mode, ni, C.d_rp, C.d_ci, C.d_vals, x1, x2, j1,
-                       j2, z, C.dt, ca, cb, y, y2, nr, skip);
+                       j2, z, C.dt, ca, cb, y, y2, nr, skip, y3);
   else if (nr <= 8)
-    csr_coop_mode<8, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_mode<8, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
   else if (nr <= 16)
-    csr_coop_mode<16, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_mode<16, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
   else
-    csr_coop_mode<32, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip);
+    csr_coop_mode<32, 20>(C, st, mode, x1, x2, j1, j2, z, ca, cb, y, y2, skip, y3);
 }
 
 
@@ -2139,9 +2159,11 @@ static void csr_launch(Ctx& C, hipStream_t st, int mode, const double* x1, const
 // passes; a last residual and check.  Each solve runs `iters` CG iterations
 // (the kernels return at once after convergence).  One read-back after the
 // graph gives the norms, the checks and every solve's CG state.  The
-// graph replaces C.step_graph.
+// graph goes into slot sg (which keeps its buffers and counts).  tx, sx
+// (may be null): T x and S x of the accepted iterate, from its residual.
 template <class T>
-static void capture_step(Ctx& C, const double* b, double* x, double* tx, int iters, int sweeps) {
+static void capture_step(Ctx& C, Ctx::StepGraph& sg, const double* b, double* x, double* tx, double* sx, int iters,
+                         int sweeps) {
   hipStream_t st = C.st;
   const int nr = C.nrhs;
   const int64_t n = C.P.nint * nr;
@@ -2156,7 +2178,7 @@ static void capture_step(Ctx& C, const double* b, double* x, double* tx, int ite
     hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_rpart, C.d_rs);
     dd_solve_once<T>(C, b, x, nullptr, it_dummy, rr_dummy, gate, iters, 0);
     for (int k = 1; k <= sweeps + 1; ++k) {
-      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx, gate + (k - 1));
+      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx, gate + (k - 1), sx);
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.P.nint, (const double*)C.g_r,
                          (const double*)C.g_r, nr, C.d_rpart, (const int*)(gate + (k - 1)));
       hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(kScalarThreads), 0, st, k, nr, (const double*)C.d_rpart,
@@ -2174,11 +2196,17 @@ static void capture_step(Ctx& C, const double* b, double* x, double* tx, int ite
   }
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamEndCapture(st, &g));
-  hipError_t e = hipGraphInstantiate(&C.step_graph, g, nullptr, nullptr, 0);
+  if (sg.g) HIPCHK(hipGraphExecDestroy(sg.g));
+  sg = Ctx::StepGraph{};
+  hipError_t e = hipGraphInstantiate(&sg.g, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   HIPCHK(e);
-  C.step_iters = iters;
-  C.step_sweeps = sweeps;
+  sg.b = b;
+  sg.x = x;
+  sg.tx = tx;
+  sg.sx = sx;
+  sg.iters = iters;
+  sg.sweeps = sweeps;
 }
 
 // A^-1 b with iterative refinement in the mixed form.  b, x: [nint][nrhs].
@@ -2188,7 +2216,7 @@ static void capture_step(Ctx& C, const double* b, double* x, double* tx, int ite
 template <class T>
 static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd_stats* stats,
                          const char* what = "b", double* tx = nullptr, bool* tx_done = nullptr,
-                         bool step = false) {
+                         bool step = false, double* sx = nullptr) {
   const int nr = C.nrhs;
   const int64_t n = C.P.nint * nr;
   hipStream_t st = C.st;
@@ -2217,12 +2245,17 @@ static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd
   if (graph) {
     const int I = std::min(C.opt.cg_max_iter, C.need_iters);
     const int S = std::min({C.need_sweeps, C.opt.refine_max, kMaxGraphSweeps});
-    if (!C.step_graph || C.step_iters != I || C.step_sweeps != S) {
-      if (C.step_graph) HIPCHK(hipGraphExecDestroy(C.step_graph));
-      C.step_graph = nullptr;
-      capture_step<T>(C, b, x, tx, I, S);
+    Ctx::StepGraph* sg = nullptr;
+    for (auto& e : C.step_graphs)
+      if (e.g && e.b == b && e.x == x && e.tx == tx && e.sx == sx && e.iters == I && e.sweeps == S) sg = &e;
+    if (!sg) {  // the least recently used slot
+      sg = &C.step_graphs[0];
+      for (auto& e : C.step_graphs)
+        if (e.used < sg->used) sg = &e;
+      capture_step<T>(C, *sg, b, x, tx, sx, I, S);
     }
-    HIPCHK(hipGraphLaunch(C.step_graph, st));
+    sg->used = ++C.step_clock;
+    HIPCHK(hipGraphLaunch(sg->g, st));
     HIPCHK(hipMemcpyAsync(C.h_rs, C.d_rs, sizeof(RefineState), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     const RefineState& R = *C.h_rs;
@@ -2258,7 +2291,7 @@ static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd
     status = dd_solve_once<T>(C, b, x, warm, iters, relres);
     for (int r = 0; r < nr; ++r) solve_iters[0] = std::max(solve_iters[0], iters[r]);
     if (refine) {
-      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx);
+      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx, nullptr, sx);
       double rn[kMaxRhs];
       dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
       ok = true;
@@ -2285,7 +2318,7 @@ static int solve_refined(Ctx& C, const double* b, double* x, Ctx::Warm* warm, dd
     hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, st, n, 1.0, (const double*)C.g_t4, x,
                        (const int*)nullptr);
     ++sweeps;
-    csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx);
+    csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx, nullptr, sx);
     double rn[kMaxRhs];
     dot_to_host(C, C.g_r, C.g_r, C.P.nint, rn);
     ok = true;
@@ -2335,13 +2368,48 @@ static void energy_int(Ctx& C, const double* e1, const double* e0, double* out) 
   for (int r = 0; r < nr; ++r) out[r] = a[r] + b[r];
 }
 
+// Diagnostics after a step (DD_DIAG_GAUSS: the charge update with Jint =
+// J^{n+1/2} per unknown, and with stats the Gauss-law maxima from tx = T
+// e^{n+1} (computed here when have_tx is false); DD_DIAG_ENERGY with stats).
+// e1 = e^{n+1}, e0 = e^n per unknown.  Jint and tx must not be g_t3 / g_t4
+// / g_x / g_r when the energy is asked for (they are its scratch).
+static void step_diagnostics(Ctx& C, const double* Jint, const double* e1, const double* e0, double* tx,
+                             bool have_tx, dd_stats* stats) {
+  const int nr = C.nrhs;
+  hipStream_t st = C.st;
+  if (C.opt.diagnostics & DD_DIAG_GAUSS) {
+    // q^{n+1} = q^n + dt G^T J^{n+1/2}, with max |G^T T e^{n+1} + q^{n+1}|
+    // when the stats are asked for (T e^{n+1} from the last refinement
+    // residual, or its own product in the FP64 form)
+    if (stats && !have_tx) csr_launch(C, st, 3, e1, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, tx, C.g_r);
+    double* gpart = stats ? C.d_gpart : nullptr;
+    const int vpb = (256 - 256 % nr) / nr;
+    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGaussBlocks, nblk(C.P.nv, vpb)));
+    hipLaunchKernelGGL(k_gauss_step, dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
+                       C.d_vdof, C.d_nodeint, Jint, C.dt, stats ? (const double*)tx : nullptr, C.d_q, gpart);
+    if (stats) {
+      hipLaunchKernelGGL(k_gauss_max, dim3(1), dim3(1024), 0, st, (int)gb, nr, (const double*)C.d_gpart, C.d_gmax);
+      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * nr * 2, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int r = 0; r < nr; ++r) {
+        stats->gauss_residual[r] = C.h_partial[2 * r];
+        stats->charge_max[r] = C.h_partial[2 * r + 1];
+      }
+    }
+  }
+}
+
+static void step_energy(Ctx& C, const double* e1, const double* e0, dd_stats* stats) {
+  if (stats && (C.opt.diagnostics & DD_DIAG_ENERGY)) energy_int(C, e1, e0, stats->energy);
+  if (stats) stats->diagnostics = C.opt.diagnostics & (DD_DIAG_GAUSS | DD_DIAG_ENERGY);
+}
+
 template <class T>
 static int step_impl(Ctx& C, const double* J1, const double* J0, const double* En, const double* Enm1,
                      double* Enext, dd_stats* stats) {
   const int nr = C.nrhs;
   const int64_t ni = C.P.nint, ne = C.P.ne;
   hipStream_t st = C.st;
-  const int64_t n = ni * nr;
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, En, ne, C.g_t1, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, Enm1, ne, C.g_t2, nr, 1.0);
   hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
@@ -2356,30 +2424,80 @@ static int step_impl(Ctx& C, const double* J1, const double* J0, const double* E
                                 "J, E_n or E_nm1", gauss ? C.g_t2 : nullptr, &have_tx, true);
   hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.g_e,
                      Enext, nr, 0, 1.0);
-  if (gauss) {
-    // q^{n+1} = q^n + dt G^T J^{n+1/2}, with max |G^T T e^{n+1} + q^{n+1}|
-    // when the stats are asked for (T e^{n+1} from the last refinement
-    // residual, or its own product in the FP64 form)
-    // (g_t3 still holds J^{n+1/2} per unknown, converted for the load)
-    if (stats && !have_tx) csr_launch(C, st, 3, C.g_e, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.g_t2, C.g_r);
-    double* gpart = stats ? C.d_gpart : nullptr;
-    const int vpb = (256 - 256 % nr) / nr;
-    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGaussBlocks, nblk(C.P.nv, vpb)));
-    hipLaunchKernelGGL(k_gauss_step, dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
-                       C.d_vdof, C.d_nodeint, (const double*)C.g_t3, C.dt, stats ? (const double*)C.g_t2 : nullptr,
-                       C.d_q, gpart);
-    if (stats) hipLaunchKernelGGL(k_gauss_max, dim3(1), dim3(1024), 0, st, (int)gb, nr, (const double*)C.d_gpart, C.d_gmax);
-    if (stats) {
-      HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * nr * 2, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      for (int r = 0; r < nr; ++r) {
-        stats->gauss_residual[r] = C.h_partial[2 * r];
-        stats->charge_max[r] = C.h_partial[2 * r + 1];
-      }
-    }
+  // (g_t3 still holds J^{n+1/2} per unknown, converted for the load)
+  step_diagnostics(C, C.g_t3, C.g_e, C.g_t1, C.g_t2, have_tx, stats);
+  step_energy(C, C.g_e, C.g_t1, stats);
+  HIPCHK(hipGetLastError());
+  return status;
+}
+
+// ---- resident Newmark state ------------------------------------------------------
+// The context keeps e^n and e^{n-1} per unknown with their products T e and
+// S e, and J^{n-1/2}: a step needs no layout conversion of its inputs but J
+// and no sparse product for its load; the accepted iterate's products come
+// from the refinement's last residual (or one product without refinement).
+static void resident_alloc(Ctx& C) {
+  if (C.rs_alloc) return;
+  const int64_t n = C.P.nint * C.nrhs;
+  for (int k = 0; k < 2; ++k) {
+    C.rs_e[k] = dalloc<double>(n, C.owned);
+    C.rs_te[k] = dalloc<double>(n, C.owned);
+    C.rs_se[k] = dalloc<double>(n, C.owned);
   }
-  if (stats && (C.opt.diagnostics & DD_DIAG_ENERGY)) energy_int(C, C.g_e, C.g_t1, stats->energy);
-  if (stats) stats->diagnostics = C.opt.diagnostics & (DD_DIAG_GAUSS | DD_DIAG_ENERGY);
+  C.rs_j = dalloc<double>(n, C.owned);
+  C.rs_alloc = true;
+}
+
+// products of both stored iterates with the current matrices
+static void resident_products(Ctx& C) {
+  for (int k = 0; k < 2; ++k)
+    csr_launch(C, C.st, 3, C.rs_e[k], nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.rs_te[k], C.rs_se[k]);
+  C.rs_stale = false;
+}
+
+static void resident_set(Ctx& C, const double* En, const double* Enm1, const double* Jprev) {
+  resident_alloc(C);
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne, n = ni * nr;
+  hipStream_t st = C.st;
+  C.rs_p = 0;
+  const double* src[3] = {En, Enm1, Jprev};
+  double* dst[3] = {C.rs_e[0], C.rs_e[1], C.rs_j};
+  for (int k = 0; k < 3; ++k) {
+    if (src[k])
+      hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, src[k], ne, dst[k],
+                         nr, 1.0);
+    else
+      hipLaunchKernelGGL(k_zero<double>, dim3(nblk(n)), dim3(256), 0, st, n, dst[k], (const int*)nullptr);
+  }
+  resident_products(C);
+  HIPCHK(hipGetLastError());
+}
+
+template <class T>
+static int step_resident_impl(Ctx& C, const double* J1, double* Enext, dd_stats* stats) {
+  if (!C.rs_alloc) resident_set(C, nullptr, nullptr, nullptr);  // e^0 = e^-1 = 0, J^{-1/2} = 0
+  if (C.rs_stale) resident_products(C);
+  const int nr = C.nrhs;
+  const int64_t ni = C.P.nint, ne = C.P.ne, n = ni * nr;
+  hipStream_t st = C.st;
+  const int p = C.rs_p, q = 1 - p;  // e^n in slot p; e^{n+1} replaces e^{n-1} in slot q
+  hipLaunchKernelGGL(k_edges_to_int, dim3(nblk(ni, 64)), dim3(256), 0, st, ni, C.d_interior, J1, ne, C.g_t3, nr, 1.0);
+  hipLaunchKernelGGL(k_newmark_load, dim3(nblk(n)), dim3(256), 0, st, n, (const double*)C.rs_te[p],
+                     (const double*)C.rs_se[p], (const double*)C.rs_te[q], (const double*)C.rs_se[q],
+                     (const double*)C.g_t3, (const double*)C.rs_j, C.dt, C.beta * C.dt * C.dt,
+                     (2 * C.beta - 1) * C.dt * C.dt, C.g_b);
+  bool have_tx = false;
+  int status = solve_refined<T>(C, C.g_b, C.rs_e[q], C.opt.warm_start ? &C.warm_fw : nullptr, stats, "J",
+                                C.rs_te[q], &have_tx, true, C.rs_se[q]);
+  if (!have_tx)
+    csr_launch(C, st, 3, C.rs_e[q], nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, C.rs_te[q], C.rs_se[q]);
+  hipLaunchKernelGGL(k_int_to_edges, dim3(nblk(ne, 64)), dim3(256), 0, st, ne, C.d_dof, (const double*)C.rs_e[q],
+                     Enext, nr, 0, 1.0);
+  step_diagnostics(C, C.g_t3, C.rs_e[q], C.rs_e[p], C.rs_te[q], true, stats);
+  std::swap(C.g_t3, C.rs_j);  // J^{n+1/2} kept; the old buffer becomes scratch
+  step_energy(C, C.rs_e[q], C.rs_e[p], stats);
+  C.rs_p = q;
   HIPCHK(hipGetLastError());
   return status;
 }
@@ -3347,6 +3465,41 @@ int dd_step(void* ctx, const double* J_half, const double* J_prev_half, const do
   API_BEGIN
   int rc = C.fp32 ? step_impl<float>(C, J_half, J_prev_half, E_n, E_nm1, E_next, stats)
                   : step_impl<double>(C, J_half, J_prev_half, E_n, E_nm1, E_next, stats);
+  prof_resolve(C);
+  if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
+  return rc;
+  API_END
+}
+
+int dd_state_set(void* ctx, const double* E_n, const double* E_nm1, const double* J_prev_half) {
+  if (!ctx) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_state_set called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  API_BEGIN
+  resident_set(C, E_n, E_nm1, J_prev_half);
+  return DD_OK;
+  API_END
+}
+
+int dd_step_resident(void* ctx, const double* J_half, double* E_next, dd_stats* stats) {
+  if (!ctx || !J_half || !E_next) {
+    g_err = "null argument";
+    return DD_ERR_ARG;
+  }
+  Ctx& C = *(Ctx*)ctx;
+  if (!C.factored) {
+    g_err = "dd_step_resident called before dd_factor";
+    return DD_ERR_STATE;
+  }
+  API_BEGIN
+  int rc = C.fp32 ? step_resident_impl<float>(C, J_half, E_next, stats)
+                  : step_resident_impl<double>(C, J_half, E_next, stats);
   prof_resolve(C);
   if (rc == DD_ERR_NO_CONVERGENCE) g_err = "interface CG or refinement did not reach its tolerance";
   return rc;

@@ -1595,7 +1595,7 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
                                              const double* __restrict__ j1, const double* __restrict__ j2,
                                              const double* __restrict__ z, double dt, double ca, double cb,
                                              double* __restrict__ y, double* __restrict__ y2, int nrhs,
-                                             const int* __restrict__ skip) {
+                                             const int* __restrict__ skip, double* __restrict__ y3) {
   if (skip && *skip) return;
   const int64_t i = xcd_contiguous_block() * blockDim.x + threadIdx.x;
   if (i >= nint * nrhs) return;
@@ -1651,6 +1651,7 @@ __global__ void __launch_bounds__(256) k_csr(int mode, int64_t nint, const int64
   } else if (mode == 1) {
     y[i] = z[i] - (t1 + ca * s1);
     if (y2) y2[i] = t1;
+    if (y3) y3[i] = s1;
   } else if (mode == 2) {
     y[i] = 2.0 * t1 + cb * s1;
     y2[i] = t1 + ca * s1;
@@ -1680,7 +1681,7 @@ __global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* _
                                                   const double* __restrict__ j1, const double* __restrict__ j2,
                                                   const double* __restrict__ z, double dt, double ca, double cb,
                                                   double* __restrict__ y, double* __restrict__ y2, int nrhs,
-                                                  const int* __restrict__ skip) {
+                                                  const int* __restrict__ skip, double* __restrict__ y3) {
   static_assert(G == 8 || G == 16 || G == 32, "lanes per row");
   if (skip && *skip) return;
   static_assert(NB % 4 == 0, "index reads of four");
@@ -1774,6 +1775,7 @@ __global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* _
   } else if constexpr (MODE == 1) {
     y[o] = z[o] - (t1 + ca * s1);
     if (y2) y2[o] = t1;
+    if (y3) y3[o] = s1;
   } else if constexpr (MODE == 2) {
     y[o] = 2.0 * t1 + cb * s1;
     y2[o] = t1 + ca * s1;
@@ -1781,6 +1783,20 @@ __global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* _
     y[o] = t1;
     y2[o] = s1;
   }
+}
+
+// Newmark load from stored products (the resident step): with te = T e,
+// se = S e of e^n (0) and e^{n-1} (1),
+//   y = (2 T e^n + cb S e^n) - (T e^{n-1} + ca S e^{n-1}) - dt (J^{n+1/2} - J^{n-1/2}),
+// the same expression, in the same order, as mode 0 of k_csr / k_csr_coop.
+__global__ void __launch_bounds__(256) k_newmark_load(int64_t n, const double* __restrict__ te0,
+                                                      const double* __restrict__ se0, const double* __restrict__ te1,
+                                                      const double* __restrict__ se1, const double* __restrict__ j1,
+                                                      const double* __restrict__ j0, double dt, double ca, double cb,
+                                                      double* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = (2.0 * te0[i] + cb * se0[i]) - (te1[i] + ca * se1[i]) - dt * (j1[i] - j0[i]);
 }
 
 // --------------------------------------------------------------------------

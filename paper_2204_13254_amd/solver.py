@@ -339,6 +339,27 @@ class DDSolver:
                                   n.ctypes.data_as(C.c_void_p)))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
 
+    def state_set(self, E_n=None, E_nm1=None, J_prev_half=None):
+        """Load the context's resident Newmark state (dd_state_set); None is
+        zero."""
+        for a, nm in ((E_n, "E_n"), (E_nm1, "E_nm1"), (J_prev_half, "J_prev_half")):
+            if a is not None:
+                self._len(a, self.nrhs * self.n_edges, nm)
+        check(self.lib.dd_state_set(self.h, None if E_n is None else _dev(E_n),
+                                    None if E_nm1 is None else _dev(E_nm1),
+                                    None if J_prev_half is None else _dev(J_prev_half)))
+
+    def step_resident(self, J_half, E_next=None, stats=False, raise_on_error=True):
+        """One Newmark step of the resident state (dd_step_resident)."""
+        if E_next is None:
+            E_next = self.new_field()
+        self._len(J_half, self.nrhs * self.n_edges, "J_half")
+        self._len(E_next, self.nrhs * self.n_edges, "E_next")
+        rc = self.lib.dd_step_resident(self.h, _dev(J_half), _dev(E_next), C.byref(self.stats) if stats else None)
+        if raise_on_error:
+            check(rc)
+        return E_next
+
     def last_stats(self):
         s = self.stats
         n = self.nrhs
