@@ -177,6 +177,67 @@ static void order_interiors(Plan& P, const double* coords, const int32_t* partit
   }
 }
 
+// Order of each subdomain's interface and corner blocks.  It changes only
+// how the couplings L_GI and L_cI of the factor fall into tiles: the
+// nonzero pattern of a row of L_GI is a property of that row alone (the
+// dissection pieces of the interior that the unknown shares a tet with, and
+// the separators above them).  Rows are sorted by the first interior
+// position (in the dissection order) that they touch, so the rows next to
+// one piece sit together and share its tiles instead of spreading a few
+// nonzero rows over many tiles.  Ties keep ascending unknown id; rows that
+// touch no interior unknown go last.  The multipliers' local positions are
+// moved with their rows.
+static void order_boundary(Plan& P, const int32_t* partition) {
+  std::vector<int64_t> tptr(P.nsub + 1, 0), tlist(P.nt);
+  for (int64_t t = 0; t < P.nt; ++t) tptr[partition[t] + 1]++;
+  for (int32_t s = 0; s < P.nsub; ++s) tptr[s + 1] += tptr[s];
+  {
+    std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+    for (int64_t t = 0; t < P.nt; ++t) tlist[fill[partition[t]]++] = t;
+  }
+  std::vector<int32_t> ipos(P.nint, -1), key(P.nint, INT32_MAX);
+  // moved[s][old position - nI] = new position of the interface / corner row
+  std::vector<std::vector<int32_t>> moved(P.nsub);
+  for (int32_t s = 0; s < P.nsub; ++s) {
+    const SubInfo& q = P.subs[s];
+    auto& L = P.local[s];
+    for (int32_t a = 0; a < q.nI; ++a) ipos[L[a]] = a;
+    for (int64_t k = tptr[s]; k < tptr[s + 1]; ++k) {
+      const int64_t t = tlist[k];
+      int32_t d[6];
+      for (int e = 0; e < 6; ++e) d[e] = P.dof[P.tet_edges[t * 6 + e]];
+      for (int a = 0; a < 6; ++a) {
+        if (d[a] < 0 || ipos[d[a]] < 0) continue;
+        for (int b = 0; b < 6; ++b)
+          if (d[b] >= 0 && ipos[d[b]] < 0) key[d[b]] = std::min(key[d[b]], ipos[d[a]]);
+      }
+    }
+    auto& mv = moved[s];
+    mv.resize(q.nG + q.nC);
+    for (int seg = 0; seg < 2; ++seg) {
+      const int32_t b = seg == 0 ? q.nI : q.nI + q.nG, n = seg == 0 ? q.nG : q.nC;
+      std::vector<int32_t> idx(n);
+      std::iota(idx.begin(), idx.end(), 0);
+      // the segment is ascending by unknown id: a stable sort keeps that
+      // order among equal keys
+      std::stable_sort(idx.begin(), idx.end(),
+                       [&](int32_t x, int32_t y) { return key[L[b + x]] < key[L[b + y]]; });
+      std::vector<int32_t> seg_new(n);
+      for (int32_t k = 0; k < n; ++k) {
+        seg_new[k] = L[b + idx[k]];
+        mv[b + idx[k] - q.nI] = b + k;
+      }
+      std::copy(seg_new.begin(), seg_new.end(), L.begin() + b);
+    }
+    for (int32_t a = 0; a < q.nI; ++a) ipos[L[a]] = -1;
+    for (int32_t a = q.nI; a < q.nI + q.nG + q.nC; ++a) key[L[a]] = INT32_MAX;
+  }
+  for (size_t l = 0; l < P.lam_dof.size(); ++l) {
+    P.lam_p0[l] = moved[P.lam_s0[l]][P.lam_p0[l] - P.subs[P.lam_s0[l]].nI];
+    P.lam_p1[l] = moved[P.lam_s1[l]][P.lam_p1[l] - P.subs[P.lam_s1[l]].nI];
+  }
+}
+
 int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets,
                const int32_t* partition, Plan& P, std::string& msg) {
   if (nv <= 0 || nt <= 0 || !coords || !tets || !partition) {
@@ -399,6 +460,7 @@ int build_plan(int64_t nv, const double* coords, int64_t nt, const int32_t* tets
     }
   order_corners(P, coords);
   order_interiors(P, coords, partition);
+  order_boundary(P, partition);
   return DD_OK;
 }
 

@@ -92,16 +92,21 @@ def test_classes_and_lambda_map_brute_force(n, parts):
         lo, hi = sorted(subs_of[e])
         assert (L["sub_lo"][l], L["sub_hi"][l]) == (lo, hi)
     # positions: the interface block of a subdomain follows its interior
-    # block and lists its interface edges in ascending canonical id, so the
-    # brute-force interface list of each subdomain maps (sub, pos) back to
-    # an edge; both sides of every multiplier must name its edge
-    gam_of = [sorted(e for e in gam if s in subs_of[e]) for s in range(a.n_sub)]
+    # block, and every interface edge of the subdomain is one multiplier's
+    # side there: the positions of the multipliers that enter a subdomain
+    # cover its interface block exactly once, and the edges found there are
+    # the brute-force interface edges of that subdomain (in the library's
+    # own order of the block)
+    gam_of = [[-1] * int(per[s, 1]) for s in range(a.n_sub)]
     for side in ("lo", "hi"):
         sub, pos = L["sub_" + side], L["pos_" + side]
         off = pos - per[sub, 0]
         assert np.all(off >= 0) and np.all(off < per[sub, 1])
-        back = np.array([gam_of[s_][o] for s_, o in zip(sub, off)])
-        assert np.array_equal(back, L["edge"])
+        for s_, o, e in zip(sub, off, L["edge"]):
+            assert gam_of[s_][o] == -1
+            gam_of[s_][o] = int(e)
+    for s in range(a.n_sub):
+        assert sorted(gam_of[s]) == sorted(e for e in gam if s in subs_of[e])
 
     # restriction R_s of an edge field to each subdomain's interface rows
     def restrict(x):
