@@ -1583,6 +1583,42 @@ static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, c
 
 // fork: work queued on st so far is visible to the side stream; join: the
 // side stream's work is visible to everything queued on st afterwards
+// Right-hand sides per lane in the vector forms of the multiplier-space
+// kernels (k_*_v): 4 when nrhs is a multiple of 4, else 2 when even, else
+// the scalar forms.
+static int vec_width(int nr) { return nr % 4 == 0 ? 4 : (nr % 2 == 0 ? 2 : 1); }
+
+// v[rows[k]] = sign * p[lam[k]] (B_s^T p on the listed interface rows)
+template <class T>
+static void lambda_gather(Ctx& C, int64_t n, const int32_t* lam, const double* p, T* v, const int* skip) {
+  const int nr = C.nrhs, V = vec_width(nr);
+  hipStream_t st = C.st;
+  if (V == 4)
+    hipLaunchKernelGGL((k_lambda_gather_v<T, 4>), dim3(nblk(n * nr / 4)), dim3(256), 0, st, n, C.d_grow, lam, p, v,
+                       nr, skip);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_lambda_gather_v<T, 2>), dim3(nblk(n * nr / 2)), dim3(256), 0, st, n, C.d_grow, lam, p, v,
+                       nr, skip);
+  else
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.d_grow, lam, p, v, nr, skip);
+}
+
+// Fp = sum_s B_s (u + u2) with the partials of p . Fp (p may be null)
+template <class T>
+static void scatter_dot(Ctx& C, const T* u, const T* u2, double* Fp, const double* p, const int* skip) {
+  const int nr = C.nrhs, V = vec_width(nr);
+  hipStream_t st = C.st;
+  if (V == 4)
+    hipLaunchKernelGGL((k_scatter_dot_v<T, 4>), dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1, u,
+                       u2, Fp, p, nr, C.d_partial, skip);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_scatter_dot_v<T, 2>), dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1, u,
+                       u2, Fp, p, nr, C.d_partial, skip);
+  else
+    hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1, u, u2,
+                       Fp, p, nr, C.d_partial, skip);
+}
+
 static void fork_side(Ctx& C) {
   HIPCHK(hipEventRecord(C.ev_fork, C.st));
   HIPCHK(hipStreamWaitEvent(C.st2, C.ev_fork, 0));
@@ -1673,12 +1709,9 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
   hipStream_t st = C.st;
   void **X = C.X;
   if (!gathered)
-    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_glam, p, (T*)X[5], nr, skip);
+    lambda_gather<T>(C, C.n_grow, C.d_glam, p, (T*)X[5], skip);
   apply_local<T>(C, skip);
-  hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
-                     (const T*)X[8], (const T*)corner_part(C), Fp, dot ? p : (const double*)nullptr, nr,
-                     C.d_partial, skip);
+  scatter_dot<T>(C, (const T*)X[8], (const T*)corner_part(C), Fp, dot ? p : (const double*)nullptr, skip);
 }
 
 // Robin variant: y = G lam = lam + lam(partner side) - R (x_G response of
@@ -1689,8 +1722,7 @@ static void apply_G(Ctx& C, const double* lam, double* y, const int* skip) {
   const int nr = C.nrhs;
   const int64_t n = C.n_grow, nl = n * nr;
   hipStream_t st = C.st;
-  hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_grow, C.d_code2, lam,
-                     (T*)C.X[5], nr, skip);
+  lambda_gather<T>(C, n, C.d_code2, lam, (T*)C.X[5], skip);
   apply_local<T>(C, skip);
   hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow, C.d_rval,
                      C.d_partner2, lam, (const T*)C.X[8], (const T*)corner_part(C), y, nr, skip);
@@ -1890,13 +1922,23 @@ static void transposed_r(Ctx& C, const int* gate) {
   mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one, gate);
 }
 
-// z = K_lam r (the lumped preconditioner) with the r.z and r.r partials:
-// two rows in flight per lane, their nonzeros in batches of 8 (batches of
-// 12 held more registers than four waves per SIMD allow and spilled: 19.65
-// against 19.40 ms/step; one row of 12: 19.75; four rows of 6: 20.02)
+// z = K_lam r (the lumped preconditioner) with the r.z and r.r partials.
+// Vector form for even nrhs: at 16 RHS, four per lane, one row in flight,
+// nonzeros in batches of 4 (16.60 -> 16.17 ms/step at 64^3 with 16 RHS;
+// one row in batches of 8 the same, two rows spill).  Scalar form: two rows
+// in flight per lane, their nonzeros in batches of 8 (batches of 12 spilled:
+// 19.65 against 19.40 ms/step; one row of 12: 19.75; four rows of 6: 20.02)
 static void lam_precond(Ctx& C, const int* skip) {
-  hipLaunchKernelGGL((k_lam_precond<2, 8>), dim3(kDotBlocks), dim3(256), 0, C.st, C.nlam, C.d_lrp, C.d_lci,
-                     C.d_lvals, (const double*)C.d_res, C.d_z, C.nrhs, C.d_partial, C.d_partial2, skip);
+  const int nr = C.nrhs;
+  if (vec_width(nr) == 4)
+    hipLaunchKernelGGL((k_lam_precond_v<1, 4, 4>), dim3(kDotBlocks), dim3(256), 0, C.st, C.nlam, C.d_lrp, C.d_lci,
+                       C.d_lvals, (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, skip);
+  else if (vec_width(nr) == 2)
+    hipLaunchKernelGGL((k_lam_precond_v<2, 4, 2>), dim3(kDotBlocks), dim3(256), 0, C.st, C.nlam, C.d_lrp, C.d_lci,
+                       C.d_lvals, (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, skip);
+  else
+    hipLaunchKernelGGL((k_lam_precond<2, 8>), dim3(kDotBlocks), dim3(256), 0, C.st, C.nlam, C.d_lrp, C.d_lci,
+                       C.d_lvals, (const double*)C.d_res, C.d_z, nr, C.d_partial, C.d_partial2, skip);
 }
 
 // x = A^-1 b (one decomposed solve, unknown-major [nint][nrhs] FP64).
@@ -1917,8 +1959,15 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   const bool captured = fixed_iters > 0;
   if (captured && (warm || C.opt.method == 1))
     throw DDError{DD_ERR_STATE, "captured solve: no warm start, first variant only"};
-  hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
-                     (T*)X[0], nr, gate);
+  if (vec_width(nr) == 4)
+    hipLaunchKernelGGL((k_split_v<T, 4>), dim3(nblk(C.rows_total * nr / 4)), dim3(256), 0, st, C.rows_total,
+                       C.d_rowsrc, b, (T*)X[0], nr, gate);
+  else if (vec_width(nr) == 2)
+    hipLaunchKernelGGL((k_split_v<T, 2>), dim3(nblk(C.rows_total * nr / 2)), dim3(256), 0, st, C.rows_total,
+                       C.d_rowsrc, b, (T*)X[0], nr, gate);
+  else
+    hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
+                       (T*)X[0], nr, gate);
   // r rows: t = L_rr^-1 w_r;  corner rows: g = w_c - L_cr t, as three products
   // over the column blocks of the factor store:
   //   t_I = L_II^-1 w_I                                  (X1, I rows)
@@ -1946,13 +1995,11 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     // ---- Robin variant: GMRES on the per-side multipliers, then the same
     // recovery with each subdomain's own multipliers as interface loads
     status = dp2_gmres<T>(C, iters, relres);
-    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_code2, (const double*)C.d_lam2, (T*)X[5], nr, (const int*)nullptr);
+    lambda_gather<T>(C, C.n_grow, C.d_code2, (const double*)C.d_lam2, (T*)X[5], nullptr);
     mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
   } else if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
-    hipLaunchKernelGGL(k_scatter_dot<T>, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1,
-                       (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, nr, C.d_partial, gate);
+    scatter_dot<T>(C, (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, gate);
     // ---- CG on F lambda = d (stage 0 of k_cg_scalar resets the whole state) ----
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
                        C.d_partial, gate);
@@ -1985,8 +2032,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
                        gate);
     // v = B_s^T p for the first F application, padding rows zeroed (later
     // ones are written by k_cg_p_scatter, which leaves padding rows alone)
-    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_glam, (const double*)C.d_p, (T*)X[5], nr, gate);
+    lambda_gather<T>(C, C.n_grow, C.d_glam, (const double*)C.d_p, (T*)X[5], gate);
     const int* done = &C.d_cg->done;
     int it = 0;
     // an even block of iterations, so that every replay starts on p = d_p
@@ -2016,9 +2062,16 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       }
       // p' and v = B_s^T p' in multiplier order (a gather over the interface
       // rows computed each p' twice: 19.65 against 19.40 ms/step)
-      hipLaunchKernelGGL(k_cg_p_scatter<T>, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1, nr,
-                         (const CgState*)C.d_cg, (const double*)(pre ? C.d_z : C.d_res), (const double*)pc, pn,
-                         (T*)X[5]);
+      const double* base = pre ? C.d_z : C.d_res;
+      if (vec_width(nr) == 4)
+        hipLaunchKernelGGL((k_cg_p_scatter_v<T, 4>), dim3(nblk(nl / 4)), dim3(256), 0, st, C.nlam, C.d_lrow0,
+                           C.d_lrow1, nr, (const CgState*)C.d_cg, base, (const double*)pc, pn, (T*)X[5]);
+      else if (vec_width(nr) == 2)
+        hipLaunchKernelGGL((k_cg_p_scatter_v<T, 2>), dim3(nblk(nl / 2)), dim3(256), 0, st, C.nlam, C.d_lrow0,
+                           C.d_lrow1, nr, (const CgState*)C.d_cg, base, (const double*)pc, pn, (T*)X[5]);
+      else
+        hipLaunchKernelGGL(k_cg_p_scatter<T>, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, C.d_lrow0, C.d_lrow1, nr,
+                           (const CgState*)C.d_cg, base, (const double*)pc, pn, (T*)X[5]);
     };
     // captured step: a fixed number of iterations, the state snapshotted
     if (captured) {
@@ -2077,8 +2130,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     // ---- recovery -------------------------------------------------------------------
     // v_l = B_s^T lambda; interface rows of X1: t - t_l = t - Linv_GG v_l (in
     // place); its corner rows: y = Psi_G v_l (the same pass)
-    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(C.n_grow * nr)), dim3(256), 0, st, C.n_grow, C.d_grow,
-                       C.d_glam, (const double*)C.d_lam, (T*)X[5], nr, gate);
+    lambda_gather<T>(C, C.n_grow, C.d_glam, (const double*)C.d_lam, (T*)X[5], gate);
     mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone, gate);
   } else {
     // no interface: t_l = 0, y = 0 (X6, whose corner rows the coarse gather reads)
@@ -2104,8 +2156,15 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
                        C.d_csccrow, (const T*)X[5], (T*)X[1], mone, nr, gate);
   transposed_r<T>(C, gate);
-  hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
-                     (const T*)X[5], x, nr, gate);
+  if (vec_width(nr) == 4)
+    hipLaunchKernelGGL((k_collect_v<T, 4>), dim3(nblk(C.P.nint * nr / 4)), dim3(256), 0, st, (int64_t)C.P.nint,
+                       C.d_dsrc, (const T*)X[5], x, nr, gate);
+  else if (vec_width(nr) == 2)
+    hipLaunchKernelGGL((k_collect_v<T, 2>), dim3(nblk(C.P.nint * nr / 2)), dim3(256), 0, st, (int64_t)C.P.nint,
+                       C.d_dsrc, (const T*)X[5], x, nr, gate);
+  else
+    hipLaunchKernelGGL(k_collect<T>, dim3(nblk(C.P.nint * nr)), dim3(256), 0, st, (int64_t)C.P.nint, C.d_dsrc,
+                       (const T*)X[5], x, nr, gate);
   HIPCHK(hipGetLastError());
   return status;
 }

@@ -1426,6 +1426,65 @@ __global__ void __launch_bounds__(256) k_pack_tiles(int64_t ntiles, T* __restric
 }
 
 // --------------------------------------------------------------------------
+// V consecutive right-hand sides of one row in single loads / stores (the
+// row slice is aligned to 4V bytes for float and to 16 bytes for double:
+// rows hold nrhs entries, nrhs a multiple of V, and buffers are 256-byte
+// aligned).  The vector forms of the multiplier-space kernels below give
+// each lane V right-hand sides, so index loads are shared by nrhs / V lanes
+// instead of nrhs and each gather moves 4V or 8V contiguous bytes.
+// --------------------------------------------------------------------------
+template <class T, int V>
+__device__ __forceinline__ void vload(const T* __restrict__ p, T (&o)[V]) {
+  static_assert(V == 2 || V == 4, "vector width");
+  if constexpr (sizeof(T) == 4 && V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  } else if constexpr (sizeof(T) == 4) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    o[0] = t.x; o[1] = t.y;
+  } else {
+#pragma unroll
+    for (int h = 0; h < V / 2; ++h) {
+      const double2 t = reinterpret_cast<const double2*>(p)[h];
+      o[2 * h] = t.x; o[2 * h + 1] = t.y;
+    }
+  }
+}
+
+template <class T, int V>
+__device__ __forceinline__ void vstore(T* __restrict__ p, const T (&o)[V]) {
+  static_assert(V == 2 || V == 4, "vector width");
+  if constexpr (sizeof(T) == 4 && V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
+  } else {
+#pragma unroll
+    for (int h = 0; h < V / 2; ++h) reinterpret_cast<double2*>(p)[h] = make_double2(o[2 * h], o[2 * h + 1]);
+  }
+}
+
+// block partials of per-RHS sums held V to a lane: lane (l, q), l < lpr,
+// q < G = nrhs / V, holds right-hand sides q V .. q V + V - 1; summed over l
+// in lane order.  Ends with a barrier (callable twice in a row).
+template <int V>
+__device__ __forceinline__ void block_rhs_sum_v(const double (&s)[V], int nrhs, int lpr,
+                                                double* __restrict__ partial) {
+  __shared__ double red[256 * V];
+  const int tid = threadIdx.x, G = nrhs / V;
+#pragma unroll
+  for (int v = 0; v < V; ++v) red[tid * V + v] = s[v];
+  __syncthreads();
+  if (tid < nrhs) {
+    const int q = tid / V, v = tid % V;
+    double t = 0.0;
+    for (int l = 0; l < lpr; ++l) t += red[(l * G + q) * V + v];
+    partial[blockIdx.x * kMaxRhs + tid] = t;
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------------------
 // Maps between the global unknown space, the multipliers and local blocks.
 // --------------------------------------------------------------------------
 // Local block rows <- owner split of a global FP64 vector [nint][nrhs]
@@ -1503,6 +1562,73 @@ __global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, co
   int r = (int)(i % nrhs);
   int64_t c = crow[k];
   x[rows[k] * nrhs + r] = c >= 0 ? scale * z[c * nrhs + r] : (T)0;
+}
+
+// Vector forms of k_split, k_lambda_gather and k_collect: one thread per
+// (row, group of V right-hand sides).
+template <class T, int V>
+__global__ void k_split_v(int64_t rows, const int32_t* __restrict__ src, const double* __restrict__ b,
+                          T* __restrict__ w, int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * G) return;
+  const int64_t row = i / G;
+  const int q = (int)(i - row * G);
+  const int32_t d = src[row];
+  double x[V];
+  T y[V];
+  if (d >= 0) {
+    vload<double, V>(b + (int64_t)d * nrhs + q * V, x);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) y[v] = (T)x[v];
+  vstore<T, V>(w + row * nrhs + q * V, y);
+}
+
+template <class T, int V>
+__global__ void k_lambda_gather_v(int64_t n, const int64_t* __restrict__ rows, const int32_t* __restrict__ lam,
+                                  const double* __restrict__ p, T* __restrict__ v, int nrhs,
+                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * G) return;
+  const int64_t k = i / G;
+  const int q = (int)(i - k * G);
+  const int32_t l = lam[k];
+  double x[V];
+  T y[V];
+  if (l >= 0) {
+    vload<double, V>(p + (int64_t)(l >> 1) * nrhs + q * V, x);
+  } else {
+#pragma unroll
+    for (int u = 0; u < V; ++u) x[u] = 0.0;
+  }
+  const double sg = l >= 0 && (l & 1) ? -1.0 : 1.0;
+#pragma unroll
+  for (int u = 0; u < V; ++u) y[u] = (T)(sg * x[u]);
+  vstore<T, V>(v + rows[k] * nrhs + q * V, y);
+}
+
+template <class T, int V>
+__global__ void k_collect_v(int64_t nint, const int64_t* __restrict__ dsrc, const T* __restrict__ x,
+                            double* __restrict__ e, int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nint * G) return;
+  const int64_t d = i / G;
+  const int q = (int)(i - d * G);
+  T y[V];
+  double o[V];
+  vload<T, V>(x + dsrc[d] * nrhs + q * V, y);
+#pragma unroll
+  for (int u = 0; u < V; ++u) o[u] = (double)y[u];
+  vstore<double, V>(e + d * nrhs + q * V, o);
 }
 
 // Global FP64 result of unknown d = the owner's copy (dsrc[d] = row).
@@ -1896,6 +2022,68 @@ __global__ void __launch_bounds__(256) k_scatter_dot(int64_t nlam, const int64_t
   block_rhs_sum(s, nrhs, lpr, partial);
 }
 
+// Vector form of k_scatter_dot (V right-hand sides per lane).
+template <class T, int V>
+__global__ void __launch_bounds__(256) k_scatter_dot_v(int64_t nlam, const int64_t* __restrict__ row0,
+                                                       const int64_t* __restrict__ row1, const T* __restrict__ u,
+                                                       const T* __restrict__ u2, double* __restrict__ Fp,
+                                                       const double* __restrict__ p, int nrhs,
+                                                       double* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V, lpr = 256 / G;
+  const int tid = threadIdx.x, q = tid % G, lane = tid / G;
+  constexpr int RU = 4;
+  const int64_t stride = (int64_t)gridDim.x * lpr;
+  double s[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) s[v] = 0.0;
+  if (lane < lpr) {
+    for (int64_t l0 = (int64_t)blockIdx.x * lpr + lane; l0 < nlam; l0 += RU * stride) {
+      int64_t a[RU], b[RU], lc[RU];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        lc[j] = l < nlam ? l : nlam - 1;
+        a[j] = row0[lc[j]] * nrhs + q * V;
+        b[j] = row1[lc[j]] * nrhs + q * V;
+      }
+      T ua[RU][V], ub[RU][V], ta[RU][V], tb[RU][V];
+      double pv[RU][V];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        vload<T, V>(u + a[j], ua[j]);
+        vload<T, V>(u + b[j], ub[j]);
+        if (u2) {
+          vload<T, V>(u2 + a[j], ta[j]);
+          vload<T, V>(u2 + b[j], tb[j]);
+        }
+        if (p) {
+          vload<double, V>(p + lc[j] * nrhs + q * V, pv[j]);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) pv[j][v] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        if (l < nlam) {
+          double f[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const T x0 = u2 ? (T)(ua[j][v] + ta[j][v]) : ua[j][v];
+            const T x1 = u2 ? (T)(ub[j][v] + tb[j][v]) : ub[j][v];
+            f[v] = (double)x0 - (double)x1;
+            if (p) s[v] += pv[j][v] * f[v];
+          }
+          vstore<double, V>(Fp + l * nrhs + q * V, f);
+        }
+      }
+    }
+  }
+  block_rhs_sum_v<V>(s, nrhs, lpr, partial);
+}
+
 struct CgState {
   double rr[kMaxRhs];      // current r.r
   double rz[kMaxRhs];      // current r.z (z = preconditioned r; r.r without a preconditioner)
@@ -2105,6 +2293,93 @@ __global__ void __launch_bounds__(256, 4) k_lam_precond(int64_t nlam, const int6
   block_rhs_sum(sr, nrhs, lpr, partial_b);
 }
 
+// Vector form of k_lam_precond: V consecutive right-hand sides per lane
+// (nrhs a multiple of V, G = nrhs / V lanes per row), so that the index and
+// value loads of a nonzero are shared by G lanes instead of nrhs and each
+// gather moves 8V contiguous bytes.  RU rows per lane in flight, their
+// nonzeros in batches of KB, as in k_lam_precond; each right-hand side's
+// rows and nonzeros are summed in the order of the plain loop, the block
+// partials over lanes in lane order.
+template <int RU, int KB, int V>
+__global__ void __launch_bounds__(256, 4) k_lam_precond_v(int64_t nlam, const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ ci, const double* __restrict__ val,
+                                                       const double* __restrict__ res, double* __restrict__ z,
+                                                       int nrhs, double* __restrict__ partial,
+                                                       double* __restrict__ partial_b, const int* __restrict__ skip) {
+  static_assert(V == 2 || V == 4, "right-hand sides per lane");
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int lpr = 256 / G;
+  const int tid = threadIdx.x, q = tid % G, lane = tid / G;
+  const int64_t stride = (int64_t)gridDim.x * lpr;
+  double sz[V], sr[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) sz[v] = sr[v] = 0.0;
+  auto load = [&](const double* a, double (&o)[V]) { vload<double, V>(a, o); };
+  if (lane < lpr) {
+    for (int64_t l0 = (int64_t)blockIdx.x * lpr + lane; l0 < nlam; l0 += RU * stride) {
+      int64_t ka[RU], kz[RU];
+      double rv[RU][V], acc[RU][V];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        const int64_t lc = l < nlam ? l : nlam - 1;
+        const int64_t a0 = rp[lc], a1 = rp[lc + 1];
+        load(res + lc * nrhs + q * V, rv[j]);
+        ka[j] = a0;
+        kz[j] = l < nlam ? a1 : a0;  // rows past the end are empty
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[j][v] = 0.0;
+      }
+      int nb = 0;
+#pragma unroll
+      for (int j = 0; j < RU; ++j) nb = max(nb, (int)((kz[j] - ka[j] + KB - 1) / KB));
+      for (int bi = 0; bi < nb; ++bi) {
+        int32_t c[RU][KB];
+        double w[RU][KB], x[RU][KB][V];
+#pragma unroll
+        for (int j = 0; j < RU; ++j)
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            const int64_t k = ka[j] + (int64_t)bi * KB + u;
+            const int64_t kc = k < kz[j] ? k : 0;  // in bounds (the matrix is not empty here)
+            c[j][u] = ci[kc];
+            w[j][u] = val[kc];
+          }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < RU; ++j)
+#pragma unroll
+          for (int u = 0; u < KB; ++u) load(res + (int64_t)c[j][u] * nrhs + q * V, x[j][u]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < RU; ++j)
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            const int64_t k = ka[j] + (int64_t)bi * KB + u;
+            const double wv = k < kz[j] ? w[j][u] : 0.0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[j][v] += wv * x[j][u][v];
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const int64_t l = l0 + j * stride;
+        if (l < nlam) {
+          vstore<double, V>(z + l * nrhs + q * V, acc[j]);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            sz[v] += rv[j][v] * acc[j][v];
+            sr[v] += rv[j][v] * rv[j][v];
+          }
+        }
+      }
+    }
+  }
+  block_rhs_sum_v<V>(sz, nrhs, lpr, partial);
+  block_rhs_sum_v<V>(sr, nrhs, lpr, partial_b);
+}
+
 // p' = base + beta p for the RHS still active after the beta stage (p kept
 // otherwise; base = z, or r without a preconditioner), once per multiplier
 // (coalesced reads and writes of the multiplier vectors), then v = B_s^T p'
@@ -2125,6 +2400,35 @@ __global__ void k_cg_p_scatter(int64_t nlam, const int64_t* __restrict__ row0, c
   pnext[i] = pn;
   v[row0[l] * nrhs + r] = (T)pn;
   v[row1[l] * nrhs + r] = (T)(-pn);
+}
+
+// Vector form of k_cg_p_scatter: one thread per (multiplier, group of V
+// right-hand sides).
+template <class T, int V>
+__global__ void k_cg_p_scatter_v(int64_t nlam, const int64_t* __restrict__ row0, const int64_t* __restrict__ row1,
+                                 int nrhs, const CgState* __restrict__ st, const double* __restrict__ base,
+                                 const double* __restrict__ pcur, double* __restrict__ pnext, T* __restrict__ v) {
+  if (st->done) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlam * G) return;
+  const int64_t l = i / G;
+  const int q = (int)(i - l * G);
+  const int64_t o = l * nrhs + q * V;
+  double bv[V], pc[V], pn[V];
+  vload<double, V>(base + o, bv);
+  vload<double, V>(pcur + o, pc);
+  T yp[V], ym[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int r = q * V + u;
+    pn[u] = st->active[r] ? bv[u] + st->beta[r] * pc[u] : pc[u];
+    yp[u] = (T)pn[u];
+    ym[u] = (T)(-pn[u]);
+  }
+  vstore<double, V>(pnext + o, pn);
+  vstore<T, V>(v + row0[l] * nrhs + q * V, yp);
+  vstore<T, V>(v + row1[l] * nrhs + q * V, ym);
 }
 
 __global__ void k_extrap(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
