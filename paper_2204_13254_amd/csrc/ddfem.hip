@@ -2237,7 +2237,15 @@ static void capture_step(Ctx& C, Ctx::StepGraph& sg, const double* b, double* x,
     hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_rpart, C.d_rs);
     dd_solve_once<T>(C, b, x, nullptr, it_dummy, rr_dummy, gate, iters, 0);
     for (int k = 1; k <= sweeps + 1; ++k) {
-      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, tx, gate + (k - 1), sx);
+      // only the last residual writes T x and S x (460 MB less at 64^3 with
+      // 16 RHS), and it runs even when an earlier check has passed (x is
+      // then the accepted iterate, the later sweeps being skipped), so T x
+      // and S x always belong to the returned x.  Its norm and check stay
+      // gated.  The residual arithmetic is the same in every pass (captured
+      // and eager steps agree bit for bit).
+      const bool last = k == sweeps + 1;
+      csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, last ? tx : nullptr,
+                 last && tx ? nullptr : gate + (k - 1), last ? sx : nullptr);
       hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.P.nint, (const double*)C.g_r,
                          (const double*)C.g_r, nr, C.d_rpart, (const int*)(gate + (k - 1)));
       hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(kScalarThreads), 0, st, k, nr, (const double*)C.d_rpart,

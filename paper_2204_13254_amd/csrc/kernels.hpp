@@ -617,6 +617,65 @@ struct MvItem {
 constexpr int32_t kListMask = (1 << 25) - 1;
 constexpr int32_t kPairMask = (1 << 21) - 1;
 
+// --------------------------------------------------------------------------
+// V consecutive right-hand sides of one row in single loads / stores (the
+// row slice is aligned to 4V bytes for float and to 16 bytes for double:
+// rows hold nrhs entries, nrhs a multiple of V, and buffers are 256-byte
+// aligned).  The vector forms of the multiplier-space kernels below give
+// each lane V right-hand sides, so index loads are shared by nrhs / V lanes
+// instead of nrhs and each gather moves 4V or 8V contiguous bytes.
+// --------------------------------------------------------------------------
+template <class T, int V>
+__device__ __forceinline__ void vload(const T* __restrict__ p, T (&o)[V]) {
+  static_assert(V == 2 || V == 4, "vector width");
+  if constexpr (sizeof(T) == 4 && V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  } else if constexpr (sizeof(T) == 4) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    o[0] = t.x; o[1] = t.y;
+  } else {
+#pragma unroll
+    for (int h = 0; h < V / 2; ++h) {
+      const double2 t = reinterpret_cast<const double2*>(p)[h];
+      o[2 * h] = t.x; o[2 * h + 1] = t.y;
+    }
+  }
+}
+
+template <class T, int V>
+__device__ __forceinline__ void vstore(T* __restrict__ p, const T (&o)[V]) {
+  static_assert(V == 2 || V == 4, "vector width");
+  if constexpr (sizeof(T) == 4 && V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+  } else if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
+  } else {
+#pragma unroll
+    for (int h = 0; h < V / 2; ++h) reinterpret_cast<double2*>(p)[h] = make_double2(o[2 * h], o[2 * h + 1]);
+  }
+}
+
+// block partials of per-RHS sums held V to a lane: lane (l, q), l < lpr,
+// q < G = nrhs / V, holds right-hand sides q V .. q V + V - 1; summed over l
+// in lane order.  Ends with a barrier (callable twice in a row).
+template <int V>
+__device__ __forceinline__ void block_rhs_sum_v(const double (&s)[V], int nrhs, int lpr,
+                                                double* __restrict__ partial) {
+  __shared__ double red[256 * V];
+  const int tid = threadIdx.x, G = nrhs / V;
+#pragma unroll
+  for (int v = 0; v < V; ++v) red[tid * V + v] = s[v];
+  __syncthreads();
+  if (tid < nrhs) {
+    const int q = tid / V, v = tid % V;
+    double t = 0.0;
+    for (int l = 0; l < lpr; ++l) t += red[(l * G + q) * V + v];
+    partial[blockIdx.x * kMaxRhs + tid] = t;
+  }
+  __syncthreads();
+}
+
 struct MvOut {
   int32_t s, o, slot0, nslot;
 };
@@ -1302,24 +1361,33 @@ __global__ void __launch_bounds__(256) k_mv_reduce(int64_t n_out, const MvOut* _
   const T alpha = crow ? alpha_c : alpha_r;
   const int64_t base = (q.row_off + (int64_t)w.o * kNB) * nrhs;
   const int64_t stride = (int64_t)kNB * nrhs;
-  for (int e = threadIdx.x; e < kNB * nrhs; e += 256) {
+  // four consecutive elements per thread (a block holds 32 nrhs elements, a
+  // multiple of 4, and every slot and output block starts on a multiple of 4)
+  for (int e = 4 * threadIdx.x; e < kNB * nrhs; e += 4 * 256) {
     const T* pp = partial + (int64_t)w.slot0 * stride + e;
-    T s = 0;
+    T s[4] = {0, 0, 0, 0};
     // up to eight loads in flight before their adds (n is uniform: scalar
     // branches, no wasted loads); the sum keeps slot order
     for (int k = 0; k < w.nslot; k += 8) {
       const int n = min(8, w.nslot - k);
-      T p[8];
+      T p[8][4];
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (u < n) p[u] = pp[(int64_t)(k + u) * stride];
+        if (u < n) vload<T, 4>(pp + (int64_t)(k + u) * stride, p[u]);
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (u < n) s += p[u];
+        if (u < n)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s[c] += p[u][c];
     }
-    T v = alpha * s;
-    if (add) v += add[base + e];
-    out[base + e] = v;
+    T v[4], a[4];
+    if (add) vload<T, 4>(add + base + e, a);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      v[c] = alpha * s[c];
+      if (add) v[c] += a[c];
+    }
+    vstore<T, 4>(out + base + e, v);
   }
 }
 
@@ -1423,65 +1491,6 @@ __global__ void __launch_bounds__(256) k_pack_tiles(int64_t ntiles, T* __restric
     p[swz<T>(r, c)] = a[r][c];
     q[swz<T>(r, c)] = a[c][r];
   }
-}
-
-// --------------------------------------------------------------------------
-// V consecutive right-hand sides of one row in single loads / stores (the
-// row slice is aligned to 4V bytes for float and to 16 bytes for double:
-// rows hold nrhs entries, nrhs a multiple of V, and buffers are 256-byte
-// aligned).  The vector forms of the multiplier-space kernels below give
-// each lane V right-hand sides, so index loads are shared by nrhs / V lanes
-// instead of nrhs and each gather moves 4V or 8V contiguous bytes.
-// --------------------------------------------------------------------------
-template <class T, int V>
-__device__ __forceinline__ void vload(const T* __restrict__ p, T (&o)[V]) {
-  static_assert(V == 2 || V == 4, "vector width");
-  if constexpr (sizeof(T) == 4 && V == 4) {
-    const float4 t = *reinterpret_cast<const float4*>(p);
-    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
-  } else if constexpr (sizeof(T) == 4) {
-    const float2 t = *reinterpret_cast<const float2*>(p);
-    o[0] = t.x; o[1] = t.y;
-  } else {
-#pragma unroll
-    for (int h = 0; h < V / 2; ++h) {
-      const double2 t = reinterpret_cast<const double2*>(p)[h];
-      o[2 * h] = t.x; o[2 * h + 1] = t.y;
-    }
-  }
-}
-
-template <class T, int V>
-__device__ __forceinline__ void vstore(T* __restrict__ p, const T (&o)[V]) {
-  static_assert(V == 2 || V == 4, "vector width");
-  if constexpr (sizeof(T) == 4 && V == 4) {
-    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
-  } else if constexpr (sizeof(T) == 4) {
-    *reinterpret_cast<float2*>(p) = make_float2(o[0], o[1]);
-  } else {
-#pragma unroll
-    for (int h = 0; h < V / 2; ++h) reinterpret_cast<double2*>(p)[h] = make_double2(o[2 * h], o[2 * h + 1]);
-  }
-}
-
-// block partials of per-RHS sums held V to a lane: lane (l, q), l < lpr,
-// q < G = nrhs / V, holds right-hand sides q V .. q V + V - 1; summed over l
-// in lane order.  Ends with a barrier (callable twice in a row).
-template <int V>
-__device__ __forceinline__ void block_rhs_sum_v(const double (&s)[V], int nrhs, int lpr,
-                                                double* __restrict__ partial) {
-  __shared__ double red[256 * V];
-  const int tid = threadIdx.x, G = nrhs / V;
-#pragma unroll
-  for (int v = 0; v < V; ++v) red[tid * V + v] = s[v];
-  __syncthreads();
-  if (tid < nrhs) {
-    const int q = tid / V, v = tid % V;
-    double t = 0.0;
-    for (int l = 0; l < lpr; ++l) t += red[(l * G + q) * V + v];
-    partial[blockIdx.x * kMaxRhs + tid] = t;
-  }
-  __syncthreads();
 }
 
 // --------------------------------------------------------------------------
