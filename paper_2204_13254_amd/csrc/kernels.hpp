@@ -1920,6 +1920,125 @@ __global__ void __launch_bounds__(256) k_csr_coop(int64_t nint, const int64_t* _
   }
 }
 
+// Vector form of k_csr_coop: G lanes of a row with V right-hand sides each
+// (nrhs = G V; G a power of two, so a row never straddles a wave).  A row's
+// nonzeros are staged in LDS in batches of NB (the G lanes load NB / G each)
+// and read back as broadcasts; each gather moves the V right-hand sides of
+// one column (8V contiguous bytes), in chunks of 4 up to the wave's longest
+// row.  Every right-hand side sums its products in ascending nonzero order,
+// as in k_csr.  Modes as in k_csr.
+template <int G, int V, int NB, int MODE>
+__global__ void __launch_bounds__(256) k_csr_vec(int64_t nint, const int64_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci, const double2* __restrict__ v,
+                                                 const double* __restrict__ x1, const double* __restrict__ x2,
+                                                 const double* __restrict__ j1, const double* __restrict__ j2,
+                                                 const double* __restrict__ z, double dt, double ca, double cb,
+                                                 double* __restrict__ y, double* __restrict__ y2, int nrhs,
+                                                 const int* __restrict__ skip, double* __restrict__ y3) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "lanes per row");
+  static_assert(NB % G == 0 && NB % 4 == 0, "batch shape");
+  if (skip && *skip) return;
+  constexpr int ROWS = 256 / G;  // rows per workgroup
+  constexpr int E = NB / G;      // staged nonzeros per lane
+  __shared__ int32_t s_c[ROWS * NB];
+  __shared__ double2 s_v[ROWS * NB];
+  const int64_t blk = xcd_contiguous_block();
+  if (blk * ROWS >= nint) return;  // whole workgroup past the last row
+  const int lr = (int)threadIdx.x % G;
+  const int64_t row_raw = blk * ROWS + (int)threadIdx.x / G;
+  const bool live = row_raw < nint;
+  const int64_t row = live ? row_raw : nint - 1;
+  const int gb = ((int)threadIdx.x / G) * NB;  // this row's LDS slots
+  const int64_t xo = (int64_t)lr * V;            // this lane's right-hand sides
+  const int64_t k0 = rp[row], k1 = rp[row + 1];
+  int nbat = (int)((k1 - k0 + NB - 1) / NB);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) nbat = max(nbat, __shfl_xor(nbat, off));
+  double t1[V], s1[V], t2[V], s2[V];
+#pragma unroll
+  for (int w = 0; w < V; ++w) t1[w] = s1[w] = t2[w] = s2[w] = 0.0;
+  for (int bi = 0; bi < nbat; ++bi) {
+    const int64_t kb = k0 + (int64_t)bi * NB;
+    int wcnt = (int)(k1 - kb < NB ? (k1 - kb > 0 ? k1 - kb : 0) : NB);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) wcnt = max(wcnt, __shfl_xor(wcnt, off));
+    wcnt = __builtin_amdgcn_readfirstlane(wcnt);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int slot = e * G + lr;
+      const int64_t k = kb + slot;
+      const int64_t kc = k < k1 ? k : (k1 > k0 ? k0 : 0);  // in bounds (nnz > 0)
+      const int32_t cv = ci[kc];
+      const double2 vv = v[kc];
+      // padding: the row's first column with a zero value
+      s_c[gb + slot] = cv;
+      s_v[gb + slot] = k < k1 ? vv : make_double2(0.0, 0.0);
+    }
+    wave_lds_sync();
+    auto run = [&](const double* __restrict__ xv, double (&tt)[V], double (&ss)[V]) {
+      double a[NB][V];
+#pragma unroll
+      for (int q = 0; q < NB / 4; ++q) {
+        if (wcnt > 4 * q) {
+#pragma unroll
+          for (int u = 4 * q; u < 4 * q + 4; ++u) vload<double, V>(xv + (int64_t)s_c[gb + u] * nrhs + xo, a[u]);
+        } else {
+#pragma unroll
+          for (int u = 4 * q; u < 4 * q + 4; ++u)
+#pragma unroll
+            for (int w = 0; w < V; ++w) a[u][w] = 0.0;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const double2 vv = s_v[gb + u];
+#pragma unroll
+        for (int w = 0; w < V; ++w) {
+          tt[w] += vv.x * a[u][w];
+          ss[w] += vv.y * a[u][w];
+        }
+      }
+    };
+    run(x1, t1, s1);
+    if constexpr (MODE == 0) {
+      __asm__ volatile("" ::: "memory");
+      run(x2, t2, s2);
+    }
+    wave_lds_sync();  // the next batch overwrites this row's slots
+  }
+  if (!live) return;
+  const int64_t o = row * nrhs + xo;
+  double r0[V], r1[V], r2[V];
+  if constexpr (MODE == 0) {
+    double a1[V], a2[V];
+    vload<double, V>(j1 + o, a1);
+    vload<double, V>(j2 + o, a2);
+#pragma unroll
+    for (int w = 0; w < V; ++w) r0[w] = (2.0 * t1[w] + cb * s1[w]) - (t2[w] + ca * s2[w]) - dt * (a1[w] - a2[w]);
+    vstore<double, V>(y + o, r0);
+  } else if constexpr (MODE == 1) {
+    double zz[V];
+    vload<double, V>(z + o, zz);
+#pragma unroll
+    for (int w = 0; w < V; ++w) r0[w] = zz[w] - (t1[w] + ca * s1[w]);
+    vstore<double, V>(y + o, r0);
+    if (y2) vstore<double, V>(y2 + o, t1);
+    if (y3) vstore<double, V>(y3 + o, s1);
+  } else if constexpr (MODE == 2) {
+#pragma unroll
+    for (int w = 0; w < V; ++w) {
+      r1[w] = 2.0 * t1[w] + cb * s1[w];
+      r2[w] = t1[w] + ca * s1[w];
+    }
+    vstore<double, V>(y + o, r1);
+    vstore<double, V>(y2 + o, r2);
+  } else {
+    vstore<double, V>(y + o, t1);
+    vstore<double, V>(y2 + o, s1);
+  }
+}
+
 // Newmark load from stored products (the resident step): with te = T e,
 // se = S e of e^n (0) and e^{n-1} (1),
 //   y = (2 T e^n + cb S e^n) - (T e^{n-1} + ca S e^{n-1}) - dt (J^{n+1/2} - J^{n-1/2}),

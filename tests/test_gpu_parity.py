@@ -116,8 +116,10 @@ def test_uneven_graded_multi_rhs(prec, tol, nrhs):
 
 
 # right-hand-side counts 2, 6, 12 and 24 take the per-thread sparse (T, S)
-# product and its cooperative forms with 8, 16 and 32 lanes per row
-@pytest.mark.parametrize("nrhs", [2, 6, 12, 24])
+# product and its cooperative forms with 8, 16 and 32 lanes per row; 8, 16
+# and 32 its vector form (two right-hand sides per lane, 4, 8 and 16 lanes
+# per row)
+@pytest.mark.parametrize("nrhs", [2, 6, 8, 12, 16, 24, 32])
 def test_gauss_law_and_energy_match_oracle(nrhs):
     c, t, p, eps = _case(6, 2, eps_seed=4)
     dt = 0.05
