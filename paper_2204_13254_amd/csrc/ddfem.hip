@@ -1588,6 +1588,18 @@ static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, c
 // the scalar forms.
 static int vec_width(int nr) { return nr % 4 == 0 ? 4 : (nr % 2 == 0 ? 2 : 1); }
 
+// per-RHS block partials of x . y over n rows [n][nrhs] (kDotBlocks blocks)
+static void dot_partial(Ctx& C, hipStream_t st, int64_t n, const double* x, const double* y, double* partial,
+                        const int* skip) {
+  const int nr = C.nrhs, V = vec_width(nr);
+  if (V == 4)
+    hipLaunchKernelGGL((k_dot_partial_v<4>), dim3(kDotBlocks), dim3(256), 0, st, n, x, y, nr, partial, skip);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_dot_partial_v<2>), dim3(kDotBlocks), dim3(256), 0, st, n, x, y, nr, partial, skip);
+  else
+    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, n, x, y, nr, partial, skip);
+}
+
 // v[rows[k]] = sign * p[lam[k]] (B_s^T p on the listed interface rows)
 template <class T>
 static void lambda_gather(Ctx& C, int64_t n, const int32_t* lam, const double* p, T* v, const int* skip) {
@@ -1808,8 +1820,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
                      C.d_partner2, (const double*)nullptr, (const T*)C.X[4], (const T*)nullptr, C.d_gm_rhs, nr,
                      (const int*)nullptr);
   hipLaunchKernelGGL(k_zero<double>, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_lam2, (const int*)nullptr);
-  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, n, (const double*)C.d_gm_rhs,
-                     (const double*)C.d_gm_rhs, nr, C.d_gm_wpart, (const int*)nullptr);
+  dot_partial(C, st, n, (const double*)C.d_gm_rhs, (const double*)C.d_gm_rhs, C.d_gm_wpart, nullptr);
   hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_gm_wpart, gs);
   auto read_state = [&]() {
     HIPCHK(hipMemcpyAsync(C.h_gm_st, gs, sizeof(GmState), hipMemcpyDeviceToHost, st));
@@ -1831,8 +1842,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
       apply_G<T>(C, C.d_lam2, V, nullptr);
       hipLaunchKernelGGL(k_rsub, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_gm_rhs, V);
     }
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, n, (const double*)V, (const double*)V, nr,
-                       C.d_gm_wpart, (const int*)nullptr);
+    dot_partial(C, st, n, (const double*)V, (const double*)V, C.d_gm_wpart, nullptr);
     hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_gm_wpart, gs,
                        C.d_gm_g, m, cap);
     hipLaunchKernelGGL(k_vnormalize, dim3(nblk(nl)), dim3(256), 0, st, n, (const double*)V, (const double*)gs->ss,
@@ -1883,8 +1893,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
 }
 
 static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, double* out) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, C.st, n, x, y, C.nrhs, C.d_partial,
-                     (const int*)nullptr);
+  dot_partial(C, C.st, n, x, y, C.d_partial, nullptr);
   HIPCHK(hipMemcpyAsync(C.h_partial, C.d_partial, sizeof(double) * kDotBlocks * kMaxRhs, hipMemcpyDeviceToHost,
                         C.st));
   HIPCHK(hipStreamSynchronize(C.st));
@@ -2001,8 +2010,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     const int64_t nl = C.nlam * nr;
     scatter_dot<T>(C, (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, gate);
     // ---- CG on F lambda = d (stage 0 of k_cg_scalar resets the whole state) ----
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_d, C.d_d, nr,
-                       C.d_partial, gate);
+    dot_partial(C, st, C.nlam, C.d_d, C.d_d, C.d_partial, gate);
     hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 0, nr, (const double*)C.d_partial,
                        (const double*)nullptr, C.d_cg, C.opt.cg_tol, gate);
     hipLaunchKernelGGL(k_copy, dim3(nblk(nl)), dim3(256), 0, st, nl, (const double*)C.d_d, C.d_res, gate);
@@ -2014,8 +2022,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
         HIPCHK(hipMemcpyAsync(C.d_lam, warm->cur, nl * sizeof(double), hipMemcpyDeviceToDevice, st));
       apply_F<T>(C, C.d_lam, C.d_Fp, nullptr);
       hipLaunchKernelGGL(k_sub, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_d, C.d_Fp, C.d_res);
-      hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.nlam, C.d_res, C.d_res, nr,
-                         C.d_partial, (const int*)nullptr);
+      dot_partial(C, st, C.nlam, C.d_res, C.d_res, C.d_partial, nullptr);
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 3, nr, (const double*)C.d_partial,
                          (const double*)nullptr, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
     } else {
@@ -2049,8 +2056,15 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 1, nr, (const double*)C.d_partial,
                          (const double*)nullptr, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
       if (pre) {
-        hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
-                           (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
+        if (vec_width(nr) == 4)
+          hipLaunchKernelGGL((k_cg_xr_v<4>), dim3(nblk(nl / 4)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                             (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
+        else if (vec_width(nr) == 2)
+          hipLaunchKernelGGL((k_cg_xr_v<2>), dim3(nblk(nl / 2)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                             (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
+        else
+          hipLaunchKernelGGL(k_cg_xr, dim3(nblk(nl)), dim3(256), 0, st, C.nlam, nr, (const CgState*)C.d_cg,
+                             (const double*)pc, (const double*)C.d_Fp, C.d_lam, C.d_res);
         lam_precond(C, done);
         hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(kScalarThreads), 0, st, 2, nr, (const double*)C.d_partial,
                            (const double*)C.d_partial2, C.d_cg, C.opt.cg_tol, (const int*)nullptr);
@@ -2260,8 +2274,7 @@ static void capture_step(Ctx& C, Ctx::StepGraph& sg, const double* b, double* x,
   HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   try {
     int* gate = reinterpret_cast<int*>(reinterpret_cast<char*>(C.d_rs) + offsetof(RefineState, gate));
-    hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.P.nint, b, b, nr, C.d_rpart,
-                       (const int*)nullptr);
+    dot_partial(C, st, C.P.nint, b, b, C.d_rpart, nullptr);
     hipLaunchKernelGGL(k_refine_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_rpart, C.d_rs);
     dd_solve_once<T>(C, b, x, nullptr, it_dummy, rr_dummy, gate, iters, 0);
     for (int k = 1; k <= sweeps + 1; ++k) {
@@ -2274,8 +2287,7 @@ static void capture_step(Ctx& C, Ctx::StepGraph& sg, const double* b, double* x,
       const bool last = k == sweeps + 1;
       csr_launch(C, st, 1, x, nullptr, nullptr, nullptr, b, ca, cb, C.g_r, last ? tx : nullptr,
                  last && tx ? nullptr : gate + (k - 1), last ? sx : nullptr);
-      hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, C.P.nint, (const double*)C.g_r,
-                         (const double*)C.g_r, nr, C.d_rpart, (const int*)(gate + (k - 1)));
+      dot_partial(C, st, C.P.nint, (const double*)C.g_r, (const double*)C.g_r, C.d_rpart, gate + (k - 1));
       hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(kScalarThreads), 0, st, k, nr, (const double*)C.d_rpart,
                          C.opt.refine_tol, C.d_rs, C.d_cg);
       if (k > sweeps) break;
@@ -2478,10 +2490,16 @@ static void step_diagnostics(Ctx& C, const double* Jint, const double* e1, const
     // residual, or its own product in the FP64 form)
     if (stats && !have_tx) csr_launch(C, st, 3, e1, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, tx, C.g_r);
     double* gpart = stats ? C.d_gpart : nullptr;
-    const int vpb = (256 - 256 % nr) / nr;
+    // even nrhs: two right-hand sides per lane
+    const int lanes = nr % 2 == 0 ? nr / 2 : nr;
+    const int vpb = (256 - 256 % lanes) / lanes;
     const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGaussBlocks, nblk(C.P.nv, vpb)));
-    hipLaunchKernelGGL(k_gauss_step, dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
-                       C.d_vdof, C.d_nodeint, Jint, C.dt, stats ? (const double*)tx : nullptr, C.d_q, gpart);
+    if (nr % 2 == 0)
+      hipLaunchKernelGGL((k_gauss_step_v<2>), dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
+                         C.d_vdof, C.d_nodeint, Jint, C.dt, stats ? (const double*)tx : nullptr, C.d_q, gpart);
+    else
+      hipLaunchKernelGGL(k_gauss_step, dim3(gb), dim3(256), 0, st, (int64_t)C.P.nv, nr, C.d_vptr,
+                         C.d_vdof, C.d_nodeint, Jint, C.dt, stats ? (const double*)tx : nullptr, C.d_q, gpart);
     if (stats) {
       hipLaunchKernelGGL(k_gauss_max, dim3(1), dim3(1024), 0, st, (int)gb, nr, (const double*)C.d_gpart, C.d_gmax);
       HIPCHK(hipMemcpyAsync(C.h_partial, C.d_gmax, sizeof(double) * nr * 2, hipMemcpyDeviceToHost, st));

@@ -2084,6 +2084,30 @@ __global__ void __launch_bounds__(256) k_dot_partial(int64_t n, const double* __
   }
 }
 
+// Vector form of k_dot_partial: V right-hand sides per lane (nrhs a
+// multiple of V), one 8V-byte load of each vector per row.
+template <int V>
+__global__ void __launch_bounds__(256) k_dot_partial_v(int64_t n, const double* __restrict__ x,
+                                                       const double* __restrict__ y, int nrhs,
+                                                       double* __restrict__ partial, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V, lpr = 256 / G;
+  const int tid = threadIdx.x, q = tid % G, lane = tid / G;
+  double s[V];
+#pragma unroll
+  for (int w = 0; w < V; ++w) s[w] = 0.0;
+  if (lane < lpr) {
+    for (int64_t row = (int64_t)blockIdx.x * lpr + lane; row < n; row += (int64_t)gridDim.x * lpr) {
+      double a[V], b[V];
+      vload<double, V>(x + row * nrhs + q * V, a);
+      vload<double, V>(y + row * nrhs + q * V, b);
+#pragma unroll
+      for (int w = 0; w < V; ++w) s[w] += a[w] * b[w];
+    }
+  }
+  block_rhs_sum_v<V>(s, nrhs, lpr, partial);
+}
+
 // Block-level sum of per-thread values s (thread layout tid = lane*nrhs + r)
 // into partial[blockIdx.x][r].
 __device__ __forceinline__ void block_rhs_sum(double s, int nrhs, int lanes_per_rhs, double* __restrict__ partial) {
@@ -2341,6 +2365,30 @@ __global__ void k_cg_xr(int64_t n, int nrhs, const CgState* __restrict__ st, con
   const double a = st->alpha[(int)(i % nrhs)];
   lam[i] += a * p[i];
   res[i] -= a * Fp[i];
+}
+
+// Vector form of k_cg_xr: V consecutive entries (of one multiplier row) per
+// thread, nrhs a multiple of V.
+template <int V>
+__global__ void k_cg_xr_v(int64_t n, int nrhs, const CgState* __restrict__ st, const double* __restrict__ p,
+                          const double* __restrict__ Fp, double* __restrict__ lam, double* __restrict__ res) {
+  if (st->done) return;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+  if (i >= n * nrhs) return;
+  const int r0 = (int)(i % nrhs);
+  double pv[V], fv[V], lv[V], rv[V];
+  vload<double, V>(p + i, pv);
+  vload<double, V>(Fp + i, fv);
+  vload<double, V>(lam + i, lv);
+  vload<double, V>(res + i, rv);
+#pragma unroll
+  for (int w = 0; w < V; ++w) {
+    const double a = st->alpha[r0 + w];
+    lv[w] += a * pv[w];
+    rv[w] -= a * fv[w];
+  }
+  vstore<double, V>(lam + i, lv);
+  vstore<double, V>(res + i, rv);
 }
 
 // z = K_lam r (the lumped preconditioner, CSR in multiplier space), fused
@@ -2763,6 +2811,86 @@ __global__ void __launch_bounds__(256) k_gauss_step(int64_t nv, int nrhs, const 
     for (int u = t + nrhs; u < bs; u += nrhs) {
       a = nan_max(a, red[0][u]);
       b = fmax(b, red[1][u]);
+    }
+    part[(int64_t)blockIdx.x * 2 * kMaxRhs + 2 * t] = a;
+    part[(int64_t)blockIdx.x * 2 * kMaxRhs + 2 * t + 1] = b;
+  }
+}
+
+// Vector form of k_gauss_step: V right-hand sides per lane (nrhs a multiple
+// of V; G = nrhs / V lanes per vertex), each gather one 8V-byte load.
+template <int V>
+__global__ void __launch_bounds__(256) k_gauss_step_v(int64_t nv, int nrhs, const int64_t* __restrict__ vptr,
+                                                      const int32_t* __restrict__ vdof,
+                                                      const uint8_t* __restrict__ node_int,
+                                                      const double* __restrict__ J, double dt,
+                                                      const double* __restrict__ Tx, double* __restrict__ q,
+                                                      double* __restrict__ part) {
+  const int G = nrhs / V;
+  const int bs = 256 - 256 % G, vpb = bs / G;
+  const int t = threadIdx.x, lq = t % G;
+  double mres[V], mq[V];
+#pragma unroll
+  for (int w = 0; w < V; ++w) mres[w] = mq[w] = 0.0;
+  for (int64_t v = (int64_t)blockIdx.x * vpb + t / G; t < bs && v < nv; v += (int64_t)gridDim.x * vpb) {
+    if (!node_int[v]) continue;  // the charge of boundary vertices stays 0
+    double sj[V], st[V];
+#pragma unroll
+    for (int w = 0; w < V; ++w) sj[w] = st[w] = 0.0;
+    constexpr int GB = 8;
+    const int64_t k0 = vptr[v], k1 = vptr[v + 1];
+    for (int64_t kb = k0; kb < k1; kb += GB) {
+      int32_t code[GB];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) code[u] = vdof[kb + u < k1 ? kb + u : k1 - 1];
+      double jv[GB][V], tv[GB][V];
+#pragma unroll
+      for (int u = 0; u < GB; ++u) {
+        const int64_t o = (int64_t)(code[u] >> 1) * nrhs + lq * V;
+        vload<double, V>(J + o, jv[u]);
+        if (Tx) {
+          vload<double, V>(Tx + o, tv[u]);
+        } else {
+#pragma unroll
+          for (int w = 0; w < V; ++w) tv[u][w] = 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < GB; ++u)
+        if (kb + u < k1) {
+          const double sg = (code[u] & 1) ? -1.0 : 1.0;
+#pragma unroll
+          for (int w = 0; w < V; ++w) {
+            sj[w] += sg * jv[u][w];
+            st[w] += sg * tv[u][w];
+          }
+        }
+    }
+    const int64_t o = v * nrhs + lq * V;
+    double qn[V];
+    vload<double, V>(q + o, qn);
+#pragma unroll
+    for (int w = 0; w < V; ++w) {
+      qn[w] = qn[w] + dt * sj[w];
+      mq[w] = fmax(mq[w], fabs(qn[w]));
+      mres[w] = nan_max(mres[w], fabs(st[w] + qn[w]));
+    }
+    vstore<double, V>(q + o, qn);
+  }
+  if (!part) return;
+  __shared__ double red[2][256 * V];
+#pragma unroll
+  for (int w = 0; w < V; ++w) {
+    red[0][t * V + w] = mres[w];
+    red[1][t * V + w] = mq[w];
+  }
+  __syncthreads();
+  if (t < nrhs) {
+    const int g = t / V, w = t % V;
+    double a = red[0][g * V + w], b = red[1][g * V + w];
+    for (int u = g + G; u < bs; u += G) {
+      a = nan_max(a, red[0][u * V + w]);
+      b = fmax(b, red[1][u * V + w]);
     }
     part[(int64_t)blockIdx.x * 2 * kMaxRhs + 2 * t] = a;
     part[(int64_t)blockIdx.x * 2 * kMaxRhs + 2 * t + 1] = b;
