@@ -1664,16 +1664,36 @@ __global__ void __launch_bounds__(256) k_edges_to_int(int64_t nint, const int32_
   __shared__ double tile[64][kMaxRhs + 1];
   const int64_t d0 = (int64_t)blockIdx.x * 64;
   const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * nrhs; e += 256) {
+  // all of a thread's loads (up to 64 kMaxRhs / 256) in flight before the
+  // LDS stores
+  constexpr int K = 64 * kMaxRhs / 256;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = tid + 256 * k;
     const int r = e / 64, dl = e % 64;
     const int64_t d = d0 + dl;
-    if (d < nint) tile[dl][r] = scale * src[(int64_t)r * ne + interior[d]];
+    v[k] = e < 64 * nrhs && d < nint ? scale * src[(int64_t)r * ne + interior[d]] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = tid + 256 * k;
+    if (e < 64 * nrhs) tile[e % 64][e / 64] = v[k];
   }
   __syncthreads();
-  for (int e = tid; e < 64 * nrhs; e += 256) {
-    const int dl = e / nrhs, r = e % nrhs;
-    const int64_t d = d0 + dl;
-    if (d < nint) dst[d * nrhs + r] = tile[dl][r];
+  if (nrhs % 2 == 0) {
+    // pairs of right-hand sides in 16-byte stores
+    for (int e = tid; e < 32 * nrhs; e += 256) {
+      const int dl = 2 * e / nrhs, r = 2 * e % nrhs;
+      const int64_t d = d0 + dl;
+      if (d < nint) *reinterpret_cast<double2*>(dst + d * nrhs + r) = make_double2(tile[dl][r], tile[dl][r + 1]);
+    }
+  } else {
+    for (int e = tid; e < 64 * nrhs; e += 256) {
+      const int dl = e / nrhs, r = e % nrhs;
+      const int64_t d = d0 + dl;
+      if (d < nint) dst[d * nrhs + r] = tile[dl][r];
+    }
   }
 }
 
@@ -1683,12 +1703,27 @@ __global__ void __launch_bounds__(256) k_int_to_edges(int64_t ne, const int32_t*
   __shared__ double tile[64][kMaxRhs + 1];
   const int64_t e0 = (int64_t)blockIdx.x * 64;
   const int tid = threadIdx.x;
-  for (int k = tid; k < 64 * nrhs; k += 256) {
-    const int el = k / nrhs, r = k % nrhs;
-    const int64_t e = e0 + el;
-    if (e < ne) {
-      const int32_t d = dof[e];
-      tile[el][r] = d >= 0 ? scale * src[(int64_t)d * nrhs + r] : 0.0;
+  if (nrhs % 2 == 0) {
+    // pairs of right-hand sides in 16-byte loads
+    for (int k = tid; k < 32 * nrhs; k += 256) {
+      const int el = 2 * k / nrhs, r = 2 * k % nrhs;
+      const int64_t e = e0 + el;
+      if (e < ne) {
+        const int32_t d = dof[e];
+        double2 x = make_double2(0.0, 0.0);
+        if (d >= 0) x = *reinterpret_cast<const double2*>(src + (int64_t)d * nrhs + r);
+        tile[el][r] = d >= 0 ? scale * x.x : 0.0;
+        tile[el][r + 1] = d >= 0 ? scale * x.y : 0.0;
+      }
+    }
+  } else {
+    for (int k = tid; k < 64 * nrhs; k += 256) {
+      const int el = k / nrhs, r = k % nrhs;
+      const int64_t e = e0 + el;
+      if (e < ne) {
+        const int32_t d = dof[e];
+        tile[el][r] = d >= 0 ? scale * src[(int64_t)d * nrhs + r] : 0.0;
+      }
     }
   }
   __syncthreads();
