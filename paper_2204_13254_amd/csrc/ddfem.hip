@@ -1615,6 +1615,38 @@ static void lambda_gather(Ctx& C, int64_t n, const int32_t* lam, const double* p
     hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.d_grow, lam, p, v, nr, skip);
 }
 
+// coarse rows of y = (add) + sum over each corner's subdomain rows of x
+template <class T>
+static void coarse_gather(Ctx& C, hipStream_t st, const T* x, T* y, const T* add, const int* skip) {
+  const int nr = C.nrhs, V = vec_width(nr);
+  const int64_t n = (int64_t)C.Kc * NB;
+  if (V == 4)
+    hipLaunchKernelGGL((k_coarse_gather_v<T, 4>), dim3(nblk(n * nr / 4)), dim3(256), 0, st, n, C.coarse_row0,
+                       C.d_cgptr, C.d_cgrows, x, y, add, nr, skip);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_coarse_gather_v<T, 2>), dim3(nblk(n * nr / 2)), dim3(256), 0, st, n, C.coarse_row0,
+                       C.d_cgptr, C.d_cgrows, x, y, add, nr, skip);
+  else
+    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.coarse_row0, C.d_cgptr,
+                       C.d_cgrows, x, y, add, nr, skip);
+}
+
+// subdomain corner rows of x = scale * their coarse rows of z
+template <class T>
+static void corner_scatter(Ctx& C, hipStream_t st, const T* z, T* x, T scale, const int* skip) {
+  const int nr = C.nrhs, V = vec_width(nr);
+  const int64_t n = C.n_csc;
+  if (V == 4)
+    hipLaunchKernelGGL((k_corner_scatter_v<T, 4>), dim3(nblk(n * nr / 4)), dim3(256), 0, st, n, C.d_cscrows,
+                       C.d_csccrow, z, x, scale, nr, skip);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_corner_scatter_v<T, 2>), dim3(nblk(n * nr / 2)), dim3(256), 0, st, n, C.d_cscrows,
+                       C.d_csccrow, z, x, scale, nr, skip);
+  else
+    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.d_cscrows, C.d_csccrow, z,
+                       x, scale, nr, skip);
+}
+
 // Fp = sum_s B_s (u + u2) with the partials of p . Fp (p may be null)
 template <class T>
 static void scatter_dot(Ctx& C, const T* u, const T* u2, double* Fp, const double* p, const int* skip) {
@@ -1699,12 +1731,9 @@ static void apply_local(Ctx& C, const int* skip) {
   symv<T>(C, X[5], X[8], skip, overlap);
   if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, (T)1, skip);
   if (C.Kc > 0) {
-    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
-                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[6], (T*)X[6],
-                       (const T*)nullptr, nr, skip);
+    coarse_gather<T>(C, st, (const T*)X[6], (T*)X[6], nullptr, skip);
     coarse_solve<T>(C, X[6], X[7], X[5], skip);
-    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[6], (T)1, nr, skip);
+    corner_scatter<T>(C, st, (const T*)X[5], (T*)X[6], (T)1, skip);
   }
   // Psi_G^T z goes to its own buffer (rows of subdomains without corners
   // stay zero from setup), so it does not wait for M v; consumers add X9
@@ -1925,8 +1954,7 @@ static void transposed_r(Ctx& C, const int* gate) {
   const int nr = C.nrhs;
   mv<T>(C, C.trail_T, true, X[1], X[5], nullptr, one, gate);
   if (C.Kc > 0)
-    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, C.st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[5], one, nr, gate);
+    corner_scatter<T>(C, C.st, (const T*)X[5], (T*)X[5], one, gate);
   mv<T>(C, C.cross_T, true, X[5], X[2], X[1], mone, gate);
   mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one, gate);
 }
@@ -1986,12 +2014,9 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   forward_r<T>(C, gate);
   if (C.Kc > 0) {
     // f_c = sum B_c^T g (coarse rows of X1, kept for the recovery); z0 = K_cc^-1 f_c
-    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
-                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)X[1], (T*)X[1],
-                       (const T*)nullptr, nr, gate);
+    coarse_gather<T>(C, st, (const T*)X[1], (T*)X[1], nullptr, gate);
     coarse_solve<T>(C, X[1], X[2], X[3], gate);
-    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[3], (T*)X[1], mone, nr, gate);
+    corner_scatter<T>(C, st, (const T*)X[3], (T*)X[1], mone, gate);
   }
   // d-contribution: Linv_GG^T t_G - Psi_G^T z0
   mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one, gate);
@@ -2157,9 +2182,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     // x_c = K_cc^-1 (f_c + sum B_c^T y)  (coarse rows of X5; y on the corner
     // rows of X1, written by the interface recovery pass, or of X6 = 0)
     const void* ysrc = C.nlam > 0 ? X[1] : X[6];
-    hipLaunchKernelGGL(k_coarse_gather<T>, dim3(nblk((int64_t)C.Kc * NB * nr)), dim3(256), 0, st,
-                       (int64_t)C.Kc * NB, C.coarse_row0, C.d_cgptr, C.d_cgrows, (const T*)ysrc, (T*)X[6],
-                       (const T*)X[1], nr, gate);
+    coarse_gather<T>(C, st, (const T*)ysrc, (T*)X[6], (const T*)X[1], gate);
     coarse_solve<T>(C, X[6], X[7], X[5], gate);
   }
   // x_r = L_rr^-T (t' - L_cr^T x_c), t' = t - [0; t_l] (the r rows of X1):
@@ -2167,8 +2190,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   //   v_I = t_I - L_GI^T x_G - L_cI^T x_c                (X2, I rows; X5's corner rows get x_c)
   //   x_I = L_II^-T v_I                                  (X5, I rows)
   if (C.Kc > 0)
-    hipLaunchKernelGGL(k_corner_scatter<T>, dim3(nblk(C.n_csc * nr)), dim3(256), 0, st, C.n_csc, C.d_cscrows,
-                       C.d_csccrow, (const T*)X[5], (T*)X[1], mone, nr, gate);
+    corner_scatter<T>(C, st, (const T*)X[5], (T*)X[1], mone, gate);
   transposed_r<T>(C, gate);
   if (vec_width(nr) == 4)
     hipLaunchKernelGGL((k_collect_v<T, 4>), dim3(nblk(C.P.nint * nr / 4)), dim3(256), 0, st, (int64_t)C.P.nint,

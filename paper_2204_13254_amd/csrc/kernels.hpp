@@ -1573,6 +1573,63 @@ __global__ void k_corner_scatter(int64_t n, const int64_t* __restrict__ rows, co
   x[rows[k] * nrhs + r] = c >= 0 ? scale * z[c * nrhs + r] : (T)0;
 }
 
+// Vector forms of k_coarse_gather and k_corner_scatter: one thread per
+// (row, group of V right-hand sides); the same sums in the same order.
+template <class T, int V>
+__global__ void k_coarse_gather_v(int64_t ncrows, int64_t crow0, const int64_t* __restrict__ ptr,
+                                  const int64_t* __restrict__ rows, const T* __restrict__ x, T* __restrict__ y,
+                                  const T* __restrict__ add, int nrhs, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncrows * G) return;
+  const int64_t c = i / G;
+  const int q = (int)(i - c * G);
+  double s[V];
+#pragma unroll
+  for (int w = 0; w < V; ++w) s[w] = 0.0;
+  for (int64_t k = ptr[c]; k < ptr[c + 1]; ++k) {
+    T a[V];
+    vload<T, V>(x + rows[k] * nrhs + q * V, a);
+#pragma unroll
+    for (int w = 0; w < V; ++w) s[w] += (double)a[w];
+  }
+  const int64_t o = (crow0 + c) * nrhs + q * V;
+  T out[V];
+  if (add) {
+    T a[V];
+    vload<T, V>(add + o, a);
+#pragma unroll
+    for (int w = 0; w < V; ++w) s[w] += (double)a[w];
+  }
+#pragma unroll
+  for (int w = 0; w < V; ++w) out[w] = (T)s[w];
+  vstore<T, V>(y + o, out);
+}
+
+template <class T, int V>
+__global__ void k_corner_scatter_v(int64_t n, const int64_t* __restrict__ rows, const int64_t* __restrict__ crow,
+                                   const T* __restrict__ z, T* __restrict__ x, T scale, int nrhs,
+                                   const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * G) return;
+  const int64_t k = i / G;
+  const int q = (int)(i - k * G);
+  const int64_t c = crow[k];
+  T a[V];
+  if (c >= 0) {
+    vload<T, V>(z + c * nrhs + q * V, a);
+#pragma unroll
+    for (int w = 0; w < V; ++w) a[w] = scale * a[w];
+  } else {
+#pragma unroll
+    for (int w = 0; w < V; ++w) a[w] = (T)0;
+  }
+  vstore<T, V>(x + rows[k] * nrhs + q * V, a);
+}
+
 // Vector forms of k_split, k_lambda_gather and k_collect: one thread per
 // (row, group of V right-hand sides).
 template <class T, int V>
