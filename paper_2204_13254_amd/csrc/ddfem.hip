@@ -1600,19 +1600,22 @@ static void dot_partial(Ctx& C, hipStream_t st, int64_t n, const double* x, cons
     hipLaunchKernelGGL(k_dot_partial, dim3(kDotBlocks), dim3(256), 0, st, n, x, y, nr, partial, skip);
 }
 
-// v[rows[k]] = sign * p[lam[k]] (B_s^T p on the listed interface rows)
+// v[rows[k]] = sign * p[lam[k]] (B_s^T p on the listed interface rows); with
+// add: v = add - sign * p
 template <class T>
-static void lambda_gather(Ctx& C, int64_t n, const int32_t* lam, const double* p, T* v, const int* skip) {
+static void lambda_gather(Ctx& C, int64_t n, const int32_t* lam, const double* p, T* v, const int* skip,
+                          const T* add = nullptr) {
   const int nr = C.nrhs, V = vec_width(nr);
   hipStream_t st = C.st;
   if (V == 4)
     hipLaunchKernelGGL((k_lambda_gather_v<T, 4>), dim3(nblk(n * nr / 4)), dim3(256), 0, st, n, C.d_grow, lam, p, v,
-                       nr, skip);
+                       nr, skip, add);
   else if (V == 2)
     hipLaunchKernelGGL((k_lambda_gather_v<T, 2>), dim3(nblk(n * nr / 2)), dim3(256), 0, st, n, C.d_grow, lam, p, v,
-                       nr, skip);
+                       nr, skip, add);
   else
-    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.d_grow, lam, p, v, nr, skip);
+    hipLaunchKernelGGL(k_lambda_gather<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.d_grow, lam, p, v, nr, skip,
+                       add);
 }
 
 // coarse rows of y = (add) + sum over each corner's subdomain rows of x
@@ -1672,13 +1675,13 @@ static void join_side(Ctx& C) {
   HIPCHK(hipStreamWaitEvent(C.st, C.ev_join, 0));
 }
 
-// out (interface rows) = M in: the symmetric product and its reduce
+// The symmetric product M in into the partial slots (the per-class event
+// timing of DD_PROF_SCHUR covers this kernel alone), and the reduce of the
+// slots: out (interface rows) = add + M in.
 template <class T>
-static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side) {
-  if (C.sym.n == 0) return;
+static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s) {
   hipEvent_t e0, e1;
   bool timed = prof_begin(C, DD_PROF_SCHUR, &e0, &e1);
-  hipStream_t s = side ? C.st2 : C.st;
   int64_t ng = (C.sym.n + 3) / 4;
   if (C.tuning.sym_persist > 0) ng = std::min<int64_t>(ng, C.tuning.sym_persist);
   const dim3 grid((unsigned)ng);
@@ -1697,10 +1700,23 @@ static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side) 
       DD_SYMV(2, 2);
   }
 #undef DD_SYMV
-  hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)C.sym.n_out), dim3(256), 0, s, C.sym.n_out, C.sym.outs,
-                     C.d_subs, (const T*)C.sym.partial, (T*)out, (const T*)nullptr, (T)1, (const T*)nullptr, (T)1,
-                     C.nrhs, skip);
   if (timed) HIPCHK(hipEventRecord(e1, C.st));
+}
+
+template <class T>
+static void symv_reduce(Ctx& C, void* out, const void* add, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(k_mv_reduce<T>, dim3((unsigned)C.sym.n_out), dim3(256), 0, s, C.sym.n_out, C.sym.outs,
+                     C.d_subs, (const T*)C.sym.partial, (T*)out, (const T*)add, (T)1, (const T*)nullptr, (T)1,
+                     C.nrhs, skip);
+}
+
+// out (interface rows) = M in
+template <class T>
+static void symv(Ctx& C, const void* in, void* out, const int* skip, bool side) {
+  if (C.sym.n == 0) return;
+  hipStream_t s = side ? C.st2 : C.st;
+  symv_product<T>(C, in, skip, s);
+  symv_reduce<T>(C, out, nullptr, skip, s);
 }
 
 // coarse: y rows of Xin (coarse block) -> Xout coarse rows = K_cc^-1 y via
@@ -1739,6 +1755,36 @@ static void apply_local(Ctx& C, const int* skip) {
   // stay zero from setup), so it does not wait for M v; consumers add X9
   if (C.Kc > 0) mv<T>(C, C.corner_T, true, X[6], X[9], nullptr, (T)1, skip);
   if (overlap) join_side(C);
+}
+
+// The interface and corner part of a local solve (pre-solve and recovery),
+// from u on the interface rows of `u` and the corner loads g' on the corner
+// rows of `gp`:
+//   x_c = K_cc^-1 sum_s B_c^T (g' - Psi_G u)       (coarse rows of xc)
+//   out = M u - Psi_G^T x_c                          (interface rows of out)
+// With L_rr^-1 split by the column blocks of the factor, this is the
+// interface and corner part of K_rr^-1 applied to the subdomain loads after
+// the interior elimination: M u = L_GG^-T L_GG^-1 u, and Psi_G = L_cG L_GG^-1
+// carries the corner coupling.  M u runs on the side stream beside the
+// corner chain (X6, X7, X9), as in apply_local; out may be u (the product
+// has read u before the reduce writes out).
+template <class T>
+static void interface_local(Ctx& C, void* u, const void* gp, void* out, void* xc, const int* skip) {
+  void** X = C.X;
+  const bool overlap = C.Kc > 0 && C.sym.n > 0 && !C.prof;
+  if (overlap) fork_side(C);
+  if (C.sym.n > 0) symv_product<T>(C, u, skip, overlap ? C.st2 : C.st);
+  if (C.Kc > 0) {
+    // corner rows of X6: g' - Psi_G u; their coarse sum; x_c = K_cc^-1 (.)
+    mv<T>(C, C.corner_N, false, u, X[6], nullptr, (T)1, skip, gp, (T)-1);
+    coarse_gather<T>(C, C.st, (const T*)X[6], (T*)X[6], nullptr, skip);
+    coarse_solve<T>(C, X[6], X[7], xc, skip);
+    // -x_c on the corner rows of X6; X9 = -Psi_G^T x_c
+    corner_scatter<T>(C, C.st, (const T*)xc, (T*)X[6], (T)-1, skip);
+    mv<T>(C, C.corner_T, true, X[6], X[9], nullptr, (T)1, skip);
+  }
+  if (overlap) join_side(C);
+  if (C.sym.n > 0) symv_reduce<T>(C, out, C.Kc > 0 ? X[9] : nullptr, skip, C.st);
 }
 
 // the second part of the local response (X9) when there is one
@@ -1933,32 +1979,6 @@ static void dot_to_host(Ctx& C, const double* x, const double* y, int64_t n, dou
   }
 }
 
-// The r-block substitutions of a DD solve through the factor store's column
-// blocks (L_rr^-1 = [L_II^-1, 0; -L_GG^-1 L_GI L_II^-1, L_GG^-1]):
-// forward_r: X0 (w, corner rows w_c) -> X1 = [L_rr^-1 w_r; w_c - L_cr L_rr^-1
-// w_r] with X2 as scratch; transposed_r: X1 = [t'; -x_c] with x_c in X5's
-// coarse rows -> X5 r rows = L_rr^-T (t' - L_cr^T x_c), X2 as scratch.
-template <class T>
-static void forward_r(Ctx& C, const int* gate) {
-  void** X = C.X;
-  const T one = 1, mone = -1;
-  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, gate);
-  mv<T>(C, C.cross_N, false, X[1], X[2], X[0], mone, gate, X[0], mone);
-  mv<T>(C, C.trail_N, false, X[2], X[1], nullptr, one, gate, X[2], mone);
-}
-
-template <class T>
-static void transposed_r(Ctx& C, const int* gate) {
-  void** X = C.X;
-  const T one = 1, mone = -1;
-  const int nr = C.nrhs;
-  mv<T>(C, C.trail_T, true, X[1], X[5], nullptr, one, gate);
-  if (C.Kc > 0)
-    corner_scatter<T>(C, C.st, (const T*)X[5], (T*)X[5], one, gate);
-  mv<T>(C, C.cross_T, true, X[5], X[2], X[1], mone, gate);
-  mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one, gate);
-}
-
 // z = K_lam r (the lumped preconditioner) with the r.z and r.r partials.
 // Vector form for even nrhs: at 16 RHS, four per lane, one row in flight,
 // nonzeros in batches of 4 (16.60 -> 16.17 ms/step at 64^3 with 16 RHS;
@@ -2005,21 +2025,17 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
   else
     hipLaunchKernelGGL(k_split<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total, C.d_rowsrc, b,
                        (T*)X[0], nr, gate);
-  // r rows: t = L_rr^-1 w_r;  corner rows: g = w_c - L_cr t, as three products
-  // over the column blocks of the factor store:
+  // Through the column blocks of the factor store (L_rr^-1 = [L_II^-1, 0;
+  // -L_GG^-1 L_GI L_II^-1, L_GG^-1]):
   //   t_I = L_II^-1 w_I                                  (X1, I rows)
   //   y_G = w_G - L_GI t_I,  g' = w_c - L_cI t_I        (X2, Gamma and corner rows)
-  //   t_G = L_GG^-1 y_G,     g = g' - Psi_G y_G          (X1, Gamma and corner rows)
-  // (L_cG t_G = L_cG L_GG^-1 y_G = Psi_G y_G)
-  forward_r<T>(C, gate);
-  if (C.Kc > 0) {
-    // f_c = sum B_c^T g (coarse rows of X1, kept for the recovery); z0 = K_cc^-1 f_c
-    coarse_gather<T>(C, st, (const T*)X[1], (T*)X[1], nullptr, gate);
-    coarse_solve<T>(C, X[1], X[2], X[3], gate);
-    corner_scatter<T>(C, st, (const T*)X[3], (T*)X[1], mone, gate);
-  }
-  // d-contribution: Linv_GG^T t_G - Psi_G^T z0
-  mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one, gate);
+  // both kept for the recovery; then the interface part with M = L_GG^-T
+  // L_GG^-1 and Psi_G = L_cG L_GG^-1:
+  //   z0 = K_cc^-1 sum B_c^T (g' - Psi_G y_G),  X4 = M y_G - Psi_G^T z0
+  // (the d-contribution of every subdomain)
+  mv<T>(C, C.full_N, false, X[0], X[1], nullptr, one, gate);
+  mv<T>(C, C.cross_N, false, X[1], X[2], X[0], mone, gate, X[0], mone);
+  interface_local<T>(C, X[2], X[2], X[4], X[3], gate);
   for (int r = 0; r < nr; ++r) {
     iters[r] = 0;
     relres[r] = 0.0;
@@ -2029,8 +2045,7 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
     // ---- Robin variant: GMRES on the per-side multipliers, then the same
     // recovery with each subdomain's own multipliers as interface loads
     status = dp2_gmres<T>(C, iters, relres);
-    lambda_gather<T>(C, C.n_grow, C.d_code2, (const double*)C.d_lam2, (T*)X[5], nullptr);
-    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
+    lambda_gather<T>(C, C.n_grow, C.d_code2, (const double*)C.d_lam2, (T*)X[5], nullptr, (const T*)X[2]);
   } else if (C.nlam > 0) {
     const int64_t nl = C.nlam * nr;
     scatter_dot<T>(C, (const T*)X[4], (const T*)nullptr, C.d_d, (const double*)nullptr, gate);
@@ -2167,31 +2182,19 @@ static int dd_solve_once(Ctx& C, const double* b, double* x, Ctx::Warm* warm, in
       warm->have = std::min(2, warm->have + 1);
     }
     // ---- recovery -------------------------------------------------------------------
-    // v_l = B_s^T lambda; interface rows of X1: t - t_l = t - Linv_GG v_l (in
-    // place); its corner rows: y = Psi_G v_l (the same pass)
-    lambda_gather<T>(C, C.n_grow, C.d_glam, (const double*)C.d_lam, (T*)X[5], gate);
-    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone, gate);
-  } else {
-    // no interface: t_l = 0, y = 0 (X6, whose corner rows the coarse gather reads)
-    hipLaunchKernelGGL(k_zero<T>, dim3(nblk(C.rows_total * nr)), dim3(256), 0, st, C.rows_total * nr, (T*)X[6],
-                       gate);
-    if (captured)
-      hipLaunchKernelGGL(k_cg_snapshot, dim3(1), dim3(64), 0, st, slot, nr, (const CgState*)C.d_cg, C.d_rs, gate);
+    // u = y_G - B_s^T lambda on the interface rows of X5
+    lambda_gather<T>(C, C.n_grow, C.d_glam, (const double*)C.d_lam, (T*)X[5], gate, (const T*)X[2]);
+  } else if (captured) {
+    hipLaunchKernelGGL(k_cg_snapshot, dim3(1), dim3(64), 0, st, slot, nr, (const CgState*)C.d_cg, C.d_rs, gate);
   }
-  if (C.Kc > 0) {
-    // x_c = K_cc^-1 (f_c + sum B_c^T y)  (coarse rows of X5; y on the corner
-    // rows of X1, written by the interface recovery pass, or of X6 = 0)
-    const void* ysrc = C.nlam > 0 ? X[1] : X[6];
-    coarse_gather<T>(C, st, (const T*)ysrc, (T*)X[6], (const T*)X[1], gate);
-    coarse_solve<T>(C, X[6], X[7], X[5], gate);
-  }
-  // x_r = L_rr^-T (t' - L_cr^T x_c), t' = t - [0; t_l] (the r rows of X1):
-  //   x_G = L_GG^-T t'_G - Psi_G^T x_c                   (X5, Gamma rows; X1's corner rows get -x_c)
-  //   v_I = t_I - L_GI^T x_G - L_cI^T x_c                (X2, I rows; X5's corner rows get x_c)
-  //   x_I = L_II^-T v_I                                  (X5, I rows)
-  if (C.Kc > 0)
-    corner_scatter<T>(C, st, (const T*)X[5], (T*)X[1], mone, gate);
-  transposed_r<T>(C, gate);
+  // x_c = K_cc^-1 sum B_c^T (g' - Psi_G u) (coarse rows of X5, where the
+  // collect reads corner unknowns), x_G = M u - Psi_G^T x_c (interface rows
+  // of X5); u = y_G without multipliers
+  interface_local<T>(C, C.nlam > 0 ? X[5] : X[2], X[2], X[5], X[5], gate);
+  // x_c on the corner rows of X5; x_I = L_II^-T (t_I - L_GI^T x_G - L_cI^T x_c)
+  if (C.Kc > 0) corner_scatter<T>(C, st, (const T*)X[5], (T*)X[5], one, gate);
+  mv<T>(C, C.cross_T, true, X[5], X[2], X[1], mone, gate);
+  mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one, gate);
   if (vec_width(nr) == 4)
     hipLaunchKernelGGL((k_collect_v<T, 4>), dim3(nblk(C.P.nint * nr / 4)), dim3(256), 0, st, (int64_t)C.P.nint,
                        C.d_dsrc, (const T*)X[5], x, nr, gate);
@@ -2859,8 +2862,6 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
   };
   auto coarse = [&] { coarse_solve<T>(C, X[6], X[7], X[5], nullptr); };
   auto trailing = [&] {
-    mv<T>(C, C.trail_T, true, X[1], X[4], nullptr, one);
-    mv<T>(C, C.trail_N, false, X[5], X[1], X[1], mone);
     mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
     mv<T>(C, C.corner_T, true, X[6], X[8], nullptr, one);
   };

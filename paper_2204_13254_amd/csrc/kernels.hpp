@@ -1513,10 +1513,12 @@ __global__ void k_split(int64_t rows, const int32_t* __restrict__ src, const dou
 
 // v[row] = sign(row) * p[lam(row)] on listed rows (interface rows of every
 // subdomain, padding rows included with lam = -1 -> 0): B_s^T p.
+// With add: v[row] = add[row] - sign(row) * p[lam(row)] (the interface load
+// left after the multipliers, y_G - B_s^T lambda).
 template <class T>
 __global__ void k_lambda_gather(int64_t n, const int64_t* __restrict__ rows, const int32_t* __restrict__ lam,
                                 const double* __restrict__ p, T* __restrict__ v, int nrhs,
-                                const int* __restrict__ skip) {
+                                const int* __restrict__ skip, const T* __restrict__ add) {
   if (skip && *skip) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * nrhs) return;
@@ -1525,7 +1527,8 @@ __global__ void k_lambda_gather(int64_t n, const int64_t* __restrict__ rows, con
   int32_t l = lam[k];
   double x = 0.0;
   if (l >= 0) x = (double)(l & 1 ? -1 : 1) * p[(int64_t)(l >> 1) * nrhs + r];
-  v[rows[k] * nrhs + r] = (T)x;
+  const int64_t o = rows[k] * nrhs + r;
+  v[o] = add ? (T)(add[o] - (T)x) : (T)x;
 }
 
 // F p = sum_s B_s u_s: each multiplier pulls its two copies (+lo, -hi).
@@ -1658,7 +1661,7 @@ __global__ void k_split_v(int64_t rows, const int32_t* __restrict__ src, const d
 template <class T, int V>
 __global__ void k_lambda_gather_v(int64_t n, const int64_t* __restrict__ rows, const int32_t* __restrict__ lam,
                                   const double* __restrict__ p, T* __restrict__ v, int nrhs,
-                                  const int* __restrict__ skip) {
+                                  const int* __restrict__ skip, const T* __restrict__ add) {
   if (skip && *skip) return;
   const int G = nrhs / V;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1675,9 +1678,16 @@ __global__ void k_lambda_gather_v(int64_t n, const int64_t* __restrict__ rows, c
     for (int u = 0; u < V; ++u) x[u] = 0.0;
   }
   const double sg = l >= 0 && (l & 1) ? -1.0 : 1.0;
+  const int64_t o = rows[k] * nrhs + q * V;
 #pragma unroll
   for (int u = 0; u < V; ++u) y[u] = (T)(sg * x[u]);
-  vstore<T, V>(v + rows[k] * nrhs + q * V, y);
+  if (add) {
+    T a[V];
+    vload<T, V>(add + o, a);
+#pragma unroll
+    for (int u = 0; u < V; ++u) y[u] = (T)(a[u] - y[u]);
+  }
+  vstore<T, V>(v + o, y);
 }
 
 template <class T, int V>
