@@ -108,7 +108,9 @@ typedef struct {
   int full_quarter;   /* full passes: 1 = the lanes of all-zero 16 x 16 quarters of a tile
                          read a cached zero tile instead of memory */
   int from_cache;     /* 1: read from the cache, no timing */
-  double full_ms, full_ms_default, coarse_ms, coarse_ms_default, trailing_ms, trailing_ms_default;
+  double full_ms, full_ms_default, coarse_ms, coarse_ms_default;
+  double trailing_ms, trailing_ms_default;  /* the corner-coupling passes Psi_Gamma u and
+                                               Psi_Gamma^T z (tuned by `chunk`) */
   int sym_persist;    /* symmetric product of the interface operator: workgroups of a persistent
                          grid (a multiple of 8), or 0 for one workgroup per four work items; a
                          smaller grid leaves wave slots to the corner and coarse chain that runs
@@ -414,11 +416,15 @@ int dd_step_mixed(void* ctx, const double* J_half, const double* E_n, const doub
  * recorded on the context's stream around each launch (adds two event
  * records per launch while enabled).  Classes: */
 enum {
-  DD_PROF_TRAILING = 0, /* interface-block inverse-factor products (pre-solve, recovery) */
+  DD_PROF_TRAILING = 0, /* no launches (kept for the numbering): no pass applies the interface
+                           blocks of the inverse factors alone; the solves use M below */
   DD_PROF_FULL = 1,     /* interior inverse-factor products L_II^-1, L_II^-T (pre-solve, recovery) */
-  DD_PROF_SCHUR = 2,    /* interface blocks of the local inverses, M u (once per CG iteration) */
+  DD_PROF_SCHUR = 2,    /* interface blocks of the local inverses, M u: the symmetric product
+                           kernel alone, without the reduce of its partials (once per CG
+                           iteration, once in the pre-solve and in the recovery) */
   DD_PROF_COARSE = 3,   /* coarse corner inverse factor */
-  DD_PROF_CORNER = 4,   /* corner rows Psi_Gamma u and Psi_Gamma^T z (twice per CG iteration) */
+  DD_PROF_CORNER = 4,   /* corner rows Psi_Gamma u and Psi_Gamma^T z (twice per CG iteration,
+                           pre-solve and recovery) */
   DD_PROF_CROSS = 5,    /* couplings L_GammaI, L_cI of interface and corner rows to the interior
                            (pre-solve, recovery) */
   DD_PROF_CLASSES = 6

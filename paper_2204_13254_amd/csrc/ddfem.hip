@@ -166,7 +166,7 @@ struct Ctx {
   bool tune_applied = false;  // dd_factor has run the tuner (or read its cache) once
   // output blocks of every product class (host), kept so that the work lists
   // can be rebuilt with other chunk lengths
-  std::vector<MvItem> blk_trail_N, blk_trail_T, blk_corner_N, blk_corner_T, blk_co_N, blk_co_T, blk_full_N,
+  std::vector<MvItem> blk_corner_N, blk_corner_T, blk_co_N, blk_co_T, blk_full_N,
       blk_full_T, blk_cross_N, blk_cross_T;
   // per-row tile lists (host) of the I x I passes (L_II^-1) and of the
   // [Gamma; c] x I passes (L_GI, L_cI)
@@ -266,12 +266,11 @@ struct Ctx {
   double* d_gpart = nullptr;  // their workgroup shares [kGaussBlocks][2 kMaxRhs]
   int32_t* d_vdof = nullptr; // vertex -> unknowns (d << 1 | tail), the lists of d_vedge
   // work lists
-  // full_*: r-block inverse factor with the premultiplied corner rows Psi_r;
-  // trail_N: interface rows of Linv_GG (recovery); trail_T: Linv_GG^T with
-  // Psi_Gamma^T (pre-solve); co_*: coarse inverse factor
-  // corner_N / corner_T: Psi_Gamma u on the corner rows / Psi_Gamma^T z
-  // onto the interface rows
-  Items full_N, full_T, cross_N, cross_T, trail_N, trail_T, co_N, co_T, corner_N, corner_T;
+  // full_*: interior inverse factor L_II^-1; cross_*: the couplings L_GI,
+  // L_cI of the interface and corner rows to the interior; co_*: coarse
+  // inverse factor; corner_N / corner_T: Psi_Gamma u on the corner rows /
+  // Psi_Gamma^T z onto the interface rows
+  Items full_N, full_T, cross_N, cross_T, co_N, co_T, corner_N, corner_T;
   // symmetric product M u (panel pairs, partial slots, fixed-order reduce)
   struct SymList {
     SymItem* d = nullptr;
@@ -933,30 +932,22 @@ static void build_device(Ctx& C, const double* coords) {
   }
   // ---- work lists --------------------------------------------------------------------
   {
-    // forward passes also produce the corner rows (Psi times the input),
-    // transposed passes run over [o, K) so they include Psi^T (corner inputs)
-    // (the full r-block lists are built from the nonzero tiles after the
-    // first factorisation)
-    std::vector<MvItem> tN, tT, oN, oT, cN, cT;
+    // corner rows Psi_Gamma u over the interface columns, and Psi_Gamma^T z
+    // onto the interface rows of subdomains with corners; coarse inverse
+    // factor rows (the r-block lists are built from the nonzero tiles after
+    // the first factorisation)
+    std::vector<MvItem> oN, oT, cN, cT;
     for (int s = 0; s < nsub; ++s) {
       const SubDev& q = C.subs_h[s];
-      int kr = q.kI + q.kG;
-      for (int o = kr; o < q.K; ++o) {
-        tN.push_back({s, o, q.kI, kr, -1, 0});
-        cN.push_back({s, o, q.kI, kr, -1, 0});
-      }
-      for (int o = q.kI; o < kr; ++o) {
-        tN.push_back({s, o, q.kI, o + 1, -1, 0});  // interface rows only (corner rows: cN)
-        tT.push_back({s, o, o, q.K, -1, 0});
-        if (q.kC > 0) cT.push_back({s, o, kr, q.K, -1, 0});
-      }
+      const int kr = q.kI + q.kG;
+      for (int o = kr; o < q.K; ++o) cN.push_back({s, o, q.kI, kr, -1, 0});
+      if (q.kC > 0)
+        for (int o = q.kI; o < kr; ++o) cT.push_back({s, o, kr, q.K, -1, 0});
     }
     for (int o = 0; o < C.Kc; ++o) {
       oN.push_back({nsub, o, 0, o + 1, -1, 0});
       oT.push_back({nsub, o, o, C.Kc, -1, 0});
     }
-    C.trail_N = make_items(C, tN, C.tuning.chunk);
-    C.trail_T = make_items(C, tT, C.tuning.chunk);
     // runs beside the coarse chain: own partial slots
     make_sym_list(C, sym_width(C), wsz);
     C.corner_N = make_items(C, cN, C.tuning.chunk);
@@ -965,8 +956,6 @@ static void build_device(Ctx& C, const double* coords) {
     C.corner_T = make_items(C, cT, C.tuning.chunk);
     C.co_N = make_items(C, oN, C.tuning.chunk);
     C.co_T = make_items(C, oT, C.tuning.chunk);
-    C.blk_trail_N.swap(tN);
-    C.blk_trail_T.swap(tT);
     C.blk_corner_N.swap(cN);
     C.blk_corner_T.swap(cT);
     void* p = nullptr;
@@ -1495,7 +1484,6 @@ static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
 }
 
 static int item_class(const Ctx& C, const Items& it) {
-  if (&it == &C.trail_N || &it == &C.trail_T) return DD_PROF_TRAILING;
   if (&it == &C.corner_N || &it == &C.corner_T) return DD_PROF_CORNER;
   if (&it == &C.full_N || &it == &C.full_T) return DD_PROF_FULL;
   if (&it == &C.cross_N || &it == &C.cross_T) return DD_PROF_CROSS;
@@ -2722,8 +2710,6 @@ static void rebuild_lists(Ctx& C, int which) {
   HIPCHK(hipStreamSynchronize(C.st));
   drop_graphs(C);
   if (which & 1) {
-    remake(C.trail_N, C.blk_trail_N, C.tuning.chunk, false, 1);
-    remake(C.trail_T, C.blk_trail_T, C.tuning.chunk, false, 1);
     remake(C.corner_N, C.blk_corner_N, C.tuning.chunk, false, 1);
     remake(C.corner_T, C.blk_corner_T, C.tuning.chunk, false, 1);
   }
@@ -2861,6 +2847,7 @@ static void autotune_impl(Ctx& C, dd_tuning* out) {
     mv<T>(C, C.full_T, true, X[2], X[5], nullptr, one);
   };
   auto coarse = [&] { coarse_solve<T>(C, X[6], X[7], X[5], nullptr); };
+  // (the corner-coupling passes; the result fields keep their names)
   auto trailing = [&] {
     mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, one);
     mv<T>(C, C.corner_T, true, X[6], X[8], nullptr, one);
