@@ -1732,8 +1732,11 @@ static void apply_local(Ctx& C, const int* skip) {
   void **X = C.X;
   const bool overlap = C.Kc > 0 && !C.prof;
   if (overlap) fork_side(C);
-  symv<T>(C, X[5], X[8], skip, overlap);
+  // the corner rows are submitted first, so that the chain on st (the longer
+  // one) gets its workgroups dispatched ahead of the symmetric product's
+  // (graded 48^3: 16.1 -> 15.5 ms/step; 64^3 unchanged)
   if (C.Kc > 0) mv<T>(C, C.corner_N, false, X[5], X[6], nullptr, (T)1, skip);
+  symv<T>(C, X[5], X[8], skip, overlap);
   if (C.Kc > 0) {
     coarse_gather<T>(C, st, (const T*)X[6], (T*)X[6], nullptr, skip);
     coarse_solve<T>(C, X[6], X[7], X[5], skip);
@@ -1761,10 +1764,11 @@ static void interface_local(Ctx& C, void* u, const void* gp, void* out, void* xc
   void** X = C.X;
   const bool overlap = C.Kc > 0 && C.sym.n > 0 && !C.prof;
   if (overlap) fork_side(C);
+  // corner rows first, as in apply_local
+  if (C.Kc > 0) mv<T>(C, C.corner_N, false, u, X[6], nullptr, (T)1, skip, gp, (T)-1);
   if (C.sym.n > 0) symv_product<T>(C, u, skip, overlap ? C.st2 : C.st);
   if (C.Kc > 0) {
-    // corner rows of X6: g' - Psi_G u; their coarse sum; x_c = K_cc^-1 (.)
-    mv<T>(C, C.corner_N, false, u, X[6], nullptr, (T)1, skip, gp, (T)-1);
+    // corner rows of X6: g' - Psi_G u (above); their coarse sum; x_c = K_cc^-1 (.)
     coarse_gather<T>(C, C.st, (const T*)X[6], (T*)X[6], nullptr, skip);
     coarse_solve<T>(C, X[6], X[7], xc, skip);
     // -x_c on the corner rows of X6; X9 = -Psi_G^T x_c
