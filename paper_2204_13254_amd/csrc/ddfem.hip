@@ -1793,6 +1793,23 @@ static void apply_F(Ctx& C, const double* p, double* Fp, const int* skip, bool d
   scatter_dot<T>(C, (const T*)X[8], (const T*)corner_part(C), Fp, dot ? p : (const double*)nullptr, skip);
 }
 
+// y = (lam + lam(partner side)) - R (U + U2) over the n side rows (lam may
+// be null), four or two right-hand sides per thread when nrhs allows
+template <class T>
+static void robin_apply(Ctx& C, int64_t n, const double* lam, const T* U, const T* U2, double* y, const int* skip) {
+  const int nr = C.nrhs, V = vec_width(nr);
+  hipStream_t st = C.st;
+  if (V == 4)
+    hipLaunchKernelGGL((k_robin_apply_v<T, 4>), dim3(nblk(n * nr / 4)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow,
+                       C.d_rval, C.d_partner2, lam, U, U2, y, nr, skip);
+  else if (V == 2)
+    hipLaunchKernelGGL((k_robin_apply_v<T, 2>), dim3(nblk(n * nr / 2)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow,
+                       C.d_rval, C.d_partner2, lam, U, U2, y, nr, skip);
+  else
+    hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(n * nr)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow, C.d_rval,
+                       C.d_partner2, lam, U, U2, y, nr, skip);
+}
+
 // Robin variant: y = G lam = lam + lam(partner side) - R (x_G response of
 // the other side), with the response of every side computed by apply_local;
 // every kernel returns at once while *skip != 0
@@ -1803,8 +1820,7 @@ static void apply_G(Ctx& C, const double* lam, double* y, const int* skip) {
   hipStream_t st = C.st;
   lambda_gather<T>(C, n, C.d_code2, lam, (T*)C.X[5], skip);
   apply_local<T>(C, skip);
-  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow, C.d_rval,
-                     C.d_partner2, lam, (const T*)C.X[8], (const T*)corner_part(C), y, nr, skip);
+  robin_apply<T>(C, n, lam, (const T*)C.X[8], (const T*)corner_part(C), y, skip);
 }
 
 // the two projections of classical Gram-Schmidt (k_gm_project), for nv <= KMAX
@@ -1883,9 +1899,7 @@ static int dp2_gmres(Ctx& C, int* iters, double* relres) {
   const int cap = C.opt.cg_max_iter;
   const int chk = std::max(1, std::min(C.opt.check_every, m));
   const int nblocks = (m + chk - 1) / chk;
-  hipLaunchKernelGGL(k_robin_apply<T>, dim3(nblk(nl)), dim3(256), 0, st, n, C.d_rrp, C.d_rrow, C.d_rval,
-                     C.d_partner2, (const double*)nullptr, (const T*)C.X[4], (const T*)nullptr, C.d_gm_rhs, nr,
-                     (const int*)nullptr);
+  robin_apply<T>(C, n, nullptr, (const T*)C.X[4], (const T*)nullptr, C.d_gm_rhs, nullptr);
   hipLaunchKernelGGL(k_zero<double>, dim3(nblk(nl)), dim3(256), 0, st, nl, C.d_lam2, (const int*)nullptr);
   dot_partial(C, st, n, (const double*)C.d_gm_rhs, (const double*)C.d_gm_rhs, C.d_gm_wpart, nullptr);
   hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(kScalarThreads), 0, st, nr, (const double*)C.d_gm_wpart, gs);

@@ -58,6 +58,55 @@ __global__ void __launch_bounds__(256) k_robin_apply(int64_t n, const int64_t* _
   y[i] = s;
 }
 
+// Vector form of k_robin_apply: one thread per (side row, group of V
+// right-hand sides), each gather one load of V consecutive values (nrhs a
+// multiple of V); the same sums in the same order.
+template <class T, int V>
+__global__ void __launch_bounds__(256) k_robin_apply_v(int64_t n, const int64_t* __restrict__ rp,
+                                                       const int64_t* __restrict__ rrow,
+                                                       const double* __restrict__ val,
+                                                       const int32_t* __restrict__ partner,
+                                                       const double* __restrict__ lam, const T* __restrict__ U,
+                                                       const T* __restrict__ U2, double* __restrict__ y, int nrhs,
+                                                       const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int G = nrhs / V;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * G) return;
+  const int64_t k = i / G;
+  const int q = (int)(i - k * G);
+  double s[V];
+  if (lam) {
+    vload<double, V>(lam + k * nrhs + q * V, s);
+    const int32_t pq = partner[k];
+    if (pq >= 0) {
+      double t[V];
+      vload<double, V>(lam + (int64_t)pq * nrhs + q * V, t);
+#pragma unroll
+      for (int w = 0; w < V; ++w) s[w] += t[w];
+    }
+  } else {
+#pragma unroll
+    for (int w = 0; w < V; ++w) s[w] = 0.0;
+  }
+  const int64_t j0 = rp[k], j1 = rp[k + 1];
+  for (int64_t j = j0; j < j1; ++j) {
+    const int64_t x = rrow[j] * nrhs + q * V;
+    T u[V];
+    vload<T, V>(U + x, u);
+    if (U2) {
+      T u2[V];
+      vload<T, V>(U2 + x, u2);
+#pragma unroll
+      for (int w = 0; w < V; ++w) u[w] = (T)(u[w] + u2[w]);
+    }
+    const double a = val[j];
+#pragma unroll
+    for (int w = 0; w < V; ++w) s[w] -= a * (double)u[w];
+  }
+  vstore<double, V>(y + k * nrhs + q * V, s);
+}
+
 // Block shares of nv dot products V_k . w per right-hand side:
 // partial[(k * gridDim.x + b) * kMaxRhs + r] (fixed order, no atomics).
 // Workgroup row y takes vectors 8y .. 8y+7, so w is read once per 8 vectors.
