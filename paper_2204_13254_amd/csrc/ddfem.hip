@@ -1835,7 +1835,11 @@ static void gm_project(Ctx& C, int nv, double* w, const int* stop) {
 #define DD_GM_PROJECT(K)                                                                                      \
   hipLaunchKernelGGL((k_gm_project<K, FIRST>), dim3(kDotBlocks), dim3(256), 0, st, n, nv, V, ldv,             \
                      (const double*)C.d_gm_h, w, nr, part, ss, stop)
-  if (nv <= 8)
+  if (nv <= 8 && nr % 2 == 0)
+    // two right-hand sides per lane (a wider form holds too many registers)
+    hipLaunchKernelGGL((k_gm_project_v<8, FIRST, 2>), dim3(kDotBlocks), dim3(256), 0, st, n, nv, V, ldv,
+                       (const double*)C.d_gm_h, w, nr, part, ss, stop);
+  else if (nv <= 8)
     DD_GM_PROJECT(8);
   else if (nv <= 16)
     DD_GM_PROJECT(16);
@@ -1866,8 +1870,15 @@ static void gmres_iteration(Ctx& C, int j) {
   const int* stop = &gs->stop;
   apply_G<T>(C, V + (int64_t)j * ldv, w, stop);
   // h1 = [V_0 .. V_j, w]^T w (the last entry, |w|^2, is not used)
-  hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, (j + 2 + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n, j + 2,
-                     (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial, stop);
+  if (vec_width(nr) == 4)
+    hipLaunchKernelGGL((k_mdot_v<4>), dim3(kDotBlocks, (j + 2 + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n,
+                       j + 2, (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial, stop);
+  else if (vec_width(nr) == 2)
+    hipLaunchKernelGGL((k_mdot_v<2>), dim3(kDotBlocks, (j + 2 + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n,
+                       j + 2, (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial, stop);
+  else
+    hipLaunchKernelGGL(k_mdot, dim3(kDotBlocks, (j + 2 + kMdotChunk - 1) / kMdotChunk), dim3(256), 0, st, n, j + 2,
+                       (const double*)V, ldv, (const double*)w, nr, C.d_gm_partial, stop);
   hipLaunchKernelGGL(k_mdot_reduce, dim3(j + 2), dim3(256), 0, st, j + 2, nr, kDotBlocks,
                      (const double*)C.d_gm_partial, C.d_gm_h, C.d_gm_tot, 1, stop);
   // w' = w - V h1 with h2 = V^T w' and |w'|^2

@@ -147,6 +147,54 @@ __global__ void __launch_bounds__(256) k_mdot(int64_t n, int nv, const double* _
   }
 }
 
+// Vector form of k_mdot: V right-hand sides per lane (nrhs a multiple of
+// V), one 8V-byte load of each vector per row.
+template <int V>
+__global__ void __launch_bounds__(256) k_mdot_v(int64_t n, int nv, const double* __restrict__ Vb, int64_t ldv,
+                                                const double* __restrict__ w, int nrhs, double* __restrict__ partial,
+                                                const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int tid = threadIdx.x;
+  const int G = nrhs / V, lpr = 256 / G;
+  const int q = tid % G, lane = tid / G;
+  const int k0 = blockIdx.y * kMdotChunk;
+  const int kn = nv - k0 < kMdotChunk ? nv - k0 : kMdotChunk;
+  double s[kMdotChunk][V];
+#pragma unroll
+  for (int k = 0; k < kMdotChunk; ++k)
+#pragma unroll
+    for (int u = 0; u < V; ++u) s[k][u] = 0.0;
+  if (lane < lpr)
+    for (int64_t row = (int64_t)blockIdx.x * lpr + lane; row < n; row += (int64_t)gridDim.x * lpr) {
+      const int64_t e = row * nrhs + q * V;
+      double x[V];
+      vload<double, V>(w + e, x);
+#pragma unroll
+      for (int k = 0; k < kMdotChunk; ++k)
+        if (k < kn) {
+          double a[V];
+          vload<double, V>(Vb + (k0 + k) * ldv + e, a);
+#pragma unroll
+          for (int u = 0; u < V; ++u) s[k][u] += a[u] * x[u];
+        }
+    }
+  __shared__ double red[256 * V];
+#pragma unroll
+  for (int k = 0; k < kMdotChunk; ++k) {
+    if (k >= kn) break;
+#pragma unroll
+    for (int u = 0; u < V; ++u) red[tid * V + u] = s[k][u];
+    __syncthreads();
+    if (tid < nrhs) {
+      const int qq = tid / V, u = tid % V;
+      double t = 0.0;
+      for (int l = 0; l < lpr; ++l) t += red[(l * G + qq) * V + u];
+      partial[((int64_t)(k0 + k) * gridDim.x + blockIdx.x) * kMaxRhs + tid] = t;
+    }
+    __syncthreads();
+  }
+}
+
 // h[k][r] = sum_b partial (fixed order); with tot, tot[k][r] = h[k][r]
 // (assign) or tot[k][r] += h[k][r].  One workgroup per k: a power-of-two
 // number of lanes per right-hand side take strided block shares, then a
@@ -252,6 +300,88 @@ __global__ void __launch_bounds__(256) k_gm_project(int64_t n, int nv, const dou
     if (tid < nrhs) {
       double t = 0.0;
       for (int l2 = 0; l2 < lpr; ++l2) t += red[l2 * nrhs + tid];
+      partial[((int64_t)k * gridDim.x + blockIdx.x) * kMaxRhs + tid] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Vector form of k_gm_project: V right-hand sides per lane (nrhs a multiple
+// of V); the same sums per right-hand side.
+template <int KMAX, bool FIRST, int V>
+__global__ void __launch_bounds__(256) k_gm_project_v(int64_t n, int nv, const double* __restrict__ Vb, int64_t ldv,
+                                                      const double* __restrict__ h, double* __restrict__ w, int nrhs,
+                                                      double* __restrict__ partial, const double* __restrict__ ss,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double hs[KMAX * kMaxRhs];
+  __shared__ double red[256 * V];
+  for (int t = threadIdx.x; t < nv * kMaxRhs; t += blockDim.x) hs[t] = h[t];
+  __syncthreads();
+  const int G = nrhs / V, lpr = 256 / G;
+  const int tid = threadIdx.x, q = tid % G, lane = tid / G;
+  double hk[KMAX][V], dots[KMAX][V];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      hk[k][u] = k < nv ? hs[k * kMaxRhs + q * V + u] : 0.0;
+      dots[k][u] = 0.0;
+    }
+  double nn[V], scale[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    nn[u] = 0.0;
+    scale[u] = 1.0;
+    if (!FIRST) {
+      const double qq = ss[q * V + u];
+      scale[u] = qq > 0.0 ? 1.0 / sqrt(qq) : 0.0;
+    }
+  }
+  if (lane < lpr)
+    for (int64_t row = (int64_t)blockIdx.x * lpr + lane; row < n; row += (int64_t)gridDim.x * lpr) {
+      const int64_t e = row * nrhs + q * V;
+      double vk[KMAX][V];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        if (k < nv) {
+          vload<double, V>(Vb + k * ldv + e, vk[k]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < V; ++u) vk[k][u] = 0.0;
+        }
+      }
+      double wv[V];
+      vload<double, V>(w + e, wv);
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) acc += hk[k][u] * vk[k][u];
+        const double v = wv[u] - acc;
+        if (FIRST) {
+          wv[u] = v;
+#pragma unroll
+          for (int k = 0; k < KMAX; ++k) dots[k][u] += vk[k][u] * v;
+          nn[u] += v * v;
+        } else {
+          wv[u] = v * scale[u];
+        }
+      }
+      vstore<double, V>(w + e, wv);
+    }
+  if (!FIRST) return;
+  // block partials of the nv dots and |w'|^2 (fixed order)
+#pragma unroll
+  for (int k = 0; k <= KMAX; ++k) {
+    if (k > nv) break;
+#pragma unroll
+    for (int u = 0; u < V; ++u) red[tid * V + u] = k < nv ? dots[k < KMAX ? k : 0][u] : nn[u];
+    __syncthreads();
+    if (tid < nrhs) {
+      const int qq = tid / V, u = tid % V;
+      double t = 0.0;
+      for (int l2 = 0; l2 < lpr; ++l2) t += red[(l2 * G + qq) * V + u];
       partial[((int64_t)k * gridDim.x + blockIdx.x) * kMaxRhs + tid] = t;
     }
     __syncthreads();
