@@ -2,19 +2,21 @@
 //
 // Per-step data flow of the decomposed solve (Sec. III-A, eq. (f1schur);
 // local factors L_rr of [I | Gamma] with the corner rows L_cr and local
-// corner Schur complements K_s).  Stored inverses (Sec. III-C):
-// Linv = L_rr^-1, Psi = L_cr Linv (kept in the corner tile rows), and the
-// interface block of the local inverse M = (K_rr^-1)_GG = Linv_GG^T Linv_GG.
-//   pre-solve : w = owner split of b;  t = Linv_rr w_r;
-//               f_c = sum_s B_c^T (w_c - Psi_r w_r);  z0 = K_cc^-1 f_c;
-//               d = sum_s B_s (Linv_GG^T t_G - Psi_G^T z0_s)
+// corner Schur complements K_s).  Stored per subdomain (the local inverses
+// of Sec. III-C, split by the factor's column blocks): Linv_II = L_II^-1;
+// the couplings L_GI, L_cI as factored; Psi_G = L_cG L_GG^-1 in the corner
+// rows; the interface block of the local inverse
+// M = (K_rr^-1)_GG = L_GG^-T L_GG^-1.
+//   pre-solve : w = owner split of b;  t_I = Linv_II w_I;
+//               y_G = w_G - L_GI t_I;  g' = w_c - L_cI t_I;
+//               z0 = K_cc^-1 sum_s B_c^T (g' - Psi_G y_G);
+//               d = sum_s B_s (M y_G - Psi_G^T z0)
 //   CG on F lambda = d with
 //               F p = sum_s B_s (M v + Psi_G^T z_s),  v = B_s^T p,
 //               z = K_cc^-1 sum_s B_c^T Psi_G v
-//   recovery  : v_l = B_s^T lambda;  t_l = Linv_GG v_l;
-//               x_c = K_cc^-1 (f_c + sum_s B_c^T Psi_G v_l);
-//               x_r = Linv_rr^T (t - [0; t_l]) - Psi_r^T x_c;
-//               e = owner's copy.
+//   recovery  : u = y_G - B_s^T lambda;
+//               x_c = K_cc^-1 sum_s B_c^T (g' - Psi_G u);  x_G = M u - Psi_G^T x_c;
+//               x_I = Linv_II^T (t_I - L_GI^T x_G - L_cI^T x_c);  e = owner's copy.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
