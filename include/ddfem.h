@@ -150,8 +150,9 @@ typedef struct {
   int32_t n_sub, n_lambda, n_corner, nrhs, precision, tile;
   int64_t factor_bytes;    /* device bytes of all stored factors */
   int64_t trailing_bytes;  /* bytes of the interface blocks of the inverse factors
-                              with the corner rows Psi_Gamma (pre-solve and
-                              recovery), unpadded */
+                              with the corner rows Psi_Gamma, unpadded (the
+                              factorisation forms M and Psi_Gamma from them;
+                              no solve pass reads the inverse blocks alone) */
   int64_t schur_bytes;     /* bytes of the interface blocks of the local inverses,
                               M = (K_rr^-1)_GammaGamma, packed lower triangle (read once
                               per CG iteration), unpadded */
