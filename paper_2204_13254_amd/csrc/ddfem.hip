@@ -1558,9 +1558,7 @@ static void mv(Ctx& C, const Items& it, bool trans, const void* in, void* out, c
   bool timed = prof_begin(C, item_class(C, it), &e0, &e1);
   hipStream_t s = side ? C.st2 : C.st;
   const int cls = item_class(C, it);
-  if (cls == DD_PROF_TRAILING)
-    mv_dispatch<T, DD_PROF_TRAILING>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
-  else if (cls == DD_PROF_FULL)
+  if (cls == DD_PROF_FULL)
     mv_dispatch<T, DD_PROF_FULL>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (cls == DD_PROF_CROSS)
     mv_dispatch<T, DD_PROF_CROSS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
