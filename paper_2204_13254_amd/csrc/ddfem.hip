@@ -1673,9 +1673,17 @@ static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s)
   int64_t ng = (C.sym.n + 3) / 4;
   if (C.tuning.sym_persist > 0) ng = std::min<int64_t>(ng, C.tuning.sym_persist);
   const dim3 grid((unsigned)ng);
-#define DD_SYMV(NB16, PW)                                                                                     \
-  hipLaunchKernelGGL((k_symv<T, NB16, PW>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,      \
+  // a full RHS block (16 or 32) takes the instance with a compile-time stride
+#define DD_SYMV_LD(NB16, PW, LD)                                                                              \
+  hipLaunchKernelGGL((k_symv<T, NB16, PW, LD>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,  \
                      (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip)
+#define DD_SYMV(NB16, PW)                \
+  do {                                   \
+    if (C.nrhs == 16 * (NB16))           \
+      DD_SYMV_LD(NB16, PW, 16 * (NB16)); \
+    else                                 \
+      DD_SYMV_LD(NB16, PW, 0);           \
+  } while (0)
   if (sizeof(T) == 4 && C.sym.pw == 4) {
     if (C.nrhs <= 16)
       DD_SYMV(1, 4);
@@ -1688,6 +1696,7 @@ static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s)
       DD_SYMV(2, 2);
   }
 #undef DD_SYMV
+#undef DD_SYMV_LD
   if (timed) HIPCHK(hipEventRecord(e1, C.st));
 }
 

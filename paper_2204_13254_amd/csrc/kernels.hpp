@@ -732,7 +732,7 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
   // barriers: the waves of a workgroup are independent.
   const int64_t ngroups = (n_items + 3) / 4;
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    const int64_t wi = grp * 4 + (threadIdx.x >> 6);
+    const int64_t wi = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     if (wi >= n_items) continue;
     const MvItem w = items[wi];
     if (w.s < 0) continue;  // padding item
@@ -924,7 +924,7 @@ __global__ void __launch_bounds__(256) k_tile_mv2(int64_t n_items, const MvItem*
   if (skip && *skip) return;
   const int64_t ngroups = (n_items + 3) / 4;
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    const int64_t wi = grp * 4 + (threadIdx.x >> 6);
+    const int64_t wi = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
     if (wi >= n_items) continue;
     const MvItem w = items[wi];
     if (w.s < 0) continue;  // padding item
@@ -1198,14 +1198,20 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class T, int NB16, int PW>
-__global__ void __launch_bounds__(256) k_symv(int64_t n_items, const SymItem* __restrict__ items,
+// FP32 at 16 RHS fits three waves per SIMD without spills (the stream of
+// tiles needs the loads of more waves in flight).
+template <class T, int NB16, int PW, int LD>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 16 && sizeof(T) == 4 ? 3 : 1))) k_symv(int64_t n_items, const SymItem* __restrict__ items,
                                               const SubDev* __restrict__ subs, const int64_t* __restrict__ m_off,
                                               const T* __restrict__ mt, const T* __restrict__ in,
-                                              T* __restrict__ partial, int nrhs, const int* __restrict__ skip) {
+                                              T* __restrict__ partial, int nrhs_rt, const int* __restrict__ skip) {
+  // LD > 0: the RHS count is LD (= 16 NB16), a compile-time row stride
+  const int nrhs = LD > 0 ? LD : nrhs_rt;
   if (skip && *skip) return;
   __shared__ T lds[4][kNB][kNB + 1];
-  const int wv = threadIdx.x >> 6;
+  // the wave index is uniform over the wave: item, subdomain record and
+  // tile addresses go to scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // one item per wave; a grid smaller than the item groups walks them
   // (groups b, b + G, ...: G a multiple of 8 keeps a workgroup on its XCD).
   // No workgroup barriers below: waves are independent.
