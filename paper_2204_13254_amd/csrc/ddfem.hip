@@ -1492,7 +1492,7 @@ static int item_class(const Ctx& C, const Items& it) {
   return DD_PROF_COARSE;
 }
 
-template <class T, int NV, int NB16, int CLS>
+template <class T, int NV, int NB16, int CLS, int LD>
 static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const void* in, void* out, const void* add,
                       T alpha, const void* add_c, T alpha_c, const int* skip) {
   const bool split = it.n_out > 0;
@@ -1507,20 +1507,20 @@ static void mv_launch(Ctx& C, hipStream_t s, const Items& it, bool trans, const 
     if (it.oct) {
       int64_t g8 = it.n;  // one workgroup per item (a multiple of 8)
       if (C.tuning.full_persist > 0) g8 = std::min<int64_t>(g8, C.tuning.full_persist);
-      hipLaunchKernelGGL((k_tile_mv8<T, NB16, CLS>), dim3((unsigned)g8), dim3(256), 0, s, it.n, it.d, C.d_subs,
+      hipLaunchKernelGGL((k_tile_mv8<T, NB16, CLS, LD>), dim3((unsigned)g8), dim3(256), 0, s, it.n, it.d, C.d_subs,
                          tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
                          (int)trans, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
     } else if (it.pair) {
-      hipLaunchKernelGGL((k_tile_mv2<T, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d, C.d_subs,
+      hipLaunchKernelGGL((k_tile_mv2<T, NB16, CLS, LD>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d, C.d_subs,
                          tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c, C.nrhs,
                          (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
     } else {
-      hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
+      hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS, LD>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
                          C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c,
                          C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
     }
   } else {
-    hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
+    hipLaunchKernelGGL((k_tile_mv<T, NV, NB16, CLS, LD>), dim3((unsigned)grid), dim3(256), 0, s, it.n, it.d,
                        C.d_subs, tiles, (const T*)in, (T*)out, (const T*)add, alpha, (const T*)add_c, alpha_c,
                        C.nrhs, (int)trans, partial, (const int32_t*)it.mlist, skip, (const T*)C.d_zero_tile);
   }
@@ -1533,18 +1533,23 @@ template <class T, int CLS>
 static void mv_dispatch(Ctx& C, hipStream_t s, const Items& it, bool trans, const void* in, void* out,
                         const void* add, T alpha, const void* add_c, T alpha_c, const int* skip) {
   const int nr = C.nrhs;
+  // full RHS blocks (16, 32) take the instances with a compile-time stride
   if (nr == 1)
-    mv_launch<T, 1, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 1, 0, CLS, 0>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr == 2)
-    mv_launch<T, 2, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 2, 0, CLS, 0>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 4)
-    mv_launch<T, 4, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 4, 0, CLS, 0>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else if (nr <= 8)
-    mv_launch<T, 8, 0, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
-  else if (nr <= 16)
-    mv_launch<T, 0, 1, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 8, 0, CLS, 0>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+  else if (nr == 16)
+    mv_launch<T, 0, 1, CLS, 16>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+  else if (nr < 16)
+    mv_launch<T, 0, 1, CLS, 0>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+  else if (nr == 32)
+    mv_launch<T, 0, 2, CLS, 32>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
   else
-    mv_launch<T, 0, 2, CLS>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
+    mv_launch<T, 0, 2, CLS, 0>(C, s, it, trans, in, out, add, alpha, add_c, alpha_c, skip);
 }
 
 // out = add + alpha * (product) on r-row output blocks, add_c + alpha_c *

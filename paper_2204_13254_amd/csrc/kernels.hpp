@@ -716,15 +716,17 @@ __device__ __forceinline__ void load_chunk8(const T* __restrict__ blk, int l, T*
 // NV > 0: vector path for nrhs <= NV; NV == 0: MFMA path with NB16 RHS blocks.
 // CLS only names the product class in kernel traces (0 interface blocks of
 // the inverse factors, 1 full r-blocks, 3 coarse, 4 corner rows).
-template <class T, int NV, int NB16, int CLS>
+template <class T, int NV, int NB16, int CLS, int LD>
 __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* __restrict__ items,
                                                  const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                  const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
-                                                 T alpha_c, int nrhs, int trans, T* __restrict__ partial,
+                                                 T alpha_c, int nrhs_rt, int trans, T* __restrict__ partial,
                                                  const int32_t* __restrict__ mlist, const int* __restrict__ skip,
                                                  const T* __restrict__ zero) {
   if (skip && *skip) return;
+  // LD > 0: the RHS count is LD (= 16 NB16), a compile-time row stride
+  const int nrhs = LD > 0 ? LD : nrhs_rt;
   // Work groups of 4 items (one per wave); workgroup b takes groups b,
   // b + gridDim.x, ...: one pass over the list with as many workgroups as
   // groups, or a persistent grid (a multiple of 8, so that every group a
@@ -913,15 +915,17 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
 // not shared).  An entry's absent tile is read from `zero`, one zero tile
 // (cached after its first use).  Split items write partial slots w.slot
 // (block o) and w.slot2 (block o2), as k_tile_mv does.
-template <class T, int NB16, int CLS>
+template <class T, int NB16, int CLS, int LD>
 __global__ void __launch_bounds__(256) k_tile_mv2(int64_t n_items, const MvItem* __restrict__ items,
                                                   const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                   const T* __restrict__ in, T* __restrict__ out,
                                                   const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
-                                                  T alpha_c, int nrhs, int trans, T* __restrict__ partial,
+                                                  T alpha_c, int nrhs_rt, int trans, T* __restrict__ partial,
                                                   const int32_t* __restrict__ mlist, const int* __restrict__ skip,
                                                   const T* __restrict__ zero) {
   if (skip && *skip) return;
+  // LD > 0: the RHS count is LD (= 16 NB16), a compile-time row stride
+  const int nrhs = LD > 0 ? LD : nrhs_rt;
   const int64_t ngroups = (n_items + 3) / 4;
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t wi = grp * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
@@ -1041,14 +1045,16 @@ __global__ void __launch_bounds__(256) k_tile_mv2(int64_t n_items, const MvItem*
 // tile reads `zero`.  Double-buffered LDS, one workgroup barrier per entry;
 // outputs are written directly (octet items are not split).
 constexpr int32_t kOctMask = (1 << 23) - 1;
-template <class T, int NB16, int CLS>
+template <class T, int NB16, int CLS, int LD>
 __global__ void __launch_bounds__(256) k_tile_mv8(int64_t n_items, const MvItem* __restrict__ items,
                                                   const SubDev* __restrict__ subs, const T* __restrict__ tiles,
                                                   const T* __restrict__ in, T* __restrict__ out,
                                                   const T* __restrict__ add, T alpha, const T* __restrict__ add_c,
-                                                  T alpha_c, int nrhs, int trans, const int32_t* __restrict__ mlist,
+                                                  T alpha_c, int nrhs_rt, int trans, const int32_t* __restrict__ mlist,
                                                   const int* __restrict__ skip, const T* __restrict__ zero) {
   if (skip && *skip) return;
+  // LD > 0: the RHS count is LD (= 16 NB16), a compile-time row stride
+  const int nrhs = LD > 0 ? LD : nrhs_rt;
   constexpr int LP = kNB + 4;            // LDS pitch of one RHS column (16-byte multiple)
   constexpr int XPER = (kNB * 16 * NB16 + 255) / 256;
   __shared__ __align__(16) T xs[2][16 * NB16][LP];
