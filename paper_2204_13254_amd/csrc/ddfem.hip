@@ -280,6 +280,7 @@ struct Ctx {
     MvOut* outs = nullptr;
     int64_t n_out = 0;
     void* partial = nullptr;
+    void* zero = nullptr;  // one zero tile (positions outside the stored triangle)
     int pw = 0;  // panel width the list was built for
   } sym;
   // work vectors
@@ -493,6 +494,7 @@ static void make_sym_list(Ctx& C, int pw, size_t wsz) {
   release(C, C.sym.d);
   release(C, C.sym.outs);
   release(C, C.sym.partial);
+  release(C, C.sym.zero);
   C.sym = Ctx::SymList{};
   C.sym.pw = pw;
   std::vector<SymItem> v;
@@ -519,6 +521,10 @@ static void make_sym_list(Ctx& C, int pw, size_t wsz) {
   HIPCHK(hipMalloc(&p, std::max<int64_t>(1, slot) * kTile * C.nrhs * wsz / NB));
   C.owned.push_back(p);
   C.sym.partial = p;
+  HIPCHK(hipMalloc(&p, kTile * wsz));
+  C.owned.push_back(p);
+  HIPCHK(hipMemsetAsync(p, 0, kTile * wsz, C.st));
+  C.sym.zero = p;
 }
 
 static void build_device(Ctx& C, const double* coords) {
@@ -1681,7 +1687,7 @@ static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s)
   // a full RHS block (16 or 32) takes the instance with a compile-time stride
 #define DD_SYMV_LD(NB16, PW, LD)                                                                              \
   hipLaunchKernelGGL((k_symv<T, NB16, PW, LD>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,  \
-                     (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip)
+                     (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip, (const T*)C.sym.zero)
 #define DD_SYMV(NB16, PW)                \
   do {                                   \
     if (C.nrhs == 16 * (NB16))           \
@@ -1689,12 +1695,18 @@ static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s)
     else                                 \
       DD_SYMV_LD(NB16, PW, 0);           \
   } while (0)
-  if (sizeof(T) == 4 && C.sym.pw == 4) {
-    if (C.nrhs <= 16)
-      DD_SYMV(1, 4);
-    else
-      DD_SYMV(2, 4);
-  } else {
+  // panel width 4 exists for FP32 only (FP64 accumulators do not fit)
+  bool pw4 = false;
+  if constexpr (sizeof(T) == 4) {
+    if (C.sym.pw == 4) {
+      pw4 = true;
+      if (C.nrhs <= 16)
+        DD_SYMV(1, 4);
+      else
+        DD_SYMV(2, 4);
+    }
+  }
+  if (!pw4) {
     if (C.nrhs <= 16)
       DD_SYMV(1, 2);
     else

@@ -1204,13 +1204,17 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+#ifndef SYMV_DEPTH
+#define SYMV_DEPTH 2  // FP32 tiles in flight per wave in k_symv
+#endif
 // FP32 at 16 RHS fits three waves per SIMD without spills (the stream of
 // tiles needs the loads of more waves in flight).
 template <class T, int NB16, int PW, int LD>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 16 && sizeof(T) == 4 ? 3 : 1))) k_symv(int64_t n_items, const SymItem* __restrict__ items,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 16 && sizeof(T) == 4 && (SYMV_DEPTH == 1 || PW == 2) ? 3 : 1))) k_symv(int64_t n_items, const SymItem* __restrict__ items,
                                               const SubDev* __restrict__ subs, const int64_t* __restrict__ m_off,
                                               const T* __restrict__ mt, const T* __restrict__ in,
-                                              T* __restrict__ partial, int nrhs_rt, const int* __restrict__ skip) {
+                                              T* __restrict__ partial, int nrhs_rt, const int* __restrict__ skip,
+                                              const T* __restrict__ zero) {
   // LD > 0: the RHS count is LD (= 16 NB16), a compile-time row stride
   const int nrhs = LD > 0 ? LD : nrhs_rt;
   if (skip && *skip) return;
@@ -1248,11 +1252,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 
       const int jr = t / PW, jc = t % PW;
       return o0 + jr < kG && m0 + jc < kG && (!diag || jc <= jr);
     };
-    auto next_valid = [&](int t) -> int {
-      for (int u = t + 1; u < PW * PW; ++u)
-        if (valid(u)) return u;
-      return -1;
-    };
     auto tile_of = [&](int t) -> const T* {
       const int o = o0 + t / PW, m = m0 + t % PW;
       return mb + ((int64_t)o * (o + 1) / 2 + m) * kTile;
@@ -1272,26 +1271,39 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 
         }
       }
     };
-    // u_m is prefetched with each tile; u_o only changes with the row (loaded
-    // at its first tile, covered by the row part's MFMAs)
-    T cur[16], nxt[16], xm[8 * NB16], xmn[8 * NB16], xo[8 * NB16];
-    // tile 0 = (o0, m0) is always valid: o0 < kG and m0 <= o0
-    load_chunk8(tile_of(0), l, cur);
-    load_chunk8(tile_of(0) + 512, l, cur + 8);
-    load_x(m0, xm);
-    load_x(o0, xo);
+    // Static schedule over the PW x PW positions of the pair (all indices
+    // compile-time after unrolling, so the ring buffers need no copies): tile
+    // t + D and its u_m block are loaded while tile t is used.  A position
+    // outside the stored triangle or past the last interface tile reads the
+    // zero tile (its u_m block clamped in range), so its products add zero;
+    // every load is unconditional.  u_o changes with the row: the next row's
+    // block is loaded when the current row starts.
+    constexpr int DEPTH = sizeof(T) == 4 ? SYMV_DEPTH : 1;
+    constexpr int NT = PW * PW, NBUF = DEPTH + 1;
+    T tb[NBUF][16], xb[NBUF][8 * NB16], xo[8 * NB16], xon[8 * NB16];
+    auto tile_addr = [&](int t) -> const T* { return valid(t) ? tile_of(t) : zero; };
+    auto clampb = [&](int b) { return b < kG ? b : kG - 1; };
+    auto prefetch = [&](int t) {
+      const T* tp = tile_addr(t);
+      load_chunk8(tp, l, tb[t % NBUF]);
+      load_chunk8(tp + 512, l, tb[t % NBUF] + 8);
+      load_x(clampb(m0 + t % PW), xb[t % NBUF]);
+    };
 #pragma unroll
-    for (int t = 0; t < PW * PW; ++t) {
-      if (!valid(t)) continue;
+    for (int t = 0; t < DEPTH && t < NT; ++t) prefetch(t);
+    load_x(o0, xo);
+    if (PW > 1) load_x(clampb(o0 + 1), xon);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
       const int jr = t / PW, jc = t % PW;
-      if (jc == 0 && jr > 0) load_x(o0 + jr, xo);
-      const int tn = next_valid(t);
-      if (tn >= 0) {
-        const T* tp = tile_of(tn);
-        load_chunk8(tp, l, nxt);
-        load_chunk8(tp + 512, l, nxt + 8);
-        load_x(m0 + tn % PW, xmn);
+      if (jc == 0 && jr > 0) {
+#pragma unroll
+        for (int u = 0; u < 8 * NB16; ++u) xo[u] = xon[u];
+        if (jr + 1 < PW) load_x(clampb(o0 + jr + 1), xon);
       }
+      if (t + DEPTH < NT) prefetch(t + DEPTH);
+      const T* cur = tb[t % NBUF];
+      const T* xm = xb[t % NBUF];
 #pragma unroll
       for (int nb = 0; nb < NB16; ++nb)
 #pragma unroll
@@ -1299,7 +1311,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 
           racc[jr][0][nb] = Mfma<T>::op(cur[ks], xm[nb * 8 + ks], racc[jr][0][nb]);
           racc[jr][1][nb] = Mfma<T>::op(cur[8 + ks], xm[nb * 8 + ks], racc[jr][1][nb]);
         }
-      if (!diag || jc != jr) {
+      // the column part of a diagonal tile would count it twice; above the
+      // diagonal of a diagonal pair the tile is zero
+      if (!diag || jc < jr) {
         // column part: lane (g, i) needs M(8g + ks, cb*16 + i)
         wave_lds_sync();
 #pragma unroll
@@ -1319,12 +1333,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LD == 
             cacc[jc][0][nb] = Mfma<T>::op(tt[ks], xo[nb * 8 + ks], cacc[jc][0][nb]);
             cacc[jc][1][nb] = Mfma<T>::op(tt[8 + ks], xo[nb * 8 + ks], cacc[jc][1][nb]);
           }
-      }
-      if (tn >= 0) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
-#pragma unroll
-        for (int u = 0; u < 8 * NB16; ++u) xm[u] = xmn[u];
       }
     }
     // ---- partial blocks ---------------------------------------------------------
