@@ -415,7 +415,9 @@ int dd_step_mixed(void* ctx, const double* J_half, const double* E_n, const doub
 
 /* Per-class timing of the batched tile products, measured with HIP events
  * recorded on the context's stream around each launch (adds two event
- * records per launch while enabled).  Classes: */
+ * records per launch while enabled; the symmetric product's events are
+ * attached to its kernel dispatch instead, so they time its execution).
+ * Classes: */
 enum {
   DD_PROF_TRAILING = 0, /* no launches (kept for the numbering): no pass applies the interface
                            blocks of the inverse factors alone; the solves use M below */

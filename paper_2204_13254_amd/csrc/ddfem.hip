@@ -17,6 +17,7 @@
 //   recovery  : u = y_G - B_s^T lambda;
 //               x_c = K_cc^-1 sum_s B_c^T (g' - Psi_G u);  x_G = M u - Psi_G^T x_c;
 //               x_I = Linv_II^T (t_I - L_GI^T x_G - L_cI^T x_c);  e = owner's copy.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1476,7 +1477,8 @@ static void prof_resolve(Ctx& C) {
   C.ev_next = 0;
 }
 
-static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
+// record_start = false: the caller attaches both events to its launch
+static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b, bool record_start = true) {
   if (!C.prof) return false;
   if (C.ev_next + 2 > C.ev_pool.size()) prof_resolve(C);
   while (C.ev_pool.size() < C.ev_next + 2) {
@@ -1487,7 +1489,7 @@ static bool prof_begin(Ctx& C, int cls, hipEvent_t* a, hipEvent_t* b) {
   *a = C.ev_pool[C.ev_next++];
   *b = C.ev_pool[C.ev_next++];
   C.ev_pending.push_back({cls, {*a, *b}});
-  HIPCHK(hipEventRecord(*a, C.st));
+  if (record_start) HIPCHK(hipEventRecord(*a, C.st));
   return true;
 }
 
@@ -1674,20 +1676,29 @@ static void join_side(Ctx& C) {
   HIPCHK(hipStreamWaitEvent(C.st, C.ev_join, 0));
 }
 
-// The symmetric product M in into the partial slots (the per-class event
-// timing of DD_PROF_SCHUR covers this kernel alone), and the reduce of the
-// slots: out (interface rows) = add + M in.
+// The symmetric product M in into the partial slots, and the reduce of the
+// slots: out (interface rows) = add + M in.  The per-class timing of
+// DD_PROF_SCHUR covers this kernel alone: its events are attached to the
+// kernel's dispatch (start and end of its execution).
 template <class T>
 static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s) {
-  hipEvent_t e0, e1;
-  bool timed = prof_begin(C, DD_PROF_SCHUR, &e0, &e1);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = prof_begin(C, DD_PROF_SCHUR, &e0, &e1, false);
   int64_t ng = (C.sym.n + 3) / 4;
   if (C.tuning.sym_persist > 0) ng = std::min<int64_t>(ng, C.tuning.sym_persist);
   const dim3 grid((unsigned)ng);
   // a full RHS block (16 or 32) takes the instance with a compile-time stride
-#define DD_SYMV_LD(NB16, PW, LD)                                                                              \
-  hipLaunchKernelGGL((k_symv<T, NB16, PW, LD>), grid, dim3(256), 0, s, C.sym.n, C.sym.d, C.d_subs, C.d_m_off,  \
-                     (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip, (const T*)C.sym.zero)
+  // (timing happens in eager steps only; captured steps launch plainly)
+#define DD_SYMV_ARGS                                                                                      \
+  C.sym.n, C.sym.d, C.d_subs, C.d_m_off, (const T*)C.d_mtri, (const T*)in, (T*)C.sym.partial, C.nrhs, skip, \
+      (const T*)C.sym.zero
+#define DD_SYMV_LD(NB16, PW, LD)                                                                       \
+  do {                                                                                                 \
+    if (timed)                                                                                         \
+      hipExtLaunchKernelGGL((k_symv<T, NB16, PW, LD>), grid, dim3(256), 0, s, e0, e1, 0, DD_SYMV_ARGS); \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_symv<T, NB16, PW, LD>), grid, dim3(256), 0, s, DD_SYMV_ARGS);              \
+  } while (0)
 #define DD_SYMV(NB16, PW)                \
   do {                                   \
     if (C.nrhs == 16 * (NB16))           \
@@ -1714,7 +1725,7 @@ static void symv_product(Ctx& C, const void* in, const int* skip, hipStream_t s)
   }
 #undef DD_SYMV
 #undef DD_SYMV_LD
-  if (timed) HIPCHK(hipEventRecord(e1, C.st));
+#undef DD_SYMV_ARGS
 }
 
 template <class T>
