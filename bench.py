@@ -32,6 +32,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# dense MFMA peaks by element size (FP32, FP64), TFLOP/s
+MFMA_PEAK_TFLOPS = {4: 157.3, 8: 78.6}
 
 
 def make_sources(w, coords, tets, steps, workers, start_method="fork"):
@@ -449,6 +451,9 @@ def roofline(s, per, nrhs, prof):
              "full": "interior inverse factors L_II^-1", "schur": "interface blocks of the local inverses, M u",
              "corner": "corner rows Psi_Gamma", "coarse": "coarse inverse factor",
              "cross": "couplings L_GammaI, L_cI to the interior"}
+    # the symmetric product's arithmetic: y = M u with M symmetric n_G x n_G
+    # costs 2 n_G^2 flops per RHS (on MFMA in the factor precision)
+    flops = {"schur": 2.0 * nrhs * float((nG.astype(np.float64) ** 2).sum())}
     dom = max(algo, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_ms = dom_ms / max(1, dom_n)
@@ -458,6 +463,22 @@ def roofline(s, per, nrhs, prof):
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": int(algo[dom]), "avg_launch_ms": round(avg_ms, 4),
             "launches": dom_n, "class": dom}
+    if dom in flops:
+        # both limits of the launch: HBM bytes at 8 TB/s and MFMA flops at
+        # the dense peak; the larger one is the bound
+        peak_tf = MFMA_PEAK_TFLOPS[wsz]
+        t_hbm = algo[dom] / (HBM_PEAK_GBS * 1e9)
+        t_mfma = flops[dom] / (peak_tf * 1e12)
+        tf = flops[dom] / (avg_ms * 1e-3) / 1e12
+        roof["flops_per_launch"] = int(flops[dom])
+        roof["mfma_tflops"] = round(tf, 2)
+        roof["mfma_frac"] = round(tf / peak_tf, 4)
+        roof["mfma_over_hbm_time"] = round(t_mfma / t_hbm, 3)
+        if t_mfma > t_hbm:
+            roof["hbm_achieved_GBps"] = roof["achieved"]
+            roof["hbm_frac"] = roof["frac"]
+            roof.update({"bound": "mfma", "achieved": round(tf, 2), "peak": peak_tf, "unit": "TFLOP/s",
+                         "frac": round(tf / peak_tf, 4)})
     other = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                  "GBps": (round(algo[k] / (v[0] / v[1] * 1e-3) / 1e9, 1) if k in algo and v[1] else None)}
              for k, v in prof.items()}
