@@ -799,28 +799,50 @@ __global__ void __launch_bounds__(256) k_tile_mv(int64_t n_items, const MvItem* 
       load_chunk8(((zq >> ch) & 1) ? zero : tp, l, c);
       load_chunk8((((zq >> (2 + ch)) & 1) ? zero : tp) + 512, l, c + 8);
     };
-    if (w.lo < w.hi) {
+    if constexpr (MF) {
+      // two tiles (and their input blocks) in flight: a ring of three
+      // buffers over the item's tiles, the loop unrolled by three so that
+      // each buffer stays in fixed registers (no copies between iterations)
+      T rb[3][16], rx[3][NX];
+      auto ld = [&](int k, int u) {
+        const int32_t e = ent(k);
+        load_tile(e, rb[u]);
+        load_x(e & kListMask, rx[u]);
+      };
+      auto mm = [&](int u) {
+#pragma unroll
+        for (int nb = 0; nb < NB16; ++nb)
+#pragma unroll
+          for (int ks = 0; ks < 8; ++ks) {
+            macc[nb] = Mfma<T>::op(rb[u][ks], rx[u][nb * 8 + ks], macc[nb]);
+            macc[NB16 + nb] = Mfma<T>::op(rb[u][8 + ks], rx[u][nb * 8 + ks], macc[NB16 + nb]);
+          }
+      };
+      if (w.lo < w.hi) ld(w.lo, 0);
+      if (w.lo + 1 < w.hi) ld(w.lo + 1, 1);
+      for (int k = w.lo; k < w.hi; k += 3) {
+        if (k + 2 < w.hi) ld(k + 2, 2);
+        mm(0);
+        if (k + 3 < w.hi) ld(k + 3, 0);
+        if (k + 1 < w.hi) mm(1);
+        if (k + 4 < w.hi) ld(k + 4, 1);
+        if (k + 2 < w.hi) mm(2);
+      }
+    }
+    if (!MF && w.lo < w.hi) {
       const int32_t e0 = ent(w.lo);
       load_tile(e0, cur);
       load_x(e0 & kListMask, xc);
     }
-    for (int k = w.lo; k < w.hi; ++k) {
+    // vector path: one tile in flight
+    for (int k = w.lo; k < (MF ? w.lo : w.hi); ++k) {
       const int m = ent(k) & kListMask;
       if (k + 1 < w.hi) {
         const int32_t e1 = ent(k + 1);
         load_tile(e1, nxt);
         load_x(e1 & kListMask, xn);
       }
-      if constexpr (MF) {
-#pragma unroll
-        for (int nb = 0; nb < NB16; ++nb) {
-#pragma unroll
-          for (int ks = 0; ks < 8; ++ks) {
-            macc[nb] = Mfma<T>::op(cur[ks], xc[nb * 8 + ks], macc[nb]);
-            macc[NB16 + nb] = Mfma<T>::op(cur[8 + ks], xc[nb * 8 + ks], macc[NB16 + nb]);
-          }
-        }
-      } else if constexpr (PX) {
+      if constexpr (PX) {
 #pragma unroll
         for (int ks = 0; ks < 8; ++ks)
 #pragma unroll
