@@ -31,7 +31,7 @@ from workloads.probes import sketch_vectors
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-WORKERS = 16     # the GPU machine's CPU share
+WORKERS = 16     # source-generation processes (the CPU share of a one-GPU host)
 
 
 def _run(s, J, record_every=1):
