@@ -142,10 +142,11 @@ def kernel_source_sha(cls="full"):
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profiles(cls):
-    """Counter-derived HBM bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by
-    the copy-kernel calibration), or None when no summary matches the current
-    kernel sources."""
+def _profiled_class(cls, workload):
+    """The committed counter summary of a product class (profiles/traffic.json:
+    FETCH_SIZE + WRITE_SIZE bytes per launch scaled by the copy-kernel
+    calibration, and the rocprofv3 average kernel time), or None when it was
+    taken on another workload or on other kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -153,9 +154,14 @@ def _traffic_from_profiles(cls):
     except (OSError, ValueError):
         return None
     v = t.get("classes", {}).get(cls)
-    if v is None or v.get("source_sha") != kernel_source_sha(cls):
+    if v is None or t.get("workload") != workload or v.get("source_sha") != kernel_source_sha(cls):
         return None
-    return v.get("bytes_per_launch")
+    return v
+
+
+def _traffic_from_profiles(cls, workload):
+    v = _profiled_class(cls, workload)
+    return None if v is None else v.get("bytes_per_launch")
 
 
 def pic_leg(s, w, E, steps, dev, log, sort_every=10, cycles=5, cpu_sample=0):
@@ -637,8 +643,15 @@ def main():
     roof, other = roofline(s, per, w.nrhs, prof)
     if roof["class"] in _CLASS_SOURCE:
         # HBM traffic per launch of the dominant class, from committed counter
-        # summaries, valid only for the kernel source they were taken on
-        roof["traffic"] = _traffic_from_profiles(roof["class"])
+        # summaries, valid only for the kernel source they were taken on; the
+        # same summary's rocprofv3 kernel time gives the fraction beside the
+        # live one
+        roof["traffic"] = _traffic_from_profiles(roof["class"], w.name)
+        pc = _profiled_class(roof["class"], w.name)
+        if pc and pc.get("rocprof_avg_ms") and roof["bound"] == "hbm":
+            r_ms = pc["rocprof_avg_ms"]
+            roof["rocprof_avg_ms"] = round(r_ms, 4)
+            roof["frac_rocprof"] = round(roof["bytes_per_launch"] / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
 
     # ---------------- mixed E/B step (faces carry B) on the same solver -----------------
     mixed = None

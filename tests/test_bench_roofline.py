@@ -58,3 +58,14 @@ def test_mfma_bound_at_32_rhs():
     # the HBM figures stay beside it
     assert abs(roof["hbm_achieved_GBps"] - bytes_ / 0.03e-3 / 1e9) < 0.1
     assert abs(roof["hbm_frac"] - roof["hbm_achieved_GBps"] / 8000.0) < 1e-4
+
+
+def test_committed_counter_summary_matches_the_kernel_sources():
+    # the committed FETCH/WRITE summary of every product class was taken on
+    # the current kernel sources of the 64^3 workload (else the bench reports
+    # no traffic); another workload never borrows it
+    for cls in ("full", "cross", "schur"):
+        v = bench._profiled_class(cls, "cavity64_box10_beam16")
+        assert v is not None, cls
+        assert v["bytes_per_launch"] > 0 and v["rocprof_avg_ms"] > 0
+        assert bench._profiled_class(cls, "graded48_rcb512_32rhs") is None
